@@ -1,0 +1,8 @@
+"""FP64 CPU checker for the SSI-COV path.
+
+TEST INFRASTRUCTURE ONLY: imported by the tests, the smoke entry point and the
+CPU-baseline leg of the benchmark, never by the library.  It shares no code
+with the GPU path.
+"""
+from .ssicov_ref import *  # noqa: F401,F403
+from . import philox  # noqa: F401
