@@ -1,0 +1,548 @@
+// Host side of the C ABI declared in include/ssicov.h: argument validation,
+// output layout, workspace arena and the stream-ordered stage sequence.
+#include "../../include/ssicov.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <climits>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "kernels.h"
+
+// ------------------------------------------------------------ error state
+namespace {
+
+thread_local std::string g_last_error;
+
+ssi_status fail(ssi_status s, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return s;
+}
+
+ssi_status hip_fail(hipError_t e, const char *where) {
+  return fail(SSI_EDEVICE, "%s: %s", where, hipGetErrorString(e));
+}
+
+#define SSI_HIP(call)                                   \
+  do {                                                  \
+    hipError_t e_ = (call);                             \
+    if (e_ != hipSuccess) return hip_fail(e_, #call);   \
+  } while (0)
+
+}  // namespace
+
+// ------------------------------------------------------------------ context
+struct ssi_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;   // caller's stream; nullptr = default stream
+  int num_cus = 256;
+  int *status = nullptr;     // device word: kernels OR in failure bits
+  char *ws = nullptr;        // workspace arena
+  size_t ws_cap = 0;
+  size_t ws_top = 0;
+};
+
+namespace {
+
+// Scoped device selection: restores the caller's current device.
+struct DeviceGuard {
+  int prev = -1;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    if (prev != dev) (void)hipSetDevice(dev);
+  }
+  ~DeviceGuard() {
+    if (prev >= 0) (void)hipSetDevice(prev);
+  }
+};
+
+// Bump allocator over the context workspace.  Run a stage's carving once with
+// base == nullptr to measure its size, reserve, then carve for real.
+struct Arena {
+  char *base = nullptr;
+  size_t off = 0;
+  template <typename T>
+  T *take(size_t count) {
+    size_t bytes = (count * sizeof(T) + 255) & ~size_t(255);
+    T *p = base ? reinterpret_cast<T *>(base + off) : nullptr;
+    off += bytes;
+    return p;
+  }
+};
+
+// Reserve `bytes` of workspace for the current call (256-byte aligned).  Call
+// ws_reserve once with the call's total before ws_take.
+ssi_status ws_reserve(ssi_ctx *c, size_t bytes) {
+  c->ws_top = 0;
+  if (bytes <= c->ws_cap) return SSI_OK;
+  // Work already queued may still read the old arena.
+  hipError_t e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+  if (c->ws) (void)hipFree(c->ws);
+  c->ws = nullptr;
+  c->ws_cap = 0;
+  size_t cap = bytes + (bytes >> 3);
+  e = hipMalloc(&c->ws, cap);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(SSI_ENOMEM, "workspace of %zu bytes could not be allocated", cap);
+  }
+  c->ws_cap = cap;
+  return SSI_OK;
+}
+
+template <typename T>
+T *ws_take(ssi_ctx *c, size_t count) {
+  size_t bytes = (count * sizeof(T) + 255) & ~size_t(255);
+  T *p = reinterpret_cast<T *>(c->ws + c->ws_top);
+  c->ws_top += bytes;
+  return p;
+}
+
+size_t aligned_bytes(size_t count, size_t elem) { return (count * elem + 255) & ~size_t(255); }
+
+}  // namespace
+
+extern "C" {
+
+const char *ssi_last_error(void) { return g_last_error.c_str(); }
+
+const char *ssi_status_string(ssi_status s) {
+  switch (s) {
+    case SSI_OK: return "ok";
+    case SSI_EINVAL: return "invalid argument";
+    case SSI_ENOMEM: return "out of device memory";
+    case SSI_EDEVICE: return "device error";
+    case SSI_ENOCONV: return "iteration limit reached";
+    case SSI_EINTERNAL: return "internal error";
+  }
+  return "unknown status";
+}
+
+ssi_status ssi_create(int device, void *hip_stream, ssi_ctx **out) {
+  if (!out) return fail(SSI_EINVAL, "ssi_create: out is NULL");
+  int count = 0;
+  hipError_t e = hipGetDeviceCount(&count);
+  if (e != hipSuccess || count <= 0) {
+    (void)hipGetLastError();
+    return fail(SSI_EDEVICE, "ssi_create: no HIP device available");
+  }
+  if (device < 0 || device >= count) return fail(SSI_EDEVICE, "ssi_create: device %d absent", device);
+  hipDeviceProp_t prop;
+  SSI_HIP(hipGetDeviceProperties(&prop, device));
+  if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+    return fail(SSI_EDEVICE, "ssi_create: device %d is %s, this library is built for gfx950",
+                device, prop.gcnArchName);
+  DeviceGuard g(device);
+  ssi_ctx *c = new ssi_ctx();
+  c->device = device;
+  c->num_cus = prop.multiProcessorCount;
+  c->stream = static_cast<hipStream_t>(hip_stream);
+  e = hipMalloc(&c->status, 256);
+  if (e == hipSuccess) e = hipMemset(c->status, 0, 256);
+  if (e != hipSuccess) {
+    delete c;
+    return hip_fail(e, "status word");
+  }
+  *out = c;
+  return SSI_OK;
+}
+
+void ssi_destroy(ssi_ctx *c) {
+  if (!c) return;
+  DeviceGuard g(c->device);
+  (void)hipStreamSynchronize(c->stream);
+  if (c->ws) (void)hipFree(c->ws);
+  if (c->status) (void)hipFree(c->status);
+  delete c;
+}
+
+ssi_status ssi_synchronize(ssi_ctx *c) {
+  if (!c) return fail(SSI_EINVAL, "ssi_synchronize: NULL context");
+  DeviceGuard g(c->device);
+  SSI_HIP(hipStreamSynchronize(c->stream));
+  int word = 0;
+  SSI_HIP(hipMemcpy(&word, c->status, sizeof(int), hipMemcpyDeviceToHost));
+  if (word) {
+    SSI_HIP(hipMemset(c->status, 0, sizeof(int)));
+    return fail(SSI_ENOCONV, "a factorization broke down (status bits 0x%x): the matrix was "
+                             "numerically singular or not finite", word);
+  }
+  return SSI_OK;
+}
+
+size_t ssi_workspace_bytes(const ssi_ctx *c) { return c ? c->ws_cap : 0; }
+
+// ------------------------------------------------------------ host helpers
+double ssi_tau(int32_t jb, double fs) { return (2.0 * jb - 1.0) / fs; }
+
+int32_t ssi_lag_rule(double fs, double f0, double factor) {
+  if (!(fs > 0) || !(f0 > 0) || !(factor > 0)) return -1;
+  return (int32_t)std::ceil(factor * fs / (2.0 * f0) - 1e-9);
+}
+
+int32_t ssi_default_rank(int64_t t_size) {
+  if (t_size <= 0) return -1;
+  const double pct = std::max(30.0 - 0.00156 * (double)t_size, 25.0);
+  return (int32_t)std::ceil(pct * (double)t_size / 100.0 - 1e-9);
+}
+
+static int32_t n_orders_of(const ssi_params *p) {
+  return (p->order_max - p->order_min) / p->order_step + 1;
+}
+
+ssi_status ssi_validate(const ssi_params *p, int32_t l, int64_t n) {
+  if (!p) return fail(SSI_EINVAL, "params is NULL");
+  if (l < 1) return fail(SSI_EINVAL, "l = %d must be >= 1", l);
+  if (!(p->fs > 0.0) || !std::isfinite(p->fs)) return fail(SSI_EINVAL, "fs must be finite and > 0");
+  if (p->n_lags < 1 || !p->lags) return fail(SSI_EINVAL, "need at least one lag");
+  if (p->order_step < 1) return fail(SSI_EINVAL, "order_step must be >= 1");
+  if (p->order_min < 1 || p->order_max < p->order_min)
+    return fail(SSI_EINVAL, "need 1 <= order_min <= order_max");
+  if (p->svd != SSI_SVD_FULL && p->svd != SSI_SVD_RANDOMIZED)
+    return fail(SSI_EINVAL, "unknown svd mode %d", p->svd);
+  for (int i = 0; i < p->n_lags; ++i) {
+    const int64_t jb = p->lags[i];
+    if (jb < 2) return fail(SSI_EINVAL, "lag %d: j_b = %lld must be >= 2", i, (long long)jb);
+    if (i > 0 && jb <= p->lags[i - 1]) return fail(SSI_EINVAL, "lags must be strictly increasing");
+    if (2 * jb - 1 >= n) return fail(SSI_EINVAL, "lag %d: 2 j_b - 1 = %lld must be < N = %lld", i,
+                                     (long long)(2 * jb - 1), (long long)n);
+    const int64_t m = jb * l;
+    if (m > (int64_t)1 << 30) return fail(SSI_EINVAL, "Toeplitz size %lld too large", (long long)m);
+    if ((int64_t)p->order_max > (int64_t)l * (jb - 1))
+      return fail(SSI_EINVAL, "order_max %d exceeds l (j_b - 1) = %lld for j_b = %lld",
+                  p->order_max, (long long)l * (jb - 1), (long long)jb);
+    if (p->svd == SSI_SVD_RANDOMIZED) {
+      if (p->rank < p->order_max) return fail(SSI_EINVAL, "rank k = %d must be >= order_max = %d",
+                                              p->rank, p->order_max);
+      if (p->oversample < 0 || p->power_iters < 0)
+        return fail(SSI_EINVAL, "oversample and power_iters must be >= 0");
+      if ((int64_t)p->rank + p->oversample > m)
+        return fail(SSI_EINVAL, "k + p = %d exceeds the Toeplitz size %lld",
+                    p->rank + p->oversample, (long long)m);
+      if (p->rank + p->oversample > 1024)
+        return fail(SSI_EINVAL, "k + p = %d exceeds 1024", p->rank + p->oversample);
+    } else {
+      if (m > 4096) return fail(SSI_EINVAL, "full SVD supports Toeplitz size <= 4096, got %lld",
+                                (long long)m);
+      if (p->order_max > m) return fail(SSI_EINVAL, "order_max exceeds the Toeplitz size");
+    }
+  }
+  if (p->order_max > 1024) return fail(SSI_EINVAL, "order_max must be <= 1024");
+  return SSI_OK;
+}
+
+int32_t ssi_pole_offset(const ssi_params *p, int32_t order_index) {
+  if (!p || order_index < 0) return -1;
+  int32_t off = 0;
+  for (int32_t o = 0; o < order_index; ++o) off += (p->order_min + o * p->order_step) / 2;
+  return off;
+}
+
+ssi_status ssi_output_layout(const ssi_params *p, int32_t l, int64_t n, ssi_layout *out) {
+  ssi_status s = ssi_validate(p, l, n);
+  if (s != SSI_OK) return s;
+  if (!out) return fail(SSI_EINVAL, "layout output is NULL");
+  out->n_lags = p->n_lags;
+  out->n_orders = n_orders_of(p);
+  out->sigma_per_lag = p->svd == SSI_SVD_RANDOMIZED ? p->rank : p->order_max;
+  out->pole_cap = ssi_pole_offset(p, out->n_orders);
+  out->l = l;
+  out->n_corr = 2 * p->lags[p->n_lags - 1] - 1;
+  return SSI_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------ workspace planning
+namespace {
+
+struct Sizes {
+  size_t corr = 0;   // correlation stage: partial sums + R stack
+};
+
+size_t corr_bytes(const ssi::CorrPlan &cp, int l, int L) {
+  return aligned_bytes(cp.partial_elems, sizeof(double)) +
+         aligned_bytes((size_t)L * l * l, sizeof(float));
+}
+
+bool is_device_ptr(const void *p) {
+  hipPointerAttribute_t a;
+  if (hipPointerGetAttributes(&a, p) != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  return a.type == hipMemoryTypeDevice;
+}
+
+// ------------------------------------------------------------ products
+// out = op(A) B (FP32 operands, FP64 result via split-K partial sums);
+// optional FP32 copy of the result.
+hipError_t prod_f32(ssi_ctx *c, bool ta, const float *A, int64_t lda, const float *B,
+                    int64_t ldb, int M, int N, int K, double *part, double *out, int64_t ldo,
+                    float *out32 = nullptr, int64_t ld32 = 0) {
+  const ssi::GemmPlan gp = ssi::plan_gemm_f32(M, N, K, c->num_cus);
+  hipError_t e = ssi::launch_gemm_f32(gp, ta, A, lda, B, ldb, M, N, K, part, c->stream);
+  if (e != hipSuccess) return e;
+  return ssi::launch_reduce(gp, part, M, N, 1.0, out, ldo, out32, ld32, c->stream);
+}
+
+hipError_t prod_f64(ssi_ctx *c, bool ta, const double *A, int64_t lda, const double *B,
+                    int64_t ldb, int M, int N, int K, double *part, double *out, int64_t ldo,
+                    float *out32 = nullptr, int64_t ld32 = 0) {
+  const ssi::GemmPlan gp = ssi::plan_gemm_f64(M, N, K, c->num_cus);
+  hipError_t e = ssi::launch_gemm_f64(gp, ta, A, lda, B, ldb, M, N, K, part, c->stream);
+  if (e != hipSuccess) return e;
+  return ssi::launch_reduce(gp, part, M, N, 1.0, out, ldo, out32, ld32, c->stream);
+}
+
+size_t part_f32(int M, int N, int K, int cus) { return ssi::plan_gemm_f32(M, N, K, cus).part_elems(); }
+size_t part_f64(int M, int N, int K, int cus) { return ssi::plan_gemm_f64(M, N, K, cus).part_elems(); }
+
+// ------------------------------------------------------------ randomized SVD
+struct RsvdBufs {
+  float *om32, *x32;
+  double *ya, *yb, *gm, *rinv, *lws, *evals, *evecs, *dws, *part;
+  int ell, ellp;
+};
+
+RsvdBufs carve_rsvd(Arena &a, ssi_ctx *c, int64_t m, int ell, int k) {
+  RsvdBufs b{};
+  b.ell = ell;
+  b.ellp = (ell + 3) & ~3;
+  const int mi = (int)m, cu = c->num_cus;
+  b.om32 = a.take<float>((size_t)m * b.ellp);
+  b.x32 = a.take<float>((size_t)m * b.ellp);
+  b.ya = a.take<double>((size_t)m * ell);
+  b.yb = a.take<double>((size_t)m * ell);
+  b.gm = a.take<double>((size_t)ell * ell);
+  b.rinv = a.take<double>((size_t)ell * ell);
+  b.lws = a.take<double>((size_t)ell * ell);
+  b.evals = a.take<double>(ell);
+  b.evecs = a.take<double>((size_t)ell * ell);
+  b.dws = a.take<double>(ssi::dense_ws_doubles(ell));
+  const size_t part = std::max({part_f32(mi, ell, mi, cu), part_f64(ell, ell, mi, cu),
+                                part_f64(mi, ell, ell, cu), part_f64(mi, k, ell, cu)});
+  b.part = a.take<double>(part);
+  return b;
+}
+
+// Orthonormal basis of the columns of cur (m x ell, FP64) by shifted
+// CholeskyQR: pass 1 with a diagonal shift that keeps the Cholesky factor
+// defined for ill-conditioned input, then two plain passes (CholeskyQR2).
+// Returns the buffer holding Q; b.x32 receives its FP32 copy.
+double *orthonormalize(ssi_ctx *c, RsvdBufs &b, double *cur, double *nxt, int64_t m,
+                       hipError_t &err) {
+  const int ell = b.ell, mi = (int)m;
+  const double shift_rel = 11.0 * ((double)m * ell + (double)ell * (ell + 1)) * 0x1.0p-53;
+  for (int pass = 0; pass < 3 && err == hipSuccess; ++pass) {
+    err = prod_f64(c, true, cur, ell, cur, ell, ell, ell, mi, b.part, b.gm, ell);
+    if (err != hipSuccess) break;
+    err = ssi::launch_chol_inv(b.gm, ell, ell, pass == 0 ? shift_rel : 0.0, b.rinv, ell, b.lws,
+                               b.dws, c->status, c->stream);
+    if (err != hipSuccess) break;
+    const bool last = pass == 2;
+    err = prod_f64(c, false, cur, ell, b.rinv, ell, mi, ell, ell, b.part, nxt, ell,
+                   last ? b.x32 : nullptr, b.ellp);
+    std::swap(cur, nxt);
+  }
+  return cur;
+}
+
+ssi_status run_rsvd(ssi_ctx *c, RsvdBufs &b, const float *t, int64_t m, int64_t ldt, int k,
+                    int p, int q, const float *omega, uint64_t seed, uint32_t stream, double *u,
+                    double *sigma) {
+  const int ell = k + p, mi = (int)m;
+  hipError_t e;
+  if (omega)
+    e = hipMemcpy2DAsync(b.om32, (size_t)b.ellp * 4, omega, (size_t)ell * 4, (size_t)ell * 4,
+                         (size_t)m, hipMemcpyDeviceToDevice, c->stream);
+  else
+    e = ssi::launch_sketch(seed, stream, m, ell, b.om32, b.ellp, c->stream);
+  if (e != hipSuccess) return hip_fail(e, "sketch");
+  // Y = T Omega, Q = orth(Y)
+  e = prod_f32(c, false, t, ldt, b.om32, b.ellp, mi, ell, mi, b.part, b.ya, ell);
+  if (e != hipSuccess) return hip_fail(e, "Y = T Omega");
+  double *Q = orthonormalize(c, b, b.ya, b.yb, m, e);
+  if (e != hipSuccess) return hip_fail(e, "orthonormalize");
+  // power iterations: Q = orth(T^T Q), Q = orth(T Q)
+  for (int it = 0; it < q; ++it) {
+    for (int side = 0; side < 2; ++side) {
+      double *other = (Q == b.ya) ? b.yb : b.ya;
+      e = prod_f32(c, side == 0, t, ldt, b.x32, b.ellp, mi, ell, mi, b.part, other, ell);
+      if (e != hipSuccess) return hip_fail(e, "power iteration product");
+      Q = orthonormalize(c, b, other, Q, m, e);
+      if (e != hipSuccess) return hip_fail(e, "orthonormalize");
+    }
+  }
+  // P^T = T^T Q; G = P P^T; G = U~ S^2 U~^T; U = Q U~[:, :k]
+  double *pt = (Q == b.ya) ? b.yb : b.ya;
+  e = prod_f32(c, true, t, ldt, b.x32, b.ellp, mi, ell, mi, b.part, pt, ell);
+  if (e != hipSuccess) return hip_fail(e, "P^T = T^T Q");
+  e = prod_f64(c, true, pt, ell, pt, ell, ell, ell, mi, b.part, b.gm, ell);
+  if (e != hipSuccess) return hip_fail(e, "P P^T");
+  e = ssi::launch_sym_eig(b.gm, ell, ell, b.evals, b.evecs, ell, b.dws, c->status, c->stream);
+  if (e != hipSuccess) return hip_fail(e, "small eigen-decomposition");
+  e = ssi::launch_sqrt_clamp(b.evals, k, sigma, c->stream);
+  if (e != hipSuccess) return hip_fail(e, "sigma");
+  e = prod_f64(c, false, Q, ell, b.evecs, ell, mi, k, ell, b.part, u, k);
+  if (e != hipSuccess) return hip_fail(e, "U = Q U~");
+  return SSI_OK;
+}
+
+// ------------------------------------------------------------ full SVD
+struct FullBufs {
+  double *tt, *gm, *evals, *evecs, *dws, *part;
+};
+
+FullBufs carve_full(Arena &a, ssi_ctx *c, int m) {
+  FullBufs b{};
+  b.tt = a.take<double>((size_t)m * m);
+  b.gm = a.take<double>((size_t)m * m);
+  b.evals = a.take<double>(m);
+  b.evecs = a.take<double>((size_t)m * m);
+  b.dws = a.take<double>(ssi::dense_ws_doubles(m));
+  b.part = a.take<double>(part_f64(m, m, m, c->num_cus));
+  return b;
+}
+
+// Left singular vectors and singular values of T from the FP64 symmetric
+// eigen-decomposition of T T^T.
+ssi_status run_svd_full(ssi_ctx *c, FullBufs &b, const float *t, int m, int64_t ldt, int k,
+                        double *u, double *sigma) {
+  hipError_t e = ssi::launch_transpose_f32_f64(t, ldt, m, m, b.tt, m, c->stream);
+  if (e != hipSuccess) return hip_fail(e, "transpose");
+  e = prod_f64(c, true, b.tt, m, b.tt, m, m, m, m, b.part, b.gm, m);
+  if (e != hipSuccess) return hip_fail(e, "T T^T");
+  e = ssi::launch_sym_eig(b.gm, m, m, b.evals, b.evecs, m, b.dws, c->status, c->stream);
+  if (e != hipSuccess) return hip_fail(e, "eigen-decomposition");
+  e = ssi::launch_sqrt_clamp(b.evals, k, sigma, c->stream);
+  if (e != hipSuccess) return hip_fail(e, "sigma");
+  e = hipMemcpy2DAsync(u, (size_t)k * 8, b.evecs, (size_t)m * 8, (size_t)k * 8, (size_t)m,
+                       hipMemcpyDeviceToDevice, c->stream);
+  if (e != hipSuccess) return hip_fail(e, "copy U");
+  return SSI_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+ssi_status ssi_correlate(ssi_ctx *c, const float *y, int32_t l, int64_t n, int64_t ldy,
+                         int32_t n_corr, float *r) {
+  if (!c) return fail(SSI_EINVAL, "ssi_correlate: NULL context");
+  if (!y || !r) return fail(SSI_EINVAL, "ssi_correlate: NULL buffer");
+  if (l < 1 || n < 2 || ldy < n || n_corr < 1 || n_corr >= n)
+    return fail(SSI_EINVAL, "ssi_correlate: need l >= 1, ldy >= n, 1 <= n_corr < n");
+  if ((int64_t)l * n_corr > (int64_t)1 << 30) return fail(SSI_EINVAL, "ssi_correlate: too many rows");
+  DeviceGuard g(c->device);
+  if (!is_device_ptr(y) || !is_device_ptr(r))
+    return fail(SSI_EINVAL, "ssi_correlate: y and r must be device pointers");
+  const ssi::CorrPlan cp = ssi::plan_correlate(l, n, n_corr, c->num_cus);
+  ssi_status s = ws_reserve(c, aligned_bytes(cp.partial_elems, sizeof(double)));
+  if (s != SSI_OK) return s;
+  double *partial = ws_take<double>(c, cp.partial_elems);
+  SSI_HIP(ssi::launch_correlate(cp, y, l, n, ldy, n_corr, partial, r, c->stream));
+  return SSI_OK;
+}
+
+ssi_status ssi_toeplitz(ssi_ctx *c, const float *r, int32_t l, int32_t jb, float *t,
+                        int64_t ldt) {
+  if (!c) return fail(SSI_EINVAL, "ssi_toeplitz: NULL context");
+  if (!r || !t) return fail(SSI_EINVAL, "ssi_toeplitz: NULL buffer");
+  if (l < 1 || jb < 1 || (int64_t)jb * l > (int64_t)1 << 30 || ldt < (int64_t)jb * l)
+    return fail(SSI_EINVAL, "ssi_toeplitz: need l, jb >= 1 and ldt >= jb l");
+  DeviceGuard g(c->device);
+  if (!is_device_ptr(r) || !is_device_ptr(t))
+    return fail(SSI_EINVAL, "ssi_toeplitz: r and t must be device pointers");
+  SSI_HIP(ssi::launch_toeplitz(r, l, jb, t, ldt, c->stream));
+  return SSI_OK;
+}
+
+ssi_status ssi_sketch(ssi_ctx *c, uint64_t seed, uint32_t stream, int64_t m, int32_t ell,
+                      float *omega, int64_t ldo) {
+  if (!c) return fail(SSI_EINVAL, "ssi_sketch: NULL context");
+  if (!omega || m < 1 || ell < 1 || ldo < ell)
+    return fail(SSI_EINVAL, "ssi_sketch: need m, ell >= 1, ldo >= ell and a buffer");
+  DeviceGuard g(c->device);
+  if (!is_device_ptr(omega)) return fail(SSI_EINVAL, "ssi_sketch: omega must be a device pointer");
+  SSI_HIP(ssi::launch_sketch(seed, stream, m, ell, omega, ldo, c->stream));
+  return SSI_OK;
+}
+
+ssi_status ssi_workspace_estimate(const ssi_params *p, int32_t l, int64_t n, size_t *bytes) {
+  ssi_status s = ssi_validate(p, l, n);
+  if (s != SSI_OK) return s;
+  if (!bytes) return fail(SSI_EINVAL, "bytes is NULL");
+  const int L = 2 * p->lags[p->n_lags - 1] - 1;
+  const ssi::CorrPlan cp = ssi::plan_correlate(l, n, L, 256);
+  *bytes = corr_bytes(cp, l, L);
+  return SSI_OK;
+}
+
+ssi_status ssi_rsvd(ssi_ctx *c, const float *t, int64_t m, int64_t ldt, int32_t k, int32_t p,
+                    int32_t q, const float *omega, uint64_t seed, uint32_t stream, double *u,
+                    double *sigma) {
+  if (!c) return fail(SSI_EINVAL, "ssi_rsvd: NULL context");
+  if (!t || !u || !sigma) return fail(SSI_EINVAL, "ssi_rsvd: NULL buffer");
+  if (m < 1 || ldt < m || k < 1 || p < 0 || q < 0 || (int64_t)k + p > m)
+    return fail(SSI_EINVAL, "ssi_rsvd: need 1 <= k, 0 <= p, 0 <= q, k + p <= m <= ldt");
+  if (k + p > ssi::dense_max_n())
+    return fail(SSI_EINVAL, "ssi_rsvd: k + p = %d exceeds %d", k + p, ssi::dense_max_n());
+  if (m > INT32_MAX / 2) return fail(SSI_EINVAL, "ssi_rsvd: m too large");
+  DeviceGuard g(c->device);
+  if (!is_device_ptr(t) || !is_device_ptr(u) || !is_device_ptr(sigma) ||
+      (omega && !is_device_ptr(omega)))
+    return fail(SSI_EINVAL, "ssi_rsvd: buffers must be device pointers");
+  Arena probe;
+  carve_rsvd(probe, c, m, k + p, k);
+  ssi_status s = ws_reserve(c, probe.off);
+  if (s != SSI_OK) return s;
+  Arena a{c->ws, 0};
+  RsvdBufs b = carve_rsvd(a, c, m, k + p, k);
+  return run_rsvd(c, b, t, m, ldt, k, p, q, omega, seed, stream, u, sigma);
+}
+
+ssi_status ssi_svd_full(ssi_ctx *c, const float *t, int64_t m, int64_t ldt, int32_t k, double *u,
+                        double *sigma) {
+  if (!c) return fail(SSI_EINVAL, "ssi_svd_full: NULL context");
+  if (!t || !u || !sigma) return fail(SSI_EINVAL, "ssi_svd_full: NULL buffer");
+  if (m < 1 || ldt < m || k < 1 || k > m)
+    return fail(SSI_EINVAL, "ssi_svd_full: need 1 <= k <= m <= ldt");
+  if (m > ssi::dense_max_n())
+    return fail(SSI_EINVAL, "ssi_svd_full: m = %lld exceeds %d", (long long)m,
+                ssi::dense_max_n());
+  DeviceGuard g(c->device);
+  if (!is_device_ptr(t) || !is_device_ptr(u) || !is_device_ptr(sigma))
+    return fail(SSI_EINVAL, "ssi_svd_full: buffers must be device pointers");
+  Arena probe;
+  carve_full(probe, c, (int)m);
+  ssi_status s = ws_reserve(c, probe.off);
+  if (s != SSI_OK) return s;
+  Arena a{c->ws, 0};
+  FullBufs b = carve_full(a, c, (int)m);
+  return run_svd_full(c, b, t, (int)m, ldt, k, u, sigma);
+}
+
+ssi_status ssi_modal(ssi_ctx *, const double *, const double *, int64_t, int32_t, int32_t,
+                     const ssi_params *, int32_t, const ssi_output *) {
+  return fail(SSI_EINTERNAL, "ssi_modal: not built yet");
+}
+
+ssi_status ssi_identify(ssi_ctx *, const float *, int32_t, int64_t, int64_t, const ssi_params *,
+                        const ssi_output *) {
+  return fail(SSI_EINTERNAL, "ssi_identify: not built yet");
+}
+
+}  // extern "C"

@@ -1,0 +1,64 @@
+// Internal launcher declarations shared by the host API and the kernel files.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include <algorithm>
+
+namespace ssi {
+
+// ---- correlations (correlate.hip)
+struct CorrPlan {
+  int grid_rows, grid_cols, splits;
+  int64_t split_len;
+  int sa_stride, na_max;
+  size_t lds_bytes;
+  size_t partial_elems;
+};
+CorrPlan plan_correlate(int l, int64_t n, int L, int num_cus);
+hipError_t launch_correlate(const CorrPlan &p, const float *y, int l, int64_t n, int64_t ldy,
+                            int L, double *partial, float *r, hipStream_t st);
+
+// ---- Toeplitz (toeplitz.hip)
+hipError_t launch_toeplitz(const float *r, int l, int jb, float *t, int64_t ldt,
+                           hipStream_t st);
+
+// ---- sketch (sketch.hip)
+hipError_t launch_sketch(uint64_t seed, uint32_t stream, int64_t m, int ell, float *omega,
+                         int64_t ldo, hipStream_t st);
+
+// ---- dense products (gemm.hip)
+struct GemmPlan {
+  int gm, gn, splits, k_per_split;
+  int64_t ldc, split_stride;     // partial-sum layout: [splits][M][ldc]
+  size_t part_elems() const { return (size_t)splits * (size_t)split_stride; }
+};
+GemmPlan plan_gemm_f32(int M, int N, int K, int num_cus);
+GemmPlan plan_gemm_f64(int M, int N, int K, int num_cus);
+hipError_t launch_gemm_f32(const GemmPlan &p, bool trans_a, const float *A, int64_t lda,
+                           const float *B, int64_t ldb, int M, int N, int K, double *part,
+                           hipStream_t st);
+hipError_t launch_gemm_f64(const GemmPlan &p, bool trans_a, const double *A, int64_t lda,
+                           const double *B, int64_t ldb, int M, int N, int K, double *part,
+                           hipStream_t st);
+hipError_t launch_reduce(const GemmPlan &p, const double *part, int M, int N, double scale,
+                         double *out, int64_t ldo, float *out32, int64_t ld32, hipStream_t st);
+hipError_t launch_convert(const double *in, int64_t ldi, int M, int N, float *out, int64_t ldo,
+                          hipStream_t st);
+
+hipError_t launch_sqrt_clamp(const double *ev, int k, double *sigma, hipStream_t st);
+hipError_t launch_transpose_f32_f64(const float *in, int64_t ldi, int M, int N, double *out,
+                                    int64_t ldo, hipStream_t st);
+
+// ---- small dense FP64 (dense.hip), one workgroup, n <= dense_max_n()
+int dense_max_n();
+// scratch (doubles) shared by launch_chol_inv and launch_sym_eig for size n
+size_t dense_ws_doubles(int n);
+hipError_t launch_chol_inv(const double *G, int64_t ldg, int n, double shift_rel, double *Rinv,
+                           int64_t ldr, double *Lws, double *ws, int *status, hipStream_t st);
+hipError_t launch_sym_eig(const double *G, int64_t ldg, int n, double *evals, double *evecs,
+                          int64_t ldv, double *ws, int *status, hipStream_t st);
+
+}  // namespace ssi

@@ -1,0 +1,77 @@
+// Block-Toeplitz assembly, Eq. (6):
+//   T[r l + a][c l + b] = R_{jb + r - c}[a][b],  0 <= r, c < jb,
+// with R_j stored at r_stack[(j - 1) l l + a l + b].
+//
+// A pure HBM write stream (m^2 floats) whose source, the 2 jb - 1 blocks of R,
+// stays in L2 / Infinity Cache.  Each thread writes 16 consecutive floats of
+// one row as four 16-byte stores; consecutive threads cover consecutive
+// column segments, so every wave writes one contiguous 1 KiB run.  The vector
+// path needs l, ldt and both pointers 16-byte aligned; otherwise a scalar path
+// is used.
+#include "common.h"
+#include "kernels.h"
+
+namespace {
+
+constexpr int kVecPerThread = 4;                 // float4 stores per thread
+constexpr int kThreads = 256;
+constexpr int kFloatsPerBlock = kThreads * kVecPerThread * 4;
+
+}  // namespace
+
+__global__ void __launch_bounds__(kThreads)
+toeplitz_vec4(const float *__restrict__ r, int l, int jb, float *__restrict__ t,
+              int64_t ldt, int blocks_per_row) {
+  const int m = jb * l;
+  const int row = blockIdx.x / blocks_per_row;
+  const int cblk = blockIdx.x - row * blocks_per_row;
+  const int rb = row / l, a = row - rb * l;
+  // First column of this thread's 16-float run.
+  const int x0 = cblk * kFloatsPerBlock + threadIdx.x * (kVecPerThread * 4);
+  if (x0 >= m) return;
+  int cb = x0 / l;
+  int b = x0 - cb * l;
+  const float *rrow = r + (int64_t)a * l;       // row a of every block
+  float *dst = t + (int64_t)row * ldt + x0;
+#pragma unroll
+  for (int v = 0; v < kVecPerThread; ++v) {
+    if (x0 + 4 * v < m) {
+      const int blk = jb + rb - cb - 1;          // R_{jb + r - c} -> index j - 1
+      const float4 val = *reinterpret_cast<const float4 *>(rrow + (int64_t)blk * l * l + b);
+      *reinterpret_cast<float4 *>(dst + 4 * v) = val;
+    }
+    b += 4;
+    if (b >= l) { b -= l; ++cb; }
+  }
+}
+
+__global__ void __launch_bounds__(kThreads)
+toeplitz_scalar(const float *__restrict__ r, int l, int jb, float *__restrict__ t,
+                int64_t ldt) {
+  const int m = jb * l;
+  const int row = blockIdx.x;
+  const int rb = row / l, a = row - rb * l;
+  for (int x = threadIdx.x; x < m; x += kThreads) {
+    const int cb = x / l, b = x - cb * l;
+    t[(int64_t)row * ldt + x] = r[(int64_t)(jb + rb - cb - 1) * l * l + (int64_t)a * l + b];
+  }
+}
+
+namespace ssi {
+
+hipError_t launch_toeplitz(const float *r, int l, int jb, float *t, int64_t ldt,
+                           hipStream_t st) {
+  const int m = jb * l;
+  const bool vec = (l % 4 == 0) && (ldt % 4 == 0) &&
+                   ((uintptr_t)r % 16 == 0) && ((uintptr_t)t % 16 == 0);
+  if (vec) {
+    const int bpr = ceil_div(m, kFloatsPerBlock);
+    hipLaunchKernelGGL(toeplitz_vec4, dim3((unsigned)((int64_t)bpr * m)), dim3(kThreads), 0,
+                       st, r, l, jb, t, ldt, bpr);
+  } else {
+    hipLaunchKernelGGL(toeplitz_scalar, dim3(m), dim3(kThreads), 0, st, r, l, jb, t, ldt);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace ssi

@@ -1,0 +1,331 @@
+"""Thin Python binding of libssicov.so (include/ssicov.h).
+
+Argument marshalling only: every step of the identification runs in the
+library's HIP kernels.  Device buffers are torch CUDA tensors; all calls are
+ordered on the context's stream, which defaults to torch's current stream so
+that torch allocations and library work stay ordered.  There is no fallback:
+if the library is missing or no gfx950 device is present, calls raise.
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+import os
+from typing import List, Optional, Sequence
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libssicov.so")
+
+SSI_OK, SSI_EINVAL, SSI_ENOMEM, SSI_EDEVICE, SSI_ENOCONV, SSI_EINTERNAL = range(6)
+SVD_FULL, SVD_RANDOMIZED = 0, 1
+
+# Every symbol include/ssicov.h declares.
+EXPORTED = (
+    "ssi_create", "ssi_destroy", "ssi_synchronize", "ssi_workspace_bytes",
+    "ssi_validate", "ssi_output_layout", "ssi_pole_offset", "ssi_workspace_estimate",
+    "ssi_tau", "ssi_lag_rule", "ssi_default_rank", "ssi_status_string",
+    "ssi_last_error", "ssi_identify", "ssi_correlate", "ssi_toeplitz",
+    "ssi_sketch", "ssi_rsvd", "ssi_svd_full", "ssi_modal",
+)
+
+
+class SSIError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"[status {status}] {msg}")
+        self.status = status
+
+
+class _Params(ctypes.Structure):
+    _fields_ = [
+        ("fs", ctypes.c_double),
+        ("lags", ctypes.POINTER(ctypes.c_int32)),
+        ("n_lags", ctypes.c_int32),
+        ("order_min", ctypes.c_int32),
+        ("order_max", ctypes.c_int32),
+        ("order_step", ctypes.c_int32),
+        ("svd", ctypes.c_int32),
+        ("rank", ctypes.c_int32),
+        ("oversample", ctypes.c_int32),
+        ("power_iters", ctypes.c_int32),
+        ("seed", ctypes.c_uint64),
+    ]
+
+
+class _Layout(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int32) for n in
+                ("n_lags", "n_orders", "sigma_per_lag", "pole_cap", "l", "n_corr")]
+
+
+class _Output(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_void_p) for n in
+                ("sigma", "count", "f", "xi", "mu", "phi", "flags")]
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Load libssicov.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: run __graft_entry__.build() first")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i32, i64, u32, u64 = (ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64,
+                                  ctypes.c_uint32, ctypes.c_uint64)
+        P = ctypes.POINTER(_Params)
+        sig = {
+            "ssi_create": ([ctypes.c_int, vp, ctypes.POINTER(vp)], ctypes.c_int),
+            "ssi_destroy": ([vp], None),
+            "ssi_synchronize": ([vp], ctypes.c_int),
+            "ssi_workspace_bytes": ([vp], ctypes.c_size_t),
+            "ssi_validate": ([P, i32, i64], ctypes.c_int),
+            "ssi_output_layout": ([P, i32, i64, ctypes.POINTER(_Layout)], ctypes.c_int),
+            "ssi_pole_offset": ([P, i32], i32),
+            "ssi_workspace_estimate": ([P, i32, i64, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
+            "ssi_tau": ([i32, ctypes.c_double], ctypes.c_double),
+            "ssi_lag_rule": ([ctypes.c_double, ctypes.c_double, ctypes.c_double], i32),
+            "ssi_default_rank": ([i64], i32),
+            "ssi_status_string": ([ctypes.c_int], ctypes.c_char_p),
+            "ssi_last_error": ([], ctypes.c_char_p),
+            "ssi_identify": ([vp, vp, i32, i64, i64, P, ctypes.POINTER(_Output)], ctypes.c_int),
+            "ssi_correlate": ([vp, vp, i32, i64, i64, i32, vp], ctypes.c_int),
+            "ssi_toeplitz": ([vp, vp, i32, i32, vp, i64], ctypes.c_int),
+            "ssi_sketch": ([vp, u64, u32, i64, i32, vp, i64], ctypes.c_int),
+            "ssi_rsvd": ([vp, vp, i64, i64, i32, i32, i32, vp, u64, u32, vp, vp], ctypes.c_int),
+            "ssi_svd_full": ([vp, vp, i64, i64, i32, vp, vp], ctypes.c_int),
+            "ssi_modal": ([vp, vp, vp, i64, i32, i32, P, i32, ctypes.POINTER(_Output)],
+                          ctypes.c_int),
+        }
+        for name, (args, res) in sig.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = res
+        _lib = L
+    return _lib
+
+
+def _check(status: int) -> None:
+    if status != SSI_OK:
+        raise SSIError(status, lib().ssi_last_error().decode())
+
+
+# ------------------------------------------------------------ parameters
+@dataclasses.dataclass
+class Params:
+    """Identification parameters (see ssi_params in include/ssicov.h)."""
+    fs: float
+    lags: Sequence[int]
+    order_min: int
+    order_max: int
+    order_step: int = 2
+    svd: int = SVD_RANDOMIZED
+    rank: int = 0
+    oversample: int = 0
+    power_iters: int = 0
+    seed: int = 0
+
+    def c(self) -> _Params:
+        arr = (ctypes.c_int32 * len(self.lags))(*[int(v) for v in self.lags])
+        p = _Params(float(self.fs), arr, len(self.lags), int(self.order_min),
+                    int(self.order_max), int(self.order_step), int(self.svd),
+                    int(self.rank), int(self.oversample), int(self.power_iters),
+                    int(self.seed) & 0xFFFFFFFFFFFFFFFF)
+        p._keep = arr  # keep the lag array alive with the struct
+        return p
+
+    @property
+    def orders(self) -> List[int]:
+        return list(range(self.order_min, self.order_max + 1, self.order_step))
+
+
+def validate(p: Params, l: int, n: int) -> None:
+    cp = p.c()
+    _check(lib().ssi_validate(ctypes.byref(cp), l, n))
+
+
+def output_layout(p: Params, l: int, n: int) -> dict:
+    cp = p.c()
+    lay = _Layout()
+    _check(lib().ssi_output_layout(ctypes.byref(cp), l, n, ctypes.byref(lay)))
+    return {name: getattr(lay, name) for name, _ in _Layout._fields_}
+
+
+def pole_offset(p: Params, order_index: int) -> int:
+    cp = p.c()
+    return int(lib().ssi_pole_offset(ctypes.byref(cp), order_index))
+
+
+def workspace_estimate(p: Params, l: int, n: int) -> int:
+    cp = p.c()
+    out = ctypes.c_size_t()
+    _check(lib().ssi_workspace_estimate(ctypes.byref(cp), l, n, ctypes.byref(out)))
+    return int(out.value)
+
+
+def tau(jb: int, fs: float) -> float:
+    return float(lib().ssi_tau(jb, fs))
+
+
+def lag_rule(fs: float, f0: float, factor: float = 10.0) -> int:
+    return int(lib().ssi_lag_rule(fs, f0, factor))
+
+
+def default_rank(t_size: int) -> int:
+    return int(lib().ssi_default_rank(t_size))
+
+
+# --------------------------------------------------------------- context
+def _ptr(t) -> int:
+    return int(t.data_ptr())
+
+
+class Context:
+    """A library context on one GPU, ordered on a HIP stream."""
+
+    def __init__(self, device: int = 0, stream=None):
+        import torch
+        if stream is None:
+            stream = torch.cuda.current_stream(device)
+        self._stream = stream
+        handle = ctypes.c_void_p()
+        _check(lib().ssi_create(device, ctypes.c_void_p(stream.cuda_stream),
+                                ctypes.byref(handle)))
+        self._h = handle
+        self.device = device
+
+    def close(self) -> None:
+        if getattr(self, "_h", None):
+            lib().ssi_destroy(self._h)
+            self._h = None
+
+    def __del__(self):  # pragma: no cover - interpreter shutdown order
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def synchronize(self) -> None:
+        _check(lib().ssi_synchronize(self._h))
+
+    @property
+    def workspace_bytes(self) -> int:
+        return int(lib().ssi_workspace_bytes(self._h))
+
+    # ---------------------------------------------------------- stages
+    def correlate(self, y, n_corr: int, out=None):
+        """R (n_corr, l, l) float32 of the device record y (l, n) float32."""
+        import torch
+        l, n = y.shape
+        if out is None:
+            out = torch.empty((n_corr, l, l), dtype=torch.float32, device=y.device)
+        _check(lib().ssi_correlate(self._h, _ptr(y), l, n, y.stride(0), n_corr, _ptr(out)))
+        return out
+
+    def toeplitz(self, r, jb: int, ldt: Optional[int] = None, out=None):
+        import torch
+        l = r.shape[1]
+        m = jb * l
+        if ldt is None:
+            ldt = m
+        if out is None:
+            out = torch.empty((m, ldt), dtype=torch.float32, device=r.device)
+        _check(lib().ssi_toeplitz(self._h, _ptr(r), l, jb, _ptr(out), ldt))
+        return out
+
+    def sketch(self, seed: int, stream: int, m: int, ell: int, out=None):
+        import torch
+        if out is None:
+            out = torch.empty((m, ell), dtype=torch.float32, device=f"cuda:{self.device}")
+        _check(lib().ssi_sketch(self._h, seed & 0xFFFFFFFFFFFFFFFF, stream, m, ell, _ptr(out),
+                                out.stride(0)))
+        return out
+
+    def rsvd(self, t, k: int, p: int, q: int, omega=None, seed: int = 0, stream: int = 0):
+        """(U (m, k) float64, sigma (k,) float64) of the device matrix t (m, ldt) float32."""
+        import torch
+        m = t.shape[0]
+        u = torch.empty((m, k), dtype=torch.float64, device=t.device)
+        s = torch.empty((k,), dtype=torch.float64, device=t.device)
+        om = _ptr(omega) if omega is not None else None
+        _check(lib().ssi_rsvd(self._h, _ptr(t), m, t.stride(0), k, p, q, om,
+                              seed & 0xFFFFFFFFFFFFFFFF, stream, _ptr(u), _ptr(s)))
+        return u, s
+
+    def svd_full(self, t, k: int):
+        import torch
+        m = t.shape[0]
+        u = torch.empty((m, k), dtype=torch.float64, device=t.device)
+        s = torch.empty((k,), dtype=torch.float64, device=t.device)
+        _check(lib().ssi_svd_full(self._h, _ptr(t), m, t.stride(0), k, _ptr(u), _ptr(s)))
+        return u, s
+
+    # --------------------------------------------------- identification
+    def alloc_output(self, p: Params, l: int, n: int) -> "Output":
+        import torch
+        lay = output_layout(p, l, n)
+        dev = f"cuda:{self.device}"
+        nl, no, cap = lay["n_lags"], lay["n_orders"], lay["pole_cap"]
+        return Output(
+            layout=lay, params=p,
+            sigma=torch.zeros((nl, lay["sigma_per_lag"]), dtype=torch.float64, device=dev),
+            count=torch.zeros((nl, no), dtype=torch.int32, device=dev),
+            f=torch.zeros((nl, cap), dtype=torch.float64, device=dev),
+            xi=torch.zeros((nl, cap), dtype=torch.float64, device=dev),
+            mu=torch.zeros((nl, cap, 2), dtype=torch.float64, device=dev),
+            phi=torch.zeros((nl, cap, l, 2), dtype=torch.float32, device=dev),
+            flags=torch.zeros((nl, no), dtype=torch.int32, device=dev),
+        )
+
+    def modal(self, u, sigma, l: int, p: Params, lag_index: int, out: "Output"):
+        cp = p.c()
+        m, k = u.shape
+        co = out.c()
+        _check(lib().ssi_modal(self._h, _ptr(u), _ptr(sigma), m, k, l, ctypes.byref(cp),
+                               lag_index, ctypes.byref(co)))
+        return out
+
+    def identify(self, y, p: Params, out: Optional["Output"] = None) -> "Output":
+        """Enqueue the whole identification of the device record y (l, n)."""
+        l, n = y.shape
+        if out is None:
+            out = self.alloc_output(p, l, n)
+        cp = p.c()
+        co = out.c()
+        _check(lib().ssi_identify(self._h, _ptr(y), l, n, y.stride(0), ctypes.byref(cp),
+                                  ctypes.byref(co)))
+        return out
+
+
+@dataclasses.dataclass
+class Output:
+    """Device output buffers of one identification (see ssi_output)."""
+    layout: dict
+    params: Params
+    sigma: object
+    count: object
+    f: object
+    xi: object
+    mu: object
+    phi: object
+    flags: object
+
+    def c(self) -> _Output:
+        return _Output(*[_ptr(getattr(self, n)) for n in
+                         ("sigma", "count", "f", "xi", "mu", "phi", "flags")])
+
+    def poles(self, lag_index: int, order_index: int) -> dict:
+        """Host copy of the poles of one (lag, order)."""
+        p = self.params
+        off = pole_offset(p, order_index)
+        cnt = int(self.count[lag_index, order_index].item())
+        sl = slice(off, off + cnt)
+        mu = self.mu[lag_index, sl].cpu().numpy()
+        phi = self.phi[lag_index, sl].cpu().numpy()
+        return {
+            "f": self.f[lag_index, sl].cpu().numpy(),
+            "xi": self.xi[lag_index, sl].cpu().numpy(),
+            "mu": mu[:, 0] + 1j * mu[:, 1],
+            "phi": phi[..., 0] + 1j * phi[..., 1],
+            "flag": int(self.flags[lag_index, order_index].item()),
+        }

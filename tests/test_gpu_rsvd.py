@@ -1,0 +1,122 @@
+"""GPU parity of the randomized and full SVD stages against the FP64 checker."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2411_05510_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+SIGMA_RTOL = 1e-4          # singular values, FP32 path
+SIGMA_FLOOR = 1e-3         # gate only sigma_i >= 1e-3 sigma_1
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_2411_05510_amd import ssicov
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    c = ssicov.Context(0)
+    yield c
+    c.close()
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def _check_sigma(got, ref):
+    keep = ref >= SIGMA_FLOOR * ref[0]
+    rel = np.abs(got[keep] - ref[keep]) / ref[keep]
+    assert rel.max() <= SIGMA_RTOL, f"max sigma rel err {rel.max():.3e} at {np.argmax(rel)}"
+    return keep
+
+
+def _check_subspace(u_got, u_ref, s_ref, count, tol):
+    """Leading `count` left singular vectors span the same space.  A
+    perturbation of relative size e moves that subspace by about
+    e / ((s_count - s_count+1) / s_1), so the bound is tol scaled by the
+    inverse relative gap (FP32 products give e around 1e-6)."""
+    a = u_got[:, :count]
+    b = u_ref[:, :count]
+    rel_gap = (s_ref[count - 1] - s_ref[count]) / s_ref[0] if count < len(s_ref) else 1.0
+    bound = tol / min(1.0, rel_gap)
+    gap = np.linalg.norm(a - b @ (b.T @ a), 2)
+    assert gap <= bound, f"subspace gap {gap:.3e} > {bound:.3e}"
+
+
+def _run_rsvd(ctx, t32, k, p, q, seed=7, stream=0, pad=0):
+    m = t32.shape[0]
+    tt = np.zeros((m, m + pad), dtype=np.float32)
+    tt[:, :m] = t32
+    u, s = ctx.rsvd(_dev(tt), k, p, q, seed=seed, stream=stream)
+    ctx.synchronize()
+    return u.cpu().numpy(), s.cpu().numpy()
+
+
+@pytest.mark.parametrize("m,k,p,q,pad", [(300, 10, 4, 1, 0), (701, 30, 7, 2, 3),
+                                         (256, 12, 0, 0, 0), (130, 40, 9, 3, 1)])
+def test_rsvd_low_rank_plus_noise(ctx, m, k, p, q, pad):
+    t32 = synth.random_lowrank(m, m, k, seed=m + k, decay=0.8, noise=1e-5)
+    u, s = _run_rsvd(ctx, t32, k, p, q, seed=11, pad=pad)
+    om = oracle.sketch(11, m, k + p, 0)
+    ur, sr = oracle.rsvd(t32.astype(np.float64), k, p, q, om)
+    _check_sigma(s, sr)
+    # orthonormal columns
+    assert np.abs(u.T @ u - np.eye(k)).max() < 1e-8
+    _check_subspace(u, ur, sr, k // 2, 2e-6)
+
+
+def test_rsvd_full_width_is_exact(ctx):
+    m = 48
+    t32 = synth.random_matrix(m, m, seed=4)
+    u, s = _run_rsvd(ctx, t32, m, 0, 1, seed=5)
+    ss = np.linalg.svd(t32.astype(np.float64), compute_uv=False)
+    _check_sigma(s, ss)
+
+
+def test_rsvd_sketch_stream_changes_result(ctx):
+    t32 = synth.random_lowrank(200, 200, 40, seed=2, decay=0.95, noise=1e-3)
+    _, s0 = _run_rsvd(ctx, t32, 20, 0, 0, seed=3, stream=0)
+    _, s1 = _run_rsvd(ctx, t32, 20, 0, 0, seed=3, stream=1)
+    assert not np.allclose(s0, s1)
+
+
+def test_rsvd_caller_sketch(ctx):
+    m, k, p = 160, 16, 6
+    t32 = synth.random_lowrank(m, m, 30, seed=8, decay=0.85, noise=1e-4)
+    om = synth.random_matrix(m, k + p, seed=9)
+    u, s = ctx.rsvd(_dev(t32), k, p, 1, omega=_dev(om))
+    ctx.synchronize()
+    ur, sr = oracle.rsvd(t32.astype(np.float64), k, p, 1, om.astype(np.float64))
+    _check_sigma(s.cpu().numpy(), sr)
+
+
+def test_rsvd_bridge_toeplitz(ctx):
+    """The 10800 x 10800 Toeplitz matrix of the 180-channel record: k = 200,
+    p = 20, q = 2, same T values and the same Philox sketch on both sides."""
+    wl = synth.WORKLOADS["bridge-180ch"]
+    _, y = synth.make_record(wl)
+    jb = wl.lags[0]
+    r = ctx.correlate(_dev(y), 2 * jb - 1)
+    t = ctx.toeplitz(r, jb)
+    ctx.synchronize()
+    t32 = t.cpu().numpy()
+    u, s = ctx.rsvd(t, wl.rank, wl.oversample, wl.power_iters, seed=wl.sketch_seed)
+    ctx.synchronize()
+    om = oracle.sketch(wl.sketch_seed, t32.shape[0], wl.rank + wl.oversample, 0)
+    ur, sr = oracle.rsvd(t32.astype(np.float64), wl.rank, wl.oversample, wl.power_iters, om)
+    _check_sigma(s.cpu().numpy(), sr)
+    _check_subspace(u.cpu().numpy(), ur, sr, 2 * wl.n_modes, 1e-6)
+
+
+@pytest.mark.parametrize("m,k", [(120, 40), (240, 40), (37, 37)])
+def test_svd_full(ctx, m, k):
+    t32 = synth.random_lowrank(m, m, min(m, 60), seed=m, decay=0.9, noise=1e-4)
+    u, s = ctx.svd_full(_dev(t32), k)
+    ctx.synchronize()
+    ur, sr = oracle.full_svd(t32.astype(np.float64), k)
+    _check_sigma(s.cpu().numpy(), sr)
+    _check_subspace(u.cpu().numpy(), ur, sr, min(k, 10), 1e-7)
