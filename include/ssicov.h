@@ -116,11 +116,32 @@ ssi_status ssi_synchronize(ssi_ctx *ctx);
 /* Bytes of device workspace currently held by the context. */
 size_t ssi_workspace_bytes(const ssi_ctx *ctx);
 
+/* Stage timing.  When enabled, the context records a pair of HIP events on
+ * its stream around every stage it enqueues; ssi_profile_read synchronizes,
+ * adds the elapsed times into per-stage totals and returns them.  Stage ids:
+ * SSI_STAGE_* below.  ms[i] (milliseconds) and calls[i] are accumulated since
+ * the last read; n_stages is the length of both caller arrays (host). */
+enum {
+  SSI_STAGE_CORR_MFMA = 0,   /* correlation contraction kernel          */
+  SSI_STAGE_CORR_REDUCE,     /* split-K reduction of the correlations   */
+  SSI_STAGE_TOEPLITZ,        /* block-Toeplitz assembly                 */
+  SSI_STAGE_SKETCH,          /* Gaussian sketch                         */
+  SSI_STAGE_PRODUCTS,        /* T X and T^T X products (incl. reduce)   */
+  SSI_STAGE_ORTH,            /* CholeskyQR orthonormalisations          */
+  SSI_STAGE_SMALL_SVD,       /* P P^T, eigen-decomposition, U = Q U~    */
+  SSI_STAGE_SHIFT_LS,        /* Gram matrices, Cholesky, W              */
+  SSI_STAGE_EIG,             /* per-order Hessenberg, QR, poles         */
+  SSI_STAGE_COUNT
+};
+ssi_status ssi_set_profiling(ssi_ctx *ctx, int enable);
+ssi_status ssi_profile_read(ssi_ctx *ctx, double *ms, int32_t *calls, int32_t n_stages);
+
 /* ----------------------------------------------- host-only helpers (no GPU) */
 
 /* Check parameters against l channels and n samples: 2 <= j_b, 2 j_b - 1 < n,
- * 1 <= order_min <= order_max <= min(k, l (j_b - 1)) for every lag, and for
- * the randomized mode order_max <= k, k + p <= j_b l.  Host-only. */
+ * 1 <= order_min <= order_max <= min(l (j_b - 1), 224) for every lag; for the
+ * randomized mode order_max <= k and k + p <= min(j_b l, 1024); for the full
+ * SVD j_b l <= 1024.  Host-only. */
 ssi_status ssi_validate(const ssi_params *p, int32_t l, int64_t n);
 /* Output buffer sizes for ssi_identify.  Host-only. */
 ssi_status ssi_output_layout(const ssi_params *p, int32_t l, int64_t n,
@@ -186,14 +207,17 @@ ssi_status ssi_rsvd(ssi_ctx *ctx, const float *t, int64_t m, int64_t ldt,
 
 /* Exact SVD of the m x m matrix T (Eq. (8)): leading k left singular vectors
  * u (device m x k doubles) and singular values sigma (device, k doubles),
- * via the FP64 symmetric eigen-decomposition of T T^T.  m <= 4096. */
+ * via the FP64 symmetric eigen-decomposition of T T^T.  m <= 1024. */
 ssi_status ssi_svd_full(ssi_ctx *ctx, const float *t, int64_t m, int64_t ldt,
                         int32_t k, double *u, double *sigma);
 
-/* Modal stage for one lag (Eq. (9)-(12)): for every order of p, O = U_n
- * S_n^1/2, C = first l rows, A = pinv(O_top) O_bot, eig(A), poles.
- * u: device m x k doubles (ld k), sigma: device k doubles, m = jb l.
- * Writes lag slot `lag_index` of `out` (sigma is not written). */
+/* Modal stage for one lag (Eq. (9)-(12)): for every order n of p, O = U_n
+ * S_n^1/2, C = first l rows, A = pinv(O_top) O_bot, eig(A), poles.  Computed
+ * through the similar matrix pinv(U_top,n) U_bot,n, which has the same
+ * eigenvalues, with phi = U[0:l, :n] psi (so sigma only scales and is not
+ * read).  u: device m x k doubles (ld k), sigma: device k doubles, m = jb l,
+ * order_max <= min(k, m - l, 224).  Writes lag slot `lag_index` of `out`
+ * (out->sigma is not written). */
 ssi_status ssi_modal(ssi_ctx *ctx, const double *u, const double *sigma,
                      int64_t m, int32_t k, int32_t l, const ssi_params *p,
                      int32_t lag_index, const ssi_output *out);

@@ -51,6 +51,13 @@ struct ssi_ctx {
   char *ws = nullptr;        // workspace arena
   size_t ws_cap = 0;
   size_t ws_top = 0;
+  // stage timing
+  bool profiling = false;
+  std::vector<hipEvent_t> ev_pool;
+  struct Rec { int stage; hipEvent_t a, b; };
+  std::vector<Rec> recs;
+  double acc_ms[SSI_STAGE_COUNT] = {};
+  int32_t acc_calls[SSI_STAGE_COUNT] = {};
 };
 
 namespace {
@@ -101,6 +108,37 @@ ssi_status ws_reserve(ssi_ctx *c, size_t bytes) {
   c->ws_cap = cap;
   return SSI_OK;
 }
+
+hipEvent_t take_event(ssi_ctx *c) {
+  if (!c->ev_pool.empty()) {
+    hipEvent_t e = c->ev_pool.back();
+    c->ev_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Records an event pair around a stage when profiling is on.
+struct StageTimer {
+  ssi_ctx *c;
+  int stage;
+  hipEvent_t a = nullptr;
+  StageTimer(ssi_ctx *ctx, int s) : c(ctx), stage(s) {
+    if (c && c->profiling) {
+      a = take_event(c);
+      if (a) (void)hipEventRecord(a, c->stream);
+    }
+  }
+  ~StageTimer() {
+    if (!a) return;
+    hipEvent_t b = take_event(c);
+    if (!b) return;
+    (void)hipEventRecord(b, c->stream);
+    c->recs.push_back({stage, a, b});
+  }
+};
 
 template <typename T>
 T *ws_take(ssi_ctx *c, size_t count) {
@@ -165,6 +203,11 @@ void ssi_destroy(ssi_ctx *c) {
   (void)hipStreamSynchronize(c->stream);
   if (c->ws) (void)hipFree(c->ws);
   if (c->status) (void)hipFree(c->status);
+  for (auto &r : c->recs) {
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
+  }
+  for (auto e : c->ev_pool) (void)hipEventDestroy(e);
   delete c;
 }
 
@@ -183,6 +226,36 @@ ssi_status ssi_synchronize(ssi_ctx *c) {
 }
 
 size_t ssi_workspace_bytes(const ssi_ctx *c) { return c ? c->ws_cap : 0; }
+
+ssi_status ssi_set_profiling(ssi_ctx *c, int enable) {
+  if (!c) return fail(SSI_EINVAL, "ssi_set_profiling: NULL context");
+  c->profiling = enable != 0;
+  return SSI_OK;
+}
+
+ssi_status ssi_profile_read(ssi_ctx *c, double *ms, int32_t *calls, int32_t n_stages) {
+  if (!c || !ms || !calls || n_stages < 0) return fail(SSI_EINVAL, "ssi_profile_read: bad argument");
+  DeviceGuard g(c->device);
+  SSI_HIP(hipStreamSynchronize(c->stream));
+  for (auto &r : c->recs) {
+    float t = 0.f;
+    SSI_HIP(hipEventElapsedTime(&t, r.a, r.b));
+    c->acc_ms[r.stage] += t;
+    c->acc_calls[r.stage] += 1;
+    c->ev_pool.push_back(r.a);
+    c->ev_pool.push_back(r.b);
+  }
+  c->recs.clear();
+  for (int i = 0; i < n_stages; ++i) {
+    ms[i] = i < SSI_STAGE_COUNT ? c->acc_ms[i] : 0.0;
+    calls[i] = i < SSI_STAGE_COUNT ? c->acc_calls[i] : 0;
+  }
+  for (int i = 0; i < SSI_STAGE_COUNT; ++i) {
+    c->acc_ms[i] = 0.0;
+    c->acc_calls[i] = 0;
+  }
+  return SSI_OK;
+}
 
 // ------------------------------------------------------------ host helpers
 double ssi_tau(int32_t jb, double fs) { return (2.0 * jb - 1.0) / fs; }
@@ -231,15 +304,18 @@ ssi_status ssi_validate(const ssi_params *p, int32_t l, int64_t n) {
       if ((int64_t)p->rank + p->oversample > m)
         return fail(SSI_EINVAL, "k + p = %d exceeds the Toeplitz size %lld",
                     p->rank + p->oversample, (long long)m);
-      if (p->rank + p->oversample > 1024)
-        return fail(SSI_EINVAL, "k + p = %d exceeds 1024", p->rank + p->oversample);
+      if (p->rank + p->oversample > ssi::dense_max_n())
+        return fail(SSI_EINVAL, "k + p = %d exceeds %d", p->rank + p->oversample,
+                    ssi::dense_max_n());
     } else {
-      if (m > 4096) return fail(SSI_EINVAL, "full SVD supports Toeplitz size <= 4096, got %lld",
-                                (long long)m);
+      if (m > ssi::dense_max_n())
+        return fail(SSI_EINVAL, "full SVD supports Toeplitz size <= %d, got %lld",
+                    ssi::dense_max_n(), (long long)m);
       if (p->order_max > m) return fail(SSI_EINVAL, "order_max exceeds the Toeplitz size");
     }
   }
-  if (p->order_max > 1024) return fail(SSI_EINVAL, "order_max must be <= 1024");
+  if (p->order_max > ssi::modal_max_order())
+    return fail(SSI_EINVAL, "order_max must be <= %d", ssi::modal_max_order());
   return SSI_OK;
 }
 
@@ -317,7 +393,8 @@ struct RsvdBufs {
   int ell, ellp;
 };
 
-RsvdBufs carve_rsvd(Arena &a, ssi_ctx *c, int64_t m, int ell, int k) {
+RsvdBufs carve_rsvd(Arena &a, ssi_ctx *c, int64_t m, int ell, int k,
+                    const int64_t *m_all = nullptr, int n_m = 0) {
   RsvdBufs b{};
   b.ell = ell;
   b.ellp = (ell + 3) & ~3;
@@ -332,8 +409,12 @@ RsvdBufs carve_rsvd(Arena &a, ssi_ctx *c, int64_t m, int ell, int k) {
   b.evals = a.take<double>(ell);
   b.evecs = a.take<double>((size_t)ell * ell);
   b.dws = a.take<double>(ssi::dense_ws_doubles(ell));
-  const size_t part = std::max({part_f32(mi, ell, mi, cu), part_f64(ell, ell, mi, cu),
-                                part_f64(mi, ell, ell, cu), part_f64(mi, k, ell, cu)});
+  size_t part = 0;
+  for (int i = 0; i < (m_all ? n_m : 1); ++i) {
+    const int mm = m_all ? (int)m_all[i] : mi;
+    part = std::max({part, part_f32(mm, ell, mm, cu), part_f64(ell, ell, mm, cu),
+                     part_f64(mm, ell, ell, cu), part_f64(mm, k, ell, cu)});
+  }
   b.part = a.take<double>(part);
   return b;
 }
@@ -365,31 +446,51 @@ ssi_status run_rsvd(ssi_ctx *c, RsvdBufs &b, const float *t, int64_t m, int64_t 
                     double *sigma) {
   const int ell = k + p, mi = (int)m;
   hipError_t e;
-  if (omega)
-    e = hipMemcpy2DAsync(b.om32, (size_t)b.ellp * 4, omega, (size_t)ell * 4, (size_t)ell * 4,
-                         (size_t)m, hipMemcpyDeviceToDevice, c->stream);
-  else
-    e = ssi::launch_sketch(seed, stream, m, ell, b.om32, b.ellp, c->stream);
+  {
+    StageTimer tm(c, SSI_STAGE_SKETCH);
+    if (omega)
+      e = hipMemcpy2DAsync(b.om32, (size_t)b.ellp * 4, omega, (size_t)ell * 4, (size_t)ell * 4,
+                           (size_t)m, hipMemcpyDeviceToDevice, c->stream);
+    else
+      e = ssi::launch_sketch(seed, stream, m, ell, b.om32, b.ellp, c->stream);
+  }
   if (e != hipSuccess) return hip_fail(e, "sketch");
   // Y = T Omega, Q = orth(Y)
-  e = prod_f32(c, false, t, ldt, b.om32, b.ellp, mi, ell, mi, b.part, b.ya, ell);
+  {
+    StageTimer tm(c, SSI_STAGE_PRODUCTS);
+    e = prod_f32(c, false, t, ldt, b.om32, b.ellp, mi, ell, mi, b.part, b.ya, ell);
+  }
   if (e != hipSuccess) return hip_fail(e, "Y = T Omega");
-  double *Q = orthonormalize(c, b, b.ya, b.yb, m, e);
+  double *Q;
+  {
+    StageTimer tm(c, SSI_STAGE_ORTH);
+    Q = orthonormalize(c, b, b.ya, b.yb, m, e);
+  }
   if (e != hipSuccess) return hip_fail(e, "orthonormalize");
   // power iterations: Q = orth(T^T Q), Q = orth(T Q)
   for (int it = 0; it < q; ++it) {
     for (int side = 0; side < 2; ++side) {
       double *other = (Q == b.ya) ? b.yb : b.ya;
-      e = prod_f32(c, side == 0, t, ldt, b.x32, b.ellp, mi, ell, mi, b.part, other, ell);
+      {
+        StageTimer tm(c, SSI_STAGE_PRODUCTS);
+        e = prod_f32(c, side == 0, t, ldt, b.x32, b.ellp, mi, ell, mi, b.part, other, ell);
+      }
       if (e != hipSuccess) return hip_fail(e, "power iteration product");
-      Q = orthonormalize(c, b, other, Q, m, e);
+      {
+        StageTimer tm(c, SSI_STAGE_ORTH);
+        Q = orthonormalize(c, b, other, Q, m, e);
+      }
       if (e != hipSuccess) return hip_fail(e, "orthonormalize");
     }
   }
   // P^T = T^T Q; G = P P^T; G = U~ S^2 U~^T; U = Q U~[:, :k]
   double *pt = (Q == b.ya) ? b.yb : b.ya;
-  e = prod_f32(c, true, t, ldt, b.x32, b.ellp, mi, ell, mi, b.part, pt, ell);
+  {
+    StageTimer tm(c, SSI_STAGE_PRODUCTS);
+    e = prod_f32(c, true, t, ldt, b.x32, b.ellp, mi, ell, mi, b.part, pt, ell);
+  }
   if (e != hipSuccess) return hip_fail(e, "P^T = T^T Q");
+  StageTimer tm_small(c, SSI_STAGE_SMALL_SVD);
   e = prod_f64(c, true, pt, ell, pt, ell, ell, ell, mi, b.part, b.gm, ell);
   if (e != hipSuccess) return hip_fail(e, "P P^T");
   e = ssi::launch_sym_eig(b.gm, ell, ell, b.evals, b.evecs, ell, b.dws, c->status, c->stream);
@@ -435,6 +536,169 @@ ssi_status run_svd_full(ssi_ctx *c, FullBufs &b, const float *t, int m, int64_t 
   return SSI_OK;
 }
 
+// ------------------------------------------------------------ modal stage
+struct ModalBufs {
+  ssi::ModalSizes sz;
+  double *gt, *hm, *rinv, *lws, *w, *dws, *part;
+  double *xbuf, *hbuf, *qbuf, *vref, *taus, *chbuf, *evbuf, *gscr, *vscr;
+  double *tf, *txi, *tmu, *tphi;
+  int *npole, *pidx, *flags_tmp;
+};
+
+ModalBufs carve_modal(Arena &a, ssi_ctx *c, int64_t m, int l, const ssi_params *p) {
+  ModalBufs b{};
+  const int nmax = p->order_max;
+  b.sz = ssi::modal_sizes(p->order_min, nmax, p->order_step, l);
+  const int cu = c->num_cus;
+  const int kk = nmax;                       // leading columns used by the orders
+  b.gt = a.take<double>((size_t)kk * kk);
+  b.hm = a.take<double>((size_t)kk * kk);
+  b.rinv = a.take<double>((size_t)kk * kk);
+  b.lws = a.take<double>((size_t)kk * kk);
+  b.w = a.take<double>((size_t)kk * kk);
+  b.dws = a.take<double>(ssi::dense_ws_doubles(kk));
+  b.part = a.take<double>(std::max(part_f64(kk, kk, (int)(m - l), cu), part_f64(kk, kk, kk, cu)));
+  b.xbuf = a.take<double>(b.sz.sq);
+  b.hbuf = a.take<double>(b.sz.sq);
+  b.qbuf = a.take<double>(b.sz.sq);
+  b.vref = a.take<double>(b.sz.vref);
+  b.taus = a.take<double>(b.sz.taus);
+  b.chbuf = a.take<double>(b.sz.ch);
+  b.evbuf = a.take<double>(2 * b.sz.vec);
+  b.gscr = a.take<double>((size_t)b.sz.n_orders * b.sz.francis_glb);
+  b.vscr = a.take<double>((size_t)b.sz.vec_waves * b.sz.vec_stride);
+  b.tf = a.take<double>(b.sz.poles);
+  b.txi = a.take<double>(b.sz.poles);
+  b.tmu = a.take<double>(2 * b.sz.poles);
+  b.tphi = a.take<double>(2 * b.sz.poles * l);
+  b.npole = a.take<int>(b.sz.n_orders);
+  b.pidx = a.take<int>(b.sz.vec);
+  b.flags_tmp = a.take<int>(b.sz.n_orders);
+  return b;
+}
+
+// U: m x k (ld k).  Writes lag slot lag_i of out.
+ssi_status run_modal(ssi_ctx *c, ModalBufs &b, const double *u, int64_t m, int k, int l,
+                     const ssi_params *p, int lag_i, const ssi_output *out) {
+  const int kk = p->order_max, mt = (int)(m - l);
+  hipError_t e;
+  StageTimer tm_ls(c, SSI_STAGE_SHIFT_LS);
+  // Gram matrices of the shifted observability blocks (leading kk columns)
+  e = prod_f64(c, true, u, k, u, k, kk, kk, mt, b.part, b.gt, kk);
+  if (e != hipSuccess) return hip_fail(e, "U_top^T U_top");
+  e = prod_f64(c, true, u, k, u + (int64_t)l * k, k, kk, kk, mt, b.part, b.hm, kk);
+  if (e != hipSuccess) return hip_fail(e, "U_top^T U_bot");
+  e = ssi::launch_chol_inv(b.gt, kk, kk, 0.0, b.rinv, kk, b.lws, b.dws, c->status, c->stream);
+  if (e != hipSuccess) return hip_fail(e, "Cholesky of U_top^T U_top");
+  e = prod_f64(c, true, b.rinv, kk, b.hm, kk, kk, kk, kk, b.part, b.w, kk);
+  if (e != hipSuccess) return hip_fail(e, "W = R^-T H");
+  const int no = b.sz.n_orders;
+  int32_t pole_cap = 0;
+  for (int o = 0; o < no; ++o) pole_cap += (p->order_min + o * p->order_step) / 2;
+  ssi::ModalArgs a{};
+  a.sizes = b.sz;
+  a.nmin = p->order_min;
+  a.step = p->order_step;
+  a.ldw = kk;
+  a.ldu = k;
+  a.l = l;
+  a.fs = p->fs;
+  a.u = u;                    // C_h uses U[0:l, :n]
+  a.rinv = b.rinv;
+  a.w = b.w;
+  a.xbuf = b.xbuf; a.hbuf = b.hbuf; a.qbuf = b.qbuf; a.vref = b.vref; a.taus = b.taus;
+  a.chbuf = b.chbuf; a.evbuf = b.evbuf; a.gscr = b.gscr; a.vscr = b.vscr;
+  a.tf = b.tf; a.txi = b.txi; a.tmu = b.tmu; a.tphi = b.tphi;
+  a.npole = b.npole; a.pidx = b.pidx; a.flags_tmp = b.flags_tmp;
+  a.count = out->count + (int64_t)lag_i * no;
+  a.flags = out->flags + (int64_t)lag_i * no;
+  a.f = out->f + (int64_t)lag_i * pole_cap;
+  a.xi = out->xi + (int64_t)lag_i * pole_cap;
+  a.mu = out->mu + 2 * (int64_t)lag_i * pole_cap;
+  a.phi = out->phi + 2 * (int64_t)lag_i * pole_cap * l;
+  StageTimer tm_eig(c, SSI_STAGE_EIG);
+  e = ssi::launch_modal(a, c->stream);
+  if (e != hipSuccess) return hip_fail(e, "modal kernels");
+  return SSI_OK;
+}
+
+// ------------------------------------------------------------ identification
+struct IdentBufs {
+  ssi::CorrPlan cp;
+  double *corr_part;
+  float *r;
+  float *t;
+  int64_t ldt;
+  double *u, *sig;
+  RsvdBufs rb;
+  FullBufs fb;
+  ModalBufs mb;
+};
+
+IdentBufs carve_identify(Arena &a, ssi_ctx *c, int l, int64_t n, const ssi_params *p) {
+  IdentBufs b{};
+  const int L = 2 * p->lags[p->n_lags - 1] - 1;
+  const int64_t mmax = (int64_t)p->lags[p->n_lags - 1] * l;
+  b.cp = ssi::plan_correlate(l, n, L, c->num_cus);
+  b.corr_part = a.take<double>(b.cp.partial_elems);
+  b.r = a.take<float>((size_t)L * l * l);
+  b.ldt = (mmax + 3) & ~int64_t(3);
+  b.t = a.take<float>((size_t)mmax * b.ldt);
+  const int kcols = p->svd == SSI_SVD_RANDOMIZED ? p->rank : p->order_max;
+  b.u = a.take<double>((size_t)mmax * kcols);
+  b.sig = a.take<double>(kcols);
+  if (p->svd == SSI_SVD_RANDOMIZED) {
+    std::vector<int64_t> ms(p->n_lags);
+    for (int i = 0; i < p->n_lags; ++i) ms[i] = (int64_t)p->lags[i] * l;
+    b.rb = carve_rsvd(a, c, mmax, p->rank + p->oversample, p->rank, ms.data(), p->n_lags);
+  }
+  else b.fb = carve_full(a, c, (int)mmax);
+  b.mb = carve_modal(a, c, mmax, l, p);
+  return b;
+}
+
+ssi_status run_identify(ssi_ctx *c, IdentBufs &b, const float *y, int l, int64_t n,
+                        int64_t ldy, const ssi_params *p, const ssi_output *out) {
+  const int L = 2 * p->lags[p->n_lags - 1] - 1;
+  hipError_t e;
+  {
+    StageTimer tm(c, SSI_STAGE_CORR_MFMA);
+    e = ssi::launch_correlate_mfma(b.cp, y, l, n, ldy, L, b.corr_part, c->stream);
+  }
+  if (e != hipSuccess) return hip_fail(e, "correlations");
+  {
+    StageTimer tm(c, SSI_STAGE_CORR_REDUCE);
+    e = ssi::launch_correlate_reduce(b.cp, l, n, L, b.corr_part, b.r, c->stream);
+  }
+  if (e != hipSuccess) return hip_fail(e, "correlation reduction");
+  const int kcols = p->svd == SSI_SVD_RANDOMIZED ? p->rank : p->order_max;
+  for (int i = 0; i < p->n_lags; ++i) {
+    const int jb = p->lags[i];
+    const int64_t m = (int64_t)jb * l;
+    const int64_t ldt = (m + 3) & ~int64_t(3);
+    {
+      StageTimer tm(c, SSI_STAGE_TOEPLITZ);
+      e = ssi::launch_toeplitz(b.r, l, jb, b.t, ldt, c->stream);
+    }
+    if (e != hipSuccess) return hip_fail(e, "Toeplitz");
+    ssi_status s;
+    if (p->svd == SSI_SVD_RANDOMIZED) {
+      // rebuild the RSVD views for this lag's m (buffers are sized for the largest)
+      s = run_rsvd(c, b.rb, b.t, m, ldt, p->rank, p->oversample, p->power_iters, nullptr,
+                   p->seed, (uint32_t)i, b.u, b.sig);
+    } else {
+      s = run_svd_full(c, b.fb, b.t, (int)m, ldt, kcols, b.u, b.sig);
+    }
+    if (s != SSI_OK) return s;
+    e = hipMemcpyAsync(out->sigma + (int64_t)i * kcols, b.sig, sizeof(double) * kcols,
+                       hipMemcpyDeviceToDevice, c->stream);
+    if (e != hipSuccess) return hip_fail(e, "sigma copy");
+    s = run_modal(c, b.mb, b.u, m, kcols, l, p, i, out);
+    if (s != SSI_OK) return s;
+  }
+  return SSI_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -453,7 +717,12 @@ ssi_status ssi_correlate(ssi_ctx *c, const float *y, int32_t l, int64_t n, int64
   ssi_status s = ws_reserve(c, aligned_bytes(cp.partial_elems, sizeof(double)));
   if (s != SSI_OK) return s;
   double *partial = ws_take<double>(c, cp.partial_elems);
-  SSI_HIP(ssi::launch_correlate(cp, y, l, n, ldy, n_corr, partial, r, c->stream));
+  {
+    StageTimer tm(c, SSI_STAGE_CORR_MFMA);
+    SSI_HIP(ssi::launch_correlate_mfma(cp, y, l, n, ldy, n_corr, partial, c->stream));
+  }
+  StageTimer tm(c, SSI_STAGE_CORR_REDUCE);
+  SSI_HIP(ssi::launch_correlate_reduce(cp, l, n, n_corr, partial, r, c->stream));
   return SSI_OK;
 }
 
@@ -466,6 +735,7 @@ ssi_status ssi_toeplitz(ssi_ctx *c, const float *r, int32_t l, int32_t jb, float
   DeviceGuard g(c->device);
   if (!is_device_ptr(r) || !is_device_ptr(t))
     return fail(SSI_EINVAL, "ssi_toeplitz: r and t must be device pointers");
+  StageTimer tm(c, SSI_STAGE_TOEPLITZ);
   SSI_HIP(ssi::launch_toeplitz(r, l, jb, t, ldt, c->stream));
   return SSI_OK;
 }
@@ -485,9 +755,10 @@ ssi_status ssi_workspace_estimate(const ssi_params *p, int32_t l, int64_t n, siz
   ssi_status s = ssi_validate(p, l, n);
   if (s != SSI_OK) return s;
   if (!bytes) return fail(SSI_EINVAL, "bytes is NULL");
-  const int L = 2 * p->lags[p->n_lags - 1] - 1;
-  const ssi::CorrPlan cp = ssi::plan_correlate(l, n, L, 256);
-  *bytes = corr_bytes(cp, l, L);
+  ssi_ctx probe_ctx;
+  Arena a;
+  carve_identify(a, &probe_ctx, l, n, p);
+  *bytes = a.off;
   return SSI_OK;
 }
 
@@ -535,14 +806,44 @@ ssi_status ssi_svd_full(ssi_ctx *c, const float *t, int64_t m, int64_t ldt, int3
   return run_svd_full(c, b, t, (int)m, ldt, k, u, sigma);
 }
 
-ssi_status ssi_modal(ssi_ctx *, const double *, const double *, int64_t, int32_t, int32_t,
-                     const ssi_params *, int32_t, const ssi_output *) {
-  return fail(SSI_EINTERNAL, "ssi_modal: not built yet");
+ssi_status ssi_modal(ssi_ctx *c, const double *u, const double *sigma, int64_t m, int32_t k,
+                     int32_t l, const ssi_params *p, int32_t lag_index, const ssi_output *out) {
+  (void)sigma;   // the eigenvalues of A do not depend on S (similarity); kept for the ABI
+  if (!c || !u || !p || !out) return fail(SSI_EINVAL, "ssi_modal: NULL argument");
+  if (l < 1 || m <= l || k < 1) return fail(SSI_EINVAL, "ssi_modal: need 1 <= l < m, k >= 1");
+  if (p->order_step < 1 || p->order_min < 1 || p->order_max < p->order_min ||
+      p->order_max > k || p->order_max > m - l || p->order_max > ssi::modal_max_order())
+    return fail(SSI_EINVAL, "ssi_modal: need 1 <= order_min <= order_max <= min(k, m - l, %d)",
+                ssi::modal_max_order());
+  if (!(p->fs > 0.0)) return fail(SSI_EINVAL, "ssi_modal: fs must be > 0");
+  if (lag_index < 0 || lag_index >= p->n_lags) return fail(SSI_EINVAL, "ssi_modal: bad lag index");
+  DeviceGuard g(c->device);
+  Arena probe;
+  carve_modal(probe, c, m, l, p);
+  ssi_status s = ws_reserve(c, probe.off);
+  if (s != SSI_OK) return s;
+  Arena a{c->ws, 0};
+  ModalBufs b = carve_modal(a, c, m, l, p);
+  return run_modal(c, b, u, m, k, l, p, lag_index, out);
 }
 
-ssi_status ssi_identify(ssi_ctx *, const float *, int32_t, int64_t, int64_t, const ssi_params *,
-                        const ssi_output *) {
-  return fail(SSI_EINTERNAL, "ssi_identify: not built yet");
+ssi_status ssi_identify(ssi_ctx *c, const float *y, int32_t l, int64_t n, int64_t ldy,
+                        const ssi_params *p, const ssi_output *out) {
+  if (!c || !y || !p || !out) return fail(SSI_EINVAL, "ssi_identify: NULL argument");
+  ssi_status s = ssi_validate(p, l, n);
+  if (s != SSI_OK) return s;
+  if (ldy < n) return fail(SSI_EINVAL, "ssi_identify: ldy < n");
+  if (!out->sigma || !out->count || !out->f || !out->xi || !out->mu || !out->phi || !out->flags)
+    return fail(SSI_EINVAL, "ssi_identify: NULL output buffer");
+  DeviceGuard g(c->device);
+  if (!is_device_ptr(y)) return fail(SSI_EINVAL, "ssi_identify: y must be a device pointer");
+  Arena probe;
+  carve_identify(probe, c, l, n, p);
+  s = ws_reserve(c, probe.off);
+  if (s != SSI_OK) return s;
+  Arena a{c->ws, 0};
+  IdentBufs b = carve_identify(a, c, l, n, p);
+  return run_identify(c, b, y, l, n, ldy, p, out);
 }
 
 }  // extern "C"

@@ -193,9 +193,8 @@ CorrPlan plan_correlate(int l, int64_t n, int L, int num_cus) {
   return p;
 }
 
-hipError_t launch_correlate(const CorrPlan &p, const float *y, int l, int64_t n,
-                            int64_t ldy, int L, double *partial, float *r,
-                            hipStream_t st) {
+hipError_t launch_correlate_mfma(const CorrPlan &p, const float *y, int l, int64_t n, int64_t ldy,
+                                 int L, double *partial, hipStream_t st) {
   dim3 grid(p.grid_rows, p.grid_cols, p.splits);
   if (p.lds_bytes > 65536) {
     hipError_t e = hipFuncSetAttribute((const void *)correlate_mfma,
@@ -205,14 +204,24 @@ hipError_t launch_correlate(const CorrPlan &p, const float *y, int l, int64_t n,
   }
   hipLaunchKernelGGL(correlate_mfma, grid, dim3(256), p.lds_bytes, st, y, l, n, ldy, L,
                      p.split_len, partial, p.sa_stride, p.na_max);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
+  return hipGetLastError();
+}
+
+hipError_t launch_correlate_reduce(const CorrPlan &p, int l, int64_t n, int L,
+                                   const double *partial, float *r, hipStream_t st) {
   const int64_t total = (int64_t)l * L * l;
   int blocks = (int)ceil_div<int64_t>(total, 256);
   if (blocks > 65535 * 8) blocks = 65535 * 8;
   hipLaunchKernelGGL(correlate_reduce, dim3(blocks), dim3(256), 0, st, partial, l, L,
                      p.splits, 1.0 / (double)n, r);
   return hipGetLastError();
+}
+
+hipError_t launch_correlate(const CorrPlan &p, const float *y, int l, int64_t n, int64_t ldy,
+                            int L, double *partial, float *r, hipStream_t st) {
+  hipError_t e = launch_correlate_mfma(p, y, l, n, ldy, L, partial, st);
+  if (e != hipSuccess) return e;
+  return launch_correlate_reduce(p, l, n, L, partial, r, st);
 }
 
 }  // namespace ssi

@@ -20,6 +20,10 @@ struct CorrPlan {
 CorrPlan plan_correlate(int l, int64_t n, int L, int num_cus);
 hipError_t launch_correlate(const CorrPlan &p, const float *y, int l, int64_t n, int64_t ldy,
                             int L, double *partial, float *r, hipStream_t st);
+hipError_t launch_correlate_mfma(const CorrPlan &p, const float *y, int l, int64_t n, int64_t ldy,
+                                 int L, double *partial, hipStream_t st);
+hipError_t launch_correlate_reduce(const CorrPlan &p, int l, int64_t n, int L,
+                                   const double *partial, float *r, hipStream_t st);
 
 // ---- Toeplitz (toeplitz.hip)
 hipError_t launch_toeplitz(const float *r, int l, int jb, float *t, int64_t ldt,
@@ -60,5 +64,30 @@ hipError_t launch_chol_inv(const double *G, int64_t ldg, int n, double shift_rel
                            int64_t ldr, double *Lws, double *ws, int *status, hipStream_t st);
 hipError_t launch_sym_eig(const double *G, int64_t ldg, int n, double *evals, double *evecs,
                           int64_t ldv, double *ws, int *status, hipStream_t st);
+
+// ---- modal stage (modal.hip)
+int modal_max_order();
+struct ModalSizes {
+  int n_orders;
+  int64_t sq, vec, poles;       // sums over orders of n^2, n, n/2
+  int64_t vref, taus, ch;       // doubles
+  int64_t vec_waves, vec_stride, francis_glb;
+};
+ModalSizes modal_sizes(int nmin, int nmax, int step, int l);
+struct ModalArgs {
+  ModalSizes sizes;
+  int nmin, step, l;
+  int ldw;                      // leading dimension of rinv and w
+  int ldu;                      // leading dimension of u
+  double fs;
+  const double *u, *rinv, *w;
+  double *xbuf, *hbuf, *qbuf, *vref, *taus, *chbuf, *evbuf, *gscr, *vscr;
+  double *tf, *txi, *tmu, *tphi;
+  int *npole, *pidx, *flags_tmp;
+  int32_t *count, *flags;       // outputs of this lag
+  double *f, *xi, *mu;
+  float *phi;
+};
+hipError_t launch_modal(const ModalArgs &a, hipStream_t st);
 
 }  // namespace ssi

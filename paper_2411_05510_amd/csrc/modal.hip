@@ -1,0 +1,793 @@
+// Modal stage for one lag, every model order at once (Eq. (9)-(12)).
+//
+// With O = U_n S_n^1/2 (Eq. (9)), the shift least squares of Eq. (10) gives
+//   A_n = S^-1/2 X_n S^1/2,  X_n = pinv(U_top,n) U_bot,n,
+// so A_n and X_n have the same eigenvalues and phi = C psi_A = U[0:l, :n] psi_X.
+// All orders share one Cholesky factorisation: with U_top^T U_top = R^T R and
+// W = R^-T U_top^T U_bot (both leading blocks nest because R^-1 is upper
+// triangular), X_n = R^-1[:n, :n] W[:n, :n].
+//
+// Per order n (one workgroup each):
+//   form_x      X_n = Rinv[:n,:n] W[:n,:n]
+//   hess        Householder reduction X_n = Q H Q^T (H upper Hessenberg),
+//               matrix held in registers over a 16 x 32 thread grid
+//   qform       Q explicitly, then C_h = U[0:l, :n] Q
+//   francis     eigenvalues of H by the Francis double-shift QR iteration with
+//               deflation, H packed in LDS (n <= 200) or in global scratch
+//   vec         per pole (Im mu > 0): inverse iteration on H - mu I in complex
+//               arithmetic (Hessenberg LU with partial pivoting), psi_H, then
+//               phi = C_h psi_H, normalised; lambda = ln(mu) f_s, f, xi
+//   sort        poles of the order sorted by (f, xi) into the output slots
+#include "common.h"
+#include "kernels.h"
+
+namespace {
+
+constexpr int kT = 512;                 // threads of the register-tile kernels
+constexpr int kTP = 14, kTQ = 7;        // 16 x 32 grid, n <= 224
+constexpr int kNR = 224;
+
+SSI_DEV int row_of(int tr, int p) { return tr + 16 * p; }
+SSI_DEV int col_of(int tc, int q) { return tc + 32 * q; }
+SSI_DEV double sel(bool c, double v) { return c ? v : 0.0; }
+
+SSI_DEV double col_group_sum(double v) {
+  v += __shfl_xor(v, 1, 64);
+  v += __shfl_xor(v, 2, 64);
+  v += __shfl_xor(v, 4, 64);
+  v += __shfl_xor(v, 8, 64);
+  return v;
+}
+
+struct OrderGeo {
+  int n;          // model order
+  int64_t sq;     // sum of n'^2 over earlier orders
+  int64_t vec;    // sum of n' over earlier orders
+  int pole;       // sum of n'/2 over earlier orders
+};
+
+SSI_DEV OrderGeo order_geo(int o, int nmin, int step) {
+  OrderGeo g{nmin + o * step, 0, 0, 0};
+  for (int i = 0; i < o; ++i) {
+    const int m = nmin + i * step;
+    g.sq += (int64_t)m * m;
+    g.vec += m;
+    g.pole += m / 2;
+  }
+  return g;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ form_x
+// X_n[i][j] = sum_{r=i}^{n-1} Rinv[i][r] W[r][j]
+__global__ void __launch_bounds__(256)
+form_x_kernel(const double *__restrict__ rinv, const double *__restrict__ w, int k, int nmin,
+              int step, double *__restrict__ xbuf) {
+  const OrderGeo g = order_geo(blockIdx.y, nmin, step);
+  const int n = g.n;
+  double *x = xbuf + g.sq;
+  const int total = n * n;
+  for (int idx = blockIdx.x * 256 + threadIdx.x; idx < total; idx += gridDim.x * 256) {
+    const int i = idx / n, j = idx - i * n;
+    double s = 0.0;
+    for (int r = i; r < n; ++r) s += rinv[(int64_t)i * k + r] * w[(int64_t)r * k + j];
+    x[idx] = s;
+  }
+}
+
+// ------------------------------------------------------------------ hess
+// Householder reduction of X_n (n <= 224) to upper Hessenberg form.  Writes H
+// (n x n, ld n) to hbuf, reflector vectors (rows of kNR) to vref and their
+// scalars to taus.
+__global__ void __launch_bounds__(kT)
+hess_kernel(const double *__restrict__ xbuf, int nmin, int step, double *__restrict__ hbuf,
+            double *__restrict__ vref, double *__restrict__ taus) {
+  __shared__ double vbuf[kNR];
+  __shared__ double ypart[8][kNR];
+  __shared__ double stau;
+  const OrderGeo geo = order_geo(blockIdx.x, nmin, step);
+  const int n = geo.n;
+  const double *X = xbuf + geo.sq;
+  double *H = hbuf + geo.sq;
+  double *vr = vref + (size_t)blockIdx.x * kNR * kNR;
+  double *tv = taus + (size_t)blockIdx.x * kNR;
+  const int t = threadIdx.x, tr = t & 15, tc = t >> 4, lane = t & 63, wave = t >> 6;
+  double g[kTP][kTQ];
+#pragma unroll
+  for (int p = 0; p < kTP; ++p)
+#pragma unroll
+    for (int q = 0; q < kTQ; ++q) {
+      const int i = row_of(tr, p), j = col_of(tc, q);
+      g[p][q] = sel(i < n && j < n, X[(int64_t)min(i, n - 1) * n + min(j, n - 1)]);
+    }
+  for (int k = 0; k + 2 < n; ++k) {
+    const int kq = k >> 5;
+    if (tc == (k & 31)) {
+      double s2 = 0.0, x1 = 0.0;
+#pragma unroll
+      for (int p = 0; p < kTP; ++p) {
+        const int i = row_of(tr, p);
+        double v = 0.0;
+#pragma unroll
+        for (int q = 0; q < kTQ; ++q) v = (q == kq) ? g[p][q] : v;
+        x1 += sel(i == k + 1, v);
+        s2 += sel(i > k + 1 && i < n, v * v);
+      }
+      s2 = col_group_sum(s2);
+      x1 = col_group_sum(x1);
+      double tau = 0.0, v1 = 0.0;
+      if (s2 > 0.0) {
+        const double alpha = -copysign(sqrt(x1 * x1 + s2), x1);
+        v1 = x1 - alpha;
+        tau = 2.0 / (s2 + v1 * v1);
+      }
+#pragma unroll
+      for (int p = 0; p < kTP; ++p) {
+        const int i = row_of(tr, p);
+        double gv = 0.0;
+#pragma unroll
+        for (int q = 0; q < kTQ; ++q) gv = (q == kq) ? g[p][q] : gv;
+        if (i < n) {
+          const double v = (i == k + 1) ? v1 : sel(i > k + 1, gv);
+          vbuf[i] = v;
+          vr[(size_t)k * kNR + i] = v;
+        }
+      }
+      if (tr == 0) {
+        stau = tau;
+        tv[k] = tau;
+      }
+    }
+    __syncthreads();
+    const double tau = stau;
+    if (tau != 0.0) {
+      // left: X -= tau v (v^T X)
+      double zq[kTQ];
+#pragma unroll
+      for (int q = 0; q < kTQ; ++q) zq[q] = 0.0;
+#pragma unroll
+      for (int p = 0; p < kTP; ++p) {
+        const int i = row_of(tr, p);
+        const double vi = sel(i > k && i < n, vbuf[min(i, kNR - 1)]);
+#pragma unroll
+        for (int q = 0; q < kTQ; ++q) zq[q] += vi * g[p][q];
+      }
+#pragma unroll
+      for (int q = 0; q < kTQ; ++q) zq[q] = tau * col_group_sum(zq[q]);
+      double vj[kTQ];
+#pragma unroll
+      for (int q = 0; q < kTQ; ++q) {
+        const int j = col_of(tc, q);
+        vj[q] = sel(j > k && j < n, vbuf[min(j, kNR - 1)]);
+      }
+#pragma unroll
+      for (int p = 0; p < kTP; ++p) {
+        const int i = row_of(tr, p);
+        const double vi = sel(i > k && i < n, vbuf[min(i, kNR - 1)]);
+        double acc = 0.0;
+#pragma unroll
+        for (int q = 0; q < kTQ; ++q) {
+          g[p][q] -= vi * zq[q];
+          acc += g[p][q] * vj[q];
+        }
+        // right: y = X v (row sums over all 32 grid columns)
+        acc += __shfl_xor(acc, 16, 64);
+        acc += __shfl_xor(acc, 32, 64);
+        if ((lane >> 4) == 0) ypart[wave][i] = acc;
+      }
+      __syncthreads();
+#pragma unroll
+      for (int p = 0; p < kTP; ++p) {
+        const int i = row_of(tr, p);
+        double y = 0.0;
+#pragma unroll
+        for (int w = 0; w < 8; ++w) y += ypart[w][i];
+        y *= tau;
+#pragma unroll
+        for (int q = 0; q < kTQ; ++q) g[p][q] -= y * vj[q];
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int p = 0; p < kTP; ++p)
+#pragma unroll
+    for (int q = 0; q < kTQ; ++q) {
+      const int i = row_of(tr, p), j = col_of(tc, q);
+      if (i < n && j < n) H[(int64_t)i * n + j] = (j >= i - 1) ? g[p][q] : 0.0;
+    }
+}
+
+// ------------------------------------------------------------------ qform
+// Q = H_0 H_1 ... H_{n-3} (applied to the identity), written to qbuf.
+__global__ void __launch_bounds__(kT)
+qform_kernel(int nmin, int step, const double *__restrict__ vref,
+             const double *__restrict__ taus, double *__restrict__ qbuf) {
+  __shared__ double vbuf[kNR];
+  const OrderGeo geo = order_geo(blockIdx.x, nmin, step);
+  const int n = geo.n;
+  const double *vr = vref + (size_t)blockIdx.x * kNR * kNR;
+  const double *tv = taus + (size_t)blockIdx.x * kNR;
+  double *Q = qbuf + geo.sq;
+  const int t = threadIdx.x, tr = t & 15, tc = t >> 4;
+  double g[kTP][kTQ];
+#pragma unroll
+  for (int p = 0; p < kTP; ++p)
+#pragma unroll
+    for (int q = 0; q < kTQ; ++q)
+      g[p][q] = sel(row_of(tr, p) == col_of(tc, q) && row_of(tr, p) < n, 1.0);
+  for (int k = n - 3; k >= 0; --k) {
+    for (int i = t; i < n; i += kT) vbuf[i] = (i > k) ? vr[(size_t)k * kNR + i] : 0.0;
+    __syncthreads();
+    const double tau = tv[k];
+    if (tau != 0.0) {
+      double sq[kTQ];
+#pragma unroll
+      for (int q = 0; q < kTQ; ++q) sq[q] = 0.0;
+#pragma unroll
+      for (int p = 0; p < kTP; ++p) {
+        const int i = row_of(tr, p);
+        const double vi = sel(i > k && i < n, vbuf[min(i, kNR - 1)]);
+#pragma unroll
+        for (int q = 0; q < kTQ; ++q) sq[q] += vi * g[p][q];
+      }
+#pragma unroll
+      for (int q = 0; q < kTQ; ++q) sq[q] = tau * col_group_sum(sq[q]);
+#pragma unroll
+      for (int p = 0; p < kTP; ++p) {
+        const int i = row_of(tr, p);
+        const double vi = sel(i > k && i < n, vbuf[min(i, kNR - 1)]);
+#pragma unroll
+        for (int q = 0; q < kTQ; ++q) g[p][q] -= vi * sq[q];
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int p = 0; p < kTP; ++p)
+#pragma unroll
+    for (int q = 0; q < kTQ; ++q) {
+      const int i = row_of(tr, p), j = col_of(tc, q);
+      if (i < n && j < n) Q[(int64_t)i * n + j] = g[p][q];
+    }
+}
+
+// C_h = U[0:l, :n] Q  (l x n per order, ld n)
+__global__ void __launch_bounds__(256)
+ch_kernel(const double *__restrict__ u, int k, int l, int nmin, int step,
+          const double *__restrict__ qbuf, double *__restrict__ chbuf) {
+  const OrderGeo geo = order_geo(blockIdx.y, nmin, step);
+  const int n = geo.n;
+  const double *Q = qbuf + geo.sq;
+  double *C = chbuf + (int64_t)l * geo.vec;
+  const int total = l * n;
+  for (int idx = blockIdx.x * 256 + threadIdx.x; idx < total; idx += gridDim.x * 256) {
+    const int a = idx / n, c = idx - a * n;
+    double s = 0.0;
+    for (int r = 0; r < n; ++r) s += u[(int64_t)a * k + r] * Q[(int64_t)r * n + c];
+    C[idx] = s;
+  }
+}
+
+// ------------------------------------------------------------------ francis
+namespace {
+
+// Upper Hessenberg matrix in packed rows (row 0: columns 0..n-1; row i >= 1:
+// columns i-1..n-1) plus the bulge entries (i, i-2) and (i, i-3) of the
+// Francis sweep, which live only near the current bulge (slots i mod 4).
+struct PackedH {
+  double *a;        // packed rows
+  double *b2, *b3;  // [4] bulge slots
+  int n;
+  SSI_DEV int64_t idx(int i, int j) const {
+    if (i == 0) return j;
+    return (int64_t)n + (int64_t)(i - 1) * (n + 1) - (int64_t)(i - 1) * i / 2 + (j - (i - 1));
+  }
+  SSI_DEV double get(int i, int j) const {
+    if (j >= i - 1) return a[idx(i, j)];
+    if (j == i - 2) return b2[i & 3];
+    if (j == i - 3) return b3[i & 3];
+    return 0.0;
+  }
+  SSI_DEV void set(int i, int j, double v) const {
+    if (j >= i - 1) a[idx(i, j)] = v;
+    else if (j == i - 2) b2[i & 3] = v;
+    else if (j == i - 3) b3[i & 3] = v;
+  }
+  static __host__ __device__ int64_t size(int n) {
+    return (int64_t)n + (int64_t)(n - 1) * (n + 2) / 2;
+  }
+};
+
+constexpr int kFT = 256;                 // francis threads
+constexpr int kLdsDoubles = 20300;       // packed H in LDS for n <= 200 (20299 doubles)
+
+SSI_DEV void two_by_two_eigs(double a, double b, double c, double d, double *wr, double *wi) {
+  const double p = 0.5 * (a - d);
+  const double disc = p * p + b * c;
+  const double mid = 0.5 * (a + d);
+  if (disc >= 0.0) {
+    const double r = sqrt(disc);
+    const double l1 = mid + copysign(r, mid == 0.0 ? 1.0 : mid);
+    const double det = a * d - b * c;
+    const double l2 = (l1 != 0.0) ? det / l1 : mid - copysign(r, mid == 0.0 ? 1.0 : mid);
+    wr[0] = l1; wi[0] = 0.0;
+    wr[1] = l2; wi[1] = 0.0;
+  } else {
+    const double im = sqrt(-disc);
+    wr[0] = mid; wi[0] = im;
+    wr[1] = mid; wi[1] = -im;
+  }
+}
+
+}  // namespace
+
+// Eigenvalues of H_n.  ev: [2][n] (re, im) per order at 2 * vec(o).  Writes
+// the count of eigenvalues with Im > 0 to npole[o] and their indices (in the
+// order found) to pidx at vec(o).  flags[o] = 1 if the iteration limit hit.
+template <bool LDS>
+__global__ void __launch_bounds__(kFT)
+francis_kernel(const double *__restrict__ hbuf, int nmin, int step, int o_first,
+               double *__restrict__ gscr, double *__restrict__ evbuf, int *__restrict__ npole,
+               int *__restrict__ pidx, int *__restrict__ flags) {
+  extern __shared__ double lds_h[];
+  __shared__ double bulge[8];
+  __shared__ int s_l;
+  __shared__ double s_x, s_y, s_z;
+  const int o = o_first + blockIdx.x;
+  const OrderGeo geo = order_geo(o, nmin, step);
+  const int n = geo.n;
+  const double *Hin = hbuf + geo.sq;
+  double *wr = evbuf + 2 * geo.vec, *wi = wr + n;
+  const int t = threadIdx.x;
+  PackedH H;
+  H.n = n;
+  H.a = LDS ? lds_h : gscr + (size_t)blockIdx.x * (size_t)PackedH::size(kNR);
+  H.b2 = bulge;
+  H.b3 = bulge + 4;
+  for (int i = 0; i < n; ++i) {
+    const int j0 = i == 0 ? 0 : i - 1;
+    for (int j = j0 + t; j < n; j += kFT) H.a[H.idx(i, j)] = Hin[(int64_t)i * n + j];
+  }
+  if (t < 8) bulge[t] = 0.0;
+  __syncthreads();
+
+  const double eps = 2.220446049250313e-16;
+  int hi = n - 1;
+  int iter = 0, total = 0;
+  const int itmax = 30 * max(10, n);
+  bool failed = false;
+  while (hi >= 0) {
+    // ---- deflation: largest l in (0, hi] with a negligible subdiagonal
+    if (t == 0) s_l = 0;
+    __syncthreads();
+    for (int i = 1 + t; i <= hi; i += kFT) {
+      const double sub = fabs(H.get(i, i - 1));
+      double ref = fabs(H.get(i - 1, i - 1)) + fabs(H.get(i, i));
+      if (ref == 0.0) {
+        if (i - 2 >= 0) ref += fabs(H.get(i - 1, i - 2));
+        if (i + 1 <= hi) ref += fabs(H.get(i + 1, i));
+      }
+      if (sub <= eps * ref) atomicMax(&s_l, i);
+    }
+    __syncthreads();
+    const int l = s_l;
+    if (l > 0 && t == 0) H.set(l, l - 1, 0.0);
+    if (l == hi) {                       // 1 x 1 block
+      if (t == 0) { wr[hi] = H.get(hi, hi); wi[hi] = 0.0; }
+      hi -= 1;
+      iter = 0;
+      __syncthreads();
+      continue;
+    }
+    if (l == hi - 1) {                   // 2 x 2 block
+      if (t == 0) {
+        double r2[2], i2[2];
+        two_by_two_eigs(H.get(hi - 1, hi - 1), H.get(hi - 1, hi), H.get(hi, hi - 1),
+                        H.get(hi, hi), r2, i2);
+        wr[hi - 1] = r2[0]; wi[hi - 1] = i2[0];
+        wr[hi] = r2[1]; wi[hi] = i2[1];
+      }
+      hi -= 2;
+      iter = 0;
+      __syncthreads();
+      continue;
+    }
+    if (++total > itmax) {
+      failed = true;
+      break;
+    }
+    ++iter;
+    // ---- shifts: eigenvalues of the trailing 2 x 2 block, or ad hoc shifts
+    double s, tt;
+    if (iter % 11 == 10) {
+      const double e = fabs(H.get(hi, hi - 1)) + fabs(H.get(hi - 1, hi - 2));
+      const double h11 = 0.75 * e + H.get(hi, hi), h12 = -0.4375 * e;
+      s = 2.0 * h11;
+      tt = h11 * h11 - h12 * e;
+    } else {
+      const double a = H.get(hi - 1, hi - 1), b = H.get(hi - 1, hi);
+      const double c = H.get(hi, hi - 1), d = H.get(hi, hi);
+      s = a + d;
+      tt = a * d - b * c;
+    }
+    // first column of (H - s1 I)(H - s2 I)
+    const double h00 = H.get(l, l), h01 = H.get(l, l + 1), h10 = H.get(l + 1, l);
+    const double h11 = H.get(l + 1, l + 1), h21 = H.get(l + 2, l + 1);
+    double x = h00 * h00 + h01 * h10 - s * h00 + tt;
+    double y = h10 * (h00 + h11 - s);
+    double z = h10 * h21;
+    for (int k = l; k <= hi - 1; ++k) {
+      const bool three = k < hi - 1;
+      // Householder reflector P = I - beta v v^T with P (x, y, z)^T = (alpha, 0, 0)^T
+      const double zz = three ? z : 0.0;
+      const double nrm = sqrt(x * x + y * y + zz * zz);
+      double v0 = 1.0, v1 = 0.0, v2 = 0.0, beta = 0.0;
+      if (nrm > 0.0 && (y != 0.0 || zz != 0.0)) {
+        const double alpha = -copysign(nrm, x);
+        const double u0 = x - alpha;
+        v1 = y / u0;
+        v2 = zz / u0;
+        beta = -u0 / alpha;            // 2 / (v^T v) with v = (1, v1, v2)
+      }
+      if (beta != 0.0) {
+        // rows k..k+2 (k+1 for the final 2 x 2 step), columns q..hi
+        const int q = max(l, k - 1);
+        for (int j = q + t; j <= hi; j += kFT) {
+          const double a0 = H.get(k, j), a1 = H.get(k + 1, j);
+          const double a2 = three ? H.get(k + 2, j) : 0.0;
+          const double d = beta * (a0 + v1 * a1 + v2 * a2);
+          H.set(k, j, a0 - d);
+          H.set(k + 1, j, a1 - d * v1);
+          if (three) H.set(k + 2, j, a2 - d * v2);
+        }
+        __syncthreads();
+        if (k > l && t == 0) {           // annihilated bulge entries
+          H.set(k + 1, k - 1, 0.0);
+          if (three) H.set(k + 2, k - 1, 0.0);
+        }
+        // columns k..k+2, rows l..min(k+3, hi)
+        const int r = min(k + 3, hi);
+        for (int i = l + t; i <= r; i += kFT) {
+          const double a0 = H.get(i, k), a1 = H.get(i, k + 1);
+          const double a2 = three ? H.get(i, k + 2) : 0.0;
+          const double d = beta * (a0 + v1 * a1 + v2 * a2);
+          H.set(i, k, a0 - d);
+          H.set(i, k + 1, a1 - d * v1);
+          if (three) H.set(i, k + 2, a2 - d * v2);
+        }
+      }
+      __syncthreads();
+      if (k < hi - 1) {
+        if (t == 0) {
+          s_x = H.get(k + 1, k);
+          s_y = H.get(k + 2, k);
+          s_z = (k < hi - 2) ? H.get(k + 3, k) : 0.0;
+        }
+        __syncthreads();
+        x = s_x;
+        y = s_y;
+        z = s_z;
+        __syncthreads();
+      }
+    }
+  }
+  if (t == 0) {
+    int cnt = 0;
+    if (!failed) {
+      for (int i = 0; i < n; ++i)
+        if (wi[i] > 0.0) pidx[geo.vec + cnt++] = i;
+    }
+    npole[o] = cnt;
+    flags[o] = failed ? 1 : 0;
+  }
+}
+
+// ------------------------------------------------------------------ vec
+namespace {
+
+struct cplx { double re, im; };
+SSI_DEV cplx cmul(cplx a, cplx b) { return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re}; }
+SSI_DEV cplx csub(cplx a, cplx b) { return {a.re - b.re, a.im - b.im}; }
+SSI_DEV double cabs1(cplx a) { return fabs(a.re) + fabs(a.im); }
+SSI_DEV cplx cdiv(cplx a, cplx b) {
+  // Smith's algorithm
+  if (fabs(b.re) >= fabs(b.im)) {
+    const double r = b.im / b.re, den = b.re + r * b.im;
+    return {(a.re + a.im * r) / den, (a.im - a.re * r) / den};
+  }
+  const double r = b.re / b.im, den = b.im + r * b.re;
+  return {(a.re * r + a.im) / den, (a.im * r - a.re) / den};
+}
+SSI_DEV double wsum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+SSI_DEV double wmax(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+  return v;
+}
+
+}  // namespace
+
+// One wave per pole.  Items (order, j) run over a persistent grid; each wave
+// owns scratch for the U rows of its LU.  Writes unsorted poles: f, xi, mu,
+// phi (l complex) at slot pole(o) + j of the temporary arrays.
+__global__ void __launch_bounds__(64)
+vec_kernel(const double *__restrict__ hbuf, const double *__restrict__ chbuf,
+           const double *__restrict__ evbuf, const int *__restrict__ npole,
+           const int *__restrict__ pidx, int nmin, int step, int n_orders, int l, double fs,
+           double *__restrict__ scratch, int64_t scratch_stride, double *__restrict__ tf,
+           double *__restrict__ txi, double *__restrict__ tmu, double *__restrict__ tphi) {
+  __shared__ double act_re[2][kNR], act_im[2][kNR];
+  __shared__ double x_re[kNR], x_im[kNR];
+  __shared__ double mult_re[kNR], mult_im[kNR];
+  __shared__ int swp[kNR];
+  const int lane = threadIdx.x;
+  double *ure = scratch + (size_t)blockIdx.x * scratch_stride;
+  double *uim = ure + scratch_stride / 2;
+  int total = 0;
+  for (int o = 0; o < n_orders; ++o) total += (nmin + o * step) / 2;
+  for (int item = blockIdx.x; item < total; item += gridDim.x) {
+    // locate (o, j)
+    int o = 0, rem = item;
+    while (rem >= (nmin + o * step) / 2) {
+      rem -= (nmin + o * step) / 2;
+      ++o;
+    }
+    const int j = rem;
+    const OrderGeo geo = order_geo(o, nmin, step);
+    const int n = geo.n;
+    if (j >= npole[o]) continue;
+    const double *Hn = hbuf + geo.sq;
+    const double *wr = evbuf + 2 * geo.vec, *wi = wr + n;
+    const int e = pidx[geo.vec + j];
+    const cplx mu{wr[e], wi[e]};
+    // U row r occupies [off(r), off(r) + n - r) with off(r) = r n - r (r - 1) / 2
+    auto uoff = [&](int r) { return (int64_t)r * n - (int64_t)r * (r - 1) / 2; };
+    double hnorm = 0.0;
+    for (int c = lane; c < n; c += 64) hnorm = fmax(hnorm, fabs(Hn[c]) + fabs(Hn[(int64_t)(n - 1) * n + c]));
+    hnorm = fmax(wmax(hnorm), cabs1(mu));
+    const double tiny = 2.220446049250313e-16 * fmax(hnorm, 1e-300);
+    // ---- LU of H - mu I with adjacent-row partial pivoting
+    int cur = 0;
+    for (int c = lane; c < n; c += 64) {
+      act_re[0][c] = Hn[c] - (c == 0 ? mu.re : 0.0);
+      act_im[0][c] = (c == 0 ? -mu.im : 0.0);
+    }
+    __syncthreads();
+    for (int r = 0; r + 1 < n; ++r) {
+      const cplx piv_a{act_re[cur][r], act_im[cur][r]};
+      const double sub = Hn[(int64_t)(r + 1) * n + r];
+      const bool swap = fabs(sub) > cabs1(piv_a);
+      cplx m;
+      if (swap) m = cdiv(piv_a, cplx{sub, 0.0});
+      else {
+        cplx pa = piv_a;
+        if (cabs1(pa) < tiny) pa = cplx{tiny, 0.0};
+        m = cdiv(cplx{sub, 0.0}, pa);
+      }
+      const int64_t off = uoff(r);
+      for (int c = r + lane; c < n; c += 64) {
+        const cplx arow{act_re[cur][c], act_im[cur][c]};
+        const cplx nrow{Hn[(int64_t)(r + 1) * n + c] - (c == r + 1 ? mu.re : 0.0),
+                        (c == r + 1 ? -mu.im : 0.0)};
+        const cplx urow = swap ? nrow : arow;
+        const cplx other = swap ? arow : nrow;
+        ure[off + (c - r)] = urow.re;
+        uim[off + (c - r)] = urow.im;
+        if (c > r) {
+          const cplx na = csub(other, cmul(m, urow));
+          act_re[cur ^ 1][c] = na.re;
+          act_im[cur ^ 1][c] = na.im;
+        }
+      }
+      if (lane == 0) {
+        mult_re[r] = m.re;
+        mult_im[r] = m.im;
+        swp[r] = swap;
+      }
+      if (!swap && lane == 0 && cabs1(piv_a) < tiny) ure[off] = tiny, uim[off] = 0.0;
+      cur ^= 1;
+      __syncthreads();
+    }
+    {
+      const int64_t off = uoff(n - 1);
+      if (lane == 0) {
+        cplx last{act_re[cur][n - 1], act_im[cur][n - 1]};
+        if (cabs1(last) < tiny) last = cplx{tiny, 0.0};
+        ure[off] = last.re;
+        uim[off] = last.im;
+      }
+    }
+    __syncthreads();
+    // ---- two solves: U x = 1, then (L U) x = x
+    for (int c = lane; c < n; c += 64) { x_re[c] = 1.0; x_im[c] = 0.0; }
+    __syncthreads();
+    for (int pass = 0; pass < 2; ++pass) {
+      if (pass == 1 && lane == 0) {
+        for (int r = 0; r + 1 < n; ++r) {
+          cplx bj{x_re[r], x_im[r]}, bn{x_re[r + 1], x_im[r + 1]};
+          if (swp[r]) { const cplx tmp = bj; bj = bn; bn = tmp; }
+          const cplx nb = csub(bn, cmul(cplx{mult_re[r], mult_im[r]}, bj));
+          x_re[r] = bj.re; x_im[r] = bj.im;
+          x_re[r + 1] = nb.re; x_im[r + 1] = nb.im;
+        }
+      }
+      __syncthreads();
+      for (int r = n - 1; r >= 0; --r) {
+        const int64_t off = uoff(r);
+        double sre = 0.0, sim = 0.0;
+        for (int c = r + 1 + lane; c < n; c += 64) {
+          const cplx uv{ure[off + (c - r)], uim[off + (c - r)]};
+          const cplx xv = cmul(uv, cplx{x_re[c], x_im[c]});
+          sre += xv.re;
+          sim += xv.im;
+        }
+        sre = wsum(sre);
+        sim = wsum(sim);
+        if (lane == 0) {
+          const cplx num = csub(cplx{x_re[r], x_im[r]}, cplx{sre, sim});
+          const cplx xr = cdiv(num, cplx{ure[off], uim[off]});
+          x_re[r] = xr.re;
+          x_im[r] = xr.im;
+        }
+        __syncthreads();
+      }
+      double mx = 0.0;
+      for (int c = lane; c < n; c += 64) mx = fmax(mx, cabs1(cplx{x_re[c], x_im[c]}));
+      mx = wmax(mx);
+      const double inv = mx > 0.0 ? 1.0 / mx : 1.0;
+      for (int c = lane; c < n; c += 64) { x_re[c] *= inv; x_im[c] *= inv; }
+      __syncthreads();
+    }
+    // ---- phi = C_h psi_H, unit 2-norm, largest-modulus entry real positive
+    const double *C = chbuf + (int64_t)l * geo.vec;
+    const int slot = geo.pole + j;
+    double *ph = tphi + (size_t)slot * l * 2;
+    double nrm2 = 0.0, best = -1.0, bre = 1.0, bim = 0.0;
+    for (int a = lane; a < l; a += 64) {
+      double sre = 0.0, sim = 0.0;
+      for (int c = 0; c < n; ++c) {
+        const double cv = C[(int64_t)a * n + c];
+        sre += cv * x_re[c];
+        sim += cv * x_im[c];
+      }
+      ph[2 * a] = sre;
+      ph[2 * a + 1] = sim;
+      const double m2 = sre * sre + sim * sim;
+      nrm2 += m2;
+      if (m2 > best) { best = m2; bre = sre; bim = sim; }
+    }
+    nrm2 = wsum(nrm2);
+    // lane holding the largest-modulus entry (ties: lowest lane)
+    double bmax = wmax(best);
+    const unsigned long long ball = __ballot(best == bmax);
+    const int src = __ffsll((long long)ball) - 1;
+    bre = __shfl(bre, src, 64);
+    bim = __shfl(bim, src, 64);
+    const double bm = sqrt(bre * bre + bim * bim);
+    const double inv = (nrm2 > 0.0 && bm > 0.0) ? 1.0 / (sqrt(nrm2) * bm) : 1.0;
+    // multiply by conj(b) / (|b| |phi|)
+    const double cre = bre * inv, cim = -bim * inv;
+    for (int a = lane; a < l; a += 64) {
+      const double pr = ph[2 * a], pi = ph[2 * a + 1];
+      ph[2 * a] = pr * cre - pi * cim;
+      ph[2 * a + 1] = pr * cim + pi * cre;
+    }
+    if (lane == 0) {
+      const double lr = 0.5 * log(mu.re * mu.re + mu.im * mu.im) * fs;
+      const double li = atan2(mu.im, mu.re) * fs;
+      const double al = sqrt(lr * lr + li * li);
+      tf[slot] = al / (2.0 * M_PI);
+      txi[slot] = -lr / al;
+      tmu[2 * slot] = mu.re;
+      tmu[2 * slot + 1] = mu.im;
+    }
+    __syncthreads();
+  }
+}
+
+// ------------------------------------------------------------------ sort
+// Poles of order o sorted by (f, xi), index as the final tie-break.
+__global__ void __launch_bounds__(256)
+sort_kernel(int nmin, int step, int l, const int *__restrict__ npole,
+            const int *__restrict__ flags_in, const double *__restrict__ tf,
+            const double *__restrict__ txi, const double *__restrict__ tmu,
+            const double *__restrict__ tphi, int32_t *__restrict__ count,
+            int32_t *__restrict__ flags_out, double *__restrict__ f, double *__restrict__ xi,
+            double *__restrict__ mu, float *__restrict__ phi) {
+  const int o = blockIdx.x;
+  const OrderGeo geo = order_geo(o, nmin, step);
+  const int cnt = npole[o];
+  const int base = geo.pole;
+  if (threadIdx.x == 0) {
+    count[o] = cnt;
+    flags_out[o] = flags_in[o];
+  }
+  for (int i = threadIdx.x; i < cnt; i += blockDim.x) {
+    const double fi = tf[base + i], xi_i = txi[base + i];
+    int rank = 0;
+    for (int j = 0; j < cnt; ++j) {
+      const double fj = tf[base + j], xj = txi[base + j];
+      rank += (fj < fi) || (fj == fi && (xj < xi_i || (xj == xi_i && j < i)));
+    }
+    const int dst = base + rank;
+    f[dst] = fi;
+    xi[dst] = xi_i;
+    mu[2 * dst] = tmu[2 * (base + i)];
+    mu[2 * dst + 1] = tmu[2 * (base + i) + 1];
+    for (int a = 0; a < l; ++a) {
+      phi[((size_t)dst * l + a) * 2] = (float)tphi[((size_t)(base + i) * l + a) * 2];
+      phi[((size_t)dst * l + a) * 2 + 1] = (float)tphi[((size_t)(base + i) * l + a) * 2 + 1];
+    }
+  }
+}
+
+// ------------------------------------------------------------------ launch
+namespace ssi {
+
+int modal_max_order() { return kNR; }
+
+size_t modal_francis_lds(int n) {
+  return n <= 200 ? sizeof(double) * kLdsDoubles : 0;
+}
+
+ModalSizes modal_sizes(int nmin, int nmax, int step, int l) {
+  ModalSizes s{};
+  s.n_orders = (nmax - nmin) / step + 1;
+  for (int o = 0; o < s.n_orders; ++o) {
+    const int64_t n = nmin + (int64_t)o * step;
+    s.sq += n * n;
+    s.vec += n;
+    s.poles += n / 2;
+  }
+  s.vref = (int64_t)s.n_orders * kNR * kNR;
+  s.taus = (int64_t)s.n_orders * kNR;
+  s.ch = (int64_t)l * s.vec;
+  s.vec_waves = 1024;
+  s.vec_stride = 2 * ((int64_t)kNR * (kNR + 1) / 2 + 64);
+  s.francis_glb = (int64_t)PackedH::size(kNR);
+  return s;
+}
+
+hipError_t launch_modal(const ModalArgs &a, hipStream_t st) {
+  const ModalSizes &s = a.sizes;
+  const int no = s.n_orders;
+  hipLaunchKernelGGL(form_x_kernel, dim3(64, no), dim3(256), 0, st, a.rinv, a.w, a.ldw, a.nmin,
+                     a.step, a.xbuf);
+  hipLaunchKernelGGL(hess_kernel, dim3(no), dim3(kT), 0, st, a.xbuf, a.nmin, a.step, a.hbuf,
+                     a.vref, a.taus);
+  hipLaunchKernelGGL(qform_kernel, dim3(no), dim3(kT), 0, st, a.nmin, a.step, a.vref, a.taus,
+                     a.qbuf);
+  hipLaunchKernelGGL(ch_kernel, dim3(32, no), dim3(256), 0, st, a.u, a.ldu, a.l, a.nmin, a.step,
+                     a.qbuf, a.chbuf);
+  // orders with n <= 200 keep H in LDS; larger ones use global scratch
+  int n_lds = 0;
+  for (int o = 0; o < no; ++o)
+    if (a.nmin + o * a.step <= 200) n_lds = o + 1;
+  if (n_lds > 0) {
+    hipError_t e = hipFuncSetAttribute((const void *)francis_kernel<true>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)(sizeof(double) * kLdsDoubles));
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(francis_kernel<true>, dim3(n_lds), dim3(kFT),
+                       sizeof(double) * kLdsDoubles, st, a.hbuf, a.nmin, a.step, 0, a.gscr,
+                       a.evbuf, a.npole, a.pidx, a.flags_tmp);
+  }
+  if (n_lds < no)
+    hipLaunchKernelGGL(francis_kernel<false>, dim3(no - n_lds), dim3(kFT), 0, st, a.hbuf,
+                       a.nmin, a.step, n_lds, a.gscr, a.evbuf, a.npole, a.pidx, a.flags_tmp);
+  hipLaunchKernelGGL(vec_kernel, dim3((unsigned)s.vec_waves), dim3(64), 0, st, a.hbuf, a.chbuf,
+                     a.evbuf, a.npole, a.pidx, a.nmin, a.step, no, a.l, a.fs, a.vscr,
+                     s.vec_stride, a.tf, a.txi, a.tmu, a.tphi);
+  hipLaunchKernelGGL(sort_kernel, dim3(no), dim3(256), 0, st, a.nmin, a.step, a.l, a.npole,
+                     a.flags_tmp, a.tf, a.txi, a.tmu, a.tphi, a.count, a.flags, a.f, a.xi, a.mu,
+                     a.phi);
+  return hipGetLastError();
+}
+
+}  // namespace ssi

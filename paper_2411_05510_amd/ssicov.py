@@ -11,6 +11,8 @@ from __future__ import annotations
 import ctypes
 import dataclasses
 import os
+
+import numpy as np
 from typing import List, Optional, Sequence
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -25,8 +27,12 @@ EXPORTED = (
     "ssi_validate", "ssi_output_layout", "ssi_pole_offset", "ssi_workspace_estimate",
     "ssi_tau", "ssi_lag_rule", "ssi_default_rank", "ssi_status_string",
     "ssi_last_error", "ssi_identify", "ssi_correlate", "ssi_toeplitz",
-    "ssi_sketch", "ssi_rsvd", "ssi_svd_full", "ssi_modal",
+    "ssi_sketch", "ssi_rsvd", "ssi_svd_full", "ssi_modal", "ssi_set_profiling",
+    "ssi_profile_read",
 )
+
+STAGES = ("corr_mfma", "corr_reduce", "toeplitz", "sketch", "products", "orth",
+          "small_svd", "shift_ls", "eig")
 
 
 class SSIError(RuntimeError):
@@ -96,6 +102,9 @@ def lib() -> ctypes.CDLL:
             "ssi_svd_full": ([vp, vp, i64, i64, i32, vp, vp], ctypes.c_int),
             "ssi_modal": ([vp, vp, vp, i64, i32, i32, P, i32, ctypes.POINTER(_Output)],
                           ctypes.c_int),
+            "ssi_set_profiling": ([vp, ctypes.c_int], ctypes.c_int),
+            "ssi_profile_read": ([vp, ctypes.POINTER(ctypes.c_double),
+                                  ctypes.POINTER(ctypes.c_int32), i32], ctypes.c_int),
         }
         for name, (args, res) in sig.items():
             fn = getattr(L, name)
@@ -212,6 +221,17 @@ class Context:
     def workspace_bytes(self) -> int:
         return int(lib().ssi_workspace_bytes(self._h))
 
+    def set_profiling(self, enable: bool) -> None:
+        _check(lib().ssi_set_profiling(self._h, 1 if enable else 0))
+
+    def profile_read(self) -> dict:
+        """{stage: (total ms, calls)} accumulated since the last read."""
+        n = len(STAGES)
+        ms = (ctypes.c_double * n)()
+        calls = (ctypes.c_int32 * n)()
+        _check(lib().ssi_profile_read(self._h, ms, calls, n))
+        return {name: (float(ms[i]), int(calls[i])) for i, name in enumerate(STAGES)}
+
     # ---------------------------------------------------------- stages
     def correlate(self, y, n_corr: int, out=None):
         """R (n_corr, l, l) float32 of the device record y (l, n) float32."""
@@ -321,7 +341,7 @@ class Output:
         cnt = int(self.count[lag_index, order_index].item())
         sl = slice(off, off + cnt)
         mu = self.mu[lag_index, sl].cpu().numpy()
-        phi = self.phi[lag_index, sl].cpu().numpy()
+        phi = self.phi[lag_index, sl].cpu().numpy().astype(np.float64)
         return {
             "f": self.f[lag_index, sl].cpu().numpy(),
             "xi": self.xi[lag_index, sl].cpu().numpy(),

@@ -1,0 +1,251 @@
+"""GPU parity of the modal stage and of the whole identification against the
+FP64 checker.
+
+Gates (FP32 path): singular values rel <= 1e-4 for sigma_i >= 1e-3 sigma_1;
+frequencies rel <= 1e-5 on physical poles.  A physical pole is a checker pole
+within 1 % in frequency and with MAC >= 0.9 to a generated mode; each must
+have a GPU pole at the same (lag, order), matched by nearest frequency.
+Damping and MAC of those poles are gated at abs 1e-4 and 0.9999.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2411_05510_amd import synth
+from modelref import mac, modal_correlations
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+F_RTOL = 1e-5
+XI_ATOL = 1e-4
+MAC_MIN = 0.9999
+SIGMA_RTOL, SIGMA_FLOOR = 1e-4, 1e-3
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_2411_05510_amd import ssicov
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    c = ssicov.Context(0)
+    yield c
+    c.close()
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def _params(wl, lags=None, **kw):
+    from paper_2411_05510_amd import ssicov
+    d = dict(fs=wl.fs, lags=list(lags or wl.lags), order_min=wl.order_min,
+             order_max=wl.order_max, order_step=wl.order_step,
+             svd=ssicov.SVD_FULL if wl.svd == "full" else ssicov.SVD_RANDOMIZED,
+             rank=wl.rank, oversample=wl.oversample, power_iters=wl.power_iters,
+             seed=wl.sketch_seed)
+    d.update(kw)
+    return ssicov.Params(**d)
+
+
+def _physical(poles, sysm, f_tol=0.01, mac_min=0.9):
+    """Indices of checker poles that are physical, with their mode index."""
+    out = []
+    for r, fr in enumerate(sysm.freqs):
+        if len(poles) == 0:
+            continue
+        i = int(np.argmin(np.abs(poles.f - fr)))
+        if abs(poles.f[i] - fr) / fr < f_tol and mac(poles.phi[i], sysm.shapes[:, r]) >= mac_min:
+            out.append(i)
+    return out
+
+
+def _compare_order(gpu, ref, phys, stats):
+    assert gpu["flag"] == 0
+    gf = gpu["f"]
+    for i in phys:
+        j = int(np.argmin(np.abs(gf - ref.f[i])))
+        ef = abs(gf[j] - ref.f[i]) / ref.f[i]
+        ex = abs(gpu["xi"][j] - ref.xi[i])
+        em = mac(gpu["phi"][j], ref.phi[i])
+        stats["f"].append(ef)
+        stats["xi"].append(ex)
+        stats["mac"].append(em)
+
+
+def _check_lag(out, lag_i, res, sysm, orders, stats):
+    for oi, order in enumerate(orders):
+        ref = res.poles[oi]
+        gpu = out.poles(lag_i, oi)
+        _compare_order(gpu, ref, _physical(ref, sysm), stats)
+        # every order: counts agree up to pole pairs at the real axis
+        assert abs(len(gpu["f"]) - len(ref)) <= 1 + len(ref) // 20
+
+
+def _assert_stats(stats):
+    assert stats["f"], "no physical poles compared"
+    f = np.array(stats["f"]); x = np.array(stats["xi"]); m = np.array(stats["mac"])
+    assert f.max() <= F_RTOL, f"max f rel err {f.max():.3e}"
+    assert x.max() <= XI_ATOL, f"max xi abs err {x.max():.3e}"
+    assert m.min() >= MAC_MIN, f"min MAC {m.min():.6f}"
+
+
+def _check_sigma(got, ref):
+    keep = ref >= SIGMA_FLOOR * ref[0]
+    rel = np.abs(got[: len(ref)][keep] - ref[keep]) / ref[keep]
+    assert rel.max() <= SIGMA_RTOL, f"max sigma rel err {rel.max():.3e}"
+
+
+# ------------------------------------------------------------ modal stage
+def test_modal_stage_same_inputs(ctx):
+    """Checker U and sigma of the small record's Toeplitz matrix into both
+    modal stages: every physical pole agrees to near FP64 precision."""
+    from paper_2411_05510_amd import ssicov
+    wl = synth.WORKLOADS["small-full-svd"]
+    sysm, y = synth.make_record(wl)
+    jb = wl.lags[0]
+    t = oracle.toeplitz(oracle.correlations(y, 2 * jb - 1), jb)
+    u, s = oracle.full_svd(t, wl.order_max)
+    p = _params(wl)
+    out = ctx.alloc_output(p, wl.l, wl.n)
+    ctx.modal(_dev(u), _dev(s), wl.l, p, 0, out)
+    ctx.synchronize()
+    ref = oracle.modal(u, s, wl.l, wl.orders, wl.fs)
+    stats = {"f": [], "xi": [], "mac": []}
+    for oi in range(len(wl.orders)):
+        gpu = out.poles(0, oi)
+        _compare_order(gpu, ref[oi], _physical(ref[oi], sysm), stats)
+        # all poles, not only physical ones: same count and near-equal values
+        assert len(gpu["f"]) == len(ref[oi])
+        if len(ref[oi]):
+            np.testing.assert_allclose(gpu["f"], ref[oi].f, rtol=1e-8)
+            np.testing.assert_allclose(gpu["xi"], ref[oi].xi, rtol=1e-6, atol=1e-10)
+    f = np.array(stats["f"])
+    assert f.max() <= 1e-10
+    # mode shapes are returned as FP32 complex: MAC resolution about 1e-7
+    assert np.array(stats["mac"]).min() >= 1 - 1e-6
+
+
+def test_modal_exact_model(ctx):
+    """Exact correlations of the generator's model: the order-2n poles are the
+    generated modes."""
+    wl = synth.WORKLOADS["small-full-svd"]
+    sysm = synth.draw_system(wl.l, wl.n_modes, wl.f_range, wl.zeta_range, wl.fs,
+                             wl.struct_seed)
+    jb = 6
+    t = oracle.toeplitz(modal_correlations(sysm, 2 * jb - 1), jb)
+    u, s = oracle.full_svd(t, 2 * wl.n_modes)
+    p = _params(wl, lags=[jb], order_min=2 * wl.n_modes, order_max=2 * wl.n_modes)
+    out = ctx.alloc_output(p, wl.l, 1000)
+    ctx.modal(_dev(u), _dev(s), wl.l, p, 0, out)
+    ctx.synchronize()
+    g = out.poles(0, 0)
+    np.testing.assert_allclose(g["f"], sysm.freqs, rtol=1e-10)
+    np.testing.assert_allclose(g["xi"], sysm.zetas, rtol=1e-8)
+    for r in range(wl.n_modes):
+        assert mac(g["phi"][r], sysm.shapes[:, r]) > 1 - 1e-6   # phi stored FP32
+
+
+# ------------------------------------------------------------ identification
+def test_identify_small_full_svd(ctx):
+    wl = synth.WORKLOADS["small-full-svd"]
+    sysm, y = synth.make_record(wl)
+    p = _params(wl)
+    out = ctx.identify(_dev(y), p)
+    ctx.synchronize()
+    res = oracle.identify(y, wl.fs, wl.lags, wl.orders, svd="full")
+    _check_sigma(out.sigma[0].cpu().numpy(), res[0].sigma)
+    stats = {"f": [], "xi": [], "mac": []}
+    _check_lag(out, 0, res[0], sysm, wl.orders, stats)
+    _assert_stats(stats)
+
+
+def test_identify_two_lags_odd_orders(ctx):
+    wl = synth.WORKLOADS["small-full-svd"]
+    sysm, y = synth.make_record(wl, n=12000)
+    lags, orders = [9, 14], list(range(3, 26, 1))
+    p = _params(wl, lags=lags, order_min=3, order_max=25, order_step=1)
+    out = ctx.identify(_dev(y), p)
+    ctx.synchronize()
+    res = oracle.identify(y, wl.fs, lags, orders, svd="full")
+    stats = {"f": [], "xi": [], "mac": []}
+    for i in range(len(lags)):
+        _check_sigma(out.sigma[i].cpu().numpy(), res[i].sigma)
+        _check_lag(out, i, res[i], sysm, orders, stats)
+    _assert_stats(stats)
+
+
+def test_identify_randomized_two_lags(ctx):
+    """Randomized SVD per lag (Philox stream = lag index), 60 channels."""
+    wl = synth.Workload(name="mid", l=60, n=30000, fs=100.0, n_modes=8,
+                        f_range=(0.5, 20.0), zeta_range=(0.005, 0.03), noise=0.05,
+                        lags=(12, 20), svd="randomized", rank=60, oversample=10,
+                        power_iters=2, order_min=2, order_max=60, order_step=2,
+                        struct_seed=77, noise_seed=78, sketch_seed=79)
+    sysm, y = synth.make_record(wl)
+    p = _params(wl)
+    out = ctx.identify(_dev(y), p)
+    ctx.synchronize()
+    res = oracle.identify(y, wl.fs, wl.lags, wl.orders, svd="randomized", rank=wl.rank,
+                          oversample=wl.oversample, power_iters=wl.power_iters,
+                          seed=wl.sketch_seed)
+    stats = {"f": [], "xi": [], "mac": []}
+    for i in range(len(wl.lags)):
+        _check_sigma(out.sigma[i].cpu().numpy(), res[i].sigma)
+        _check_lag(out, i, res[i], sysm, wl.orders, stats)
+    _assert_stats(stats)
+
+
+def test_identify_orders_above_200(ctx):
+    """Orders 202..224 take the global-memory Hessenberg path; ell = 240 takes
+    the global-memory small eigensolver."""
+    wl = synth.Workload(name="wide", l=40, n=20000, fs=100.0, n_modes=6,
+                        f_range=(1.0, 20.0), zeta_range=(0.01, 0.03), noise=0.05,
+                        lags=(8,), svd="randomized", rank=224, oversample=16,
+                        power_iters=1, order_min=196, order_max=224, order_step=4,
+                        struct_seed=5, noise_seed=6, sketch_seed=7)
+    sysm, y = synth.make_record(wl)
+    p = _params(wl)
+    out = ctx.identify(_dev(y), p)
+    ctx.synchronize()
+    res = oracle.identify(y, wl.fs, wl.lags, wl.orders, svd="randomized", rank=wl.rank,
+                          oversample=wl.oversample, power_iters=wl.power_iters,
+                          seed=wl.sketch_seed)
+    stats = {"f": [], "xi": [], "mac": []}
+    _check_sigma(out.sigma[0].cpu().numpy(), res[0].sigma)
+    _check_lag(out, 0, res[0], sysm, wl.orders, stats)
+    _assert_stats(stats)
+
+
+def test_identify_deterministic(ctx):
+    wl = synth.WORKLOADS["small-full-svd"]
+    _, y = synth.make_record(wl, n=8000)
+    p = _params(wl)
+    yd = _dev(y)
+    a = ctx.identify(yd, p)
+    ctx.synchronize()
+    fa = a.f.clone(); pa = a.phi.clone()
+    b = ctx.identify(yd, p)
+    ctx.synchronize()
+    assert torch.equal(fa, b.f) and torch.equal(pa, b.phi)
+
+
+def test_identify_bridge_record(ctx):
+    """The 180-channel, 30-minute record at j_b = 60 (10800 x 10800 Toeplitz),
+    randomized SVD k = 200, p = 20, q = 2, orders 2..200: the configuration
+    the benchmark times."""
+    wl = synth.WORKLOADS["bridge-180ch"]
+    sysm, y = synth.make_record(wl)
+    p = _params(wl)
+    out = ctx.identify(_dev(y), p)
+    ctx.synchronize()
+    res = oracle.identify(y, wl.fs, wl.lags, wl.orders, svd="randomized", rank=wl.rank,
+                          oversample=wl.oversample, power_iters=wl.power_iters,
+                          seed=wl.sketch_seed)
+    _check_sigma(out.sigma[0].cpu().numpy(), res[0].sigma)
+    stats = {"f": [], "xi": [], "mac": []}
+    _check_lag(out, 0, res[0], sysm, wl.orders, stats)
+    _assert_stats(stats)
+    print(f"bridge: {len(stats['f'])} physical poles, max f rel {max(stats['f']):.2e}, "
+          f"max xi abs {max(stats['xi']):.2e}, min MAC {min(stats['mac']):.8f}")

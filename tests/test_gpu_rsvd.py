@@ -96,15 +96,13 @@ def test_rsvd_caller_sketch(ctx):
 
 def test_rsvd_bridge_toeplitz(ctx):
     """The 10800 x 10800 Toeplitz matrix of the 180-channel record: k = 200,
-    p = 20, q = 2, same T values and the same Philox sketch on both sides."""
+    p = 20, q = 2.  T comes from the checker's own correlations (rounded to
+    FP32) and both sides draw the same Philox sketch."""
     wl = synth.WORKLOADS["bridge-180ch"]
     _, y = synth.make_record(wl)
     jb = wl.lags[0]
-    r = ctx.correlate(_dev(y), 2 * jb - 1)
-    t = ctx.toeplitz(r, jb)
-    ctx.synchronize()
-    t32 = t.cpu().numpy()
-    u, s = ctx.rsvd(t, wl.rank, wl.oversample, wl.power_iters, seed=wl.sketch_seed)
+    t32 = oracle.toeplitz(oracle.correlations(y, 2 * jb - 1), jb).astype(np.float32)
+    u, s = ctx.rsvd(_dev(t32), wl.rank, wl.oversample, wl.power_iters, seed=wl.sketch_seed)
     ctx.synchronize()
     om = oracle.sketch(wl.sketch_seed, t32.shape[0], wl.rank + wl.oversample, 0)
     ur, sr = oracle.rsvd(t32.astype(np.float64), wl.rank, wl.oversample, wl.power_iters, om)
