@@ -129,7 +129,8 @@ def main() -> int:
         "config": {
             "workload": f"{WORKLOAD}: l=180 channels, N=180000 samples at 100 Hz, j_b=60 "
                         "(10800x10800 Toeplitz), randomized SVD k=200 p=20 q=2, "
-                        "orders 2..200 step 2, FP32 MFMA products, FP64 small factorizations",
+                        "orders 2..200 step 2; correlations on FP32 MFMA, T x Q products on FP64 MFMA, "
+                        "FP64 factorizations and eigen-analysis",
             "latency_ms_p50": float(np.percentile(step_ms, 50)),
             "latency_ms_p99": float(np.percentile(step_ms, 99)),
             "stage_ms_per_step": {k: v[0] / args.steps for k, v in stages.items()},

@@ -363,15 +363,13 @@ bool is_device_ptr(const void *p) {
 }
 
 // ------------------------------------------------------------ products
-// out = op(A) B (FP32 operands, FP64 result via split-K partial sums);
-// optional FP32 copy of the result.
-hipError_t prod_f32(ssi_ctx *c, bool ta, const float *A, int64_t lda, const float *B,
-                    int64_t ldb, int M, int N, int K, double *part, double *out, int64_t ldo,
-                    float *out32 = nullptr, int64_t ld32 = 0) {
-  const ssi::GemmPlan gp = ssi::plan_gemm_f32(M, N, K, c->num_cus);
-  hipError_t e = ssi::launch_gemm_f32(gp, ta, A, lda, B, ldb, M, N, K, part, c->stream);
+// out = op(T) X with T FP32 and X FP64 (FP64 MFMA, split-K partial sums).
+hipError_t prod_tf64(ssi_ctx *c, bool ta, const float *T, int64_t ldt, const double *X,
+                     int64_t ldx, int M, int N, int K, double *part, double *out, int64_t ldo) {
+  const ssi::GemmPlan gp = ssi::plan_gemm_tf64(M, N, K, c->num_cus);
+  hipError_t e = ssi::launch_gemm_tf64(gp, ta, T, ldt, X, ldx, M, N, K, part, c->stream);
   if (e != hipSuccess) return e;
-  return ssi::launch_reduce(gp, part, M, N, 1.0, out, ldo, out32, ld32, c->stream);
+  return ssi::launch_reduce(gp, part, M, N, 1.0, out, ldo, nullptr, 0, c->stream);
 }
 
 hipError_t prod_f64(ssi_ctx *c, bool ta, const double *A, int64_t lda, const double *B,
@@ -383,24 +381,21 @@ hipError_t prod_f64(ssi_ctx *c, bool ta, const double *A, int64_t lda, const dou
   return ssi::launch_reduce(gp, part, M, N, 1.0, out, ldo, out32, ld32, c->stream);
 }
 
-size_t part_f32(int M, int N, int K, int cus) { return ssi::plan_gemm_f32(M, N, K, cus).part_elems(); }
+size_t part_tf64(int M, int N, int K, int cus) { return ssi::plan_gemm_tf64(M, N, K, cus).part_elems(); }
 size_t part_f64(int M, int N, int K, int cus) { return ssi::plan_gemm_f64(M, N, K, cus).part_elems(); }
 
 // ------------------------------------------------------------ randomized SVD
 struct RsvdBufs {
-  float *om32, *x32;
-  double *ya, *yb, *gm, *rinv, *lws, *evals, *evecs, *dws, *part;
-  int ell, ellp;
+  double *om, *ya, *yb, *gm, *rinv, *lws, *evals, *evecs, *dws, *part;
+  int ell;
 };
 
 RsvdBufs carve_rsvd(Arena &a, ssi_ctx *c, int64_t m, int ell, int k,
                     const int64_t *m_all = nullptr, int n_m = 0) {
   RsvdBufs b{};
   b.ell = ell;
-  b.ellp = (ell + 3) & ~3;
   const int mi = (int)m, cu = c->num_cus;
-  b.om32 = a.take<float>((size_t)m * b.ellp);
-  b.x32 = a.take<float>((size_t)m * b.ellp);
+  b.om = a.take<double>((size_t)m * ell);
   b.ya = a.take<double>((size_t)m * ell);
   b.yb = a.take<double>((size_t)m * ell);
   b.gm = a.take<double>((size_t)ell * ell);
@@ -412,30 +407,30 @@ RsvdBufs carve_rsvd(Arena &a, ssi_ctx *c, int64_t m, int ell, int k,
   size_t part = 0;
   for (int i = 0; i < (m_all ? n_m : 1); ++i) {
     const int mm = m_all ? (int)m_all[i] : mi;
-    part = std::max({part, part_f32(mm, ell, mm, cu), part_f64(ell, ell, mm, cu),
+    part = std::max({part, part_tf64(mm, ell, mm, cu), part_f64(ell, ell, mm, cu),
                      part_f64(mm, ell, ell, cu), part_f64(mm, k, ell, cu)});
   }
   b.part = a.take<double>(part);
   return b;
 }
 
-// Orthonormal basis of the columns of cur (m x ell, FP64) by shifted
-// CholeskyQR: pass 1 with a diagonal shift that keeps the Cholesky factor
-// defined for ill-conditioned input, then two plain passes (CholeskyQR2).
-// Returns the buffer holding Q; b.x32 receives its FP32 copy.
+// Basis of the columns of cur (m x ell, FP64) by shifted CholeskyQR: pass 1
+// with a diagonal shift that keeps the Cholesky factor defined for
+// ill-conditioned input, then plain passes.  passes = 3 (shifted
+// CholeskyQR2) gives an orthonormal Q; passes = 1 keeps the span with a
+// well-conditioned basis, which is all the power iteration needs between
+// products.  Returns the buffer holding Q.
 double *orthonormalize(ssi_ctx *c, RsvdBufs &b, double *cur, double *nxt, int64_t m,
-                       hipError_t &err) {
+                       int passes, hipError_t &err) {
   const int ell = b.ell, mi = (int)m;
   const double shift_rel = 11.0 * ((double)m * ell + (double)ell * (ell + 1)) * 0x1.0p-53;
-  for (int pass = 0; pass < 3 && err == hipSuccess; ++pass) {
+  for (int pass = 0; pass < passes && err == hipSuccess; ++pass) {
     err = prod_f64(c, true, cur, ell, cur, ell, ell, ell, mi, b.part, b.gm, ell);
     if (err != hipSuccess) break;
     err = ssi::launch_chol_inv(b.gm, ell, ell, pass == 0 ? shift_rel : 0.0, b.rinv, ell, b.lws,
                                b.dws, c->status, c->stream);
     if (err != hipSuccess) break;
-    const bool last = pass == 2;
-    err = prod_f64(c, false, cur, ell, b.rinv, ell, mi, ell, ell, b.part, nxt, ell,
-                   last ? b.x32 : nullptr, b.ellp);
+    err = prod_f64(c, false, cur, ell, b.rinv, ell, mi, ell, ell, b.part, nxt, ell);
     std::swap(cur, nxt);
   }
   return cur;
@@ -449,22 +444,21 @@ ssi_status run_rsvd(ssi_ctx *c, RsvdBufs &b, const float *t, int64_t m, int64_t 
   {
     StageTimer tm(c, SSI_STAGE_SKETCH);
     if (omega)
-      e = hipMemcpy2DAsync(b.om32, (size_t)b.ellp * 4, omega, (size_t)ell * 4, (size_t)ell * 4,
-                           (size_t)m, hipMemcpyDeviceToDevice, c->stream);
+      e = ssi::launch_convert_f32_f64(omega, ell, mi, ell, b.om, ell, c->stream);
     else
-      e = ssi::launch_sketch(seed, stream, m, ell, b.om32, b.ellp, c->stream);
+      e = ssi::launch_sketch(seed, stream, m, ell, b.om, ell, c->stream);
   }
   if (e != hipSuccess) return hip_fail(e, "sketch");
   // Y = T Omega, Q = orth(Y)
   {
     StageTimer tm(c, SSI_STAGE_PRODUCTS);
-    e = prod_f32(c, false, t, ldt, b.om32, b.ellp, mi, ell, mi, b.part, b.ya, ell);
+    e = prod_tf64(c, false, t, ldt, b.om, ell, mi, ell, mi, b.part, b.ya, ell);
   }
   if (e != hipSuccess) return hip_fail(e, "Y = T Omega");
   double *Q;
   {
     StageTimer tm(c, SSI_STAGE_ORTH);
-    Q = orthonormalize(c, b, b.ya, b.yb, m, e);
+    Q = orthonormalize(c, b, b.ya, b.yb, m, q == 0 ? 3 : 1, e);
   }
   if (e != hipSuccess) return hip_fail(e, "orthonormalize");
   // power iterations: Q = orth(T^T Q), Q = orth(T Q)
@@ -473,12 +467,13 @@ ssi_status run_rsvd(ssi_ctx *c, RsvdBufs &b, const float *t, int64_t m, int64_t 
       double *other = (Q == b.ya) ? b.yb : b.ya;
       {
         StageTimer tm(c, SSI_STAGE_PRODUCTS);
-        e = prod_f32(c, side == 0, t, ldt, b.x32, b.ellp, mi, ell, mi, b.part, other, ell);
+        e = prod_tf64(c, side == 0, t, ldt, Q, ell, mi, ell, mi, b.part, other, ell);
       }
       if (e != hipSuccess) return hip_fail(e, "power iteration product");
       {
         StageTimer tm(c, SSI_STAGE_ORTH);
-        Q = orthonormalize(c, b, other, Q, m, e);
+        const bool final_basis = it == q - 1 && side == 1;
+        Q = orthonormalize(c, b, other, Q, m, final_basis ? 3 : 1, e);
       }
       if (e != hipSuccess) return hip_fail(e, "orthonormalize");
     }
@@ -487,7 +482,7 @@ ssi_status run_rsvd(ssi_ctx *c, RsvdBufs &b, const float *t, int64_t m, int64_t 
   double *pt = (Q == b.ya) ? b.yb : b.ya;
   {
     StageTimer tm(c, SSI_STAGE_PRODUCTS);
-    e = prod_f32(c, true, t, ldt, b.x32, b.ellp, mi, ell, mi, b.part, pt, ell);
+    e = prod_tf64(c, true, t, ldt, Q, ell, mi, ell, mi, b.part, pt, ell);
   }
   if (e != hipSuccess) return hip_fail(e, "P^T = T^T Q");
   StageTimer tm_small(c, SSI_STAGE_SMALL_SVD);
@@ -582,16 +577,18 @@ ssi_status run_modal(ssi_ctx *c, ModalBufs &b, const double *u, int64_t m, int k
                      const ssi_params *p, int lag_i, const ssi_output *out) {
   const int kk = p->order_max, mt = (int)(m - l);
   hipError_t e;
-  StageTimer tm_ls(c, SSI_STAGE_SHIFT_LS);
-  // Gram matrices of the shifted observability blocks (leading kk columns)
-  e = prod_f64(c, true, u, k, u, k, kk, kk, mt, b.part, b.gt, kk);
-  if (e != hipSuccess) return hip_fail(e, "U_top^T U_top");
-  e = prod_f64(c, true, u, k, u + (int64_t)l * k, k, kk, kk, mt, b.part, b.hm, kk);
-  if (e != hipSuccess) return hip_fail(e, "U_top^T U_bot");
-  e = ssi::launch_chol_inv(b.gt, kk, kk, 0.0, b.rinv, kk, b.lws, b.dws, c->status, c->stream);
-  if (e != hipSuccess) return hip_fail(e, "Cholesky of U_top^T U_top");
-  e = prod_f64(c, true, b.rinv, kk, b.hm, kk, kk, kk, kk, b.part, b.w, kk);
-  if (e != hipSuccess) return hip_fail(e, "W = R^-T H");
+  {
+    StageTimer tm_ls(c, SSI_STAGE_SHIFT_LS);
+    // Gram matrices of the shifted observability blocks (leading kk columns)
+    e = prod_f64(c, true, u, k, u, k, kk, kk, mt, b.part, b.gt, kk);
+    if (e != hipSuccess) return hip_fail(e, "U_top^T U_top");
+    e = prod_f64(c, true, u, k, u + (int64_t)l * k, k, kk, kk, mt, b.part, b.hm, kk);
+    if (e != hipSuccess) return hip_fail(e, "U_top^T U_bot");
+    e = ssi::launch_chol_inv(b.gt, kk, kk, 0.0, b.rinv, kk, b.lws, b.dws, c->status, c->stream);
+    if (e != hipSuccess) return hip_fail(e, "Cholesky of U_top^T U_top");
+    e = prod_f64(c, true, b.rinv, kk, b.hm, kk, kk, kk, kk, b.part, b.w, kk);
+    if (e != hipSuccess) return hip_fail(e, "W = R^-T H");
+  }
   const int no = b.sz.n_orders;
   int32_t pole_cap = 0;
   for (int o = 0; o < no; ++o) pole_cap += (p->order_min + o * p->order_step) / 2;

@@ -58,42 +58,11 @@ template <int TP, int TQ, bool GM>
 struct Tile {
   double r[GM ? 1 : TP][GM ? 1 : TQ];
   double *gp;   // GM: slot (p, q) at gp[(p * TQ + q) * kThreads]
-  // (p, q) must be compile-time after unrolling in register mode
+  // (p, q) must be compile-time after unrolling in register mode: a run-time
+  // index into the register array would move it to scratch memory
   SSI_DEV double &operator()(int p, int q) {
     if constexpr (GM) return gp[(size_t)(p * TQ + q) * kThreads];
     else return r[p][q];
-  }
-  // column index qr known only at run time: select, never index registers
-  SSI_DEV double getq(int p, int qr) {
-    if constexpr (GM) return gp[(size_t)(p * TQ + qr) * kThreads];
-    double v = 0.0;
-#pragma unroll
-    for (int q = 0; q < TQ; ++q) v = (q == qr) ? r[p][q] : v;
-    return v;
-  }
-  SSI_DEV void setq(int p, int qr, double v) {
-    if constexpr (GM) {
-      gp[(size_t)(p * TQ + qr) * kThreads] = v;
-    } else {
-#pragma unroll
-      for (int q = 0; q < TQ; ++q) r[p][q] = (q == qr) ? v : r[p][q];
-    }
-  }
-  // row index pr known only at run time
-  SSI_DEV double getp(int pr, int q) {
-    if constexpr (GM) return gp[(size_t)(pr * TQ + q) * kThreads];
-    double v = 0.0;
-#pragma unroll
-    for (int p = 0; p < TP; ++p) v = (p == pr) ? r[p][q] : v;
-    return v;
-  }
-  SSI_DEV void setp(int pr, int q, double v) {
-    if constexpr (GM) {
-      gp[(size_t)(pr * TQ + q) * kThreads] = v;
-    } else {
-#pragma unroll
-      for (int p = 0; p < TP; ++p) r[p][q] = (p == pr) ? v : r[p][q];
-    }
   }
 };
 
@@ -138,45 +107,59 @@ chol_kernel(const double *__restrict__ G, int64_t ldg, int n, double shift_rel,
     for (int q = 0; q < TQ; ++q)
       g(p, q) += sel(row_of(tr, p) == col_of(tc, q) && row_of(tr, p) < n, shift);
 
-  for (int k = 0; k < n; ++k) {
-    const int kq = k >> 5;
-    if (tr == (k & 15) && tc == (k & 31)) {
-      double d = 0.0;
+  // Column k lives in column block kq = k / 32.  The block loop is unrolled in
+  // register mode, so the pivot column's registers are compile-time indices;
+  // row blocks above the pivot and blocks strictly above the diagonal are
+  // never touched again and are skipped.
+#pragma unroll UQ
+  for (int kq = 0; kq < TQ; ++kq) {
+    const int k0 = 32 * kq, k1 = min(k0 + 32, n);
+    for (int k = k0; k < k1; ++k) {
+      if (tr == (k & 15) && tc == (k & 31)) {
+        double d = 0.0;
 #pragma unroll UP
-      for (int p = 0; p < TP; ++p) d += sel(row_of(tr, p) == k, g.getq(p, kq));
-      if (!(d > 0.0)) {
-        bad = 1;
-        d = 1e-300;
+        for (int p = 0; p < TP; ++p) {
+          if (p < 2 * kq) continue;
+          d += sel(row_of(tr, p) == k, g(p, kq));
+        }
+        if (!(d > 0.0)) {
+          bad = 1;
+          d = 1e-300;
+        }
+        piv = sqrt(d);
       }
-      piv = sqrt(d);
-    }
-    __syncthreads();
-    const double pv = piv, rpv = 1.0 / pv;
-    if (tc == (k & 31)) {
+      __syncthreads();
+      const double pv = piv, rpv = 1.0 / pv;
+      if (tc == (k & 31)) {
+#pragma unroll UP
+        for (int p = 0; p < TP; ++p) {
+          if (p < 2 * kq) continue;
+          const int i = row_of(tr, p);
+          const double nv = (i == k) ? pv : g(p, kq) * rpv;
+          if (i >= k && i < n) {
+            g(p, kq) = nv;
+            colbuf[i] = nv;
+          }
+        }
+      }
+      __syncthreads();
+      double cj[TQ];
+#pragma unroll UQ
+      for (int q = 0; q < TQ; ++q) {
+        const int j = col_of(tc, q);
+        cj[q] = sel(q >= kq && j > k && j < n, colbuf[min(j, kN - 1)]);
+      }
 #pragma unroll UP
       for (int p = 0; p < TP; ++p) {
         const int i = row_of(tr, p);
-        const double nv = (i == k) ? pv : g.getq(p, kq) * rpv;
-        if (i >= k && i < n) {
-          g.setq(p, kq, nv);
-          colbuf[i] = nv;
+        if (p < 2 * kq || (GM && (i <= k || i >= n))) continue;
+        const double ci = sel(i > k && i < n, colbuf[min(i, kN - 1)]);
+#pragma unroll UQ
+        for (int q = 0; q < TQ; ++q) {
+          if (q < kq || 32 * q > 16 * p + 15) continue;
+          g(p, q) -= ci * cj[q];
         }
       }
-    }
-    __syncthreads();
-    double cj[TQ];
-#pragma unroll UQ
-    for (int q = 0; q < TQ; ++q) {
-      const int j = col_of(tc, q);
-      cj[q] = sel(j > k && j < n, colbuf[min(j, kN - 1)]);
-    }
-#pragma unroll UP
-    for (int p = 0; p < TP; ++p) {
-      const int i = row_of(tr, p);
-      if (GM && (i <= k || i >= n)) continue;
-      const double ci = sel(i > k && i < n, colbuf[min(i, kN - 1)]);
-#pragma unroll UQ
-      for (int q = 0; q < TQ; ++q) g(p, q) -= ci * cj[q];
     }
   }
 #pragma unroll UP
@@ -206,43 +189,55 @@ tri_inv_kernel(int n, const double *__restrict__ Lws, double *__restrict__ Rinv,
 #pragma unroll UQ
     for (int q = 0; q < TQ; ++q)
       g(p, q) = sel(row_of(tr, p) == col_of(tc, q) && row_of(tr, p) < n, 1.0);
-  for (int k = 0; k < n; ++k) {
-    const int kp = k >> 4, kk = k & 7;
-    if (kk == 0) {
-      for (int idx = t; idx < 8 * kN; idx += kThreads) {
-        const int c = idx / kN, i = idx - c * kN;
-        const int col = k + c;
-        lcol[c][i] = sel(col < n && i >= col && i < n,
-                         Lws[(int64_t)min(i, n - 1) * n + min(col, n - 1)]);
+  // Row k lives in row block kp = k / 16.  The block loop is unrolled in
+  // register mode, so the pivot row's registers are compile-time indices; X is
+  // lower triangular, so finished row blocks and the column blocks right of
+  // the current row block are skipped.
+#pragma unroll UP
+  for (int kp = 0; kp < TP; ++kp) {
+    const int k0 = 16 * kp, k1 = min(k0 + 16, n);
+    for (int k = k0; k < k1; ++k) {
+      const int kk = k & 7;
+      if (kk == 0) {
+        for (int idx = t; idx < 8 * kN; idx += kThreads) {
+          const int c = idx / kN, i = idx - c * kN;
+          const int col = k + c;
+          lcol[c][i] = sel(col < n && i >= col && i < n,
+                           Lws[(int64_t)min(i, n - 1) * n + min(col, n - 1)]);
+        }
+        __syncthreads();
+      }
+      const double rlkk = 1.0 / lcol[kk][k];
+      if (tr == (k & 15)) {
+#pragma unroll UQ
+        for (int q = 0; q < TQ; ++q) {
+          if (32 * q > k0 + 15) continue;
+          const int j = col_of(tc, q);
+          const double v = g(kp, q) * rlkk;
+          g(kp, q) = v;
+          if (j < n) rowbuf[j] = v;
+        }
       }
       __syncthreads();
-    }
-    const double rlkk = 1.0 / lcol[kk][k];
-    if (tr == (k & 15)) {
+      double rj[TQ];
 #pragma unroll UQ
       for (int q = 0; q < TQ; ++q) {
         const int j = col_of(tc, q);
-        const double v = g.getp(kp, q) * rlkk;
-        g.setp(kp, q, v);
-        if (j < n) rowbuf[j] = v;
+        rj[q] = sel(32 * q <= k0 + 15 && j <= k && j < n, rowbuf[min(j, kN - 1)]);
       }
-    }
-    __syncthreads();
-    double rj[TQ];
-#pragma unroll UQ
-    for (int q = 0; q < TQ; ++q) {
-      const int j = col_of(tc, q);
-      rj[q] = sel(j <= k && j < n, rowbuf[min(j, kN - 1)]);
-    }
 #pragma unroll UP
-    for (int p = 0; p < TP; ++p) {
-      const int i = row_of(tr, p);
-      if (GM && (i <= k || i >= n)) continue;
-      const double li = sel(i > k && i < n, lcol[kk][min(i, kN - 1)]);
+      for (int p = 0; p < TP; ++p) {
+        const int i = row_of(tr, p);
+        if (p < kp || (GM && (i <= k || i >= n))) continue;
+        const double li = sel(i > k && i < n, lcol[kk][min(i, kN - 1)]);
 #pragma unroll UQ
-      for (int q = 0; q < TQ; ++q) g(p, q) -= li * rj[q];
+        for (int q = 0; q < TQ; ++q) {
+          if (32 * q > k0 + 15) continue;
+          g(p, q) -= li * rj[q];
+        }
+      }
+      __syncthreads();
     }
-    __syncthreads();
   }
 #pragma unroll UP
   for (int p = 0; p < TP; ++p)
@@ -254,7 +249,7 @@ tri_inv_kernel(int n, const double *__restrict__ Lws, double *__restrict__ Rinv,
 }
 
 // ------------------------------------------------------------ sym eigen
-// Scratch layout (doubles): vref[kN][kN] | tau[kN] | d[kN] | e[kN] | lu[5][kN][kN]
+// Scratch layout (doubles): vref[kN][kN] | tau[kN] | d[kN] | e[kN]
 template <int TP, int TQ, bool GM>
 __global__ void __launch_bounds__(kThreads)
 sym_tridiag_kernel(const double *__restrict__ G, int64_t ldg, int n, double *__restrict__ ws,
@@ -280,90 +275,104 @@ sym_tridiag_kernel(const double *__restrict__ G, int64_t ldg, int n, double *__r
       g(p, q) = sel(i < n && j < n, G[(int64_t)min(i, n - 1) * ldg + min(j, n - 1)]);
     }
 
-  for (int k = 0; k + 2 < n; ++k) {
-    const int kq = k >> 5;
-    if (tc == (k & 31)) {
-      // Householder vector of column k below the diagonal
-      double s2 = 0.0, x1 = 0.0, dk = 0.0;
+  // Column k lives in column block kq = k / 32; the unrolled block loop makes
+  // the owner's registers compile-time indices.  Rows and columns at or above
+  // the pivot are final (d, e are recorded), so blocks before kq (columns) and
+  // before 2 kq (rows) are skipped.
+#pragma unroll UQ
+  for (int kq = 0; kq < TQ; ++kq) {
+    const int k0 = 32 * kq, k1 = min(k0 + 32, n - 2);
+    for (int k = k0; k < k1; ++k) {
+      if (tc == (k & 31)) {
+        // Householder vector of column k below the diagonal
+        double s2 = 0.0, x1 = 0.0, dk = 0.0;
 #pragma unroll UP
-      for (int p = 0; p < TP; ++p) {
-        const int i = row_of(tr, p);
-        const double v = g.getq(p, kq);
-        x1 += sel(i == k + 1, v);
-        s2 += sel(i > k + 1 && i < n, v * v);
-        dk += sel(i == k, v);
-      }
-      s2 = col_group_sum(s2);
-      x1 = col_group_sum(x1);
-      dk = col_group_sum(dk);
-      double tau = 0.0, alpha = x1, v1 = 0.0;
-      if (s2 > 0.0) {
-        alpha = -copysign(sqrt(x1 * x1 + s2), x1);
-        v1 = x1 - alpha;
-        tau = 2.0 / (s2 + v1 * v1);
-      }
+        for (int p = 0; p < TP; ++p) {
+          const int i = row_of(tr, p);
+          const double v = g(p, kq);
+          x1 += sel(i == k + 1, v);
+          s2 += sel(i > k + 1 && i < n, v * v);
+          dk += sel(i == k, v);
+        }
+        s2 = col_group_sum(s2);
+        x1 = col_group_sum(x1);
+        dk = col_group_sum(dk);
+        double tau = 0.0, alpha = x1, v1 = 0.0;
+        if (s2 > 0.0) {
+          alpha = -copysign(sqrt(x1 * x1 + s2), x1);
+          v1 = x1 - alpha;
+          tau = 2.0 / (s2 + v1 * v1);
+        }
 #pragma unroll UP
-      for (int p = 0; p < TP; ++p) {
-        const int i = row_of(tr, p);
-        if (i < n) {
-          const double v = (i == k + 1) ? v1 : sel(i > k + 1, g.getq(p, kq));
-          vbuf[i] = v;
-          vref[(size_t)k * kN + i] = v;
+        for (int p = 0; p < TP; ++p) {
+          const int i = row_of(tr, p);
+          if (i < n) {
+            const double v = (i == k + 1) ? v1 : sel(i > k + 1, g(p, kq));
+            vbuf[i] = v;
+            vref[(size_t)k * kN + i] = v;
+          }
+        }
+        if (tr == 0) {
+          stau = tau;
+          tauv[k] = tau;
+          dd[k] = dk;
+          ee[k] = alpha;
         }
       }
-      if (tr == 0) {
-        stau = tau;
-        tauv[k] = tau;
-        dd[k] = dk;
-        ee[k] = alpha;
-      }
-    }
-    __syncthreads();
-    const double tau = stau;
-    if (tau != 0.0) {
-      // p = tau G v by column sums (G symmetric); K = v^T p
-      double sq[TQ];
+      __syncthreads();
+      const double tau = stau;
+      if (tau != 0.0) {
+        // p = tau G v by column sums (G symmetric); K = v^T p
+        double sq[TQ];
 #pragma unroll UQ
-      for (int q = 0; q < TQ; ++q) sq[q] = 0.0;
+        for (int q = 0; q < TQ; ++q) sq[q] = 0.0;
 #pragma unroll UP
-      for (int p = 0; p < TP; ++p) {
-        const int i = row_of(tr, p);
-        if (GM && (i <= k || i >= n)) continue;
-        const double vi = sel(i > k && i < n, vbuf[min(i, kN - 1)]);
+        for (int p = 0; p < TP; ++p) {
+          const int i = row_of(tr, p);
+          if (p < 2 * kq || (GM && (i <= k || i >= n))) continue;
+          const double vi = sel(i > k && i < n, vbuf[min(i, kN - 1)]);
 #pragma unroll UQ
-        for (int q = 0; q < TQ; ++q) sq[q] += g(p, q) * vi;
-      }
-      double kpart = 0.0;
+          for (int q = 0; q < TQ; ++q) {
+            if (q < kq) continue;
+            sq[q] += g(p, q) * vi;
+          }
+        }
+        double kpart = 0.0;
 #pragma unroll UQ
-      for (int q = 0; q < TQ; ++q) {
-        const double s = tau * col_group_sum(sq[q]);
-        const int j = col_of(tc, q);
-        if (tr == 0 && j < n) {
-          pbuf[j] = s;
-          kpart += s * sel(j > k, vbuf[j]);
+        for (int q = 0; q < TQ; ++q) {
+          if (q < kq) continue;
+          const double s = tau * col_group_sum(sq[q]);
+          const int j = col_of(tc, q);
+          if (tr == 0 && j < n) {
+            pbuf[j] = s;
+            kpart += s * sel(j > k, vbuf[j]);
+          }
+        }
+        const double K = block_sum_all(kpart, red);
+        const double c = 0.5 * tau * K;
+        // G -= v w^T + w v^T with w = p - c v
+        double vj[TQ], wj[TQ];
+#pragma unroll UQ
+        for (int q = 0; q < TQ; ++q) {
+          const int j = col_of(tc, q);
+          vj[q] = sel(q >= kq && j > k && j < n, vbuf[min(j, kN - 1)]);
+          wj[q] = sel(q >= kq && j < n, pbuf[min(j, kN - 1)] - c * vj[q]);
+        }
+#pragma unroll UP
+        for (int p = 0; p < TP; ++p) {
+          const int i = row_of(tr, p);
+          if (p < 2 * kq || (GM && i >= n)) continue;
+          const double vi = sel(i > k && i < n, vbuf[min(i, kN - 1)]);
+          const double wi = sel(i < n, pbuf[min(i, kN - 1)] - c * vi);
+#pragma unroll UQ
+          for (int q = 0; q < TQ; ++q) {
+            if (q < kq) continue;
+            g(p, q) -= vi * wj[q] + wi * vj[q];
+          }
         }
       }
-      const double K = block_sum_all(kpart, red);
-      const double c = 0.5 * tau * K;
-      // G -= v w^T + w v^T with w = p - c v
-      double vj[TQ], wj[TQ];
-#pragma unroll UQ
-      for (int q = 0; q < TQ; ++q) {
-        const int j = col_of(tc, q);
-        vj[q] = sel(j > k && j < n, vbuf[min(j, kN - 1)]);
-        wj[q] = sel(j < n, pbuf[min(j, kN - 1)] - c * vj[q]);
-      }
-#pragma unroll UP
-      for (int p = 0; p < TP; ++p) {
-        const int i = row_of(tr, p);
-        if (GM && i >= n) continue;
-        const double vi = sel(i > k && i < n, vbuf[min(i, kN - 1)]);
-        const double wi = sel(i < n, pbuf[min(i, kN - 1)] - c * vi);
-#pragma unroll UQ
-        for (int q = 0; q < TQ; ++q) g(p, q) -= vi * wj[q] + wi * vj[q];
-      }
+      __syncthreads();
     }
-    __syncthreads();
   }
   // trailing 2 x 2 (or 1 x 1) block
 #pragma unroll UP
@@ -400,132 +409,145 @@ SSI_DEV double hash_unit(uint32_t a, uint32_t b) {
   return 0.5 + (double)(h & 0xFFFF) * (1.0 / 65536.0);   // in [0.5, 1.5)
 }
 
-SSI_DEV double block_max_n(double v, double *red, int nt) {
+SSI_DEV double wave_min_d(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = fmin(v, __shfl_xor(v, off, 64));
+  return v;
+}
+
+SSI_DEV double wave_max_d(double v) {
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
-  __syncthreads();
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
-  __syncthreads();
-  double r = red[0];
-  for (int w = 1; w < (nt >> 6); ++w) r = fmax(r, red[w]);
-  return r;
+  return v;
 }
 
 }  // namespace
 
-// Eigenpairs of the tridiagonal (d, e): eigenvalue t (descending) by
-// bisection, its eigenvector by inverse iteration; one thread per eigenvalue.
-template <int KN>
-__global__ void __launch_bounds__(1024)
+// Eigenpairs of the tridiagonal (d, e), one wave per eigenvalue; wave t of the
+// grid takes the t-th largest.  The eigenvalue comes from multisection of the
+// Sturm count: each round the 64 lanes count at 64 interior points of the
+// bracket [lo, hi] (invariant: count(lo) <= target < count(hi)) and the
+// bracket shrinks to the pair of neighbouring points that straddles the
+// target, a factor 65 per round.  The eigenvector comes from inverse
+// iteration (three solves) with the LU factors of T - lambda I, partial
+// pivoting, held in the wave's slice of LDS and run by lane 0.
+template <int KN, int EPW>
+__global__ void __launch_bounds__(64 * EPW)
 sym_tridiag_eig_kernel(int n, double *__restrict__ evals, double *__restrict__ evecs,
-                       int64_t ldv, double *__restrict__ ws) {
+                       int64_t ldv, const double *__restrict__ ws) {
   __shared__ double dd[KN];
   __shared__ double ee[KN];
   __shared__ double e2[KN];
-  __shared__ double red[16];
-  const int t0 = threadIdx.x, nt = blockDim.x;
+  __shared__ double lu[EPW][5][KN];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int t = blockIdx.x * EPW + wv;
   const double *tauv = ws + (size_t)KN * KN;
-  double *lu = ws + (size_t)KN * KN + 3 * KN;
-  for (int i = t0; i < n; i += nt) {
+  for (int i = threadIdx.x; i < n; i += 64 * EPW) {
     dd[i] = tauv[KN + i];
-    ee[i] = tauv[2 * KN + i];
+    const double e = (i < n - 1) ? tauv[2 * KN + i] : 0.0;
+    ee[i] = e;
+    e2[i] = e * e;
   }
-  __syncthreads();
-  for (int i = t0; i < n; i += nt) e2[i] = (i < n - 1) ? ee[i] * ee[i] : 0.0;
   __syncthreads();
   double lo_part = 1e300, hi_part = -1e300, emax_part = 0.0;
-  for (int i = t0; i < n; i += nt) {
-    const double r = (i > 0 ? fabs(ee[i - 1]) : 0.0) + (i < n - 1 ? fabs(ee[i]) : 0.0);
+  for (int i = lane; i < n; i += 64) {
+    const double r = (i > 0 ? fabs(ee[i - 1]) : 0.0) + fabs(ee[i]);
     lo_part = fmin(lo_part, dd[i] - r);
     hi_part = fmax(hi_part, dd[i] + r);
-    if (i < n - 1) emax_part = fmax(emax_part, e2[i]);
+    emax_part = fmax(emax_part, e2[i]);
   }
-  const double glo = -block_max_n(-lo_part, red, nt);
-  const double ghi = block_max_n(hi_part, red, nt);
-  const double e2max = block_max_n(emax_part, red, nt);
+  const double glo = wave_min_d(lo_part), ghi = wave_max_d(hi_part);
+  const double e2max = wave_max_d(emax_part);
   const double gnorm = fmax(fabs(glo), fabs(ghi));
   const double pivmin = 2.2250738585072014e-308 * fmax(1.0, e2max);
   const double span = ghi - glo;
-  double *u0 = lu, *u1 = lu + (size_t)KN * KN, *u2 = lu + 2 * (size_t)KN * KN;
-  double *ml = lu + 3 * (size_t)KN * KN, *xv = lu + 4 * (size_t)KN * KN;
-  const double tiny = 2.220446049250313e-16 * fmax(gnorm, 1e-300);
-  for (int t = t0; t < n; t += nt) {
+  const double eps = 2.220446049250313e-16;
+  const double tiny = eps * fmax(gnorm, 1e-300);
+  double *u0 = lu[wv][0], *u1 = lu[wv][1], *u2 = lu[wv][2], *ml = lu[wv][3], *xv = lu[wv][4];
+  if (t < n) {
     const int target = n - 1 - t;              // ascending index of the t-th largest
     double lo = glo - 1e-14 * span - 2.0 * pivmin, hi = ghi + 1e-14 * span + 2.0 * pivmin;
-    for (int it = 0; it < 128; ++it) {
-      const double mid = 0.5 * (lo + hi);
-      if (hi - lo <= 2.0 * 2.220446049250313e-16 * fmax(fabs(lo), fabs(hi)) + pivmin ||
-          mid <= lo || mid >= hi)
-        break;
-      if (sturm_count(dd, e2, n, mid, pivmin) > target) hi = mid;
-      else lo = mid;
+    for (int round = 0; round < 64; ++round) {
+      if (hi - lo <= 2.0 * eps * fmax(fabs(lo), fabs(hi)) + pivmin) break;
+      const double x = lo + (hi - lo) * ((double)(lane + 1) * (1.0 / 65.0));
+      const bool above = sturm_count(dd, e2, n, x, pivmin) > target;
+      const uint64_t mask = __ballot(above);
+      const int f = mask ? __ffsll((unsigned long long)mask) - 1 : 64;
+      const double nhi = (f < 64) ? __shfl(x, f, 64) : hi;
+      const double nlo = (f > 0) ? __shfl(x, f - 1, 64) : lo;
+      if (!(nhi < hi || nlo > lo)) break;      // points no longer separate
+      hi = fmin(hi, nhi);
+      lo = fmax(lo, nlo);
     }
     const double lam = 0.5 * (lo + hi);
-    evals[t] = lam;
-
-    // inverse iteration: LU with partial pivoting of T - lam I (a row swap is
-    // marked by adding 4 to the multiplier, which is at most 1 in magnitude)
-    double a = dd[0] - lam, b = (n > 1) ? ee[0] : 0.0, c = 0.0;
-    for (int j = 0; j + 1 < n; ++j) {
-      const double sub = ee[j];
-      const double an = dd[j + 1] - lam;
-      const double cn = (j + 2 < n) ? ee[j + 1] : 0.0;
-      if (fabs(a) >= fabs(sub)) {
-        const double aa = (fabs(a) < tiny) ? copysign(tiny, a == 0.0 ? 1.0 : a) : a;
-        const double m = sub / aa;
-        u0[(size_t)j * KN + t] = aa;
-        u1[(size_t)j * KN + t] = b;
-        u2[(size_t)j * KN + t] = c;
-        ml[(size_t)j * KN + t] = m;
-        a = an - m * b;
-        b = cn - m * c;
-        c = 0.0;
-      } else {
-        const double m = a / sub;
-        u0[(size_t)j * KN + t] = sub;
-        u1[(size_t)j * KN + t] = an;
-        u2[(size_t)j * KN + t] = cn;
-        ml[(size_t)j * KN + t] = m + 4.0;
-        const double na = b - m * an, nb = c - m * cn;
-        a = na;
-        b = nb;
-        c = 0.0;
-      }
-    }
-    if (fabs(a) < tiny) a = copysign(tiny, a == 0.0 ? 1.0 : a);
-    u0[(size_t)(n - 1) * KN + t] = a;
-    u1[(size_t)(n - 1) * KN + t] = 0.0;
-    u2[(size_t)(n - 1) * KN + t] = 0.0;
-    for (int j = 0; j < n; ++j) xv[(size_t)j * KN + t] = hash_unit(t, j);
-    for (int it = 0; it < 3; ++it) {
+    if (lane == 0) {
+      evals[t] = lam;
+      // LU with partial pivoting of T - lam I; a row swap is marked by adding
+      // 4 to the multiplier (at most 1 in magnitude).  u0 holds 1 / pivot.
+      double a = dd[0] - lam, b = (n > 1) ? ee[0] : 0.0, c = 0.0;
       for (int j = 0; j + 1 < n; ++j) {
-        double m = ml[(size_t)j * KN + t];
-        double bj = xv[(size_t)j * KN + t], bn = xv[(size_t)(j + 1) * KN + t];
-        if (m > 2.0) {
-          m -= 4.0;
-          const double tmp = bj;
-          bj = bn;
-          bn = tmp;
+        const double sub = ee[j];
+        const double an = dd[j + 1] - lam;
+        const double cn = (j + 2 < n) ? ee[j + 1] : 0.0;
+        if (fabs(a) >= fabs(sub)) {
+          const double aa = (fabs(a) < tiny) ? copysign(tiny, a == 0.0 ? 1.0 : a) : a;
+          const double m = sub / aa;
+          u0[j] = 1.0 / aa;
+          u1[j] = b;
+          u2[j] = c;
+          ml[j] = m;
+          a = an - m * b;
+          b = cn - m * c;
+        } else {
+          const double m = a / sub;
+          u0[j] = 1.0 / sub;
+          u1[j] = an;
+          u2[j] = cn;
+          ml[j] = m + 4.0;
+          a = b - m * an;
+          b = c - m * cn;
         }
-        xv[(size_t)j * KN + t] = bj;
-        xv[(size_t)(j + 1) * KN + t] = bn - m * bj;
+        c = 0.0;
       }
-      double x1 = 0.0, x2 = 0.0, nrm = 0.0;
-      for (int j = n - 1; j >= 0; --j) {
-        const double xj = (xv[(size_t)j * KN + t] - u1[(size_t)j * KN + t] * x1 -
-                           u2[(size_t)j * KN + t] * x2) / u0[(size_t)j * KN + t];
-        xv[(size_t)j * KN + t] = xj;
-        x2 = x1;
-        x1 = xj;
-        nrm = fmax(nrm, fabs(xj));
+      if (fabs(a) < tiny) a = copysign(tiny, a == 0.0 ? 1.0 : a);
+      u0[n - 1] = 1.0 / a;
+      u1[n - 1] = 0.0;
+      u2[n - 1] = 0.0;
+      for (int j = 0; j < n; ++j) xv[j] = hash_unit(t, j);
+      for (int it = 0; it < 3; ++it) {
+        double bj = xv[0];
+        for (int j = 0; j + 1 < n; ++j) {
+          double m = ml[j];
+          double bn = xv[j + 1];
+          if (m > 2.0) {
+            m -= 4.0;
+            const double tmp = bj;
+            bj = bn;
+            bn = tmp;
+          }
+          xv[j] = bj;
+          bj = bn - m * bj;
+        }
+        xv[n - 1] = bj;
+        double x1 = 0.0, x2 = 0.0, nrm = 0.0;
+        for (int j = n - 1; j >= 0; --j) {
+          const double xj = (xv[j] - u1[j] * x1 - u2[j] * x2) * u0[j];
+          xv[j] = xj;
+          x2 = x1;
+          x1 = xj;
+          nrm = fmax(nrm, fabs(xj));
+        }
+        const double inv = 1.0 / nrm;
+        for (int j = 0; j < n; ++j) xv[j] *= inv;
       }
-      const double inv = 1.0 / nrm;
-      for (int j = 0; j < n; ++j) xv[(size_t)j * KN + t] *= inv;
     }
+  }
+  __syncthreads();
+  if (t < n) {
     double s = 0.0;
-    for (int j = 0; j < n; ++j) s += xv[(size_t)j * KN + t] * xv[(size_t)j * KN + t];
-    const double inv = 1.0 / sqrt(s);
-    for (int j = 0; j < n; ++j) evecs[(int64_t)j * ldv + t] = xv[(size_t)j * KN + t] * inv;
+    for (int j = lane; j < n; j += 64) s += xv[j] * xv[j];
+    const double inv = 1.0 / sqrt(wave_sum(s));
+    for (int j = lane; j < n; j += 64) evecs[(int64_t)j * ldv + t] = xv[j] * inv;
   }
 }
 
@@ -549,34 +571,39 @@ sym_backtransform_kernel(int n, double *__restrict__ evecs, int64_t ldv,
       const int i = row_of(tr, p), j = col_of(tc, q);
       g(p, q) = sel(i < n && j < n, evecs[(int64_t)min(i, n - 1) * ldv + min(j, n - 1)]);
     }
-  for (int k = n - 3; k >= 0; --k) {
-    for (int i = t; i < n; i += kThreads) vbuf[i] = (i > k) ? vref[(size_t)k * kN + i] : 0.0;
-    __syncthreads();
-    const double tau = tauv[k];
-    if (tau != 0.0) {
-      double sq[TQ];
-#pragma unroll UQ
-      for (int q = 0; q < TQ; ++q) sq[q] = 0.0;
+  // Reflector k touches rows > k only: row blocks before k / 16 are skipped.
 #pragma unroll UP
-      for (int p = 0; p < TP; ++p) {
-        const int i = row_of(tr, p);
-        if (GM && (i <= k || i >= n)) continue;
-        const double vi = sel(i > k && i < n, vbuf[min(i, kN - 1)]);
+  for (int kb = TP - 1; kb >= 0; --kb) {
+    const int k0 = 16 * kb, k1 = min(k0 + 16, n - 2);
+    for (int k = k1 - 1; k >= k0; --k) {
+      for (int i = t; i < n; i += kThreads) vbuf[i] = (i > k) ? vref[(size_t)k * kN + i] : 0.0;
+      __syncthreads();
+      const double tau = tauv[k];
+      if (tau != 0.0) {
+        double sq[TQ];
 #pragma unroll UQ
-        for (int q = 0; q < TQ; ++q) sq[q] += vi * g(p, q);
-      }
-#pragma unroll UQ
-      for (int q = 0; q < TQ; ++q) sq[q] = tau * col_group_sum(sq[q]);
+        for (int q = 0; q < TQ; ++q) sq[q] = 0.0;
 #pragma unroll UP
-      for (int p = 0; p < TP; ++p) {
-        const int i = row_of(tr, p);
-        if (GM && (i <= k || i >= n)) continue;
-        const double vi = sel(i > k && i < n, vbuf[min(i, kN - 1)]);
+        for (int p = 0; p < TP; ++p) {
+          const int i = row_of(tr, p);
+          if (p < kb || (GM && (i <= k || i >= n))) continue;
+          const double vi = sel(i > k && i < n, vbuf[min(i, kN - 1)]);
 #pragma unroll UQ
-        for (int q = 0; q < TQ; ++q) g(p, q) -= vi * sq[q];
+          for (int q = 0; q < TQ; ++q) sq[q] += vi * g(p, q);
+        }
+#pragma unroll UQ
+        for (int q = 0; q < TQ; ++q) sq[q] = tau * col_group_sum(sq[q]);
+#pragma unroll UP
+        for (int p = 0; p < TP; ++p) {
+          const int i = row_of(tr, p);
+          if (p < kb || (GM && (i <= k || i >= n))) continue;
+          const double vi = sel(i > k && i < n, vbuf[min(i, kN - 1)]);
+#pragma unroll UQ
+          for (int q = 0; q < TQ; ++q) g(p, q) -= vi * sq[q];
+        }
       }
+      __syncthreads();
     }
-    __syncthreads();
   }
 #pragma unroll UP
   for (int p = 0; p < TP; ++p)
@@ -595,9 +622,9 @@ constexpr int kGlbP = 64, kGlbQ = 32;     // n <= 1024
 constexpr int kRegN = Geo<kRegP, kRegQ>::kN;
 constexpr int kGlbN = Geo<kGlbP, kGlbQ>::kN;
 
-double *glb_tile(double *ws) {
-  return ws + (size_t)kGlbN * kGlbN + 3 * kGlbN + 5 * (size_t)kGlbN * kGlbN;
-}
+constexpr int kRegEpw = 4, kGlbEpw = 1;   // eigenvalues (waves) per workgroup
+
+double *glb_tile(double *ws) { return ws + (size_t)kGlbN * kGlbN + 3 * kGlbN; }
 }  // namespace
 
 int dense_max_n() { return kGlbN; }
@@ -605,7 +632,7 @@ int dense_max_n() { return kGlbN; }
 size_t dense_ws_doubles(int n) {
   const size_t kn = n <= kRegN ? kRegN : kGlbN;
   const size_t tile = n <= kRegN ? 0 : (size_t)kGlbP * kGlbQ * kThreads;
-  return kn * kn + 3 * kn + 5 * kn * kn + tile;
+  return kn * kn + 3 * kn + tile;
 }
 
 hipError_t launch_chol_inv(const double *G, int64_t ldg, int n, double shift_rel, double *Rinv,
@@ -631,16 +658,16 @@ hipError_t launch_sym_eig(const double *G, int64_t ldg, int n, double *evals, do
   if (n <= kRegN) {
     hipLaunchKernelGGL((sym_tridiag_kernel<kRegP, kRegQ, false>), dim3(1), dim3(kThreads), 0,
                        st, G, ldg, n, ws, ws);
-    hipLaunchKernelGGL((sym_tridiag_eig_kernel<kRegN>), dim3(1), dim3(256), 0, st, n, evals,
-                       evecs, ldv, ws);
+    hipLaunchKernelGGL((sym_tridiag_eig_kernel<kRegN, kRegEpw>), dim3(ceil_div(n, kRegEpw)),
+                       dim3(64 * kRegEpw), 0, st, n, evals, evecs, ldv, ws);
     hipLaunchKernelGGL((sym_backtransform_kernel<kRegP, kRegQ, false>), dim3(1),
                        dim3(kThreads), 0, st, n, evecs, ldv, ws, ws);
   } else {
     double *tile = glb_tile(ws);
     hipLaunchKernelGGL((sym_tridiag_kernel<kGlbP, kGlbQ, true>), dim3(1), dim3(kThreads), 0,
                        st, G, ldg, n, ws, tile);
-    hipLaunchKernelGGL((sym_tridiag_eig_kernel<kGlbN>), dim3(1), dim3(1024), 0, st, n, evals,
-                       evecs, ldv, ws);
+    hipLaunchKernelGGL((sym_tridiag_eig_kernel<kGlbN, kGlbEpw>), dim3(ceil_div(n, kGlbEpw)),
+                       dim3(64 * kGlbEpw), 0, st, n, evals, evecs, ldv, ws);
     hipLaunchKernelGGL((sym_backtransform_kernel<kGlbP, kGlbQ, true>), dim3(1),
                        dim3(kThreads), 0, st, n, evecs, ldv, ws, tile);
   }

@@ -1,22 +1,25 @@
 // Dense products of the randomized SVD and the modal stage.
 //
-// gemm_f32: C = op(A) B with FP32 operands on v_mfma_f32_16x16x4f32 (the
-//   sketch, power-iteration and projection products Y = T X, Z = T^T X).
-//   Tile 64 x 224 x 32: the thin side (ell = k + p columns) fits one or two
-//   column blocks, the long side is split across workgroups and along K
-//   (split-K); each workgroup folds its fp32 accumulators into fp64 every 256
-//   k and writes fp64 partial sums, added by reduce_splits in a fixed order.
-//   LDS holds both tiles k-contiguous so every lane fetches four consecutive
-//   k of its row with one 16-byte read and feeds four MFMA steps from it.
-// gemm_f64: the same with FP64 operands on v_mfma_f64_16x16x4f64 (Gram
-//   matrices, basis updates, small triangular products).  Tile 64 x 64 x 16.
+// gemm_tf64: C = op(T) X with T in FP32 (the Toeplitz matrix as stored) and X
+//   in FP64, on v_mfma_f64_16x16x4f64 with FP64 accumulation: the sketch,
+//   power-iteration and projection products Y = T X, Z = T^T X.  T is
+//   converted exactly to FP64 in registers, so the only rounding is FP64
+//   accumulation.  Tile 64 x 224 x 16: the thin side (ell = k + p columns)
+//   fits one column block, the long side is split across workgroups and
+//   along K.  The flat grid is decoded split-fastest, so with 8 splits the
+//   workgroups of one K slice land on one XCD (dispatch is round-robin over
+//   the 8 XCDs) and that XCD's L2 holds the slice of X they all read.
+//   Partial sums (FP64) are added by reduce_splits in a fixed order.
+// gemm_f64: FP64 operands on v_mfma_f64_16x16x4f64 (Gram matrices, basis
+//   updates, small triangular products).  Tile 64 x 64 x 16.
 #include "common.h"
 #include "kernels.h"
 
 namespace {
 
-constexpr int kBM = 64, kBN = 224, kKT = 32, kLS = kKT + 4;   // fp32 tiles
-constexpr int kFlush = 8;                                    // K-tiles per fp64 fold
+constexpr int tBM = 64, tBN = 224, tKT = 16;
+constexpr int tLA = tKT + 4;    // FP32 A row stride in LDS (floats)
+constexpr int tLB = tKT + 2;    // FP64 B row stride in LDS (doubles)
 
 constexpr int dBM = 64, dBN = 64, dKT = 16, dLS = dKT + 2;    // fp64 tiles
 
@@ -35,111 +38,112 @@ SSI_DEV float4 load4(const float *__restrict__ p, int64_t ld, int64_t row, int64
   return v;
 }
 
+SSI_DEV float f4get(const float4 &v, int s) {
+  return s == 0 ? v.x : s == 1 ? v.y : s == 2 ? v.z : v.w;
+}
+
 }  // namespace
 
 // C_part[split][i][j] = sum_{k in split} op(A)[i][k] B[k][j]
 //   TA = false: A is M x K (lda);  TA = true: A is K x M (lda), op(A) = A^T.
-//   B is K x N (ldb).
-template <bool TA, bool VEC>
+//   A FP32, B FP64 K x N (ldb).  VEC: lda % 4 == 0 and A 16-byte aligned;
+//   BVEC: ldb even and B 16-byte aligned.
+// In MFMA step s the 16-lane group g of a wave supplies k = 4 g + s of the
+// 16-wide K tile, so each lane reads its four k of a row with one LDS read.
+template <bool TA, bool VEC, bool BVEC>
 __global__ void __launch_bounds__(256, 2)
-gemm_f32_mfma(const float *__restrict__ A, int64_t lda, const float *__restrict__ B,
-              int64_t ldb, double *__restrict__ C, int64_t ldc, int64_t split_stride, int M,
-              int N, int K, int k_per_split) {
-  __shared__ __attribute__((aligned(16))) float As[kBM * kLS];
-  __shared__ __attribute__((aligned(16))) float Bs[kBN * kLS];
+gemm_tf64_mfma(const float *__restrict__ A, int64_t lda, const double *__restrict__ B,
+               int64_t ldb, double *__restrict__ C, int64_t ldc, int64_t split_stride, int M,
+               int N, int K, int k_per_split, int gm, int splits) {
+  __shared__ __attribute__((aligned(16))) float As[tBM * tLA];
+  __shared__ __attribute__((aligned(16))) double Bs[tBN * tLB];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wr = wave & 1, wc = wave >> 1;
-  const int m0 = blockIdx.x * kBM, n0 = blockIdx.y * kBN;
-  const int kb = blockIdx.z * k_per_split;
+  const int split = blockIdx.x % splits;
+  const int rest = blockIdx.x / splits;
+  const int m0 = (rest % gm) * tBM, n0 = (rest / gm) * tBN;
+  const int kb = split * k_per_split;
   const int ke = min(K, kb + k_per_split);
 
-  f32x4 acc[2][7];
-  double accd[2][7][4];
+  f64x4 acc[2][7];
 #pragma unroll
   for (int rt = 0; rt < 2; ++rt)
 #pragma unroll
-    for (int ct = 0; ct < 7; ++ct) {
-      acc[rt][ct] = f32x4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-      for (int q = 0; q < 4; ++q) accd[rt][ct][q] = 0.0;
-    }
+    for (int ct = 0; ct < 7; ++ct) acc[rt][ct] = f64x4{0.0, 0.0, 0.0, 0.0};
   bool colok[7];
 #pragma unroll
   for (int ct = 0; ct < 7; ++ct) colok[ct] = n0 + wc * 112 + ct * 16 < N;
 
-  int tiles = 0;
-  for (int k0 = kb; k0 < ke; k0 += kKT) {
+  for (int k0 = kb; k0 < ke; k0 += tKT) {
     __syncthreads();
-    // ---- A tile -> As[i][k]
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const int idx = tid + 256 * h;
-      if (!TA) {
-        const int r = idx >> 3, c4 = idx & 7;
-        const float4 v = load4<VEC>(A, lda, m0 + r, M, k0 + 4 * c4, ke);
-        *reinterpret_cast<float4 *>(&As[r * kLS + 4 * c4]) = v;
-      } else {
-        const int kr = idx >> 4, c4 = idx & 15;
-        const float4 v = (k0 + kr < ke) ? load4<VEC>(A, lda, k0 + kr, ke, m0 + 4 * c4, M)
-                                        : make_float4(0.f, 0.f, 0.f, 0.f);
-        As[(4 * c4 + 0) * kLS + kr] = v.x;
-        As[(4 * c4 + 1) * kLS + kr] = v.y;
-        As[(4 * c4 + 2) * kLS + kr] = v.z;
-        As[(4 * c4 + 3) * kLS + kr] = v.w;
-      }
+    // ---- A tile -> As[i][k] (FP32): 64 x 16, one float4 per thread
+    if (!TA) {
+      const int r = tid >> 2, c4 = tid & 3;
+      const float4 v = load4<VEC>(A, lda, m0 + r, M, k0 + 4 * c4, ke);
+      *reinterpret_cast<float4 *>(&As[r * tLA + 4 * c4]) = v;
+    } else {
+      const int kr = tid >> 4, c4 = tid & 15;
+      const float4 v = (k0 + kr < ke) ? load4<VEC>(A, lda, k0 + kr, ke, m0 + 4 * c4, M)
+                                      : make_float4(0.f, 0.f, 0.f, 0.f);
+      As[(4 * c4 + 0) * tLA + kr] = v.x;
+      As[(4 * c4 + 1) * tLA + kr] = v.y;
+      As[(4 * c4 + 2) * tLA + kr] = v.z;
+      As[(4 * c4 + 3) * tLA + kr] = v.w;
     }
-    // ---- B tile -> Bs[j][k]
+    // ---- B tile -> Bs[j][k] (FP64): 16 x 224, seven double pairs per thread
 #pragma unroll
     for (int h = 0; h < 7; ++h) {
       const int idx = tid + 256 * h;
-      const int kr = idx / 56, c4 = idx - kr * 56;
-      const float4 v = (k0 + kr < ke) ? load4<VEC>(B, ldb, k0 + kr, ke, n0 + 4 * c4, N)
-                                      : make_float4(0.f, 0.f, 0.f, 0.f);
-      Bs[(4 * c4 + 0) * kLS + kr] = v.x;
-      Bs[(4 * c4 + 1) * kLS + kr] = v.y;
-      Bs[(4 * c4 + 2) * kLS + kr] = v.z;
-      Bs[(4 * c4 + 3) * kLS + kr] = v.w;
+      const int kr = idx / 112, c2 = idx - kr * 112;
+      const int gk = k0 + kr, gj = n0 + 2 * c2;
+      double v0 = 0.0, v1 = 0.0;
+      if (gk < ke) {
+        const double *q = B + (int64_t)gk * ldb + gj;
+        if (BVEC && gj + 1 < N) {
+          const double2 v = *reinterpret_cast<const double2 *>(q);
+          v0 = v.x;
+          v1 = v.y;
+        } else {
+          if (gj < N) v0 = q[0];
+          if (gj + 1 < N) v1 = q[1];
+        }
+      }
+      Bs[(2 * c2) * tLB + kr] = v0;
+      Bs[(2 * c2 + 1) * tLB + kr] = v1;
     }
     __syncthreads();
 
+    const int ko = 4 * (lane >> 4);
+    float4 a4[2];
+    double bv[7][4];
 #pragma unroll
-    for (int g = 0; g < kKT / 16; ++g) {
-      const int ko = g * 16 + 4 * (lane >> 4);
-      float4 a4[2], b4[7];
+    for (int rt = 0; rt < 2; ++rt)
+      a4[rt] = *reinterpret_cast<const float4 *>(&As[(wr * 32 + rt * 16 + (lane & 15)) * tLA + ko]);
 #pragma unroll
-      for (int rt = 0; rt < 2; ++rt)
-        a4[rt] = *reinterpret_cast<const float4 *>(&As[(wr * 32 + rt * 16 + (lane & 15)) * kLS + ko]);
-#pragma unroll
-      for (int ct = 0; ct < 7; ++ct)
-        b4[ct] = *reinterpret_cast<const float4 *>(&Bs[(wc * 112 + ct * 16 + (lane & 15)) * kLS + ko]);
-#pragma unroll
-      for (int t = 0; t < 4; ++t) {
-#pragma unroll
-        for (int ct = 0; ct < 7; ++ct) {
-          if (!colok[ct]) continue;
-          const float bv = t == 0 ? b4[ct].x : t == 1 ? b4[ct].y : t == 2 ? b4[ct].z : b4[ct].w;
-#pragma unroll
-          for (int rt = 0; rt < 2; ++rt) {
-            const float av = t == 0 ? a4[rt].x : t == 1 ? a4[rt].y : t == 2 ? a4[rt].z : a4[rt].w;
-            acc[rt][ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc[rt][ct], 0, 0, 0);
-          }
-        }
-      }
+    for (int ct = 0; ct < 7; ++ct) {
+      const double2 *bp =
+          reinterpret_cast<const double2 *>(&Bs[(wc * 112 + ct * 16 + (lane & 15)) * tLB + ko]);
+      const double2 lo = bp[0], hi = bp[1];
+      bv[ct][0] = lo.x;
+      bv[ct][1] = lo.y;
+      bv[ct][2] = hi.x;
+      bv[ct][3] = hi.y;
     }
-    if (++tiles == kFlush || k0 + kKT >= ke) {
-      tiles = 0;
 #pragma unroll
-      for (int rt = 0; rt < 2; ++rt)
+    for (int s = 0; s < 4; ++s) {
 #pragma unroll
-        for (int ct = 0; ct < 7; ++ct) {
+      for (int ct = 0; ct < 7; ++ct) {
+        if (!colok[ct]) continue;
 #pragma unroll
-          for (int q = 0; q < 4; ++q) accd[rt][ct][q] += (double)acc[rt][ct][q];
-          acc[rt][ct] = f32x4{0.f, 0.f, 0.f, 0.f};
-        }
+        for (int rt = 0; rt < 2; ++rt)
+          acc[rt][ct] = __builtin_amdgcn_mfma_f64_16x16x4f64((double)f4get(a4[rt], s),
+                                                             bv[ct][s], acc[rt][ct], 0, 0, 0);
+      }
     }
   }
 
-  double *dst = C + (int64_t)blockIdx.z * split_stride;
+  // D layout of 16x16x4f64: lane holds rows (lane/16) + 4 q, column lane%16.
+  double *dst = C + (int64_t)split * split_stride;
 #pragma unroll
   for (int rt = 0; rt < 2; ++rt)
 #pragma unroll
@@ -147,8 +151,8 @@ gemm_f32_mfma(const float *__restrict__ A, int64_t lda, const float *__restrict_
       const int col = n0 + wc * 112 + ct * 16 + (lane & 15);
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        const int row = m0 + wr * 32 + rt * 16 + 4 * (lane >> 4) + q;
-        if (row < M && col < N) dst[(int64_t)row * ldc + col] = accd[rt][ct][q];
+        const int row = m0 + wr * 32 + rt * 16 + (lane >> 4) + 4 * q;
+        if (row < M && col < N) dst[(int64_t)row * ldc + col] = acc[rt][ct][q];
       }
     }
 }
@@ -254,6 +258,18 @@ convert_f64_f32(const double *__restrict__ in, int64_t ldi, int M, int N,
   }
 }
 
+// out[i][j] = (double) in[i][j]
+__global__ void __launch_bounds__(256)
+convert_f32_f64(const float *__restrict__ in, int64_t ldi, int M, int N,
+                double *__restrict__ out, int64_t ldo) {
+  const int64_t total = (int64_t)M * N;
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = idx / N, j = idx - i * N;
+    out[i * ldo + j] = (double)in[i * ldi + j];
+  }
+}
+
 // sigma[i] = sqrt(max(evals[i], 0)), i < k
 __global__ void sqrt_clamp_kernel(const double *__restrict__ ev, int k, double *__restrict__ sigma) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -283,16 +299,19 @@ int grid_cap(int64_t work) {
 }
 }  // namespace
 
-GemmPlan plan_gemm_f32(int M, int N, int K, int num_cus) {
+GemmPlan plan_gemm_tf64(int M, int N, int K, int num_cus) {
   GemmPlan p{};
-  p.gm = ceil_div(M, kBM);
-  p.gn = ceil_div(N, kBN);
+  p.gm = ceil_div(M, tBM);
+  p.gn = ceil_div(N, tBN);
+  // Eight K slices (one per XCD) once K is long enough for each to keep its
+  // workgroups busy; fewer for short K.
   const int64_t tiles = (int64_t)p.gm * p.gn;
-  int64_t splits = ceil_div<int64_t>((int64_t)num_cus * 2, tiles);
-  const int64_t max_splits = ceil_div<int64_t>(K, 256);
+  int64_t splits = 8;
+  if (tiles * 8 < (int64_t)num_cus) splits = ceil_div<int64_t>((int64_t)num_cus * 2, tiles);
+  const int64_t max_splits = ceil_div<int64_t>(K, 512);
   splits = std::max<int64_t>(1, std::min(splits, max_splits));
   int64_t kps = ceil_div<int64_t>(K, splits);
-  kps = ceil_div<int64_t>(kps, kKT) * kKT;
+  kps = ceil_div<int64_t>(kps, tKT) * tKT;
   p.k_per_split = (int)kps;
   p.splits = (int)ceil_div<int64_t>(K, kps);
   p.ldc = N;
@@ -317,27 +336,28 @@ GemmPlan plan_gemm_f64(int M, int N, int K, int num_cus) {
   return p;
 }
 
-hipError_t launch_gemm_f32(const GemmPlan &p, bool trans_a, const float *A, int64_t lda,
-                           const float *B, int64_t ldb, int M, int N, int K, double *part,
-                           hipStream_t st) {
-  dim3 grid(p.gm, p.gn, p.splits);
-  const bool vec = (lda % 4 == 0) && (ldb % 4 == 0) && ((uintptr_t)A % 16 == 0) &&
-                   ((uintptr_t)B % 16 == 0);
-  if (trans_a) {
-    if (vec)
-      hipLaunchKernelGGL((gemm_f32_mfma<true, true>), grid, dim3(256), 0, st, A, lda, B, ldb,
-                         part, p.ldc, p.split_stride, M, N, K, p.k_per_split);
-    else
-      hipLaunchKernelGGL((gemm_f32_mfma<true, false>), grid, dim3(256), 0, st, A, lda, B, ldb,
-                         part, p.ldc, p.split_stride, M, N, K, p.k_per_split);
-  } else {
-    if (vec)
-      hipLaunchKernelGGL((gemm_f32_mfma<false, true>), grid, dim3(256), 0, st, A, lda, B, ldb,
-                         part, p.ldc, p.split_stride, M, N, K, p.k_per_split);
-    else
-      hipLaunchKernelGGL((gemm_f32_mfma<false, false>), grid, dim3(256), 0, st, A, lda, B, ldb,
-                         part, p.ldc, p.split_stride, M, N, K, p.k_per_split);
-  }
+template <bool TA>
+static void launch_tf64_variant(const GemmPlan &p, bool vec, bool bvec, const float *A,
+                                int64_t lda, const double *B, int64_t ldb, int M, int N, int K,
+                                double *part, hipStream_t st) {
+  const dim3 grid((unsigned)((int64_t)p.gm * p.gn * p.splits));
+#define SSI_TF64(V, BV)                                                                      \
+  hipLaunchKernelGGL((gemm_tf64_mfma<TA, V, BV>), grid, dim3(256), 0, st, A, lda, B, ldb, part, \
+                     p.ldc, p.split_stride, M, N, K, p.k_per_split, p.gm, p.splits)
+  if (vec && bvec) SSI_TF64(true, true);
+  else if (vec) SSI_TF64(true, false);
+  else if (bvec) SSI_TF64(false, true);
+  else SSI_TF64(false, false);
+#undef SSI_TF64
+}
+
+hipError_t launch_gemm_tf64(const GemmPlan &p, bool trans_a, const float *A, int64_t lda,
+                            const double *B, int64_t ldb, int M, int N, int K, double *part,
+                            hipStream_t st) {
+  const bool vec = (lda % 4 == 0) && ((uintptr_t)A % 16 == 0);
+  const bool bvec = (ldb % 2 == 0) && ((uintptr_t)B % 16 == 0);
+  if (trans_a) launch_tf64_variant<true>(p, vec, bvec, A, lda, B, ldb, M, N, K, part, st);
+  else launch_tf64_variant<false>(p, vec, bvec, A, lda, B, ldb, M, N, K, part, st);
   return hipGetLastError();
 }
 
@@ -364,6 +384,13 @@ hipError_t launch_reduce(const GemmPlan &p, const double *part, int M, int N, do
 hipError_t launch_convert(const double *in, int64_t ldi, int M, int N, float *out, int64_t ldo,
                           hipStream_t st) {
   hipLaunchKernelGGL(convert_f64_f32, dim3(grid_cap((int64_t)M * N)), dim3(256), 0, st, in,
+                     ldi, M, N, out, ldo);
+  return hipGetLastError();
+}
+
+hipError_t launch_convert_f32_f64(const float *in, int64_t ldi, int M, int N, double *out,
+                                  int64_t ldo, hipStream_t st) {
+  hipLaunchKernelGGL(convert_f32_f64, dim3(grid_cap((int64_t)M * N)), dim3(256), 0, st, in,
                      ldi, M, N, out, ldo);
   return hipGetLastError();
 }

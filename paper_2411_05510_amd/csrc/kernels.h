@@ -32,6 +32,8 @@ hipError_t launch_toeplitz(const float *r, int l, int jb, float *t, int64_t ldt,
 // ---- sketch (sketch.hip)
 hipError_t launch_sketch(uint64_t seed, uint32_t stream, int64_t m, int ell, float *omega,
                          int64_t ldo, hipStream_t st);
+hipError_t launch_sketch(uint64_t seed, uint32_t stream, int64_t m, int ell, double *omega,
+                         int64_t ldo, hipStream_t st);
 
 // ---- dense products (gemm.hip)
 struct GemmPlan {
@@ -39,11 +41,11 @@ struct GemmPlan {
   int64_t ldc, split_stride;     // partial-sum layout: [splits][M][ldc]
   size_t part_elems() const { return (size_t)splits * (size_t)split_stride; }
 };
-GemmPlan plan_gemm_f32(int M, int N, int K, int num_cus);
+GemmPlan plan_gemm_tf64(int M, int N, int K, int num_cus);
 GemmPlan plan_gemm_f64(int M, int N, int K, int num_cus);
-hipError_t launch_gemm_f32(const GemmPlan &p, bool trans_a, const float *A, int64_t lda,
-                           const float *B, int64_t ldb, int M, int N, int K, double *part,
-                           hipStream_t st);
+hipError_t launch_gemm_tf64(const GemmPlan &p, bool trans_a, const float *A, int64_t lda,
+                            const double *B, int64_t ldb, int M, int N, int K, double *part,
+                            hipStream_t st);
 hipError_t launch_gemm_f64(const GemmPlan &p, bool trans_a, const double *A, int64_t lda,
                            const double *B, int64_t ldb, int M, int N, int K, double *part,
                            hipStream_t st);
@@ -52,6 +54,8 @@ hipError_t launch_reduce(const GemmPlan &p, const double *part, int M, int N, do
 hipError_t launch_convert(const double *in, int64_t ldi, int M, int N, float *out, int64_t ldo,
                           hipStream_t st);
 
+hipError_t launch_convert_f32_f64(const float *in, int64_t ldi, int M, int N, double *out,
+                                  int64_t ldo, hipStream_t st);
 hipError_t launch_sqrt_clamp(const double *ev, int k, double *sigma, hipStream_t st);
 hipError_t launch_transpose_f32_f64(const float *in, int64_t ldi, int M, int N, double *out,
                                     int64_t ldo, hipStream_t st);

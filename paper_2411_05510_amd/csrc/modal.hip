@@ -101,94 +101,104 @@ hess_kernel(const double *__restrict__ xbuf, int nmin, int step, double *__restr
       const int i = row_of(tr, p), j = col_of(tc, q);
       g[p][q] = sel(i < n && j < n, X[(int64_t)min(i, n - 1) * n + min(j, n - 1)]);
     }
-  for (int k = 0; k + 2 < n; ++k) {
-    const int kq = k >> 5;
-    if (tc == (k & 31)) {
-      double s2 = 0.0, x1 = 0.0;
+  // Column k lives in column block kq = k / 32; the unrolled block loop makes
+  // the owner's registers compile-time indices.  The left update touches rows
+  // > k and (up to rounding residue that is never read again) columns >= k;
+  // the right update touches columns > k of every row.
+#pragma unroll kTQ
+  for (int kq = 0; kq < kTQ; ++kq) {
+    const int k0 = 32 * kq, k1 = min(k0 + 32, n - 2);
+    for (int k = k0; k < k1; ++k) {
+      if (tc == (k & 31)) {
+        double s2 = 0.0, x1 = 0.0;
 #pragma unroll
-      for (int p = 0; p < kTP; ++p) {
-        const int i = row_of(tr, p);
-        double v = 0.0;
-#pragma unroll
-        for (int q = 0; q < kTQ; ++q) v = (q == kq) ? g[p][q] : v;
-        x1 += sel(i == k + 1, v);
-        s2 += sel(i > k + 1 && i < n, v * v);
-      }
-      s2 = col_group_sum(s2);
-      x1 = col_group_sum(x1);
-      double tau = 0.0, v1 = 0.0;
-      if (s2 > 0.0) {
-        const double alpha = -copysign(sqrt(x1 * x1 + s2), x1);
-        v1 = x1 - alpha;
-        tau = 2.0 / (s2 + v1 * v1);
-      }
-#pragma unroll
-      for (int p = 0; p < kTP; ++p) {
-        const int i = row_of(tr, p);
-        double gv = 0.0;
-#pragma unroll
-        for (int q = 0; q < kTQ; ++q) gv = (q == kq) ? g[p][q] : gv;
-        if (i < n) {
-          const double v = (i == k + 1) ? v1 : sel(i > k + 1, gv);
-          vbuf[i] = v;
-          vr[(size_t)k * kNR + i] = v;
+        for (int p = 0; p < kTP; ++p) {
+          const int i = row_of(tr, p);
+          const double v = g[p][kq];
+          x1 += sel(i == k + 1, v);
+          s2 += sel(i > k + 1 && i < n, v * v);
         }
-      }
-      if (tr == 0) {
-        stau = tau;
-        tv[k] = tau;
-      }
-    }
-    __syncthreads();
-    const double tau = stau;
-    if (tau != 0.0) {
-      // left: X -= tau v (v^T X)
-      double zq[kTQ];
-#pragma unroll
-      for (int q = 0; q < kTQ; ++q) zq[q] = 0.0;
-#pragma unroll
-      for (int p = 0; p < kTP; ++p) {
-        const int i = row_of(tr, p);
-        const double vi = sel(i > k && i < n, vbuf[min(i, kNR - 1)]);
-#pragma unroll
-        for (int q = 0; q < kTQ; ++q) zq[q] += vi * g[p][q];
-      }
-#pragma unroll
-      for (int q = 0; q < kTQ; ++q) zq[q] = tau * col_group_sum(zq[q]);
-      double vj[kTQ];
-#pragma unroll
-      for (int q = 0; q < kTQ; ++q) {
-        const int j = col_of(tc, q);
-        vj[q] = sel(j > k && j < n, vbuf[min(j, kNR - 1)]);
-      }
-#pragma unroll
-      for (int p = 0; p < kTP; ++p) {
-        const int i = row_of(tr, p);
-        const double vi = sel(i > k && i < n, vbuf[min(i, kNR - 1)]);
-        double acc = 0.0;
-#pragma unroll
-        for (int q = 0; q < kTQ; ++q) {
-          g[p][q] -= vi * zq[q];
-          acc += g[p][q] * vj[q];
+        s2 = col_group_sum(s2);
+        x1 = col_group_sum(x1);
+        double tau = 0.0, v1 = 0.0;
+        if (s2 > 0.0) {
+          const double alpha = -copysign(sqrt(x1 * x1 + s2), x1);
+          v1 = x1 - alpha;
+          tau = 2.0 / (s2 + v1 * v1);
         }
-        // right: y = X v (row sums over all 32 grid columns)
-        acc += __shfl_xor(acc, 16, 64);
-        acc += __shfl_xor(acc, 32, 64);
-        if ((lane >> 4) == 0) ypart[wave][i] = acc;
+#pragma unroll
+        for (int p = 0; p < kTP; ++p) {
+          const int i = row_of(tr, p);
+          if (i < n) {
+            const double v = (i == k + 1) ? v1 : sel(i > k + 1, g[p][kq]);
+            vbuf[i] = v;
+            vr[(size_t)k * kNR + i] = v;
+          }
+        }
+        if (tr == 0) {
+          stau = tau;
+          tv[k] = tau;
+        }
       }
       __syncthreads();
+      const double tau = stau;
+      if (tau != 0.0) {
+        // left: X -= tau v (v^T X)
+        double zq[kTQ];
 #pragma unroll
-      for (int p = 0; p < kTP; ++p) {
-        const int i = row_of(tr, p);
-        double y = 0.0;
+        for (int q = 0; q < kTQ; ++q) zq[q] = 0.0;
 #pragma unroll
-        for (int w = 0; w < 8; ++w) y += ypart[w][i];
-        y *= tau;
+        for (int p = 0; p < kTP; ++p) {
+          if (p < 2 * kq) continue;
+          const int i = row_of(tr, p);
+          const double vi = sel(i > k && i < n, vbuf[min(i, kNR - 1)]);
 #pragma unroll
-        for (int q = 0; q < kTQ; ++q) g[p][q] -= y * vj[q];
+          for (int q = 0; q < kTQ; ++q) {
+            if (q < kq) continue;
+            zq[q] += vi * g[p][q];
+          }
+        }
+#pragma unroll
+        for (int q = 0; q < kTQ; ++q) zq[q] = (q < kq) ? 0.0 : tau * col_group_sum(zq[q]);
+        double vj[kTQ];
+#pragma unroll
+        for (int q = 0; q < kTQ; ++q) {
+          const int j = col_of(tc, q);
+          vj[q] = sel(q >= kq && j > k && j < n, vbuf[min(j, kNR - 1)]);
+        }
+#pragma unroll
+        for (int p = 0; p < kTP; ++p) {
+          const int i = row_of(tr, p);
+          const double vi = sel(i > k && i < n, vbuf[min(i, kNR - 1)]);
+          double acc = 0.0;
+#pragma unroll
+          for (int q = 0; q < kTQ; ++q) {
+            if (q < kq) continue;
+            if (p >= 2 * kq) g[p][q] -= vi * zq[q];
+            acc += g[p][q] * vj[q];
+          }
+          // right: y = X v (row sums over all 32 grid columns)
+          acc += __shfl_xor(acc, 16, 64);
+          acc += __shfl_xor(acc, 32, 64);
+          if ((lane >> 4) == 0) ypart[wave][i] = acc;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int p = 0; p < kTP; ++p) {
+          const int i = row_of(tr, p);
+          double y = 0.0;
+#pragma unroll
+          for (int w = 0; w < 8; ++w) y += ypart[w][i];
+          y *= tau;
+#pragma unroll
+          for (int q = 0; q < kTQ; ++q) {
+            if (q < kq) continue;
+            g[p][q] -= y * vj[q];
+          }
+        }
       }
+      __syncthreads();
     }
-    __syncthreads();
   }
 #pragma unroll
   for (int p = 0; p < kTP; ++p)
@@ -217,32 +227,39 @@ qform_kernel(int nmin, int step, const double *__restrict__ vref,
 #pragma unroll
     for (int q = 0; q < kTQ; ++q)
       g[p][q] = sel(row_of(tr, p) == col_of(tc, q) && row_of(tr, p) < n, 1.0);
-  for (int k = n - 3; k >= 0; --k) {
-    for (int i = t; i < n; i += kT) vbuf[i] = (i > k) ? vr[(size_t)k * kNR + i] : 0.0;
-    __syncthreads();
-    const double tau = tv[k];
-    if (tau != 0.0) {
-      double sq[kTQ];
+  // Reflector k touches rows > k only: row blocks before k / 16 are skipped.
+#pragma unroll kTP
+  for (int kb = kTP - 1; kb >= 0; --kb) {
+    const int k0 = 16 * kb, k1 = min(k0 + 16, n - 2);
+    for (int k = k1 - 1; k >= k0; --k) {
+      for (int i = t; i < n; i += kT) vbuf[i] = (i > k) ? vr[(size_t)k * kNR + i] : 0.0;
+      __syncthreads();
+      const double tau = tv[k];
+      if (tau != 0.0) {
+        double sq[kTQ];
 #pragma unroll
-      for (int q = 0; q < kTQ; ++q) sq[q] = 0.0;
+        for (int q = 0; q < kTQ; ++q) sq[q] = 0.0;
 #pragma unroll
-      for (int p = 0; p < kTP; ++p) {
-        const int i = row_of(tr, p);
-        const double vi = sel(i > k && i < n, vbuf[min(i, kNR - 1)]);
+        for (int p = 0; p < kTP; ++p) {
+          if (p < kb) continue;
+          const int i = row_of(tr, p);
+          const double vi = sel(i > k && i < n, vbuf[min(i, kNR - 1)]);
 #pragma unroll
-        for (int q = 0; q < kTQ; ++q) sq[q] += vi * g[p][q];
+          for (int q = 0; q < kTQ; ++q) sq[q] += vi * g[p][q];
+        }
+#pragma unroll
+        for (int q = 0; q < kTQ; ++q) sq[q] = tau * col_group_sum(sq[q]);
+#pragma unroll
+        for (int p = 0; p < kTP; ++p) {
+          if (p < kb) continue;
+          const int i = row_of(tr, p);
+          const double vi = sel(i > k && i < n, vbuf[min(i, kNR - 1)]);
+#pragma unroll
+          for (int q = 0; q < kTQ; ++q) g[p][q] -= vi * sq[q];
+        }
       }
-#pragma unroll
-      for (int q = 0; q < kTQ; ++q) sq[q] = tau * col_group_sum(sq[q]);
-#pragma unroll
-      for (int p = 0; p < kTP; ++p) {
-        const int i = row_of(tr, p);
-        const double vi = sel(i > k && i < n, vbuf[min(i, kNR - 1)]);
-#pragma unroll
-        for (int q = 0; q < kTQ; ++q) g[p][q] -= vi * sq[q];
-      }
+      __syncthreads();
     }
-    __syncthreads();
   }
 #pragma unroll
   for (int p = 0; p < kTP; ++p)
@@ -273,35 +290,26 @@ ch_kernel(const double *__restrict__ u, int k, int l, int nmin, int step,
 // ------------------------------------------------------------------ francis
 namespace {
 
-// Upper Hessenberg matrix in packed rows (row 0: columns 0..n-1; row i >= 1:
-// columns i-1..n-1) plus the bulge entries (i, i-2) and (i, i-3) of the
-// Francis sweep, which live only near the current bulge (slots i mod 4).
-struct PackedH {
-  double *a;        // packed rows
-  double *b2, *b3;  // [4] bulge slots
-  int n;
-  SSI_DEV int64_t idx(int i, int j) const {
-    if (i == 0) return j;
-    return (int64_t)n + (int64_t)(i - 1) * (n + 1) - (int64_t)(i - 1) * i / 2 + (j - (i - 1));
-  }
-  SSI_DEV double get(int i, int j) const {
-    if (j >= i - 1) return a[idx(i, j)];
-    if (j == i - 2) return b2[i & 3];
-    if (j == i - 3) return b3[i & 3];
-    return 0.0;
-  }
-  SSI_DEV void set(int i, int j, double v) const {
-    if (j >= i - 1) a[idx(i, j)] = v;
-    else if (j == i - 2) b2[i & 3] = v;
-    else if (j == i - 3) b3[i & 3] = v;
-  }
-  static __host__ __device__ int64_t size(int n) {
-    return (int64_t)n + (int64_t)(n - 1) * (n + 2) / 2;
-  }
-};
+constexpr int kFT = 256;                 // four waves per order
+constexpr int kLdsDoubles = 20312;       // packed H (20299 doubles at n = 200) + 8 bulge slots
 
-constexpr int kFT = 256;                 // francis threads
-constexpr int kLdsDoubles = 20300;       // packed H in LDS for n <= 200 (20299 doubles)
+// Upper Hessenberg H in packed rows (row 0: columns 0..n-1; row i >= 1:
+// columns i-1..n-1), followed by 8 slots for the entries (i, i-2) and
+// (i, i-3) that the Francis bulge creates below the subdiagonal; those live
+// only next to the current bulge, so slot i mod 4 suffices.  Index selection
+// is branch-free.
+struct HIdx {
+  int n, b2, b3;
+  SSI_DEV int row_start(int i) const {
+    return i == 0 ? 0 : n + (i - 1) * (n + 1) - ((i - 1) * i) / 2;
+  }
+  SSI_DEV int operator()(int i, int j) const {
+    const int packed = row_start(i) + j - (i > 0 ? i - 1 : 0);
+    const int bulge = (j == i - 2 ? b2 : b3) + (i & 3);
+    return j >= i - 1 ? packed : bulge;
+  }
+  static __host__ __device__ int packed_size(int n) { return n + ((n - 1) * (n + 2)) / 2; }
+};
 
 SSI_DEV void two_by_two_eigs(double a, double b, double c, double d, double *wr, double *wi) {
   const double p = 0.5 * (a - d);
@@ -321,71 +329,96 @@ SSI_DEV void two_by_two_eigs(double a, double b, double c, double d, double *wr,
   }
 }
 
+SSI_DEV int wave_max_int(int v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = max(v, __shfl_xor(v, off, 64));
+  return v;
+}
+
+// Maximum over the workgroup; every thread gets the result.
+SSI_DEV int block_max_int(int v, int *red) {
+  v = wave_max_int(v);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  int r = red[0];
+#pragma unroll
+  for (int w = 1; w < kFT / 64; ++w) r = max(r, red[w]);
+  __syncthreads();
+  return r;
+}
+
 }  // namespace
 
-// Eigenvalues of H_n.  ev: [2][n] (re, im) per order at 2 * vec(o).  Writes
-// the count of eigenvalues with Im > 0 to npole[o] and their indices (in the
-// order found) to pidx at vec(o).  flags[o] = 1 if the iteration limit hit.
+// Eigenvalues of H_n by the Francis double-shift QR iteration (eigenvalues
+// only, so updates stay inside the active window [l, hi]); ad hoc shifts
+// after 10 iterations without deflation.  ev: (re[n], im[n]) per order at
+// 2 vec(o).  Writes the number of eigenvalues with Im > 0 to npole[o] and
+// their indices to pidx at vec(o); flags[o] = 1 if the iteration limit hit.
+//
+// One workgroup of four waves per order.  Each bulge step is two phases
+// separated by barriers: the reflector (computed redundantly by every thread
+// from the column the previous step produced) is applied to rows k..k+2 over
+// columns k..hi, then to columns k..k+2 over rows l..k+3.  The reflected
+// column k-1 becomes (alpha, 0, 0) exactly; it is written in the column phase
+// so that no thread can overwrite it while another still reads it as the
+// reflector's input.
 template <bool LDS>
 __global__ void __launch_bounds__(kFT)
 francis_kernel(const double *__restrict__ hbuf, int nmin, int step, int o_first,
-               double *__restrict__ gscr, double *__restrict__ evbuf, int *__restrict__ npole,
-               int *__restrict__ pidx, int *__restrict__ flags) {
+               double *__restrict__ gscr, int64_t gstride, double *__restrict__ evbuf,
+               int *__restrict__ npole, int *__restrict__ pidx, int *__restrict__ flags) {
   extern __shared__ double lds_h[];
-  __shared__ double bulge[8];
-  __shared__ int s_l;
-  __shared__ double s_x, s_y, s_z;
+  __shared__ int red[kFT / 64];
   const int o = o_first + blockIdx.x;
   const OrderGeo geo = order_geo(o, nmin, step);
   const int n = geo.n;
   const double *Hin = hbuf + geo.sq;
   double *wr = evbuf + 2 * geo.vec, *wi = wr + n;
   const int t = threadIdx.x;
-  PackedH H;
-  H.n = n;
-  H.a = LDS ? lds_h : gscr + (size_t)blockIdx.x * (size_t)PackedH::size(kNR);
-  H.b2 = bulge;
-  H.b3 = bulge + 4;
+  double *A = LDS ? lds_h : gscr + (size_t)blockIdx.x * gstride;
+  const int psz = HIdx::packed_size(n);
+  const HIdx ix{n, psz, psz + 4};
   for (int i = 0; i < n; ++i) {
     const int j0 = i == 0 ? 0 : i - 1;
-    for (int j = j0 + t; j < n; j += kFT) H.a[H.idx(i, j)] = Hin[(int64_t)i * n + j];
+    const int rs = ix.row_start(i);
+    for (int j = j0 + t; j < n; j += kFT) A[rs + j - j0] = Hin[(int64_t)i * n + j];
   }
-  if (t < 8) bulge[t] = 0.0;
+  if (t < 8) A[psz + t] = 0.0;
   __syncthreads();
 
   const double eps = 2.220446049250313e-16;
-  int hi = n - 1;
-  int iter = 0, total = 0;
+  int hi = n - 1, iter = 0, total = 0;
   const int itmax = 30 * max(10, n);
   bool failed = false;
   while (hi >= 0) {
-    // ---- deflation: largest l in (0, hi] with a negligible subdiagonal
-    if (t == 0) s_l = 0;
-    __syncthreads();
-    for (int i = 1 + t; i <= hi; i += kFT) {
-      const double sub = fabs(H.get(i, i - 1));
-      double ref = fabs(H.get(i - 1, i - 1)) + fabs(H.get(i, i));
+    // deflation: largest l in (0, hi] with a negligible subdiagonal entry
+    int cand = 0;
+    for (int i = hi - t; i >= 1; i -= kFT) {
+      const double sub = fabs(A[ix(i, i - 1)]);
+      double ref = fabs(A[ix(i - 1, i - 1)]) + fabs(A[ix(i, i)]);
       if (ref == 0.0) {
-        if (i - 2 >= 0) ref += fabs(H.get(i - 1, i - 2));
-        if (i + 1 <= hi) ref += fabs(H.get(i + 1, i));
+        if (i >= 2) ref += fabs(A[ix(i - 1, i - 2)]);
+        if (i + 1 <= hi) ref += fabs(A[ix(i + 1, i)]);
       }
-      if (sub <= eps * ref) atomicMax(&s_l, i);
+      if (sub <= eps * ref) {
+        cand = i;
+        break;
+      }
     }
-    __syncthreads();
-    const int l = s_l;
-    if (l > 0 && t == 0) H.set(l, l - 1, 0.0);
-    if (l == hi) {                       // 1 x 1 block
-      if (t == 0) { wr[hi] = H.get(hi, hi); wi[hi] = 0.0; }
+    const int l = block_max_int(cand, red);
+    if (l > 0 && t == 0) A[ix(l, l - 1)] = 0.0;
+    if (l == hi) {
+      if (t == 0) { wr[hi] = A[ix(hi, hi)]; wi[hi] = 0.0; }
       hi -= 1;
       iter = 0;
       __syncthreads();
       continue;
     }
-    if (l == hi - 1) {                   // 2 x 2 block
+    if (l == hi - 1) {
       if (t == 0) {
         double r2[2], i2[2];
-        two_by_two_eigs(H.get(hi - 1, hi - 1), H.get(hi - 1, hi), H.get(hi, hi - 1),
-                        H.get(hi, hi), r2, i2);
+        two_by_two_eigs(A[ix(hi - 1, hi - 1)], A[ix(hi - 1, hi)], A[ix(hi, hi - 1)],
+                        A[ix(hi, hi)], r2, i2);
         wr[hi - 1] = r2[0]; wi[hi - 1] = i2[0];
         wr[hi] = r2[1]; wi[hi] = i2[1];
       }
@@ -399,80 +432,81 @@ francis_kernel(const double *__restrict__ hbuf, int nmin, int step, int o_first,
       break;
     }
     ++iter;
-    // ---- shifts: eigenvalues of the trailing 2 x 2 block, or ad hoc shifts
     double s, tt;
     if (iter % 11 == 10) {
-      const double e = fabs(H.get(hi, hi - 1)) + fabs(H.get(hi - 1, hi - 2));
-      const double h11 = 0.75 * e + H.get(hi, hi), h12 = -0.4375 * e;
+      const double e = fabs(A[ix(hi, hi - 1)]) + fabs(A[ix(hi - 1, hi - 2)]);
+      const double h11 = 0.75 * e + A[ix(hi, hi)], h12 = -0.4375 * e;
       s = 2.0 * h11;
       tt = h11 * h11 - h12 * e;
     } else {
-      const double a = H.get(hi - 1, hi - 1), b = H.get(hi - 1, hi);
-      const double c = H.get(hi, hi - 1), d = H.get(hi, hi);
+      const double a = A[ix(hi - 1, hi - 1)], b = A[ix(hi - 1, hi)];
+      const double c = A[ix(hi, hi - 1)], d = A[ix(hi, hi)];
       s = a + d;
       tt = a * d - b * c;
     }
-    // first column of (H - s1 I)(H - s2 I)
-    const double h00 = H.get(l, l), h01 = H.get(l, l + 1), h10 = H.get(l + 1, l);
-    const double h11 = H.get(l + 1, l + 1), h21 = H.get(l + 2, l + 1);
+    // first column of (H - s1 I)(H - s2 I) restricted to the window
+    const double h00 = A[ix(l, l)], h01 = A[ix(l, l + 1)], h10 = A[ix(l + 1, l)];
+    const double h11 = A[ix(l + 1, l + 1)], h21 = A[ix(l + 2, l + 1)];
     double x = h00 * h00 + h01 * h10 - s * h00 + tt;
     double y = h10 * (h00 + h11 - s);
     double z = h10 * h21;
+    __syncthreads();                      // all reads above precede the first update
     for (int k = l; k <= hi - 1; ++k) {
       const bool three = k < hi - 1;
-      // Householder reflector P = I - beta v v^T with P (x, y, z)^T = (alpha, 0, 0)^T
       const double zz = three ? z : 0.0;
       const double nrm = sqrt(x * x + y * y + zz * zz);
-      double v0 = 1.0, v1 = 0.0, v2 = 0.0, beta = 0.0;
-      if (nrm > 0.0 && (y != 0.0 || zz != 0.0)) {
-        const double alpha = -copysign(nrm, x);
+      const bool act = nrm > 0.0 && (y != 0.0 || zz != 0.0);
+      double alpha = 0.0, v1 = 0.0, v2 = 0.0, beta = 0.0;
+      if (act) {
+        alpha = -copysign(nrm, x);
         const double u0 = x - alpha;
         v1 = y / u0;
         v2 = zz / u0;
-        beta = -u0 / alpha;            // 2 / (v^T v) with v = (1, v1, v2)
-      }
-      if (beta != 0.0) {
-        // rows k..k+2 (k+1 for the final 2 x 2 step), columns q..hi
-        const int q = max(l, k - 1);
-        for (int j = q + t; j <= hi; j += kFT) {
-          const double a0 = H.get(k, j), a1 = H.get(k + 1, j);
-          const double a2 = three ? H.get(k + 2, j) : 0.0;
+        beta = -u0 / alpha;
+        // rows k..k+2, columns k..hi; entry (k+2, k) is a bulge slot
+        const int r0 = ix.row_start(k) - (k > 0 ? k - 1 : 0);
+        const int r1 = ix.row_start(k + 1) - k;
+        const int r2 = three ? ix.row_start(k + 2) - (k + 1) : r1;
+        const int b2 = psz + ((k + 2) & 3);
+        for (int j = k + t; j <= hi; j += kFT) {
+          const int i0 = r0 + j, i1 = r1 + j;
+          const int i2 = three ? (j == k ? b2 : r2 + j) : i1;
+          const double a0 = A[i0], a1 = A[i1];
+          const double a2 = three ? A[i2] : 0.0;
           const double d = beta * (a0 + v1 * a1 + v2 * a2);
-          H.set(k, j, a0 - d);
-          H.set(k + 1, j, a1 - d * v1);
-          if (three) H.set(k + 2, j, a2 - d * v2);
+          A[i0] = a0 - d;
+          A[i1] = a1 - d * v1;
+          if (three) A[i2] = a2 - d * v2;
         }
-        __syncthreads();
-        if (k > l && t == 0) {           // annihilated bulge entries
-          H.set(k + 1, k - 1, 0.0);
-          if (three) H.set(k + 2, k - 1, 0.0);
+      }
+      __syncthreads();
+      if (act) {
+        if (k > l && t == 0) {           // the reflected column k - 1
+          A[ix(k, k - 1)] = alpha;
+          A[ix(k + 1, k - 1)] = 0.0;
+          if (three) A[ix(k + 2, k - 1)] = 0.0;
         }
         // columns k..k+2, rows l..min(k+3, hi)
         const int r = min(k + 3, hi);
         for (int i = l + t; i <= r; i += kFT) {
-          const double a0 = H.get(i, k), a1 = H.get(i, k + 1);
-          const double a2 = three ? H.get(i, k + 2) : 0.0;
+          const int i0 = ix(i, k), i1 = ix(i, k + 1), i2 = three ? ix(i, k + 2) : i1;
+          const double a0 = A[i0], a1 = A[i1];
+          const double a2 = three ? A[i2] : 0.0;
           const double d = beta * (a0 + v1 * a1 + v2 * a2);
-          H.set(i, k, a0 - d);
-          H.set(i, k + 1, a1 - d * v1);
-          if (three) H.set(i, k + 2, a2 - d * v2);
+          A[i0] = a0 - d;
+          A[i1] = a1 - d * v1;
+          if (three) A[i2] = a2 - d * v2;
         }
       }
       __syncthreads();
       if (k < hi - 1) {
-        if (t == 0) {
-          s_x = H.get(k + 1, k);
-          s_y = H.get(k + 2, k);
-          s_z = (k < hi - 2) ? H.get(k + 3, k) : 0.0;
-        }
-        __syncthreads();
-        x = s_x;
-        y = s_y;
-        z = s_z;
-        __syncthreads();
+        x = A[ix(k + 1, k)];
+        y = A[ix(k + 2, k)];
+        z = (k < hi - 2) ? A[ix(k + 3, k)] : 0.0;
       }
     }
   }
+  __syncthreads();
   if (t == 0) {
     int cnt = 0;
     if (!failed) {
@@ -732,9 +766,6 @@ namespace ssi {
 
 int modal_max_order() { return kNR; }
 
-size_t modal_francis_lds(int n) {
-  return n <= 200 ? sizeof(double) * kLdsDoubles : 0;
-}
 
 ModalSizes modal_sizes(int nmin, int nmax, int step, int l) {
   ModalSizes s{};
@@ -750,7 +781,7 @@ ModalSizes modal_sizes(int nmin, int nmax, int step, int l) {
   s.ch = (int64_t)l * s.vec;
   s.vec_waves = 1024;
   s.vec_stride = 2 * ((int64_t)kNR * (kNR + 1) / 2 + 64);
-  s.francis_glb = (int64_t)PackedH::size(kNR);
+  s.francis_glb = (int64_t)HIdx::packed_size(kNR) + 8;
   return s;
 }
 
@@ -776,11 +807,12 @@ hipError_t launch_modal(const ModalArgs &a, hipStream_t st) {
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(francis_kernel<true>, dim3(n_lds), dim3(kFT),
                        sizeof(double) * kLdsDoubles, st, a.hbuf, a.nmin, a.step, 0, a.gscr,
-                       a.evbuf, a.npole, a.pidx, a.flags_tmp);
+                       s.francis_glb, a.evbuf, a.npole, a.pidx, a.flags_tmp);
   }
   if (n_lds < no)
     hipLaunchKernelGGL(francis_kernel<false>, dim3(no - n_lds), dim3(kFT), 0, st, a.hbuf,
-                       a.nmin, a.step, n_lds, a.gscr, a.evbuf, a.npole, a.pidx, a.flags_tmp);
+                       a.nmin, a.step, n_lds, a.gscr, s.francis_glb, a.evbuf, a.npole, a.pidx,
+                       a.flags_tmp);
   hipLaunchKernelGGL(vec_kernel, dim3((unsigned)s.vec_waves), dim3(64), 0, st, a.hbuf, a.chbuf,
                      a.evbuf, a.npole, a.pidx, a.nmin, a.step, no, a.l, a.fs, a.vscr,
                      s.vec_stride, a.tf, a.txi, a.tmu, a.tphi);

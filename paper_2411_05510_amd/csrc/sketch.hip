@@ -35,8 +35,9 @@ SSI_DEV double uniform52(uint32_t lo, uint32_t hi) {
 
 }  // namespace
 
+template <typename T>
 __global__ void __launch_bounds__(256)
-sketch_philox(uint64_t seed, uint32_t stream, int64_t m, int ell, float *__restrict__ omega,
+sketch_philox(uint64_t seed, uint32_t stream, int64_t m, int ell, T *__restrict__ omega,
               int64_t ldo) {
   const int64_t total = m * (int64_t)ell;
   const int64_t pairs = (total + 1) / 2;
@@ -51,26 +52,39 @@ sketch_philox(uint64_t seed, uint32_t stream, int64_t m, int ell, float *__restr
     const int64_t e0 = 2 * g;
     {
       const int64_t i = e0 / ell, c = e0 - i * ell;
-      omega[i * ldo + c] = (float)(rad * cs);
+      omega[i * ldo + c] = (T)(rad * cs);
     }
     if (e0 + 1 < total) {
       const int64_t e1 = e0 + 1;
       const int64_t i = e1 / ell, c = e1 - i * ell;
-      omega[i * ldo + c] = (float)(rad * sn);
+      omega[i * ldo + c] = (T)(rad * sn);
     }
   }
 }
 
 namespace ssi {
 
-hipError_t launch_sketch(uint64_t seed, uint32_t stream, int64_t m, int ell, float *omega,
+namespace {
+template <typename T>
+hipError_t sketch_launch(uint64_t seed, uint32_t stream, int64_t m, int ell, T *omega,
                          int64_t ldo, hipStream_t st) {
   const int64_t pairs = (m * (int64_t)ell + 1) / 2;
   int64_t blocks = ceil_div<int64_t>(pairs, 256);
   if (blocks > 8192) blocks = 8192;
-  hipLaunchKernelGGL(sketch_philox, dim3((unsigned)blocks), dim3(256), 0, st, seed, stream, m,
+  hipLaunchKernelGGL(sketch_philox<T>, dim3((unsigned)blocks), dim3(256), 0, st, seed, stream, m,
                      ell, omega, ldo);
   return hipGetLastError();
+}
+}  // namespace
+
+hipError_t launch_sketch(uint64_t seed, uint32_t stream, int64_t m, int ell, float *omega,
+                         int64_t ldo, hipStream_t st) {
+  return sketch_launch(seed, stream, m, ell, omega, ldo, st);
+}
+
+hipError_t launch_sketch(uint64_t seed, uint32_t stream, int64_t m, int ell, double *omega,
+                         int64_t ldo, hipStream_t st) {
+  return sketch_launch(seed, stream, m, ell, omega, ldo, st);
 }
 
 }  // namespace ssi
