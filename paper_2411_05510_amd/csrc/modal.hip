@@ -290,26 +290,39 @@ ch_kernel(const double *__restrict__ u, int k, int l, int nmin, int step,
 // ------------------------------------------------------------------ francis
 namespace {
 
-constexpr int kFT = 256;                 // four waves per order
-constexpr int kLdsDoubles = 20312;       // packed H (20299 doubles at n = 200) + 8 bulge slots
+constexpr int kNB = 5;                   // bulges (shift pairs) per multishift sweep
+constexpr int kFT = 64 * kNB;            // one wave per bulge
+constexpr int kSM = 2 * kNB;             // order of the trailing block that supplies shifts
+constexpr int kRing = 16;                // bulge-slot ring rows, >= 3 kNB + 1, power of two
+constexpr int kMsMin = 24;               // active windows from this size use multishift sweeps
+// LDS after the packed H: bulge slots (2 kRing), the shift block's
+// eigenvalues (2 kSM), shift pairs (2 kNB) and the shift block (kSM^2).
+constexpr int kExtra = 2 * kRing + 2 * kSM + 2 * kNB + kSM * kSM;
+constexpr int kLdsMaxN = 200;
+constexpr int kRowIt = (kNR + 63) / 64;  // panel elements per lane in a bulge step
+constexpr int kLdsDoubles = 20299 + kExtra;   // 20299 = packed size at n = 200
 
 // Upper Hessenberg H in packed rows (row 0: columns 0..n-1; row i >= 1:
-// columns i-1..n-1), followed by 8 slots for the entries (i, i-2) and
-// (i, i-3) that the Francis bulge creates below the subdiagonal; those live
-// only next to the current bulge, so slot i mod 4 suffices.  Index selection
-// is branch-free.
+// columns i-1..n-1), followed by slots for the entries (i, i-2) and (i, i-3)
+// that bulges create below the subdiagonal.  Those exist only inside the
+// chain of bulges (at most 3 kNB consecutive rows), so a ring of kRing rows
+// indexed by i mod kRing suffices.  Index selection is branch-free.
 struct HIdx {
   int n, b2, b3;
-  SSI_DEV int row_start(int i) const {
-    return i == 0 ? 0 : n + (i - 1) * (n + 1) - ((i - 1) * i) / 2;
-  }
+  // packed index of (i, j), j >= i - 1, is base(i) + j
+  SSI_DEV int base(int i) const { return __mul24(i, n) - (__mul24(i, i - 1) >> 1); }
+  SSI_DEV int row_start(int i) const { return base(i) + (i > 0 ? i - 1 : 0); }
   SSI_DEV int operator()(int i, int j) const {
-    const int packed = row_start(i) + j - (i > 0 ? i - 1 : 0);
-    const int bulge = (j == i - 2 ? b2 : b3) + (i & 3);
-    return j >= i - 1 ? packed : bulge;
+    const int bulge = (j == i - 2 ? b2 : b3) + (i & (kRing - 1));
+    return j >= i - 1 ? base(i) + j : bulge;
   }
-  static __host__ __device__ int packed_size(int n) { return n + ((n - 1) * (n + 2)) / 2; }
+  static constexpr __host__ __device__ int packed_size(int n) {
+    return n + ((n - 1) * (n + 2)) / 2;
+  }
 };
+static_assert(HIdx::packed_size(kLdsMaxN) == 20299, "packed size at the LDS limit");
+static_assert(kLdsDoubles * 8 + 64 <= 160 * 1024, "Francis LDS budget");
+static_assert(kRing >= 3 * kNB + 1, "bulge ring too short for the chain");
 
 SSI_DEV void two_by_two_eigs(double a, double b, double c, double d, double *wr, double *wi) {
   const double p = 0.5 * (a - d);
@@ -347,21 +360,302 @@ SSI_DEV int block_max_int(int v, int *red) {
   return r;
 }
 
+// Orders LDS accesses of one wave (the lanes run in lockstep, so a fence
+// against compiler reordering is all the ordering needed).
+SSI_DEV void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
+// Eigenvalues of the m x m upper Hessenberg matrix a (row-major, ld kSM, m <=
+// kSM; entries below the subdiagonal are zero and stay in place) by the
+// double-shift QR iteration, run by one wave.  Returns false if the
+// iteration limit is hit.
+SSI_DEV bool small_eig(double *a, int m, double *er, double *ei, int lane) {
+  const double eps = 2.220446049250313e-16;
+  int hi = m - 1, iter = 0, total = 0;
+  while (hi >= 0) {
+    int cand = 0;
+    for (int i = hi - lane; i >= 1; i -= 64) {
+      const double sub = fabs(a[i * kSM + i - 1]);
+      double ref = fabs(a[(i - 1) * kSM + i - 1]) + fabs(a[i * kSM + i]);
+      if (ref == 0.0) {
+        if (i >= 2) ref += fabs(a[(i - 1) * kSM + i - 2]);
+        if (i + 1 <= hi) ref += fabs(a[(i + 1) * kSM + i]);
+      }
+      if (sub <= eps * ref) {
+        cand = i;
+        break;
+      }
+    }
+    const int l = wave_max_int(cand);
+    wave_sync();
+    if (l > 0 && lane == 0) a[l * kSM + l - 1] = 0.0;
+    if (l == hi) {
+      er[hi] = a[hi * kSM + hi];
+      ei[hi] = 0.0;
+      hi -= 1;
+      iter = 0;
+      wave_sync();
+      continue;
+    }
+    if (l == hi - 1) {
+      double r2[2], i2[2];
+      two_by_two_eigs(a[(hi - 1) * kSM + hi - 1], a[(hi - 1) * kSM + hi], a[hi * kSM + hi - 1],
+                      a[hi * kSM + hi], r2, i2);
+      er[hi - 1] = r2[0]; ei[hi - 1] = i2[0];
+      er[hi] = r2[1]; ei[hi] = i2[1];
+      hi -= 2;
+      iter = 0;
+      wave_sync();
+      continue;
+    }
+    if (++total > 30 * kSM) return false;
+    ++iter;
+    double sh, tt;
+    if (iter % 11 == 10) {
+      const double e = fabs(a[hi * kSM + hi - 1]) + fabs(a[(hi - 1) * kSM + hi - 2]);
+      const double h11 = 0.75 * e + a[hi * kSM + hi], h12 = -0.4375 * e;
+      sh = 2.0 * h11;
+      tt = h11 * h11 - h12 * e;
+    } else {
+      const double p = a[(hi - 1) * kSM + hi - 1], q = a[(hi - 1) * kSM + hi];
+      const double r = a[hi * kSM + hi - 1], d = a[hi * kSM + hi];
+      sh = p + d;
+      tt = p * d - q * r;
+    }
+    const double h00 = a[l * kSM + l], h01 = a[l * kSM + l + 1], h10 = a[(l + 1) * kSM + l];
+    const double h11 = a[(l + 1) * kSM + l + 1], h21 = a[(l + 2) * kSM + l + 1];
+    double x = h00 * h00 + h01 * h10 - sh * h00 + tt;
+    double y = h10 * (h00 + h11 - sh);
+    double z = h10 * h21;
+    wave_sync();
+    for (int k = l; k <= hi - 1; ++k) {
+      const bool three = k < hi - 1;
+      const double zz = three ? z : 0.0;
+      const double nrm = sqrt(x * x + y * y + zz * zz);
+      if (nrm > 0.0 && (y != 0.0 || zz != 0.0)) {
+        const double alpha = -copysign(nrm, x);
+        const double u0 = x - alpha;
+        const double v1 = y / u0, v2 = zz / u0;
+        const double beta = -u0 / alpha;
+        const int q0 = max(l, k - 1);
+        for (int j = q0 + lane; j <= hi; j += 64) {
+          const double a0 = a[k * kSM + j], a1 = a[(k + 1) * kSM + j];
+          const double a2 = three ? a[(k + 2) * kSM + j] : 0.0;
+          const double d = beta * (a0 + v1 * a1 + v2 * a2);
+          a[k * kSM + j] = a0 - d;
+          a[(k + 1) * kSM + j] = a1 - d * v1;
+          if (three) a[(k + 2) * kSM + j] = a2 - d * v2;
+        }
+        wave_sync();
+        if (k > l && lane == 0) {
+          a[(k + 1) * kSM + k - 1] = 0.0;
+          if (three) a[(k + 2) * kSM + k - 1] = 0.0;
+        }
+        const int r = min(k + 3, hi);
+        for (int i = l + lane; i <= r; i += 64) {
+          const double a0 = a[i * kSM + k], a1 = a[i * kSM + k + 1];
+          const double a2 = three ? a[i * kSM + k + 2] : 0.0;
+          const double d = beta * (a0 + v1 * a1 + v2 * a2);
+          a[i * kSM + k] = a0 - d;
+          a[i * kSM + k + 1] = a1 - d * v1;
+          if (three) a[i * kSM + k + 2] = a2 - d * v2;
+        }
+        wave_sync();
+      }
+      if (k < hi - 1) {
+        x = a[(k + 1) * kSM + k];
+        y = a[(k + 2) * kSM + k];
+        z = (k < hi - 2) ? a[(k + 3) * kSM + k] : 0.0;
+      }
+      wave_sync();
+    }
+  }
+  return true;
+}
+
 }  // namespace
 
-// Eigenvalues of H_n by the Francis double-shift QR iteration (eigenvalues
-// only, so updates stay inside the active window [l, hi]); ad hoc shifts
-// after 10 iterations without deflation.  ev: (re[n], im[n]) per order at
+// 3-element Householder reflector (1, v1, v2) with scalar beta that maps
+// (x, y, z) to (alpha, 0, 0); beta = 0 when there is nothing to annihilate.
+// 1/||.|| and 1/u0 come from the hardware estimates refined by two Newton
+// steps each (r <- r (3 - s r^2) / 2 and q <- q (2 - u q)).
+SSI_DEV void householder3(double x, double y, double z, double &v1, double &v2, double &beta,
+                          double &alpha) {
+  const double s = x * x + y * y + z * z;
+  v1 = v2 = beta = alpha = 0.0;
+  if (!(s > 0.0) || (y == 0.0 && z == 0.0)) return;
+  double r = __builtin_amdgcn_rsq(s);
+  r = r * (1.5 - 0.5 * s * r * r);
+  r = r * (1.5 - 0.5 * s * r * r);
+  const double nrm = s * r;
+  alpha = -copysign(nrm, x);
+  const double u0 = x - alpha;                 // |u0| = |x| + ||.||
+  double q = __builtin_amdgcn_rcp(u0);
+  q = q * (2.0 - u0 * q);
+  q = q * (2.0 - u0 * q);
+  v1 = y * q;
+  v2 = z * q;
+  beta = 1.0 + fabs(x) * r;                    // -u0 / alpha
+}
+
+SSI_DEV double readlane_d(double v, int src) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), src);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), src);
+  return __hiloint2double(hi, lo);
+}
+
+template <int N>
+SSI_DEV double pick(const double (&v)[N], int u) {
+  double x = v[0];
+#pragma unroll
+  for (int q = 1; q < N; ++q) x = (u == q) ? v[q] : x;
+  return x;
+}
+
+// One sweep of nb bulges over the active window [l, hi] (nb = 1: one wave,
+// wave-level ordering only).  Wave b carries bulge b; shp holds the shift
+// pairs (s, t).
+template <bool kBlock>
+SSI_DEV void chase(double *A, const HIdx &ix, int l, int hi, int nb, const double *shp,
+                   int wave, int lane) {
+  const int psz = ix.b2;
+  const int stages = (hi - l) + 3 * (nb - 1);
+  // The column a bulge needs at its next step is the one its own right-hand
+  // update produced in this step (no other update touches it before the next
+  // reflector), so it is forwarded from the lanes that computed it.
+  bool have = false;
+  double nx = 0.0, ny = 0.0, nz = 0.0;
+  for (int st = 0; st < stages; ++st) {
+    const int k = l + st - 3 * wave;
+    const bool on = wave < nb && k >= l && k <= hi - 1;
+    const bool three = k < hi - 1;
+    double v1 = 0.0, v2 = 0.0, beta = 0.0, alpha = 0.0;
+    if (on) {
+      double x, y, z;
+      if (have) {
+        x = nx;
+        y = ny;
+        z = nz;
+      } else if (k == l) {
+        const double sh = shp[2 * wave], tt = shp[2 * wave + 1];
+        const double h00 = A[ix(l, l)], h01 = A[ix(l, l + 1)], h10 = A[ix(l + 1, l)];
+        const double h11 = A[ix(l + 1, l + 1)], h21 = A[ix(l + 2, l + 1)];
+        x = h00 * h00 + h01 * h10 - sh * h00 + tt;
+        y = h10 * (h00 + h11 - sh);
+        z = h10 * h21;
+      } else {
+        x = A[ix(k, k - 1)];
+        y = A[ix(k + 1, k - 1)];
+        z = three ? A[ix(k + 2, k - 1)] : 0.0;
+      }
+      householder3(x, y, three ? z : 0.0, v1, v2, beta, alpha);
+    }
+    const bool act = on && beta != 0.0;
+    have = false;
+    if (act) {
+      // rows k..k+2 over columns k..hi; entry (k+2, k) is a bulge slot
+      const int r0 = ix.base(k), r1 = ix.base(k + 1);
+      const int r2 = three ? ix.base(k + 2) : r1;
+      const int s2 = psz + ((k + 2) & (kRing - 1));
+      const int len = hi - k + 1;
+      int i0[kRowIt], i1[kRowIt], i2[kRowIt];
+      double a0[kRowIt], a1[kRowIt], a2[kRowIt];
+#pragma unroll
+      for (int u = 0; u < kRowIt; ++u) {
+        if (64 * u >= len) break;
+        const int j = k + min(lane + 64 * u, len - 1);
+        i0[u] = r0 + j;
+        i1[u] = r1 + j;
+        i2[u] = three ? (j == k ? s2 : r2 + j) : i1[u];
+        a0[u] = A[i0[u]];
+        a1[u] = A[i1[u]];
+        a2[u] = three ? A[i2[u]] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < kRowIt; ++u) {
+        if (64 * u >= len) break;
+        if (lane + 64 * u >= len) continue;
+        const double d = beta * (a0[u] + v1 * a1[u] + v2 * a2[u]);
+        A[i0[u]] = a0[u] - d;
+        A[i1[u]] = a1[u] - d * v1;
+        if (three) A[i2[u]] = a2[u] - d * v2;
+      }
+      if (k > l && lane == 0) {          // the reflected column k - 1
+        A[r0 + k - 1] = alpha;
+        A[psz + ((k + 1) & (kRing - 1))] = 0.0;
+        if (three) A[psz + kRing + ((k + 2) & (kRing - 1))] = 0.0;
+      }
+    }
+    if (kBlock) __syncthreads(); else wave_sync();
+    if (act) {
+      // columns k..k+2 over rows l..min(k+3, hi); entries (k+2, k),
+      // (k+3, k) and (k+3, k+1) are bulge slots
+      const int len = min(k + 3, hi) - l + 1;
+      const int sk2 = psz + ((k + 2) & (kRing - 1));
+      const int sk3 = psz + ((k + 3) & (kRing - 1));
+      int i0[kRowIt], i1[kRowIt], i2[kRowIt];
+      double a0[kRowIt], a1[kRowIt], a2[kRowIt], nv[kRowIt];
+#pragma unroll
+      for (int u = 0; u < kRowIt; ++u) {
+        nv[u] = 0.0;
+        if (64 * u >= len) break;
+        const int i = l + min(lane + 64 * u, len - 1);
+        const int bi = ix.base(i) + k;
+        i0[u] = i < k + 2 ? bi : (i == k + 2 ? sk2 : sk3 + kRing);
+        i1[u] = i < k + 3 ? bi + 1 : sk3;
+        i2[u] = three ? bi + 2 : i1[u];
+        a0[u] = A[i0[u]];
+        a1[u] = A[i1[u]];
+        a2[u] = three ? A[i2[u]] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < kRowIt; ++u) {
+        if (64 * u >= len) break;
+        if (lane + 64 * u >= len) continue;
+        const double d = beta * (a0[u] + v1 * a1[u] + v2 * a2[u]);
+        nv[u] = a0[u] - d;
+        A[i0[u]] = nv[u];
+        A[i1[u]] = a1[u] - d * v1;
+        if (three) A[i2[u]] = a2[u] - d * v2;
+      }
+      // next reflector input: column k, rows k+1, k+2 and (when the next
+      // step has three rows, i.e. k + 3 <= hi) k+3
+      const int e1 = k + 1 - l, e2 = k + 2 - l, e3 = k + 3 - l;
+      nx = readlane_d(pick(nv, e1 >> 6), e1 & 63);
+      ny = readlane_d(pick(nv, e2 >> 6), e2 & 63);
+      nz = (k + 3 <= hi) ? readlane_d(pick(nv, e3 >> 6), e3 & 63) : 0.0;
+      have = true;
+    }
+    if (kBlock) __syncthreads(); else wave_sync();
+  }
+}
+
+// Eigenvalues of H_n by the QR iteration (eigenvalues only, so updates stay
+// inside the active window [l, hi]).  ev: (re[n], im[n]) per order at
 // 2 vec(o).  Writes the number of eigenvalues with Im > 0 to npole[o] and
 // their indices to pidx at vec(o); flags[o] = 1 if the iteration limit hit.
 //
-// One workgroup of four waves per order.  Each bulge step is two phases
-// separated by barriers: the reflector (computed redundantly by every thread
-// from the column the previous step produced) is applied to rows k..k+2 over
-// columns k..hi, then to columns k..k+2 over rows l..k+3.  The reflected
-// column k-1 becomes (alpha, 0, 0) exactly; it is written in the column phase
-// so that no thread can overwrite it while another still reads it as the
-// reflector's input.
+// One workgroup of four waves per order.  Windows of kMsMin rows or more take
+// small-bulge multishift sweeps: the kSM eigenvalues of the trailing kSM x kSM
+// block (computed by one wave) give kNB shift pairs, one per bulge; the
+// bulges enter at the top three rows apart and are chased down together.
+// Smaller windows, and every eleventh sweep without deflation (ad hoc
+// shifts), use one double-shift bulge.  Wave b carries bulge b.  Each stage
+// of a sweep advances every bulge by one row in two phases separated by
+// barriers; bulges are three rows apart, so their reflectors touch disjoint
+// rows and columns and commute:
+//   rows      each wave computes its bulge's 3-element reflector (all lanes,
+//             redundantly) from the column its previous step left, or from
+//             its shift pair when it enters, then applies it from the left:
+//             rows k..k+2 over columns k..hi, and sets the reflected column
+//             k-1 to (alpha, 0, 0);
+//   columns   each wave applies its reflector from the right: columns
+//             k..k+2 over rows l..k+3.
+// The column k-1 a wave reads at the start of a stage is changed in that
+// stage only by its own row phase and by the right-hand update of the bulge
+// behind it, which runs after the barrier.
 template <bool LDS>
 __global__ void __launch_bounds__(kFT)
 francis_kernel(const double *__restrict__ hbuf, int nmin, int step, int o_first,
@@ -369,21 +663,26 @@ francis_kernel(const double *__restrict__ hbuf, int nmin, int step, int o_first,
                int *__restrict__ npole, int *__restrict__ pidx, int *__restrict__ flags) {
   extern __shared__ double lds_h[];
   __shared__ int red[kFT / 64];
+  __shared__ int small_ok;
   const int o = o_first + blockIdx.x;
   const OrderGeo geo = order_geo(o, nmin, step);
   const int n = geo.n;
   const double *Hin = hbuf + geo.sq;
   double *wr = evbuf + 2 * geo.vec, *wi = wr + n;
-  const int t = threadIdx.x;
+  const int t = threadIdx.x, lane = t & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(t >> 6);
   double *A = LDS ? lds_h : gscr + (size_t)blockIdx.x * gstride;
   const int psz = HIdx::packed_size(n);
-  const HIdx ix{n, psz, psz + 4};
+  const HIdx ix{n, psz, psz + kRing};
+  double *sev = A + psz + 2 * kRing;         // [2][kSM]
+  double *shp = sev + 2 * kSM;               // [kNB][2]: s, t of each shift pair
+  double *sblk = shp + 2 * kNB;              // [kSM][kSM]
   for (int i = 0; i < n; ++i) {
     const int j0 = i == 0 ? 0 : i - 1;
     const int rs = ix.row_start(i);
     for (int j = j0 + t; j < n; j += kFT) A[rs + j - j0] = Hin[(int64_t)i * n + j];
   }
-  if (t < 8) A[psz + t] = 0.0;
+  for (int i = t; i < 2 * kRing; i += kFT) A[psz + i] = 0.0;
   __syncthreads();
 
   const double eps = 2.220446049250313e-16;
@@ -432,78 +731,77 @@ francis_kernel(const double *__restrict__ hbuf, int nmin, int step, int o_first,
       break;
     }
     ++iter;
-    double s, tt;
-    if (iter % 11 == 10) {
-      const double e = fabs(A[ix(hi, hi - 1)]) + fabs(A[ix(hi - 1, hi - 2)]);
-      const double h11 = 0.75 * e + A[ix(hi, hi)], h12 = -0.4375 * e;
-      s = 2.0 * h11;
-      tt = h11 * h11 - h12 * e;
-    } else {
-      const double a = A[ix(hi - 1, hi - 1)], b = A[ix(hi - 1, hi)];
-      const double c = A[ix(hi, hi - 1)], d = A[ix(hi, hi)];
-      s = a + d;
-      tt = a * d - b * c;
+    // ---- shifts
+    int nb = 1;
+    if (hi - l + 1 >= kMsMin && iter % 11 != 10) {
+      const int m0 = hi - kSM + 1;
+      for (int idx = t; idx < kSM * kSM; idx += kFT) {
+        const int i = idx / kSM, j = idx - i * kSM;
+        sblk[idx] = (j >= i - 1) ? A[ix(m0 + i, m0 + j)] : 0.0;
+      }
+      __syncthreads();
+      if (wave == 0) {
+        const bool ok = small_eig(sblk, kSM, sev, sev + kSM, lane);
+        if (lane == 0) {
+          small_ok = ok ? 1 : 0;
+          if (ok) {
+            // complex conjugate pairs as they come, real shifts two by two
+            int b = 0, pend = -1;
+            for (int i = 0; i < kSM; ++i) {
+              const double re = sev[i], im = sev[kSM + i];
+              if (im > 0.0) {
+                shp[2 * b] = 2.0 * re;
+                shp[2 * b + 1] = re * re + im * im;
+                ++b;
+              } else if (im == 0.0) {
+                if (pend < 0) {
+                  pend = i;
+                } else {
+                  const double r0 = sev[pend];
+                  shp[2 * b] = r0 + re;
+                  shp[2 * b + 1] = r0 * re;
+                  ++b;
+                  pend = -1;
+                }
+              }
+            }
+            if (pend >= 0 && b < kNB) {      // cannot happen for an even kSM
+              shp[2 * b] = 2.0 * sev[pend];
+              shp[2 * b + 1] = sev[pend] * sev[pend];
+              ++b;
+            }
+            small_ok = (b == kNB) ? 1 : 0;
+          }
+        }
+      }
+      __syncthreads();
+      if (small_ok) nb = kNB;
     }
-    // first column of (H - s1 I)(H - s2 I) restricted to the window
-    const double h00 = A[ix(l, l)], h01 = A[ix(l, l + 1)], h10 = A[ix(l + 1, l)];
-    const double h11 = A[ix(l + 1, l + 1)], h21 = A[ix(l + 2, l + 1)];
-    double x = h00 * h00 + h01 * h10 - s * h00 + tt;
-    double y = h10 * (h00 + h11 - s);
-    double z = h10 * h21;
-    __syncthreads();                      // all reads above precede the first update
-    for (int k = l; k <= hi - 1; ++k) {
-      const bool three = k < hi - 1;
-      const double zz = three ? z : 0.0;
-      const double nrm = sqrt(x * x + y * y + zz * zz);
-      const bool act = nrm > 0.0 && (y != 0.0 || zz != 0.0);
-      double alpha = 0.0, v1 = 0.0, v2 = 0.0, beta = 0.0;
-      if (act) {
-        alpha = -copysign(nrm, x);
-        const double u0 = x - alpha;
-        v1 = y / u0;
-        v2 = zz / u0;
-        beta = -u0 / alpha;
-        // rows k..k+2, columns k..hi; entry (k+2, k) is a bulge slot
-        const int r0 = ix.row_start(k) - (k > 0 ? k - 1 : 0);
-        const int r1 = ix.row_start(k + 1) - k;
-        const int r2 = three ? ix.row_start(k + 2) - (k + 1) : r1;
-        const int b2 = psz + ((k + 2) & 3);
-        for (int j = k + t; j <= hi; j += kFT) {
-          const int i0 = r0 + j, i1 = r1 + j;
-          const int i2 = three ? (j == k ? b2 : r2 + j) : i1;
-          const double a0 = A[i0], a1 = A[i1];
-          const double a2 = three ? A[i2] : 0.0;
-          const double d = beta * (a0 + v1 * a1 + v2 * a2);
-          A[i0] = a0 - d;
-          A[i1] = a1 - d * v1;
-          if (three) A[i2] = a2 - d * v2;
-        }
+    if (nb == 1 && t == 0) {
+      double sh, tt;
+      if (iter % 11 == 10) {
+        const double e = fabs(A[ix(hi, hi - 1)]) + fabs(A[ix(hi - 1, hi - 2)]);
+        const double h11 = 0.75 * e + A[ix(hi, hi)], h12 = -0.4375 * e;
+        sh = 2.0 * h11;
+        tt = h11 * h11 - h12 * e;
+      } else {
+        const double a = A[ix(hi - 1, hi - 1)], b = A[ix(hi - 1, hi)];
+        const double c = A[ix(hi, hi - 1)], d = A[ix(hi, hi)];
+        sh = a + d;
+        tt = a * d - b * c;
       }
+      shp[0] = sh;
+      shp[1] = tt;
+    }
+    __syncthreads();
+
+    // ---- sweep: nb bulges, bulge b (wave b) enters at stage 3 b; a single
+    // bulge needs no block barriers
+    if (nb > 1) {
+      chase<true>(A, ix, l, hi, nb, shp, wave, lane);
+    } else {
+      if (wave == 0) chase<false>(A, ix, l, hi, 1, shp, 0, lane);
       __syncthreads();
-      if (act) {
-        if (k > l && t == 0) {           // the reflected column k - 1
-          A[ix(k, k - 1)] = alpha;
-          A[ix(k + 1, k - 1)] = 0.0;
-          if (three) A[ix(k + 2, k - 1)] = 0.0;
-        }
-        // columns k..k+2, rows l..min(k+3, hi)
-        const int r = min(k + 3, hi);
-        for (int i = l + t; i <= r; i += kFT) {
-          const int i0 = ix(i, k), i1 = ix(i, k + 1), i2 = three ? ix(i, k + 2) : i1;
-          const double a0 = A[i0], a1 = A[i1];
-          const double a2 = three ? A[i2] : 0.0;
-          const double d = beta * (a0 + v1 * a1 + v2 * a2);
-          A[i0] = a0 - d;
-          A[i1] = a1 - d * v1;
-          if (three) A[i2] = a2 - d * v2;
-        }
-      }
-      __syncthreads();
-      if (k < hi - 1) {
-        x = A[ix(k + 1, k)];
-        y = A[ix(k + 2, k)];
-        z = (k < hi - 2) ? A[ix(k + 3, k)] : 0.0;
-      }
     }
   }
   __syncthreads();
@@ -781,7 +1079,7 @@ ModalSizes modal_sizes(int nmin, int nmax, int step, int l) {
   s.ch = (int64_t)l * s.vec;
   s.vec_waves = 1024;
   s.vec_stride = 2 * ((int64_t)kNR * (kNR + 1) / 2 + 64);
-  s.francis_glb = (int64_t)HIdx::packed_size(kNR) + 8;
+  s.francis_glb = (int64_t)HIdx::packed_size(kNR) + kExtra;
   return s;
 }
 
@@ -799,7 +1097,7 @@ hipError_t launch_modal(const ModalArgs &a, hipStream_t st) {
   // orders with n <= 200 keep H in LDS; larger ones use global scratch
   int n_lds = 0;
   for (int o = 0; o < no; ++o)
-    if (a.nmin + o * a.step <= 200) n_lds = o + 1;
+    if (a.nmin + o * a.step <= kLdsMaxN) n_lds = o + 1;
   if (n_lds > 0) {
     hipError_t e = hipFuncSetAttribute((const void *)francis_kernel<true>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize,
