@@ -16,19 +16,41 @@
 
 namespace {
 
-constexpr int kWaves = 4;            // waves per workgroup
+constexpr int kThreads = 512;        // 8 waves: 4 row blocks x 2 column halves
 constexpr int kRowsPerWave = 64;     // 4 MFMA row tiles of 16
-constexpr int kRowsPerWG = kWaves * kRowsPerWave;
-constexpr int kColsPerWG = 64;       // 4 MFMA column tiles of 16, shared by waves
+constexpr int kColsPerWave = 32;     // 2 MFMA column tiles of 16
+constexpr int kRowsPerWG = 4 * kRowsPerWave;
+constexpr int kColsPerWG = 2 * kColsPerWave;
 constexpr int kST = 128;             // samples per LDS tile
-constexpr int kSB = kST + 2;         // LDS row stride of the B tile (floats)
+constexpr int kSB = kST + 4;         // LDS row stride of the B tile (floats): rows stay
+                                     // 16-byte aligned and the 16 rows a fragment
+                                     // read touches start in distinct banks
 constexpr int kFlushTiles = 2;       // fold fp32 into fp64 every 256 samples
+
+// Four consecutive samples s..s+3 of one channel row p, zero at and past lim.
+template <bool VEC>
+SSI_DEV float4 load4(const float *__restrict__ p, int64_t s, int64_t lim) {
+  if (VEC && s + 3 < lim) return *reinterpret_cast<const float4 *>(p + s);
+  float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+  if (s < lim) v.x = p[s];
+  if (s + 1 < lim) v.y = p[s + 1];
+  if (s + 2 < lim) v.z = p[s + 2];
+  if (s + 3 < lim) v.w = p[s + 3];
+  return v;
+}
+
+SSI_DEV float4 zero4() { return make_float4(0.f, 0.f, 0.f, 0.f); }
 
 }  // namespace
 
 // One workgroup: rows [r0, r0 + 256) x columns [c0, c0 + 64) over samples
-// [s_begin, s_end).  Writes fp64 partial sums partial[split][r][b].
-__global__ void __launch_bounds__(256, 2)
+// [s_begin, s_end); wave w owns rows 64 (w % 4).. and columns 32 (w / 4)...
+// Tiles are loaded with 16-byte loads (VEC: ldy % 4 == 0 and y 16-byte
+// aligned), all issued before the first is written to LDS; tiles that lie
+// inside the split (B) or the record (A window) skip the per-sample guards.
+// Writes fp64 partial sums partial[split][r][b].
+template <bool VEC>
+__global__ void __launch_bounds__(kThreads, 2)
 correlate_mfma(const float *__restrict__ y, int l, int64_t n, int64_t ldy, int L,
                int64_t split_len, double *__restrict__ partial, int sa_stride,
                int na_max) {
@@ -46,70 +68,87 @@ correlate_mfma(const float *__restrict__ y, int l, int64_t n, int64_t ldy, int L
 
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
+  const int wr = wave & 3, wc = wave >> 2;
   const int a_first = r0 / L;
   const int a_last = min(l - 1, (min(r0 + kRowsPerWG, rows_total) - 1) / L);
   const int na = a_last - a_first + 1;     // <= na_max by construction
-  const int wa = kST + L;                  // A window length per channel
+  const int wa4 = (kST + L + 3) / 4;       // A window length per channel (float4)
+  const int na4 = na * wa4;
 
-  // Per-lane LDS offsets of the A rows (4 row tiles) and B columns (4 tiles).
+  // Per-lane LDS offsets of the A rows (4 row tiles) and B columns (2 tiles).
   int offA[4];
-  bool rowok[4];
 #pragma unroll
   for (int t = 0; t < 4; ++t) {
-    const int r = r0 + wave * kRowsPerWave + t * 16 + (lane & 15);
-    rowok[t] = r < rows_total;
-    const int rr = rowok[t] ? r : r0;
-    const int a = rr / L, j = rr - a * L + 1;
+    const int r = min(r0 + wr * kRowsPerWave + t * 16 + (lane & 15), rows_total - 1);
+    const int a = r / L, j = r - a * L + 1;
     offA[t] = (a - a_first) * sa_stride + j + (lane >> 4);
   }
-  int offB[4];
+  int offB[2];
 #pragma unroll
-  for (int u = 0; u < 4; ++u) offB[u] = (u * 16 + (lane & 15)) * kSB + (lane >> 4);
+  for (int u = 0; u < 2; ++u)
+    offB[u] = (wc * kColsPerWave + u * 16 + (lane & 15)) * kSB + (lane >> 4);
 
-  f32x4 acc[4][4];
-  double accd[4][4][4];
+  f32x4 acc[4][2];
+  double accd[4][2][4];
 #pragma unroll
   for (int t = 0; t < 4; ++t)
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
+    for (int u = 0; u < 2; ++u) {
       acc[t][u] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
       for (int q = 0; q < 4; ++q) accd[t][u][q] = 0.0;
     }
 
+  // this thread's B elements: rows bb = tid / 32 + 16 h, float4 column tid % 32
+  const int bb0 = tid >> 5, bc4 = tid & 31;
   int tile_count = 0;
   for (int64_t s0 = s_begin; s0 < s_end; s0 += kST) {
-    __syncthreads();
-    // B tile: y[c0 + bb][s0 + t] for s in the split, zero elsewhere.
-    for (int idx = tid; idx < kColsPerWG * kST; idx += 256) {
-      const int bb = idx / kST, t = idx - bb * kST;
-      const int b = c0 + bb;
-      const int64_t s = s0 + t;
-      float v = 0.f;
-      if (b < l && s < s_end) v = y[(int64_t)b * ldy + s];
-      yb[bb * kSB + t] = v;
+    // B tile: y[c0 + bb][s0 + t] for s in the split, zero elsewhere
+    float4 rb[4];
+    const bool full_b = s0 + kST <= s_end;
+#pragma unroll
+    for (int h = 0; h < 4; ++h) {
+      const int b = c0 + bb0 + 16 * h;
+      const float *row = y + (int64_t)min(b, l - 1) * ldy;
+      float4 v;
+      if (VEC && full_b) v = *reinterpret_cast<const float4 *>(row + s0 + 4 * bc4);
+      else v = load4<VEC>(row, s0 + 4 * bc4, s_end);
+      rb[h] = b < l ? v : zero4();
     }
-    // A window: y[a][s0 + t] for t < kST + L, zero past the record.
-    for (int idx = tid; idx < na * wa; idx += 256) {
-      const int i = idx / wa, t = idx - i * wa;
-      const int64_t s = s0 + t;
-      float v = 0.f;
-      if (s < n) v = y[(int64_t)(a_first + i) * ldy + s];
-      ya[i * sa_stride + t] = v;
+    // A window: y[a][s0 + t] for t < kST + L, zero past the record
+    float4 ra;
+    int ia = 0, ca = 0;
+    const bool full_a = s0 + 4 * wa4 <= n;
+    if (tid < na4) {
+      ia = tid / wa4;
+      ca = tid - ia * wa4;
+      const float *row = y + (int64_t)(a_first + ia) * ldy;
+      if (VEC && full_a) ra = *reinterpret_cast<const float4 *>(row + s0 + 4 * ca);
+      else ra = load4<VEC>(row, s0 + 4 * ca, n);
+    }
+    __syncthreads();                       // previous tile's reads are done
+#pragma unroll
+    for (int h = 0; h < 4; ++h)
+      *reinterpret_cast<float4 *>(&yb[(bb0 + 16 * h) * kSB + 4 * bc4]) = rb[h];
+    if (tid < na4) *reinterpret_cast<float4 *>(&ya[ia * sa_stride + 4 * ca]) = ra;
+    for (int idx = tid + kThreads; idx < na4; idx += kThreads) {   // wide windows (small L)
+      const int i = idx / wa4, c4 = idx - i * wa4;
+      *reinterpret_cast<float4 *>(&ya[i * sa_stride + 4 * c4]) =
+          load4<VEC>(y + (int64_t)(a_first + i) * ldy, s0 + 4 * c4, n);
     }
     __syncthreads();
 
 #pragma unroll 4
     for (int kk = 0; kk < kST; kk += 4) {
-      float af[4], bf[4];
+      float af[4], bf[2];
 #pragma unroll
       for (int t = 0; t < 4; ++t) af[t] = ya[offA[t] + kk];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) bf[u] = yb[offB[u] + kk];
+      for (int u = 0; u < 2; ++u) bf[u] = yb[offB[u] + kk];
 #pragma unroll
       for (int t = 0; t < 4; ++t)
 #pragma unroll
-        for (int u = 0; u < 4; ++u)
+        for (int u = 0; u < 2; ++u)
           acc[t][u] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[t], bf[u], acc[t][u], 0, 0, 0);
     }
 
@@ -118,7 +157,7 @@ correlate_mfma(const float *__restrict__ y, int l, int64_t n, int64_t ldy, int L
 #pragma unroll
       for (int t = 0; t < 4; ++t)
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
+        for (int u = 0; u < 2; ++u) {
 #pragma unroll
           for (int q = 0; q < 4; ++q) accd[t][u][q] += (double)acc[t][u][q];
           acc[t][u] = f32x4{0.f, 0.f, 0.f, 0.f};
@@ -131,16 +170,15 @@ correlate_mfma(const float *__restrict__ y, int l, int64_t n, int64_t ldy, int L
 #pragma unroll
   for (int t = 0; t < 4; ++t) {
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int b = c0 + u * 16 + (lane & 15);
+    for (int u = 0; u < 2; ++u) {
+      const int b = c0 + wc * kColsPerWave + u * 16 + (lane & 15);
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        const int r = r0 + wave * kRowsPerWave + t * 16 + 4 * (lane >> 4) + q;
+        const int r = r0 + wr * kRowsPerWave + t * 16 + 4 * (lane >> 4) + q;
         if (r < rows_total && b < l) dst[(int64_t)r * l + b] = accd[t][u][q];
       }
     }
   }
-  (void)rowok;
   (void)na_max;
 }
 
@@ -186,8 +224,9 @@ CorrPlan plan_correlate(int l, int64_t n, int L, int num_cus) {
   // A window rows: channels spanned by 256 flattened rows.
   p.na_max = kRowsPerWG / L + 2;
   if (p.na_max > l) p.na_max = l;
-  p.sa_stride = kST + L + 2;
-  if ((p.sa_stride & 31) == 0) p.sa_stride += 2;
+  // A window row stride: whole float4s, not a multiple of 32 floats
+  p.sa_stride = (kST + L + 3) / 4 * 4;
+  if ((p.sa_stride & 31) == 0) p.sa_stride += 4;
   p.lds_bytes = sizeof(float) * ((size_t)kColsPerWG * kSB + (size_t)p.na_max * p.sa_stride);
   p.partial_elems = (size_t)p.splits * rows_total * l;
   return p;
@@ -196,14 +235,19 @@ CorrPlan plan_correlate(int l, int64_t n, int L, int num_cus) {
 hipError_t launch_correlate_mfma(const CorrPlan &p, const float *y, int l, int64_t n, int64_t ldy,
                                  int L, double *partial, hipStream_t st) {
   dim3 grid(p.grid_rows, p.grid_cols, p.splits);
+  const bool vec = (ldy % 4 == 0) && ((uintptr_t)y % 16 == 0);
+  const void *fn = vec ? (const void *)correlate_mfma<true> : (const void *)correlate_mfma<false>;
   if (p.lds_bytes > 65536) {
-    hipError_t e = hipFuncSetAttribute((const void *)correlate_mfma,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize,
+    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize,
                                        (int)p.lds_bytes);
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL(correlate_mfma, grid, dim3(256), p.lds_bytes, st, y, l, n, ldy, L,
-                     p.split_len, partial, p.sa_stride, p.na_max);
+  if (vec)
+    hipLaunchKernelGGL(correlate_mfma<true>, grid, dim3(kThreads), p.lds_bytes, st, y, l, n,
+                       ldy, L, p.split_len, partial, p.sa_stride, p.na_max);
+  else
+    hipLaunchKernelGGL(correlate_mfma<false>, grid, dim3(kThreads), p.lds_bytes, st, y, l, n,
+                       ldy, L, p.split_len, partial, p.sa_stride, p.na_max);
   return hipGetLastError();
 }
 
