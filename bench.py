@@ -16,8 +16,10 @@ CPU checker timed on the host for one identification of the same record.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -27,6 +29,37 @@ sys.path.insert(0, ROOT)
 WORKLOAD = "bridge-180ch"
 FP32_MFMA_PEAK_TFLOPS = 157.3       # MI355X dense FP32 matrix peak
 HBM_PEAK_GBS = 8000.0
+COPY_PROBE_BYTES = 256 << 20        # plain device copy used to calibrate HBM byte counters
+PMC_SUMMARY = os.path.join(ROOT, "profiles", "correlate_mfma_bridge180_pmc.md")
+KERNEL_SOURCE = os.path.join(ROOT, "paper_2411_05510_amd", "csrc", "correlate.hip")
+
+
+def measured_traffic():
+    """HBM bytes per correlate_mfma launch from the committed counter summary,
+    or None when the summary is missing or the kernel source has changed since
+    the counters were taken."""
+    try:
+        text = open(PMC_SUMMARY).read()
+        src = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
+    except OSError:
+        return None
+    m_hash = re.search(r"source_sha256:\s*([0-9a-f]{64})", text)
+    m_val = re.search(r"traffic_bytes_per_launch:\s*([0-9.eE+]+)", text)
+    if not m_hash or not m_val or m_hash.group(1) != src:
+        return None
+    return float(m_val.group(1))
+
+
+def blas_threads() -> int:
+    """Threads the host BLAS pools actually use (what the checker runs on)."""
+    try:
+        from threadpoolctl import threadpool_info
+        n = max((p.get("num_threads", 0) for p in threadpool_info()), default=0)
+        if n:
+            return int(n)
+    except Exception:
+        pass
+    return int(os.environ.get("OMP_NUM_THREADS", "0")) or (os.cpu_count() or 1)
 
 
 def corr_flops(l: int, n: int, L: int) -> float:
@@ -40,6 +73,8 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="run one plain device copy of 256 MiB first (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
@@ -63,6 +98,13 @@ def main() -> int:
     ctx = ssicov.Context(0)
     out = ctx.alloc_output(p, wl.l, wl.n)
     stream = torch.cuda.current_stream(dev)
+    if args.copy_probe:
+        src = torch.ones(COPY_PROBE_BYTES // 4, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     for _ in range(args.warmup):
         ctx.identify(yd, p, out)
@@ -107,8 +149,7 @@ def main() -> int:
                         oversample=wl.oversample, power_iters=wl.power_iters,
                         seed=wl.sketch_seed)
         cpu_s = time.perf_counter() - t1
-        threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count()
-        cpu = {"value": 1.0 / cpu_s, "unit": "identifications/s", "cores": threads,
+        cpu = {"value": 1.0 / cpu_s, "unit": "identifications/s", "cores": blas_threads(),
                "kind": "oracle",
                "sample": f"one full identification of the same {WORKLOAD} record "
                          f"(FP64 numpy checker, {cpu_s:.1f} s)"}
@@ -145,7 +186,7 @@ def main() -> int:
             "peak": FP32_MFMA_PEAK_TFLOPS,
             "unit": "TFLOP/s",
             "frac": achieved / FP32_MFMA_PEAK_TFLOPS,
-            "traffic": None,
+            "traffic": measured_traffic(),
             "avg_kernel_ms": corr_avg_ms,
             "algorithmic_flops_per_launch": flops,
         },

@@ -47,13 +47,28 @@ typedef enum ssi_status {
   SSI_ENOMEM = 2,     /* device workspace could not be allocated            */
   SSI_EDEVICE = 3,    /* HIP runtime error or no usable gfx950 device       */
   SSI_ENOCONV = 4,    /* an iterative kernel hit its iteration limit        */
-  SSI_EINTERNAL = 5
+  SSI_EINTERNAL = 5,
+  SSI_EBUSY = 6       /* serving: the request has not finished yet          */
 } ssi_status;
 
 typedef enum ssi_svd_mode {
   SSI_SVD_FULL = 0,        /* exact SVD of T (Eq. (8)); for small T          */
   SSI_SVD_RANDOMIZED = 1   /* randomized SVD (Algorithm 1, Eq. (13)-(18))   */
 } ssi_svd_mode;
+
+/* Arithmetic of the range-finder products of the randomized SVD (the sketch
+ * Y = T Omega and the power-iteration products).  The projection P = Q^T T,
+ * every orthonormalization, the small SVD, the shift least squares and the
+ * eigen-analysis are FP64 in both modes. */
+typedef enum ssi_precision {
+  SSI_PREC_FP32 = 0,   /* T as stored (FP32) times FP64 X, FP64 MFMA accumulation */
+  SSI_PREC_BF16 = 1,   /* T and X rounded to BF16 (nearest even), FP32 MFMA
+                          accumulation, FP64 sum of the K slices                   */
+  SSI_PREC_BF16X3 = 2  /* T and X split into BF16 hi + lo parts (lo = BF16 of the
+                          remainder), three BF16 MFMA products hi hi + hi lo +
+                          lo hi with FP32 accumulation: about 16 significant bits
+                          per operand                                              */
+} ssi_precision;
 
 /* Identification parameters (Section 2.1 and 2.3 control parameters). */
 typedef struct ssi_params {
@@ -70,6 +85,9 @@ typedef struct ssi_params {
   int32_t oversample;         /* randomized: p >= 0; sketch width ell = k + p <= m  */
   int32_t power_iters;        /* randomized: q >= 0                                 */
   uint64_t seed;              /* Gaussian sketch seed (Philox-4x32-10 key)          */
+  int32_t prec;               /* ssi_precision of the range-finder products;
+                                 other than SSI_PREC_FP32 needs
+                                 svd = SSI_SVD_RANDOMIZED                          */
 } ssi_params;
 
 /* Sizes of the device output buffers of ssi_identify, from ssi_output_layout. */
@@ -136,6 +154,38 @@ enum {
 ssi_status ssi_set_profiling(ssi_ctx *ctx, int enable);
 ssi_status ssi_profile_read(ssi_ctx *ctx, double *ms, int32_t *calls, int32_t n_stages);
 
+/* Lag sweep of the 3D stabilization diagram (Section 2.3, step i) over n
+ * streams (1 <= n <= 4, default 1).  With n > 1, ssi_identify computes the
+ * correlations once on the context stream, then runs lag i (Toeplitz, SVD and
+ * modal stage) on internal stream i % n, each with its own buffers, and makes
+ * the context stream wait for all of them before later work: results are
+ * identical to n = 1; lags of different streams overlap on the device.  The
+ * internal streams are created here (default priority, non-blocking).
+ * Synchronizes the context stream. */
+ssi_status ssi_set_lag_streams(ssi_ctx *ctx, int32_t n);
+/* Graph mode for ssi_identify (default off).  When on, every ssi_identify
+ * call is keyed by all its arguments (pointers, sizes, parameters, lag
+ * streams).  The first call with a key runs eagerly, waits for completion,
+ * and captures the whole identification - all lags and orders - into one HIP
+ * graph; later calls with the same key launch that graph on the context
+ * stream.  Graphs are dropped when the workspace grows, the lag-stream count
+ * changes or graph mode is turned off.  Stage profiling is not recorded for
+ * graph launches.  The output buffers and y must stay allocated while a
+ * graph that names them may be launched. */
+ssi_status ssi_set_graphs(ssi_ctx *ctx, int enable);
+/* Autotuning of the range-finder products (default off).  When on, the
+ * first product of each (precision, orientation, M, N, K) times candidate
+ * K-slice counts {2, 4, 6, 8, 12, 16} with HIP events on the context stream
+ * (each candidate computes the full product, so results are unaffected) and
+ * keeps the fastest for the life of the context.  Tuning synchronizes the
+ * stream once per new shape and never runs inside a graph capture. */
+ssi_status ssi_set_autotune(ssi_ctx *ctx, int enable);
+/* K-slice count chosen by the autotuner for a product, 0 if not tuned.
+ * kind: 0 = FP32 x FP64 product, 1 = BF16 product, 3 = split BF16 product;
+ * trans: 1 for T^T X. */
+int32_t ssi_tuned_splits(const ssi_ctx *ctx, int32_t kind, int32_t trans, int32_t m,
+                         int32_t n, int32_t k);
+
 /* ----------------------------------------------- host-only helpers (no GPU) */
 
 /* Check parameters against l channels and n samples: 2 <= j_b, 2 j_b - 1 < n,
@@ -196,14 +246,17 @@ ssi_status ssi_sketch(ssi_ctx *ctx, uint64_t seed, uint32_t stream, int64_t m,
 
 /* Randomized SVD of the m x m matrix T (Algorithm 1, Eq. (13)-(18)):
  * Y = T Omega; Q = orth(Y); q times: Q = orth(T^T Q), Q = orth(T Q);
- * P = Q^T T; P = U~ S V^T; U = Q U~.  Products on FP32 MFMA; orthonormal
- * bases, the small SVD and U in FP64.
+ * P = Q^T T; P = U~ S V^T; U = Q U~.  The range-finder products follow
+ * `prec` (ssi_precision); the projection multiplies FP32 T by FP64 Q with
+ * FP64 MFMA accumulation; orthonormal bases (shifted CholeskyQR), the small
+ * SVD and U are FP64.
  * t: device m x ldt floats.  omega: device m x (k+p) floats (ld k+p), or NULL
  * to draw it with ssi_sketch(seed, stream).  u: device m x k doubles
  * (row-major, ld k).  sigma: device k doubles, descending. */
 ssi_status ssi_rsvd(ssi_ctx *ctx, const float *t, int64_t m, int64_t ldt,
-                    int32_t k, int32_t p, int32_t q, const float *omega,
-                    uint64_t seed, uint32_t stream, double *u, double *sigma);
+                    int32_t k, int32_t p, int32_t q, int32_t prec,
+                    const float *omega, uint64_t seed, uint32_t stream, double *u,
+                    double *sigma);
 
 /* Exact SVD of the m x m matrix T (Eq. (8)): leading k left singular vectors
  * u (device m x k doubles) and singular values sigma (device, k doubles),
@@ -221,6 +274,119 @@ ssi_status ssi_svd_full(ssi_ctx *ctx, const float *t, int64_t m, int64_t ldt,
 ssi_status ssi_modal(ssi_ctx *ctx, const double *u, const double *sigma,
                      int64_t m, int32_t k, int32_t l, const ssi_params *p,
                      int32_t lag_index, const ssi_output *out);
+
+/* ------------------------------------------------- stability analysis */
+
+/* Thresholds of the hard criteria (Section 2.1 end) and of the soft
+ * criteria of the 3D stabilization diagram (Eq. (19)).  The paper's 3D
+ * analysis of the frame uses xi_max 0.10, mpc_min 0.60, mpd_max 0.50,
+ * alpha_f 0.01, alpha_xi 0.03, alpha_mac 0.02. */
+typedef struct ssi_stability_params {
+  double xi_max;      /* keep 0 < xi <= xi_max                                  */
+  double mpc_min;     /* keep MPC > mpc_min                                     */
+  double mpd_max;     /* keep MPD < mpd_max (MPD normalized to [0, 1])          */
+  double alpha_f;     /* |f_i - f_j| / max(f_i, f_j) <= alpha_f                 */
+  double alpha_xi;    /* |xi_i - xi_j| / max(xi_i, xi_j) <= alpha_xi            */
+  double alpha_mac;   /* 1 - MAC(phi_i, phi_j) <= alpha_mac                      */
+} ssi_stability_params;
+
+enum {
+  SSI_POLE_HC = 1,          /* passes the hard criteria                         */
+  SSI_POLE_STABLE_ORDER = 2,/* matches a pole of the previous order, same lag   */
+  SSI_POLE_STABLE_LAG = 4,  /* matches a pole of the previous lag, same order   */
+  SSI_POLE_STABLE = 8       /* hard criteria and (order or lag match), Eq. (19) */
+};
+
+/* Stability of every pole of an identification (device buffers `out` of
+ * ssi_identify with the same p and l).  Per pole slot [lag][pole_cap]:
+ *   mpc: modal phase collinearity ((Sxx - Syy)^2 + 4 Sxy^2) / (Sxx + Syy)^2
+ *        with Sxx = |Re phi|^2, Syy = |Im phi|^2, Sxy = Re phi . Im phi;
+ *   mpd: mean phase deviation: the |phi_a|-weighted mean angle between the
+ *        components phi_a and the principal line of the points
+ *        (Re phi_a, Im phi_a), over pi/2;
+ *   flags: SSI_POLE_* bits.  A pole matches a neighbour (previous order of
+ *        the same lag, or same order of the previous lag) when that
+ *        neighbour passes the hard criteria and all three soft thresholds
+ *        hold for the pair.  Empty slots get 0.
+ * mpc, mpd: device doubles, flags: device bytes, each n_lags * pole_cap.
+ * FP64 throughout (mode shapes widened from FP32).  Stream-ordered. */
+ssi_status ssi_stability(ssi_ctx *ctx, const ssi_params *p, int32_t l,
+                         const ssi_output *out, const ssi_stability_params *sp,
+                         double *mpc, double *mpd, uint8_t *flags);
+
+/* ------------------------------------------------------------- serving */
+
+/* Continuous batching of identifications on one GPU, for monitoring many
+ * structures at once (one request = one window of one record).  Requests
+ * are queued by ssi_server_submit and admitted, in arrival order with
+ * skip-ahead past a request that does not fit, to free slots while the device
+ * memory the slots hold stays within the budget.  Each slot owns a context on
+ * its own non-blocking stream and device buffers that grow on demand and are
+ * kept; slots run concurrently, so work of different requests overlaps on the
+ * device.  A request's result does not depend on what else runs (every
+ * kernel is deterministic and the work of a request stays on its slot).
+ * All functions are thread-safe. */
+typedef struct ssi_server ssi_server;
+
+typedef struct ssi_server_config {
+  int32_t device;          /* HIP device                                        */
+  int32_t max_inflight;    /* slots: requests on the GPU at once, 1..64         */
+  size_t hbm_budget;       /* bytes the slots may hold in total; 0 = 80 % of the
+                              free device memory at creation                     */
+} ssi_server_config;
+
+/* Timestamps in microseconds since the server was created (-1: not yet). */
+typedef struct ssi_request_info {
+  ssi_status status;       /* of the identification, once finished             */
+  int32_t slot;            /* slot that ran it, -1 while queued                 */
+  double t_submit_us, t_start_us, t_done_us;
+  size_t footprint;        /* bytes charged at admission (ssi_footprint)        */
+} ssi_request_info;
+
+/* Host copies of one request's outputs, in the ssi_output layout of
+ * `layout`.  Owned by the server until ssi_server_release. */
+typedef struct ssi_host_result {
+  ssi_layout layout;
+  const double *sigma;
+  const int32_t *count;
+  const double *f, *xi, *mu;
+  const float *phi;
+  const int32_t *flags;
+} ssi_host_result;
+
+typedef struct ssi_server_stats {
+  uint64_t submitted, completed, failed;
+  int32_t queued, running;
+  int32_t peak_inflight;   /* most requests running at once                     */
+  uint64_t peak_bytes;     /* most device bytes held or reserved by the slots   */
+  uint64_t held_bytes;     /* bytes held now                                    */
+  uint64_t budget;
+} ssi_server_stats;
+
+/* Device bytes one identification of these sizes holds: the context
+ * workspace (with its growth margin), y and the output buffers.  Host-only. */
+ssi_status ssi_footprint(const ssi_params *p, int32_t l, int64_t n, size_t *bytes);
+ssi_status ssi_server_create(const ssi_server_config *cfg, ssi_server **out);
+/* Waits for every submitted request to finish, then frees all slots. */
+void ssi_server_destroy(ssi_server *srv);
+/* Queue one identification.  y: host pointer, l x n floats, channel-major
+ * (ld ldy); copied before returning, as are the parameters (lags included).
+ * Returns at once with a ticket.  SSI_EINVAL for invalid parameters (as
+ * ssi_validate), SSI_ENOMEM if the request alone exceeds the budget. */
+ssi_status ssi_server_submit(ssi_server *srv, const float *y, int32_t l, int64_t n,
+                             int64_t ldy, const ssi_params *p, uint64_t *ticket);
+/* SSI_EBUSY while queued or running, SSI_OK once finished (the request's own
+ * status is info->status).  info may be NULL. */
+ssi_status ssi_server_poll(ssi_server *srv, uint64_t ticket, ssi_request_info *info);
+/* Blocks until the request has finished. */
+ssi_status ssi_server_wait(ssi_server *srv, uint64_t ticket, ssi_request_info *info);
+/* Host result of a finished request; its status if it failed. */
+ssi_status ssi_server_result(ssi_server *srv, uint64_t ticket, const ssi_host_result **res);
+/* Forget a finished request and free its host result. */
+ssi_status ssi_server_release(ssi_server *srv, uint64_t ticket);
+ssi_status ssi_server_get_stats(ssi_server *srv, ssi_server_stats *out);
+/* Thread-local message for the last failed server call. */
+const char *ssi_server_last_error(void);
 
 #ifdef __cplusplus
 }

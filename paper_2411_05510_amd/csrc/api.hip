@@ -10,7 +10,9 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "kernels.h"
@@ -43,9 +45,12 @@ ssi_status hip_fail(hipError_t e, const char *where) {
 }  // namespace
 
 // ------------------------------------------------------------------ context
+constexpr int kMaxLanes = 4;      // concurrent lag streams of one identification
+
 struct ssi_ctx {
   int device = 0;
-  hipStream_t stream = nullptr;   // caller's stream; nullptr = default stream
+  hipStream_t stream = nullptr;   // stream work is enqueued on right now
+  hipStream_t user_stream = nullptr;   // caller's stream; nullptr = default stream
   int num_cus = 256;
   int *status = nullptr;     // device word: kernels OR in failure bits
   char *ws = nullptr;        // workspace arena
@@ -58,6 +63,23 @@ struct ssi_ctx {
   std::vector<Rec> recs;
   double acc_ms[SSI_STAGE_COUNT] = {};
   int32_t acc_calls[SSI_STAGE_COUNT] = {};
+  // lag sweep over several streams (fork / join through events)
+  int n_lanes = 1;
+  hipStream_t lanes[kMaxLanes] = {};
+  hipEvent_t fork_ev = nullptr;
+  hipEvent_t join_ev[kMaxLanes] = {};
+  // identifications captured as HIP graphs, keyed by every argument
+  bool graphs = false;
+  bool capturing = false;
+  hipStream_t cap_stream = nullptr;
+  struct Graph {
+    std::vector<unsigned char> key;
+    hipGraphExec_t exec;
+  };
+  std::vector<Graph> graph_cache;
+  // product autotuning: (kind, trans, M, N, K) -> K slices
+  bool autotune = false;
+  std::map<std::tuple<int, int, int, int, int>, int> tuned;
 };
 
 namespace {
@@ -88,14 +110,23 @@ struct Arena {
   }
 };
 
+void drop_graphs(ssi_ctx *c) {
+  for (auto &g : c->graph_cache) (void)hipGraphExecDestroy(g.exec);
+  c->graph_cache.clear();
+}
+
 // Reserve `bytes` of workspace for the current call (256-byte aligned).  Call
 // ws_reserve once with the call's total before ws_take.
 ssi_status ws_reserve(ssi_ctx *c, size_t bytes) {
   c->ws_top = 0;
   if (bytes <= c->ws_cap) return SSI_OK;
-  // Work already queued may still read the old arena.
+  // Work already queued may still read the old arena; captured graphs point
+  // into it.
   hipError_t e = hipStreamSynchronize(c->stream);
   if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+  for (int s = 0; s < c->n_lanes; ++s)
+    if (c->lanes[s]) (void)hipStreamSynchronize(c->lanes[s]);
+  drop_graphs(c);
   if (c->ws) (void)hipFree(c->ws);
   c->ws = nullptr;
   c->ws_cap = 0;
@@ -164,6 +195,7 @@ const char *ssi_status_string(ssi_status s) {
     case SSI_EDEVICE: return "device error";
     case SSI_ENOCONV: return "iteration limit reached";
     case SSI_EINTERNAL: return "internal error";
+    case SSI_EBUSY: return "request not finished";
   }
   return "unknown status";
 }
@@ -187,6 +219,7 @@ ssi_status ssi_create(int device, void *hip_stream, ssi_ctx **out) {
   c->device = device;
   c->num_cus = prop.multiProcessorCount;
   c->stream = static_cast<hipStream_t>(hip_stream);
+  c->user_stream = c->stream;
   e = hipMalloc(&c->status, 256);
   if (e == hipSuccess) e = hipMemset(c->status, 0, 256);
   if (e != hipSuccess) {
@@ -201,6 +234,16 @@ void ssi_destroy(ssi_ctx *c) {
   if (!c) return;
   DeviceGuard g(c->device);
   (void)hipStreamSynchronize(c->stream);
+  for (int s = 0; s < kMaxLanes; ++s)
+    if (c->lanes[s]) {
+      (void)hipStreamSynchronize(c->lanes[s]);
+      (void)hipStreamDestroy(c->lanes[s]);
+    }
+  for (int s = 0; s < kMaxLanes; ++s)
+    if (c->join_ev[s]) (void)hipEventDestroy(c->join_ev[s]);
+  if (c->fork_ev) (void)hipEventDestroy(c->fork_ev);
+  drop_graphs(c);
+  if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
   if (c->ws) (void)hipFree(c->ws);
   if (c->status) (void)hipFree(c->status);
   for (auto &r : c->recs) {
@@ -215,6 +258,8 @@ ssi_status ssi_synchronize(ssi_ctx *c) {
   if (!c) return fail(SSI_EINVAL, "ssi_synchronize: NULL context");
   DeviceGuard g(c->device);
   SSI_HIP(hipStreamSynchronize(c->stream));
+  for (int s = 0; s < c->n_lanes; ++s)
+    if (c->lanes[s]) SSI_HIP(hipStreamSynchronize(c->lanes[s]));
   int word = 0;
   SSI_HIP(hipMemcpy(&word, c->status, sizeof(int), hipMemcpyDeviceToHost));
   if (word) {
@@ -231,6 +276,48 @@ ssi_status ssi_set_profiling(ssi_ctx *c, int enable) {
   if (!c) return fail(SSI_EINVAL, "ssi_set_profiling: NULL context");
   c->profiling = enable != 0;
   return SSI_OK;
+}
+
+ssi_status ssi_set_lag_streams(ssi_ctx *c, int32_t n) {
+  if (!c) return fail(SSI_EINVAL, "ssi_set_lag_streams: NULL context");
+  if (n < 1 || n > kMaxLanes)
+    return fail(SSI_EINVAL, "ssi_set_lag_streams: n = %d must be in [1, %d]", n, kMaxLanes);
+  DeviceGuard g(c->device);
+  SSI_HIP(hipStreamSynchronize(c->stream));
+  if (!c->fork_ev) SSI_HIP(hipEventCreateWithFlags(&c->fork_ev, hipEventDisableTiming));
+  for (int s = 0; s < n; ++s) {
+    if (!c->lanes[s]) SSI_HIP(hipStreamCreateWithFlags(&c->lanes[s], hipStreamNonBlocking));
+    if (!c->join_ev[s]) SSI_HIP(hipEventCreateWithFlags(&c->join_ev[s], hipEventDisableTiming));
+  }
+  if (n != c->n_lanes) drop_graphs(c);
+  c->n_lanes = n;
+  return SSI_OK;
+}
+
+ssi_status ssi_set_graphs(ssi_ctx *c, int enable) {
+  if (!c) return fail(SSI_EINVAL, "ssi_set_graphs: NULL context");
+  DeviceGuard g(c->device);
+  if (enable && !c->cap_stream)
+    SSI_HIP(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+  if (!enable) {
+    SSI_HIP(hipStreamSynchronize(c->stream));
+    drop_graphs(c);
+  }
+  c->graphs = enable != 0;
+  return SSI_OK;
+}
+
+ssi_status ssi_set_autotune(ssi_ctx *c, int enable) {
+  if (!c) return fail(SSI_EINVAL, "ssi_set_autotune: NULL context");
+  c->autotune = enable != 0;
+  return SSI_OK;
+}
+
+int32_t ssi_tuned_splits(const ssi_ctx *c, int32_t kind, int32_t trans, int32_t m, int32_t n,
+                         int32_t k) {
+  if (!c) return 0;
+  auto it = c->tuned.find(std::make_tuple(kind, trans, m, n, k));
+  return it == c->tuned.end() ? 0 : it->second;
 }
 
 ssi_status ssi_profile_read(ssi_ctx *c, double *ms, int32_t *calls, int32_t n_stages) {
@@ -285,6 +372,10 @@ ssi_status ssi_validate(const ssi_params *p, int32_t l, int64_t n) {
     return fail(SSI_EINVAL, "need 1 <= order_min <= order_max");
   if (p->svd != SSI_SVD_FULL && p->svd != SSI_SVD_RANDOMIZED)
     return fail(SSI_EINVAL, "unknown svd mode %d", p->svd);
+  if (p->prec != SSI_PREC_FP32 && p->prec != SSI_PREC_BF16 && p->prec != SSI_PREC_BF16X3)
+    return fail(SSI_EINVAL, "unknown precision %d", p->prec);
+  if (p->prec != SSI_PREC_FP32 && p->svd != SSI_SVD_RANDOMIZED)
+    return fail(SSI_EINVAL, "BF16 products apply to the randomized SVD only");
   for (int i = 0; i < p->n_lags; ++i) {
     const int64_t jb = p->lags[i];
     if (jb < 2) return fail(SSI_EINVAL, "lag %d: j_b = %lld must be >= 2", i, (long long)jb);
@@ -364,12 +455,56 @@ bool is_device_ptr(const void *p) {
 
 // ------------------------------------------------------------ products
 // out = op(T) X with T FP32 and X FP64 (FP64 MFMA, split-K partial sums).
+// Number of K slices of a range-finder product.  With autotuning on, the
+// first product of each shape times every candidate slice count on the
+// stream (each run computes the full, correct product) and keeps the fastest
+// for later calls, which are then also safe to capture in a graph.
+constexpr int kTuneSplits[] = {2, 4, 6, 8, 12, 16};
+constexpr int kTuneMaxSplits = 16;
+
+template <typename Launch>
+int tuned_splits(ssi_ctx *c, int kind, bool ta, int M, int N, int K, Launch &&run,
+                 hipError_t &err) {
+  const auto key = std::make_tuple(kind, ta ? 1 : 0, M, N, K);
+  auto it = c->tuned.find(key);
+  if (it != c->tuned.end()) return it->second;
+  if (!c->autotune || c->capturing) return 0;
+  hipEvent_t a = take_event(c), b = take_event(c);
+  if (!a || !b) return 0;
+  int best = 0;
+  float best_ms = 0.f;
+  for (int cand : kTuneSplits) {
+    err = run(cand);                            // warm-up
+    if (err == hipSuccess) err = hipEventRecord(a, c->stream);
+    for (int r = 0; r < 3 && err == hipSuccess; ++r) err = run(cand);
+    if (err == hipSuccess) err = hipEventRecord(b, c->stream);
+    if (err == hipSuccess) err = hipEventSynchronize(b);
+    float ms = 0.f;
+    if (err == hipSuccess) err = hipEventElapsedTime(&ms, a, b);
+    if (err != hipSuccess) break;
+    if (best == 0 || ms < best_ms) {
+      best = cand;
+      best_ms = ms;
+    }
+  }
+  c->ev_pool.push_back(a);
+  c->ev_pool.push_back(b);
+  if (err == hipSuccess && best > 0) c->tuned[key] = best;
+  return best;
+}
+
 hipError_t prod_tf64(ssi_ctx *c, bool ta, const float *T, int64_t ldt, const double *X,
                      int64_t ldx, int M, int N, int K, double *part, double *out, int64_t ldo) {
-  const ssi::GemmPlan gp = ssi::plan_gemm_tf64(M, N, K, c->num_cus);
-  hipError_t e = ssi::launch_gemm_tf64(gp, ta, T, ldt, X, ldx, M, N, K, part, c->stream);
-  if (e != hipSuccess) return e;
-  return ssi::launch_reduce(gp, part, M, N, 1.0, out, ldo, nullptr, 0, c->stream);
+  auto run = [&](int splits) {
+    const ssi::GemmPlan gp = ssi::plan_gemm_tf64(M, N, K, c->num_cus, splits);
+    hipError_t e = ssi::launch_gemm_tf64(gp, ta, T, ldt, X, ldx, M, N, K, part, c->stream);
+    if (e != hipSuccess) return e;
+    return ssi::launch_reduce(gp, part, M, N, 1.0, out, ldo, nullptr, 0, c->stream);
+  };
+  hipError_t err = hipSuccess;
+  const int splits = tuned_splits(c, 0, ta, M, N, K, run, err);
+  if (err != hipSuccess) return err;
+  return run(splits);
 }
 
 hipError_t prod_f64(ssi_ctx *c, bool ta, const double *A, int64_t lda, const double *B,
@@ -381,19 +516,49 @@ hipError_t prod_f64(ssi_ctx *c, bool ta, const double *A, int64_t lda, const dou
   return ssi::launch_reduce(gp, part, M, N, 1.0, out, ldo, out32, ld32, c->stream);
 }
 
-size_t part_tf64(int M, int N, int K, int cus) { return ssi::plan_gemm_tf64(M, N, K, cus).part_elems(); }
+// out = op(T) X with T and X rounded to BF16, FP32 MFMA accumulation, FP32
+// split partials summed in FP64 (the reduced-precision range finder).
+hipError_t prod_bf16(ssi_ctx *c, bool ta, const float *T, int64_t ldt, const double *X,
+                     int64_t ldx, int M, int N, int K, int nt, uint16_t *xt, float *part,
+                     double *out, int64_t ldo) {
+  const ssi::BfPlan bp0 = ssi::plan_gemm_tbf16(M, N, K, c->num_cus, 0, nt);
+  hipError_t e = ssi::launch_pack_bf16(bp0, X, ldx, K, N, xt, c->stream);
+  if (e != hipSuccess) return e;
+  auto run = [&](int splits) {
+    const ssi::BfPlan bp = ssi::plan_gemm_tbf16(M, N, K, c->num_cus, splits, nt);
+    hipError_t e2 = ssi::launch_gemm_tbf16(bp, ta, T, ldt, xt, M, N, K, part, c->stream);
+    if (e2 != hipSuccess) return e2;
+    return ssi::launch_reduce_f32(bp, part, M, N, out, ldo, c->stream);
+  };
+  hipError_t err = hipSuccess;
+  const int splits = tuned_splits(c, nt, ta, M, N, K, run, err);
+  if (err != hipSuccess) return err;
+  return run(splits);
+}
+
+// Partial-sum elements of a range-finder product: the planned K slices, or
+// the largest autotuning candidate when tuning may run.
+size_t part_tf64(int M, int N, int K, int cus, bool tune = false) {
+  size_t e = ssi::plan_gemm_tf64(M, N, K, cus).part_elems();
+  if (tune) e = std::max(e, ssi::plan_gemm_tf64(M, N, K, cus, kTuneMaxSplits).part_elems());
+  return e;
+}
 size_t part_f64(int M, int N, int K, int cus) { return ssi::plan_gemm_f64(M, N, K, cus).part_elems(); }
 
 // ------------------------------------------------------------ randomized SVD
 struct RsvdBufs {
   double *om, *ya, *yb, *gm, *rinv, *lws, *evals, *evecs, *dws, *part;
+  uint16_t *xt;        // BF16 X^T of the reduced-precision products
+  float *part32;       // their FP32 split partials
   int ell;
+  int prec;
 };
 
-RsvdBufs carve_rsvd(Arena &a, ssi_ctx *c, int64_t m, int ell, int k,
+RsvdBufs carve_rsvd(Arena &a, ssi_ctx *c, int64_t m, int ell, int k, int prec,
                     const int64_t *m_all = nullptr, int n_m = 0) {
   RsvdBufs b{};
   b.ell = ell;
+  b.prec = prec;
   const int mi = (int)m, cu = c->num_cus;
   b.om = a.take<double>((size_t)m * ell);
   b.ya = a.take<double>((size_t)m * ell);
@@ -407,10 +572,25 @@ RsvdBufs carve_rsvd(Arena &a, ssi_ctx *c, int64_t m, int ell, int k,
   size_t part = 0;
   for (int i = 0; i < (m_all ? n_m : 1); ++i) {
     const int mm = m_all ? (int)m_all[i] : mi;
-    part = std::max({part, part_tf64(mm, ell, mm, cu), part_f64(ell, ell, mm, cu),
+    part = std::max({part, part_tf64(mm, ell, mm, cu, c->autotune), part_f64(ell, ell, mm, cu),
                      part_f64(mm, ell, ell, cu), part_f64(mm, k, ell, cu)});
   }
   b.part = a.take<double>(part);
+  if (prec == SSI_PREC_BF16 || prec == SSI_PREC_BF16X3) {
+    const int nt = prec == SSI_PREC_BF16X3 ? 3 : 1;
+    size_t xt = 0, p32 = 0;
+    for (int i = 0; i < (m_all ? n_m : 1); ++i) {
+      const int mm = m_all ? (int)m_all[i] : mi;
+      const ssi::BfPlan bp = ssi::plan_gemm_tbf16(mm, ell, mm, cu, 0, nt);
+      xt = std::max(xt, bp.xt_elems());
+      p32 = std::max(p32, bp.part_elems());
+      if (c->autotune)
+        p32 = std::max(p32,
+                       ssi::plan_gemm_tbf16(mm, ell, mm, cu, kTuneMaxSplits, nt).part_elems());
+    }
+    b.xt = a.take<uint16_t>(xt);
+    b.part32 = a.take<float>(p32);
+  }
   return b;
 }
 
@@ -452,7 +632,11 @@ ssi_status run_rsvd(ssi_ctx *c, RsvdBufs &b, const float *t, int64_t m, int64_t 
   // Y = T Omega, Q = orth(Y)
   {
     StageTimer tm(c, SSI_STAGE_PRODUCTS);
-    e = prod_tf64(c, false, t, ldt, b.om, ell, mi, ell, mi, b.part, b.ya, ell);
+    if (b.prec != SSI_PREC_FP32)
+      e = prod_bf16(c, false, t, ldt, b.om, ell, mi, ell, mi, b.prec == SSI_PREC_BF16X3 ? 3 : 1,
+                    b.xt, b.part32, b.ya, ell);
+    else
+      e = prod_tf64(c, false, t, ldt, b.om, ell, mi, ell, mi, b.part, b.ya, ell);
   }
   if (e != hipSuccess) return hip_fail(e, "Y = T Omega");
   double *Q;
@@ -467,7 +651,11 @@ ssi_status run_rsvd(ssi_ctx *c, RsvdBufs &b, const float *t, int64_t m, int64_t 
       double *other = (Q == b.ya) ? b.yb : b.ya;
       {
         StageTimer tm(c, SSI_STAGE_PRODUCTS);
-        e = prod_tf64(c, side == 0, t, ldt, Q, ell, mi, ell, mi, b.part, other, ell);
+        if (b.prec != SSI_PREC_FP32)
+          e = prod_bf16(c, side == 0, t, ldt, Q, ell, mi, ell, mi,
+                        b.prec == SSI_PREC_BF16X3 ? 3 : 1, b.xt, b.part32, other, ell);
+        else
+          e = prod_tf64(c, side == 0, t, ldt, Q, ell, mi, ell, mi, b.part, other, ell);
       }
       if (e != hipSuccess) return hip_fail(e, "power iteration product");
       {
@@ -478,7 +666,10 @@ ssi_status run_rsvd(ssi_ctx *c, RsvdBufs &b, const float *t, int64_t m, int64_t 
       if (e != hipSuccess) return hip_fail(e, "orthonormalize");
     }
   }
-  // P^T = T^T Q; G = P P^T; G = U~ S^2 U~^T; U = Q U~[:, :k]
+  // P^T = T^T Q; G = P P^T; G = U~ S^2 U~^T; U = Q U~[:, :k].  The projection
+  // is always taken in full precision (FP32 T, FP64 Q and accumulation): a
+  // reduced-precision range finder only perturbs the basis Q, and P = Q^T T
+  // of that basis is then exact to FP64 rounding.
   double *pt = (Q == b.ya) ? b.yb : b.ya;
   {
     StageTimer tm(c, SSI_STAGE_PRODUCTS);
@@ -620,39 +811,86 @@ ssi_status run_modal(ssi_ctx *c, ModalBufs &b, const double *u, int64_t m, int k
 }
 
 // ------------------------------------------------------------ identification
-struct IdentBufs {
-  ssi::CorrPlan cp;
-  double *corr_part;
-  float *r;
+// Buffers of one lag stream ("lane"): the lags i with i % n_lanes == lane run
+// on it one after another, so each lane is sized for its largest lag.
+struct LaneBufs {
   float *t;
-  int64_t ldt;
   double *u, *sig;
   RsvdBufs rb;
   FullBufs fb;
   ModalBufs mb;
 };
 
+struct IdentBufs {
+  ssi::CorrPlan cp;
+  double *corr_part;
+  float *r;
+  int n_lanes;
+  LaneBufs lane[kMaxLanes];
+};
+
+int lanes_for(const ssi_ctx *c, const ssi_params *p) { return std::min(c->n_lanes, p->n_lags); }
+
 IdentBufs carve_identify(Arena &a, ssi_ctx *c, int l, int64_t n, const ssi_params *p) {
   IdentBufs b{};
   const int L = 2 * p->lags[p->n_lags - 1] - 1;
-  const int64_t mmax = (int64_t)p->lags[p->n_lags - 1] * l;
   b.cp = ssi::plan_correlate(l, n, L, c->num_cus);
   b.corr_part = a.take<double>(b.cp.partial_elems);
   b.r = a.take<float>((size_t)L * l * l);
-  b.ldt = (mmax + 3) & ~int64_t(3);
-  b.t = a.take<float>((size_t)mmax * b.ldt);
+  b.n_lanes = lanes_for(c, p);
   const int kcols = p->svd == SSI_SVD_RANDOMIZED ? p->rank : p->order_max;
-  b.u = a.take<double>((size_t)mmax * kcols);
-  b.sig = a.take<double>(kcols);
-  if (p->svd == SSI_SVD_RANDOMIZED) {
-    std::vector<int64_t> ms(p->n_lags);
-    for (int i = 0; i < p->n_lags; ++i) ms[i] = (int64_t)p->lags[i] * l;
-    b.rb = carve_rsvd(a, c, mmax, p->rank + p->oversample, p->rank, ms.data(), p->n_lags);
+  for (int s = 0; s < b.n_lanes; ++s) {
+    LaneBufs &lb = b.lane[s];
+    std::vector<int64_t> ms;
+    for (int i = s; i < p->n_lags; i += b.n_lanes) ms.push_back((int64_t)p->lags[i] * l);
+    const int64_t mmax = *std::max_element(ms.begin(), ms.end());
+    const int64_t ldt = (mmax + 3) & ~int64_t(3);
+    lb.t = a.take<float>((size_t)mmax * ldt);
+    lb.u = a.take<double>((size_t)mmax * kcols);
+    lb.sig = a.take<double>(kcols);
+    if (p->svd == SSI_SVD_RANDOMIZED)
+      lb.rb = carve_rsvd(a, c, mmax, p->rank + p->oversample, p->rank, p->prec, ms.data(),
+                         (int)ms.size());
+    else
+      lb.fb = carve_full(a, c, (int)mmax);
+    lb.mb = carve_modal(a, c, mmax, l, p);
   }
-  else b.fb = carve_full(a, c, (int)mmax);
-  b.mb = carve_modal(a, c, mmax, l, p);
   return b;
 }
+
+// Enqueues one lag (Toeplitz, SVD, modal stage) on c->stream.
+ssi_status run_lag(ssi_ctx *c, LaneBufs &b, const float *r, int l, const ssi_params *p, int i,
+                   const ssi_output *out) {
+  const int jb = p->lags[i];
+  const int64_t m = (int64_t)jb * l;
+  const int64_t ldt = (m + 3) & ~int64_t(3);
+  const int kcols = p->svd == SSI_SVD_RANDOMIZED ? p->rank : p->order_max;
+  hipError_t e;
+  {
+    StageTimer tm(c, SSI_STAGE_TOEPLITZ);
+    e = ssi::launch_toeplitz(r, l, jb, b.t, ldt, c->stream);
+  }
+  if (e != hipSuccess) return hip_fail(e, "Toeplitz");
+  ssi_status s;
+  if (p->svd == SSI_SVD_RANDOMIZED)
+    s = run_rsvd(c, b.rb, b.t, m, ldt, p->rank, p->oversample, p->power_iters, nullptr, p->seed,
+                 (uint32_t)i, b.u, b.sig);
+  else
+    s = run_svd_full(c, b.fb, b.t, (int)m, ldt, kcols, b.u, b.sig);
+  if (s != SSI_OK) return s;
+  e = hipMemcpyAsync(out->sigma + (int64_t)i * kcols, b.sig, sizeof(double) * kcols,
+                     hipMemcpyDeviceToDevice, c->stream);
+  if (e != hipSuccess) return hip_fail(e, "sigma copy");
+  return run_modal(c, b.mb, b.u, m, kcols, l, p, i, out);
+}
+
+// Points c->stream at another stream for the lifetime of the guard.
+struct StreamSwap {
+  ssi_ctx *c;
+  hipStream_t saved;
+  StreamSwap(ssi_ctx *ctx, hipStream_t s) : c(ctx), saved(ctx->stream) { c->stream = s; }
+  ~StreamSwap() { c->stream = saved; }
+};
 
 ssi_status run_identify(ssi_ctx *c, IdentBufs &b, const float *y, int l, int64_t n,
                         int64_t ldy, const ssi_params *p, const ssi_output *out) {
@@ -668,32 +906,31 @@ ssi_status run_identify(ssi_ctx *c, IdentBufs &b, const float *y, int l, int64_t
     e = ssi::launch_correlate_reduce(b.cp, l, n, L, b.corr_part, b.r, c->stream);
   }
   if (e != hipSuccess) return hip_fail(e, "correlation reduction");
-  const int kcols = p->svd == SSI_SVD_RANDOMIZED ? p->rank : p->order_max;
-  for (int i = 0; i < p->n_lags; ++i) {
-    const int jb = p->lags[i];
-    const int64_t m = (int64_t)jb * l;
-    const int64_t ldt = (m + 3) & ~int64_t(3);
-    {
-      StageTimer tm(c, SSI_STAGE_TOEPLITZ);
-      e = ssi::launch_toeplitz(b.r, l, jb, b.t, ldt, c->stream);
+  if (b.n_lanes == 1) {
+    for (int i = 0; i < p->n_lags; ++i) {
+      ssi_status s = run_lag(c, b.lane[0], b.r, l, p, i, out);
+      if (s != SSI_OK) return s;
     }
-    if (e != hipSuccess) return hip_fail(e, "Toeplitz");
-    ssi_status s;
-    if (p->svd == SSI_SVD_RANDOMIZED) {
-      // rebuild the RSVD views for this lag's m (buffers are sized for the largest)
-      s = run_rsvd(c, b.rb, b.t, m, ldt, p->rank, p->oversample, p->power_iters, nullptr,
-                   p->seed, (uint32_t)i, b.u, b.sig);
-    } else {
-      s = run_svd_full(c, b.fb, b.t, (int)m, ldt, kcols, b.u, b.sig);
-    }
-    if (s != SSI_OK) return s;
-    e = hipMemcpyAsync(out->sigma + (int64_t)i * kcols, b.sig, sizeof(double) * kcols,
-                       hipMemcpyDeviceToDevice, c->stream);
-    if (e != hipSuccess) return hip_fail(e, "sigma copy");
-    s = run_modal(c, b.mb, b.u, m, kcols, l, p, i, out);
-    if (s != SSI_OK) return s;
+    return SSI_OK;
   }
-  return SSI_OK;
+  // Several lanes: fork after the correlations, join before returning, so the
+  // caller's stream sees one ordered identification.  Lags of different
+  // lanes overlap on the device (the latency-bound modal stage of one lag
+  // runs beside the products of the next).
+  hipStream_t main = c->stream;
+  SSI_HIP(hipEventRecord(c->fork_ev, main));
+  for (int s = 0; s < b.n_lanes; ++s) SSI_HIP(hipStreamWaitEvent(c->lanes[s], c->fork_ev, 0));
+  ssi_status st = SSI_OK;
+  for (int i = 0; i < p->n_lags && st == SSI_OK; ++i) {
+    const int s = i % b.n_lanes;
+    StreamSwap sw(c, c->lanes[s]);
+    st = run_lag(c, b.lane[s], b.r, l, p, i, out);
+  }
+  for (int s = 0; s < b.n_lanes; ++s) {
+    SSI_HIP(hipEventRecord(c->join_ev[s], c->lanes[s]));
+    SSI_HIP(hipStreamWaitEvent(main, c->join_ev[s], 0));
+  }
+  return st;
 }
 
 }  // namespace
@@ -760,8 +997,8 @@ ssi_status ssi_workspace_estimate(const ssi_params *p, int32_t l, int64_t n, siz
 }
 
 ssi_status ssi_rsvd(ssi_ctx *c, const float *t, int64_t m, int64_t ldt, int32_t k, int32_t p,
-                    int32_t q, const float *omega, uint64_t seed, uint32_t stream, double *u,
-                    double *sigma) {
+                    int32_t q, int32_t prec, const float *omega, uint64_t seed, uint32_t stream,
+                    double *u, double *sigma) {
   if (!c) return fail(SSI_EINVAL, "ssi_rsvd: NULL context");
   if (!t || !u || !sigma) return fail(SSI_EINVAL, "ssi_rsvd: NULL buffer");
   if (m < 1 || ldt < m || k < 1 || p < 0 || q < 0 || (int64_t)k + p > m)
@@ -769,16 +1006,18 @@ ssi_status ssi_rsvd(ssi_ctx *c, const float *t, int64_t m, int64_t ldt, int32_t 
   if (k + p > ssi::dense_max_n())
     return fail(SSI_EINVAL, "ssi_rsvd: k + p = %d exceeds %d", k + p, ssi::dense_max_n());
   if (m > INT32_MAX / 2) return fail(SSI_EINVAL, "ssi_rsvd: m too large");
+  if (prec != SSI_PREC_FP32 && prec != SSI_PREC_BF16 && prec != SSI_PREC_BF16X3)
+    return fail(SSI_EINVAL, "ssi_rsvd: unknown precision %d", prec);
   DeviceGuard g(c->device);
   if (!is_device_ptr(t) || !is_device_ptr(u) || !is_device_ptr(sigma) ||
       (omega && !is_device_ptr(omega)))
     return fail(SSI_EINVAL, "ssi_rsvd: buffers must be device pointers");
   Arena probe;
-  carve_rsvd(probe, c, m, k + p, k);
+  carve_rsvd(probe, c, m, k + p, k, prec);
   ssi_status s = ws_reserve(c, probe.off);
   if (s != SSI_OK) return s;
   Arena a{c->ws, 0};
-  RsvdBufs b = carve_rsvd(a, c, m, k + p, k);
+  RsvdBufs b = carve_rsvd(a, c, m, k + p, k, prec);
   return run_rsvd(c, b, t, m, ldt, k, p, q, omega, seed, stream, u, sigma);
 }
 
@@ -824,6 +1063,50 @@ ssi_status ssi_modal(ssi_ctx *c, const double *u, const double *sigma, int64_t m
   return run_modal(c, b, u, m, k, l, p, lag_index, out);
 }
 
+ssi_status ssi_stability(ssi_ctx *c, const ssi_params *p, int32_t l, const ssi_output *out,
+                         const ssi_stability_params *sp, double *mpc, double *mpd,
+                         uint8_t *flags) {
+  if (!c || !p || !out || !sp || !mpc || !mpd || !flags)
+    return fail(SSI_EINVAL, "ssi_stability: NULL argument");
+  if (!out->count || !out->f || !out->xi || !out->phi)
+    return fail(SSI_EINVAL, "ssi_stability: NULL output buffer");
+  if (l < 1 || p->n_lags < 1 || p->order_step < 1 || p->order_min < 1 ||
+      p->order_max < p->order_min)
+    return fail(SSI_EINVAL, "ssi_stability: bad sizes");
+  if (!(sp->xi_max > 0.0) || !(sp->alpha_f >= 0.0) || !(sp->alpha_xi >= 0.0) ||
+      !(sp->alpha_mac >= 0.0))
+    return fail(SSI_EINVAL, "ssi_stability: thresholds must be non-negative (xi_max > 0)");
+  DeviceGuard g(c->device);
+  const int n_orders = n_orders_of(p);
+  const int pole_cap = ssi_pole_offset(p, n_orders);
+  const size_t slots = (size_t)p->n_lags * pole_cap;
+  ssi_status s = ws_reserve(c, aligned_bytes(slots, 1));
+  if (s != SSI_OK) return s;
+  ssi::StabilityArgs a{};
+  a.n_lags = p->n_lags;
+  a.n_orders = n_orders;
+  a.nmin = p->order_min;
+  a.step = p->order_step;
+  a.pole_cap = pole_cap;
+  a.l = l;
+  a.count = out->count;
+  a.f = out->f;
+  a.xi = out->xi;
+  a.phi = out->phi;
+  a.xi_max = sp->xi_max;
+  a.mpc_min = sp->mpc_min;
+  a.mpd_max = sp->mpd_max;
+  a.alpha_f = sp->alpha_f;
+  a.alpha_xi = sp->alpha_xi;
+  a.alpha_mac = sp->alpha_mac;
+  a.mpc = mpc;
+  a.mpd = mpd;
+  a.hc = ws_take<uint8_t>(c, slots);
+  a.flags = flags;
+  SSI_HIP(ssi::launch_stability(a, c->stream));
+  return SSI_OK;
+}
+
 ssi_status ssi_identify(ssi_ctx *c, const float *y, int32_t l, int64_t n, int64_t ldy,
                         const ssi_params *p, const ssi_output *out) {
   if (!c || !y || !p || !out) return fail(SSI_EINVAL, "ssi_identify: NULL argument");
@@ -840,7 +1123,67 @@ ssi_status ssi_identify(ssi_ctx *c, const float *y, int32_t l, int64_t n, int64_
   if (s != SSI_OK) return s;
   Arena a{c->ws, 0};
   IdentBufs b = carve_identify(a, c, l, n, p);
-  return run_identify(c, b, y, l, n, ldy, p, out);
+  if (!c->graphs) return run_identify(c, b, y, l, n, ldy, p, out);
+
+  // Graph mode: every argument (pointers included) keys a captured graph of
+  // the whole identification.  The first call with a key runs eagerly (any
+  // autotuning happens there) and then captures; later calls launch the
+  // graph on the caller's stream.
+  std::vector<unsigned char> key;
+  auto put = [&key](const void *v, size_t nb) {
+    const unsigned char *q = static_cast<const unsigned char *>(v);
+    key.insert(key.end(), q, q + nb);
+  };
+  const void *ptrs[] = {y, out->sigma, out->count, out->f, out->xi, out->mu, out->phi,
+                        out->flags, c->ws};
+  put(ptrs, sizeof ptrs);
+  put(&l, sizeof l);
+  put(&n, sizeof n);
+  put(&ldy, sizeof ldy);
+  ssi_params pc = *p;
+  pc.lags = nullptr;
+  put(&pc, sizeof pc);
+  put(p->lags, sizeof(int32_t) * p->n_lags);
+  put(&c->n_lanes, sizeof c->n_lanes);
+  for (auto &g : c->graph_cache)
+    if (g.key == key) {
+      SSI_HIP(hipGraphLaunch(g.exec, c->stream));
+      return SSI_OK;
+    }
+  s = run_identify(c, b, y, l, n, ldy, p, out);
+  if (s != SSI_OK) return s;
+  // the lanes join the capture below; let the eager run drain from them first
+  SSI_HIP(hipStreamSynchronize(c->stream));
+  for (int ln = 0; ln < c->n_lanes; ++ln)
+    if (c->lanes[ln]) SSI_HIP(hipStreamSynchronize(c->lanes[ln]));
+  hipGraph_t graph = nullptr;
+  {
+    StreamSwap sw(c, c->cap_stream);
+    const bool prof = c->profiling;
+    c->profiling = false;
+    c->capturing = true;
+    hipError_t e = hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeRelaxed);
+    if (e != hipSuccess) {
+      c->profiling = prof;
+      c->capturing = false;
+      return hip_fail(e, "hipStreamBeginCapture");
+    }
+    s = run_identify(c, b, y, l, n, ldy, p, out);
+    e = hipStreamEndCapture(c->cap_stream, &graph);
+    c->profiling = prof;
+    c->capturing = false;
+    if (s != SSI_OK) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return s;
+    }
+    if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+  }
+  hipGraphExec_t exec = nullptr;
+  hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate");
+  c->graph_cache.push_back({std::move(key), exec});
+  return SSI_OK;
 }
 
 }  // extern "C"

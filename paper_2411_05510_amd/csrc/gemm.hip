@@ -18,8 +18,8 @@
 namespace {
 
 constexpr int tBM = 64, tBN = 224, tKT = 16;
-constexpr int tLA = tKT + 4;    // FP32 A row stride in LDS (floats)
-constexpr int tLB = tKT + 2;    // FP64 B row stride in LDS (doubles)
+constexpr int tLA = tKT + 4;    // FP32 A row stride in LDS (floats), A stored [i][k]
+constexpr int tLB = tBN + 4;    // FP64 B row stride in LDS (doubles), B stored [k][j]
 
 constexpr int dBM = 64, dBN = 64, dKT = 16, dLS = dKT + 2;    // fp64 tiles
 
@@ -48,15 +48,17 @@ SSI_DEV float f4get(const float4 &v, int s) {
 //   TA = false: A is M x K (lda);  TA = true: A is K x M (lda), op(A) = A^T.
 //   A FP32, B FP64 K x N (ldb).  VEC: lda % 4 == 0 and A 16-byte aligned;
 //   BVEC: ldb even and B 16-byte aligned.
-// In MFMA step s the 16-lane group g of a wave supplies k = 4 g + s of the
-// 16-wide K tile, so each lane reads its four k of a row with one LDS read.
+// Each K tile (16) is loaded into registers with all loads in flight at once
+// (out-of-range rows and columns read a clamped in-range address and are
+// zeroed by select), then written to LDS.  In MFMA step s of K sub-tile h the
+// 16-lane group g of a wave supplies k = 16 h + 4 g + s.
 template <bool TA, bool VEC, bool BVEC>
 __global__ void __launch_bounds__(256, 2)
 gemm_tf64_mfma(const float *__restrict__ A, int64_t lda, const double *__restrict__ B,
                int64_t ldb, double *__restrict__ C, int64_t ldc, int64_t split_stride, int M,
                int N, int K, int k_per_split, int gm, int splits) {
   __shared__ __attribute__((aligned(16))) float As[tBM * tLA];
-  __shared__ __attribute__((aligned(16))) double Bs[tBN * tLB];
+  __shared__ __attribute__((aligned(16))) double Bs[tKT * tLB];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wr = wave & 1, wc = wave >> 1;
   const int split = blockIdx.x % splits;
@@ -75,69 +77,92 @@ gemm_tf64_mfma(const float *__restrict__ A, int64_t lda, const double *__restric
   for (int ct = 0; ct < 7; ++ct) colok[ct] = n0 + wc * 112 + ct * 16 < N;
 
   for (int k0 = kb; k0 < ke; k0 += tKT) {
-    __syncthreads();
-    // ---- A tile -> As[i][k] (FP32): 64 x 16, one float4 per thread
-    if (!TA) {
-      const int r = tid >> 2, c4 = tid & 3;
-      const float4 v = load4<VEC>(A, lda, m0 + r, M, k0 + 4 * c4, ke);
-      *reinterpret_cast<float4 *>(&As[r * tLA + 4 * c4]) = v;
-    } else {
-      const int kr = tid >> 4, c4 = tid & 15;
-      const float4 v = (k0 + kr < ke) ? load4<VEC>(A, lda, k0 + kr, ke, m0 + 4 * c4, M)
-                                      : make_float4(0.f, 0.f, 0.f, 0.f);
-      As[(4 * c4 + 0) * tLA + kr] = v.x;
-      As[(4 * c4 + 1) * tLA + kr] = v.y;
-      As[(4 * c4 + 2) * tLA + kr] = v.z;
-      As[(4 * c4 + 3) * tLA + kr] = v.w;
+    // ---- A tile (64 x 16 FP32): one float4 per thread
+    float4 ra[1];
+#pragma unroll
+    for (int h = 0; h < 1; ++h) {
+      const int idx = tid + 256 * h;
+      if (!TA) {
+        const int r = idx >> 2, c4 = idx & 3;              // row, 4-column group of k
+        const int gi = m0 + r, gk = k0 + 4 * c4;
+        const float *p = A + (int64_t)min(gi, M - 1) * lda;
+        float4 v;
+        if (VEC && gk + 3 < ke) v = *reinterpret_cast<const float4 *>(p + gk);
+        else v = load4<false>(p, 0, 0, 1, gk, ke);
+        ra[h] = gi < M ? v : make_float4(0.f, 0.f, 0.f, 0.f);
+      } else {
+        const int kr = idx >> 4, c4 = idx & 15;            // k row, 4-column group of i
+        const int gk = k0 + kr, gi = m0 + 4 * c4;
+        const float *p = A + (int64_t)min(gk, ke - 1) * lda;
+        float4 v;
+        if (VEC && gi + 3 < M) v = *reinterpret_cast<const float4 *>(p + gi);
+        else v = load4<false>(p, 0, 0, 1, gi, M);
+        ra[h] = gk < ke ? v : make_float4(0.f, 0.f, 0.f, 0.f);
+      }
     }
-    // ---- B tile -> Bs[j][k] (FP64): 16 x 224, seven double pairs per thread
+    // ---- B tile (16 x 224 FP64): seven double pairs per thread
+    double2 rbv[7];
 #pragma unroll
     for (int h = 0; h < 7; ++h) {
       const int idx = tid + 256 * h;
       const int kr = idx / 112, c2 = idx - kr * 112;
       const int gk = k0 + kr, gj = n0 + 2 * c2;
-      double v0 = 0.0, v1 = 0.0;
-      if (gk < ke) {
-        const double *q = B + (int64_t)gk * ldb + gj;
-        if (BVEC && gj + 1 < N) {
-          const double2 v = *reinterpret_cast<const double2 *>(q);
-          v0 = v.x;
-          v1 = v.y;
-        } else {
-          if (gj < N) v0 = q[0];
-          if (gj + 1 < N) v1 = q[1];
-        }
+      const double *q = B + (int64_t)min(gk, ke - 1) * ldb;
+      double2 v;
+      if (BVEC && gj + 1 < N) {
+        v = *reinterpret_cast<const double2 *>(q + gj);
+      } else {
+        v.x = q[min(gj, N - 1)];
+        v.y = q[min(gj + 1, N - 1)];
+        if (gj >= N) v.x = 0.0;
+        if (gj + 1 >= N) v.y = 0.0;
       }
-      Bs[(2 * c2) * tLB + kr] = v0;
-      Bs[(2 * c2 + 1) * tLB + kr] = v1;
+      rbv[h] = gk < ke ? v : make_double2(0.0, 0.0);
+    }
+    __syncthreads();                      // previous tile's reads are done
+#pragma unroll
+    for (int h = 0; h < 1; ++h) {
+      const int idx = tid + 256 * h;
+      if (!TA) {
+        const int r = idx >> 2, c4 = idx & 3;
+        *reinterpret_cast<float4 *>(&As[r * tLA + 4 * c4]) = ra[h];
+      } else {
+        const int kr = idx >> 4, c4 = idx & 15;
+        As[(4 * c4 + 0) * tLA + kr] = ra[h].x;
+        As[(4 * c4 + 1) * tLA + kr] = ra[h].y;
+        As[(4 * c4 + 2) * tLA + kr] = ra[h].z;
+        As[(4 * c4 + 3) * tLA + kr] = ra[h].w;
+      }
+    }
+#pragma unroll
+    for (int h = 0; h < 7; ++h) {
+      const int idx = tid + 256 * h;
+      const int kr = idx / 112, c2 = idx - kr * 112;
+      *reinterpret_cast<double2 *>(&Bs[kr * tLB + 2 * c2]) = rbv[h];
     }
     __syncthreads();
 
-    const int ko = 4 * (lane >> 4);
-    float4 a4[2];
-    double bv[7][4];
 #pragma unroll
-    for (int rt = 0; rt < 2; ++rt)
-      a4[rt] = *reinterpret_cast<const float4 *>(&As[(wr * 32 + rt * 16 + (lane & 15)) * tLA + ko]);
+    for (int hk = 0; hk < tKT / 16; ++hk) {
+      const int ko = 16 * hk + 4 * (lane >> 4);
+      float4 a4[2];
 #pragma unroll
-    for (int ct = 0; ct < 7; ++ct) {
-      const double2 *bp =
-          reinterpret_cast<const double2 *>(&Bs[(wc * 112 + ct * 16 + (lane & 15)) * tLB + ko]);
-      const double2 lo = bp[0], hi = bp[1];
-      bv[ct][0] = lo.x;
-      bv[ct][1] = lo.y;
-      bv[ct][2] = hi.x;
-      bv[ct][3] = hi.y;
-    }
+      for (int rt = 0; rt < 2; ++rt)
+        a4[rt] = *reinterpret_cast<const float4 *>(
+            &As[(wr * 32 + rt * 16 + (lane & 15)) * tLA + ko]);
 #pragma unroll
-    for (int s = 0; s < 4; ++s) {
+      for (int s = 0; s < 4; ++s) {
+        double bv[7];
 #pragma unroll
-      for (int ct = 0; ct < 7; ++ct) {
-        if (!colok[ct]) continue;
+        for (int ct = 0; ct < 7; ++ct) bv[ct] = Bs[(ko + s) * tLB + wc * 112 + ct * 16 + (lane & 15)];
 #pragma unroll
-        for (int rt = 0; rt < 2; ++rt)
-          acc[rt][ct] = __builtin_amdgcn_mfma_f64_16x16x4f64((double)f4get(a4[rt], s),
-                                                             bv[ct][s], acc[rt][ct], 0, 0, 0);
+        for (int ct = 0; ct < 7; ++ct) {
+          if (!colok[ct]) continue;
+#pragma unroll
+          for (int rt = 0; rt < 2; ++rt)
+            acc[rt][ct] = __builtin_amdgcn_mfma_f64_16x16x4f64((double)f4get(a4[rt], s),
+                                                               bv[ct], acc[rt][ct], 0, 0, 0);
+        }
       }
     }
   }
@@ -299,7 +324,7 @@ int grid_cap(int64_t work) {
 }
 }  // namespace
 
-GemmPlan plan_gemm_tf64(int M, int N, int K, int num_cus) {
+GemmPlan plan_gemm_tf64(int M, int N, int K, int num_cus, int force_splits) {
   GemmPlan p{};
   p.gm = ceil_div(M, tBM);
   p.gn = ceil_div(N, tBN);
@@ -310,6 +335,7 @@ GemmPlan plan_gemm_tf64(int M, int N, int K, int num_cus) {
   if (tiles * 8 < (int64_t)num_cus) splits = ceil_div<int64_t>((int64_t)num_cus * 2, tiles);
   const int64_t max_splits = ceil_div<int64_t>(K, 512);
   splits = std::max<int64_t>(1, std::min(splits, max_splits));
+  if (force_splits > 0) splits = std::min<int64_t>(force_splits, ceil_div<int64_t>(K, tKT));
   int64_t kps = ceil_div<int64_t>(K, splits);
   kps = ceil_div<int64_t>(kps, tKT) * tKT;
   p.k_per_split = (int)kps;

@@ -1,0 +1,330 @@
+// Reduced-precision range-finder products: C = op(T) X with both operands
+// rounded to BF16 and FP32 accumulation on v_mfma_f32_16x16x32_bf16.
+//
+// T is the FP32 block-Toeplitz matrix as stored; each 64 x 64 tile is read
+// once from HBM (16-byte loads, 256 contiguous bytes per row segment), rounded
+// to BF16 (round to nearest even) and written to LDS, transposed on the way
+// for op(T) = T^T.  X arrives pre-rounded and transposed (xt[j][k], BF16,
+// rows padded to a multiple of 224 and columns to a multiple of 64 with
+// zeros), so its tile loads need no bounds checks.  A workgroup owns 64 rows
+// of the output and all 224 columns of one column block, over one K slice;
+// FP32 partial sums of the K slices are added in FP64 by
+// reduce_splits_f32.  The flat grid is decoded split-fastest, so the
+// workgroups of one K slice share an XCD and its L2 holds their slice of X.
+//
+// BF16 keeps the FP32 exponent range, so no scaling is needed for these
+// operands (T entries are correlations, X entries are O(1/sqrt(m))).
+#include "common.h"
+#include "kernels.h"
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+namespace {
+
+constexpr int bBM = 64, bBN = 224;
+
+// FP32 -> BF16, round to nearest even (NaN kept quiet).
+SSI_DEV uint16_t bf16_rne(float f) {
+  uint32_t u = __float_as_uint(f);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+
+// FP64 -> BF16, round to nearest even in one rounding: truncate to FP32 and
+// set the last FP32 bit when the truncation was inexact (round to odd), which
+// keeps the sticky information for the final rounding to 8 significant bits.
+SSI_DEV uint16_t bf16_rne(double d) {
+  float f = __double2float_rz(d);
+  if ((double)f != d && d == d) f = __uint_as_float(__float_as_uint(f) | 1u);
+  return bf16_rne(f);
+}
+
+SSI_DEV uint32_t pack2(uint16_t lo, uint16_t hi) { return (uint32_t)lo | ((uint32_t)hi << 16); }
+
+}  // namespace
+
+// C_part[split][i][j] = sum_{k in split} op(A)[i][k] X[k][j]
+//   TA = false: A is M x K (lda);  TA = true: A is K x M (lda), op(A) = A^T.
+//   xt: BF16 planes of X^T, each N_pad x ldx (ldx >= K rounded up to the
+//   tile, zero-padded); plane 1 (NT = 3) holds the rounding remainders.
+//   VEC: lda % 4 == 0 and A 16-byte aligned.
+//   NT = 1: one BF16 product.  NT = 3: split operands a = a_hi + a_lo,
+//   x = x_hi + x_lo (each part BF16) and three products a_hi x_hi + a_hi x_lo
+//   + a_lo x_hi, which carry about 16 significant bits of each operand.
+template <bool TA, bool VEC, int NT>
+__global__ void __launch_bounds__(256, 2)
+gemm_tbf16_mfma(const float *__restrict__ A, int64_t lda, const uint16_t *__restrict__ xt,
+                int64_t ldx, int64_t plane, float *__restrict__ C, int64_t ldc,
+                int64_t split_stride, int M, int N, int K, int k_per_split, int gm, int splits) {
+  constexpr int KT = NT == 1 ? 64 : 32;          // K tile
+  constexpr int LS = KT + 8;                     // LDS row stride (bf16)
+  constexpr int NP = NT == 1 ? 1 : 2;            // operand planes
+  constexpr int AV = KT / 16;                    // float4 of A per thread
+  constexpr int BC = (bBN * KT / 8 + 255) / 256; // 16-byte chunks of B per thread and plane
+  __shared__ __attribute__((aligned(16))) uint16_t As[NP][bBM * LS];
+  __shared__ __attribute__((aligned(16))) uint16_t Bs[NP][bBN * LS];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wr = wave & 1, wc = wave >> 1;
+  const int split = blockIdx.x % splits;
+  const int rest = blockIdx.x / splits;
+  const int m0 = (rest % gm) * bBM, n0 = (rest / gm) * bBN;
+  const int kb = split * k_per_split;
+  const int ke = min(K, kb + k_per_split);
+
+  f32x4 acc[2][7];
+#pragma unroll
+  for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+    for (int ct = 0; ct < 7; ++ct) acc[rt][ct] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+  float4 ra[AV];
+  uint4 rb[NP][BC];
+  // Global -> registers for the tile at k0.  A: 64 x KT FP32; rows (or k rows
+  // for TA) beyond the matrix or the slice read a clamped in-range address
+  // and are zeroed.  B: 224 x KT BF16 per plane, always in range.
+  auto load = [&](int k0) {
+#pragma unroll
+    for (int h = 0; h < AV; ++h) {
+      const int idx = tid + 256 * h;
+      if (!TA) {
+        const int r = idx / (KT / 4), c4 = idx % (KT / 4);
+        const int gi = m0 + r, gk = k0 + 4 * c4;
+        const float *p = A + (int64_t)min(gi, M - 1) * lda;
+        float4 v;
+        if (VEC && gk + 3 < ke) {
+          v = *reinterpret_cast<const float4 *>(p + gk);
+        } else {
+          v.x = gk < ke ? p[min(gk, K - 1)] : 0.f;
+          v.y = gk + 1 < ke ? p[min(gk + 1, K - 1)] : 0.f;
+          v.z = gk + 2 < ke ? p[min(gk + 2, K - 1)] : 0.f;
+          v.w = gk + 3 < ke ? p[min(gk + 3, K - 1)] : 0.f;
+        }
+        ra[h] = gi < M ? v : make_float4(0.f, 0.f, 0.f, 0.f);
+      } else {
+        const int r = idx >> 4, c4 = idx & 15;    // k row, 4-column group of i
+        const int gk = k0 + r, gi = m0 + 4 * c4;
+        const float *p = A + (int64_t)min(gk, K - 1) * lda;
+        float4 v;
+        if (VEC && gi + 3 < M) {
+          v = *reinterpret_cast<const float4 *>(p + gi);
+        } else {
+          v.x = gi < M ? p[min(gi, M - 1)] : 0.f;
+          v.y = gi + 1 < M ? p[min(gi + 1, M - 1)] : 0.f;
+          v.z = gi + 2 < M ? p[min(gi + 2, M - 1)] : 0.f;
+          v.w = gi + 3 < M ? p[min(gi + 3, M - 1)] : 0.f;
+        }
+        ra[h] = gk < ke ? v : make_float4(0.f, 0.f, 0.f, 0.f);
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < NP; ++q)
+#pragma unroll
+      for (int h = 0; h < BC; ++h) {
+        const int idx = tid + 256 * h;
+        if (idx < bBN * KT / 8) {
+          const int j = idx / (KT / 8), c8 = idx % (KT / 8);
+          rb[q][h] = *reinterpret_cast<const uint4 *>(xt + q * plane + (int64_t)(n0 + j) * ldx +
+                                                      k0 + 8 * c8);
+        }
+      }
+  };
+  // Registers -> LDS (BF16 planes), A as As[i][k], B as Bs[j][k].
+  auto store = [&]() {
+#pragma unroll
+    for (int h = 0; h < AV; ++h) {
+      const int idx = tid + 256 * h;
+      const float v[4] = {ra[h].x, ra[h].y, ra[h].z, ra[h].w};
+      uint16_t hi[4], lo[4];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        hi[e] = bf16_rne(v[e]);
+        lo[e] = NT == 3 ? bf16_rne(v[e] - __uint_as_float((uint32_t)hi[e] << 16)) : (uint16_t)0;
+      }
+#pragma unroll
+      for (int q = 0; q < NP; ++q) {
+        const uint16_t *w = q == 0 ? hi : lo;
+        if (!TA) {
+          const int r = idx / (KT / 4), c4 = idx % (KT / 4);
+          uint2 u;
+          u.x = pack2(w[0], w[1]);
+          u.y = pack2(w[2], w[3]);
+          *reinterpret_cast<uint2 *>(&As[q][r * LS + 4 * c4]) = u;
+        } else {
+          const int r = idx >> 4, c4 = idx & 15;
+#pragma unroll
+          for (int e = 0; e < 4; ++e) As[q][(4 * c4 + e) * LS + r] = w[e];
+        }
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < NP; ++q)
+#pragma unroll
+      for (int h = 0; h < BC; ++h) {
+        const int idx = tid + 256 * h;
+        if (idx < bBN * KT / 8) {
+          const int j = idx / (KT / 8), c8 = idx % (KT / 8);
+          *reinterpret_cast<uint4 *>(&Bs[q][j * LS + 8 * c8]) = rb[q][h];
+        }
+      }
+  };
+
+  if (kb < ke) load(kb);
+  for (int k0 = kb; k0 < ke; k0 += KT) {
+    __syncthreads();                       // previous tile's LDS reads are done
+    store();
+    __syncthreads();
+    if (k0 + KT < ke) load(k0 + KT);       // next tile in flight during the MFMAs
+#pragma unroll
+    for (int kk = 0; kk < KT; kk += 32) {
+      const int ko = kk + 8 * (lane >> 4);
+      bf16x8 af[NP][2];
+#pragma unroll
+      for (int q = 0; q < NP; ++q)
+#pragma unroll
+        for (int rt = 0; rt < 2; ++rt)
+          af[q][rt] = *reinterpret_cast<const bf16x8 *>(
+              &As[q][(wr * 32 + rt * 16 + (lane & 15)) * LS + ko]);
+#pragma unroll
+      for (int ct = 0; ct < 7; ++ct) {
+        const int brow = (wc * 112 + ct * 16 + (lane & 15)) * LS + ko;
+        const bf16x8 bhi = *reinterpret_cast<const bf16x8 *>(&Bs[0][brow]);
+        if (NT == 3) {
+          const bf16x8 blo = *reinterpret_cast<const bf16x8 *>(&Bs[NP - 1][brow]);
+#pragma unroll
+          for (int rt = 0; rt < 2; ++rt) {
+            acc[rt][ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[NP - 1][rt], bhi, acc[rt][ct], 0, 0, 0);
+            acc[rt][ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[0][rt], blo, acc[rt][ct], 0, 0, 0);
+          }
+        }
+#pragma unroll
+        for (int rt = 0; rt < 2; ++rt)
+          acc[rt][ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[0][rt], bhi, acc[rt][ct], 0, 0, 0);
+      }
+    }
+  }
+
+  // D layout of 16x16 MFMA: lane holds rows 4 (lane/16) + q, column lane%16.
+  float *dst = C + (int64_t)split * split_stride;
+#pragma unroll
+  for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+    for (int ct = 0; ct < 7; ++ct) {
+      const int col = n0 + wc * 112 + ct * 16 + (lane & 15);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int row = m0 + wr * 32 + rt * 16 + 4 * (lane >> 4) + q;
+        if (row < M && col < N) dst[(int64_t)row * ldc + col] = acc[rt][ct][q];
+      }
+    }
+}
+
+// out[i][j] = sum_s part[s][i][j] (FP32 partials summed in FP64, fixed order)
+__global__ void __launch_bounds__(256)
+reduce_splits_f32(const float *__restrict__ part, int splits, int64_t split_stride, int64_t ldp,
+                  int M, int N, double *__restrict__ out, int64_t ldo) {
+  const int64_t total = (int64_t)M * N;
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = idx / N, j = idx - i * N;
+    double s = 0.0;
+    for (int sp = 0; sp < splits; ++sp) s += (double)part[sp * split_stride + i * ldp + j];
+    out[i * ldo + j] = s;
+  }
+}
+
+// xt[j][k] = bf16(x[k][j]) for j < N, k < K; zero in the padding
+// (j < n_pad, k < k_pad).  With a second plane (lo != nullptr) the remainder
+// x - hi is rounded to BF16 there.  64 x 64 tiles through LDS.
+__global__ void __launch_bounds__(256)
+pack_bf16_t(const double *__restrict__ x, int64_t ldx, int K, int N, uint16_t *__restrict__ xt,
+            uint16_t *__restrict__ lo, int64_t ldt, int n_pad, int k_pad) {
+  __shared__ uint16_t tile[2][64][66];
+  const int k0 = blockIdx.x * 64, j0 = blockIdx.y * 64;
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  for (int r = ty; r < 64; r += 4) {          // read rows k of x, columns j
+    const int k = k0 + r, j = j0 + tx;
+    const double v = (k < K && j < N) ? x[(int64_t)k * ldx + j] : 0.0;
+    const uint16_t h = bf16_rne(v);
+    tile[0][r][tx] = h;
+    tile[1][r][tx] = bf16_rne(v - (double)__uint_as_float((uint32_t)h << 16));
+  }
+  __syncthreads();
+  for (int r = ty; r < 64; r += 4) {          // write rows j of xt, columns k
+    const int j = j0 + r, k = k0 + tx;
+    if (j < n_pad && k < k_pad) {
+      xt[(int64_t)j * ldt + k] = tile[0][tx][r];
+      if (lo) lo[(int64_t)j * ldt + k] = tile[1][tx][r];
+    }
+  }
+}
+
+namespace ssi {
+
+namespace {
+int grid_cap_b(int64_t work) {
+  int64_t b = ceil_div<int64_t>(work, 256);
+  return (int)std::max<int64_t>(1, std::min<int64_t>(b, 16384));
+}
+}  // namespace
+
+BfPlan plan_gemm_tbf16(int M, int N, int K, int num_cus, int force_splits, int nt) {
+  BfPlan p{};
+  const int bKT = nt == 3 ? 32 : 64;
+  p.nt = nt;
+  p.gm = ceil_div(M, bBM);
+  p.gn = ceil_div(N, bBN);
+  const int64_t tiles = (int64_t)p.gm * p.gn;
+  int64_t splits = ceil_div<int64_t>((int64_t)num_cus * 2, tiles);
+  splits = std::max<int64_t>(1, std::min<int64_t>(std::min<int64_t>(splits, 8),
+                                                  ceil_div<int64_t>(K, 512)));
+  if (force_splits > 0) splits = std::min<int64_t>(force_splits, ceil_div<int64_t>(K, bKT));
+  int64_t kps = ceil_div<int64_t>(ceil_div<int64_t>(K, splits), bKT) * bKT;
+  p.k_per_split = (int)kps;
+  p.splits = (int)ceil_div<int64_t>(K, kps);
+  p.ldc = N;
+  p.split_stride = (int64_t)M * N;
+  p.n_pad = p.gn * bBN;
+  p.k_pad = (int)(ceil_div<int64_t>(K, 64) * 64);
+  p.ldx = p.k_pad;
+  return p;
+}
+
+hipError_t launch_pack_bf16(const BfPlan &p, const double *x, int64_t ldx, int K, int N,
+                            uint16_t *xt, hipStream_t st) {
+  dim3 grid(ceil_div(p.k_pad, 64), ceil_div(p.n_pad, 64));
+  uint16_t *lo = p.nt == 3 ? xt + p.plane() : nullptr;
+  hipLaunchKernelGGL(pack_bf16_t, grid, dim3(256), 0, st, x, ldx, K, N, xt, lo, p.ldx, p.n_pad,
+                     p.k_pad);
+  return hipGetLastError();
+}
+
+hipError_t launch_gemm_tbf16(const BfPlan &p, bool trans_a, const float *A, int64_t lda,
+                             const uint16_t *xt, int M, int N, int K, float *part,
+                             hipStream_t st) {
+  const bool vec = (lda % 4 == 0) && ((uintptr_t)A % 16 == 0);
+  const dim3 grid((unsigned)((int64_t)p.gm * p.gn * p.splits));
+#define SSI_BF(TA, V, NT)                                                                   \
+  hipLaunchKernelGGL((gemm_tbf16_mfma<TA, V, NT>), grid, dim3(256), 0, st, A, lda, xt, p.ldx, \
+                     (int64_t)p.plane(), part, p.ldc, p.split_stride, M, N, K, p.k_per_split,  \
+                     p.gm, p.splits)
+#define SSI_BF_NT(TA, V) \
+  do { if (p.nt == 3) SSI_BF(TA, V, 3); else SSI_BF(TA, V, 1); } while (0)
+  if (trans_a) {
+    if (vec) SSI_BF_NT(true, true); else SSI_BF_NT(true, false);
+  } else {
+    if (vec) SSI_BF_NT(false, true); else SSI_BF_NT(false, false);
+  }
+#undef SSI_BF_NT
+#undef SSI_BF
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce_f32(const BfPlan &p, const float *part, int M, int N, double *out,
+                             int64_t ldo, hipStream_t st) {
+  hipLaunchKernelGGL(reduce_splits_f32, dim3(grid_cap_b((int64_t)M * N)), dim3(256), 0, st,
+                     part, p.splits, p.split_stride, p.ldc, M, N, out, ldo);
+  return hipGetLastError();
+}
+
+}  // namespace ssi

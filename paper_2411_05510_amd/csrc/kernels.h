@@ -41,7 +41,9 @@ struct GemmPlan {
   int64_t ldc, split_stride;     // partial-sum layout: [splits][M][ldc]
   size_t part_elems() const { return (size_t)splits * (size_t)split_stride; }
 };
-GemmPlan plan_gemm_tf64(int M, int N, int K, int num_cus);
+// splits > 0 forces the number of K slices (autotuning); 0 picks it from the
+// shape and the CU count.
+GemmPlan plan_gemm_tf64(int M, int N, int K, int num_cus, int splits = 0);
 GemmPlan plan_gemm_f64(int M, int N, int K, int num_cus);
 hipError_t launch_gemm_tf64(const GemmPlan &p, bool trans_a, const float *A, int64_t lda,
                             const double *B, int64_t ldb, int M, int N, int K, double *part,
@@ -53,6 +55,26 @@ hipError_t launch_reduce(const GemmPlan &p, const double *part, int M, int N, do
                          double *out, int64_t ldo, float *out32, int64_t ld32, hipStream_t st);
 hipError_t launch_convert(const double *in, int64_t ldi, int M, int N, float *out, int64_t ldo,
                           hipStream_t st);
+
+// ---- reduced-precision range-finder products (gemm_bf16.hip)
+struct BfPlan {
+  int gm, gn, splits, k_per_split;
+  int64_t ldc, split_stride;     // FP32 partial sums: [splits][M][ldc]
+  int n_pad, k_pad;              // BF16 operand X^T: n_pad x k_pad (ld ldx), zero-padded
+  int64_t ldx;
+  int nt;                        // 1: one BF16 product; 3: split (hi + lo) operands
+  size_t part_elems() const { return (size_t)splits * (size_t)split_stride; }
+  size_t plane() const { return (size_t)n_pad * (size_t)ldx; }
+  size_t xt_elems() const { return plane() * (nt == 3 ? 2 : 1); }
+};
+BfPlan plan_gemm_tbf16(int M, int N, int K, int num_cus, int splits = 0, int nt = 1);
+hipError_t launch_pack_bf16(const BfPlan &p, const double *x, int64_t ldx, int K, int N,
+                            uint16_t *xt, hipStream_t st);
+hipError_t launch_gemm_tbf16(const BfPlan &p, bool trans_a, const float *A, int64_t lda,
+                             const uint16_t *xt, int M, int N, int K, float *part,
+                             hipStream_t st);
+hipError_t launch_reduce_f32(const BfPlan &p, const float *part, int M, int N, double *out,
+                             int64_t ldo, hipStream_t st);
 
 hipError_t launch_convert_f32_f64(const float *in, int64_t ldi, int M, int N, double *out,
                                   int64_t ldo, hipStream_t st);
@@ -93,5 +115,18 @@ struct ModalArgs {
   float *phi;
 };
 hipError_t launch_modal(const ModalArgs &a, hipStream_t st);
+
+// ---- stability analysis (stability.hip)
+struct StabilityArgs {
+  int n_lags, n_orders, nmin, step, pole_cap, l;
+  const int32_t *count;
+  const double *f, *xi;
+  const float *phi;
+  double xi_max, mpc_min, mpd_max, alpha_f, alpha_xi, alpha_mac;
+  double *mpc, *mpd;
+  uint8_t *hc;                  // workspace: hard-criteria verdict per slot
+  uint8_t *flags;
+};
+hipError_t launch_stability(const StabilityArgs &a, hipStream_t st);
 
 }  // namespace ssi

@@ -730,6 +730,34 @@ francis_kernel(const double *__restrict__ hbuf, int nmin, int step, int o_first,
       failed = true;
       break;
     }
+    // A trailing block of at most kSM rows is finished by one wave on its own
+    // copy: its eigenvalues do not depend on the rows above it, and the
+    // single-wave iteration needs no workgroup barriers.
+    if (hi - l + 1 <= kSM) {
+      const int mb = hi - l + 1;
+      for (int idx = t; idx < kSM * kSM; idx += kFT) {
+        const int i = idx / kSM, j = idx - i * kSM;
+        sblk[idx] = (i < mb && j < mb && j >= i - 1) ? A[ix(l + i, l + j)] : 0.0;
+      }
+      __syncthreads();
+      if (wave == 0) {
+        const bool ok = small_eig(sblk, mb, sev, sev + kSM, lane);
+        if (lane == 0) {
+          small_ok = ok ? 1 : 0;
+          if (ok)
+            for (int i = 0; i < mb; ++i) {
+              wr[l + i] = sev[i];
+              wi[l + i] = sev[kSM + i];
+            }
+        }
+      }
+      __syncthreads();
+      if (small_ok) {
+        hi = l - 1;
+        iter = 0;
+        continue;
+      }
+    }
     ++iter;
     // ---- shifts
     int nb = 1;

@@ -3,11 +3,12 @@
 // with R_j stored at r_stack[(j - 1) l l + a l + b].
 //
 // A pure HBM write stream (m^2 floats) whose source, the 2 jb - 1 blocks of R,
-// stays in L2 / Infinity Cache.  Each thread writes 16 consecutive floats of
-// one row as four 16-byte stores; consecutive threads cover consecutive
-// column segments, so every wave writes one contiguous 1 KiB run.  The vector
-// path needs l, ldt and both pointers 16-byte aligned; otherwise a scalar path
-// is used.
+// stays in L2 / Infinity Cache.  A workgroup covers 4096 floats of one row;
+// in each of its four 16-byte store instructions the lanes of a wave write
+// consecutive float4s, so every store instruction of a wave is one contiguous
+// 1 KiB run of full cache lines.  The vector path needs l, ldt and both
+// pointers 16-byte aligned (a float4 then never straddles two blocks);
+// otherwise a scalar path is used.
 #include "common.h"
 #include "kernels.h"
 
@@ -26,22 +27,17 @@ toeplitz_vec4(const float *__restrict__ r, int l, int jb, float *__restrict__ t,
   const int row = blockIdx.x / blocks_per_row;
   const int cblk = blockIdx.x - row * blocks_per_row;
   const int rb = row / l, a = row - rb * l;
-  // First column of this thread's 16-float run.
-  const int x0 = cblk * kFloatsPerBlock + threadIdx.x * (kVecPerThread * 4);
-  if (x0 >= m) return;
-  int cb = x0 / l;
-  int b = x0 - cb * l;
   const float *rrow = r + (int64_t)a * l;       // row a of every block
-  float *dst = t + (int64_t)row * ldt + x0;
+  float *dst = t + (int64_t)row * ldt;
 #pragma unroll
   for (int v = 0; v < kVecPerThread; ++v) {
-    if (x0 + 4 * v < m) {
+    const int x = cblk * kFloatsPerBlock + (v * kThreads + (int)threadIdx.x) * 4;
+    if (x < m) {
+      const int cb = x / l, b = x - cb * l;
       const int blk = jb + rb - cb - 1;          // R_{jb + r - c} -> index j - 1
       const float4 val = *reinterpret_cast<const float4 *>(rrow + (int64_t)blk * l * l + b);
-      *reinterpret_cast<float4 *>(dst + 4 * v) = val;
+      *reinterpret_cast<float4 *>(dst + x) = val;
     }
-    b += 4;
-    if (b >= l) { b -= l; ++cb; }
   }
 }
 

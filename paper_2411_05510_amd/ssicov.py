@@ -18,8 +18,9 @@ from typing import List, Optional, Sequence
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libssicov.so")
 
-SSI_OK, SSI_EINVAL, SSI_ENOMEM, SSI_EDEVICE, SSI_ENOCONV, SSI_EINTERNAL = range(6)
+SSI_OK, SSI_EINVAL, SSI_ENOMEM, SSI_EDEVICE, SSI_ENOCONV, SSI_EINTERNAL, SSI_EBUSY = range(7)
 SVD_FULL, SVD_RANDOMIZED = 0, 1
+PREC_FP32, PREC_BF16, PREC_BF16X3 = 0, 1, 2
 
 # Every symbol include/ssicov.h declares.
 EXPORTED = (
@@ -28,8 +29,13 @@ EXPORTED = (
     "ssi_tau", "ssi_lag_rule", "ssi_default_rank", "ssi_status_string",
     "ssi_last_error", "ssi_identify", "ssi_correlate", "ssi_toeplitz",
     "ssi_sketch", "ssi_rsvd", "ssi_svd_full", "ssi_modal", "ssi_set_profiling",
-    "ssi_profile_read",
+    "ssi_profile_read", "ssi_set_lag_streams", "ssi_set_graphs", "ssi_set_autotune",
+    "ssi_tuned_splits", "ssi_footprint", "ssi_server_create", "ssi_server_destroy",
+    "ssi_server_submit", "ssi_server_poll", "ssi_server_wait", "ssi_server_result",
+    "ssi_server_release", "ssi_server_get_stats", "ssi_server_last_error", "ssi_stability",
 )
+
+POLE_HC, POLE_STABLE_ORDER, POLE_STABLE_LAG, POLE_STABLE = 1, 2, 4, 8
 
 STAGES = ("corr_mfma", "corr_reduce", "toeplitz", "sketch", "products", "orth",
           "small_svd", "shift_ls", "eig")
@@ -54,12 +60,43 @@ class _Params(ctypes.Structure):
         ("oversample", ctypes.c_int32),
         ("power_iters", ctypes.c_int32),
         ("seed", ctypes.c_uint64),
+        ("prec", ctypes.c_int32),
     ]
 
 
 class _Layout(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int32) for n in
                 ("n_lags", "n_orders", "sigma_per_lag", "pole_cap", "l", "n_corr")]
+
+
+class _StabilityParams(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_double) for n in
+                ("xi_max", "mpc_min", "mpd_max", "alpha_f", "alpha_xi", "alpha_mac")]
+
+
+class _ServerConfig(ctypes.Structure):
+    _fields_ = [("device", ctypes.c_int32), ("max_inflight", ctypes.c_int32),
+                ("hbm_budget", ctypes.c_size_t)]
+
+
+class _RequestInfo(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int), ("slot", ctypes.c_int32),
+                ("t_submit_us", ctypes.c_double), ("t_start_us", ctypes.c_double),
+                ("t_done_us", ctypes.c_double), ("footprint", ctypes.c_size_t)]
+
+
+class _HostResult(ctypes.Structure):
+    _fields_ = [("layout", _Layout), ("sigma", ctypes.c_void_p), ("count", ctypes.c_void_p),
+                ("f", ctypes.c_void_p), ("xi", ctypes.c_void_p), ("mu", ctypes.c_void_p),
+                ("phi", ctypes.c_void_p), ("flags", ctypes.c_void_p)]
+
+
+class _ServerStats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_uint64), ("completed", ctypes.c_uint64),
+                ("failed", ctypes.c_uint64), ("queued", ctypes.c_int32),
+                ("running", ctypes.c_int32), ("peak_inflight", ctypes.c_int32),
+                ("peak_bytes", ctypes.c_uint64), ("held_bytes", ctypes.c_uint64),
+                ("budget", ctypes.c_uint64)]
 
 
 class _Output(ctypes.Structure):
@@ -98,13 +135,31 @@ def lib() -> ctypes.CDLL:
             "ssi_correlate": ([vp, vp, i32, i64, i64, i32, vp], ctypes.c_int),
             "ssi_toeplitz": ([vp, vp, i32, i32, vp, i64], ctypes.c_int),
             "ssi_sketch": ([vp, u64, u32, i64, i32, vp, i64], ctypes.c_int),
-            "ssi_rsvd": ([vp, vp, i64, i64, i32, i32, i32, vp, u64, u32, vp, vp], ctypes.c_int),
+            "ssi_rsvd": ([vp, vp, i64, i64, i32, i32, i32, i32, vp, u64, u32, vp, vp], ctypes.c_int),
             "ssi_svd_full": ([vp, vp, i64, i64, i32, vp, vp], ctypes.c_int),
             "ssi_modal": ([vp, vp, vp, i64, i32, i32, P, i32, ctypes.POINTER(_Output)],
                           ctypes.c_int),
             "ssi_set_profiling": ([vp, ctypes.c_int], ctypes.c_int),
             "ssi_profile_read": ([vp, ctypes.POINTER(ctypes.c_double),
                                   ctypes.POINTER(ctypes.c_int32), i32], ctypes.c_int),
+            "ssi_set_lag_streams": ([vp, i32], ctypes.c_int),
+            "ssi_set_graphs": ([vp, ctypes.c_int], ctypes.c_int),
+            "ssi_set_autotune": ([vp, ctypes.c_int], ctypes.c_int),
+            "ssi_tuned_splits": ([vp, i32, i32, i32, i32, i32], i32),
+            "ssi_footprint": ([P, i32, i64, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
+            "ssi_server_create": ([ctypes.POINTER(_ServerConfig), ctypes.POINTER(vp)],
+                                  ctypes.c_int),
+            "ssi_server_destroy": ([vp], None),
+            "ssi_server_submit": ([vp, vp, i32, i64, i64, P, ctypes.POINTER(u64)], ctypes.c_int),
+            "ssi_server_poll": ([vp, u64, ctypes.POINTER(_RequestInfo)], ctypes.c_int),
+            "ssi_server_wait": ([vp, u64, ctypes.POINTER(_RequestInfo)], ctypes.c_int),
+            "ssi_server_result": ([vp, u64, ctypes.POINTER(ctypes.POINTER(_HostResult))],
+                                  ctypes.c_int),
+            "ssi_server_release": ([vp, u64], ctypes.c_int),
+            "ssi_server_get_stats": ([vp, ctypes.POINTER(_ServerStats)], ctypes.c_int),
+            "ssi_server_last_error": ([], ctypes.c_char_p),
+            "ssi_stability": ([vp, P, i32, ctypes.POINTER(_Output),
+                               ctypes.POINTER(_StabilityParams), vp, vp, vp], ctypes.c_int),
         }
         for name, (args, res) in sig.items():
             fn = getattr(L, name)
@@ -117,6 +172,11 @@ def lib() -> ctypes.CDLL:
 def _check(status: int) -> None:
     if status != SSI_OK:
         raise SSIError(status, lib().ssi_last_error().decode())
+
+
+def _check_srv(status: int) -> None:
+    if status != SSI_OK:
+        raise SSIError(status, lib().ssi_server_last_error().decode())
 
 
 # ------------------------------------------------------------ parameters
@@ -133,13 +193,14 @@ class Params:
     oversample: int = 0
     power_iters: int = 0
     seed: int = 0
+    prec: int = PREC_FP32
 
     def c(self) -> _Params:
         arr = (ctypes.c_int32 * len(self.lags))(*[int(v) for v in self.lags])
         p = _Params(float(self.fs), arr, len(self.lags), int(self.order_min),
                     int(self.order_max), int(self.order_step), int(self.svd),
                     int(self.rank), int(self.oversample), int(self.power_iters),
-                    int(self.seed) & 0xFFFFFFFFFFFFFFFF)
+                    int(self.seed) & 0xFFFFFFFFFFFFFFFF, int(self.prec))
         p._keep = arr  # keep the lag array alive with the struct
         return p
 
@@ -169,6 +230,14 @@ def workspace_estimate(p: Params, l: int, n: int) -> int:
     cp = p.c()
     out = ctypes.c_size_t()
     _check(lib().ssi_workspace_estimate(ctypes.byref(cp), l, n, ctypes.byref(out)))
+    return int(out.value)
+
+
+def footprint(p: Params, l: int, n: int) -> int:
+    """Device bytes one identification of these sizes holds (admission)."""
+    cp = p.c()
+    out = ctypes.c_size_t()
+    _check(lib().ssi_footprint(ctypes.byref(cp), l, n, ctypes.byref(out)))
     return int(out.value)
 
 
@@ -224,6 +293,18 @@ class Context:
     def set_profiling(self, enable: bool) -> None:
         _check(lib().ssi_set_profiling(self._h, 1 if enable else 0))
 
+    def set_lag_streams(self, n: int) -> None:
+        _check(lib().ssi_set_lag_streams(self._h, n))
+
+    def set_graphs(self, enable: bool) -> None:
+        _check(lib().ssi_set_graphs(self._h, 1 if enable else 0))
+
+    def set_autotune(self, enable: bool) -> None:
+        _check(lib().ssi_set_autotune(self._h, 1 if enable else 0))
+
+    def tuned_splits(self, kind: int, trans: bool, m: int, n: int, k: int) -> int:
+        return int(lib().ssi_tuned_splits(self._h, kind, 1 if trans else 0, m, n, k))
+
     def profile_read(self) -> dict:
         """{stage: (total ms, calls)} accumulated since the last read."""
         n = len(STAGES)
@@ -261,14 +342,15 @@ class Context:
                                 out.stride(0)))
         return out
 
-    def rsvd(self, t, k: int, p: int, q: int, omega=None, seed: int = 0, stream: int = 0):
+    def rsvd(self, t, k: int, p: int, q: int, omega=None, seed: int = 0, stream: int = 0,
+             prec: int = PREC_FP32):
         """(U (m, k) float64, sigma (k,) float64) of the device matrix t (m, ldt) float32."""
         import torch
         m = t.shape[0]
         u = torch.empty((m, k), dtype=torch.float64, device=t.device)
         s = torch.empty((k,), dtype=torch.float64, device=t.device)
         om = _ptr(omega) if omega is not None else None
-        _check(lib().ssi_rsvd(self._h, _ptr(t), m, t.stride(0), k, p, q, om,
+        _check(lib().ssi_rsvd(self._h, _ptr(t), m, t.stride(0), k, p, q, prec, om,
                               seed & 0xFFFFFFFFFFFFFFFF, stream, _ptr(u), _ptr(s)))
         return u, s
 
@@ -279,6 +361,24 @@ class Context:
         s = torch.empty((k,), dtype=torch.float64, device=t.device)
         _check(lib().ssi_svd_full(self._h, _ptr(t), m, t.stride(0), k, _ptr(u), _ptr(s)))
         return u, s
+
+    def stability(self, out: "Output", l: int, xi_max: float = 0.10, mpc_min: float = 0.60,
+                  mpd_max: float = 0.50, alpha_f: float = 0.01, alpha_xi: float = 0.03,
+                  alpha_mac: float = 0.02):
+        """(mpc, mpd, flags) device tensors [n_lags, pole_cap] of the poles in out."""
+        import torch
+        lay = out.layout
+        shape = (lay["n_lags"], lay["pole_cap"])
+        dev = out.f.device
+        mpc = torch.zeros(shape, dtype=torch.float64, device=dev)
+        mpd = torch.zeros(shape, dtype=torch.float64, device=dev)
+        flags = torch.zeros(shape, dtype=torch.uint8, device=dev)
+        cp = out.params.c()
+        co = out.c()
+        sp = _StabilityParams(xi_max, mpc_min, mpd_max, alpha_f, alpha_xi, alpha_mac)
+        _check(lib().ssi_stability(self._h, ctypes.byref(cp), l, ctypes.byref(co),
+                                   ctypes.byref(sp), _ptr(mpc), _ptr(mpd), _ptr(flags)))
+        return mpc, mpd, flags
 
     # --------------------------------------------------- identification
     def alloc_output(self, p: Params, l: int, n: int) -> "Output":
@@ -349,3 +449,90 @@ class Output:
             "phi": phi[..., 0] + 1j * phi[..., 1],
             "flag": int(self.flags[lag_index, order_index].item()),
         }
+
+
+# --------------------------------------------------------------- serving
+class Server:
+    """Continuous-batching identification server (ssi_server_* in the header).
+
+    submit() copies the host record and returns a ticket at once; the
+    library's dispatcher admits requests to GPU slots as slots and device
+    memory free up."""
+
+    def __init__(self, device: int = 0, max_inflight: int = 8, hbm_budget: int = 0):
+        cfg = _ServerConfig(device, max_inflight, hbm_budget)
+        h = ctypes.c_void_p()
+        _check_srv(lib().ssi_server_create(ctypes.byref(cfg), ctypes.byref(h)))
+        self._h = h
+
+    def close(self) -> None:
+        if getattr(self, "_h", None):
+            lib().ssi_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):  # pragma: no cover
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def submit(self, y: np.ndarray, p: Params) -> int:
+        y = np.ascontiguousarray(y, dtype=np.float32)
+        l, n = y.shape
+        cp = p.c()
+        t = ctypes.c_uint64()
+        _check_srv(lib().ssi_server_submit(self._h, y.ctypes.data, l, n, n, ctypes.byref(cp),
+                                           ctypes.byref(t)))
+        return int(t.value)
+
+    @staticmethod
+    def _info(inf: _RequestInfo) -> dict:
+        return {"status": inf.status, "slot": inf.slot, "t_submit_us": inf.t_submit_us,
+                "t_start_us": inf.t_start_us, "t_done_us": inf.t_done_us,
+                "footprint": int(inf.footprint)}
+
+    def poll(self, ticket: int):
+        """Request info if finished, else None."""
+        inf = _RequestInfo()
+        st = lib().ssi_server_poll(self._h, ticket, ctypes.byref(inf))
+        if st == SSI_EBUSY:
+            return None
+        _check_srv(st)
+        return self._info(inf)
+
+    def wait(self, ticket: int) -> dict:
+        inf = _RequestInfo()
+        _check_srv(lib().ssi_server_wait(self._h, ticket, ctypes.byref(inf)))
+        return self._info(inf)
+
+    def result(self, ticket: int) -> dict:
+        """Host copies (numpy) of a finished request's outputs."""
+        rp = ctypes.POINTER(_HostResult)()
+        _check_srv(lib().ssi_server_result(self._h, ticket, ctypes.byref(rp)))
+        r = rp.contents
+        lay = {name: getattr(r.layout, name) for name, _ in _Layout._fields_}
+        nl, no, cap, l = lay["n_lags"], lay["n_orders"], lay["pole_cap"], lay["l"]
+
+        def arr(ptr, ctype, shape):
+            n = int(np.prod(shape))
+            buf = ctypes.cast(ptr, ctypes.POINTER(ctype * n)).contents
+            return np.frombuffer(buf, dtype=np.dtype(ctype)).reshape(shape).copy()
+
+        return {
+            "layout": lay,
+            "sigma": arr(r.sigma, ctypes.c_double, (nl, lay["sigma_per_lag"])),
+            "count": arr(r.count, ctypes.c_int32, (nl, no)),
+            "f": arr(r.f, ctypes.c_double, (nl, cap)),
+            "xi": arr(r.xi, ctypes.c_double, (nl, cap)),
+            "mu": arr(r.mu, ctypes.c_double, (nl, cap, 2)),
+            "phi": arr(r.phi, ctypes.c_float, (nl, cap, l, 2)),
+            "flags": arr(r.flags, ctypes.c_int32, (nl, no)),
+        }
+
+    def release(self, ticket: int) -> None:
+        _check_srv(lib().ssi_server_release(self._h, ticket))
+
+    def stats(self) -> dict:
+        st = _ServerStats()
+        _check_srv(lib().ssi_server_get_stats(self._h, ctypes.byref(st)))
+        return {name: int(getattr(st, name)) for name, _ in _ServerStats._fields_}

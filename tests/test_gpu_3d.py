@@ -1,0 +1,194 @@
+"""GPU tests of the 3D stabilization-diagram sweep (Section 2.3, step i):
+several lags on concurrent streams, the whole sweep captured as one HIP graph,
+and the autotuned range-finder products.
+
+* lag streams: outputs bit-identical to the single-stream sweep;
+* graphs: every replay (with eager work and synchronizations between
+  replays, and a new record written into the same input buffer) equals the
+  eager identification of the record it saw, bit for bit;
+* autotuning: a tuned slice count is recorded and the poles agree with the
+  untuned run to FP64 summation-order rounding;
+* the 180-channel record over lags 20..100 step 10 (Toeplitz up to
+  18000 x 18000) in one graph on three lag streams: the smallest and the
+  largest lag against the FP64 checker at the FP32 gates.
+"""
+import dataclasses
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2411_05510_amd import synth
+from modelref import mac
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def _ctx():
+    from paper_2411_05510_amd import ssicov
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return ssicov.Context(0)
+
+
+MID = synth.Workload(name="mid3d", l=60, n=30000, fs=100.0, n_modes=8, f_range=(0.5, 20.0),
+                     zeta_range=(0.005, 0.03), noise=0.05, lags=(12, 16, 20, 24),
+                     svd="randomized", rank=60, oversample=10, power_iters=2, order_min=2,
+                     order_max=60, order_step=2, struct_seed=91, noise_seed=92, sketch_seed=93)
+
+
+def _params(wl, **kw):
+    from paper_2411_05510_amd import ssicov
+    d = dict(fs=wl.fs, lags=list(wl.lags), order_min=wl.order_min, order_max=wl.order_max,
+             order_step=wl.order_step, svd=ssicov.SVD_RANDOMIZED, rank=wl.rank,
+             oversample=wl.oversample, power_iters=wl.power_iters, seed=wl.sketch_seed)
+    d.update(kw)
+    return ssicov.Params(**d)
+
+
+FIELDS = ("sigma", "count", "f", "xi", "mu", "phi", "flags")
+
+
+def _snapshot(out):
+    return {k: getattr(out, k).clone() for k in FIELDS}
+
+
+def _assert_equal(a, b):
+    for k in FIELDS:
+        assert torch.equal(a[k], b[k]), f"{k} differs"
+
+
+def test_lag_streams_match_single_stream():
+    ctx = _ctx()
+    _, y = synth.make_record(MID)
+    yd = _dev(y)
+    p = _params(MID)
+    ref = _snapshot(ctx.identify(yd, p))
+    ctx.synchronize()
+    ref = _snapshot(ctx.identify(yd, p))
+    for n in (2, 3, 4):
+        ctx.set_lag_streams(n)
+        out = ctx.identify(yd, p)
+        ctx.synchronize()
+        _assert_equal(_snapshot(out), ref)
+    ctx.close()
+
+
+def test_graph_replays_match_eager():
+    from paper_2411_05510_amd import ssicov
+    ctx = _ctx()
+    _, y1 = synth.make_record(MID)
+    _, y2 = synth.make_record(dataclasses.replace(MID, noise_seed=MID.noise_seed + 1))
+    p = _params(MID)
+    # eager references for both records
+    eager = ssicov.Context(0)
+    refs = []
+    for y in (y1, y2):
+        o = eager.identify(_dev(y), p)
+        eager.synchronize()
+        refs.append(_snapshot(o))
+    eager.close()
+    assert not torch.equal(refs[0]["f"], refs[1]["f"])
+
+    ctx.set_lag_streams(2)
+    ctx.set_graphs(True)
+    yd = _dev(y1)
+    out = ctx.alloc_output(p, MID.l, MID.n)
+    for rep, which in enumerate((0, 0, 1, 0, 1)):
+        yd.copy_(_dev((y1, y2)[which]))
+        for k in FIELDS:                          # stale results must be overwritten
+            getattr(out, k).zero_()
+        torch.cuda.synchronize()
+        ctx.identify(yd, p, out)
+        ctx.synchronize()
+        _assert_equal(_snapshot(out), refs[which])
+        junk = torch.randn(1 << 20, device="cuda")  # eager work between replays
+        junk.mul_(2.0).sum().item()
+    ctx.set_graphs(False)
+    ctx.close()
+
+
+def test_autotune_records_choice():
+    ctx = _ctx()
+    _, y = synth.make_record(MID)
+    yd = _dev(y)
+    p = _params(MID)
+    ref = ctx.identify(yd, p)
+    ctx.synchronize()
+    ref = _snapshot(ref)
+    ctx.set_autotune(True)
+    out = ctx.identify(yd, p)
+    ctx.synchronize()
+    m = MID.lags[-1] * MID.l
+    ell = MID.rank + MID.oversample
+    assert ctx.tuned_splits(0, False, m, ell, m) in (2, 4, 6, 8, 12, 16)
+    assert ctx.tuned_splits(0, True, m, ell, m) in (2, 4, 6, 8, 12, 16)
+    got = _snapshot(out)
+    assert torch.equal(got["count"], ref["count"])
+    np.testing.assert_allclose(got["sigma"].cpu().numpy(), ref["sigma"].cpu().numpy(), rtol=1e-10)
+    np.testing.assert_allclose(got["f"].cpu().numpy(), ref["f"].cpu().numpy(), rtol=1e-7)
+    ctx.close()
+
+
+def test_bridge_3d_sweep_graph():
+    """lags 20..100 step 10 of the 180-channel record in one graph on three
+    lag streams; lags 20 and 100 against the checker (physical poles, FP32
+    gates)."""
+    wl = synth.WORKLOADS["bridge-180ch-3d"]
+    sysm, y = synth.make_record(wl)
+    ctx = _ctx()
+    ctx.set_lag_streams(3)
+    ctx.set_graphs(True)
+    p = _params(wl)
+    yd = _dev(y)
+    out = ctx.alloc_output(p, wl.l, wl.n)
+    ctx.identify(yd, p, out)        # eager + capture
+    ctx.synchronize()
+    first = _snapshot(out)
+    for k in FIELDS:
+        getattr(out, k).zero_()
+    ctx.identify(yd, p, out)        # graph launch
+    ctx.synchronize()
+    _assert_equal(_snapshot(out), first)
+    ctx.set_graphs(False)
+    ctx.close()
+
+    r_stack = oracle.correlations(y, 2 * wl.lags[-1] - 1)
+    ell = wl.rank + wl.oversample
+    worst = {"f": 0.0, "xi": 0.0, "mac": 1.0, "n": 0}
+    for li in (0, len(wl.lags) - 1):
+        jb = wl.lags[li]
+        t = oracle.toeplitz(r_stack, jb)
+        u, s = oracle.rsvd(t, wl.rank, wl.oversample, wl.power_iters,
+                           oracle.sketch(wl.sketch_seed, t.shape[0], ell, li))
+        del t
+        res = oracle.modal(u, s, wl.l, wl.orders, wl.fs)
+        sig = out.sigma[li].cpu().numpy()
+        keep = s >= 1e-3 * s[0]
+        assert (np.abs(sig[keep] - s[keep]) / s[keep]).max() <= 1e-4
+        for oi, ref in enumerate(res):
+            g = out.poles(li, oi)
+            assert g["flag"] == 0
+            for r, fr in enumerate(sysm.freqs):
+                if len(ref) == 0:
+                    continue
+                i = int(np.argmin(np.abs(ref.f - fr)))
+                if abs(ref.f[i] - fr) / fr >= 0.01 or mac(ref.phi[i], sysm.shapes[:, r]) < 0.9:
+                    continue
+                j = int(np.argmin(np.abs(g["f"] - ref.f[i])))
+                worst["f"] = max(worst["f"], abs(g["f"][j] - ref.f[i]) / ref.f[i])
+                worst["xi"] = max(worst["xi"], abs(g["xi"][j] - ref.xi[i]))
+                worst["mac"] = min(worst["mac"], mac(g["phi"][j], ref.phi[i]))
+                worst["n"] += 1
+    print(f"bridge 3D lags 20 and 100: {worst['n']} physical poles, max f rel "
+          f"{worst['f']:.2e}, max xi abs {worst['xi']:.2e}, min MAC {worst['mac']:.8f}")
+    assert worst["n"] > 0
+    assert worst["f"] <= 1e-5
+    assert worst["xi"] <= 1e-4
+    assert worst["mac"] >= 0.9999

@@ -1,0 +1,132 @@
+"""GPU parity of the reduced-precision (BF16) range finder.
+
+The sketch and power-iteration products round T and X to BF16 (nearest
+even) and accumulate in FP32; the projection, every orthonormalization and
+everything after stay FP64.  Gates:
+
+* operands that BF16 represents exactly and sums that FP32 holds exactly
+  (small integers): the BF16 products are exact, so with q = 0 the whole
+  randomized SVD equals the FP64 checker's to FP64 rounding;
+* general inputs: singular values within 1e-3 relative of the checker for
+  sigma_i >= 1e-2 sigma_1 (BF16 keeps 8 significant bits, a relative
+  rounding of 2^-9 per operand; the exact projection turns that into a
+  perturbation of the basis only), and the leading subspace within the
+  same error scaled by the inverse relative gap;
+* the whole identification of the 180-channel record: physical poles within
+  f rel 1e-3, damping abs 2e-3 and MAC 0.99 of the FP64 checker.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2411_05510_amd import synth
+from modelref import mac
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_2411_05510_amd import ssicov
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    c = ssicov.Context(0)
+    yield c
+    c.close()
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def _rsvd_bf16(ctx, t32, k, p, q, omega=None, seed=7, pad=0):
+    from paper_2411_05510_amd import ssicov
+    m = t32.shape[0]
+    tt = np.zeros((m, m + pad), dtype=np.float32)
+    tt[:, :m] = t32
+    om = _dev(omega) if omega is not None else None
+    u, s = ctx.rsvd(_dev(tt), k, p, q, omega=om, seed=seed, prec=ssicov.PREC_BF16)
+    ctx.synchronize()
+    return u.cpu().numpy(), s.cpu().numpy()
+
+
+@pytest.mark.parametrize("m,k,p,pad", [(701, 30, 7, 3), (640, 48, 16, 0), (97, 20, 5, 1),
+                                       (1500, 200, 20, 2)])
+def test_rsvd_bf16_exact_operands(ctx, m, k, p, pad):
+    """Integer T (|t| <= 128) and integer Omega (|w| <= 4): BF16 holds every
+    operand and FP32 every partial sum, so Y = T Omega is exact and with q = 0
+    the result equals the checker's randomized SVD to FP64 rounding.  Ragged
+    m, ell and leading dimensions cover the unaligned loads and the tails."""
+    rng = np.random.Generator(np.random.PCG64(m + 17 * k))
+    t32 = rng.integers(-128, 129, size=(m, m)).astype(np.float32)
+    om = rng.integers(-4, 5, size=(m, k + p)).astype(np.float32)
+    u, s = _rsvd_bf16(ctx, t32, k, p, 0, omega=om, pad=pad)
+    ur, sr = oracle.rsvd(t32.astype(np.float64), k, p, 0, om.astype(np.float64))
+    np.testing.assert_allclose(s, sr, rtol=1e-10)
+    # same left singular vectors up to sign where the spectrum is separated
+    gaps = np.abs(np.diff(sr)) / sr[0]
+    for i in range(k - 1):
+        if gaps[i] > 1e-3 and (i == 0 or gaps[i - 1] > 1e-3):
+            assert abs(abs(u[:, i] @ ur[:, i]) - 1.0) < 1e-8
+
+
+@pytest.mark.parametrize("m,k,p,q,pad,decay", [(701, 30, 7, 2, 3, 0.8), (1200, 60, 12, 1, 0, 0.9),
+                                               (330, 40, 9, 3, 1, 0.8)])
+def test_rsvd_bf16_accuracy(ctx, m, k, p, q, pad, decay):
+    """Low rank plus noise, Philox sketch, power iterations through both
+    product orientations (T X and T^T X)."""
+    t32 = synth.random_lowrank(m, m, k, seed=m + k, decay=decay, noise=1e-5)
+    u, s = _rsvd_bf16(ctx, t32, k, p, q, seed=11, pad=pad)
+    ur, sr = oracle.rsvd(t32.astype(np.float64), k, p, q, oracle.sketch(11, m, k + p, 0))
+    keep = sr >= 1e-2 * sr[0]
+    rel = np.abs(s[keep] - sr[keep]) / sr[keep]
+    assert rel.max() <= 1e-3, f"max sigma rel err {rel.max():.3e}"
+    assert np.abs(u.T @ u - np.eye(k)).max() < 1e-8
+    c = k // 2
+    rel_gap = (sr[c - 1] - sr[c]) / sr[0]
+    gap = np.linalg.norm(u[:, :c] - ur[:, :c] @ (ur[:, :c].T @ u[:, :c]), 2)
+    assert gap <= 1e-3 / min(1.0, rel_gap), f"subspace gap {gap:.3e}"
+
+
+def test_identify_bridge_bf16(ctx):
+    """The 180-channel record with BF16 range-finder products: every physical
+    pole of the FP64 checker (same record, same Philox sketch) within the
+    reduced-precision gates."""
+    from paper_2411_05510_amd import ssicov
+    wl = synth.WORKLOADS["bridge-180ch"]
+    sysm, y = synth.make_record(wl)
+    p = ssicov.Params(fs=wl.fs, lags=list(wl.lags), order_min=wl.order_min,
+                      order_max=wl.order_max, order_step=wl.order_step,
+                      svd=ssicov.SVD_RANDOMIZED, rank=wl.rank, oversample=wl.oversample,
+                      power_iters=wl.power_iters, seed=wl.sketch_seed, prec=ssicov.PREC_BF16)
+    out = ctx.identify(_dev(y), p)
+    ctx.synchronize()
+    res = oracle.identify(y, wl.fs, wl.lags, wl.orders, svd="randomized", rank=wl.rank,
+                          oversample=wl.oversample, power_iters=wl.power_iters,
+                          seed=wl.sketch_seed)[0]
+    sig = out.sigma[0].cpu().numpy()
+    keep = res.sigma >= 1e-2 * res.sigma[0]
+    srel = np.abs(sig[keep] - res.sigma[keep]) / res.sigma[keep]
+    ef, ex, em = [], [], []
+    for oi in range(len(wl.orders)):
+        ref = res.poles[oi]
+        g = out.poles(0, oi)
+        assert g["flag"] == 0
+        for r, fr in enumerate(sysm.freqs):
+            if len(ref) == 0:
+                continue
+            i = int(np.argmin(np.abs(ref.f - fr)))
+            if abs(ref.f[i] - fr) / fr >= 0.01 or mac(ref.phi[i], sysm.shapes[:, r]) < 0.9:
+                continue
+            j = int(np.argmin(np.abs(g["f"] - ref.f[i])))
+            ef.append(abs(g["f"][j] - ref.f[i]) / ref.f[i])
+            ex.append(abs(g["xi"][j] - ref.xi[i]))
+            em.append(mac(g["phi"][j], ref.phi[i]))
+    assert ef, "no physical poles compared"
+    print(f"bridge BF16: sigma rel max {srel.max():.2e}; {len(ef)} physical poles, "
+          f"max f rel {max(ef):.2e}, max xi abs {max(ex):.2e}, min MAC {min(em):.6f}")
+    assert max(ef) <= 1e-3
+    assert max(ex) <= 2e-3
+    assert min(em) >= 0.99
