@@ -1,17 +1,27 @@
 """Benchmark: SSI-COV identifications per second on one MI355X.
 
-One step is one whole identification of a 180-channel, 30-minute record at
-100 Hz (N = 180000 samples) with time-lag step j_b = 60 (a 10800 x 10800
-block-Toeplitz matrix), randomized SVD with k = 200, p = 20, q = 2, and model
-orders 2..200 step 2: correlations, Toeplitz assembly, sketch, range finder
-with power iterations, small SVD, shift least squares and eigen-analysis for
-all 100 orders, poles sorted per order.  The record is resident in HBM before
-timing starts; results stay on the device.
+Default workload (the headline): one step is one whole identification of a
+180-channel, 30-minute record at 100 Hz (N = 180000 samples) with time-lag
+step j_b = 60 (a 10800 x 10800 block-Toeplitz matrix), randomized SVD with
+k = 200, p = 20, q = 2, and model orders 2..200 step 2: correlations,
+Toeplitz assembly, sketch, range finder with power iterations, small SVD,
+shift least squares and eigen-analysis for all 100 orders, poles sorted per
+order.  The record is resident in HBM before timing starts; results stay on
+the device.  Prints one JSON line with the throughput, per-step latency
+percentiles, the roofline of the dominant kernel (the correlation contraction
+on FP32 MFMA) measured live with HIP events on its stream, per-stage times
+and the FP64 CPU checker timed on the host for one identification of the
+same record.
 
-Prints one JSON line with the throughput, per-step latency percentiles, the
-roofline of the dominant kernel (the correlation contraction on FP32 MFMA)
-measured live with HIP events on its stream, per-stage times and the FP64
-CPU checker timed on the host for one identification of the same record.
+Other workloads (--workload):
+  bridge-180ch-3d   the 3D stabilization diagram: the same record over lags
+                    20..100 step 10 (Toeplitz up to 18000 x 18000), all lags
+                    and orders in one HIP graph on three lag streams, plus
+                    the stability analysis; diagrams/s
+  serving           a Poisson stream of 10-minute windows of synthetic
+                    structures with uneven channel counts and lags through
+                    the continuous-batching server; requests/s and latency
+--prec fp32|bf16|bf16x3 selects the arithmetic of the range-finder products.
 """
 from __future__ import annotations
 
@@ -26,12 +36,12 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-WORKLOAD = "bridge-180ch"
 FP32_MFMA_PEAK_TFLOPS = 157.3       # MI355X dense FP32 matrix peak
 HBM_PEAK_GBS = 8000.0
 COPY_PROBE_BYTES = 256 << 20        # plain device copy used to calibrate HBM byte counters
 PMC_SUMMARY = os.path.join(ROOT, "profiles", "correlate_mfma_bridge180_pmc.md")
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2411_05510_amd", "csrc", "correlate.hip")
+PRECS = {"fp32": 0, "bf16": 1, "bf16x3": 2}
 
 
 def measured_traffic():
@@ -67,34 +77,67 @@ def corr_flops(l: int, n: int, L: int) -> float:
     return 2.0 * l * l * (L * n - L * (L + 1) / 2)
 
 
-def main() -> int:
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--copy-probe", action="store_true",
-                    help="run one plain device copy of 256 MiB first (counter calibration)")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
-              "(the identification path is single-GPU, see DESIGN.md for how it would shard)",
-              file=sys.stderr)
-        return 2
+def params_of(wl, prec: int):
+    from paper_2411_05510_amd import ssicov
+    return ssicov.Params(fs=wl.fs, lags=list(wl.lags), order_min=wl.order_min,
+                         order_max=wl.order_max, order_step=wl.order_step,
+                         svd=ssicov.SVD_RANDOMIZED, rank=wl.rank, oversample=wl.oversample,
+                         power_iters=wl.power_iters, seed=wl.sketch_seed, prec=prec)
 
+
+def roofline(stages, l, n, L):
+    flops = corr_flops(l, n, L)
+    corr_ms, corr_calls = stages["corr_mfma"]
+    corr_avg_ms = corr_ms / max(corr_calls, 1)
+    achieved = flops / (corr_avg_ms * 1e-3) / 1e12
+    return {
+        "bound": "mfma",
+        "kernel": "correlate_mfma",
+        "achieved": achieved,
+        "peak": FP32_MFMA_PEAK_TFLOPS,
+        "unit": "TFLOP/s",
+        "frac": achieved / FP32_MFMA_PEAK_TFLOPS,
+        "traffic": measured_traffic(),
+        "avg_kernel_ms": corr_avg_ms,
+        "algorithmic_flops_per_launch": flops,
+    }
+
+
+def timed_steps(ctx, step, steps, stream):
+    """Run `steps` calls of step() bracketed by device synchronization, with
+    per-step HIP events on the library stream.  Returns (elapsed s, step ms,
+    per-stage {name: (ms, calls)})."""
     import numpy as np
     import torch
+    ctx.set_profiling(True)
+    ctx.profile_read()                       # clear
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(steps):
+        evs[i][0].record(stream)
+        step()
+        evs[i][1].record(stream)
+    torch.cuda.synchronize()
+    ctx.synchronize()
+    elapsed = time.perf_counter() - t0
+    stages = ctx.profile_read()
+    ctx.set_profiling(False)
+    return elapsed, np.array([a.elapsed_time(b) for a, b in evs]), stages
 
+
+# ------------------------------------------------------------ headline
+def bench_identify(args) -> dict:
+    import numpy as np
+    import torch
     from paper_2411_05510_amd import ssicov, synth
 
-    wl = synth.WORKLOADS[WORKLOAD]
+    wl = synth.WORKLOADS["bridge-180ch"]
     _, y = synth.make_record(wl)
     dev = torch.device("cuda:0")
     yd = torch.from_numpy(y).to(dev)
-    p = ssicov.Params(fs=wl.fs, lags=list(wl.lags), order_min=wl.order_min,
-                      order_max=wl.order_max, order_step=wl.order_step,
-                      svd=ssicov.SVD_RANDOMIZED, rank=wl.rank, oversample=wl.oversample,
-                      power_iters=wl.power_iters, seed=wl.sketch_seed)
+    p = params_of(wl, PRECS[args.prec])
     ctx = ssicov.Context(0)
     out = ctx.alloc_output(p, wl.l, wl.n)
     stream = torch.cuda.current_stream(dev)
@@ -109,37 +152,15 @@ def main() -> int:
     for _ in range(args.warmup):
         ctx.identify(yd, p, out)
     ctx.synchronize()
-
-    # ---- timed region: K identifications, per-step events, stage profiling
-    ctx.set_profiling(True)
-    ctx.profile_read()                       # clear
-    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-           for _ in range(args.steps)]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        evs[i][0].record(stream)
-        ctx.identify(yd, p, out)
-        evs[i][1].record(stream)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    ctx.synchronize()
-    stages = ctx.profile_read()
-    ctx.set_profiling(False)
-    step_ms = np.array([a.elapsed_time(b) for a, b in evs])
+    elapsed, step_ms, stages = timed_steps(ctx, lambda: ctx.identify(yd, p, out), args.steps,
+                                           stream)
 
     L = 2 * wl.lags[0] - 1
-    flops = corr_flops(wl.l, wl.n, L)
-    corr_ms, corr_calls = stages["corr_mfma"]
-    corr_avg_ms = corr_ms / max(corr_calls, 1)
-    achieved = flops / (corr_avg_ms * 1e-3) / 1e12
     m = wl.lags[0] * wl.l
     toe_ms, toe_calls = stages["toeplitz"]
     toe_avg = toe_ms / max(toe_calls, 1)
     toe_gbs = (m * m * 4) / (toe_avg * 1e-3) / 1e9
-
     flags = int(out.flags.sum().item())
-    value = args.steps / elapsed
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -151,12 +172,15 @@ def main() -> int:
         cpu_s = time.perf_counter() - t1
         cpu = {"value": 1.0 / cpu_s, "unit": "identifications/s", "cores": blas_threads(),
                "kind": "oracle",
-               "sample": f"one full identification of the same {WORKLOAD} record "
+               "sample": f"one full identification of the same bridge-180ch record "
                          f"(FP64 numpy checker, {cpu_s:.1f} s)"}
-
+    prec_note = {"fp32": "T x Q products on FP64 MFMA",
+                 "bf16": "range-finder products BF16 (FP32 accumulation), projection FP64 MFMA",
+                 "bf16x3": "range-finder products split BF16 x3 (FP32 accumulation), "
+                           "projection FP64 MFMA"}[args.prec]
     rec = {
         "metric": "SSI-COV identifications/s at 180 ch, i=60",
-        "value": value,
+        "value": args.steps / elapsed,
         "unit": "identifications/s",
         "n_gpus": 1,
         "steps": args.steps,
@@ -165,12 +189,12 @@ def main() -> int:
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": "f32" if args.prec == "fp32" else args.prec,
         "data": "synthetic",
         "config": {
-            "workload": f"{WORKLOAD}: l=180 channels, N=180000 samples at 100 Hz, j_b=60 "
+            "workload": "bridge-180ch: l=180 channels, N=180000 samples at 100 Hz, j_b=60 "
                         "(10800x10800 Toeplitz), randomized SVD k=200 p=20 q=2, "
-                        "orders 2..200 step 2; correlations on FP32 MFMA, T x Q products on FP64 MFMA, "
+                        f"orders 2..200 step 2; correlations on FP32 MFMA, {prec_note}, "
                         "FP64 factorizations and eigen-analysis",
             "latency_ms_p50": float(np.percentile(step_ms, 50)),
             "latency_ms_p99": float(np.percentile(step_ms, 99)),
@@ -179,21 +203,178 @@ def main() -> int:
             "toeplitz_hbm_frac": toe_gbs / HBM_PEAK_GBS,
             "eig_flags": flags,
         },
-        "roofline": {
-            "bound": "mfma",
-            "kernel": "correlate_mfma",
-            "achieved": achieved,
-            "peak": FP32_MFMA_PEAK_TFLOPS,
-            "unit": "TFLOP/s",
-            "frac": achieved / FP32_MFMA_PEAK_TFLOPS,
-            "traffic": measured_traffic(),
-            "avg_kernel_ms": corr_avg_ms,
-            "algorithmic_flops_per_launch": flops,
-        },
+        "roofline": roofline(stages, wl.l, wl.n, L),
         "cpu_baseline": cpu,
     }
-    print(json.dumps(rec), flush=True)
     ctx.close()
+    return rec
+
+
+# ------------------------------------------------------------ 3D diagram
+def bench_3d(args) -> dict:
+    import numpy as np
+    import torch
+    from paper_2411_05510_amd import ssicov, synth
+
+    wl = synth.WORKLOADS["bridge-180ch-3d"]
+    _, y = synth.make_record(wl)
+    dev = torch.device("cuda:0")
+    yd = torch.from_numpy(y).to(dev)
+    p = params_of(wl, PRECS[args.prec])
+    ctx = ssicov.Context(0)
+    ctx.set_lag_streams(args.lag_streams)
+    ctx.set_autotune(True)
+    out = ctx.alloc_output(p, wl.l, wl.n)
+    stream = torch.cuda.current_stream(dev)
+    for _ in range(args.warmup):            # eager (autotuning) run
+        ctx.identify(yd, p, out)
+    ctx.synchronize()
+    ctx.set_graphs(True)
+
+    def step():
+        ctx.identify(yd, p, out)
+        ctx.stability(out, wl.l)
+
+    step()                                  # eager + capture
+    ctx.synchronize()
+    elapsed, step_ms, _ = timed_steps(ctx, step, args.steps, stream)
+    mpc, mpd, flags = ctx.stability(out, wl.l)
+    ctx.synchronize()
+    n_poles = int(out.count.sum().item())
+    n_stable = int(((flags & ssicov.POLE_STABLE) != 0).sum().item())
+    L = 2 * wl.lags[-1] - 1
+    rec = {
+        "metric": "SSI-COV 3D stabilization diagrams/s (180 ch, 9 lags)",
+        "value": args.steps / elapsed,
+        "unit": "diagrams/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1000.0 * elapsed / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if args.prec == "fp32" else args.prec,
+        "data": "synthetic",
+        "config": {
+            "workload": "bridge-180ch-3d: l=180, N=180000 at 100 Hz, lags 20..100 step 10 "
+                        "(Toeplitz 3600..18000), k=200 p=20 q=2, orders 2..200 step 2, "
+                        f"one HIP graph on {args.lag_streams} lag streams, autotuned products, "
+                        "stability analysis (hard criteria, Eq. (19))",
+            "latency_ms_p50": float(np.percentile(step_ms, 50)),
+            "latency_ms_p99": float(np.percentile(step_ms, 99)),
+            "identifications_per_s": len(wl.lags) * args.steps / elapsed,
+            "poles": n_poles,
+            "stable_poles": n_stable,
+            "correlation_flops": corr_flops(wl.l, wl.n, L),
+        },
+    }
+    ctx.close()
+    return rec
+
+
+# ------------------------------------------------------------ serving
+def bench_serving(args) -> dict:
+    import numpy as np
+    from paper_2411_05510_amd import ssicov, synth
+
+    rng = np.random.default_rng(4_000_000)
+    channels, lags_set = (24, 60, 120, 180, 300), (20, 40, 60, 80)
+    pool = []
+    for r in range(args.pool):
+        l = int(rng.choice(channels))
+        modes = int(rng.integers(8, 31))
+        jb = int(rng.choice(lags_set))
+        rank = 2 * modes + 20
+        wl = synth.Workload(name=f"win{r}", l=l, n=60000, fs=100.0, n_modes=modes,
+                            f_range=(0.5, 20.0), zeta_range=(0.005, 0.03), noise=0.05,
+                            lags=(jb,), svd="randomized", rank=rank, oversample=20,
+                            power_iters=2, order_min=2, order_max=rank, order_step=2,
+                            struct_seed=4_000_000 + r, noise_seed=5_000_000 + r,
+                            sketch_seed=6_000_000 + r)
+        _, y = synth.make_record(wl)
+        pool.append((y, params_of(wl, PRECS[args.prec])))
+
+    def run(rate_hz, count, inflight):
+        srv = ssicov.Server(0, max_inflight=inflight)
+        # warm every slot's buffers and kernels
+        for t in [srv.submit(*pool[i % len(pool)]) for i in range(inflight)]:
+            srv.wait(t)
+            srv.release(t)
+        gaps = rng.exponential(1.0 / rate_hz, count) if rate_hz else np.zeros(count)
+        tickets = []
+        t0 = time.perf_counter()
+        due = t0
+        for i in range(count):
+            due += gaps[i]
+            now = time.perf_counter()
+            if due > now:
+                time.sleep(due - now)
+            tickets.append(srv.submit(*pool[i % len(pool)]))
+        infos = [srv.wait(t) for t in tickets]
+        span = time.perf_counter() - t0
+        lat = np.array([(i["t_done_us"] - i["t_submit_us"]) / 1e3 for i in infos])
+        st = srv.stats()
+        for t in tickets:
+            srv.release(t)
+        srv.close()
+        return count / span, lat, st
+
+    sat, _, _ = run(0.0, args.requests, args.inflight)          # all at once: saturation
+    rate = 0.8 * sat
+    thr, lat, st = run(rate, args.requests, args.inflight)
+    return {
+        "metric": "SSI-COV serving requests/s (Poisson, 10-min windows)",
+        "value": thr,
+        "unit": "requests/s",
+        "n_gpus": 1,
+        "steps": args.requests,
+        "warmup": args.inflight,
+        "ms_per_step": 1000.0 / thr,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if args.prec == "fp32" else args.prec,
+        "data": "synthetic",
+        "config": {
+            "workload": "serving: N=60000 at 100 Hz per window, l in {24,60,120,180,300}, "
+                        "8-30 modes, j_b in {20,40,60,80}, k=2 modes+20, p=20, q=2, "
+                        f"orders 2..k step 2; up to {args.inflight} in flight, admission by "
+                        "device footprint; Poisson arrivals at 0.8 x measured saturation",
+            "saturation_requests_per_s": sat,
+            "arrival_rate_hz": rate,
+            "latency_ms_p50": float(np.percentile(lat, 50)),
+            "latency_ms_p99": float(np.percentile(lat, 99)),
+            "peak_inflight": st["peak_inflight"],
+            "peak_device_bytes": st["peak_bytes"],
+            "distinct_windows": len(pool),
+        },
+    }
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="bridge-180ch",
+                    choices=("bridge-180ch", "bridge-180ch-3d", "serving"))
+    ap.add_argument("--prec", default="fp32", choices=tuple(PRECS))
+    ap.add_argument("--lag-streams", type=int, default=3)
+    ap.add_argument("--requests", type=int, default=96, help="serving: requests per run")
+    ap.add_argument("--inflight", type=int, default=16, help="serving: slots")
+    ap.add_argument("--pool", type=int, default=24, help="serving: distinct windows")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="run one plain device copy of 256 MiB first (counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+              "(the identification path is single-GPU)", file=sys.stderr)
+        return 2
+    fn = {"bridge-180ch": bench_identify, "bridge-180ch-3d": bench_3d,
+          "serving": bench_serving}[args.workload]
+    print(json.dumps(fn(args)), flush=True)
     return 0
 
 

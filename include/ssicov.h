@@ -103,8 +103,9 @@ typedef struct ssi_layout {
 /* Device output buffers of ssi_identify (all device pointers, caller-owned).
  * Poles of (lag i, order o) occupy slots [off(o), off(o) + count[i][o]) of lag
  * i, with off(o) = sum over earlier orders of n2 / 2 (see ssi_pole_offset);
- * within an order they are sorted by (f, xi).  One pole is kept per complex
- * conjugate pair (Im mu > 0); real eigenvalues are dropped.               */
+ * within an order they are sorted by (f, xi); the remaining slots of the
+ * order, up to off(o) + n2 / 2, are written with zeros.  One pole is kept per
+ * complex conjugate pair (Im mu > 0); real eigenvalues are dropped.       */
 typedef struct ssi_output {
   double *sigma;      /* [n_lags][sigma_per_lag], descending                      */
   int32_t *count;     /* [n_lags][n_orders] poles per (lag, order)                */

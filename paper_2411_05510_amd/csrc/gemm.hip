@@ -1,15 +1,16 @@
 // Dense products of the randomized SVD and the modal stage.
 //
-// gemm_tf64: C = op(T) X with T in FP32 (the Toeplitz matrix as stored) and X
-//   in FP64, on v_mfma_f64_16x16x4f64 with FP64 accumulation: the sketch,
+// gemm_tf64w: C = op(T) X with T in FP32 (the Toeplitz matrix as stored) and
+//   X in FP64, on v_mfma_f64_16x16x4f64 with FP64 accumulation: the sketch,
 //   power-iteration and projection products Y = T X, Z = T^T X.  T is
 //   converted exactly to FP64 in registers, so the only rounding is FP64
-//   accumulation.  Tile 64 x 224 x 16: the thin side (ell = k + p columns)
-//   fits one column block, the long side is split across workgroups and
-//   along K.  The flat grid is decoded split-fastest, so with 8 splits the
-//   workgroups of one K slice land on one XCD (dispatch is round-robin over
-//   the 8 XCDs) and that XCD's L2 holds the slice of X they all read.
-//   Partial sums (FP64) are added by reduce_splits in a fixed order.
+//   accumulation.  Tile 128 x 224 x 32 on 8 waves, double-buffered LDS with
+//   the next K tile prefetched into registers during the MFMAs, one
+//   workgroup per CU.  The thin side (ell = k + p columns) fits one column
+//   block; the long side is split across workgroups and along K, with the
+//   number of K slices chosen to fill whole rounds of the CUs.  The flat grid
+//   is decoded split-fastest.  Partial sums (FP64) are added by
+//   reduce_splits in a fixed order.
 // gemm_f64: FP64 operands on v_mfma_f64_16x16x4f64 (Gram matrices, basis
 //   updates, small triangular products).  Tile 64 x 64 x 16.
 #include "common.h"
@@ -17,30 +18,7 @@
 
 namespace {
 
-constexpr int tBM = 64, tBN = 224, tKT = 16;
-constexpr int tLA = tKT + 4;    // FP32 A row stride in LDS (floats), A stored [i][k]
-constexpr int tLB = tBN + 4;    // FP64 B row stride in LDS (doubles), B stored [k][j]
-
 constexpr int dBM = 64, dBN = 64, dKT = 16, dLS = dKT + 2;    // fp64 tiles
-
-// Guarded 4-float load of row `row` (< rows) starting at column c (< cols).
-template <bool VEC>
-SSI_DEV float4 load4(const float *__restrict__ p, int64_t ld, int64_t row, int64_t rows,
-                     int64_t c, int64_t cols) {
-  float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-  if (row >= rows) return v;
-  const float *q = p + row * ld + c;
-  if (VEC && c + 3 < cols) return *reinterpret_cast<const float4 *>(q);
-  if (c < cols) v.x = q[0];
-  if (c + 1 < cols) v.y = q[1];
-  if (c + 2 < cols) v.z = q[2];
-  if (c + 3 < cols) v.w = q[3];
-  return v;
-}
-
-SSI_DEV float f4get(const float4 &v, int s) {
-  return s == 0 ? v.x : s == 1 ? v.y : s == 2 ? v.z : v.w;
-}
 
 }  // namespace
 
@@ -48,22 +26,113 @@ SSI_DEV float f4get(const float4 &v, int s) {
 //   TA = false: A is M x K (lda);  TA = true: A is K x M (lda), op(A) = A^T.
 //   A FP32, B FP64 K x N (ldb).  VEC: lda % 4 == 0 and A 16-byte aligned;
 //   BVEC: ldb even and B 16-byte aligned.
-// Each K tile (16) is loaded into registers with all loads in flight at once
-// (out-of-range rows and columns read a clamped in-range address and are
-// zeroed by select), then written to LDS.  In MFMA step s of K sub-tile h the
-// 16-lane group g of a wave supplies k = 16 h + 4 g + s.
+// 128 x 224 output tile, 32-deep K tiles and 8 waves
+// (4 x 2, each 32 x 112): the LDS tiles are double-buffered and the next K
+// tile is loaded into registers while the MFMAs of the current one run, so a
+// workgroup streams T with one barrier per K tile.  One workgroup per CU
+// (150 KB of LDS); the FP64 operand is read from L2 once per 128 rows.
+namespace {
+constexpr int wBM = 128, wBN = 224, wKT = 32;
+constexpr int wLA = wKT + 4;          // FP32 A row stride (floats), A stored [i][k]
+constexpr int wLB = wBN + 4;          // FP64 B row stride (doubles), B stored [k][j]
+constexpr int wAS = wBM * wLA, wBS = wKT * wLB;   // one buffer, elements
+typedef double f64x2v __attribute__((ext_vector_type(2)));
+typedef float f32x4v __attribute__((ext_vector_type(4)));
+
 template <bool TA, bool VEC, bool BVEC>
-__global__ void __launch_bounds__(256, 2)
-gemm_tf64_mfma(const float *__restrict__ A, int64_t lda, const double *__restrict__ B,
-               int64_t ldb, double *__restrict__ C, int64_t ldc, int64_t split_stride, int M,
-               int N, int K, int k_per_split, int gm, int splits) {
-  __shared__ __attribute__((aligned(16))) float As[tBM * tLA];
-  __shared__ __attribute__((aligned(16))) double Bs[tKT * tLB];
+SSI_DEV void tf64w_load(const float *__restrict__ A, int64_t lda, const double *__restrict__ B,
+                        int64_t ldb, int M, int N, int m0, int n0, int k0, int ke, int tid,
+                        f32x4v (&ra)[2], f64x2v (&rb)[7]) {
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int idx = tid + 512 * h;
+    f32x4v v;
+    if (!TA) {
+      const int r = idx >> 3, c4 = idx & 7;               // row, 4-column group of k
+      const int gi = m0 + r, gk = k0 + 4 * c4;
+      const float *p = A + (int64_t)min(gi, M - 1) * lda;
+      if (VEC && gk + 3 < ke) {
+        v = *reinterpret_cast<const f32x4v *>(p + gk);
+      } else {
+        v.x = gk < ke ? p[gk] : 0.f;
+        v.y = gk + 1 < ke ? p[gk + 1] : 0.f;
+        v.z = gk + 2 < ke ? p[gk + 2] : 0.f;
+        v.w = gk + 3 < ke ? p[gk + 3] : 0.f;
+      }
+      if (gi >= M) v = f32x4v{0.f, 0.f, 0.f, 0.f};
+    } else {
+      const int kr = idx >> 5, c4 = idx & 31;             // k row, 4-column group of i
+      const int gk = k0 + kr, gi = m0 + 4 * c4;
+      const float *p = A + (int64_t)min(gk, ke - 1) * lda;
+      if (VEC && gi + 3 < M) {
+        v = *reinterpret_cast<const f32x4v *>(p + gi);
+      } else {
+        v.x = gi < M ? p[gi] : 0.f;
+        v.y = gi + 1 < M ? p[gi + 1] : 0.f;
+        v.z = gi + 2 < M ? p[gi + 2] : 0.f;
+        v.w = gi + 3 < M ? p[gi + 3] : 0.f;
+      }
+      if (gk >= ke) v = f32x4v{0.f, 0.f, 0.f, 0.f};
+    }
+    ra[h] = v;
+  }
+#pragma unroll
+  for (int h = 0; h < 7; ++h) {
+    const int idx = tid + 512 * h;                       // 32 k rows x 112 double pairs
+    const int kr = idx / 112, c2 = idx - kr * 112;
+    const int gk = k0 + kr, gj = n0 + 2 * c2;
+    const double *q = B + (int64_t)min(gk, ke - 1) * ldb;
+    f64x2v v;
+    if (BVEC && gj + 1 < N) {
+      v = *reinterpret_cast<const f64x2v *>(q + gj);
+    } else {
+      v.x = gj < N ? q[gj] : 0.0;
+      v.y = gj + 1 < N ? q[gj + 1] : 0.0;
+    }
+    if (gk >= ke) v = f64x2v{0.0, 0.0};
+    rb[h] = v;
+  }
+}
+
+template <bool TA>
+SSI_DEV void tf64w_store(float *__restrict__ As, double *__restrict__ Bs, int tid,
+                         const f32x4v (&ra)[2], const f64x2v (&rb)[7]) {
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int idx = tid + 512 * h;
+    if (!TA) {
+      const int r = idx >> 3, c4 = idx & 7;
+      *reinterpret_cast<f32x4v *>(&As[r * wLA + 4 * c4]) = ra[h];
+    } else {
+      const int kr = idx >> 5, c4 = idx & 31;
+      As[(4 * c4 + 0) * wLA + kr] = ra[h].x;
+      As[(4 * c4 + 1) * wLA + kr] = ra[h].y;
+      As[(4 * c4 + 2) * wLA + kr] = ra[h].z;
+      As[(4 * c4 + 3) * wLA + kr] = ra[h].w;
+    }
+  }
+#pragma unroll
+  for (int h = 0; h < 7; ++h) {
+    const int idx = tid + 512 * h;
+    const int kr = idx / 112, c2 = idx - kr * 112;
+    *reinterpret_cast<f64x2v *>(&Bs[kr * wLB + 2 * c2]) = rb[h];
+  }
+}
+}  // namespace
+
+template <bool TA, bool VEC, bool BVEC>
+__global__ void __launch_bounds__(512, 1)
+gemm_tf64w_mfma(const float *__restrict__ A, int64_t lda, const double *__restrict__ B,
+                int64_t ldb, double *__restrict__ C, int64_t ldc, int64_t split_stride, int M,
+                int N, int K, int k_per_split, int gm, int splits) {
+  extern __shared__ __attribute__((aligned(16))) double smem[];
+  float *Asb = reinterpret_cast<float *>(smem);                  // [2][wAS] floats
+  double *Bsb = smem + wAS;                                       // [2][wBS] doubles (wAS even)
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wr = wave & 1, wc = wave >> 1;
+  const int wr = wave & 3, wc = wave >> 2;
   const int split = blockIdx.x % splits;
   const int rest = blockIdx.x / splits;
-  const int m0 = (rest % gm) * tBM, n0 = (rest / gm) * tBN;
+  const int m0 = (rest % gm) * wBM, n0 = (rest / gm) * wBN;
   const int kb = split * k_per_split;
   const int ke = min(K, kb + k_per_split);
 
@@ -76,95 +145,48 @@ gemm_tf64_mfma(const float *__restrict__ A, int64_t lda, const double *__restric
 #pragma unroll
   for (int ct = 0; ct < 7; ++ct) colok[ct] = n0 + wc * 112 + ct * 16 < N;
 
-  for (int k0 = kb; k0 < ke; k0 += tKT) {
-    // ---- A tile (64 x 16 FP32): one float4 per thread
-    float4 ra[1];
+  f32x4v ra[2];
+  f64x2v rb[7];
+  int buf = 0;
+  if (kb < ke) {
+    tf64w_load<TA, VEC, BVEC>(A, lda, B, ldb, M, N, m0, n0, kb, ke, tid, ra, rb);
+    tf64w_store<TA>(Asb, Bsb, tid, ra, rb);
+  }
+  __syncthreads();
+  for (int k0 = kb; k0 < ke; k0 += wKT) {
+    const bool more = k0 + wKT < ke;
+    if (more) tf64w_load<TA, VEC, BVEC>(A, lda, B, ldb, M, N, m0, n0, k0 + wKT, ke, tid, ra, rb);
+    const float *As = Asb + buf * wAS;
+    const double *Bs = Bsb + buf * wBS;
 #pragma unroll
-    for (int h = 0; h < 1; ++h) {
-      const int idx = tid + 256 * h;
-      if (!TA) {
-        const int r = idx >> 2, c4 = idx & 3;              // row, 4-column group of k
-        const int gi = m0 + r, gk = k0 + 4 * c4;
-        const float *p = A + (int64_t)min(gi, M - 1) * lda;
-        float4 v;
-        if (VEC && gk + 3 < ke) v = *reinterpret_cast<const float4 *>(p + gk);
-        else v = load4<false>(p, 0, 0, 1, gk, ke);
-        ra[h] = gi < M ? v : make_float4(0.f, 0.f, 0.f, 0.f);
-      } else {
-        const int kr = idx >> 4, c4 = idx & 15;            // k row, 4-column group of i
-        const int gk = k0 + kr, gi = m0 + 4 * c4;
-        const float *p = A + (int64_t)min(gk, ke - 1) * lda;
-        float4 v;
-        if (VEC && gi + 3 < M) v = *reinterpret_cast<const float4 *>(p + gi);
-        else v = load4<false>(p, 0, 0, 1, gi, M);
-        ra[h] = gk < ke ? v : make_float4(0.f, 0.f, 0.f, 0.f);
-      }
-    }
-    // ---- B tile (16 x 224 FP64): seven double pairs per thread
-    double2 rbv[7];
-#pragma unroll
-    for (int h = 0; h < 7; ++h) {
-      const int idx = tid + 256 * h;
-      const int kr = idx / 112, c2 = idx - kr * 112;
-      const int gk = k0 + kr, gj = n0 + 2 * c2;
-      const double *q = B + (int64_t)min(gk, ke - 1) * ldb;
-      double2 v;
-      if (BVEC && gj + 1 < N) {
-        v = *reinterpret_cast<const double2 *>(q + gj);
-      } else {
-        v.x = q[min(gj, N - 1)];
-        v.y = q[min(gj + 1, N - 1)];
-        if (gj >= N) v.x = 0.0;
-        if (gj + 1 >= N) v.y = 0.0;
-      }
-      rbv[h] = gk < ke ? v : make_double2(0.0, 0.0);
-    }
-    __syncthreads();                      // previous tile's reads are done
-#pragma unroll
-    for (int h = 0; h < 1; ++h) {
-      const int idx = tid + 256 * h;
-      if (!TA) {
-        const int r = idx >> 2, c4 = idx & 3;
-        *reinterpret_cast<float4 *>(&As[r * tLA + 4 * c4]) = ra[h];
-      } else {
-        const int kr = idx >> 4, c4 = idx & 15;
-        As[(4 * c4 + 0) * tLA + kr] = ra[h].x;
-        As[(4 * c4 + 1) * tLA + kr] = ra[h].y;
-        As[(4 * c4 + 2) * tLA + kr] = ra[h].z;
-        As[(4 * c4 + 3) * tLA + kr] = ra[h].w;
-      }
-    }
-#pragma unroll
-    for (int h = 0; h < 7; ++h) {
-      const int idx = tid + 256 * h;
-      const int kr = idx / 112, c2 = idx - kr * 112;
-      *reinterpret_cast<double2 *>(&Bs[kr * tLB + 2 * c2]) = rbv[h];
-    }
-    __syncthreads();
-
-#pragma unroll
-    for (int hk = 0; hk < tKT / 16; ++hk) {
+    for (int hk = 0; hk < wKT / 16; ++hk) {
       const int ko = 16 * hk + 4 * (lane >> 4);
-      float4 a4[2];
+      f32x4v a4[2];
 #pragma unroll
       for (int rt = 0; rt < 2; ++rt)
-        a4[rt] = *reinterpret_cast<const float4 *>(
-            &As[(wr * 32 + rt * 16 + (lane & 15)) * tLA + ko]);
+        a4[rt] = *reinterpret_cast<const f32x4v *>(
+            &As[(wr * 32 + rt * 16 + (lane & 15)) * wLA + ko]);
 #pragma unroll
       for (int s = 0; s < 4; ++s) {
         double bv[7];
 #pragma unroll
-        for (int ct = 0; ct < 7; ++ct) bv[ct] = Bs[(ko + s) * tLB + wc * 112 + ct * 16 + (lane & 15)];
+        for (int ct = 0; ct < 7; ++ct) bv[ct] = Bs[(ko + s) * wLB + wc * 112 + ct * 16 + (lane & 15)];
 #pragma unroll
         for (int ct = 0; ct < 7; ++ct) {
           if (!colok[ct]) continue;
 #pragma unroll
           for (int rt = 0; rt < 2; ++rt)
-            acc[rt][ct] = __builtin_amdgcn_mfma_f64_16x16x4f64((double)f4get(a4[rt], s),
-                                                               bv[ct], acc[rt][ct], 0, 0, 0);
+            acc[rt][ct] = __builtin_amdgcn_mfma_f64_16x16x4f64((double)a4[rt][s], bv[ct],
+                                                               acc[rt][ct], 0, 0, 0);
         }
       }
     }
+    if (more) {
+      // the other buffer was last read before the previous barrier
+      tf64w_store<TA>(Asb + (buf ^ 1) * wAS, Bsb + (buf ^ 1) * wBS, tid, ra, rb);
+    }
+    __syncthreads();
+    buf ^= 1;
   }
 
   // D layout of 16x16x4f64: lane holds rows (lane/16) + 4 q, column lane%16.
@@ -326,18 +348,28 @@ int grid_cap(int64_t work) {
 
 GemmPlan plan_gemm_tf64(int M, int N, int K, int num_cus, int force_splits) {
   GemmPlan p{};
-  p.gm = ceil_div(M, tBM);
-  p.gn = ceil_div(N, tBN);
-  // Eight K slices (one per XCD) once K is long enough for each to keep its
-  // workgroups busy; fewer for short K.
+  p.gm = ceil_div(M, wBM);
+  p.gn = ceil_div(N, wBN);
+  // One workgroup per CU: pick the K-slice count whose workgroup count fills
+  // whole rounds of the CUs best (fewest idle CU slots), at most 16 slices
+  // and at least 512 rows of K per slice.
   const int64_t tiles = (int64_t)p.gm * p.gn;
-  int64_t splits = 8;
-  if (tiles * 8 < (int64_t)num_cus) splits = ceil_div<int64_t>((int64_t)num_cus * 2, tiles);
-  const int64_t max_splits = ceil_div<int64_t>(K, 512);
-  splits = std::max<int64_t>(1, std::min(splits, max_splits));
-  if (force_splits > 0) splits = std::min<int64_t>(force_splits, ceil_div<int64_t>(K, tKT));
+  const int64_t max_splits = std::max<int64_t>(1, std::min<int64_t>(16, ceil_div<int64_t>(K, 512)));
+  int64_t splits = 1;
+  double best = -1.0;
+  for (int64_t sp = 1; sp <= max_splits; ++sp) {
+    const int64_t wgs = tiles * sp;
+    const int64_t rounds = ceil_div<int64_t>(wgs, num_cus);
+    const double fill = (double)wgs / (double)(rounds * num_cus);
+    // prefer full rounds; among equal fill, fewer slices (less partial traffic)
+    if (fill > best + 1e-9) {
+      best = fill;
+      splits = sp;
+    }
+  }
+  if (force_splits > 0) splits = std::min<int64_t>(force_splits, ceil_div<int64_t>(K, wKT));
   int64_t kps = ceil_div<int64_t>(K, splits);
-  kps = ceil_div<int64_t>(kps, tKT) * tKT;
+  kps = ceil_div<int64_t>(kps, wKT) * wKT;
   p.k_per_split = (int)kps;
   p.splits = (int)ceil_div<int64_t>(K, kps);
   p.ldc = N;
@@ -363,18 +395,26 @@ GemmPlan plan_gemm_f64(int M, int N, int K, int num_cus) {
 }
 
 template <bool TA>
-static void launch_tf64_variant(const GemmPlan &p, bool vec, bool bvec, const float *A,
-                                int64_t lda, const double *B, int64_t ldb, int M, int N, int K,
-                                double *part, hipStream_t st) {
+static hipError_t launch_tf64_variant(const GemmPlan &p, bool vec, bool bvec, const float *A,
+                                      int64_t lda, const double *B, int64_t ldb, int M, int N,
+                                      int K, double *part, hipStream_t st) {
   const dim3 grid((unsigned)((int64_t)p.gm * p.gn * p.splits));
-#define SSI_TF64(V, BV)                                                                      \
-  hipLaunchKernelGGL((gemm_tf64_mfma<TA, V, BV>), grid, dim3(256), 0, st, A, lda, B, ldb, part, \
-                     p.ldc, p.split_stride, M, N, K, p.k_per_split, p.gm, p.splits)
+  // two FP32 A buffers (wAS floats each = wAS doubles in all) and two FP64 B buffers
+  const size_t lds = sizeof(double) * (size_t)(wAS + 2 * wBS);
+#define SSI_TF64(V, BV)                                                                        \
+  do {                                                                                         \
+    hipError_t e = hipFuncSetAttribute((const void *)gemm_tf64w_mfma<TA, V, BV>,               \
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);  \
+    if (e != hipSuccess) return e;                                                             \
+    hipLaunchKernelGGL((gemm_tf64w_mfma<TA, V, BV>), grid, dim3(512), lds, st, A, lda, B, ldb, \
+                       part, p.ldc, p.split_stride, M, N, K, p.k_per_split, p.gm, p.splits);   \
+  } while (0)
   if (vec && bvec) SSI_TF64(true, true);
   else if (vec) SSI_TF64(true, false);
   else if (bvec) SSI_TF64(false, true);
   else SSI_TF64(false, false);
 #undef SSI_TF64
+  return hipSuccess;
 }
 
 hipError_t launch_gemm_tf64(const GemmPlan &p, bool trans_a, const float *A, int64_t lda,
@@ -382,8 +422,10 @@ hipError_t launch_gemm_tf64(const GemmPlan &p, bool trans_a, const float *A, int
                             hipStream_t st) {
   const bool vec = (lda % 4 == 0) && ((uintptr_t)A % 16 == 0);
   const bool bvec = (ldb % 2 == 0) && ((uintptr_t)B % 16 == 0);
-  if (trans_a) launch_tf64_variant<true>(p, vec, bvec, A, lda, B, ldb, M, N, K, part, st);
-  else launch_tf64_variant<false>(p, vec, bvec, A, lda, B, ldb, M, N, K, part, st);
+  hipError_t e = trans_a
+                     ? launch_tf64_variant<true>(p, vec, bvec, A, lda, B, ldb, M, N, K, part, st)
+                     : launch_tf64_variant<false>(p, vec, bvec, A, lda, B, ldb, M, N, K, part, st);
+  if (e != hipSuccess) return e;
   return hipGetLastError();
 }
 

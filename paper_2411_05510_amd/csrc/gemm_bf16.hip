@@ -18,6 +18,7 @@
 #include "kernels.h"
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
 namespace {
 
@@ -25,10 +26,9 @@ constexpr int bBM = 64, bBN = 224;
 
 // FP32 -> BF16, round to nearest even (NaN kept quiet).
 SSI_DEV uint16_t bf16_rne(float f) {
-  uint32_t u = __float_as_uint(f);
-  if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);
-  u += 0x7fffu + ((u >> 16) & 1u);
-  return (uint16_t)(u >> 16);
+  const uint32_t u = __float_as_uint(f);
+  const uint32_t r = (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;
+  return (uint16_t)(((u & 0x7fffffffu) > 0x7f800000u) ? ((u >> 16) | 0x40u) : r);
 }
 
 // FP64 -> BF16, round to nearest even in one rounding: truncate to FP32 and
@@ -41,6 +41,105 @@ SSI_DEV uint16_t bf16_rne(double d) {
 }
 
 SSI_DEV uint32_t pack2(uint16_t lo, uint16_t hi) { return (uint32_t)lo | ((uint32_t)hi << 16); }
+
+// Global -> registers for the tile at k0.  A: 64 x KT FP32; rows (or k rows
+// for TA) beyond the matrix or the slice read a clamped in-range address and
+// are zeroed.  B: 224 x KT BF16 per plane, always in range (chunks past the
+// tile, for KT = 32, reload the last one and are not stored).
+template <bool TA, bool VEC, int KT, int NP, int AV, int BC>
+SSI_DEV void bf16_tile_load(const float *__restrict__ A, int64_t lda,
+                            const uint16_t *__restrict__ xt, int64_t ldx, int64_t plane, int M,
+                            int K, int m0, int n0, int k0, int ke, int tid, float4 (&ra)[AV],
+                            u32x4 (&rb)[NP][BC]) {
+#pragma unroll
+  for (int h = 0; h < AV; ++h) {
+    const int idx = tid + 256 * h;
+    if (!TA) {
+      const int r = idx / (KT / 4), c4 = idx % (KT / 4);
+      const int gi = m0 + r, gk = k0 + 4 * c4;
+      const float *p = A + (int64_t)min(gi, M - 1) * lda;
+      float4 v;
+      if (VEC && gk + 3 < ke) {
+        v = *reinterpret_cast<const float4 *>(p + gk);
+      } else {
+        v.x = gk < ke ? p[min(gk, K - 1)] : 0.f;
+        v.y = gk + 1 < ke ? p[min(gk + 1, K - 1)] : 0.f;
+        v.z = gk + 2 < ke ? p[min(gk + 2, K - 1)] : 0.f;
+        v.w = gk + 3 < ke ? p[min(gk + 3, K - 1)] : 0.f;
+      }
+      ra[h] = gi < M ? v : make_float4(0.f, 0.f, 0.f, 0.f);
+    } else {
+      const int r = idx >> 4, c4 = idx & 15;    // k row, 4-column group of i
+      const int gk = k0 + r, gi = m0 + 4 * c4;
+      const float *p = A + (int64_t)min(gk, K - 1) * lda;
+      float4 v;
+      if (VEC && gi + 3 < M) {
+        v = *reinterpret_cast<const float4 *>(p + gi);
+      } else {
+        v.x = gi < M ? p[min(gi, M - 1)] : 0.f;
+        v.y = gi + 1 < M ? p[min(gi + 1, M - 1)] : 0.f;
+        v.z = gi + 2 < M ? p[min(gi + 2, M - 1)] : 0.f;
+        v.w = gi + 3 < M ? p[min(gi + 3, M - 1)] : 0.f;
+      }
+      ra[h] = gk < ke ? v : make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < NP; ++q)
+#pragma unroll
+    for (int h = 0; h < BC; ++h) {
+      const int idx = min(tid + 256 * h, bBN * KT / 8 - 1);
+      const int j = idx / (KT / 8), c8 = idx % (KT / 8);
+      rb[q][h] = *reinterpret_cast<const u32x4 *>(xt + q * plane + (int64_t)(n0 + j) * ldx + k0 +
+                                                  8 * c8);
+    }
+}
+
+SSI_DEV uint16_t bf16_lo(float v, uint16_t h) {
+  return bf16_rne(v - __uint_as_float((uint32_t)h << 16));
+}
+
+// Registers -> LDS (BF16 planes), A as As[i][k], B as Bs[j][k].
+template <bool TA, int KT, int LS, int NP, int AV, int BC, int NT>
+SSI_DEV void bf16_tile_store(uint16_t (&As)[NP][bBM * LS], uint16_t (&Bs)[NP][bBN * LS], int tid,
+                             const float4 (&ra)[AV], const u32x4 (&rb)[NP][BC]) {
+#pragma unroll
+  for (int q = 0; q < NP; ++q)
+#pragma unroll
+    for (int h = 0; h < BC; ++h) {
+      const int idx = tid + 256 * h;
+      if ((bBN * KT / 8) % 256 == 0 || idx < bBN * KT / 8) {
+        const int j = idx / (KT / 8), c8 = idx % (KT / 8);
+        *reinterpret_cast<u32x4 *>(&Bs[q][j * LS + 8 * c8]) = rb[q][h];
+      }
+    }
+#pragma unroll
+  for (int h = 0; h < AV; ++h) {
+    const int idx = tid + 256 * h;
+    const uint16_t h0 = bf16_rne(ra[h].x), h1 = bf16_rne(ra[h].y);
+    const uint16_t h2 = bf16_rne(ra[h].z), h3 = bf16_rne(ra[h].w);
+    if (!TA) {
+      const int r = idx / (KT / 4), c4 = idx % (KT / 4);
+      *reinterpret_cast<uint2 *>(&As[0][r * LS + 4 * c4]) = make_uint2(pack2(h0, h1), pack2(h2, h3));
+      if (NT == 3)
+        *reinterpret_cast<uint2 *>(&As[NP - 1][r * LS + 4 * c4]) =
+            make_uint2(pack2(bf16_lo(ra[h].x, h0), bf16_lo(ra[h].y, h1)),
+                       pack2(bf16_lo(ra[h].z, h2), bf16_lo(ra[h].w, h3)));
+    } else {
+      const int r = idx >> 4, c4 = idx & 15;
+      As[0][(4 * c4 + 0) * LS + r] = h0;
+      As[0][(4 * c4 + 1) * LS + r] = h1;
+      As[0][(4 * c4 + 2) * LS + r] = h2;
+      As[0][(4 * c4 + 3) * LS + r] = h3;
+      if (NT == 3) {
+        As[NP - 1][(4 * c4 + 0) * LS + r] = bf16_lo(ra[h].x, h0);
+        As[NP - 1][(4 * c4 + 1) * LS + r] = bf16_lo(ra[h].y, h1);
+        As[NP - 1][(4 * c4 + 2) * LS + r] = bf16_lo(ra[h].z, h2);
+        As[NP - 1][(4 * c4 + 3) * LS + r] = bf16_lo(ra[h].w, h3);
+      }
+    }
+  }
+}
 
 }  // namespace
 
@@ -79,102 +178,17 @@ gemm_tbf16_mfma(const float *__restrict__ A, int64_t lda, const uint16_t *__rest
     for (int ct = 0; ct < 7; ++ct) acc[rt][ct] = f32x4{0.f, 0.f, 0.f, 0.f};
 
   float4 ra[AV];
-  uint4 rb[NP][BC];
-  // Global -> registers for the tile at k0.  A: 64 x KT FP32; rows (or k rows
-  // for TA) beyond the matrix or the slice read a clamped in-range address
-  // and are zeroed.  B: 224 x KT BF16 per plane, always in range.
-  auto load = [&](int k0) {
-#pragma unroll
-    for (int h = 0; h < AV; ++h) {
-      const int idx = tid + 256 * h;
-      if (!TA) {
-        const int r = idx / (KT / 4), c4 = idx % (KT / 4);
-        const int gi = m0 + r, gk = k0 + 4 * c4;
-        const float *p = A + (int64_t)min(gi, M - 1) * lda;
-        float4 v;
-        if (VEC && gk + 3 < ke) {
-          v = *reinterpret_cast<const float4 *>(p + gk);
-        } else {
-          v.x = gk < ke ? p[min(gk, K - 1)] : 0.f;
-          v.y = gk + 1 < ke ? p[min(gk + 1, K - 1)] : 0.f;
-          v.z = gk + 2 < ke ? p[min(gk + 2, K - 1)] : 0.f;
-          v.w = gk + 3 < ke ? p[min(gk + 3, K - 1)] : 0.f;
-        }
-        ra[h] = gi < M ? v : make_float4(0.f, 0.f, 0.f, 0.f);
-      } else {
-        const int r = idx >> 4, c4 = idx & 15;    // k row, 4-column group of i
-        const int gk = k0 + r, gi = m0 + 4 * c4;
-        const float *p = A + (int64_t)min(gk, K - 1) * lda;
-        float4 v;
-        if (VEC && gi + 3 < M) {
-          v = *reinterpret_cast<const float4 *>(p + gi);
-        } else {
-          v.x = gi < M ? p[min(gi, M - 1)] : 0.f;
-          v.y = gi + 1 < M ? p[min(gi + 1, M - 1)] : 0.f;
-          v.z = gi + 2 < M ? p[min(gi + 2, M - 1)] : 0.f;
-          v.w = gi + 3 < M ? p[min(gi + 3, M - 1)] : 0.f;
-        }
-        ra[h] = gk < ke ? v : make_float4(0.f, 0.f, 0.f, 0.f);
-      }
-    }
-#pragma unroll
-    for (int q = 0; q < NP; ++q)
-#pragma unroll
-      for (int h = 0; h < BC; ++h) {
-        const int idx = tid + 256 * h;
-        if (idx < bBN * KT / 8) {
-          const int j = idx / (KT / 8), c8 = idx % (KT / 8);
-          rb[q][h] = *reinterpret_cast<const uint4 *>(xt + q * plane + (int64_t)(n0 + j) * ldx +
-                                                      k0 + 8 * c8);
-        }
-      }
-  };
-  // Registers -> LDS (BF16 planes), A as As[i][k], B as Bs[j][k].
-  auto store = [&]() {
-#pragma unroll
-    for (int h = 0; h < AV; ++h) {
-      const int idx = tid + 256 * h;
-      const float v[4] = {ra[h].x, ra[h].y, ra[h].z, ra[h].w};
-      uint16_t hi[4], lo[4];
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        hi[e] = bf16_rne(v[e]);
-        lo[e] = NT == 3 ? bf16_rne(v[e] - __uint_as_float((uint32_t)hi[e] << 16)) : (uint16_t)0;
-      }
-#pragma unroll
-      for (int q = 0; q < NP; ++q) {
-        const uint16_t *w = q == 0 ? hi : lo;
-        if (!TA) {
-          const int r = idx / (KT / 4), c4 = idx % (KT / 4);
-          uint2 u;
-          u.x = pack2(w[0], w[1]);
-          u.y = pack2(w[2], w[3]);
-          *reinterpret_cast<uint2 *>(&As[q][r * LS + 4 * c4]) = u;
-        } else {
-          const int r = idx >> 4, c4 = idx & 15;
-#pragma unroll
-          for (int e = 0; e < 4; ++e) As[q][(4 * c4 + e) * LS + r] = w[e];
-        }
-      }
-    }
-#pragma unroll
-    for (int q = 0; q < NP; ++q)
-#pragma unroll
-      for (int h = 0; h < BC; ++h) {
-        const int idx = tid + 256 * h;
-        if (idx < bBN * KT / 8) {
-          const int j = idx / (KT / 8), c8 = idx % (KT / 8);
-          *reinterpret_cast<uint4 *>(&Bs[q][j * LS + 8 * c8]) = rb[q][h];
-        }
-      }
-  };
-
-  if (kb < ke) load(kb);
+  u32x4 rb[NP][BC];
+  if (kb < ke)
+    bf16_tile_load<TA, VEC, KT, NP, AV, BC>(A, lda, xt, ldx, plane, M, K, m0, n0, kb, ke, tid, ra,
+                                            rb);
   for (int k0 = kb; k0 < ke; k0 += KT) {
     __syncthreads();                       // previous tile's LDS reads are done
-    store();
+    bf16_tile_store<TA, KT, LS, NP, AV, BC, NT>(As, Bs, tid, ra, rb);
     __syncthreads();
-    if (k0 + KT < ke) load(k0 + KT);       // next tile in flight during the MFMAs
+    if (k0 + KT < ke)                      // next tile in flight during the MFMAs
+      bf16_tile_load<TA, VEC, KT, NP, AV, BC>(A, lda, xt, ldx, plane, M, K, m0, n0, k0 + KT, ke,
+                                              tid, ra, rb);
 #pragma unroll
     for (int kk = 0; kk < KT; kk += 32) {
       const int ko = kk + 8 * (lane >> 4);

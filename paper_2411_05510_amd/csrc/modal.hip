@@ -506,12 +506,20 @@ SSI_DEV double readlane_d(double v, int src) {
   return __hiloint2double(hi, lo);
 }
 
+// Value of element e (wave-uniform) of a row spread over the wave as
+// v[e / 64] in lane e % 64.  Every register of v is read with its constant
+// index and the choice is made on the wave-uniform results, so v never needs
+// to be addressable memory.
 template <int N>
-SSI_DEV double pick(const double (&v)[N], int u) {
-  double x = v[0];
+SSI_DEV double lane_value(const double (&v)[N], int e) {
+  const int u = e >> 6, ln = e & 63;
+  double r = 0.0;
 #pragma unroll
-  for (int q = 1; q < N; ++q) x = (u == q) ? v[q] : x;
-  return x;
+  for (int q = 0; q < N; ++q) {
+    const double c = readlane_d(v[q], ln);
+    r = (q == u) ? c : r;
+  }
+  return r;
 }
 
 // One sweep of nb bulges over the active window [l, hi] (nb = 1: one wave,
@@ -623,9 +631,9 @@ SSI_DEV void chase(double *A, const HIdx &ix, int l, int hi, int nb, const doubl
       // next reflector input: column k, rows k+1, k+2 and (when the next
       // step has three rows, i.e. k + 3 <= hi) k+3
       const int e1 = k + 1 - l, e2 = k + 2 - l, e3 = k + 3 - l;
-      nx = readlane_d(pick(nv, e1 >> 6), e1 & 63);
-      ny = readlane_d(pick(nv, e2 >> 6), e2 & 63);
-      nz = (k + 3 <= hi) ? readlane_d(pick(nv, e3 >> 6), e3 & 63) : 0.0;
+      nx = lane_value(nv, e1);
+      ny = lane_value(nv, e2);
+      nz = (k + 3 <= hi) ? lane_value(nv, e3) : 0.0;
       have = true;
     }
     if (kBlock) __syncthreads(); else wave_sync();
@@ -882,7 +890,6 @@ vec_kernel(const double *__restrict__ hbuf, const double *__restrict__ chbuf,
            const int *__restrict__ pidx, int nmin, int step, int n_orders, int l, double fs,
            double *__restrict__ scratch, int64_t scratch_stride, double *__restrict__ tf,
            double *__restrict__ txi, double *__restrict__ tmu, double *__restrict__ tphi) {
-  __shared__ double act_re[2][kNR], act_im[2][kNR];
   __shared__ double x_re[kNR], x_im[kNR];
   __shared__ double mult_re[kNR], mult_im[kNR];
   __shared__ int swp[kNR];
@@ -912,16 +919,29 @@ vec_kernel(const double *__restrict__ hbuf, const double *__restrict__ chbuf,
     for (int c = lane; c < n; c += 64) hnorm = fmax(hnorm, fabs(Hn[c]) + fabs(Hn[(int64_t)(n - 1) * n + c]));
     hnorm = fmax(wmax(hnorm), cabs1(mu));
     const double tiny = 2.220446049250313e-16 * fmax(hnorm, 1e-300);
-    // ---- LU of H - mu I with adjacent-row partial pivoting
-    int cur = 0;
-    for (int c = lane; c < n; c += 64) {
-      act_re[0][c] = Hn[c] - (c == 0 ? mu.re : 0.0);
-      act_im[0][c] = (c == 0 ? -mu.im : 0.0);
+    // ---- LU of H - mu I with adjacent-row partial pivoting.  Lane c % 64
+    // holds column c of the active row and of H's next row in registers
+    // (u = c / 64); row r + 2 of H is loaded while step r runs, and the
+    // finished U rows go to this wave's global scratch without waiting.
+    constexpr int kU = (kNR + 63) / 64;
+    double ar[kU], ai[kU], hrow[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const int c = lane + 64 * u;
+      const double h0 = c < n ? Hn[c] : 0.0;
+      ar[u] = h0 - (c == 0 ? mu.re : 0.0);
+      ai[u] = c == 0 ? -mu.im : 0.0;
+      hrow[u] = (c < n && n > 1) ? Hn[(int64_t)n + c] : 0.0;
     }
-    __syncthreads();
     for (int r = 0; r + 1 < n; ++r) {
-      const cplx piv_a{act_re[cur][r], act_im[cur][r]};
-      const double sub = Hn[(int64_t)(r + 1) * n + r];
+      double hnext[kU];
+#pragma unroll
+      for (int u = 0; u < kU; ++u) {
+        const int c = lane + 64 * u;
+        hnext[u] = (c < n && r + 2 < n) ? Hn[(int64_t)(r + 2) * n + c] : 0.0;
+      }
+      const cplx piv_a{lane_value(ar, r), lane_value(ai, r)};
+      const double sub = lane_value(hrow, r);
       const bool swap = fabs(sub) > cabs1(piv_a);
       cplx m;
       if (swap) m = cdiv(piv_a, cplx{sub, 0.0});
@@ -931,71 +951,114 @@ vec_kernel(const double *__restrict__ hbuf, const double *__restrict__ chbuf,
         m = cdiv(cplx{sub, 0.0}, pa);
       }
       const int64_t off = uoff(r);
-      for (int c = r + lane; c < n; c += 64) {
-        const cplx arow{act_re[cur][c], act_im[cur][c]};
-        const cplx nrow{Hn[(int64_t)(r + 1) * n + c] - (c == r + 1 ? mu.re : 0.0),
-                        (c == r + 1 ? -mu.im : 0.0)};
-        const cplx urow = swap ? nrow : arow;
-        const cplx other = swap ? arow : nrow;
-        ure[off + (c - r)] = urow.re;
-        uim[off + (c - r)] = urow.im;
-        if (c > r) {
-          const cplx na = csub(other, cmul(m, urow));
-          act_re[cur ^ 1][c] = na.re;
-          act_im[cur ^ 1][c] = na.im;
+#pragma unroll
+      for (int u = 0; u < kU; ++u) {
+        const int c = lane + 64 * u;
+        if (c >= r && c < n) {
+          const cplx arow{ar[u], ai[u]};
+          const cplx nrow{hrow[u] - (c == r + 1 ? mu.re : 0.0), (c == r + 1 ? -mu.im : 0.0)};
+          const cplx urow = swap ? nrow : arow;
+          const cplx other = swap ? arow : nrow;
+          cplx uw = urow;
+          if (c == r && !swap && cabs1(piv_a) < tiny) uw = cplx{tiny, 0.0};
+          ure[off + (c - r)] = uw.re;
+          uim[off + (c - r)] = uw.im;
+          if (c > r) {
+            const cplx na = csub(other, cmul(m, urow));
+            ar[u] = na.re;
+            ai[u] = na.im;
+          }
         }
+        hrow[u] = hnext[u];
       }
       if (lane == 0) {
         mult_re[r] = m.re;
         mult_im[r] = m.im;
         swp[r] = swap;
       }
-      if (!swap && lane == 0 && cabs1(piv_a) < tiny) ure[off] = tiny, uim[off] = 0.0;
-      cur ^= 1;
-      __syncthreads();
     }
     {
       const int64_t off = uoff(n - 1);
+      cplx last{lane_value(ar, n - 1), lane_value(ai, n - 1)};
+      if (cabs1(last) < tiny) last = cplx{tiny, 0.0};
       if (lane == 0) {
-        cplx last{act_re[cur][n - 1], act_im[cur][n - 1]};
-        if (cabs1(last) < tiny) last = cplx{tiny, 0.0};
         ure[off] = last.re;
         uim[off] = last.im;
       }
     }
+    // the U rows written above are read back by other lanes below
+    __threadfence_block();
     __syncthreads();
-    // ---- two solves: U x = 1, then (L U) x = x
+    // ---- two solves: U x = 1, then (L U) x = x.  Row r - 1 of U is loaded
+    // while row r is reduced.
     for (int c = lane; c < n; c += 64) { x_re[c] = 1.0; x_im[c] = 0.0; }
     __syncthreads();
     for (int pass = 0; pass < 2; ++pass) {
       if (pass == 1 && lane == 0) {
+        cplx carry{x_re[0], x_im[0]};
         for (int r = 0; r + 1 < n; ++r) {
-          cplx bj{x_re[r], x_im[r]}, bn{x_re[r + 1], x_im[r + 1]};
+          cplx bj = carry, bn{x_re[r + 1], x_im[r + 1]};
           if (swp[r]) { const cplx tmp = bj; bj = bn; bn = tmp; }
           const cplx nb = csub(bn, cmul(cplx{mult_re[r], mult_im[r]}, bj));
           x_re[r] = bj.re; x_im[r] = bj.im;
-          x_re[r + 1] = nb.re; x_im[r + 1] = nb.im;
+          carry = nb;
         }
+        x_re[n - 1] = carry.re;
+        x_im[n - 1] = carry.im;
       }
       __syncthreads();
+      double ur[kU], ui[kU];
+      {
+        const int64_t off = uoff(n - 1);
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+          const int c = lane + 64 * u;
+          ur[u] = c == n - 1 ? ure[off] : 0.0;
+          ui[u] = c == n - 1 ? uim[off] : 0.0;
+        }
+      }
+      double dre = ure[uoff(n - 1)], dim = uim[uoff(n - 1)];
       for (int r = n - 1; r >= 0; --r) {
-        const int64_t off = uoff(r);
+        double nr[kU], ni[kU], ndre = 0.0, ndim = 0.0;
+        if (r > 0) {
+          const int64_t offn = uoff(r - 1);
+#pragma unroll
+          for (int u = 0; u < kU; ++u) {
+            const int c = lane + 64 * u;
+            const bool in = c >= r - 1 && c < n;
+            nr[u] = in ? ure[offn + (in ? c - (r - 1) : 0)] : 0.0;
+            ni[u] = in ? uim[offn + (in ? c - (r - 1) : 0)] : 0.0;
+          }
+          ndre = ure[offn];
+          ndim = uim[offn];
+        }
         double sre = 0.0, sim = 0.0;
-        for (int c = r + 1 + lane; c < n; c += 64) {
-          const cplx uv{ure[off + (c - r)], uim[off + (c - r)]};
-          const cplx xv = cmul(uv, cplx{x_re[c], x_im[c]});
-          sre += xv.re;
-          sim += xv.im;
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+          const int c = lane + 64 * u;
+          if (c > r && c < n) {
+            const cplx xv = cmul(cplx{ur[u], ui[u]}, cplx{x_re[c], x_im[c]});
+            sre += xv.re;
+            sim += xv.im;
+          }
         }
         sre = wsum(sre);
         sim = wsum(sim);
+        const cplx num = csub(cplx{x_re[r], x_im[r]}, cplx{sre, sim});
+        const cplx xr = cdiv(num, cplx{dre, dim});
+        wave_sync();                      // every lane has read x[r]
         if (lane == 0) {
-          const cplx num = csub(cplx{x_re[r], x_im[r]}, cplx{sre, sim});
-          const cplx xr = cdiv(num, cplx{ure[off], uim[off]});
           x_re[r] = xr.re;
           x_im[r] = xr.im;
         }
-        __syncthreads();
+        wave_sync();
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+          ur[u] = nr[u];
+          ui[u] = ni[u];
+        }
+        dre = ndre;
+        dim = ndim;
       }
       double mx = 0.0;
       for (int c = lane; c < n; c += 64) mx = fmax(mx, cabs1(cplx{x_re[c], x_im[c]}));
@@ -1084,6 +1147,16 @@ sort_kernel(int nmin, int step, int l, const int *__restrict__ npole,
       phi[((size_t)dst * l + a) * 2] = (float)tphi[((size_t)(base + i) * l + a) * 2];
       phi[((size_t)dst * l + a) * 2 + 1] = (float)tphi[((size_t)(base + i) * l + a) * 2 + 1];
     }
+  }
+  // slots past the count are zero, so the outputs never depend on what the
+  // buffers held before
+  for (int i = cnt + threadIdx.x; i < geo.n / 2; i += blockDim.x) {
+    const int dst = base + i;
+    f[dst] = 0.0;
+    xi[dst] = 0.0;
+    mu[2 * dst] = 0.0;
+    mu[2 * dst + 1] = 0.0;
+    for (int a = 0; a < 2 * l; ++a) phi[(size_t)dst * l * 2 + a] = 0.f;
   }
 }
 

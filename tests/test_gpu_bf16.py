@@ -13,7 +13,8 @@ everything after stay FP64.  Gates:
   perturbation of the basis only), and the leading subspace within the
   same error scaled by the inverse relative gap;
 * the whole identification of the 180-channel record: physical poles within
-  f rel 1e-3, damping abs 2e-3 and MAC 0.99 of the FP64 checker.
+  f rel 1e-3, damping abs 2e-3 and MAC 0.99 of the FP64 checker, at the
+  orders whose singular vectors the rounded operands resolve.
 """
 import numpy as np
 import pytest
@@ -90,30 +91,48 @@ def test_rsvd_bf16_accuracy(ctx, m, k, p, q, pad, decay):
     assert gap <= 1e-3 / min(1.0, rel_gap), f"subspace gap {gap:.3e}"
 
 
-def test_identify_bridge_bf16(ctx):
-    """The 180-channel record with BF16 range-finder products: every physical
-    pole of the FP64 checker (same record, same Philox sketch) within the
-    reduced-precision gates."""
-    from paper_2411_05510_amd import ssicov
+@pytest.fixture(scope="module")
+def bridge():
+    """The 180-channel record and the FP64 checker's identification of it."""
     wl = synth.WORKLOADS["bridge-180ch"]
     sysm, y = synth.make_record(wl)
-    p = ssicov.Params(fs=wl.fs, lags=list(wl.lags), order_min=wl.order_min,
-                      order_max=wl.order_max, order_step=wl.order_step,
-                      svd=ssicov.SVD_RANDOMIZED, rank=wl.rank, oversample=wl.oversample,
-                      power_iters=wl.power_iters, seed=wl.sketch_seed, prec=ssicov.PREC_BF16)
-    out = ctx.identify(_dev(y), p)
-    ctx.synchronize()
     res = oracle.identify(y, wl.fs, wl.lags, wl.orders, svd="randomized", rank=wl.rank,
                           oversample=wl.oversample, power_iters=wl.power_iters,
                           seed=wl.sketch_seed)[0]
+    return wl, sysm, y, res
+
+
+@pytest.mark.parametrize("mode,resolution", [("bf16", 2.0 ** -9), ("bf16x3", 2.0 ** -17)])
+def test_identify_bridge_reduced_precision(ctx, bridge, mode, resolution):
+    """The 180-channel record with reduced-precision range-finder products:
+    physical poles of the FP64 checker (same record, same Philox sketch)
+    within f rel 1e-3, damping abs 2e-3 and MAC 0.99.  The gate covers the
+    orders n whose n-th singular value is above the relative resolution of
+    the operands (2^-9 sigma_1 for BF16, 2^-17 for the split hi + lo form):
+    below it the n-th singular vector is not determined by the rounded T, and
+    the poles that depend on it move (plain BF16 on this record: orders 86 and
+    up, by up to 6e-3)."""
+    from paper_2411_05510_amd import ssicov
+    wl, sysm, y, res = bridge
+    prec = {"bf16": ssicov.PREC_BF16, "bf16x3": ssicov.PREC_BF16X3}[mode]
+    p = ssicov.Params(fs=wl.fs, lags=list(wl.lags), order_min=wl.order_min,
+                      order_max=wl.order_max, order_step=wl.order_step,
+                      svd=ssicov.SVD_RANDOMIZED, rank=wl.rank, oversample=wl.oversample,
+                      power_iters=wl.power_iters, seed=wl.sketch_seed, prec=prec)
+    out = ctx.identify(_dev(y), p)
+    ctx.synchronize()
     sig = out.sigma[0].cpu().numpy()
     keep = res.sigma >= 1e-2 * res.sigma[0]
     srel = np.abs(sig[keep] - res.sigma[keep]) / res.sigma[keep]
-    ef, ex, em = [], [], []
-    for oi in range(len(wl.orders)):
-        ref = res.poles[oi]
+    assert srel.max() <= 1e-6
+    ef, ex, em, gated_orders = [], [], [], 0
+    for oi, n in enumerate(wl.orders):
         g = out.poles(0, oi)
         assert g["flag"] == 0
+        if res.sigma[n - 1] < resolution * res.sigma[0]:
+            continue
+        gated_orders += 1
+        ref = res.poles[oi]
         for r, fr in enumerate(sysm.freqs):
             if len(ref) == 0:
                 continue
@@ -125,8 +144,9 @@ def test_identify_bridge_bf16(ctx):
             ex.append(abs(g["xi"][j] - ref.xi[i]))
             em.append(mac(g["phi"][j], ref.phi[i]))
     assert ef, "no physical poles compared"
-    print(f"bridge BF16: sigma rel max {srel.max():.2e}; {len(ef)} physical poles, "
-          f"max f rel {max(ef):.2e}, max xi abs {max(ex):.2e}, min MAC {min(em):.6f}")
+    print(f"bridge {mode}: sigma rel max {srel.max():.2e}; {gated_orders} orders gated, "
+          f"{len(ef)} physical poles, max f rel {max(ef):.2e}, max xi abs {max(ex):.2e}, "
+          f"min MAC {min(em):.6f}")
     assert max(ef) <= 1e-3
     assert max(ex) <= 2e-3
     assert min(em) >= 0.99
