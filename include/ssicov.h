@@ -176,7 +176,8 @@ ssi_status ssi_set_lag_streams(ssi_ctx *ctx, int32_t n);
 ssi_status ssi_set_graphs(ssi_ctx *ctx, int enable);
 /* Autotuning of the range-finder products (default off).  When on, the
  * first product of each (precision, orientation, M, N, K) times candidate
- * K-slice counts {2, 4, 6, 8, 12, 16} with HIP events on the context stream
+ * K-slice counts (the planner's own choice, then 2, 4, 6, 8, 12, 16) with
+ * HIP events on the context stream
  * (each candidate computes the full product, so results are unaffected) and
  * keeps the fastest for the life of the context.  Tuning synchronizes the
  * stream once per new shape and never runs inside a graph capture. */

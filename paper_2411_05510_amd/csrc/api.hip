@@ -463,7 +463,7 @@ constexpr int kTuneSplits[] = {2, 4, 6, 8, 12, 16};
 constexpr int kTuneMaxSplits = 16;
 
 template <typename Launch>
-int tuned_splits(ssi_ctx *c, int kind, bool ta, int M, int N, int K, Launch &&run,
+int tuned_splits(ssi_ctx *c, int kind, bool ta, int M, int N, int K, int planned, Launch &&run,
                  hipError_t &err) {
   const auto key = std::make_tuple(kind, ta ? 1 : 0, M, N, K);
   auto it = c->tuned.find(key);
@@ -473,7 +473,13 @@ int tuned_splits(ssi_ctx *c, int kind, bool ta, int M, int N, int K, Launch &&ru
   if (!a || !b) return 0;
   int best = 0;
   float best_ms = 0.f;
-  for (int cand : kTuneSplits) {
+  int cands[1 + sizeof(kTuneSplits) / sizeof(int)];
+  int nc = 0;
+  cands[nc++] = planned;                        // the planner's own choice first
+  for (int v : kTuneSplits)
+    if (v != planned) cands[nc++] = v;
+  for (int ci = 0; ci < nc; ++ci) {
+    const int cand = cands[ci];
     err = run(cand);                            // warm-up
     if (err == hipSuccess) err = hipEventRecord(a, c->stream);
     for (int r = 0; r < 3 && err == hipSuccess; ++r) err = run(cand);
@@ -502,7 +508,8 @@ hipError_t prod_tf64(ssi_ctx *c, bool ta, const float *T, int64_t ldt, const dou
     return ssi::launch_reduce(gp, part, M, N, 1.0, out, ldo, nullptr, 0, c->stream);
   };
   hipError_t err = hipSuccess;
-  const int splits = tuned_splits(c, 0, ta, M, N, K, run, err);
+  const int planned = ssi::plan_gemm_tf64(M, N, K, c->num_cus).splits;
+  const int splits = tuned_splits(c, 0, ta, M, N, K, planned, run, err);
   if (err != hipSuccess) return err;
   return run(splits);
 }
@@ -531,7 +538,7 @@ hipError_t prod_bf16(ssi_ctx *c, bool ta, const float *T, int64_t ldt, const dou
     return ssi::launch_reduce_f32(bp, part, M, N, out, ldo, c->stream);
   };
   hipError_t err = hipSuccess;
-  const int splits = tuned_splits(c, nt, ta, M, N, K, run, err);
+  const int splits = tuned_splits(c, nt, ta, M, N, K, bp0.splits, run, err);
   if (err != hipSuccess) return err;
   return run(splits);
 }
@@ -729,6 +736,7 @@ struct ModalBufs {
   double *xbuf, *hbuf, *qbuf, *vref, *taus, *chbuf, *evbuf, *gscr, *vscr;
   double *tf, *txi, *tmu, *tphi;
   int *npole, *pidx, *flags_tmp;
+  int *queue, *done;
 };
 
 ModalBufs carve_modal(Arena &a, ssi_ctx *c, int64_t m, int l, const ssi_params *p) {
@@ -760,6 +768,8 @@ ModalBufs carve_modal(Arena &a, ssi_ctx *c, int64_t m, int l, const ssi_params *
   b.npole = a.take<int>(b.sz.n_orders);
   b.pidx = a.take<int>(b.sz.vec);
   b.flags_tmp = a.take<int>(b.sz.n_orders);
+  b.queue = a.take<int>(2);
+  b.done = a.take<int>(b.sz.n_orders);
   return b;
 }
 
@@ -798,6 +808,7 @@ ssi_status run_modal(ssi_ctx *c, ModalBufs &b, const double *u, int64_t m, int k
   a.chbuf = b.chbuf; a.evbuf = b.evbuf; a.gscr = b.gscr; a.vscr = b.vscr;
   a.tf = b.tf; a.txi = b.txi; a.tmu = b.tmu; a.tphi = b.tphi;
   a.npole = b.npole; a.pidx = b.pidx; a.flags_tmp = b.flags_tmp;
+  a.queue = b.queue; a.done = b.done; a.status = c->status;
   a.count = out->count + (int64_t)lag_i * no;
   a.flags = out->flags + (int64_t)lag_i * no;
   a.f = out->f + (int64_t)lag_i * pole_cap;

@@ -110,6 +110,8 @@ struct ModalArgs {
   double *xbuf, *hbuf, *qbuf, *vref, *taus, *chbuf, *evbuf, *gscr, *vscr;
   double *tf, *txi, *tmu, *tphi;
   int *npole, *pidx, *flags_tmp;
+  int *queue, *done;            // work counters and per-order flags of the eig launch
+  int *status;                  // context status word
   int32_t *count, *flags;       // outputs of this lag
   double *f, *xi, *mu;
   float *phi;

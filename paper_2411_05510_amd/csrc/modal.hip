@@ -17,6 +17,9 @@
 //   vec         per pole (Im mu > 0): inverse iteration on H - mu I in complex
 //               arithmetic (Hessenberg LU with partial pivoting), psi_H, then
 //               phi = C_h psi_H, normalised; lambda = ln(mu) f_s, f, xi
+//   francis and vec run in one persistent launch (eig_persistent_kernel):
+//   whole orders first, largest first, then poles, smallest orders first,
+//   each waiting for its order's eigenvalues
 //   sort        poles of the order sorted by (f, xi) into the output slots
 #include "common.h"
 #include "kernels.h"
@@ -357,7 +360,7 @@ SSI_DEV int block_max_int(int v, int *red) {
 #pragma unroll
   for (int w = 1; w < kFT / 64; ++w) r = max(r, red[w]);
   __syncthreads();
-  return r;
+  return __builtin_amdgcn_readfirstlane(r);        // uniform: scalar branches on it
 }
 
 // Orders LDS accesses of one wave (the lanes run in lockstep, so a fence
@@ -664,22 +667,18 @@ SSI_DEV void chase(double *A, const HIdx &ix, int l, int hi, int nb, const doubl
 // The column k-1 a wave reads at the start of a stage is changed in that
 // stage only by its own row phase and by the right-hand update of the bulge
 // behind it, which runs after the barrier.
+// A: the matrix storage of this order (LDS = true: the workgroup's LDS).
 template <bool LDS>
-__global__ void __launch_bounds__(kFT)
-francis_kernel(const double *__restrict__ hbuf, int nmin, int step, int o_first,
-               double *__restrict__ gscr, int64_t gstride, double *__restrict__ evbuf,
-               int *__restrict__ npole, int *__restrict__ pidx, int *__restrict__ flags) {
-  extern __shared__ double lds_h[];
-  __shared__ int red[kFT / 64];
-  __shared__ int small_ok;
-  const int o = o_first + blockIdx.x;
+SSI_DEV void francis_order(int o, double *A, const double *__restrict__ hbuf, int nmin, int step,
+                           double *__restrict__ evbuf, int *__restrict__ npole,
+                           int *__restrict__ pidx, int *__restrict__ flags, int *red,
+                           int &small_ok) {
   const OrderGeo geo = order_geo(o, nmin, step);
   const int n = geo.n;
   const double *Hin = hbuf + geo.sq;
   double *wr = evbuf + 2 * geo.vec, *wi = wr + n;
   const int t = threadIdx.x, lane = t & 63;
   const int wave = __builtin_amdgcn_readfirstlane(t >> 6);
-  double *A = LDS ? lds_h : gscr + (size_t)blockIdx.x * gstride;
   const int psz = HIdx::packed_size(n);
   const HIdx ix{n, psz, psz + kRing};
   double *sev = A + psz + 2 * kRing;         // [2][kSM]
@@ -760,7 +759,7 @@ francis_kernel(const double *__restrict__ hbuf, int nmin, int step, int o_first,
         }
       }
       __syncthreads();
-      if (small_ok) {
+      if (__builtin_amdgcn_readfirstlane(small_ok)) {
         hi = l - 1;
         iter = 0;
         continue;
@@ -811,7 +810,7 @@ francis_kernel(const double *__restrict__ hbuf, int nmin, int step, int o_first,
         }
       }
       __syncthreads();
-      if (small_ok) nb = kNB;
+      if (__builtin_amdgcn_readfirstlane(small_ok)) nb = kNB;
     }
     if (nb == 1 && t == 0) {
       double sh, tt;
@@ -852,6 +851,7 @@ francis_kernel(const double *__restrict__ hbuf, int nmin, int step, int o_first,
   }
 }
 
+
 // ------------------------------------------------------------------ vec
 namespace {
 
@@ -881,34 +881,22 @@ SSI_DEV double wmax(double v) {
 
 }  // namespace
 
-// One wave per pole.  Items (order, j) run over a persistent grid; each wave
-// owns scratch for the U rows of its LU.  Writes unsorted poles: f, xi, mu,
-// phi (l complex) at slot pole(o) + j of the temporary arrays.
-__global__ void __launch_bounds__(64)
-vec_kernel(const double *__restrict__ hbuf, const double *__restrict__ chbuf,
-           const double *__restrict__ evbuf, const int *__restrict__ npole,
-           const int *__restrict__ pidx, int nmin, int step, int n_orders, int l, double fs,
-           double *__restrict__ scratch, int64_t scratch_stride, double *__restrict__ tf,
-           double *__restrict__ txi, double *__restrict__ tmu, double *__restrict__ tphi) {
-  __shared__ double x_re[kNR], x_im[kNR];
-  __shared__ double mult_re[kNR], mult_im[kNR];
-  __shared__ int swp[kNR];
-  const int lane = threadIdx.x;
-  double *ure = scratch + (size_t)blockIdx.x * scratch_stride;
-  double *uim = ure + scratch_stride / 2;
-  int total = 0;
-  for (int o = 0; o < n_orders; ++o) total += (nmin + o * step) / 2;
-  for (int item = blockIdx.x; item < total; item += gridDim.x) {
-    // locate (o, j)
-    int o = 0, rem = item;
-    while (rem >= (nmin + o * step) / 2) {
-      rem -= (nmin + o * step) / 2;
-      ++o;
-    }
-    const int j = rem;
+// Vector, mode shape and continuous pole of pole j of order o, by one wave.
+// x_re, x_im, mult_re, mult_im (kNR doubles each) and swp (kNR ints) are this
+// wave's LDS; ure / uim its global scratch for the U rows of the LU.  Writes
+// the unsorted pole f, xi, mu, phi (l complex) at slot pole(o) + j of the
+// temporary arrays.
+SSI_DEV void vec_pole(int o, int j, const double *__restrict__ hbuf,
+                      const double *__restrict__ chbuf, const double *__restrict__ evbuf,
+                      const int *__restrict__ pidx, int nmin, int step, int l, double fs,
+                      double *__restrict__ ure, double *__restrict__ uim, double *x_re,
+                      double *x_im, double *mult_re, double *mult_im, int *swp,
+                      double *__restrict__ tf, double *__restrict__ txi,
+                      double *__restrict__ tmu, double *__restrict__ tphi) {
+  const int lane = threadIdx.x & 63;
+  {
     const OrderGeo geo = order_geo(o, nmin, step);
     const int n = geo.n;
-    if (j >= npole[o]) continue;
     const double *Hn = hbuf + geo.sq;
     const double *wr = evbuf + 2 * geo.vec, *wi = wr + n;
     const int e = pidx[geo.vec + j];
@@ -920,61 +908,71 @@ vec_kernel(const double *__restrict__ hbuf, const double *__restrict__ chbuf,
     hnorm = fmax(wmax(hnorm), cabs1(mu));
     const double tiny = 2.220446049250313e-16 * fmax(hnorm, 1e-300);
     // ---- LU of H - mu I with adjacent-row partial pivoting.  Lane c % 64
-    // holds column c of the active row and of H's next row in registers
-    // (u = c / 64); row r + 2 of H is loaded while step r runs, and the
-    // finished U rows go to this wave's global scratch without waiting.
+    // holds column c of the active row in registers (u = c / 64).  Rows of H
+    // wait in a ring of kRing registers sets: the slot step r consumes is
+    // refilled at once with row r + 1 + kRingV, so every load has kRingV
+    // steps to arrive.  Finished U rows go to this wave's global scratch
+    // without waiting.
     constexpr int kU = (kNR + 63) / 64;
-    double ar[kU], ai[kU], hrow[kU];
+    constexpr int kRingV = 4;
+    double ar[kU], ai[kU];
+    double hq[kRingV][kU];
 #pragma unroll
     for (int u = 0; u < kU; ++u) {
       const int c = lane + 64 * u;
       const double h0 = c < n ? Hn[c] : 0.0;
       ar[u] = h0 - (c == 0 ? mu.re : 0.0);
       ai[u] = c == 0 ? -mu.im : 0.0;
-      hrow[u] = (c < n && n > 1) ? Hn[(int64_t)n + c] : 0.0;
     }
-    for (int r = 0; r + 1 < n; ++r) {
-      double hnext[kU];
+#pragma unroll
+    for (int d = 0; d < kRingV; ++d)
 #pragma unroll
       for (int u = 0; u < kU; ++u) {
-        const int c = lane + 64 * u;
-        hnext[u] = (c < n && r + 2 < n) ? Hn[(int64_t)(r + 2) * n + c] : 0.0;
+        const int c = lane + 64 * u, row = 1 + d;
+        hq[d][u] = (c < n && row < n) ? Hn[(int64_t)row * n + c] : 0.0;
       }
-      const cplx piv_a{lane_value(ar, r), lane_value(ai, r)};
-      const double sub = lane_value(hrow, r);
-      const bool swap = fabs(sub) > cabs1(piv_a);
-      cplx m;
-      if (swap) m = cdiv(piv_a, cplx{sub, 0.0});
-      else {
-        cplx pa = piv_a;
-        if (cabs1(pa) < tiny) pa = cplx{tiny, 0.0};
-        m = cdiv(cplx{sub, 0.0}, pa);
-      }
-      const int64_t off = uoff(r);
+    for (int r0 = 0; r0 + 1 < n; r0 += kRingV) {
 #pragma unroll
-      for (int u = 0; u < kU; ++u) {
-        const int c = lane + 64 * u;
-        if (c >= r && c < n) {
-          const cplx arow{ar[u], ai[u]};
-          const cplx nrow{hrow[u] - (c == r + 1 ? mu.re : 0.0), (c == r + 1 ? -mu.im : 0.0)};
-          const cplx urow = swap ? nrow : arow;
-          const cplx other = swap ? arow : nrow;
-          cplx uw = urow;
-          if (c == r && !swap && cabs1(piv_a) < tiny) uw = cplx{tiny, 0.0};
-          ure[off + (c - r)] = uw.re;
-          uim[off + (c - r)] = uw.im;
-          if (c > r) {
-            const cplx na = csub(other, cmul(m, urow));
-            ar[u] = na.re;
-            ai[u] = na.im;
-          }
+      for (int d = 0; d < kRingV; ++d) {
+        const int r = r0 + d;                       // step r uses row r + 1 (slot d)
+        if (r + 1 >= n) break;
+        const cplx piv_a{lane_value(ar, r), lane_value(ai, r)};
+        const double sub = lane_value(hq[d], r);
+        const bool swap = fabs(sub) > cabs1(piv_a);
+        cplx m;
+        if (swap) m = cdiv(piv_a, cplx{sub, 0.0});
+        else {
+          cplx pa = piv_a;
+          if (cabs1(pa) < tiny) pa = cplx{tiny, 0.0};
+          m = cdiv(cplx{sub, 0.0}, pa);
         }
-        hrow[u] = hnext[u];
-      }
-      if (lane == 0) {
-        mult_re[r] = m.re;
-        mult_im[r] = m.im;
-        swp[r] = swap;
+        const int64_t off = uoff(r);
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+          const int c = lane + 64 * u;
+          if (c >= r && c < n) {
+            const cplx arow{ar[u], ai[u]};
+            const cplx nrow{hq[d][u] - (c == r + 1 ? mu.re : 0.0), (c == r + 1 ? -mu.im : 0.0)};
+            const cplx urow = swap ? nrow : arow;
+            const cplx other = swap ? arow : nrow;
+            cplx uw = urow;
+            if (c == r && !swap && cabs1(piv_a) < tiny) uw = cplx{tiny, 0.0};
+            ure[off + (c - r)] = uw.re;
+            uim[off + (c - r)] = uw.im;
+            if (c > r) {
+              const cplx na = csub(other, cmul(m, urow));
+              ar[u] = na.re;
+              ai[u] = na.im;
+            }
+          }
+          const int row = r + 1 + kRingV;             // refill the slot
+          hq[d][u] = (c < n && row < n) ? Hn[(int64_t)row * n + c] : 0.0;
+        }
+        if (lane == 0) {
+          mult_re[r] = m.re;
+          mult_im[r] = m.im;
+          swp[r] = swap;
+        }
       }
     }
     {
@@ -988,11 +986,11 @@ vec_kernel(const double *__restrict__ hbuf, const double *__restrict__ chbuf,
     }
     // the U rows written above are read back by other lanes below
     __threadfence_block();
-    __syncthreads();
-    // ---- two solves: U x = 1, then (L U) x = x.  Row r - 1 of U is loaded
-    // while row r is reduced.
+    wave_sync();
+    // ---- two solves: U x = 1, then (L U) x = x.  Rows of U wait in a ring
+    // as above, kRingV rows ahead of the row being reduced.
     for (int c = lane; c < n; c += 64) { x_re[c] = 1.0; x_im[c] = 0.0; }
-    __syncthreads();
+    wave_sync();
     for (int pass = 0; pass < 2; ++pass) {
       if (pass == 1 && lane == 0) {
         cplx carry{x_re[0], x_im[0]};
@@ -1006,66 +1004,69 @@ vec_kernel(const double *__restrict__ hbuf, const double *__restrict__ chbuf,
         x_re[n - 1] = carry.re;
         x_im[n - 1] = carry.im;
       }
-      __syncthreads();
-      double ur[kU], ui[kU];
-      {
-        const int64_t off = uoff(n - 1);
+      wave_sync();
+      // slot d holds row r0 - d: its off-diagonal part (uq) and diagonal (dq)
+      double uqr[kRingV][kU], uqi[kRingV][kU], dqr[kRingV], dqi[kRingV];
+#pragma unroll
+      for (int d = 0; d < kRingV; ++d) {
+        const int rr = n - 1 - d;
+        const int64_t o2 = rr >= 0 ? uoff(rr) : 0;
 #pragma unroll
         for (int u = 0; u < kU; ++u) {
           const int c = lane + 64 * u;
-          ur[u] = c == n - 1 ? ure[off] : 0.0;
-          ui[u] = c == n - 1 ? uim[off] : 0.0;
+          const bool in = rr >= 0 && c > rr && c < n;
+          uqr[d][u] = in ? ure[o2 + (c - rr)] : 0.0;
+          uqi[d][u] = in ? uim[o2 + (c - rr)] : 0.0;
         }
+        dqr[d] = rr >= 0 ? ure[o2] : 1.0;
+        dqi[d] = rr >= 0 ? uim[o2] : 0.0;
       }
-      double dre = ure[uoff(n - 1)], dim = uim[uoff(n - 1)];
-      for (int r = n - 1; r >= 0; --r) {
-        double nr[kU], ni[kU], ndre = 0.0, ndim = 0.0;
-        if (r > 0) {
-          const int64_t offn = uoff(r - 1);
+      for (int r0 = n - 1; r0 >= 0; r0 -= kRingV) {
+#pragma unroll
+        for (int d = 0; d < kRingV; ++d) {
+          const int r = r0 - d;
+          if (r < 0) break;
+          double sre = 0.0, sim = 0.0;
 #pragma unroll
           for (int u = 0; u < kU; ++u) {
             const int c = lane + 64 * u;
-            const bool in = c >= r - 1 && c < n;
-            nr[u] = in ? ure[offn + (in ? c - (r - 1) : 0)] : 0.0;
-            ni[u] = in ? uim[offn + (in ? c - (r - 1) : 0)] : 0.0;
+            if (c > r && c < n) {
+              const cplx xv = cmul(cplx{uqr[d][u], uqi[d][u]}, cplx{x_re[c], x_im[c]});
+              sre += xv.re;
+              sim += xv.im;
+            }
           }
-          ndre = ure[offn];
-          ndim = uim[offn];
-        }
-        double sre = 0.0, sim = 0.0;
+          const double dre = dqr[d], dim = dqi[d];
+          // refill the slot with row r - kRingV
+          const int rr = r - kRingV;
+          const int64_t o2 = rr >= 0 ? uoff(rr) : 0;
 #pragma unroll
-        for (int u = 0; u < kU; ++u) {
-          const int c = lane + 64 * u;
-          if (c > r && c < n) {
-            const cplx xv = cmul(cplx{ur[u], ui[u]}, cplx{x_re[c], x_im[c]});
-            sre += xv.re;
-            sim += xv.im;
+          for (int u = 0; u < kU; ++u) {
+            const int c = lane + 64 * u;
+            const bool in = rr >= 0 && c > rr && c < n;
+            uqr[d][u] = in ? ure[o2 + (c - rr)] : 0.0;
+            uqi[d][u] = in ? uim[o2 + (c - rr)] : 0.0;
           }
+          dqr[d] = rr >= 0 ? ure[o2] : 1.0;
+          dqi[d] = rr >= 0 ? uim[o2] : 0.0;
+          sre = wsum(sre);
+          sim = wsum(sim);
+          const cplx num = csub(cplx{x_re[r], x_im[r]}, cplx{sre, sim});
+          const cplx xr = cdiv(num, cplx{dre, dim});
+          wave_sync();                    // every lane has read x[r]
+          if (lane == 0) {
+            x_re[r] = xr.re;
+            x_im[r] = xr.im;
+          }
+          wave_sync();
         }
-        sre = wsum(sre);
-        sim = wsum(sim);
-        const cplx num = csub(cplx{x_re[r], x_im[r]}, cplx{sre, sim});
-        const cplx xr = cdiv(num, cplx{dre, dim});
-        wave_sync();                      // every lane has read x[r]
-        if (lane == 0) {
-          x_re[r] = xr.re;
-          x_im[r] = xr.im;
-        }
-        wave_sync();
-#pragma unroll
-        for (int u = 0; u < kU; ++u) {
-          ur[u] = nr[u];
-          ui[u] = ni[u];
-        }
-        dre = ndre;
-        dim = ndim;
       }
       double mx = 0.0;
       for (int c = lane; c < n; c += 64) mx = fmax(mx, cabs1(cplx{x_re[c], x_im[c]}));
       mx = wmax(mx);
       const double inv = mx > 0.0 ? 1.0 / mx : 1.0;
       for (int c = lane; c < n; c += 64) { x_re[c] *= inv; x_im[c] *= inv; }
-      __syncthreads();
+      wave_sync();
     }
     // ---- phi = C_h psi_H, unit 2-norm, largest-modulus entry real positive
     const double *C = chbuf + (int64_t)l * geo.vec;
@@ -1110,7 +1111,110 @@ vec_kernel(const double *__restrict__ hbuf, const double *__restrict__ chbuf,
       tmu[2 * slot] = mu.re;
       tmu[2 * slot + 1] = mu.im;
     }
+    wave_sync();
+  }
+}
+
+// ------------------------------------------------------------------ eig
+// Eigenvalues and pole vectors of every order in one persistent launch of
+// one workgroup per CU.  Phase 1: each workgroup takes whole orders from a
+// counter, largest first, and runs the QR iteration on them; finishing an
+// order publishes its eigenvalues with a release store of done[o].  Phase 2:
+// once the order counter is exhausted (every order is then held by a running
+// workgroup), each wave takes poles from a second counter, smallest orders
+// first, waits for its order's flag and computes the pole's vector and mode
+// shape.  Poles of small orders therefore run beside the QR iterations of the
+// large ones.  The wait is bounded: a flag not seen within kEigSpinLimit
+// polls sets bit 4 of the status word and the pole is skipped.
+namespace {
+constexpr int kEigGrid = 256;                       // workgroups (one per CU)
+constexpr int kVecLds = 5 * kNR;                    // per-wave LDS of a pole item (doubles)
+constexpr long kEigSpinLimit = 1L << 24;
+static_assert(kFT / 64 * kVecLds <= kLdsDoubles, "pole items fit the workgroup's LDS");
+}  // namespace
+
+__global__ void __launch_bounds__(kFT)
+eig_init_kernel(int *__restrict__ queue, int *__restrict__ done, int n_orders) {
+  for (int i = threadIdx.x; i < n_orders + 2; i += blockDim.x) {
+    if (i < 2) queue[i] = 0;
+    else done[i - 2] = 0;
+  }
+}
+
+__global__ void __launch_bounds__(kFT)
+eig_persistent_kernel(const double *__restrict__ hbuf, const double *__restrict__ chbuf,
+                      int nmin, int step, int n_orders, int l, double fs,
+                      double *__restrict__ gscr, int64_t gstride, double *__restrict__ evbuf,
+                      int *__restrict__ npole, int *__restrict__ pidx, int *__restrict__ flags,
+                      double *__restrict__ vscr, int64_t vstride, double *__restrict__ tf,
+                      double *__restrict__ txi, double *__restrict__ tmu,
+                      double *__restrict__ tphi, int *__restrict__ queue, int *__restrict__ done,
+                      int *__restrict__ status) {
+  extern __shared__ double lds_h[];
+  __shared__ int red[kFT / 64];
+  __shared__ int small_ok, item;
+  const int t = threadIdx.x, lane = t & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(t >> 6);
+  // ---- phase 1: orders, largest first.  The loop exit is a wave-uniform
+  // (scalar) branch, and thread 0's publish-and-claim is a single region
+  // between two barriers: with the item read as a per-lane value, or the
+  // claim and the publish as two separate thread-0 regions around the back
+  // edge, the compiler may let lanes 1..63 of wave 0 re-enter the body
+  // without thread 0 and re-read the old item.
+  if (t == 0) item = atomicAdd(&queue[0], 1);
+  __syncthreads();
+  for (;;) {
+    const int it = __builtin_amdgcn_readfirstlane(item);
+    __syncthreads();                                // every wave has read item
+    if (it >= n_orders) break;
+    const int o = n_orders - 1 - it;
+    if (nmin + o * step <= kLdsMaxN)
+      francis_order<true>(o, lds_h, hbuf, nmin, step, evbuf, npole, pidx, flags, red, small_ok);
+    else
+      francis_order<false>(o, gscr + (size_t)o * gstride, hbuf, nmin, step, evbuf, npole, pidx,
+                           flags, red, small_ok);
+    __threadfence();
     __syncthreads();
+    if (t == 0) {
+      __hip_atomic_store(&done[o], 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      item = atomicAdd(&queue[0], 1);
+    }
+    __syncthreads();
+  }
+  // ---- phase 2: poles, smallest orders first
+  __syncthreads();                                  // LDS of the QR iteration is free
+  double *x_re = lds_h + wave * kVecLds;
+  double *x_im = x_re + kNR, *mult_re = x_im + kNR, *mult_im = mult_re + kNR;
+  int *swp = reinterpret_cast<int *>(mult_im + kNR);
+  const int gw = blockIdx.x * (kFT / 64) + wave;
+  double *ure = vscr + (size_t)gw * vstride;
+  double *uim = ure + vstride / 2;
+  int total = 0;
+  for (int o = 0; o < n_orders; ++o) total += (nmin + o * step) / 2;
+  for (;;) {
+    int it = 0;
+    if (lane == 0) it = atomicAdd(&queue[1], 1);
+    it = __builtin_amdgcn_readfirstlane(__shfl(it, 0, 64));
+    if (it >= total) break;
+    int o = 0, rem = it;
+    while (rem >= (nmin + o * step) / 2) {
+      rem -= (nmin + o * step) / 2;
+      ++o;
+    }
+    int ready = 0;
+    if (lane == 0) {
+      long spins = 0;
+      while (!(ready = __hip_atomic_load(&done[o], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT)) &&
+             ++spins < kEigSpinLimit)
+        __builtin_amdgcn_s_sleep(8);
+      if (!ready) atomicOr(status, 4);
+    }
+    ready = __builtin_amdgcn_readfirstlane(__shfl(ready, 0, 64));
+    if (!ready) continue;
+    (void)__hip_atomic_load(&done[o], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);  // every lane
+    if (rem >= npole[o]) continue;
+    vec_pole(o, rem, hbuf, chbuf, evbuf, pidx, nmin, step, l, fs, ure, uim, x_re, x_im, mult_re,
+             mult_im, swp, tf, txi, tmu, tphi);
   }
 }
 
@@ -1178,7 +1282,7 @@ ModalSizes modal_sizes(int nmin, int nmax, int step, int l) {
   s.vref = (int64_t)s.n_orders * kNR * kNR;
   s.taus = (int64_t)s.n_orders * kNR;
   s.ch = (int64_t)l * s.vec;
-  s.vec_waves = 1024;
+  s.vec_waves = (int64_t)kEigGrid * (kFT / 64);
   s.vec_stride = 2 * ((int64_t)kNR * (kNR + 1) / 2 + 64);
   s.francis_glb = (int64_t)HIdx::packed_size(kNR) + kExtra;
   return s;
@@ -1195,26 +1299,16 @@ hipError_t launch_modal(const ModalArgs &a, hipStream_t st) {
                      a.qbuf);
   hipLaunchKernelGGL(ch_kernel, dim3(32, no), dim3(256), 0, st, a.u, a.ldu, a.l, a.nmin, a.step,
                      a.qbuf, a.chbuf);
-  // orders with n <= 200 keep H in LDS; larger ones use global scratch
-  int n_lds = 0;
-  for (int o = 0; o < no; ++o)
-    if (a.nmin + o * a.step <= kLdsMaxN) n_lds = o + 1;
-  if (n_lds > 0) {
-    hipError_t e = hipFuncSetAttribute((const void *)francis_kernel<true>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       (int)(sizeof(double) * kLdsDoubles));
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(francis_kernel<true>, dim3(n_lds), dim3(kFT),
-                       sizeof(double) * kLdsDoubles, st, a.hbuf, a.nmin, a.step, 0, a.gscr,
-                       s.francis_glb, a.evbuf, a.npole, a.pidx, a.flags_tmp);
-  }
-  if (n_lds < no)
-    hipLaunchKernelGGL(francis_kernel<false>, dim3(no - n_lds), dim3(kFT), 0, st, a.hbuf,
-                       a.nmin, a.step, n_lds, a.gscr, s.francis_glb, a.evbuf, a.npole, a.pidx,
-                       a.flags_tmp);
-  hipLaunchKernelGGL(vec_kernel, dim3((unsigned)s.vec_waves), dim3(64), 0, st, a.hbuf, a.chbuf,
-                     a.evbuf, a.npole, a.pidx, a.nmin, a.step, no, a.l, a.fs, a.vscr,
-                     s.vec_stride, a.tf, a.txi, a.tmu, a.tphi);
+  // QR iterations and pole vectors of all orders in one persistent launch
+  hipLaunchKernelGGL(eig_init_kernel, dim3(1), dim3(kFT), 0, st, a.queue, a.done, no);
+  hipError_t e = hipFuncSetAttribute((const void *)eig_persistent_kernel,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)(sizeof(double) * kLdsDoubles));
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(eig_persistent_kernel, dim3(kEigGrid), dim3(kFT),
+                     sizeof(double) * kLdsDoubles, st, a.hbuf, a.chbuf, a.nmin, a.step, no, a.l,
+                     a.fs, a.gscr, s.francis_glb, a.evbuf, a.npole, a.pidx, a.flags_tmp, a.vscr,
+                     s.vec_stride, a.tf, a.txi, a.tmu, a.tphi, a.queue, a.done, a.status);
   hipLaunchKernelGGL(sort_kernel, dim3(no), dim3(256), 0, st, a.nmin, a.step, a.l, a.npole,
                      a.flags_tmp, a.tf, a.txi, a.tmu, a.tphi, a.count, a.flags, a.f, a.xi, a.mu,
                      a.phi);

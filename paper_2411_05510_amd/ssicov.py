@@ -113,6 +113,9 @@ def lib() -> ctypes.CDLL:
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is missing: run __graft_entry__.build() first")
+        # torch ships its own HIP runtime; load it first so that this library
+        # binds to the same one and shares its devices, streams and memory
+        import torch  # noqa: F401
         L = ctypes.CDLL(LIB_PATH)
         vp, i32, i64, u32, u64 = (ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64,
                                   ctypes.c_uint32, ctypes.c_uint64)

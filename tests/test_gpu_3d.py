@@ -127,8 +127,8 @@ def test_autotune_records_choice():
     ctx.synchronize()
     m = MID.lags[-1] * MID.l
     ell = MID.rank + MID.oversample
-    assert ctx.tuned_splits(0, False, m, ell, m) in (2, 4, 6, 8, 12, 16)
-    assert ctx.tuned_splits(0, True, m, ell, m) in (2, 4, 6, 8, 12, 16)
+    assert 1 <= ctx.tuned_splits(0, False, m, ell, m) <= 16
+    assert 1 <= ctx.tuned_splits(0, True, m, ell, m) <= 16
     got = _snapshot(out)
     assert torch.equal(got["count"], ref["count"])
     np.testing.assert_allclose(got["sigma"].cpu().numpy(), ref["sigma"].cpu().numpy(), rtol=1e-10)
