@@ -298,8 +298,9 @@ constexpr int kFT = 64 * kNB;            // one wave per bulge
 constexpr int kSM = 2 * kNB;             // order of the trailing block that supplies shifts
 constexpr int kRing = 16;                // bulge-slot ring rows, >= 3 kNB + 1, power of two
 constexpr int kMsMin = 24;               // active windows from this size use multishift sweeps
-// LDS after the packed H: bulge slots (2 kRing), the shift block's
-// eigenvalues (2 kSM), shift pairs (2 kNB) and the shift block (kSM^2).
+// LDS after the packed H: bulge slots (2 kRing), shift pairs (2 kNB), the
+// shift block's eigenvalues (2 kSM) and the shift block (kSM^2); the last two
+// hold a window's reflectors during a multishift sweep.
 constexpr int kExtra = 2 * kRing + 2 * kSM + 2 * kNB + kSM * kSM;
 constexpr int kLdsMaxN = 200;
 constexpr int kRowIt = (kNR + 63) / 64;  // panel elements per lane in a bulge step
@@ -525,12 +526,10 @@ SSI_DEV double lane_value(const double (&v)[N], int e) {
   return r;
 }
 
-// One sweep of nb bulges over the active window [l, hi] (nb = 1: one wave,
-// wave-level ordering only).  Wave b carries bulge b; shp holds the shift
-// pairs (s, t).
-template <bool kBlock>
-SSI_DEV void chase(double *A, const HIdx &ix, int l, int hi, int nb, const double *shp,
-                   int wave, int lane) {
+// One double-shift sweep over the active window [l, hi] by one wave (the
+// shift pair (s, t) in shp[0..1]); wave-level ordering only.
+SSI_DEV void chase1(double *A, const HIdx &ix, int l, int hi, const double *shp, int lane) {
+  constexpr int nb = 1, wave = 0;
   const int psz = ix.b2;
   const int stages = (hi - l) + 3 * (nb - 1);
   // The column a bulge needs at its next step is the one its own right-hand
@@ -599,7 +598,7 @@ SSI_DEV void chase(double *A, const HIdx &ix, int l, int hi, int nb, const doubl
         if (three) A[psz + kRing + ((k + 2) & (kRing - 1))] = 0.0;
       }
     }
-    if (kBlock) __syncthreads(); else wave_sync();
+    wave_sync();
     if (act) {
       // columns k..k+2 over rows l..min(k+3, hi); entries (k+2, k),
       // (k+3, k) and (k+3, k+1) are bulge slots
@@ -639,7 +638,202 @@ SSI_DEV void chase(double *A, const HIdx &ix, int l, int hi, int nb, const doubl
       nz = (k + 3 <= hi) ? lane_value(nv, e3) : 0.0;
       have = true;
     }
-    if (kBlock) __syncthreads(); else wave_sync();
+    wave_sync();
+  }
+}
+
+// One sweep of kNB bulges over the active window [l, hi] in windows of
+// kAdv stages (stage st puts bulge b, carried by wave b, at row k = l + st -
+// 3 b).  The rows and columns [w0, w1) of a window, w0 = l + st0 - 3 (kNB -
+// 1) and w1 = l + st0 + kAdv + 3 for its first stage st0, hold everything the
+// chain reads in those kAdv stages.  Inside the window each reflector is
+// applied from the left over columns k..w1-1 and from the right over rows
+// w0..k+3, so every phase is one element per lane.  The rest of its rows
+// (columns w1..hi) and of its columns (rows l..w0-1) is brought up to date
+// after the window: each thread takes one such column or row segment of kWin
+// entries into registers and applies the window's reflectors, recorded in
+// refl, in stage order.  Reflector (s, b) of a window touches local rows s +
+// 3 (kNB - 1 - b) .. + 2 whatever the window, so the registers are addressed
+// at compile time.  Reflectors of one stage touch disjoint rows and commute.
+// Nothing outside the window is read before it is brought up to date: a
+// window's left updates stay in its rows, its right updates in its columns,
+// and the next window starts after the deferred updates.
+constexpr int kAdv = 8;                  // stages per window
+constexpr int kWin = kAdv + 3 * kNB;     // rows and columns of a window
+static_assert(kWin <= 64, "a window row or column fits one wave");
+static_assert(3 * kNB * kAdv <= 2 * kSM + kSM * kSM, "a window's reflectors fit the shift area");
+
+// x <- P_r x for the window's reflectors r in stage order (from the left on a
+// column segment; from the right on a row segment, P_r being symmetric).
+SSI_DEV void win_apply(double (&x)[kWin], const double *refl) {
+  int off = 0;
+#pragma unroll
+  for (int s = 0; s < kAdv; ++s) {
+    const double *rs = refl + off;
+#pragma unroll
+    for (int b = 0; b < kNB; ++b) {
+      const int lr = s + 3 * (kNB - 1 - b);
+      const double v1 = rs[3 * b], v2 = rs[3 * b + 1], beta = rs[3 * b + 2];
+      const double d = beta * (x[lr] + v1 * x[lr + 1] + v2 * x[lr + 2]);
+      x[lr] -= d;
+      x[lr + 1] -= d * v1;
+      x[lr + 2] -= d * v2;
+    }
+    // The next stage's reflector loads take their address through this
+    // empty asm, which depends on the row this stage finished: the compiler
+    // can neither hoist them nor merge them with this stage's, so one stage
+    // of reflectors at a time is held in registers.
+    off += 3 * kNB;
+    __asm__ volatile("" : "+v"(off) : "v"(x[s]));
+  }
+}
+
+// Reflector of bulge `wave` for its step at row k of a sweep: from the
+// column its previous step left (forwarded in nx, ny, nz when `have`, else read
+// from A), or from its shift pair when it enters at k = l.  beta = 0 when the
+// bulge is outside the active window or there is nothing to annihilate.
+struct Refl { double v1, v2, beta, alpha; };
+SSI_DEV Refl bulge_reflector(const double *A, const HIdx &ix, int l, int hi, int k, int wave,
+                             const double *shp, bool have, double nx, double ny, double nz) {
+  Refl r{0.0, 0.0, 0.0, 0.0};
+  if (wave >= kNB || k < l || k > hi - 1) return r;
+  const bool three = k < hi - 1;
+  double x, y, z;
+  if (have) {
+    x = nx;
+    y = ny;
+    z = nz;
+  } else if (k == l) {
+    const double sh = shp[2 * wave], tt = shp[2 * wave + 1];
+    const double h00 = A[ix(l, l)], h01 = A[ix(l, l + 1)], h10 = A[ix(l + 1, l)];
+    const double h11 = A[ix(l + 1, l + 1)], h21 = A[ix(l + 2, l + 1)];
+    x = h00 * h00 + h01 * h10 - sh * h00 + tt;
+    y = h10 * (h00 + h11 - sh);
+    z = h10 * h21;
+  } else {
+    x = A[ix(k, k - 1)];
+    y = A[ix(k + 1, k - 1)];
+    z = three ? A[ix(k + 2, k - 1)] : 0.0;
+  }
+  householder3(x, y, three ? z : 0.0, r.v1, r.v2, r.beta, r.alpha);
+  return r;
+}
+
+SSI_DEV void chase_win(double *A, const HIdx &ix, int l, int hi, const double *shp,
+                       double *refl, int wave, int lane) {
+  const int t = threadIdx.x;
+  const int psz = ix.b2;
+  const int stages = (hi - l) + 3 * (kNB - 1);
+  // The reflector of a stage is computed at the end of the previous one,
+  // before its closing barrier: the column it reads is the one this bulge's
+  // own right-hand update just produced (forwarded), or entries that no
+  // update of the previous stage's column phase touches.
+  Refl rf = bulge_reflector(A, ix, l, hi, l - 3 * wave, wave, shp, false, 0.0, 0.0, 0.0);
+  for (int st0 = 0; st0 < stages; st0 += kAdv) {
+    const int w0 = l + st0 - 3 * (kNB - 1);
+    const int w1 = l + st0 + kAdv + 3;
+    const int r_beg = max(w0, l);          // first row (and column) of the window
+    const int c_end = min(w1, hi + 1);     // one past its last
+    for (int s = 0; s < kAdv; ++s) {
+      const int k = l + st0 + s - 3 * wave;
+      const bool three = k < hi - 1;
+      const double v1 = rf.v1, v2 = rf.v2, beta = rf.beta;   // v2 = 0 when !three
+      const bool act = beta != 0.0;
+      if (wave < kNB && lane == 0) {
+        double *rs = refl + 3 * (s * kNB + wave);
+        rs[0] = v1;
+        rs[1] = v2;
+        rs[2] = beta;
+      }
+      if (act) {
+        // rows k..k+2 over columns k..c_end-1; entry (k+2, k) is a bulge slot.
+        // Without a third row the third load repeats the second (v2 = 0).
+        const int r0 = ix.base(k), r1 = ix.base(k + 1);
+        const int r2 = three ? ix.base(k + 2) : r1;
+        const int s2 = psz + ((k + 2) & (kRing - 1));
+        if (lane < c_end - k) {
+          const int j = k + lane;
+          const int i0 = r0 + j, i1 = r1 + j;
+          const int i2 = three ? (j == k ? s2 : r2 + j) : i1;
+          const double a0 = A[i0], a1 = A[i1], a2 = A[i2];
+          const double d = beta * (a0 + v1 * a1 + v2 * a2);
+          A[i0] = a0 - d;
+          A[i1] = a1 - d * v1;
+          if (three) A[i2] = a2 - d * v2;
+        }
+        if (k > l && lane == 0) {          // the reflected column k - 1
+          A[r0 + k - 1] = rf.alpha;
+          A[psz + ((k + 1) & (kRing - 1))] = 0.0;
+          if (three) A[psz + kRing + ((k + 2) & (kRing - 1))] = 0.0;
+        }
+      }
+      __syncthreads();
+      bool have = false;
+      double nx = 0.0, ny = 0.0, nz = 0.0;
+      if (act) {
+        // columns k..k+2 over rows r_beg..min(k+3, hi); entries (k+2, k),
+        // (k+3, k) and (k+3, k+1) are bulge slots
+        const int rend = min(k + 3, hi);
+        const int sk2 = psz + ((k + 2) & (kRing - 1));
+        const int sk3 = psz + ((k + 3) & (kRing - 1));
+        double nv = 0.0;
+        if (lane <= rend - r_beg) {
+          const int i = r_beg + lane;
+          const int bi = ix.base(i) + k;
+          const int i0 = i < k + 2 ? bi : (i == k + 2 ? sk2 : sk3 + kRing);
+          const int i1 = i < k + 3 ? bi + 1 : sk3;
+          const int i2 = three ? bi + 2 : i1;
+          const double a0 = A[i0], a1 = A[i1], a2 = A[i2];
+          const double d = beta * (a0 + v1 * a1 + v2 * a2);
+          nv = a0 - d;
+          A[i0] = nv;
+          A[i1] = a1 - d * v1;
+          if (three) A[i2] = a2 - d * v2;
+        }
+        // next reflector input: column k, rows k+1, k+2 and (when the next
+        // step has three rows) k+3
+        nx = readlane_d(nv, k + 1 - r_beg);
+        ny = readlane_d(nv, k + 2 - r_beg);
+        nz = (k + 3 <= hi) ? readlane_d(nv, k + 3 - r_beg) : 0.0;
+        have = true;
+      }
+      rf = bulge_reflector(A, ix, l, hi, k + 1, wave, shp, have, nx, ny, nz);
+      __syncthreads();
+    }
+    // deferred updates: columns w1..hi of the window rows (from the left),
+    // rows l..r_beg-1 of the window columns (from the right)
+    const int n_right = max(0, hi - w1 + 1);
+    const int n_top = r_beg - l;
+    const int r_lo = r_beg - w0, r_hi = c_end - w0;   // local entries inside [l, hi]
+    if (t < n_right + n_top) {
+      // Entry r of this thread's segment sits at s0 + r d - (right ? r (r - 1) / 2 : 0):
+      // a column of rows w0 + r (packed row starts base(w0 + r) = base(w0) + r (n - w0)
+      // - r (r - 1) / 2) or a row over columns w0 + r.  Every entry is loaded, at an
+      // index clamped into the matrix, so the loads carry no branches and issue back to
+      // back.  Entries outside [r_lo, r_hi) are never stored: the reflectors that touch
+      // them have beta = 0 (bulges not yet in, or past, the active window) or v2 = 0
+      // (the last, two-row step), so they only multiply finite values by zero.
+      const bool right = t < n_right;
+      const int s0 = right ? ix.base(w0) + w1 + t : ix.base(l + t - n_right) + w0;
+      const int d = right ? ix.n - w0 : 1;
+      const int rmask = right ? -1 : 0;
+      const unsigned valid = ((1u << r_hi) - 1u) & ~((1u << r_lo) - 1u);
+      double x[kWin];
+      int at = s0;
+#pragma unroll
+      for (int r = 0; r < kWin; ++r) {
+        x[r] = A[min(max(at, 0), psz - 1)];
+        at += d - (r & rmask);
+      }
+      win_apply(x, refl);
+      at = s0;
+#pragma unroll
+      for (int r = 0; r < kWin; ++r) {
+        if ((valid >> r) & 1u) A[at] = x[r];
+        at += d - (r & rmask);
+      }
+    }
+    __syncthreads();
   }
 }
 
@@ -648,22 +842,22 @@ SSI_DEV void chase(double *A, const HIdx &ix, int l, int hi, int nb, const doubl
 // 2 vec(o).  Writes the number of eigenvalues with Im > 0 to npole[o] and
 // their indices to pidx at vec(o); flags[o] = 1 if the iteration limit hit.
 //
-// One workgroup of four waves per order.  Windows of kMsMin rows or more take
-// small-bulge multishift sweeps: the kSM eigenvalues of the trailing kSM x kSM
-// block (computed by one wave) give kNB shift pairs, one per bulge; the
-// bulges enter at the top three rows apart and are chased down together.
-// Smaller windows, and every eleventh sweep without deflation (ad hoc
-// shifts), use one double-shift bulge.  Wave b carries bulge b.  Each stage
-// of a sweep advances every bulge by one row in two phases separated by
+// One workgroup of kNB waves per order.  Active windows of kMsMin rows or
+// more take small-bulge multishift sweeps: the kSM eigenvalues of the
+// trailing kSM x kSM block (computed by one wave) give kNB shift pairs, one
+// per bulge; the bulges enter at the top three rows apart and are chased down
+// together, kAdv rows per window of the sweep (chase_win).  Smaller active
+// windows, and every eleventh sweep without deflation (ad hoc shifts), use
+// one double-shift bulge chased by one wave (chase1).  Wave b carries bulge
+// b.  Each stage advances every bulge by one row in two phases separated by
 // barriers; bulges are three rows apart, so their reflectors touch disjoint
 // rows and columns and commute:
 //   rows      each wave computes its bulge's 3-element reflector (all lanes,
 //             redundantly) from the column its previous step left, or from
-//             its shift pair when it enters, then applies it from the left:
-//             rows k..k+2 over columns k..hi, and sets the reflected column
-//             k-1 to (alpha, 0, 0);
-//   columns   each wave applies its reflector from the right: columns
-//             k..k+2 over rows l..k+3.
+//             its shift pair when it enters, then applies it from the left to
+//             rows k..k+2, and sets the reflected column k-1 to (alpha, 0, 0);
+//   columns   each wave applies its reflector from the right to columns
+//             k..k+2.
 // The column k-1 a wave reads at the start of a stage is changed in that
 // stage only by its own row phase and by the right-hand update of the bulge
 // behind it, which runs after the barrier.
@@ -681,9 +875,10 @@ SSI_DEV void francis_order(int o, double *A, const double *__restrict__ hbuf, in
   const int wave = __builtin_amdgcn_readfirstlane(t >> 6);
   const int psz = HIdx::packed_size(n);
   const HIdx ix{n, psz, psz + kRing};
-  double *sev = A + psz + 2 * kRing;         // [2][kSM]
-  double *shp = sev + 2 * kSM;               // [kNB][2]: s, t of each shift pair
-  double *sblk = shp + 2 * kNB;              // [kSM][kSM]
+  double *shp = A + psz + 2 * kRing;         // [kNB][2]: s, t of each shift pair
+  double *sev = shp + 2 * kNB;               // [2][kSM]
+  double *sblk = sev + 2 * kSM;              // [kSM][kSM]
+  double *refl = sev;                        // during a sweep: [kAdv][kNB][3] reflectors
   for (int i = 0; i < n; ++i) {
     const int j0 = i == 0 ? 0 : i - 1;
     const int rs = ix.row_start(i);
@@ -833,9 +1028,9 @@ SSI_DEV void francis_order(int o, double *A, const double *__restrict__ hbuf, in
     // ---- sweep: nb bulges, bulge b (wave b) enters at stage 3 b; a single
     // bulge needs no block barriers
     if (nb > 1) {
-      chase<true>(A, ix, l, hi, nb, shp, wave, lane);
+      chase_win(A, ix, l, hi, shp, refl, wave, lane);
     } else {
-      if (wave == 0) chase<false>(A, ix, l, hi, 1, shp, 0, lane);
+      if (wave == 0) chase1(A, ix, l, hi, shp, lane);
       __syncthreads();
     }
   }
