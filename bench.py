@@ -37,19 +37,23 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 FP32_MFMA_PEAK_TFLOPS = 157.3       # MI355X dense FP32 matrix peak
+BF16_MFMA_PEAK_TFLOPS = 2500.0      # MI355X dense BF16 matrix peak
 HBM_PEAK_GBS = 8000.0
 COPY_PROBE_BYTES = 256 << 20        # plain device copy used to calibrate HBM byte counters
-PMC_SUMMARY = os.path.join(ROOT, "profiles", "correlate_mfma_bridge180_pmc.md")
+PMC_SUMMARY = {"fp32": os.path.join(ROOT, "profiles", "correlate_mfma_bridge180_pmc.md"),
+               "bf16x6": os.path.join(ROOT, "profiles", "correlate_b6_bridge180_pmc.md")}
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2411_05510_amd", "csrc", "correlate.hip")
 PRECS = {"fp32": 0, "bf16": 1, "bf16x3": 2}
+CORR_MODES = {"fp32": 0, "bf16x6": 1}
+CORR_KERNEL = {"fp32": "correlate_mfma", "bf16x6": "correlate_b6"}
 
 
-def measured_traffic():
-    """HBM bytes per correlate_mfma launch from the committed counter summary,
-    or None when the summary is missing or the kernel source has changed since
-    the counters were taken."""
+def measured_traffic(corr: str):
+    """HBM bytes per launch of the correlation kernel of mode `corr` from the
+    committed counter summary, or None when the summary is missing or the
+    kernel source has changed since the counters were taken."""
     try:
-        text = open(PMC_SUMMARY).read()
+        text = open(PMC_SUMMARY[corr]).read()
         src = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
     except OSError:
         return None
@@ -85,21 +89,32 @@ def params_of(wl, prec: int):
                          power_iters=wl.power_iters, seed=wl.sketch_seed, prec=prec)
 
 
-def roofline(stages, l, n, L):
+def roofline(stages, l, n, L, corr: str):
+    """Roofline of the correlation contraction kernel.  FP32 mode: algorithmic
+    flops against the FP32 matrix peak.  BF16x6 mode: every FP32 product is six
+    BF16 products, so the kernel's algorithmic BF16 work is six times the
+    contraction's flops, against the BF16 matrix peak; the FP32-equivalent rate
+    is reported beside it."""
     flops = corr_flops(l, n, L)
     corr_ms, corr_calls = stages["corr_mfma"]
     corr_avg_ms = corr_ms / max(corr_calls, 1)
-    achieved = flops / (corr_avg_ms * 1e-3) / 1e12
+    fp32_eq = flops / (corr_avg_ms * 1e-3) / 1e12
+    if corr == "bf16x6":
+        work, peak = 6.0 * flops, BF16_MFMA_PEAK_TFLOPS
+    else:
+        work, peak = flops, FP32_MFMA_PEAK_TFLOPS
+    achieved = work / (corr_avg_ms * 1e-3) / 1e12
     return {
         "bound": "mfma",
-        "kernel": "correlate_mfma",
+        "kernel": CORR_KERNEL[corr],
         "achieved": achieved,
-        "peak": FP32_MFMA_PEAK_TFLOPS,
+        "peak": peak,
         "unit": "TFLOP/s",
-        "frac": achieved / FP32_MFMA_PEAK_TFLOPS,
-        "traffic": measured_traffic(),
+        "frac": achieved / peak,
+        "traffic": measured_traffic(corr),
         "avg_kernel_ms": corr_avg_ms,
-        "algorithmic_flops_per_launch": flops,
+        "algorithmic_flops_per_launch": work,
+        "fp32_equivalent_tflops": fp32_eq,
     }
 
 
@@ -139,6 +154,7 @@ def bench_identify(args) -> dict:
     yd = torch.from_numpy(y).to(dev)
     p = params_of(wl, PRECS[args.prec])
     ctx = ssicov.Context(0)
+    ctx.set_corr_mode(CORR_MODES[args.corr])
     ctx.set_autotune(True)                   # the warm-up calls pick the K-slice counts
     out = ctx.alloc_output(p, wl.l, wl.n)
     stream = torch.cuda.current_stream(dev)
@@ -175,6 +191,9 @@ def bench_identify(args) -> dict:
                "kind": "oracle",
                "sample": f"one full identification of the same bridge-180ch record "
                          f"(FP64 numpy checker, {cpu_s:.1f} s)"}
+    corr_note = {"fp32": "correlations on FP32 MFMA",
+                 "bf16x6": "correlations as six BF16 MFMA products of the exact three-way "
+                           "BF16 split of the FP32 samples (FP32 accumulation)"}[args.corr]
     prec_note = {"fp32": "T x Q products on FP64 MFMA",
                  "bf16": "range-finder products BF16 (FP32 accumulation), projection FP64 MFMA",
                  "bf16x3": "range-finder products split BF16 x3 (FP32 accumulation), "
@@ -195,7 +214,7 @@ def bench_identify(args) -> dict:
         "config": {
             "workload": "bridge-180ch: l=180 channels, N=180000 samples at 100 Hz, j_b=60 "
                         "(10800x10800 Toeplitz), randomized SVD k=200 p=20 q=2, "
-                        f"orders 2..200 step 2; correlations on FP32 MFMA, {prec_note}, "
+                        f"orders 2..200 step 2; {corr_note}, {prec_note}, "
                         "FP64 factorizations and eigen-analysis; product K slices autotuned "
                         "in the warm-up",
             "latency_ms_p50": float(np.percentile(step_ms, 50)),
@@ -205,7 +224,7 @@ def bench_identify(args) -> dict:
             "toeplitz_hbm_frac": toe_gbs / HBM_PEAK_GBS,
             "eig_flags": flags,
         },
-        "roofline": roofline(stages, wl.l, wl.n, L),
+        "roofline": roofline(stages, wl.l, wl.n, L, args.corr),
         "cpu_baseline": cpu,
     }
     ctx.close()
@@ -224,6 +243,7 @@ def bench_3d(args) -> dict:
     yd = torch.from_numpy(y).to(dev)
     p = params_of(wl, PRECS[args.prec])
     ctx = ssicov.Context(0)
+    ctx.set_corr_mode(CORR_MODES[args.corr])
     ctx.set_lag_streams(args.lag_streams)
     ctx.set_autotune(True)
     out = ctx.alloc_output(p, wl.l, wl.n)
@@ -362,6 +382,8 @@ def main() -> int:
     ap.add_argument("--workload", default="bridge-180ch",
                     choices=("bridge-180ch", "bridge-180ch-3d", "serving"))
     ap.add_argument("--prec", default="fp32", choices=tuple(PRECS))
+    ap.add_argument("--corr", default="bf16x6", choices=tuple(CORR_MODES),
+                    help="correlation product arithmetic")
     ap.add_argument("--lag-streams", type=int, default=3)
     ap.add_argument("--requests", type=int, default=96, help="serving: requests per run")
     ap.add_argument("--inflight", type=int, default=16, help="serving: slots")

@@ -70,6 +70,21 @@ typedef enum ssi_precision {
                           per operand                                              */
 } ssi_precision;
 
+/* Arithmetic of the correlation products (Section 2.1), a context option.
+ * Both accumulate FP32 products in FP32 over 32-sample steps, fold into FP64
+ * every 256 samples and sum the time splits in FP64. */
+typedef enum ssi_corr_mode {
+  SSI_CORR_FP32 = 0,   /* FP32 samples on v_mfma_f32_16x16x4f32                   */
+  SSI_CORR_BF16X6 = 1  /* each FP32 sample split exactly into three BF16 parts
+                          (hi + mid + lo, by truncation); the six cross products of
+                          weight >= 2^-16 on v_mfma_f32_16x16x32_bf16, each exact in
+                          FP32; the three dropped terms are below 2^-23 |y_a y_b|.
+                          Needs 6 l' N' bytes of workspace for the parts (l', N':
+                          channels and samples rounded up); falls back to
+                          SSI_CORR_FP32 when a tile would not fit (tiny lag counts
+                          with many channels).  The default.                      */
+} ssi_corr_mode;
+
 /* Identification parameters (Section 2.1 and 2.3 control parameters). */
 typedef struct ssi_params {
   double fs;                  /* sampling frequency f_s in Hz, > 0                  */
@@ -150,6 +165,7 @@ enum {
   SSI_STAGE_SMALL_SVD,       /* P P^T, eigen-decomposition, U = Q U~    */
   SSI_STAGE_SHIFT_LS,        /* Gram matrices, Cholesky, W              */
   SSI_STAGE_EIG,             /* per-order Hessenberg, QR, poles         */
+  SSI_STAGE_CORR_SPLIT,      /* BF16 parts of the record (BF16x6 mode)  */
   SSI_STAGE_COUNT
 };
 ssi_status ssi_set_profiling(ssi_ctx *ctx, int enable);
@@ -182,6 +198,10 @@ ssi_status ssi_set_graphs(ssi_ctx *ctx, int enable);
  * keeps the fastest for the life of the context.  Tuning synchronizes the
  * stream once per new shape and never runs inside a graph capture. */
 ssi_status ssi_set_autotune(ssi_ctx *ctx, int enable);
+/* Correlation product arithmetic (ssi_corr_mode) for later ssi_correlate,
+ * ssi_identify and serving calls on this context; default SSI_CORR_BF16X6.
+ * SSI_EINVAL for an unknown mode.  Drops captured graphs. */
+ssi_status ssi_set_corr_mode(ssi_ctx *ctx, int32_t mode);
 /* K-slice count chosen by the autotuner for a product, 0 if not tuned.
  * kind: 0 = FP32 x FP64 product, 1 = BF16 product, 3 = split BF16 product;
  * trans: 1 for T^T X. */

@@ -79,6 +79,8 @@ struct ssi_ctx {
   std::vector<Graph> graph_cache;
   // product autotuning: (kind, trans, M, N, K) -> K slices
   bool autotune = false;
+  // correlation product arithmetic (ssi_corr_mode)
+  int corr_mode = SSI_CORR_BF16X6;
   std::map<std::tuple<int, int, int, int, int>, int> tuned;
 };
 
@@ -313,6 +315,19 @@ ssi_status ssi_set_autotune(ssi_ctx *c, int enable) {
   return SSI_OK;
 }
 
+ssi_status ssi_set_corr_mode(ssi_ctx *c, int32_t mode) {
+  if (!c) return fail(SSI_EINVAL, "ssi_set_corr_mode: NULL context");
+  if (mode != SSI_CORR_FP32 && mode != SSI_CORR_BF16X6)
+    return fail(SSI_EINVAL, "ssi_set_corr_mode: unknown mode %d", mode);
+  if (mode != c->corr_mode) {
+    DeviceGuard g(c->device);
+    (void)hipStreamSynchronize(c->stream);
+    drop_graphs(c);
+  }
+  c->corr_mode = mode;
+  return SSI_OK;
+}
+
 int32_t ssi_tuned_splits(const ssi_ctx *c, int32_t kind, int32_t trans, int32_t m, int32_t n,
                          int32_t k) {
   if (!c) return 0;
@@ -434,15 +449,6 @@ ssi_status ssi_output_layout(const ssi_params *p, int32_t l, int64_t n, ssi_layo
 
 // ------------------------------------------------------ workspace planning
 namespace {
-
-struct Sizes {
-  size_t corr = 0;   // correlation stage: partial sums + R stack
-};
-
-size_t corr_bytes(const ssi::CorrPlan &cp, int l, int L) {
-  return aligned_bytes(cp.partial_elems, sizeof(double)) +
-         aligned_bytes((size_t)L * l * l, sizeof(float));
-}
 
 bool is_device_ptr(const void *p) {
   hipPointerAttribute_t a;
@@ -835,6 +841,7 @@ struct LaneBufs {
 struct IdentBufs {
   ssi::CorrPlan cp;
   double *corr_part;
+  uint16_t *planes;                   // BF16 parts of the record (BF16x6 correlations)
   float *r;
   int n_lanes;
   LaneBufs lane[kMaxLanes];
@@ -845,8 +852,9 @@ int lanes_for(const ssi_ctx *c, const ssi_params *p) { return std::min(c->n_lane
 IdentBufs carve_identify(Arena &a, ssi_ctx *c, int l, int64_t n, const ssi_params *p) {
   IdentBufs b{};
   const int L = 2 * p->lags[p->n_lags - 1] - 1;
-  b.cp = ssi::plan_correlate(l, n, L, c->num_cus);
+  b.cp = ssi::plan_correlate(l, n, L, c->num_cus, c->corr_mode);
   b.corr_part = a.take<double>(b.cp.partial_elems);
+  b.planes = a.take<uint16_t>(b.cp.planes_elems);
   b.r = a.take<float>((size_t)L * l * l);
   b.n_lanes = lanes_for(c, p);
   const int kcols = p->svd == SSI_SVD_RANDOMIZED ? p->rank : p->order_max;
@@ -907,9 +915,14 @@ ssi_status run_identify(ssi_ctx *c, IdentBufs &b, const float *y, int l, int64_t
                         int64_t ldy, const ssi_params *p, const ssi_output *out) {
   const int L = 2 * p->lags[p->n_lags - 1] - 1;
   hipError_t e;
+  if (b.cp.mode == SSI_CORR_BF16X6) {
+    StageTimer tm(c, SSI_STAGE_CORR_SPLIT);
+    e = ssi::launch_correlate_split(b.cp, y, l, n, ldy, b.planes, c->stream);
+    if (e != hipSuccess) return hip_fail(e, "correlation split");
+  }
   {
     StageTimer tm(c, SSI_STAGE_CORR_MFMA);
-    e = ssi::launch_correlate_mfma(b.cp, y, l, n, ldy, L, b.corr_part, c->stream);
+    e = ssi::launch_correlate_mfma(b.cp, y, l, n, ldy, L, b.corr_part, b.planes, c->stream);
   }
   if (e != hipSuccess) return hip_fail(e, "correlations");
   {
@@ -958,13 +971,19 @@ ssi_status ssi_correlate(ssi_ctx *c, const float *y, int32_t l, int64_t n, int64
   DeviceGuard g(c->device);
   if (!is_device_ptr(y) || !is_device_ptr(r))
     return fail(SSI_EINVAL, "ssi_correlate: y and r must be device pointers");
-  const ssi::CorrPlan cp = ssi::plan_correlate(l, n, n_corr, c->num_cus);
-  ssi_status s = ws_reserve(c, aligned_bytes(cp.partial_elems, sizeof(double)));
+  const ssi::CorrPlan cp = ssi::plan_correlate(l, n, n_corr, c->num_cus, c->corr_mode);
+  ssi_status s = ws_reserve(c, aligned_bytes(cp.partial_elems, sizeof(double)) +
+                                   aligned_bytes(cp.planes_elems, sizeof(uint16_t)));
   if (s != SSI_OK) return s;
   double *partial = ws_take<double>(c, cp.partial_elems);
+  uint16_t *planes = ws_take<uint16_t>(c, cp.planes_elems);
+  if (cp.mode == SSI_CORR_BF16X6) {
+    StageTimer tm(c, SSI_STAGE_CORR_SPLIT);
+    SSI_HIP(ssi::launch_correlate_split(cp, y, l, n, ldy, planes, c->stream));
+  }
   {
     StageTimer tm(c, SSI_STAGE_CORR_MFMA);
-    SSI_HIP(ssi::launch_correlate_mfma(cp, y, l, n, ldy, n_corr, partial, c->stream));
+    SSI_HIP(ssi::launch_correlate_mfma(cp, y, l, n, ldy, n_corr, partial, planes, c->stream));
   }
   StageTimer tm(c, SSI_STAGE_CORR_REDUCE);
   SSI_HIP(ssi::launch_correlate_reduce(cp, l, n, n_corr, partial, r, c->stream));

@@ -11,8 +11,23 @@
 // folded into fp64 every FLUSH_TILES tiles to bound the rounding growth over
 // long records, and the time axis is split across workgroups (split-K) whose
 // fp64 partial sums are added by a second kernel in a fixed order.
+//
+// Two product paths share the tiling, the split-K partials and the reduction:
+//   FP32   v_mfma_f32_16x16x4f32 on the FP32 samples;
+//   BF16x6 each FP32 sample is split exactly into three BF16 parts,
+//          y = hi + mid + lo (truncation: hi keeps the top 8 significant bits,
+//          mid the next 8, lo the last 8), and y_a y_b is formed from the six
+//          cross products whose weight is at least 2^-16 of the leading one
+//          (hi hi, hi mid, mid hi, hi lo, lo hi, mid mid) on
+//          v_mfma_f32_16x16x32_bf16.  Each BF16 product is exact in FP32, the
+//          dropped terms are below 2^-23 of |y_a y_b|, and accumulation is FP32
+//          with the same FP64 folding, so the sums carry FP32-product accuracy
+//          at the BF16 matrix rate.
+#include <algorithm>
+
 #include "common.h"
 #include "kernels.h"
+#include "ssicov.h"
 
 namespace {
 
@@ -182,6 +197,241 @@ correlate_mfma(const float *__restrict__ y, int l, int64_t n, int64_t ldy, int L
   (void)na_max;
 }
 
+// ------------------------------------------------------------ BF16x6 path
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+namespace {
+constexpr int kSB6 = kST + 8;        // B tile row stride (bf16): 272 bytes, 16-byte
+                                     // rows whose 16 fragment reads hit distinct banks
+
+// Top 8 significant bits of x (truncation toward zero), as BF16 bits and as FP32.
+SSI_DEV uint32_t bf16_trunc_bits(float x) { return __float_as_uint(x) >> 16; }
+SSI_DEV float bf16_trunc_val(float x) { return __uint_as_float(__float_as_uint(x) & 0xffff0000u); }
+}  // namespace
+
+// planes[q][c][s] (q = hi, mid, lo; c < lp; s < np) from y (l x n, ld ldy);
+// zero past the record and for channels c >= l.  hi + mid + lo == y exactly.
+__global__ void __launch_bounds__(256)
+split3_kernel(const float *__restrict__ y, int l, int64_t n, int64_t ldy, int lp, int64_t np,
+              uint16_t *__restrict__ planes) {
+  const int64_t per_row = np / 4;
+  const int64_t total = (int64_t)lp * per_row;
+  const int64_t plane = (int64_t)lp * np;
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const int c = (int)(idx / per_row);
+    const int64_t s = (idx - (int64_t)c * per_row) * 4;
+    float v[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+      v[i] = (c < l && s + i < n) ? y[(int64_t)c * ldy + s + i] : 0.0f;
+    uint32_t h[2], m[2], w[2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      uint32_t hb[2], mb[2], lb[2];
+#pragma unroll
+      for (int k = 0; k < 2; ++k) {
+        const float x = v[2 * i + k];
+        const float hv = bf16_trunc_val(x);
+        const float r1 = x - hv;                 // exact: the low 16 significant bits
+        const float mv = bf16_trunc_val(r1);
+        const float r2 = r1 - mv;                // exact, at most 8 significant bits
+        hb[k] = bf16_trunc_bits(x);
+        mb[k] = bf16_trunc_bits(r1);
+        lb[k] = bf16_trunc_bits(r2);
+      }
+      h[i] = hb[0] | (hb[1] << 16);
+      m[i] = mb[0] | (mb[1] << 16);
+      w[i] = lb[0] | (lb[1] << 16);
+    }
+    const int64_t o = (int64_t)c * np + s;
+    *reinterpret_cast<uint2 *>(planes + o) = make_uint2(h[0], h[1]);
+    *reinterpret_cast<uint2 *>(planes + plane + o) = make_uint2(m[0], m[1]);
+    *reinterpret_cast<uint2 *>(planes + 2 * plane + o) = make_uint2(w[0], w[1]);
+  }
+}
+
+// Same tiling and outputs as correlate_mfma, on the three BF16 planes.  One
+// K step covers 32 samples.  A fragment of rows (a, j): lane (row, g) needs
+// the 8 samples s + 8 g + j .. + 7 of channel a's window, which start at an
+// arbitrary sample; it reads the 5 dwords from the even sample at or below
+// the start and shifts them by 0 or 2 bytes (v_alignbyte).  B fragments are
+// aligned 16-byte reads.  The planes are zero past the record and past the
+// channels, so no load needs a guard; split_len is a multiple of the tile, so
+// a tile never reaches past its split except at the end of the record.
+__global__ void __launch_bounds__(kThreads, 2)
+correlate_b6(const uint16_t *__restrict__ planes, int l, int64_t n, int lp, int64_t np, int L,
+             int64_t split_len, double *__restrict__ partial, int sa_stride, int na_max) {
+  extern __shared__ __align__(16) uint16_t lds6[];
+  const int rows_total = l * L;
+  const int r0 = blockIdx.x * kRowsPerWG;
+  const int c0 = blockIdx.y * kColsPerWG;
+  const int split = blockIdx.z;
+  const int64_t s_begin = (int64_t)split * split_len;
+  const int64_t s_end = min(n, s_begin + split_len);
+  if (s_begin >= s_end) return;
+  const int64_t plane = (int64_t)lp * np;
+
+  // two buffers, each [3][64][kSB6] B tile then [3][na_max][sa_stride] A window
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int wr = wave & 3, wc = wave >> 2;
+  const int a_first = r0 / L;
+  const int a_last = min(l - 1, (min(r0 + kRowsPerWG, rows_total) - 1) / L);
+  const int na = a_last - a_first + 1;
+  const int wa8 = sa_stride / 8;                        // window chunks of 8 samples per row
+
+  // A fragment start (dword index into a plane of the window) and byte shift per row tile
+  int offA[4], shA[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    const int r = min(r0 + wr * kRowsPerWave + t * 16 + (lane & 15), rows_total - 1);
+    const int a = r / L, j = r - a * L + 1;
+    const int start = (a - a_first) * sa_stride + 8 * (lane >> 4) + j;   // in samples
+    offA[t] = start >> 1;
+    shA[t] = (start & 1) * 2;
+  }
+  int offB[2];
+#pragma unroll
+  for (int u = 0; u < 2; ++u)
+    offB[u] = (wc * kColsPerWave + u * 16 + (lane & 15)) * kSB6 + 8 * (lane >> 4);
+
+  f32x4 acc[4][2];
+  double accd[4][2][4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t)
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      acc[t][u] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int q = 0; q < 4; ++q) accd[t][u][q] = 0.0;
+    }
+
+  // B tile: 3 planes x 64 rows x 16 chunks of 8 samples = 3072 chunks, 6 per thread.
+  // A window: 3 planes x na rows x wa8 chunks.
+  const int nA = 3 * na * wa8;
+  const int buf_elems = 3 * kColsPerWG * kSB6 + 3 * na_max * sa_stride;   // one buffer
+  // Tile loads go through registers: the next tile's global loads are issued
+  // before the current tile's products and stored to the other LDS buffer
+  // after them, one barrier per tile.
+  u32x4 rb[6], ra = u32x4{0u, 0u, 0u, 0u};
+  int qa = 0, ia = 0, ca = 0;
+  if (tid < nA) {
+    qa = tid / (na * wa8);
+    const int rem = tid - qa * na * wa8;
+    ia = rem / wa8;
+    ca = rem - ia * wa8;
+  }
+  auto load_tile = [&](int64_t s0) {
+#pragma unroll
+    for (int h = 0; h < 6; ++h) {
+      const int idx = tid + kThreads * h;
+      const int q = idx >> 10, rem = idx & 1023, row = rem >> 4, ch = rem & 15;
+      rb[h] = *reinterpret_cast<const u32x4 *>(planes + q * plane + (int64_t)(c0 + row) * np +
+                                               s0 + 8 * ch);
+    }
+    if (tid < nA)
+      ra = *reinterpret_cast<const u32x4 *>(planes + qa * plane +
+                                            (int64_t)(a_first + ia) * np + s0 + 8 * ca);
+  };
+  auto store_tile = [&](int64_t s0, int buf) {
+    uint16_t *b = lds6 + buf * buf_elems;
+    uint16_t *a = b + 3 * kColsPerWG * kSB6;
+#pragma unroll
+    for (int h = 0; h < 6; ++h) {
+      const int idx = tid + kThreads * h;
+      const int q = idx >> 10, rem = idx & 1023, row = rem >> 4, ch = rem & 15;
+      *reinterpret_cast<u32x4 *>(&b[(q * kColsPerWG + row) * kSB6 + 8 * ch]) = rb[h];
+    }
+    if (tid < nA) *reinterpret_cast<u32x4 *>(&a[(qa * na_max + ia) * sa_stride + 8 * ca]) = ra;
+    for (int idx = tid + kThreads; idx < nA; idx += kThreads) {   // wide windows (small L)
+      const int q = idx / (na * wa8), rem = idx - q * na * wa8;
+      const int i = rem / wa8, c8 = rem - i * wa8;
+      *reinterpret_cast<u32x4 *>(&a[(q * na_max + i) * sa_stride + 8 * c8]) =
+          *reinterpret_cast<const u32x4 *>(planes + q * plane + (int64_t)(a_first + i) * np + s0 +
+                                           8 * c8);
+    }
+  };
+  load_tile(s_begin);
+  store_tile(s_begin, 0);
+  __syncthreads();
+  int tile_count = 0, buf = 0;
+  for (int64_t s0 = s_begin; s0 < s_end; s0 += kST, buf ^= 1) {
+    const bool more = s0 + kST < s_end;
+    if (more) load_tile(s0 + kST);
+    const uint16_t *yb = lds6 + buf * buf_elems;
+    const uint16_t *ya = yb + 3 * kColsPerWG * kSB6;
+    const uint32_t *ya32 = reinterpret_cast<const uint32_t *>(ya);
+    const int pa32 = na_max * sa_stride / 2;              // dwords per plane of the window
+#pragma unroll 2
+    for (int kk = 0; kk < kST; kk += 32) {
+      bf16x8 bf[2][3];
+#pragma unroll
+      for (int u = 0; u < 2; ++u)
+#pragma unroll
+        for (int q = 0; q < 3; ++q)
+          bf[u][q] = *reinterpret_cast<const bf16x8 *>(&yb[q * kColsPerWG * kSB6 + offB[u] + kk]);
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        bf16x8 af[3];
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+          const uint32_t *src = ya32 + q * pa32 + offA[t] + kk / 2;
+          const uint32_t d0 = src[0], d1 = src[1], d2 = src[2], d3 = src[3], d4 = src[4];
+          u32x4 w;
+          w.x = __builtin_amdgcn_alignbyte(d1, d0, shA[t]);
+          w.y = __builtin_amdgcn_alignbyte(d2, d1, shA[t]);
+          w.z = __builtin_amdgcn_alignbyte(d3, d2, shA[t]);
+          w.w = __builtin_amdgcn_alignbyte(d4, d3, shA[t]);
+          af[q] = __builtin_bit_cast(bf16x8, w);
+        }
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+          f32x4 c = acc[t][u];
+          c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[2], bf[u][0], c, 0, 0, 0);   // lo hi
+          c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[0], bf[u][2], c, 0, 0, 0);   // hi lo
+          c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[1], bf[u][1], c, 0, 0, 0);   // mid mid
+          c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[1], bf[u][0], c, 0, 0, 0);   // mid hi
+          c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[0], bf[u][1], c, 0, 0, 0);   // hi mid
+          c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[0], bf[u][0], c, 0, 0, 0);   // hi hi
+          acc[t][u] = c;
+        }
+      }
+    }
+
+    if (++tile_count == kFlushTiles || s0 + kST >= s_end) {
+      tile_count = 0;
+#pragma unroll
+      for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+#pragma unroll
+          for (int q = 0; q < 4; ++q) accd[t][u][q] += (double)acc[t][u][q];
+          acc[t][u] = f32x4{0.f, 0.f, 0.f, 0.f};
+        }
+    }
+    if (more) store_tile(s0 + kST, buf ^ 1);
+    __syncthreads();
+  }
+
+  // D layout of 16x16x32 bf16: lane holds rows 4*(lane/16)+q, column lane%16.
+  double *dst = partial + (int64_t)split * rows_total * l;
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int b = c0 + wc * kColsPerWave + u * 16 + (lane & 15);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int r = r0 + wr * kRowsPerWave + t * 16 + 4 * (lane >> 4) + q;
+        if (r < rows_total && b < l) dst[(int64_t)r * l + b] = accd[t][u][q];
+      }
+    }
+  }
+}
+
 // R[j-1][a][b] = (float)(sum_split partial[split][a L + j - 1][b] / n)
 __global__ void __launch_bounds__(256)
 correlate_reduce(const double *__restrict__ partial, int l, int L, int splits,
@@ -204,7 +454,7 @@ correlate_reduce(const double *__restrict__ partial, int l, int L, int splits,
 // ------------------------------------------------------------------ launch
 namespace ssi {
 
-CorrPlan plan_correlate(int l, int64_t n, int L, int num_cus) {
+CorrPlan plan_correlate(int l, int64_t n, int L, int num_cus, int mode) {
   CorrPlan p{};
   const int rows_total = l * L;
   p.grid_rows = ceil_div(rows_total, kRowsPerWG);
@@ -224,17 +474,55 @@ CorrPlan plan_correlate(int l, int64_t n, int L, int num_cus) {
   // A window rows: channels spanned by 256 flattened rows.
   p.na_max = kRowsPerWG / L + 2;
   if (p.na_max > l) p.na_max = l;
-  // A window row stride: whole float4s, not a multiple of 32 floats
-  p.sa_stride = (kST + L + 3) / 4 * 4;
-  if ((p.sa_stride & 31) == 0) p.sa_stride += 4;
-  p.lds_bytes = sizeof(float) * ((size_t)kColsPerWG * kSB + (size_t)p.na_max * p.sa_stride);
   p.partial_elems = (size_t)p.splits * rows_total * l;
+  p.mode = SSI_CORR_FP32;
+  if (mode == SSI_CORR_BF16X6) {
+    // window row: samples up to 129 + L past the tile start, whole 16-byte
+    // chunks, row stride not a multiple of 64 dwords
+    int sa = (kST + L + 2 + 7) / 8 * 8;
+    if ((sa & 127) == 0) sa += 8;
+    const size_t lds =
+        2 * sizeof(uint16_t) * 3 * ((size_t)kColsPerWG * kSB6 + (size_t)p.na_max * sa);
+    if (lds <= 160 * 1024) {             // both tile buffers in one CU's LDS
+      p.mode = SSI_CORR_BF16X6;
+      p.sa_stride = sa;
+      p.lds_bytes = lds;
+      p.lp = p.grid_cols * kColsPerWG;
+      p.np = (n + kST + L + 24 + 7) / 8 * 8;   // every window and tile read stays inside
+      p.planes_elems = (size_t)3 * p.lp * p.np;
+    }
+  }
+  if (p.mode == SSI_CORR_FP32) {
+    // A window row stride: whole float4s, not a multiple of 32 floats
+    p.sa_stride = (kST + L + 3) / 4 * 4;
+    if ((p.sa_stride & 31) == 0) p.sa_stride += 4;
+    p.lds_bytes = sizeof(float) * ((size_t)kColsPerWG * kSB + (size_t)p.na_max * p.sa_stride);
+  }
   return p;
 }
 
+hipError_t launch_correlate_split(const CorrPlan &p, const float *y, int l, int64_t n,
+                                  int64_t ldy, uint16_t *planes, hipStream_t st) {
+  if (p.mode != SSI_CORR_BF16X6) return hipSuccess;
+  const int64_t chunks = (int64_t)p.lp * (p.np / 4);
+  const int blocks = (int)std::min<int64_t>(ceil_div<int64_t>(chunks, 256), 65535 * 4);
+  hipLaunchKernelGGL(split3_kernel, dim3(blocks), dim3(256), 0, st, y, l, n, ldy, p.lp, p.np,
+                     planes);
+  return hipGetLastError();
+}
+
 hipError_t launch_correlate_mfma(const CorrPlan &p, const float *y, int l, int64_t n, int64_t ldy,
-                                 int L, double *partial, hipStream_t st) {
+                                 int L, double *partial, const uint16_t *planes, hipStream_t st) {
   dim3 grid(p.grid_rows, p.grid_cols, p.splits);
+  if (p.mode == SSI_CORR_BF16X6) {
+    hipError_t e = hipFuncSetAttribute((const void *)correlate_b6,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)p.lds_bytes);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(correlate_b6, grid, dim3(kThreads), p.lds_bytes, st, planes, l, n, p.lp,
+                       p.np, L, p.split_len, partial, p.sa_stride, p.na_max);
+    return hipGetLastError();
+  }
   const bool vec = (ldy % 4 == 0) && ((uintptr_t)y % 16 == 0);
   const void *fn = vec ? (const void *)correlate_mfma<true> : (const void *)correlate_mfma<false>;
   if (p.lds_bytes > 65536) {
@@ -262,8 +550,9 @@ hipError_t launch_correlate_reduce(const CorrPlan &p, int l, int64_t n, int L,
 }
 
 hipError_t launch_correlate(const CorrPlan &p, const float *y, int l, int64_t n, int64_t ldy,
-                            int L, double *partial, float *r, hipStream_t st) {
-  hipError_t e = launch_correlate_mfma(p, y, l, n, ldy, L, partial, st);
+                            int L, double *partial, uint16_t *planes, float *r, hipStream_t st) {
+  hipError_t e = launch_correlate_split(p, y, l, n, ldy, planes, st);
+  if (e == hipSuccess) e = launch_correlate_mfma(p, y, l, n, ldy, L, partial, planes, st);
   if (e != hipSuccess) return e;
   return launch_correlate_reduce(p, l, n, L, partial, r, st);
 }

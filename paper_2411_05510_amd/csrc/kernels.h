@@ -16,12 +16,21 @@ struct CorrPlan {
   int sa_stride, na_max;
   size_t lds_bytes;
   size_t partial_elems;
+  int mode;                     // SSI_CORR_FP32 or SSI_CORR_BF16X6 (the path taken)
+  int lp;                       // BF16x6: channel rows of each plane (multiple of 64)
+  int64_t np;                   // BF16x6: samples per plane row
+  size_t planes_elems;          // BF16x6: 3 lp np bf16 elements of split planes, else 0
 };
-CorrPlan plan_correlate(int l, int64_t n, int L, int num_cus);
+// mode: the requested path; BF16x6 falls back to FP32 where its tiles do not
+// fit two workgroups per CU.
+CorrPlan plan_correlate(int l, int64_t n, int L, int num_cus, int mode);
 hipError_t launch_correlate(const CorrPlan &p, const float *y, int l, int64_t n, int64_t ldy,
-                            int L, double *partial, float *r, hipStream_t st);
+                            int L, double *partial, uint16_t *planes, float *r, hipStream_t st);
+// BF16x6: the record's three BF16 parts into planes (no-op for FP32)
+hipError_t launch_correlate_split(const CorrPlan &p, const float *y, int l, int64_t n,
+                                  int64_t ldy, uint16_t *planes, hipStream_t st);
 hipError_t launch_correlate_mfma(const CorrPlan &p, const float *y, int l, int64_t n, int64_t ldy,
-                                 int L, double *partial, hipStream_t st);
+                                 int L, double *partial, const uint16_t *planes, hipStream_t st);
 hipError_t launch_correlate_reduce(const CorrPlan &p, int l, int64_t n, int L,
                                    const double *partial, float *r, hipStream_t st);
 

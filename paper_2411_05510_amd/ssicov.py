@@ -21,6 +21,7 @@ LIB_PATH = os.path.join(HERE, "libssicov.so")
 SSI_OK, SSI_EINVAL, SSI_ENOMEM, SSI_EDEVICE, SSI_ENOCONV, SSI_EINTERNAL, SSI_EBUSY = range(7)
 SVD_FULL, SVD_RANDOMIZED = 0, 1
 PREC_FP32, PREC_BF16, PREC_BF16X3 = 0, 1, 2
+CORR_FP32, CORR_BF16X6 = 0, 1
 
 # Every symbol include/ssicov.h declares.
 EXPORTED = (
@@ -30,7 +31,7 @@ EXPORTED = (
     "ssi_last_error", "ssi_identify", "ssi_correlate", "ssi_toeplitz",
     "ssi_sketch", "ssi_rsvd", "ssi_svd_full", "ssi_modal", "ssi_set_profiling",
     "ssi_profile_read", "ssi_set_lag_streams", "ssi_set_graphs", "ssi_set_autotune",
-    "ssi_tuned_splits", "ssi_footprint", "ssi_server_create", "ssi_server_destroy",
+    "ssi_set_corr_mode", "ssi_tuned_splits", "ssi_footprint", "ssi_server_create", "ssi_server_destroy",
     "ssi_server_submit", "ssi_server_poll", "ssi_server_wait", "ssi_server_result",
     "ssi_server_release", "ssi_server_get_stats", "ssi_server_last_error", "ssi_stability",
 )
@@ -38,7 +39,7 @@ EXPORTED = (
 POLE_HC, POLE_STABLE_ORDER, POLE_STABLE_LAG, POLE_STABLE = 1, 2, 4, 8
 
 STAGES = ("corr_mfma", "corr_reduce", "toeplitz", "sketch", "products", "orth",
-          "small_svd", "shift_ls", "eig")
+          "small_svd", "shift_ls", "eig", "corr_split")
 
 
 class SSIError(RuntimeError):
@@ -148,6 +149,7 @@ def lib() -> ctypes.CDLL:
             "ssi_set_lag_streams": ([vp, i32], ctypes.c_int),
             "ssi_set_graphs": ([vp, ctypes.c_int], ctypes.c_int),
             "ssi_set_autotune": ([vp, ctypes.c_int], ctypes.c_int),
+            "ssi_set_corr_mode": ([vp, i32], ctypes.c_int),
             "ssi_tuned_splits": ([vp, i32, i32, i32, i32, i32], i32),
             "ssi_footprint": ([P, i32, i64, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
             "ssi_server_create": ([ctypes.POINTER(_ServerConfig), ctypes.POINTER(vp)],
@@ -304,6 +306,10 @@ class Context:
 
     def set_autotune(self, enable: bool) -> None:
         _check(lib().ssi_set_autotune(self._h, 1 if enable else 0))
+
+    def set_corr_mode(self, mode: int) -> None:
+        """CORR_FP32 or CORR_BF16X6 (the default) for the correlation products."""
+        _check(lib().ssi_set_corr_mode(self._h, mode))
 
     def tuned_splits(self, kind: int, trans: bool, m: int, n: int, k: int) -> int:
         return int(lib().ssi_tuned_splits(self._h, kind, 1 if trans else 0, m, n, k))

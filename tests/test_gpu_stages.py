@@ -46,7 +46,12 @@ def _corr_check(ctx, y, n_corr, tol=1e-5, fwd_tol=1e-6):
 
 
 # ------------------------------------------------------------ correlations
-def test_correlate_small_record(ctx):
+MODES = pytest.mark.parametrize("mode", [0, 1], ids=["fp32", "bf16x6"])
+
+
+@MODES
+def test_correlate_small_record(ctx, mode):
+    ctx.set_corr_mode(mode)
     wl = synth.WORKLOADS["small-full-svd"]
     _, y = synth.make_record(wl)
     _corr_check(ctx, y, 2 * wl.lags[0] - 1)
@@ -54,13 +59,17 @@ def test_correlate_small_record(ctx):
 
 @pytest.mark.parametrize("l,n,L", [(37, 5003, 23), (5, 777, 60), (1, 2, 1), (1, 3000, 300),
                                    (70, 4099, 3), (3, 129, 128)])
-def test_correlate_ragged(ctx, l, n, L):
+@MODES
+def test_correlate_ragged(ctx, l, n, L, mode):
+    ctx.set_corr_mode(mode)
     y = synth.random_matrix(l, n, seed=l * 1000 + L)
     _corr_check(ctx, y, L, tol=None)
 
 
-def test_correlate_bridge_record_sampled(ctx):
+@MODES
+def test_correlate_bridge_record_sampled(ctx, mode):
     """Full 180-channel, 30-minute record, 119 lags; sampled channel pairs."""
+    ctx.set_corr_mode(mode)
     wl = synth.WORKLOADS["bridge-180ch"]
     _, y = synth.make_record(wl)
     L = 2 * wl.lags[0] - 1
@@ -80,13 +89,33 @@ def test_correlate_bridge_record_sampled(ctx):
             assert rel <= 1e-5, (a, b, rel)
 
 
-def test_correlate_deterministic(ctx):
+@MODES
+def test_correlate_deterministic(ctx, mode):
+    ctx.set_corr_mode(mode)
     y = synth.random_matrix(20, 9000, seed=3)
     yd = _dev(y)
     r1 = ctx.correlate(yd, 40).clone()
     r2 = ctx.correlate(yd, 40)
     ctx.synchronize()
     assert torch.equal(r1, r2)
+
+
+def test_correlate_modes_agree_exact_inputs(ctx):
+    """Samples with at most 8 significant bits (small integers times a power of
+    two): the BF16 split is hi alone, every product is exact in either path,
+    and sums below 2^24 are exact in FP32, so both paths return identical
+    stacks."""
+    rng = np.random.default_rng(5)
+    y = (rng.integers(-15, 16, size=(19, 3000)) * 0.25).astype(np.float32)
+    out = []
+    for mode in (0, 1):
+        ctx.set_corr_mode(mode)
+        out.append(ctx.correlate(_dev(y), 25).cpu().numpy())
+    ctx.set_corr_mode(1)
+    ref = oracle.correlations(y, 25)
+    assert np.array_equal(out[0], out[1])
+    # the exact sums are scaled by 1/N and rounded to FP32 once
+    np.testing.assert_allclose(out[1].astype(np.float64), ref, rtol=2.0 ** -23, atol=0)
 
 
 # ---------------------------------------------------------------- Toeplitz
