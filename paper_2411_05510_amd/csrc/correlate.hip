@@ -253,16 +253,19 @@ split3_kernel(const float *__restrict__ y, int l, int64_t n, int64_t ldy, int lp
 }
 
 // Same tiling and outputs as correlate_mfma, on the three BF16 planes.  One
-// K step covers 32 samples.  A fragment of rows (a, j): lane (row, g) needs
-// the 8 samples s + 8 g + j .. + 7 of channel a's window, which start at an
-// arbitrary sample; it reads the 5 dwords from the even sample at or below
-// the start and shifts them by 0 or 2 bytes (v_alignbyte).  B fragments are
-// aligned 16-byte reads.  The planes are zero past the record and past the
-// channels, so no load needs a guard; split_len is a multiple of the tile, so
-// a tile never reaches past its split except at the end of the record.
+// K step covers 32 samples.  An A fragment of rows (a, j) is, in lane (row, g),
+// the 8 samples s + 8 g + j .. + 7 of channel a's window: they start at any
+// sample, so the window is kept in LDS as eight copies shifted by 0..7 samples
+// and the fragment is one aligned 16-byte read of copy j mod 8.  B fragments
+// are aligned 16-byte reads of the B tile.  The next tile's global loads are
+// issued before the current tile's products.  The planes are zero past the
+// record and past the channels, so no load needs a guard; split_len is a
+// multiple of the tile, so a tile never reaches past its split except at the
+// end of the record.
 __global__ void __launch_bounds__(kThreads, 2)
 correlate_b6(const uint16_t *__restrict__ planes, int l, int64_t n, int lp, int64_t np, int L,
-             int64_t split_len, double *__restrict__ partial, int sa_stride, int na_max) {
+             int64_t split_len, double *__restrict__ partial, int sa_stride, int na_max,
+             int copy_stride) {
   extern __shared__ __align__(16) uint16_t lds6[];
   const int rows_total = l * L;
   const int r0 = blockIdx.x * kRowsPerWG;
@@ -273,7 +276,11 @@ correlate_b6(const uint16_t *__restrict__ planes, int l, int64_t n, int lp, int6
   if (s_begin >= s_end) return;
   const int64_t plane = (int64_t)lp * np;
 
-  // two buffers, each [3][64][kSB6] B tile then [3][na_max][sa_stride] A window
+  // [3][64][kSB6] B tile, then 8 copies (stride copy_stride) of the
+  // [3][na_max][sa_stride] A window, copy c holding window sample t + c at t
+  uint16_t *yb = lds6;
+  uint16_t *ya = lds6 + 3 * kColsPerWG * kSB6;
+  const int pa = na_max * sa_stride;                    // elements per plane of a copy
 
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
@@ -283,15 +290,12 @@ correlate_b6(const uint16_t *__restrict__ planes, int l, int64_t n, int lp, int6
   const int na = a_last - a_first + 1;
   const int wa8 = sa_stride / 8;                        // window chunks of 8 samples per row
 
-  // A fragment start (dword index into a plane of the window) and byte shift per row tile
-  int offA[4], shA[4];
+  int offA[4];
 #pragma unroll
   for (int t = 0; t < 4; ++t) {
     const int r = min(r0 + wr * kRowsPerWave + t * 16 + (lane & 15), rows_total - 1);
     const int a = r / L, j = r - a * L + 1;
-    const int start = (a - a_first) * sa_stride + 8 * (lane >> 4) + j;   // in samples
-    offA[t] = start >> 1;
-    shA[t] = (start & 1) * 2;
+    offA[t] = (j & 7) * copy_stride + (a - a_first) * sa_stride + 8 * (lane >> 4) + (j & ~7);
   }
   int offB[2];
 #pragma unroll
@@ -309,14 +313,11 @@ correlate_b6(const uint16_t *__restrict__ planes, int l, int64_t n, int lp, int6
       for (int q = 0; q < 4; ++q) accd[t][u][q] = 0.0;
     }
 
-  // B tile: 3 planes x 64 rows x 16 chunks of 8 samples = 3072 chunks, 6 per thread.
-  // A window: 3 planes x na rows x wa8 chunks.
+  // B tile: 3 planes x 64 rows x 16 chunks of 8 samples = 3072 chunks, 6 per
+  // thread.  A window: 3 planes x na rows x wa8 chunks; a thread takes chunk
+  // c8 and the one after it and writes the eight shifted copies of chunk c8.
   const int nA = 3 * na * wa8;
-  const int buf_elems = 3 * kColsPerWG * kSB6 + 3 * na_max * sa_stride;   // one buffer
-  // Tile loads go through registers: the next tile's global loads are issued
-  // before the current tile's products and stored to the other LDS buffer
-  // after them, one barrier per tile.
-  u32x4 rb[6], ra = u32x4{0u, 0u, 0u, 0u};
+  u32x4 rb[6], ra0 = u32x4{0u, 0u, 0u, 0u}, ra1 = ra0;
   int qa = 0, ia = 0, ca = 0;
   if (tid < nA) {
     qa = tid / (na * wa8);
@@ -332,39 +333,52 @@ correlate_b6(const uint16_t *__restrict__ planes, int l, int64_t n, int lp, int6
       rb[h] = *reinterpret_cast<const u32x4 *>(planes + q * plane + (int64_t)(c0 + row) * np +
                                                s0 + 8 * ch);
     }
-    if (tid < nA)
-      ra = *reinterpret_cast<const u32x4 *>(planes + qa * plane +
-                                            (int64_t)(a_first + ia) * np + s0 + 8 * ca);
+    if (tid < nA) {
+      const uint16_t *src = planes + qa * plane + (int64_t)(a_first + ia) * np + s0 + 8 * ca;
+      ra0 = *reinterpret_cast<const u32x4 *>(src);
+      ra1 = *reinterpret_cast<const u32x4 *>(src + 8);
+    }
   };
-  auto store_tile = [&](int64_t s0, int buf) {
-    uint16_t *b = lds6 + buf * buf_elems;
-    uint16_t *a = b + 3 * kColsPerWG * kSB6;
+  // the eight shifted copies of one window chunk: copy c, chunk c8 holds
+  // samples 8 c8 + c .. + 7, i.e. bytes 2c .. 2c + 15 of the chunk pair
+  auto store_shifted = [&](int q, int i, int c8, const u32x4 &lo, const u32x4 &hi) {
+    const uint32_t d[8] = {lo.x, lo.y, lo.z, lo.w, hi.x, hi.y, hi.z, hi.w};
+    uint16_t *dst = ya + (q * na_max + i) * sa_stride + 8 * c8;
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      u32x4 w;
+      const int k = c >> 1, sh = (c & 1) * 2;
+      w.x = __builtin_amdgcn_alignbyte(d[k + 1], d[k], sh);
+      w.y = __builtin_amdgcn_alignbyte(d[k + 2], d[k + 1], sh);
+      w.z = __builtin_amdgcn_alignbyte(d[k + 3], d[k + 2], sh);
+      w.w = __builtin_amdgcn_alignbyte(d[k + 4], d[k + 3], sh);
+      *reinterpret_cast<u32x4 *>(dst + c * copy_stride) = w;
+    }
+  };
+  auto store_tile = [&](int64_t s0) {
 #pragma unroll
     for (int h = 0; h < 6; ++h) {
       const int idx = tid + kThreads * h;
       const int q = idx >> 10, rem = idx & 1023, row = rem >> 4, ch = rem & 15;
-      *reinterpret_cast<u32x4 *>(&b[(q * kColsPerWG + row) * kSB6 + 8 * ch]) = rb[h];
+      *reinterpret_cast<u32x4 *>(&yb[(q * kColsPerWG + row) * kSB6 + 8 * ch]) = rb[h];
     }
-    if (tid < nA) *reinterpret_cast<u32x4 *>(&a[(qa * na_max + ia) * sa_stride + 8 * ca]) = ra;
+    if (tid < nA) store_shifted(qa, ia, ca, ra0, ra1);
     for (int idx = tid + kThreads; idx < nA; idx += kThreads) {   // wide windows (small L)
       const int q = idx / (na * wa8), rem = idx - q * na * wa8;
       const int i = rem / wa8, c8 = rem - i * wa8;
-      *reinterpret_cast<u32x4 *>(&a[(q * na_max + i) * sa_stride + 8 * c8]) =
-          *reinterpret_cast<const u32x4 *>(planes + q * plane + (int64_t)(a_first + i) * np + s0 +
-                                           8 * c8);
+      const uint16_t *src = planes + q * plane + (int64_t)(a_first + i) * np + s0 + 8 * c8;
+      store_shifted(q, i, c8, *reinterpret_cast<const u32x4 *>(src),
+                    *reinterpret_cast<const u32x4 *>(src + 8));
     }
   };
   load_tile(s_begin);
-  store_tile(s_begin, 0);
-  __syncthreads();
-  int tile_count = 0, buf = 0;
-  for (int64_t s0 = s_begin; s0 < s_end; s0 += kST, buf ^= 1) {
-    const bool more = s0 + kST < s_end;
-    if (more) load_tile(s0 + kST);
-    const uint16_t *yb = lds6 + buf * buf_elems;
-    const uint16_t *ya = yb + 3 * kColsPerWG * kSB6;
-    const uint32_t *ya32 = reinterpret_cast<const uint32_t *>(ya);
-    const int pa32 = na_max * sa_stride / 2;              // dwords per plane of the window
+  int tile_count = 0;
+  for (int64_t s0 = s_begin; s0 < s_end; s0 += kST) {
+    __syncthreads();                       // the previous tile's reads are done
+    store_tile(s0);
+    __syncthreads();
+    if (s0 + kST < s_end) load_tile(s0 + kST);
+
 #pragma unroll 2
     for (int kk = 0; kk < kST; kk += 32) {
       bf16x8 bf[2][3];
@@ -377,16 +391,8 @@ correlate_b6(const uint16_t *__restrict__ planes, int l, int64_t n, int lp, int6
       for (int t = 0; t < 4; ++t) {
         bf16x8 af[3];
 #pragma unroll
-        for (int q = 0; q < 3; ++q) {
-          const uint32_t *src = ya32 + q * pa32 + offA[t] + kk / 2;
-          const uint32_t d0 = src[0], d1 = src[1], d2 = src[2], d3 = src[3], d4 = src[4];
-          u32x4 w;
-          w.x = __builtin_amdgcn_alignbyte(d1, d0, shA[t]);
-          w.y = __builtin_amdgcn_alignbyte(d2, d1, shA[t]);
-          w.z = __builtin_amdgcn_alignbyte(d3, d2, shA[t]);
-          w.w = __builtin_amdgcn_alignbyte(d4, d3, shA[t]);
-          af[q] = __builtin_bit_cast(bf16x8, w);
-        }
+        for (int q = 0; q < 3; ++q)
+          af[q] = *reinterpret_cast<const bf16x8 *>(&ya[offA[t] + q * pa + kk]);
 #pragma unroll
         for (int u = 0; u < 2; ++u) {
           f32x4 c = acc[t][u];
@@ -412,8 +418,6 @@ correlate_b6(const uint16_t *__restrict__ planes, int l, int64_t n, int lp, int6
           acc[t][u] = f32x4{0.f, 0.f, 0.f, 0.f};
         }
     }
-    if (more) store_tile(s0 + kST, buf ^ 1);
-    __syncthreads();
   }
 
   // D layout of 16x16x32 bf16: lane holds rows 4*(lane/16)+q, column lane%16.
@@ -477,18 +481,21 @@ CorrPlan plan_correlate(int l, int64_t n, int L, int num_cus, int mode) {
   p.partial_elems = (size_t)p.splits * rows_total * l;
   p.mode = SSI_CORR_FP32;
   if (mode == SSI_CORR_BF16X6) {
-    // window row: samples up to 129 + L past the tile start, whole 16-byte
-    // chunks, row stride not a multiple of 64 dwords
-    int sa = (kST + L + 2 + 7) / 8 * 8;
-    if ((sa & 127) == 0) sa += 8;
-    const size_t lds =
-        2 * sizeof(uint16_t) * 3 * ((size_t)kColsPerWG * kSB6 + (size_t)p.na_max * sa);
-    if (lds <= 160 * 1024) {             // both tile buffers in one CU's LDS
+    // window row: samples up to 127 + L past the tile start, whole 16-byte chunks
+    const int sa = (kST + L + 7) / 8 * 8;
+    // copy stride: whole chunks, 8 dwords past a multiple of 64 dwords, so the
+    // 16 lanes of a fragment read (consecutive lags: copies 0..7 at two chunk
+    // positions) hit distinct groups of four banks
+    int cs = 3 * p.na_max * sa;
+    cs = (cs + 127) / 128 * 128 + 16;
+    const size_t lds = sizeof(uint16_t) * ((size_t)3 * kColsPerWG * kSB6 + (size_t)8 * cs);
+    if (lds <= 160 * 1024) {
       p.mode = SSI_CORR_BF16X6;
       p.sa_stride = sa;
+      p.copy_stride = cs;
       p.lds_bytes = lds;
       p.lp = p.grid_cols * kColsPerWG;
-      p.np = (n + kST + L + 24 + 7) / 8 * 8;   // every window and tile read stays inside
+      p.np = (n + 2 * kST + L + 64 + 7) / 8 * 8;   // every window and tile read stays inside
       p.planes_elems = (size_t)3 * p.lp * p.np;
     }
   }
@@ -520,7 +527,7 @@ hipError_t launch_correlate_mfma(const CorrPlan &p, const float *y, int l, int64
                                        (int)p.lds_bytes);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(correlate_b6, grid, dim3(kThreads), p.lds_bytes, st, planes, l, n, p.lp,
-                       p.np, L, p.split_len, partial, p.sa_stride, p.na_max);
+                       p.np, L, p.split_len, partial, p.sa_stride, p.na_max, p.copy_stride);
     return hipGetLastError();
   }
   const bool vec = (ldy % 4 == 0) && ((uintptr_t)y % 16 == 0);

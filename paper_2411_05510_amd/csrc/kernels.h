@@ -19,6 +19,7 @@ struct CorrPlan {
   int mode;                     // SSI_CORR_FP32 or SSI_CORR_BF16X6 (the path taken)
   int lp;                       // BF16x6: channel rows of each plane (multiple of 64)
   int64_t np;                   // BF16x6: samples per plane row
+  int copy_stride;              // BF16x6: elements between the shifted A-window copies
   size_t planes_elems;          // BF16x6: 3 lp np bf16 elements of split planes, else 0
 };
 // mode: the requested path; BF16x6 falls back to FP32 where its tiles do not
