@@ -34,13 +34,7 @@ SSI_DEV int col_of(int tc, int q) { return tc + 32 * q; }
 SSI_DEV double sel(bool c, double v) { return c ? v : 0.0; }
 
 // Sum over the 16 lanes of a grid column (lanes differ only in bits 0..3).
-SSI_DEV double col_group_sum(double v) {
-  v += __shfl_xor(v, 1, 64);
-  v += __shfl_xor(v, 2, 64);
-  v += __shfl_xor(v, 4, 64);
-  v += __shfl_xor(v, 8, 64);
-  return v;
-}
+SSI_DEV double col_group_sum(double v) { return row16_sum(v); }
 
 SSI_DEV double block_sum_all(double v, double *red) {
   v = wave_sum(v);
@@ -248,6 +242,87 @@ tri_inv_kernel(int n, const double *__restrict__ Lws, double *__restrict__ Rinv,
     }
 }
 
+// X = L^{-1} for the lower-triangular L in Lws (ld n), by columns: columns
+// are independent forward substitutions, so workgroup b takes columns
+// c0 = 16 b .. c0 + 15 and wave w of it four of them, col = c0 + 4 w + c.
+// Lane (c, p) = (lane / 16, lane % 16) forms x_i[c] = (e_i - sum_{k<i} L_ik
+// x_k[c]) / L_ii from the terms k = c0 + p + 16 q (x_k[c] = 0 below column
+// col) and the 16 lanes of c combine by shuffles.  Rows of L enter LDS in
+// blocks of 16 (columns c0..), the next block loaded into registers while
+// the current one is used; each wave's x rows live in its own slice of LDS,
+// so rows inside a block need no workgroup barrier.  Writes Rinv = X^T
+// (upper, zero below the diagonal).  LDS: 1 / L_ii [n], x [4][n][4], two L
+// blocks [2][16][n].
+constexpr int kTiQ = 14;                  // terms per lane: n - c0 <= 16 kTiQ
+constexpr int kTiRB = 16;                 // rows per L block
+__global__ void __launch_bounds__(256)
+tri_inv_cols_kernel(int n, const double *__restrict__ Lws, double *__restrict__ Rinv,
+                    int64_t ldr) {
+  extern __shared__ double tis[];
+  double *rinv = tis;
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int c = lane >> 4, p = lane & 15;
+  double *xs = tis + n + (size_t)w * n * 4;            // [rows from c0][4]
+  double *lb = tis + (size_t)17 * n;                   // [2][kTiRB][n]
+  const int c0 = 16 * blockIdx.x;
+  const int col = c0 + 4 * w + c;
+  const int width = n - c0;                            // columns c0..n-1
+  for (int i = t; i < n; i += 256) rinv[i] = 1.0 / Lws[(int64_t)i * n + i];
+  // block m holds rows c0 + 16 m .. + 15, columns c0 .. c0 + width - 1
+  constexpr int kPer = kTiRB * 16 * kTiQ / 256;        // elements per thread and block
+  double pre[kPer];
+  auto load_block = [&](int m) {
+#pragma unroll
+    for (int e = 0; e < kPer; ++e) {
+      const int idx = t + 256 * e;
+      const int rr = idx / (16 * kTiQ), kk = idx - rr * (16 * kTiQ);
+      const int i = c0 + kTiRB * m + rr, k = c0 + kk;
+      pre[e] = (i < n && kk < width && k <= i) ? Lws[(int64_t)i * n + k] : 0.0;
+    }
+  };
+  auto store_block = [&](int buf) {
+#pragma unroll
+    for (int e = 0; e < kPer; ++e) {
+      const int idx = t + 256 * e;
+      const int rr = idx / (16 * kTiQ), kk = idx - rr * (16 * kTiQ);
+      if (kk < width) lb[((size_t)buf * kTiRB + rr) * n + kk] = pre[e];
+    }
+  };
+  const int nblk = ceil_div(width, kTiRB);
+  load_block(0);
+  for (int m = 0; m < nblk; ++m) {
+    __syncthreads();                                   // block m - 2's readers are done
+    store_block(m & 1);
+    __syncthreads();
+    if (m + 1 < nblk) load_block(m + 1);
+    const double *L = lb + (size_t)(m & 1) * kTiRB * n;
+    for (int rr = 0; rr < kTiRB; ++rr) {
+      const int i = c0 + kTiRB * m + rr;
+      if (i >= n) break;
+      const int lim = i - c0;                          // terms k - c0 < lim
+      double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+      for (int q = 0; q < kTiQ; q += 2) {
+        const int k0 = p + 16 * q, k1 = k0 + 16;
+        if (k0 < lim) s0 += L[rr * n + k0] * xs[k0 * 4 + c];
+        if (k1 < lim) s1 += L[rr * n + k1] * xs[k1 * 4 + c];
+      }
+      const double s = row16_sum(s0 + s1);
+      const double x = (i < col) ? 0.0 : ((i == col ? 1.0 : 0.0) - s) * rinv[i];
+      if (p == 0) xs[lim * 4 + c] = x;
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+    }
+  }
+  // Rinv row col = X column col: zero left of the diagonal
+  for (int cc = 0; cc < 4; ++cc) {
+    const int j = c0 + 4 * w + cc;
+    if (j >= n) break;
+    for (int i = lane; i < n; i += 64)
+      Rinv[(int64_t)j * ldr + i] = (i < j) ? 0.0 : xs[(i - c0) * 4 + cc];
+  }
+}
+
 // ------------------------------------------------------------ sym eigen
 // Scratch layout (doubles): vref[kN][kN] | tau[kN] | d[kN] | e[kN]
 template <int TP, int TQ, bool GM>
@@ -409,17 +484,8 @@ SSI_DEV double hash_unit(uint32_t a, uint32_t b) {
   return 0.5 + (double)(h & 0xFFFF) * (1.0 / 65536.0);   // in [0.5, 1.5)
 }
 
-SSI_DEV double wave_min_d(double v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v = fmin(v, __shfl_xor(v, off, 64));
-  return v;
-}
-
-SSI_DEV double wave_max_d(double v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
-  return v;
-}
+SSI_DEV double wave_min_d(double v) { return wave_min(v); }
+SSI_DEV double wave_max_d(double v) { return wave_max(v); }
 
 }  // namespace
 
@@ -618,6 +684,7 @@ namespace ssi {
 
 namespace {
 constexpr int kRegP = 14, kRegQ = 7;      // n <= 224
+static_assert(16 * kTiQ >= 16 * kRegP, "column inverse covers the register path");
 constexpr int kGlbP = 64, kGlbQ = 32;     // n <= 1024
 constexpr int kRegN = Geo<kRegP, kRegQ>::kN;
 constexpr int kGlbN = Geo<kGlbP, kGlbQ>::kN;
@@ -640,8 +707,12 @@ hipError_t launch_chol_inv(const double *G, int64_t ldg, int n, double shift_rel
   if (n <= kRegN) {
     hipLaunchKernelGGL((chol_kernel<kRegP, kRegQ, false>), dim3(1), dim3(kThreads), 0, st, G,
                        ldg, n, shift_rel, Lws, ws, status);
-    hipLaunchKernelGGL((tri_inv_kernel<kRegP, kRegQ, false>), dim3(1), dim3(kThreads), 0, st, n,
-                       Lws, Rinv, ldr, ws);
+    const size_t lds = sizeof(double) * (size_t)n * (17 + 2 * kTiRB);
+    hipError_t e = hipFuncSetAttribute((const void *)tri_inv_cols_kernel,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(tri_inv_cols_kernel, dim3(ceil_div(n, 16)), dim3(256), lds, st, n, Lws,
+                       Rinv, ldr);
   } else {
     double *tile = glb_tile(ws);
     hipLaunchKernelGGL((chol_kernel<kGlbP, kGlbQ, true>), dim3(1), dim3(kThreads), 0, st, G,

@@ -34,13 +34,7 @@ SSI_DEV int row_of(int tr, int p) { return tr + 16 * p; }
 SSI_DEV int col_of(int tc, int q) { return tc + 32 * q; }
 SSI_DEV double sel(bool c, double v) { return c ? v : 0.0; }
 
-SSI_DEV double col_group_sum(double v) {
-  v += __shfl_xor(v, 1, 64);
-  v += __shfl_xor(v, 2, 64);
-  v += __shfl_xor(v, 4, 64);
-  v += __shfl_xor(v, 8, 64);
-  return v;
-}
+SSI_DEV double col_group_sum(double v) { return row16_sum(v); }
 
 struct OrderGeo {
   int n;          // model order
@@ -346,11 +340,7 @@ SSI_DEV void two_by_two_eigs(double a, double b, double c, double d, double *wr,
   }
 }
 
-SSI_DEV int wave_max_int(int v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v = max(v, __shfl_xor(v, off, 64));
-  return v;
-}
+SSI_DEV int wave_max_int(int v) { return wave_max_i(v); }
 
 // Maximum over the workgroup; every thread gets the result.
 SSI_DEV int block_max_int(int v, int *red) {
@@ -1063,16 +1053,8 @@ SSI_DEV cplx cdiv(cplx a, cplx b) {
   const double r = b.re / b.im, den = b.im + r * b.re;
   return {(a.re * r + a.im) / den, (a.im * r - a.re) / den};
 }
-SSI_DEV double wsum(double v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-  return v;
-}
-SSI_DEV double wmax(double v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
-  return v;
-}
+SSI_DEV double wsum(double v) { return wave_sum(v); }
+SSI_DEV double wmax(double v) { return wave_max(v); }
 
 }  // namespace
 
