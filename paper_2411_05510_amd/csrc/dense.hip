@@ -252,7 +252,7 @@ tri_inv_kernel(int n, const double *__restrict__ Lws, double *__restrict__ Rinv,
 // the current one is used; each wave's x rows live in its own slice of LDS,
 // so rows inside a block need no workgroup barrier.  Writes Rinv = X^T
 // (upper, zero below the diagonal).  LDS: 1 / L_ii [n], x [4][n][4], two L
-// blocks [2][16][n].
+// blocks [2][16][n], and a tail that the unguarded term loads may reach.
 constexpr int kTiQ = 14;                  // terms per lane: n - c0 <= 16 kTiQ
 constexpr int kTiRB = 16;                 // rows per L block
 __global__ void __launch_bounds__(256)
@@ -300,12 +300,17 @@ tri_inv_cols_kernel(int n, const double *__restrict__ Lws, double *__restrict__ 
       const int i = c0 + kTiRB * m + rr;
       if (i >= n) break;
       const int lim = i - c0;                          // terms k - c0 < lim
+      // every term is loaded (inside this workgroup's LDS) and the ones at
+      // and past the diagonal are dropped by a select, so the loads carry no
+      // branches
       double s0 = 0.0, s1 = 0.0;
 #pragma unroll
       for (int q = 0; q < kTiQ; q += 2) {
         const int k0 = p + 16 * q, k1 = k0 + 16;
-        if (k0 < lim) s0 += L[rr * n + k0] * xs[k0 * 4 + c];
-        if (k1 < lim) s1 += L[rr * n + k1] * xs[k1 * 4 + c];
+        const double t0 = L[rr * n + k0] * xs[k0 * 4 + c];
+        const double t1 = L[rr * n + k1] * xs[k1 * 4 + c];
+        s0 += (k0 < lim) ? t0 : 0.0;
+        s1 += (k1 < lim) ? t1 : 0.0;
       }
       const double s = row16_sum(s0 + s1);
       const double x = (i < col) ? 0.0 : ((i == col ? 1.0 : 0.0) - s) * rinv[i];
@@ -707,7 +712,9 @@ hipError_t launch_chol_inv(const double *G, int64_t ldg, int n, double shift_rel
   if (n <= kRegN) {
     hipLaunchKernelGGL((chol_kernel<kRegP, kRegQ, false>), dim3(1), dim3(kThreads), 0, st, G,
                        ldg, n, shift_rel, Lws, ws, status);
-    const size_t lds = sizeof(double) * (size_t)n * (17 + 2 * kTiRB);
+    // the term loads reach up to 16 kTiQ entries past a row or x-slice start
+    // whatever n is; the tail keeps them inside the allocation
+    const size_t lds = sizeof(double) * ((size_t)n * (17 + 2 * kTiRB) + 4 * 16 * kTiQ + 64);
     hipError_t e = hipFuncSetAttribute((const void *)tri_inv_cols_kernel,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
