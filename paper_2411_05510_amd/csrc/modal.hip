@@ -1164,8 +1164,11 @@ SSI_DEV void vec_pole(int o, int j, const double *__restrict__ hbuf,
     // the U rows written above are read back by other lanes below
     __threadfence_block();
     wave_sync();
-    // ---- two solves: U x = 1, then (L U) x = x.  Rows of U wait in a ring
-    // as above, kRingV rows ahead of the row being reduced.
+    // ---- inverse iteration: U x = 1 (the right-hand side whose L-solve is
+    // all ones), accepted when x has grown enough, max|x| eps3 >= 0.1 /
+    // sqrt(n) with eps3 = tiny (the acceptance test of LAPACK's Hessenberg
+    // inverse iteration); otherwise a second step (L U) x = x.  Rows of U wait
+    // in a ring as above, kRingV rows ahead of the row being reduced.
     for (int c = lane; c < n; c += 64) { x_re[c] = 1.0; x_im[c] = 0.0; }
     wave_sync();
     for (int pass = 0; pass < 2; ++pass) {
@@ -1244,6 +1247,7 @@ SSI_DEV void vec_pole(int o, int j, const double *__restrict__ hbuf,
       const double inv = mx > 0.0 ? 1.0 / mx : 1.0;
       for (int c = lane; c < n; c += 64) { x_re[c] *= inv; x_im[c] *= inv; }
       wave_sync();
+      if (mx * tiny >= 0.1 / sqrt((double)n)) break;    // grown enough: accepted
     }
     // ---- phi = C_h psi_H, unit 2-norm, largest-modulus entry real positive
     const double *C = chbuf + (int64_t)l * geo.vec;
