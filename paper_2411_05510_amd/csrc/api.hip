@@ -739,7 +739,7 @@ ssi_status run_svd_full(ssi_ctx *c, FullBufs &b, const float *t, int m, int64_t 
 struct ModalBufs {
   ssi::ModalSizes sz;
   double *gt, *hm, *rinv, *lws, *w, *dws, *part;
-  double *xbuf, *hbuf, *qbuf, *vref, *taus, *chbuf, *evbuf, *gscr, *vscr;
+  double *xbuf, *hbuf, *vref, *taus, *evbuf, *gscr, *vscr;
   double *tf, *txi, *tmu, *tphi;
   int *npole, *pidx, *flags_tmp;
   int *queue, *done;
@@ -760,10 +760,8 @@ ModalBufs carve_modal(Arena &a, ssi_ctx *c, int64_t m, int l, const ssi_params *
   b.part = a.take<double>(std::max(part_f64(kk, kk, (int)(m - l), cu), part_f64(kk, kk, kk, cu)));
   b.xbuf = a.take<double>(b.sz.sq);
   b.hbuf = a.take<double>(b.sz.sq);
-  b.qbuf = a.take<double>(b.sz.sq);
   b.vref = a.take<double>(b.sz.vref);
   b.taus = a.take<double>(b.sz.taus);
-  b.chbuf = a.take<double>(b.sz.ch);
   b.evbuf = a.take<double>(2 * b.sz.vec);
   b.gscr = a.take<double>((size_t)b.sz.n_orders * b.sz.francis_glb);
   b.vscr = a.take<double>((size_t)b.sz.vec_waves * b.sz.vec_stride);
@@ -807,11 +805,11 @@ ssi_status run_modal(ssi_ctx *c, ModalBufs &b, const double *u, int64_t m, int k
   a.ldu = k;
   a.l = l;
   a.fs = p->fs;
-  a.u = u;                    // C_h uses U[0:l, :n]
+  a.u = u;                    // mode shapes use U[0:l, :n]
   a.rinv = b.rinv;
   a.w = b.w;
-  a.xbuf = b.xbuf; a.hbuf = b.hbuf; a.qbuf = b.qbuf; a.vref = b.vref; a.taus = b.taus;
-  a.chbuf = b.chbuf; a.evbuf = b.evbuf; a.gscr = b.gscr; a.vscr = b.vscr;
+  a.xbuf = b.xbuf; a.hbuf = b.hbuf; a.vref = b.vref; a.taus = b.taus;
+  a.evbuf = b.evbuf; a.gscr = b.gscr; a.vscr = b.vscr;
   a.tf = b.tf; a.txi = b.txi; a.tmu = b.tmu; a.tphi = b.tphi;
   a.npole = b.npole; a.pidx = b.pidx; a.flags_tmp = b.flags_tmp;
   a.queue = b.queue; a.done = b.done; a.status = c->status;

@@ -106,7 +106,7 @@ int modal_max_order();
 struct ModalSizes {
   int n_orders;
   int64_t sq, vec, poles;       // sums over orders of n^2, n, n/2
-  int64_t vref, taus, ch;       // doubles
+  int64_t vref, taus;           // doubles
   int64_t vec_waves, vec_stride, francis_glb;
 };
 ModalSizes modal_sizes(int nmin, int nmax, int step, int l);
@@ -117,7 +117,7 @@ struct ModalArgs {
   int ldu;                      // leading dimension of u
   double fs;
   const double *u, *rinv, *w;
-  double *xbuf, *hbuf, *qbuf, *vref, *taus, *chbuf, *evbuf, *gscr, *vscr;
+  double *xbuf, *hbuf, *vref, *taus, *evbuf, *gscr, *vscr;
   double *tf, *txi, *tmu, *tphi;
   int *npole, *pidx, *flags_tmp;
   int *queue, *done;            // work counters and per-order flags of the eig launch

@@ -11,12 +11,12 @@
 //   form_x      X_n = Rinv[:n,:n] W[:n,:n]
 //   hess        Householder reduction X_n = Q H Q^T (H upper Hessenberg),
 //               matrix held in registers over a 16 x 32 thread grid
-//   qform       Q explicitly, then C_h = U[0:l, :n] Q
 //   francis     eigenvalues of H by the Francis double-shift QR iteration with
 //               deflation, H packed in LDS (n <= 200) or in global scratch
 //   vec         per pole (Im mu > 0): inverse iteration on H - mu I in complex
 //               arithmetic (Hessenberg LU with partial pivoting), psi_H, then
-//               phi = C_h psi_H, normalised; lambda = ln(mu) f_s, f, xi
+//               psi_X = Q psi_H by the Hessenberg reflectors and phi =
+//               U[0:l, :n] psi_X, normalised; lambda = ln(mu) f_s, f, xi
 //   francis and vec run in one persistent launch (eig_persistent_kernel):
 //   whole orders first, largest first, then poles, smallest orders first,
 //   each waiting for its order's eigenvalues
@@ -204,84 +204,6 @@ hess_kernel(const double *__restrict__ xbuf, int nmin, int step, double *__restr
       const int i = row_of(tr, p), j = col_of(tc, q);
       if (i < n && j < n) H[(int64_t)i * n + j] = (j >= i - 1) ? g[p][q] : 0.0;
     }
-}
-
-// ------------------------------------------------------------------ qform
-// Q = H_0 H_1 ... H_{n-3} (applied to the identity), written to qbuf.
-__global__ void __launch_bounds__(kT)
-qform_kernel(int nmin, int step, const double *__restrict__ vref,
-             const double *__restrict__ taus, double *__restrict__ qbuf) {
-  __shared__ double vbuf[kNR];
-  const OrderGeo geo = order_geo(blockIdx.x, nmin, step);
-  const int n = geo.n;
-  const double *vr = vref + (size_t)blockIdx.x * kNR * kNR;
-  const double *tv = taus + (size_t)blockIdx.x * kNR;
-  double *Q = qbuf + geo.sq;
-  const int t = threadIdx.x, tr = t & 15, tc = t >> 4;
-  double g[kTP][kTQ];
-#pragma unroll
-  for (int p = 0; p < kTP; ++p)
-#pragma unroll
-    for (int q = 0; q < kTQ; ++q)
-      g[p][q] = sel(row_of(tr, p) == col_of(tc, q) && row_of(tr, p) < n, 1.0);
-  // Reflector k touches rows > k only: row blocks before k / 16 are skipped.
-#pragma unroll kTP
-  for (int kb = kTP - 1; kb >= 0; --kb) {
-    const int k0 = 16 * kb, k1 = min(k0 + 16, n - 2);
-    for (int k = k1 - 1; k >= k0; --k) {
-      for (int i = t; i < n; i += kT) vbuf[i] = (i > k) ? vr[(size_t)k * kNR + i] : 0.0;
-      __syncthreads();
-      const double tau = tv[k];
-      if (tau != 0.0) {
-        double sq[kTQ];
-#pragma unroll
-        for (int q = 0; q < kTQ; ++q) sq[q] = 0.0;
-#pragma unroll
-        for (int p = 0; p < kTP; ++p) {
-          if (p < kb) continue;
-          const int i = row_of(tr, p);
-          const double vi = sel(i > k && i < n, vbuf[min(i, kNR - 1)]);
-#pragma unroll
-          for (int q = 0; q < kTQ; ++q) sq[q] += vi * g[p][q];
-        }
-#pragma unroll
-        for (int q = 0; q < kTQ; ++q) sq[q] = tau * col_group_sum(sq[q]);
-#pragma unroll
-        for (int p = 0; p < kTP; ++p) {
-          if (p < kb) continue;
-          const int i = row_of(tr, p);
-          const double vi = sel(i > k && i < n, vbuf[min(i, kNR - 1)]);
-#pragma unroll
-          for (int q = 0; q < kTQ; ++q) g[p][q] -= vi * sq[q];
-        }
-      }
-      __syncthreads();
-    }
-  }
-#pragma unroll
-  for (int p = 0; p < kTP; ++p)
-#pragma unroll
-    for (int q = 0; q < kTQ; ++q) {
-      const int i = row_of(tr, p), j = col_of(tc, q);
-      if (i < n && j < n) Q[(int64_t)i * n + j] = g[p][q];
-    }
-}
-
-// C_h = U[0:l, :n] Q  (l x n per order, ld n)
-__global__ void __launch_bounds__(256)
-ch_kernel(const double *__restrict__ u, int k, int l, int nmin, int step,
-          const double *__restrict__ qbuf, double *__restrict__ chbuf) {
-  const OrderGeo geo = order_geo(blockIdx.y, nmin, step);
-  const int n = geo.n;
-  const double *Q = qbuf + geo.sq;
-  double *C = chbuf + (int64_t)l * geo.vec;
-  const int total = l * n;
-  for (int idx = blockIdx.x * 256 + threadIdx.x; idx < total; idx += gridDim.x * 256) {
-    const int a = idx / n, c = idx - a * n;
-    double s = 0.0;
-    for (int r = 0; r < n; ++r) s += u[(int64_t)a * k + r] * Q[(int64_t)r * n + c];
-    C[idx] = s;
-  }
 }
 
 // ------------------------------------------------------------------ francis
@@ -1064,7 +986,8 @@ SSI_DEV double wmax(double v) { return wave_max(v); }
 // the unsorted pole f, xi, mu, phi (l complex) at slot pole(o) + j of the
 // temporary arrays.
 SSI_DEV void vec_pole(int o, int j, const double *__restrict__ hbuf,
-                      const double *__restrict__ chbuf, const double *__restrict__ evbuf,
+                      const double *__restrict__ vref, const double *__restrict__ taus,
+                      const double *__restrict__ u, int ldu, const double *__restrict__ evbuf,
                       const int *__restrict__ pidx, int nmin, int step, int l, double fs,
                       double *__restrict__ ure, double *__restrict__ uim, double *x_re,
                       double *x_im, double *mult_re, double *mult_im, int *swp,
@@ -1249,15 +1172,68 @@ SSI_DEV void vec_pole(int o, int j, const double *__restrict__ hbuf,
       wave_sync();
       if (mx * tiny >= 0.1 / sqrt((double)n)) break;    // grown enough: accepted
     }
-    // ---- phi = C_h psi_H, unit 2-norm, largest-modulus entry real positive
-    const double *C = chbuf + (int64_t)l * geo.vec;
+    // ---- psi_X = Q psi_H, Q = H_0 H_1 ... H_{n-3} the reflectors of the
+    // Hessenberg reduction (H_k = I - tau_k v_k v_k^T, v_k zero at and above
+    // row k): applied from H_{n-3} down to H_0, psi in registers (lane c % 64,
+    // slot c / 64), the reflector rows arriving through a register ring.
+    {
+      const double *vr = vref + (size_t)o * kNR * kNR;
+      const double *tv = taus + (size_t)o * kNR;
+      constexpr int kRingQ = 8;
+      double pr_[kU], pi_[kU], vq[kRingQ][kU];
+#pragma unroll
+      for (int u2 = 0; u2 < kU; ++u2) {
+        const int c = lane + 64 * u2;
+        pr_[u2] = c < n ? x_re[c] : 0.0;
+        pi_[u2] = c < n ? x_im[c] : 0.0;
+      }
+#pragma unroll
+      for (int d = 0; d < kRingQ; ++d)
+#pragma unroll
+        for (int u2 = 0; u2 < kU; ++u2) {
+          const int c = lane + 64 * u2, k = n - 3 - d;
+          vq[d][u2] = (k >= 0 && c < n) ? vr[(size_t)k * kNR + c] : 0.0;
+        }
+      for (int k0 = n - 3; k0 >= 0; k0 -= kRingQ) {
+#pragma unroll
+        for (int d = 0; d < kRingQ; ++d) {
+          const int k = k0 - d;
+          if (k < 0) break;
+          const double tau = tv[k];
+          double sre = 0.0, sim = 0.0;
+#pragma unroll
+          for (int u2 = 0; u2 < kU; ++u2) {
+            sre += vq[d][u2] * pr_[u2];
+            sim += vq[d][u2] * pi_[u2];
+          }
+          sre = tau * wsum(sre);
+          sim = tau * wsum(sim);
+#pragma unroll
+          for (int u2 = 0; u2 < kU; ++u2) {
+            pr_[u2] -= sre * vq[d][u2];
+            pi_[u2] -= sim * vq[d][u2];
+            const int c = lane + 64 * u2, kn = k - kRingQ;   // refill with reflector k - kRingQ
+            vq[d][u2] = (kn >= 0 && c < n) ? vr[(size_t)kn * kNR + c] : 0.0;
+          }
+        }
+      }
+      wave_sync();                        // every lane has read x before it is overwritten
+#pragma unroll
+      for (int u2 = 0; u2 < kU; ++u2) {
+        const int c = lane + 64 * u2;
+        if (c < n) { x_re[c] = pr_[u2]; x_im[c] = pi_[u2]; }
+      }
+      wave_sync();
+    }
+    // ---- phi = U[0:l, :n] psi_X (Eq. (12) via C = first l rows of the
+    // observability matrix), unit 2-norm, largest-modulus entry real positive
     const int slot = geo.pole + j;
     double *ph = tphi + (size_t)slot * l * 2;
     double nrm2 = 0.0, best = -1.0, bre = 1.0, bim = 0.0;
     for (int a = lane; a < l; a += 64) {
       double sre = 0.0, sim = 0.0;
       for (int c = 0; c < n; ++c) {
-        const double cv = C[(int64_t)a * n + c];
+        const double cv = u[(int64_t)a * ldu + c];
         sre += cv * x_re[c];
         sim += cv * x_im[c];
       }
@@ -1323,7 +1299,8 @@ eig_init_kernel(int *__restrict__ queue, int *__restrict__ done, int n_orders) {
 }
 
 __global__ void __launch_bounds__(kFT)
-eig_persistent_kernel(const double *__restrict__ hbuf, const double *__restrict__ chbuf,
+eig_persistent_kernel(const double *__restrict__ hbuf, const double *__restrict__ vref,
+                      const double *__restrict__ taus, const double *__restrict__ u, int ldu,
                       int nmin, int step, int n_orders, int l, double fs,
                       double *__restrict__ gscr, int64_t gstride, double *__restrict__ evbuf,
                       int *__restrict__ npole, int *__restrict__ pidx, int *__restrict__ flags,
@@ -1394,8 +1371,8 @@ eig_persistent_kernel(const double *__restrict__ hbuf, const double *__restrict_
     if (!ready) continue;
     (void)__hip_atomic_load(&done[o], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);  // every lane
     if (rem >= npole[o]) continue;
-    vec_pole(o, rem, hbuf, chbuf, evbuf, pidx, nmin, step, l, fs, ure, uim, x_re, x_im, mult_re,
-             mult_im, swp, tf, txi, tmu, tphi);
+    vec_pole(o, rem, hbuf, vref, taus, u, ldu, evbuf, pidx, nmin, step, l, fs, ure, uim, x_re,
+             x_im, mult_re, mult_im, swp, tf, txi, tmu, tphi);
   }
 }
 
@@ -1462,7 +1439,6 @@ ModalSizes modal_sizes(int nmin, int nmax, int step, int l) {
   }
   s.vref = (int64_t)s.n_orders * kNR * kNR;
   s.taus = (int64_t)s.n_orders * kNR;
-  s.ch = (int64_t)l * s.vec;
   s.vec_waves = (int64_t)kEigGrid * (kFT / 64);
   s.vec_stride = 2 * ((int64_t)kNR * (kNR + 1) / 2 + 64);
   s.francis_glb = (int64_t)HIdx::packed_size(kNR) + kExtra;
@@ -1476,10 +1452,6 @@ hipError_t launch_modal(const ModalArgs &a, hipStream_t st) {
                      a.step, a.xbuf);
   hipLaunchKernelGGL(hess_kernel, dim3(no), dim3(kT), 0, st, a.xbuf, a.nmin, a.step, a.hbuf,
                      a.vref, a.taus);
-  hipLaunchKernelGGL(qform_kernel, dim3(no), dim3(kT), 0, st, a.nmin, a.step, a.vref, a.taus,
-                     a.qbuf);
-  hipLaunchKernelGGL(ch_kernel, dim3(32, no), dim3(256), 0, st, a.u, a.ldu, a.l, a.nmin, a.step,
-                     a.qbuf, a.chbuf);
   // QR iterations and pole vectors of all orders in one persistent launch
   hipLaunchKernelGGL(eig_init_kernel, dim3(1), dim3(kFT), 0, st, a.queue, a.done, no);
   hipError_t e = hipFuncSetAttribute((const void *)eig_persistent_kernel,
@@ -1487,7 +1459,8 @@ hipError_t launch_modal(const ModalArgs &a, hipStream_t st) {
                                      (int)(sizeof(double) * kLdsDoubles));
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(eig_persistent_kernel, dim3(kEigGrid), dim3(kFT),
-                     sizeof(double) * kLdsDoubles, st, a.hbuf, a.chbuf, a.nmin, a.step, no, a.l,
+                     sizeof(double) * kLdsDoubles, st, a.hbuf, a.vref, a.taus, a.u, a.ldu,
+                     a.nmin, a.step, no, a.l,
                      a.fs, a.gscr, s.francis_glb, a.evbuf, a.npole, a.pidx, a.flags_tmp, a.vscr,
                      s.vec_stride, a.tf, a.txi, a.tmu, a.tphi, a.queue, a.done, a.status);
   hipLaunchKernelGGL(sort_kernel, dim3(no), dim3(256), 0, st, a.nmin, a.step, a.l, a.npole,
