@@ -813,6 +813,9 @@ ssi_status run_modal(ssi_ctx *c, ModalBufs &b, const double *u, int64_t m, int k
   a.tf = b.tf; a.txi = b.txi; a.tmu = b.tmu; a.tphi = b.tphi;
   a.npole = b.npole; a.pidx = b.pidx; a.flags_tmp = b.flags_tmp;
   a.queue = b.queue; a.done = b.done; a.status = c->status;
+  // with lags on several streams, a grid of one workgroup per order leaves
+  // the other CUs to the other lags' kernels
+  a.eig_grid = std::min(c->n_lanes, p->n_lags) > 1 ? no : 0;
   a.count = out->count + (int64_t)lag_i * no;
   a.flags = out->flags + (int64_t)lag_i * no;
   a.f = out->f + (int64_t)lag_i * pole_cap;

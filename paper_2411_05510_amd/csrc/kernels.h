@@ -122,6 +122,7 @@ struct ModalArgs {
   int *npole, *pidx, *flags_tmp;
   int *queue, *done;            // work counters and per-order flags of the eig launch
   int *status;                  // context status word
+  int eig_grid;                 // workgroups of the eigen-analysis launch, 0: one per CU
   int32_t *count, *flags;       // outputs of this lag
   double *f, *xi, *mu;
   float *phi;

@@ -1458,7 +1458,11 @@ hipError_t launch_modal(const ModalArgs &a, hipStream_t st) {
                                      hipFuncAttributeMaxDynamicSharedMemorySize,
                                      (int)(sizeof(double) * kLdsDoubles));
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(eig_persistent_kernel, dim3(kEigGrid), dim3(kFT),
+  // one workgroup per CU by default; a smaller grid (at least one workgroup
+  // per order) leaves CUs to work on other streams
+  const int grid = a.eig_grid > 0 ? std::min(std::max(a.eig_grid, std::min(no, kEigGrid)), kEigGrid)
+                                  : kEigGrid;
+  hipLaunchKernelGGL(eig_persistent_kernel, dim3(grid), dim3(kFT),
                      sizeof(double) * kLdsDoubles, st, a.hbuf, a.vref, a.taus, a.u, a.ldu,
                      a.nmin, a.step, no, a.l,
                      a.fs, a.gscr, s.francis_glb, a.evbuf, a.npole, a.pidx, a.flags_tmp, a.vscr,
