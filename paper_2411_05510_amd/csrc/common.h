@@ -39,6 +39,22 @@ SSI_DEV double row16_sum(double v) {
   v += dpp_d<0x140>(v);
   return v;
 }
+// Sum over the four rows of the wave at this lane's position in its row
+// (lanes l, l ^ 16, l ^ 32, l ^ 48); every lane gets its column's sum.
+// v_permlane16_swap exchanges rows 0 <-> 1 and 2 <-> 3, v_permlane32_swap the
+// two halves (VALU moves, no LDS); an FP64 value moves as two dwords.  With
+// both operands equal, the swap's two results hold v and its partner.
+SSI_DEV double rows4_sum(double v) {
+  unsigned lo = __double2loint(v), hi = __double2hiint(v);
+  const auto a = __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
+  const auto b = __builtin_amdgcn_permlane16_swap(hi, hi, false, false);
+  const double s = __hiloint2double(b[0], a[0]) + __hiloint2double(b[1], a[1]);
+  lo = __double2loint(s);
+  hi = __double2hiint(s);
+  const auto c = __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
+  const auto d = __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
+  return __hiloint2double(d[0], c[0]) + __hiloint2double(d[1], c[1]);
+}
 SSI_DEV double row16_max(double v) {
   v = fmax(v, dpp_d<0xB1>(v));
   v = fmax(v, dpp_d<0x4E>(v));

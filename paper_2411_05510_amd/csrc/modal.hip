@@ -76,7 +76,9 @@ form_x_kernel(const double *__restrict__ rinv, const double *__restrict__ w, int
 // ------------------------------------------------------------------ hess
 // Householder reduction of X_n (n <= 224) to upper Hessenberg form.  Writes H
 // (n x n, ld n) to hbuf, reflector vectors (rows of kNR) to vref and their
-// scalars to taus.
+// scalars to taus.  TP row blocks of 16 cover n <= 16 TP (13 for n <= 208
+// keeps the register tile clear of scratch spills; 14 for n <= 224).
+template <int TP>
 __global__ void __launch_bounds__(kT)
 hess_kernel(const double *__restrict__ xbuf, int nmin, int step, double *__restrict__ hbuf,
             double *__restrict__ vref, double *__restrict__ taus) {
@@ -90,9 +92,9 @@ hess_kernel(const double *__restrict__ xbuf, int nmin, int step, double *__restr
   double *vr = vref + (size_t)blockIdx.x * kNR * kNR;
   double *tv = taus + (size_t)blockIdx.x * kNR;
   const int t = threadIdx.x, tr = t & 15, tc = t >> 4, lane = t & 63, wave = t >> 6;
-  double g[kTP][kTQ];
+  double g[TP][kTQ];
 #pragma unroll
-  for (int p = 0; p < kTP; ++p)
+  for (int p = 0; p < TP; ++p)
 #pragma unroll
     for (int q = 0; q < kTQ; ++q) {
       const int i = row_of(tr, p), j = col_of(tc, q);
@@ -109,7 +111,7 @@ hess_kernel(const double *__restrict__ xbuf, int nmin, int step, double *__restr
       if (tc == (k & 31)) {
         double s2 = 0.0, x1 = 0.0;
 #pragma unroll
-        for (int p = 0; p < kTP; ++p) {
+        for (int p = 0; p < TP; ++p) {
           const int i = row_of(tr, p);
           const double v = g[p][kq];
           x1 += sel(i == k + 1, v);
@@ -124,7 +126,7 @@ hess_kernel(const double *__restrict__ xbuf, int nmin, int step, double *__restr
           tau = 2.0 / (s2 + v1 * v1);
         }
 #pragma unroll
-        for (int p = 0; p < kTP; ++p) {
+        for (int p = 0; p < TP; ++p) {
           const int i = row_of(tr, p);
           if (i < n) {
             const double v = (i == k + 1) ? v1 : sel(i > k + 1, g[p][kq]);
@@ -145,7 +147,7 @@ hess_kernel(const double *__restrict__ xbuf, int nmin, int step, double *__restr
 #pragma unroll
         for (int q = 0; q < kTQ; ++q) zq[q] = 0.0;
 #pragma unroll
-        for (int p = 0; p < kTP; ++p) {
+        for (int p = 0; p < TP; ++p) {
           if (p < 2 * kq) continue;
           const int i = row_of(tr, p);
           const double vi = sel(i > k && i < n, vbuf[min(i, kNR - 1)]);
@@ -164,7 +166,7 @@ hess_kernel(const double *__restrict__ xbuf, int nmin, int step, double *__restr
           vj[q] = sel(q >= kq && j > k && j < n, vbuf[min(j, kNR - 1)]);
         }
 #pragma unroll
-        for (int p = 0; p < kTP; ++p) {
+        for (int p = 0; p < TP; ++p) {
           const int i = row_of(tr, p);
           const double vi = sel(i > k && i < n, vbuf[min(i, kNR - 1)]);
           double acc = 0.0;
@@ -175,13 +177,12 @@ hess_kernel(const double *__restrict__ xbuf, int nmin, int step, double *__restr
             acc += g[p][q] * vj[q];
           }
           // right: y = X v (row sums over all 32 grid columns)
-          acc += __shfl_xor(acc, 16, 64);
-          acc += __shfl_xor(acc, 32, 64);
+          acc = rows4_sum(acc);
           if ((lane >> 4) == 0) ypart[wave][i] = acc;
         }
         __syncthreads();
 #pragma unroll
-        for (int p = 0; p < kTP; ++p) {
+        for (int p = 0; p < TP; ++p) {
           const int i = row_of(tr, p);
           double y = 0.0;
 #pragma unroll
@@ -198,7 +199,7 @@ hess_kernel(const double *__restrict__ xbuf, int nmin, int step, double *__restr
     }
   }
 #pragma unroll
-  for (int p = 0; p < kTP; ++p)
+  for (int p = 0; p < TP; ++p)
 #pragma unroll
     for (int q = 0; q < kTQ; ++q) {
       const int i = row_of(tr, p), j = col_of(tc, q);
@@ -1450,8 +1451,12 @@ hipError_t launch_modal(const ModalArgs &a, hipStream_t st) {
   const int no = s.n_orders;
   hipLaunchKernelGGL(form_x_kernel, dim3(64, no), dim3(256), 0, st, a.rinv, a.w, a.ldw, a.nmin,
                      a.step, a.xbuf);
-  hipLaunchKernelGGL(hess_kernel, dim3(no), dim3(kT), 0, st, a.xbuf, a.nmin, a.step, a.hbuf,
-                     a.vref, a.taus);
+  if (a.nmin + (no - 1) * a.step <= 16 * 13)
+    hipLaunchKernelGGL(hess_kernel<13>, dim3(no), dim3(kT), 0, st, a.xbuf, a.nmin, a.step,
+                       a.hbuf, a.vref, a.taus);
+  else
+    hipLaunchKernelGGL(hess_kernel<kTP>, dim3(no), dim3(kT), 0, st, a.xbuf, a.nmin, a.step,
+                       a.hbuf, a.vref, a.taus);
   // QR iterations and pole vectors of all orders in one persistent launch
   hipLaunchKernelGGL(eig_init_kernel, dim3(1), dim3(kFT), 0, st, a.queue, a.done, no);
   hipError_t e = hipFuncSetAttribute((const void *)eig_persistent_kernel,
