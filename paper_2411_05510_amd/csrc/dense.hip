@@ -76,9 +76,8 @@ chol_kernel(const double *__restrict__ G, int64_t ldg, int n, double shift_rel,
             double *__restrict__ Lws, double *__restrict__ tile_ws, int *__restrict__ status) {
   constexpr int kN = Geo<TP, TQ>::kN;
   constexpr int UP = GM ? 1 : TP, UQ = GM ? 1 : TQ;
-  __shared__ double colbuf[kN];
+  __shared__ double colbuf[2][kN];
   __shared__ double red[kWaves];
-  __shared__ double piv;
   __shared__ int bad;
   const int t = threadIdx.x, tr = t & 15, tc = t >> 4;
   Tile<TP, TQ, GM> g;
@@ -104,27 +103,28 @@ chol_kernel(const double *__restrict__ G, int64_t ldg, int n, double shift_rel,
   // Column k lives in column block kq = k / 32.  The block loop is unrolled in
   // register mode, so the pivot column's registers are compile-time indices;
   // row blocks above the pivot and blocks strictly above the diagonal are
-  // never touched again and are skipped.
+  // never touched again and are skipped.  The 16 lanes that own column k (one
+  // row of one wave) take the diagonal entry by a row sum, scale the column
+  // and publish it in colbuf[k & 1]: one workgroup barrier per column, the
+  // other buffer still being read by threads finishing column k - 1.
 #pragma unroll UQ
   for (int kq = 0; kq < TQ; ++kq) {
     const int k0 = 32 * kq, k1 = min(k0 + 32, n);
     for (int k = k0; k < k1; ++k) {
-      if (tr == (k & 15) && tc == (k & 31)) {
-        double d = 0.0;
+      double *cb = colbuf[k & 1];
+      if (tc == (k & 31)) {
+        double dpart = 0.0;
 #pragma unroll UP
         for (int p = 0; p < TP; ++p) {
           if (p < 2 * kq) continue;
-          d += sel(row_of(tr, p) == k, g(p, kq));
+          dpart += sel(row_of(tr, p) == k, g(p, kq));
         }
+        double d = row16_sum(dpart);           // the diagonal entry, in all 16 lanes
         if (!(d > 0.0)) {
           bad = 1;
           d = 1e-300;
         }
-        piv = sqrt(d);
-      }
-      __syncthreads();
-      const double pv = piv, rpv = 1.0 / pv;
-      if (tc == (k & 31)) {
+        const double pv = sqrt(d), rpv = 1.0 / pv;
 #pragma unroll UP
         for (int p = 0; p < TP; ++p) {
           if (p < 2 * kq) continue;
@@ -132,7 +132,7 @@ chol_kernel(const double *__restrict__ G, int64_t ldg, int n, double shift_rel,
           const double nv = (i == k) ? pv : g(p, kq) * rpv;
           if (i >= k && i < n) {
             g(p, kq) = nv;
-            colbuf[i] = nv;
+            cb[i] = nv;
           }
         }
       }
@@ -141,13 +141,13 @@ chol_kernel(const double *__restrict__ G, int64_t ldg, int n, double shift_rel,
 #pragma unroll UQ
       for (int q = 0; q < TQ; ++q) {
         const int j = col_of(tc, q);
-        cj[q] = sel(q >= kq && j > k && j < n, colbuf[min(j, kN - 1)]);
+        cj[q] = sel(q >= kq && j > k && j < n, cb[min(j, kN - 1)]);
       }
 #pragma unroll UP
       for (int p = 0; p < TP; ++p) {
         const int i = row_of(tr, p);
         if (p < 2 * kq || (GM && (i <= k || i >= n))) continue;
-        const double ci = sel(i > k && i < n, colbuf[min(i, kN - 1)]);
+        const double ci = sel(i > k && i < n, cb[min(i, kN - 1)]);
 #pragma unroll UQ
         for (int q = 0; q < TQ; ++q) {
           if (q < kq || 32 * q > 16 * p + 15) continue;
@@ -336,10 +336,10 @@ sym_tridiag_kernel(const double *__restrict__ G, int64_t ldg, int n, double *__r
                    double *__restrict__ tile_ws) {
   constexpr int kN = Geo<TP, TQ>::kN;
   constexpr int UP = GM ? 1 : TP, UQ = GM ? 1 : TQ;
-  __shared__ double vbuf[kN];
-  __shared__ double pbuf[kN];
+  __shared__ double vbufs[2][kN];
+  __shared__ double pbufs[2][kN];
   __shared__ double red[kWaves];
-  __shared__ double stau;
+  __shared__ double staus[2];
   const int t = threadIdx.x, tr = t & 15, tc = t >> 4;
   double *vref = ws;
   double *tauv = ws + (size_t)kN * kN;
@@ -363,6 +363,9 @@ sym_tridiag_kernel(const double *__restrict__ G, int64_t ldg, int n, double *__r
   for (int kq = 0; kq < TQ; ++kq) {
     const int k0 = 32 * kq, k1 = min(k0 + 32, n - 2);
     for (int k = k0; k < k1; ++k) {
+      // column k's vector, p and tau alternate between two buffers, so the
+      // next column's owner may publish before every thread is done with k
+      double *vbuf = vbufs[k & 1], *pbuf = pbufs[k & 1];
       if (tc == (k & 31)) {
         // Householder vector of column k below the diagonal
         double s2 = 0.0, x1 = 0.0, dk = 0.0;
@@ -393,14 +396,14 @@ sym_tridiag_kernel(const double *__restrict__ G, int64_t ldg, int n, double *__r
           }
         }
         if (tr == 0) {
-          stau = tau;
+          staus[k & 1] = tau;
           tauv[k] = tau;
           dd[k] = dk;
           ee[k] = alpha;
         }
       }
       __syncthreads();
-      const double tau = stau;
+      const double tau = staus[k & 1];
       if (tau != 0.0) {
         // p = tau G v by column sums (G symmetric); K = v^T p
         double sq[TQ];
@@ -451,7 +454,6 @@ sym_tridiag_kernel(const double *__restrict__ G, int64_t ldg, int n, double *__r
           }
         }
       }
-      __syncthreads();
     }
   }
   // trailing 2 x 2 (or 1 x 1) block

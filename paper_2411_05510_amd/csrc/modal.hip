@@ -84,7 +84,7 @@ hess_kernel(const double *__restrict__ xbuf, int nmin, int step, double *__restr
             double *__restrict__ vref, double *__restrict__ taus) {
   __shared__ double vbuf[kNR];
   __shared__ double ypart[8][kNR];
-  __shared__ double stau;
+  __shared__ double stau[2];
   const OrderGeo geo = order_geo(blockIdx.x, nmin, step);
   const int n = geo.n;
   const double *X = xbuf + geo.sq;
@@ -135,12 +135,12 @@ hess_kernel(const double *__restrict__ xbuf, int nmin, int step, double *__restr
           }
         }
         if (tr == 0) {
-          stau = tau;
+          stau[k & 1] = tau;
           tv[k] = tau;
         }
       }
       __syncthreads();
-      const double tau = stau;
+      const double tau = stau[k & 1];
       if (tau != 0.0) {
         // left: X -= tau v (v^T X)
         double zq[kTQ];
@@ -195,7 +195,9 @@ hess_kernel(const double *__restrict__ xbuf, int nmin, int step, double *__restr
           }
         }
       }
-      __syncthreads();
+      // No closing barrier: every read of vbuf for column k precedes the
+      // barrier above, ypart is rewritten only after the next column's first
+      // barrier, and tau alternates between two slots.
     }
   }
 #pragma unroll
