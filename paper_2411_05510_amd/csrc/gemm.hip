@@ -39,10 +39,17 @@ constexpr int wAS = wBM * wLA, wBS = wKT * wLB;   // one buffer, elements
 typedef double f64x2v __attribute__((ext_vector_type(2)));
 typedef float f32x4v __attribute__((ext_vector_type(4)));
 
+// Every load is issued unconditionally, from an index clamped into its row;
+// the entries outside the tile's range are flagged in msk (bit 4 h + c of the
+// A part, bit 8 + 2 h + c of the B part) and zeroed when the tile is stored.
+// The loads then stay in flight across the MFMAs of the current tile: with a
+// bounds branch around each load the compiler waits for every load before
+// issuing the next.
 template <bool TA, bool VEC, bool BVEC>
 SSI_DEV void tf64w_load(const float *__restrict__ A, int64_t lda, const double *__restrict__ B,
                         int64_t ldb, int M, int N, int m0, int n0, int k0, int ke, int tid,
-                        f32x4v (&ra)[2], f64x2v (&rb)[7]) {
+                        f32x4v (&ra)[2], f64x2v (&rb)[7], unsigned &msk) {
+  unsigned m = 0u;
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
     const int idx = tid + 512 * h;
@@ -51,28 +58,30 @@ SSI_DEV void tf64w_load(const float *__restrict__ A, int64_t lda, const double *
       const int r = idx >> 3, c4 = idx & 7;               // row, 4-column group of k
       const int gi = m0 + r, gk = k0 + 4 * c4;
       const float *p = A + (int64_t)min(gi, M - 1) * lda;
-      if (VEC && gk + 3 < ke) {
-        v = *reinterpret_cast<const f32x4v *>(p + gk);
+      if (VEC) {
+        v = *reinterpret_cast<const f32x4v *>(p + min((int64_t)gk, lda - 4));
       } else {
-        v.x = gk < ke ? p[gk] : 0.f;
-        v.y = gk + 1 < ke ? p[gk + 1] : 0.f;
-        v.z = gk + 2 < ke ? p[gk + 2] : 0.f;
-        v.w = gk + 3 < ke ? p[gk + 3] : 0.f;
+        v.x = p[min(gk, ke - 1)];
+        v.y = p[min(gk + 1, ke - 1)];
+        v.z = p[min(gk + 2, ke - 1)];
+        v.w = p[min(gk + 3, ke - 1)];
       }
-      if (gi >= M) v = f32x4v{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int c = 0; c < 4; ++c) m |= (gi < M && gk + c < ke ? 1u : 0u) << (4 * h + c);
     } else {
       const int kr = idx >> 5, c4 = idx & 31;             // k row, 4-column group of i
       const int gk = k0 + kr, gi = m0 + 4 * c4;
       const float *p = A + (int64_t)min(gk, ke - 1) * lda;
-      if (VEC && gi + 3 < M) {
-        v = *reinterpret_cast<const f32x4v *>(p + gi);
+      if (VEC) {
+        v = *reinterpret_cast<const f32x4v *>(p + min((int64_t)gi, lda - 4));
       } else {
-        v.x = gi < M ? p[gi] : 0.f;
-        v.y = gi + 1 < M ? p[gi + 1] : 0.f;
-        v.z = gi + 2 < M ? p[gi + 2] : 0.f;
-        v.w = gi + 3 < M ? p[gi + 3] : 0.f;
+        v.x = p[min(gi, M - 1)];
+        v.y = p[min(gi + 1, M - 1)];
+        v.z = p[min(gi + 2, M - 1)];
+        v.w = p[min(gi + 3, M - 1)];
       }
-      if (gk >= ke) v = f32x4v{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int c = 0; c < 4; ++c) m |= (gk < ke && gi + c < M ? 1u : 0u) << (4 * h + c);
     }
     ra[h] = v;
   }
@@ -83,39 +92,49 @@ SSI_DEV void tf64w_load(const float *__restrict__ A, int64_t lda, const double *
     const int gk = k0 + kr, gj = n0 + 2 * c2;
     const double *q = B + (int64_t)min(gk, ke - 1) * ldb;
     f64x2v v;
-    if (BVEC && gj + 1 < N) {
-      v = *reinterpret_cast<const f64x2v *>(q + gj);
+    if (BVEC) {
+      v = *reinterpret_cast<const f64x2v *>(q + min((int64_t)gj, ldb - 2));
     } else {
-      v.x = gj < N ? q[gj] : 0.0;
-      v.y = gj + 1 < N ? q[gj + 1] : 0.0;
+      v.x = q[min(gj, N - 1)];
+      v.y = q[min(gj + 1, N - 1)];
     }
-    if (gk >= ke) v = f64x2v{0.0, 0.0};
+    m |= (gk < ke && gj < N ? 1u : 0u) << (8 + 2 * h);
+    m |= (gk < ke && gj + 1 < N ? 1u : 0u) << (9 + 2 * h);
     rb[h] = v;
   }
+  msk = m;
 }
 
 template <bool TA>
 SSI_DEV void tf64w_store(float *__restrict__ As, double *__restrict__ Bs, int tid,
-                         const f32x4v (&ra)[2], const f64x2v (&rb)[7]) {
+                         const f32x4v (&ra)[2], const f64x2v (&rb)[7], unsigned msk) {
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
     const int idx = tid + 512 * h;
+    f32x4v v = ra[h];
+    v.x = (msk >> (4 * h)) & 1u ? v.x : 0.f;
+    v.y = (msk >> (4 * h + 1)) & 1u ? v.y : 0.f;
+    v.z = (msk >> (4 * h + 2)) & 1u ? v.z : 0.f;
+    v.w = (msk >> (4 * h + 3)) & 1u ? v.w : 0.f;
     if (!TA) {
       const int r = idx >> 3, c4 = idx & 7;
-      *reinterpret_cast<f32x4v *>(&As[r * wLA + 4 * c4]) = ra[h];
+      *reinterpret_cast<f32x4v *>(&As[r * wLA + 4 * c4]) = v;
     } else {
       const int kr = idx >> 5, c4 = idx & 31;
-      As[(4 * c4 + 0) * wLA + kr] = ra[h].x;
-      As[(4 * c4 + 1) * wLA + kr] = ra[h].y;
-      As[(4 * c4 + 2) * wLA + kr] = ra[h].z;
-      As[(4 * c4 + 3) * wLA + kr] = ra[h].w;
+      As[(4 * c4 + 0) * wLA + kr] = v.x;
+      As[(4 * c4 + 1) * wLA + kr] = v.y;
+      As[(4 * c4 + 2) * wLA + kr] = v.z;
+      As[(4 * c4 + 3) * wLA + kr] = v.w;
     }
   }
 #pragma unroll
   for (int h = 0; h < 7; ++h) {
     const int idx = tid + 512 * h;
     const int kr = idx / 112, c2 = idx - kr * 112;
-    *reinterpret_cast<f64x2v *>(&Bs[kr * wLB + 2 * c2]) = rb[h];
+    f64x2v v = rb[h];
+    v.x = (msk >> (8 + 2 * h)) & 1u ? v.x : 0.0;
+    v.y = (msk >> (9 + 2 * h)) & 1u ? v.y : 0.0;
+    *reinterpret_cast<f64x2v *>(&Bs[kr * wLB + 2 * c2]) = v;
   }
 }
 }  // namespace
@@ -128,7 +147,9 @@ gemm_tf64w_mfma(const float *__restrict__ A, int64_t lda, const double *__restri
   extern __shared__ __attribute__((aligned(16))) double smem[];
   float *Asb = reinterpret_cast<float *>(smem);                  // [2][wAS] floats
   double *Bsb = smem + wAS;                                       // [2][wBS] doubles (wAS even)
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);   // uniform: the column
+                                                               // checks stay scalar
   const int wr = wave & 3, wc = wave >> 2;
   const int split = blockIdx.x % splits;
   const int rest = blockIdx.x / splits;
@@ -147,15 +168,17 @@ gemm_tf64w_mfma(const float *__restrict__ A, int64_t lda, const double *__restri
 
   f32x4v ra[2];
   f64x2v rb[7];
+  unsigned msk = 0u;
   int buf = 0;
   if (kb < ke) {
-    tf64w_load<TA, VEC, BVEC>(A, lda, B, ldb, M, N, m0, n0, kb, ke, tid, ra, rb);
-    tf64w_store<TA>(Asb, Bsb, tid, ra, rb);
+    tf64w_load<TA, VEC, BVEC>(A, lda, B, ldb, M, N, m0, n0, kb, ke, tid, ra, rb, msk);
+    tf64w_store<TA>(Asb, Bsb, tid, ra, rb, msk);
   }
   __syncthreads();
   for (int k0 = kb; k0 < ke; k0 += wKT) {
     const bool more = k0 + wKT < ke;
-    if (more) tf64w_load<TA, VEC, BVEC>(A, lda, B, ldb, M, N, m0, n0, k0 + wKT, ke, tid, ra, rb);
+    if (more)
+      tf64w_load<TA, VEC, BVEC>(A, lda, B, ldb, M, N, m0, n0, k0 + wKT, ke, tid, ra, rb, msk);
     const float *As = Asb + buf * wAS;
     const double *Bs = Bsb + buf * wBS;
 #pragma unroll
@@ -183,7 +206,7 @@ gemm_tf64w_mfma(const float *__restrict__ A, int64_t lda, const double *__restri
     }
     if (more) {
       // the other buffer was last read before the previous barrier
-      tf64w_store<TA>(Asb + (buf ^ 1) * wAS, Bsb + (buf ^ 1) * wBS, tid, ra, rb);
+      tf64w_store<TA>(Asb + (buf ^ 1) * wAS, Bsb + (buf ^ 1) * wBS, tid, ra, rb, msk);
     }
     __syncthreads();
     buf ^= 1;
