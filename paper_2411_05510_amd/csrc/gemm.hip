@@ -235,7 +235,8 @@ gemm_f64_mfma(const double *__restrict__ A, int64_t lda, const double *__restric
               int N, int K, int k_per_split) {
   __shared__ double As[dBM * dLS];
   __shared__ double Bs[dBN * dLS];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int wr = wave & 1, wc = wave >> 1;
   const int m0 = blockIdx.x * dBM, n0 = blockIdx.y * dBN;
   const int kb = blockIdx.z * k_per_split;
@@ -247,27 +248,51 @@ gemm_f64_mfma(const double *__restrict__ A, int64_t lda, const double *__restric
 #pragma unroll
     for (int ct = 0; ct < 2; ++ct) acc[rt][ct] = f64x4{0.0, 0.0, 0.0, 0.0};
 
-  for (int k0 = kb; k0 < ke; k0 += dKT) {
-    __syncthreads();
+  // The next K tile is loaded into registers (from indices clamped into the
+  // matrices, entries outside the tile flagged in msk) while the MFMAs of the
+  // current one run; it is masked and stored after the next barrier.
+  double ra[4], rb[4];
+  unsigned msk = 0u;
+  auto load = [&](int k0) {
+    unsigned m = 0u;
 #pragma unroll
     for (int h = 0; h < 4; ++h) {
       const int idx = tid + 256 * h;          // 1024 elements per tile
       if (!TA) {
         const int r = idx >> 4, kr = idx & 15;
         const int gi = m0 + r, gk = k0 + kr;
-        As[r * dLS + kr] = (gi < M && gk < ke) ? A[(int64_t)gi * lda + gk] : 0.0;
+        ra[h] = A[(int64_t)min(gi, M - 1) * lda + min(gk, ke - 1)];
+        m |= (gi < M && gk < ke ? 1u : 0u) << h;
       } else {
         const int kr = idx >> 6, c = idx & 63;
         const int gi = m0 + c, gk = k0 + kr;
-        As[c * dLS + kr] = (gi < M && gk < ke) ? A[(int64_t)gk * lda + gi] : 0.0;
+        ra[h] = A[(int64_t)min(gk, ke - 1) * lda + min(gi, M - 1)];
+        m |= (gi < M && gk < ke ? 1u : 0u) << h;
       }
-      {
-        const int kr = idx >> 6, c = idx & 63;
-        const int gj = n0 + c, gk = k0 + kr;
-        Bs[c * dLS + kr] = (gj < N && gk < ke) ? B[(int64_t)gk * ldb + gj] : 0.0;
+      const int kr = idx >> 6, c = idx & 63;
+      const int gj = n0 + c, gk = k0 + kr;
+      rb[h] = B[(int64_t)min(gk, ke - 1) * ldb + min(gj, N - 1)];
+      m |= (gj < N && gk < ke ? 1u : 0u) << (4 + h);
+    }
+    msk = m;
+  };
+  if (kb < ke) load(kb);
+  for (int k0 = kb; k0 < ke; k0 += dKT) {
+    __syncthreads();
+#pragma unroll
+    for (int h = 0; h < 4; ++h) {
+      const int idx = tid + 256 * h;
+      const double a = (msk >> h) & 1u ? ra[h] : 0.0;
+      const double b = (msk >> (4 + h)) & 1u ? rb[h] : 0.0;
+      if (!TA) {
+        As[(idx >> 4) * dLS + (idx & 15)] = a;
+      } else {
+        As[(idx & 63) * dLS + (idx >> 6)] = a;
       }
+      Bs[(idx & 63) * dLS + (idx >> 6)] = b;
     }
     __syncthreads();
+    if (k0 + dKT < ke) load(k0 + dKT);
 #pragma unroll
     for (int s = 0; s < dKT / 4; ++s) {
       const int ko = 4 * s + (lane >> 4);
