@@ -643,7 +643,7 @@ sym_backtransform_kernel(int n, double *__restrict__ evecs, int64_t ldv,
                          const double *__restrict__ ws, double *__restrict__ tile_ws) {
   constexpr int kN = Geo<TP, TQ>::kN;
   constexpr int UP = GM ? 1 : TP, UQ = GM ? 1 : TQ;
-  __shared__ double vbuf[kN];
+  __shared__ double vbufs[2][kN];
   const int t = threadIdx.x, tr = t & 15, tc = t >> 4;
   const double *vref = ws;
   const double *tauv = ws + (size_t)kN * kN;
@@ -657,13 +657,31 @@ sym_backtransform_kernel(int n, double *__restrict__ evecs, int64_t ldv,
       g(p, q) = sel(i < n && j < n, evecs[(int64_t)min(i, n - 1) * ldv + min(j, n - 1)]);
     }
   // Reflector k touches rows > k only: row blocks before k / 16 are skipped.
+  // Reflectors run k = n-3 .. 0; the next one's vector entry (one per thread,
+  // n <= kThreads) and tau are loaded into registers while the current one is
+  // applied, and vectors alternate between two LDS buffers, so each reflector
+  // takes one barrier and no global round trip.
+  static_assert(Geo<TP, TQ>::kN <= kThreads || GM, "one vector entry per thread");
+  double nv = 0.0, ntau = 0.0;
+  if (n >= 3) {
+    nv = vref[(size_t)(n - 3) * kN + min(t, n - 1)];
+    ntau = tauv[n - 3];
+  }
 #pragma unroll UP
   for (int kb = TP - 1; kb >= 0; --kb) {
     const int k0 = 16 * kb, k1 = min(k0 + 16, n - 2);
     for (int k = k1 - 1; k >= k0; --k) {
-      for (int i = t; i < n; i += kThreads) vbuf[i] = (i > k) ? vref[(size_t)k * kN + i] : 0.0;
+      double *vbuf = vbufs[k & 1];
+      for (int i = t; i < n; i += kThreads) {
+        const double v = (i == t) ? nv : vref[(size_t)k * kN + i];
+        vbuf[i] = (i > k) ? v : 0.0;
+      }
+      const double tau = ntau;
       __syncthreads();
-      const double tau = tauv[k];
+      if (k > 0) {
+        nv = vref[(size_t)(k - 1) * kN + min(t, n - 1)];
+        ntau = tauv[k - 1];
+      }
       if (tau != 0.0) {
         double sq[TQ];
 #pragma unroll UQ
@@ -687,7 +705,6 @@ sym_backtransform_kernel(int n, double *__restrict__ evecs, int64_t ldv,
           for (int q = 0; q < TQ; ++q) g(p, q) -= vi * sq[q];
         }
       }
-      __syncthreads();
     }
   }
 #pragma unroll UP

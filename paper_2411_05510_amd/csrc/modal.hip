@@ -794,10 +794,21 @@ SSI_DEV void francis_order(int o, double *A, const double *__restrict__ hbuf, in
   double *sev = shp + 2 * kNB;               // [2][kSM]
   double *sblk = sev + 2 * kSM;              // [kSM][kSM]
   double *refl = sev;                        // during a sweep: [kAdv][kNB][3] reflectors
-  for (int i = 0; i < n; ++i) {
-    const int j0 = i == 0 ? 0 : i - 1;
-    const int rs = ix.row_start(i);
-    for (int j = j0 + t; j < n; j += kFT) A[rs + j - j0] = Hin[(int64_t)i * n + j];
+  // Thread t copies column t (n <= kNR < kFT) of 16 rows per round: the 16
+  // loads are unconditional (clamped) and in flight together; row by row,
+  // each load would wait for the previous row's store.
+  static_assert(kNR <= kFT, "one column per thread");
+  const int tc = min(t, n - 1);
+  for (int i0 = 0; i0 < n; i0 += 16) {
+    double v[16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) v[r] = Hin[(int64_t)min(i0 + r, n - 1) * n + tc];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int i = i0 + r;
+      const int j0 = i == 0 ? 0 : i - 1;
+      if (i < n && t < n && t >= j0) A[ix.row_start(i) + t - j0] = v[r];
+    }
   }
   for (int i = t; i < 2 * kRing; i += kFT) A[psz + i] = 0.0;
   __syncthreads();
