@@ -42,48 +42,54 @@ SSI_DEV uint16_t bf16_rne(double d) {
 
 SSI_DEV uint32_t pack2(uint16_t lo, uint16_t hi) { return (uint32_t)lo | ((uint32_t)hi << 16); }
 
-// Global -> registers for the tile at k0.  A: 64 x KT FP32; rows (or k rows
-// for TA) beyond the matrix or the slice read a clamped in-range address and
-// are zeroed.  B: 224 x KT BF16 per plane, always in range (chunks past the
-// tile, for KT = 32, reload the last one and are not stored).
+// Global -> registers for the tile at k0.  A: 64 x KT FP32; every load is
+// issued from an index clamped into its row and the entries beyond the
+// matrix or the slice are flagged in amsk (bit 4 h + c) and zeroed at store
+// time, so the loads stay in flight across the MFMAs.  B: 224 x KT BF16 per
+// plane, always in range (chunks past the tile, for KT = 32, reload the last
+// one and are not stored).
 template <bool TA, bool VEC, int KT, int NP, int AV, int BC>
 SSI_DEV void bf16_tile_load(const float *__restrict__ A, int64_t lda,
                             const uint16_t *__restrict__ xt, int64_t ldx, int64_t plane, int M,
                             int K, int m0, int n0, int k0, int ke, int tid, float4 (&ra)[AV],
-                            u32x4 (&rb)[NP][BC]) {
+                            u32x4 (&rb)[NP][BC], unsigned &amsk) {
+  unsigned m = 0u;
 #pragma unroll
   for (int h = 0; h < AV; ++h) {
     const int idx = tid + 256 * h;
+    float4 v;
     if (!TA) {
       const int r = idx / (KT / 4), c4 = idx % (KT / 4);
       const int gi = m0 + r, gk = k0 + 4 * c4;
       const float *p = A + (int64_t)min(gi, M - 1) * lda;
-      float4 v;
-      if (VEC && gk + 3 < ke) {
-        v = *reinterpret_cast<const float4 *>(p + gk);
+      if (VEC) {
+        v = *reinterpret_cast<const float4 *>(p + min((int64_t)gk, lda - 4));
       } else {
-        v.x = gk < ke ? p[min(gk, K - 1)] : 0.f;
-        v.y = gk + 1 < ke ? p[min(gk + 1, K - 1)] : 0.f;
-        v.z = gk + 2 < ke ? p[min(gk + 2, K - 1)] : 0.f;
-        v.w = gk + 3 < ke ? p[min(gk + 3, K - 1)] : 0.f;
+        v.x = p[min(gk, K - 1)];
+        v.y = p[min(gk + 1, K - 1)];
+        v.z = p[min(gk + 2, K - 1)];
+        v.w = p[min(gk + 3, K - 1)];
       }
-      ra[h] = gi < M ? v : make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+      for (int c = 0; c < 4; ++c) m |= (gi < M && gk + c < ke ? 1u : 0u) << (4 * h + c);
     } else {
       const int r = idx >> 4, c4 = idx & 15;    // k row, 4-column group of i
       const int gk = k0 + r, gi = m0 + 4 * c4;
       const float *p = A + (int64_t)min(gk, K - 1) * lda;
-      float4 v;
-      if (VEC && gi + 3 < M) {
-        v = *reinterpret_cast<const float4 *>(p + gi);
+      if (VEC) {
+        v = *reinterpret_cast<const float4 *>(p + min((int64_t)gi, lda - 4));
       } else {
-        v.x = gi < M ? p[min(gi, M - 1)] : 0.f;
-        v.y = gi + 1 < M ? p[min(gi + 1, M - 1)] : 0.f;
-        v.z = gi + 2 < M ? p[min(gi + 2, M - 1)] : 0.f;
-        v.w = gi + 3 < M ? p[min(gi + 3, M - 1)] : 0.f;
+        v.x = p[min(gi, M - 1)];
+        v.y = p[min(gi + 1, M - 1)];
+        v.z = p[min(gi + 2, M - 1)];
+        v.w = p[min(gi + 3, M - 1)];
       }
-      ra[h] = gk < ke ? v : make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+      for (int c = 0; c < 4; ++c) m |= (gk < ke && gi + c < M ? 1u : 0u) << (4 * h + c);
     }
+    ra[h] = v;
   }
+  amsk = m;
 #pragma unroll
   for (int q = 0; q < NP; ++q)
 #pragma unroll
@@ -102,7 +108,16 @@ SSI_DEV uint16_t bf16_lo(float v, uint16_t h) {
 // Registers -> LDS (BF16 planes), A as As[i][k], B as Bs[j][k].
 template <bool TA, int KT, int LS, int NP, int AV, int BC, int NT>
 SSI_DEV void bf16_tile_store(uint16_t (&As)[NP][bBM * LS], uint16_t (&Bs)[NP][bBN * LS], int tid,
-                             const float4 (&ra)[AV], const u32x4 (&rb)[NP][BC]) {
+                             const float4 (&ra_in)[AV], const u32x4 (&rb)[NP][BC],
+                             unsigned amsk) {
+  float4 ra[AV];
+#pragma unroll
+  for (int h = 0; h < AV; ++h) {
+    ra[h].x = (amsk >> (4 * h)) & 1u ? ra_in[h].x : 0.f;
+    ra[h].y = (amsk >> (4 * h + 1)) & 1u ? ra_in[h].y : 0.f;
+    ra[h].z = (amsk >> (4 * h + 2)) & 1u ? ra_in[h].z : 0.f;
+    ra[h].w = (amsk >> (4 * h + 3)) & 1u ? ra_in[h].w : 0.f;
+  }
 #pragma unroll
   for (int q = 0; q < NP; ++q)
 #pragma unroll
@@ -163,7 +178,8 @@ gemm_tbf16_mfma(const float *__restrict__ A, int64_t lda, const uint16_t *__rest
   constexpr int BC = (bBN * KT / 8 + 255) / 256; // 16-byte chunks of B per thread and plane
   __shared__ __attribute__((aligned(16))) uint16_t As[NP][bBM * LS];
   __shared__ __attribute__((aligned(16))) uint16_t Bs[NP][bBN * LS];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int wr = wave & 1, wc = wave >> 1;
   const int split = blockIdx.x % splits;
   const int rest = blockIdx.x / splits;
@@ -179,16 +195,17 @@ gemm_tbf16_mfma(const float *__restrict__ A, int64_t lda, const uint16_t *__rest
 
   float4 ra[AV];
   u32x4 rb[NP][BC];
+  unsigned amsk = 0u;
   if (kb < ke)
     bf16_tile_load<TA, VEC, KT, NP, AV, BC>(A, lda, xt, ldx, plane, M, K, m0, n0, kb, ke, tid, ra,
-                                            rb);
+                                            rb, amsk);
   for (int k0 = kb; k0 < ke; k0 += KT) {
     __syncthreads();                       // previous tile's LDS reads are done
-    bf16_tile_store<TA, KT, LS, NP, AV, BC, NT>(As, Bs, tid, ra, rb);
+    bf16_tile_store<TA, KT, LS, NP, AV, BC, NT>(As, Bs, tid, ra, rb, amsk);
     __syncthreads();
     if (k0 + KT < ke)                      // next tile in flight during the MFMAs
       bf16_tile_load<TA, VEC, KT, NP, AV, BC>(A, lda, xt, ldx, plane, M, K, m0, n0, k0 + KT, ke,
-                                              tid, ra, rb);
+                                              tid, ra, rb, amsk);
 #pragma unroll
     for (int kk = 0; kk < KT; kk += 32) {
       const int ko = kk + 8 * (lane >> 4);
