@@ -242,90 +242,6 @@ tri_inv_kernel(int n, const double *__restrict__ Lws, double *__restrict__ Rinv,
     }
 }
 
-// X = L^{-1} for the lower-triangular L in Lws (ld n), by columns: columns
-// are independent forward substitutions, so workgroup b takes columns
-// c0 = 16 b .. c0 + 15 and wave w of it four of them, col = c0 + 4 w + c.
-// Lane (c, p) = (lane / 16, lane % 16) forms x_i[c] = (e_i - sum_{k<i} L_ik
-// x_k[c]) / L_ii from the terms k = c0 + p + 16 q (x_k[c] = 0 below column
-// col) and the 16 lanes of c combine by shuffles.  Rows of L enter LDS in
-// blocks of 16 (columns c0..), the next block loaded into registers while
-// the current one is used; each wave's x rows live in its own slice of LDS,
-// so rows inside a block need no workgroup barrier.  Writes Rinv = X^T
-// (upper, zero below the diagonal).  LDS: 1 / L_ii [n], x [4][n][4], two L
-// blocks [2][16][n], and a tail that the unguarded term loads may reach.
-constexpr int kTiQ = 14;                  // terms per lane: n - c0 <= 16 kTiQ
-constexpr int kTiRB = 16;                 // rows per L block
-__global__ void __launch_bounds__(256)
-tri_inv_cols_kernel(int n, const double *__restrict__ Lws, double *__restrict__ Rinv,
-                    int64_t ldr) {
-  extern __shared__ double tis[];
-  double *rinv = tis;
-  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-  const int c = lane >> 4, p = lane & 15;
-  double *xs = tis + n + (size_t)w * n * 4;            // [rows from c0][4]
-  double *lb = tis + (size_t)17 * n;                   // [2][kTiRB][n]
-  const int c0 = 16 * blockIdx.x;
-  const int col = c0 + 4 * w + c;
-  const int width = n - c0;                            // columns c0..n-1
-  for (int i = t; i < n; i += 256) rinv[i] = 1.0 / Lws[(int64_t)i * n + i];
-  // block m holds rows c0 + 16 m .. + 15, columns c0 .. c0 + width - 1
-  constexpr int kPer = kTiRB * 16 * kTiQ / 256;        // elements per thread and block
-  double pre[kPer];
-  auto load_block = [&](int m) {
-#pragma unroll
-    for (int e = 0; e < kPer; ++e) {
-      const int idx = t + 256 * e;
-      const int rr = idx / (16 * kTiQ), kk = idx - rr * (16 * kTiQ);
-      const int i = c0 + kTiRB * m + rr, k = c0 + kk;
-      pre[e] = (i < n && kk < width && k <= i) ? Lws[(int64_t)i * n + k] : 0.0;
-    }
-  };
-  auto store_block = [&](int buf) {
-#pragma unroll
-    for (int e = 0; e < kPer; ++e) {
-      const int idx = t + 256 * e;
-      const int rr = idx / (16 * kTiQ), kk = idx - rr * (16 * kTiQ);
-      if (kk < width) lb[((size_t)buf * kTiRB + rr) * n + kk] = pre[e];
-    }
-  };
-  const int nblk = ceil_div(width, kTiRB);
-  load_block(0);
-  for (int m = 0; m < nblk; ++m) {
-    __syncthreads();                                   // block m - 2's readers are done
-    store_block(m & 1);
-    __syncthreads();
-    if (m + 1 < nblk) load_block(m + 1);
-    const double *L = lb + (size_t)(m & 1) * kTiRB * n;
-    for (int rr = 0; rr < kTiRB; ++rr) {
-      const int i = c0 + kTiRB * m + rr;
-      if (i >= n) break;
-      const int lim = i - c0;                          // terms k - c0 < lim
-      // every term is loaded (inside this workgroup's LDS) and the ones at
-      // and past the diagonal are dropped by a select, so the loads carry no
-      // branches
-      double s0 = 0.0, s1 = 0.0;
-#pragma unroll
-      for (int q = 0; q < kTiQ; q += 2) {
-        const int k0 = p + 16 * q, k1 = k0 + 16;
-        const double t0 = L[rr * n + k0] * xs[k0 * 4 + c];
-        const double t1 = L[rr * n + k1] * xs[k1 * 4 + c];
-        s0 += (k0 < lim) ? t0 : 0.0;
-        s1 += (k1 < lim) ? t1 : 0.0;
-      }
-      const double s = row16_sum(s0 + s1);
-      const double x = (i < col) ? 0.0 : ((i == col ? 1.0 : 0.0) - s) * rinv[i];
-      if (p == 0) xs[lim * 4 + c] = x;
-      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-      __builtin_amdgcn_wave_barrier();
-    }
-  }
-  // Rinv row col = X column col: zero left of the diagonal
-  for (int cc = 0; cc < 4; ++cc) {
-    const int j = c0 + 4 * w + cc;
-    if (j >= n) break;
-    for (int i = lane; i < n; i += 64)
-      Rinv[(int64_t)j * ldr + i] = (i < j) ? 0.0 : xs[(i - c0) * 4 + cc];
-  }
 }
 
 // ------------------------------------------------------------ sym eigen
@@ -716,11 +632,114 @@ sym_backtransform_kernel(int n, double *__restrict__ evecs, int64_t ldv,
     }
 }
 
+// X = L^{-1} for the lower-triangular L in Lws (ld n), n <= 16 kIbMax, by 16 x
+// 16 blocks: workgroup b takes block column b.  The inverses D_i of the
+// diagonal blocks i >= b come first (one 16-lane group per block, lane c a
+// forward substitution for column c, blocks staged in LDS); then block row by
+// block row, X_bb = D_b and X_ib = -D_i sum_{b <= j < i} L_ij X_jb, the sum on
+// v_mfma_f64_16x16x4f64 with its 16 (i - b) terms split over the four waves
+// and the partial products added through LDS.  The chain is nb - b block
+// steps instead of n - 16 b row steps.  Rows and columns past n are those of
+// the identity.  Writes Rinv = X^T (upper, zero below the diagonal) for rows
+// 16 b .. 16 b + 15.  LDS (dynamic): D [kIbMax][256], X [kIbMax][256] (the
+// diagonal blocks of L before D exists), partials [4][256].
+constexpr int kIbMax = 14;
+__global__ void __launch_bounds__(256)
+tri_inv_blk_kernel(int n, const double *__restrict__ Lws, double *__restrict__ Rinv,
+                   int64_t ldr) {
+  extern __shared__ double tib[];
+  double *dinv = tib;                                  // [kIbMax][16][16]
+  double *xc = tib + kIbMax * 256;                     // [kIbMax][16][16]
+  double *sp = tib + 2 * kIbMax * 256;                 // [4][16][16]
+  const int nb = (n + 15) >> 4, b = blockIdx.x;
+  const int t = threadIdx.x, lane = t & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(t >> 6);
+  // entry (r, j) of L padded with the identity; the load is unconditional
+  auto lg = [&](int r, int j) -> double {
+    const double v = Lws[(int64_t)min(r, n - 1) * n + min(j, n - 1)];
+    return (r < n && j < n) ? v : (r == j ? 1.0 : 0.0);
+  };
+  // stage the diagonal blocks i = b.. of L (entry t of each block)
+  {
+    double v[kIbMax];
+#pragma unroll
+    for (int g = 0; g < kIbMax; ++g) {
+      const int i = b + g;
+      v[g] = lg(16 * i + (t >> 4), 16 * i + (t & 15));
+    }
+#pragma unroll
+    for (int g = 0; g < kIbMax; ++g)
+      if (b + g < nb) xc[g * 256 + t] = v[g];
+  }
+  __syncthreads();
+  {
+    const int g = t >> 4, c = t & 15;                  // block b + g, column c
+    if (b + g < nb) {
+      const double *l = xc + g * 256;
+      double x[16];
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        double s = (r == c) ? 1.0 : 0.0;
+#pragma unroll
+        for (int j = 0; j < r; ++j) s -= l[r * 16 + j] * x[j];
+        x[r] = s / l[r * 16 + r];
+      }
+#pragma unroll
+      for (int r = 0; r < 16; ++r) dinv[g * 256 + r * 16 + c] = x[r];
+    }
+  }
+  __syncthreads();
+  const int r = t >> 4, c = t & 15;
+  const int row = 16 * b + c;                          // row of Rinv written by this thread
+  {
+    const double x = dinv[t];
+    xc[t] = x;
+    if (row < n && 16 * b + r < n) Rinv[(int64_t)row * ldr + 16 * b + r] = x;
+    if (row < n)
+      for (int i = r; i < 16 * b; i += 16) Rinv[(int64_t)row * ldr + i] = 0.0;
+  }
+  __syncthreads();
+  for (int i = b + 1; i < nb; ++i) {
+    const int ks = 4 * (i - b);                        // MFMA steps of 4 terms
+    double av[kIbMax];
+#pragma unroll
+    for (int u = 0; u < kIbMax; ++u) {
+      const int kk = 4 * (wave + 4 * u) + (lane >> 4);
+      av[u] = lg(16 * i + (lane & 15), 16 * b + kk);
+    }
+    f64x4 acc = f64x4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int u = 0; u < kIbMax; ++u) {
+      const int st = wave + 4 * u;
+      if (st < ks) {
+        const int kk = 4 * st + (lane >> 4);
+        const double bv = xc[(kk >> 4) * 256 + (kk & 15) * 16 + (lane & 15)];
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u], bv, acc, 0, 0, 0);
+      }
+    }
+    // D layout: lane holds rows (lane / 16) + 4 q, column lane % 16
+#pragma unroll
+    for (int q = 0; q < 4; ++q) sp[wave * 256 + ((lane >> 4) + 4 * q) * 16 + (lane & 15)] = acc[q];
+    __syncthreads();
+    double x = 0.0;
+    const double *d = dinv + (i - b) * 256;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+      const int e = k * 16 + c;
+      x += d[r * 16 + k] * ((sp[e] + sp[256 + e]) + (sp[512 + e] + sp[768 + e]));
+    }
+    x = -x;
+    xc[(i - b) * 256 + t] = x;
+    if (row < n && 16 * i + r < n) Rinv[(int64_t)row * ldr + 16 * i + r] = x;
+    __syncthreads();
+  }
+}
+
 namespace ssi {
 
 namespace {
 constexpr int kRegP = 14, kRegQ = 7;      // n <= 224
-static_assert(16 * kTiQ >= 16 * kRegP, "column inverse covers the register path");
+static_assert(kIbMax >= kRegP, "block inverse covers the register path");
 constexpr int kGlbP = 64, kGlbQ = 32;     // n <= 1024
 constexpr int kRegN = Geo<kRegP, kRegQ>::kN;
 constexpr int kGlbN = Geo<kGlbP, kGlbQ>::kN;
@@ -743,13 +762,11 @@ hipError_t launch_chol_inv(const double *G, int64_t ldg, int n, double shift_rel
   if (n <= kRegN) {
     hipLaunchKernelGGL((chol_kernel<kRegP, kRegQ, false>), dim3(1), dim3(kThreads), 0, st, G,
                        ldg, n, shift_rel, Lws, ws, status);
-    // the term loads reach up to 16 kTiQ entries past a row or x-slice start
-    // whatever n is; the tail keeps them inside the allocation
-    const size_t lds = sizeof(double) * ((size_t)n * (17 + 2 * kTiRB) + 4 * 16 * kTiQ + 64);
-    hipError_t e = hipFuncSetAttribute((const void *)tri_inv_cols_kernel,
+    const size_t lds = sizeof(double) * (size_t)(2 * kIbMax + 4) * 256;
+    hipError_t e = hipFuncSetAttribute((const void *)tri_inv_blk_kernel,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(tri_inv_cols_kernel, dim3(ceil_div(n, 16)), dim3(256), lds, st, n, Lws,
+    hipLaunchKernelGGL(tri_inv_blk_kernel, dim3(ceil_div(n, 16)), dim3(256), lds, st, n, Lws,
                        Rinv, ldr);
   } else {
     double *tile = glb_tile(ws);
