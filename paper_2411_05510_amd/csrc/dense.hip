@@ -242,8 +242,6 @@ tri_inv_kernel(int n, const double *__restrict__ Lws, double *__restrict__ Rinv,
     }
 }
 
-}
-
 // ------------------------------------------------------------ sym eigen
 // Scratch layout (doubles): vref[kN][kN] | tau[kN] | d[kN] | e[kN]
 template <int TP, int TQ, bool GM>
