@@ -630,6 +630,149 @@ sym_backtransform_kernel(int n, double *__restrict__ evecs, int64_t ldv,
     }
 }
 
+// Lower Cholesky factor L (into Lws, ld n, lower triangle) of G + shift_rel
+// tr(G) I, n <= 16 kCbMax, by 16 x 16 blocks (right-looking).  The blocks
+// (i, j), i >= j, of the lower triangle live in registers as MFMA
+// accumulator tiles (lane l: rows l / 16 + 4 q, column l % 16), block
+// id = i (i + 1) / 2 + j in slot id / 16 of wave id % 16.  For each block column k: its
+// blocks go to an LDS panel; wave 0 factors the diagonal block (lane r holds
+// row r, column steps through lane reads); every thread solves one panel row
+// against it; then each wave subtracts P_i P_j^T from its blocks (i, j), k <
+// j <= i, on v_mfma_f64_16x16x4f64.  Rows and columns past n are those of
+// the identity.  status bit 0 is set on a non-positive pivot.
+constexpr int kCbMax = 14;
+constexpr int kCbWaves = 16;
+constexpr int kCbSlots = (kCbMax * (kCbMax + 1) / 2 + kCbWaves - 1) / kCbWaves;
+__global__ void __launch_bounds__(64 * kCbWaves)
+chol_blk_kernel(const double *__restrict__ G, int64_t ldg, int n, double shift_rel,
+                double *__restrict__ Lws, int *__restrict__ status) {
+  __shared__ double panel[16 * kCbMax][17];           // rows of block column k, from block row k
+  __shared__ double lkk[16][17];
+  __shared__ double rdiag[16];
+  __shared__ double red[kCbWaves];
+  __shared__ int bad;
+  const int nb = (n + 15) >> 4, nblk = nb * (nb + 1) / 2;
+  const int t = threadIdx.x, lane = t & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(t >> 6);
+  int bi[kCbSlots], bj[kCbSlots];
+#pragma unroll
+  for (int s = 0; s < kCbSlots; ++s) {
+    const int id = kCbWaves * s + wave;
+    int i = 0;
+    while ((i + 1) * (i + 2) / 2 <= id) ++i;          // uniform: block row of id
+    bi[s] = id < nblk ? i : -1;
+    bj[s] = id - i * (i + 1) / 2;
+  }
+  // load G (identity past n) and the trace of its leading n x n part
+  f64x4 acc[kCbSlots];
+  double tr_part = 0.0;
+#pragma unroll
+  for (int s = 0; s < kCbSlots; ++s) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int r = 16 * bi[s] + (lane >> 4) + 4 * q, c = 16 * bj[s] + (lane & 15);
+      const double v = G[(int64_t)min(max(r, 0), n - 1) * ldg + min(c, n - 1)];
+      const bool in = bi[s] >= 0 && r < n && c < n;
+      acc[s][q] = in ? v : (bi[s] >= 0 && r == c ? 1.0 : 0.0);
+      tr_part += (in && r == c) ? v : 0.0;
+    }
+  }
+  if (t == 0) bad = 0;
+  {
+    const double w = wave_sum(tr_part);
+    if (lane == 0) red[wave] = w;
+    __syncthreads();
+    double tr = 0.0;
+#pragma unroll
+    for (int w8 = 0; w8 < kCbWaves; ++w8) tr += red[w8];
+    const double shift = shift_rel * tr;
+#pragma unroll
+    for (int s = 0; s < kCbSlots; ++s)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int r = 16 * bi[s] + (lane >> 4) + 4 * q, c = 16 * bj[s] + (lane & 15);
+        if (bi[s] >= 0 && r == c && r < n) acc[s][q] += shift;
+      }
+  }
+  for (int k = 0; k < nb; ++k) {
+    __syncthreads();                                   // the previous panel's readers are done
+#pragma unroll
+    for (int s = 0; s < kCbSlots; ++s)
+      if (bj[s] == k && bi[s] >= k) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+          panel[16 * (bi[s] - k) + (lane >> 4) + 4 * q][lane & 15] = acc[s][q];
+      }
+    __syncthreads();
+    if (wave == 0) {
+      // diagonal block: lane r < 16 holds row r
+      double a[16];
+      const int r = lane & 15;
+#pragma unroll
+      for (int c = 0; c < 16; ++c) a[c] = panel[r][c];
+#pragma unroll
+      for (int c = 0; c < 16; ++c) {
+        double piv = lane_read_d(a[c], c);
+        if (!(piv > 0.0)) {
+          if (lane == 0) bad = 1;
+          piv = 1e-300;
+        }
+        const double d = sqrt(piv), rd = 1.0 / d;
+        a[c] = (r == c) ? d : a[c] * rd;
+        if (lane == 0) rdiag[c] = rd;
+#pragma unroll
+        for (int j = c + 1; j < 16; ++j) {
+          const double xj = lane_read_d(a[c], j);
+          if (r >= j) a[j] -= a[c] * xj;
+        }
+      }
+      if (lane < 16) {
+#pragma unroll
+        for (int c = 0; c < 16; ++c) lkk[r][c] = (c <= r) ? a[c] : 0.0;
+        const int gr = 16 * k + r;
+        if (gr < n)
+#pragma unroll
+          for (int c = 0; c < 16; ++c)
+            if (c <= r && 16 * k + c < n) Lws[(int64_t)gr * n + 16 * k + c] = a[c];
+      }
+    }
+    __syncthreads();
+    // panel rows below the diagonal block: x L_kk^T = a
+    const int pr = 16 + t;
+    if (pr < 16 * (nb - k)) {
+      double x[16];
+#pragma unroll
+      for (int c = 0; c < 16; ++c) {
+        double v = panel[pr][c];
+#pragma unroll
+        for (int m = 0; m < c; ++m) v -= x[m] * lkk[c][m];
+        x[c] = v * rdiag[c];
+      }
+      const int gr = 16 * k + pr;
+#pragma unroll
+      for (int c = 0; c < 16; ++c) panel[pr][c] = x[c];
+      if (gr < n)
+#pragma unroll
+        for (int c = 0; c < 16; ++c)
+          if (16 * k + c < n) Lws[(int64_t)gr * n + 16 * k + c] = x[c];
+    }
+    __syncthreads();
+    // trailing blocks (i, j), k < j <= i: acc -= P_i P_j^T
+#pragma unroll
+    for (int s = 0; s < kCbSlots; ++s)
+      if (bj[s] > k && bi[s] >= bj[s]) {
+        const int ri = 16 * (bi[s] - k) + (lane & 15), rj = 16 * (bj[s] - k) + (lane & 15);
+#pragma unroll
+        for (int st = 0; st < 4; ++st) {
+          const int kk = 4 * st + (lane >> 4);
+          acc[s] = __builtin_amdgcn_mfma_f64_16x16x4f64(-panel[ri][kk], panel[rj][kk], acc[s],
+                                                        0, 0, 0);
+        }
+      }
+  }
+  if (t == 0 && bad) atomicOr(status, 1);
+}
+
 // X = L^{-1} for the lower-triangular L in Lws (ld n), n <= 16 kIbMax, by 16 x
 // 16 blocks: workgroup b takes block column b.  The inverses D_i of the
 // diagonal blocks i >= b come first (one 16-lane group per block, lane c a
@@ -737,7 +880,7 @@ namespace ssi {
 
 namespace {
 constexpr int kRegP = 14, kRegQ = 7;      // n <= 224
-static_assert(kIbMax >= kRegP, "block inverse covers the register path");
+static_assert(kIbMax >= kRegP && kCbMax >= kRegP, "block kernels cover the register path");
 constexpr int kGlbP = 64, kGlbQ = 32;     // n <= 1024
 constexpr int kRegN = Geo<kRegP, kRegQ>::kN;
 constexpr int kGlbN = Geo<kGlbP, kGlbQ>::kN;
@@ -758,8 +901,8 @@ size_t dense_ws_doubles(int n) {
 hipError_t launch_chol_inv(const double *G, int64_t ldg, int n, double shift_rel, double *Rinv,
                            int64_t ldr, double *Lws, double *ws, int *status, hipStream_t st) {
   if (n <= kRegN) {
-    hipLaunchKernelGGL((chol_kernel<kRegP, kRegQ, false>), dim3(1), dim3(kThreads), 0, st, G,
-                       ldg, n, shift_rel, Lws, ws, status);
+    hipLaunchKernelGGL(chol_blk_kernel, dim3(1), dim3(64 * kCbWaves), 0, st, G, ldg, n,
+                       shift_rel, Lws, status);
     const size_t lds = sizeof(double) * (size_t)(2 * kIbMax + 4) * 256;
     hipError_t e = hipFuncSetAttribute((const void *)tri_inv_blk_kernel,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
