@@ -57,19 +57,30 @@ SSI_DEV OrderGeo order_geo(int o, int nmin, int step) {
 }  // namespace
 
 // ------------------------------------------------------------------ form_x
-// X_n[i][j] = sum_{r=i}^{n-1} Rinv[i][r] W[r][j]
+// X_n[i][j] = sum_{r=i}^{n-1} Rinv[i][r] W[r][j] for every order n at once:
+// the sums of the orders are prefixes of one running sum per (i, j) over r,
+// written out at each order boundary n = r + 1 with n > j (n > i holds from
+// r >= i).  One thread per (i, j) of the largest order; the running offset
+// of the next order's matrix in xbuf advances with r.
 __global__ void __launch_bounds__(256)
 form_x_kernel(const double *__restrict__ rinv, const double *__restrict__ w, int k, int nmin,
-              int step, double *__restrict__ xbuf) {
-  const OrderGeo g = order_geo(blockIdx.y, nmin, step);
-  const int n = g.n;
-  double *x = xbuf + g.sq;
-  const int total = n * n;
-  for (int idx = blockIdx.x * 256 + threadIdx.x; idx < total; idx += gridDim.x * 256) {
-    const int i = idx / n, j = idx - i * n;
-    double s = 0.0;
-    for (int r = i; r < n; ++r) s += rinv[(int64_t)i * k + r] * w[(int64_t)r * k + j];
-    x[idx] = s;
+              int step, int no, double *__restrict__ xbuf) {
+  const int nmax = nmin + (no - 1) * step;
+  const int idx = blockIdx.x * 256 + threadIdx.x;
+  if (idx >= nmax * nmax) return;
+  const int i = idx / nmax, j = idx - i * nmax;
+  int nn = nmin, o = 0;          // next order boundary, its index
+  int64_t sq = 0;                // offset of order o's matrix
+  double s = 0.0;
+  for (int r = i; r < nmax; ++r) {
+    s += rinv[(int64_t)i * k + r] * w[(int64_t)r * k + j];
+    const int n = r + 1;
+    while (nn < n) {
+      sq += (int64_t)nn * nn;
+      nn += step;
+      ++o;
+    }
+    if (nn == n && n > j && o < no) xbuf[sq + (int64_t)i * n + j] = s;
   }
 }
 
@@ -1462,8 +1473,11 @@ ModalSizes modal_sizes(int nmin, int nmax, int step, int l) {
 hipError_t launch_modal(const ModalArgs &a, hipStream_t st) {
   const ModalSizes &s = a.sizes;
   const int no = s.n_orders;
-  hipLaunchKernelGGL(form_x_kernel, dim3(64, no), dim3(256), 0, st, a.rinv, a.w, a.ldw, a.nmin,
-                     a.step, a.xbuf);
+  {
+    const int nmax = a.nmin + (no - 1) * a.step;
+    hipLaunchKernelGGL(form_x_kernel, dim3(ceil_div(nmax * nmax, 256)), dim3(256), 0, st, a.rinv,
+                       a.w, a.ldw, a.nmin, a.step, no, a.xbuf);
+  }
   if (a.nmin + (no - 1) * a.step <= 16 * 13)
     hipLaunchKernelGGL(hess_kernel<13>, dim3(no), dim3(kT), 0, st, a.xbuf, a.nmin, a.step,
                        a.hbuf, a.vref, a.taus);
