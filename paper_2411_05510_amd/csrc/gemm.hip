@@ -324,20 +324,22 @@ gemm_f64_mfma(const double *__restrict__ A, int64_t lda, const double *__restric
     }
 }
 
-// out[i][j] = scale * sum_s part[s][i][j]; optional FP32 copy.
+// out[i][j] = scale * sum_s part[s][i][j]; optional FP32 copy.  Block
+// (x, y) takes row y (and the rows gridDim.y apart) and 256 columns from
+// 256 x: no index division, coalesced rows; splits summed in order.
 __global__ void __launch_bounds__(256)
 reduce_splits(const double *__restrict__ part, int splits, int64_t split_stride, int64_t ldp,
               int M, int N, double scale, double *__restrict__ out, int64_t ldo,
               float *__restrict__ out32, int64_t ld32) {
-  const int64_t total = (int64_t)M * N;
-  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
-       idx += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t i = idx / N, j = idx - i * N;
+  const int j = blockIdx.x * 256 + threadIdx.x;
+  if (j >= N) return;
+  for (int i = blockIdx.y; i < M; i += gridDim.y) {
+    const double *pp = part + (int64_t)i * ldp + j;
     double s = 0.0;
-    for (int sp = 0; sp < splits; ++sp) s += part[sp * split_stride + i * ldp + j];
+    for (int sp = 0; sp < splits; ++sp) s += pp[sp * split_stride];
     s *= scale;
-    if (out) out[i * ldo + j] = s;
-    if (out32) out32[i * ld32 + j] = (float)s;
+    if (out) out[(int64_t)i * ldo + j] = s;
+    if (out32) out32[(int64_t)i * ld32 + j] = (float)s;
   }
 }
 
@@ -492,8 +494,10 @@ hipError_t launch_gemm_f64(const GemmPlan &p, bool trans_a, const double *A, int
 
 hipError_t launch_reduce(const GemmPlan &p, const double *part, int M, int N, double scale,
                          double *out, int64_t ldo, float *out32, int64_t ld32, hipStream_t st) {
-  hipLaunchKernelGGL(reduce_splits, dim3(grid_cap((int64_t)M * N)), dim3(256), 0, st, part,
-                     p.splits, p.split_stride, p.ldc, M, N, scale, out, ldo, out32, ld32);
+  if (M <= 0 || N <= 0) return hipSuccess;
+  const dim3 grid(ceil_div(N, 256), std::min(M, 65535));
+  hipLaunchKernelGGL(reduce_splits, grid, dim3(256), 0, st, part, p.splits, p.split_stride,
+                     p.ldc, M, N, scale, out, ldo, out32, ld32);
   return hipGetLastError();
 }
 
