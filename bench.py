@@ -393,8 +393,8 @@ def main() -> int:
                     help="run one plain device copy of 256 MiB first (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
-              "(the identification path is single-GPU)", file=sys.stderr)
+        print(f"bench.py: the identification runs on one GPU; --gpus {args.gpus} is not supported "
+              "(one process, one device)", file=sys.stderr)
         return 2
     fn = {"bridge-180ch": bench_identify, "bridge-180ch-3d": bench_3d,
           "serving": bench_serving}[args.workload]
