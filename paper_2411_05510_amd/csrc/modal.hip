@@ -297,6 +297,29 @@ SSI_DEV void wave_sync() {
   __builtin_amdgcn_wave_barrier();
 }
 
+// 3-element Householder reflector (1, v1, v2) with scalar beta that maps
+// (x, y, z) to (alpha, 0, 0); beta = 0 when there is nothing to annihilate.
+// 1/||.|| and 1/u0 come from the hardware estimates refined by two Newton
+// steps each (r <- r (3 - s r^2) / 2 and q <- q (2 - u q)).
+SSI_DEV void householder3(double x, double y, double z, double &v1, double &v2, double &beta,
+                          double &alpha) {
+  const double s = x * x + y * y + z * z;
+  v1 = v2 = beta = alpha = 0.0;
+  if (!(s > 0.0) || (y == 0.0 && z == 0.0)) return;
+  double r = __builtin_amdgcn_rsq(s);
+  r = r * (1.5 - 0.5 * s * r * r);
+  r = r * (1.5 - 0.5 * s * r * r);
+  const double nrm = s * r;
+  alpha = -copysign(nrm, x);
+  const double u0 = x - alpha;                 // |u0| = |x| + ||.||
+  double q = __builtin_amdgcn_rcp(u0);
+  q = q * (2.0 - u0 * q);
+  q = q * (2.0 - u0 * q);
+  v1 = y * q;
+  v2 = z * q;
+  beta = 1.0 + fabs(x) * r;                    // -u0 / alpha
+}
+
 // Eigenvalues of the m x m upper Hessenberg matrix a (row-major, ld kSM, m <=
 // kSM; entries below the subdiagonal are zero and stay in place) by the
 // double-shift QR iteration, run by one wave.  Returns false if the
@@ -363,12 +386,9 @@ SSI_DEV bool small_eig(double *a, int m, double *er, double *ei, int lane) {
     for (int k = l; k <= hi - 1; ++k) {
       const bool three = k < hi - 1;
       const double zz = three ? z : 0.0;
-      const double nrm = sqrt(x * x + y * y + zz * zz);
-      if (nrm > 0.0 && (y != 0.0 || zz != 0.0)) {
-        const double alpha = -copysign(nrm, x);
-        const double u0 = x - alpha;
-        const double v1 = y / u0, v2 = zz / u0;
-        const double beta = -u0 / alpha;
+      double v1, v2, beta, alpha;
+      householder3(x, y, zz, v1, v2, beta, alpha);
+      if (beta != 0.0) {
         const int q0 = max(l, k - 1);
         for (int j = q0 + lane; j <= hi; j += 64) {
           const double a0 = a[k * kSM + j], a1 = a[(k + 1) * kSM + j];
@@ -407,28 +427,6 @@ SSI_DEV bool small_eig(double *a, int m, double *er, double *ei, int lane) {
 
 }  // namespace
 
-// 3-element Householder reflector (1, v1, v2) with scalar beta that maps
-// (x, y, z) to (alpha, 0, 0); beta = 0 when there is nothing to annihilate.
-// 1/||.|| and 1/u0 come from the hardware estimates refined by two Newton
-// steps each (r <- r (3 - s r^2) / 2 and q <- q (2 - u q)).
-SSI_DEV void householder3(double x, double y, double z, double &v1, double &v2, double &beta,
-                          double &alpha) {
-  const double s = x * x + y * y + z * z;
-  v1 = v2 = beta = alpha = 0.0;
-  if (!(s > 0.0) || (y == 0.0 && z == 0.0)) return;
-  double r = __builtin_amdgcn_rsq(s);
-  r = r * (1.5 - 0.5 * s * r * r);
-  r = r * (1.5 - 0.5 * s * r * r);
-  const double nrm = s * r;
-  alpha = -copysign(nrm, x);
-  const double u0 = x - alpha;                 // |u0| = |x| + ||.||
-  double q = __builtin_amdgcn_rcp(u0);
-  q = q * (2.0 - u0 * q);
-  q = q * (2.0 - u0 * q);
-  v1 = y * q;
-  v2 = z * q;
-  beta = 1.0 + fabs(x) * r;                    // -u0 / alpha
-}
 
 SSI_DEV double readlane_d(double v, int src) {
   const int lo = __builtin_amdgcn_readlane(__double2loint(v), src);
