@@ -95,6 +95,7 @@ hess_kernel(const double *__restrict__ xbuf, int nmin, int step, double *__restr
             double *__restrict__ vref, double *__restrict__ taus) {
   __shared__ double vbuf[kNR];
   __shared__ double ypart[8][kNR];
+  __shared__ double ybuf[kNR];
   __shared__ double stau[2];
   const OrderGeo geo = order_geo(blockIdx.x, nmin, step);
   const int n = geo.n;
@@ -192,13 +193,18 @@ hess_kernel(const double *__restrict__ xbuf, int nmin, int step, double *__restr
           if ((lane >> 4) == 0) ypart[wave][i] = acc;
         }
         __syncthreads();
+        // y_i = tau sum_w ypart[w][i], reduced once per row
+        if (t < n) {
+          double y = 0.0;
+#pragma unroll
+          for (int w = 0; w < 8; ++w) y += ypart[w][t];
+          ybuf[t] = y * tau;
+        }
+        __syncthreads();
 #pragma unroll
         for (int p = 0; p < TP; ++p) {
           const int i = row_of(tr, p);
-          double y = 0.0;
-#pragma unroll
-          for (int w = 0; w < 8; ++w) y += ypart[w][i];
-          y *= tau;
+          const double y = sel(i < n, ybuf[min(i, kNR - 1)]);
 #pragma unroll
           for (int q = 0; q < kTQ; ++q) {
             if (q < kq) continue;
@@ -207,8 +213,8 @@ hess_kernel(const double *__restrict__ xbuf, int nmin, int step, double *__restr
         }
       }
       // No closing barrier: every read of vbuf for column k precedes the
-      // barrier above, ypart is rewritten only after the next column's first
-      // barrier, and tau alternates between two slots.
+      // barriers above, ypart and ybuf are rewritten only after the next
+      // column's first barrier, and tau alternates between two slots.
     }
   }
 #pragma unroll
