@@ -234,6 +234,10 @@ constexpr int kFT = 64 * kNB;            // one wave per bulge
 constexpr int kSM = 2 * kNB;             // order of the trailing block that supplies shifts
 constexpr int kRing = 16;                // bulge-slot ring rows, >= 3 kNB + 1, power of two
 constexpr int kMsMin = 24;               // active windows from this size use multishift sweeps
+// Deflation tolerance of the trailing block's QR when it only supplies
+// shifts: shifts accurate to about 1e-10 keep the convergence of the sweeps,
+// and the block's last iterations toward machine precision are saved.
+constexpr double kShiftTol = 1e-10;
 // LDS after the packed H: bulge slots (2 kRing), shift pairs (2 kNB), the
 // shift block's eigenvalues (2 kSM) and the shift block (kSM^2); the last two
 // hold a window's reflectors during a multishift sweep.
@@ -330,8 +334,7 @@ SSI_DEV void householder3(double x, double y, double z, double &v1, double &v2, 
 // kSM; entries below the subdiagonal are zero and stay in place) by the
 // double-shift QR iteration, run by one wave.  Returns false if the
 // iteration limit is hit.
-SSI_DEV bool small_eig(double *a, int m, double *er, double *ei, int lane) {
-  const double eps = 2.220446049250313e-16;
+SSI_DEV bool small_eig(double *a, int m, double *er, double *ei, int lane, double tol) {
   int hi = m - 1, iter = 0, total = 0;
   while (hi >= 0) {
     int cand = 0;
@@ -342,7 +345,7 @@ SSI_DEV bool small_eig(double *a, int m, double *er, double *ei, int lane) {
         if (i >= 2) ref += fabs(a[(i - 1) * kSM + i - 2]);
         if (i + 1 <= hi) ref += fabs(a[(i + 1) * kSM + i]);
       }
-      if (sub <= eps * ref) {
+      if (sub <= tol * ref) {
         cand = i;
         break;
       }
@@ -884,7 +887,7 @@ SSI_DEV void francis_order(int o, double *A, const double *__restrict__ hbuf, in
       }
       __syncthreads();
       if (wave == 0) {
-        const bool ok = small_eig(sblk, mb, sev, sev + kSM, lane);
+        const bool ok = small_eig(sblk, mb, sev, sev + kSM, lane, eps);
         if (lane == 0) {
           small_ok = ok ? 1 : 0;
           if (ok)
@@ -912,7 +915,7 @@ SSI_DEV void francis_order(int o, double *A, const double *__restrict__ hbuf, in
       }
       __syncthreads();
       if (wave == 0) {
-        const bool ok = small_eig(sblk, kSM, sev, sev + kSM, lane);
+        const bool ok = small_eig(sblk, kSM, sev, sev + kSM, lane, kShiftTol);
         if (lane == 0) {
           small_ok = ok ? 1 : 0;
           if (ok) {
