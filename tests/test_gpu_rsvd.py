@@ -58,10 +58,14 @@ def _run_rsvd(ctx, t32, k, p, q, seed=7, stream=0, pad=0):
 
 @pytest.mark.parametrize("m,k,p,q,pad,decay", [(300, 10, 4, 1, 0, 0.8), (701, 30, 7, 2, 3, 0.8),
                                                (256, 12, 0, 0, 0, 0.8), (130, 40, 9, 3, 1, 0.8),
+                                               (300, 20, 13, 1, 2, 0.8), (420, 190, 19, 1, 0, 0.98),
+                                               (420, 200, 24, 1, 0, 0.98),
                                                (600, 230, 10, 1, 0, 0.99)])
 def test_rsvd_low_rank_plus_noise(ctx, m, k, p, q, pad, decay):
-    """ell = k + p = 240 takes the global-memory Cholesky, triangular inverse
-    and symmetric eigensolver (ell > 224)."""
+    """ell = k + p of 33 and 209 end in a partial 16 x 16 block of the blocked
+    Cholesky and triangular inverse, 224 fills the largest register-path block
+    count, and 240 takes the global-memory Cholesky, triangular inverse and
+    symmetric eigensolver (ell > 224)."""
     t32 = synth.random_lowrank(m, m, k, seed=m + k, decay=decay, noise=1e-5)
     u, s = _run_rsvd(ctx, t32, k, p, q, seed=11, pad=pad)
     om = oracle.sketch(11, m, k + p, 0)
