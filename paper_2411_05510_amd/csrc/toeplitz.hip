@@ -6,7 +6,10 @@
 // stays in L2 / Infinity Cache.  A workgroup covers 4096 floats of one row;
 // in each of its four 16-byte store instructions the lanes of a wave write
 // consecutive float4s, so every store instruction of a wave is one contiguous
-// 1 KiB run of full cache lines.  The vector path needs l, ldt and both
+// 1 KiB run of full cache lines.  The stores carry the nontemporal hint: T is
+// written once and read back only by the next kernel, after far more data than
+// the caches hold has passed, and with the hint the store stream runs at the
+// rate of a plain fill kernel (4.1 -> 5.6 TB/s at m = 10800).  The vector path needs l, ldt and both
 // pointers 16-byte aligned (a float4 then never straddles two blocks);
 // otherwise a scalar path is used.
 #include "common.h"
@@ -35,8 +38,8 @@ toeplitz_vec4(const float *__restrict__ r, int l, int jb, float *__restrict__ t,
     if (x < m) {
       const int cb = x / l, b = x - cb * l;
       const int blk = jb + rb - cb - 1;          // R_{jb + r - c} -> index j - 1
-      const float4 val = *reinterpret_cast<const float4 *>(rrow + (int64_t)blk * l * l + b);
-      *reinterpret_cast<float4 *>(dst + x) = val;
+      const f32x4 val = *reinterpret_cast<const f32x4 *>(rrow + (int64_t)blk * l * l + b);
+      __builtin_nontemporal_store(val, reinterpret_cast<f32x4 *>(dst + x));
     }
   }
 }
