@@ -326,7 +326,10 @@ gemm_f64_mfma(const double *__restrict__ A, int64_t lda, const double *__restric
 
 // out[i][j] = scale * sum_s part[s][i][j]; optional FP32 copy.  Block
 // (x, y) takes row y (and the rows gridDim.y apart) and 256 columns from
-// 256 x: no index division, coalesced rows; splits summed in order.
+// 256 x: no index division, coalesced rows; splits summed in order.  The
+// partials are loaded eight at a time, unconditionally (split index clamped to
+// the last one, whose repeats are not added), so the eight loads are in flight
+// together; a load per split inside the summing loop waited for the previous.
 __global__ void __launch_bounds__(256)
 reduce_splits(const double *__restrict__ part, int splits, int64_t split_stride, int64_t ldp,
               int M, int N, double scale, double *__restrict__ out, int64_t ldo,
@@ -336,7 +339,14 @@ reduce_splits(const double *__restrict__ part, int splits, int64_t split_stride,
   for (int i = blockIdx.y; i < M; i += gridDim.y) {
     const double *pp = part + (int64_t)i * ldp + j;
     double s = 0.0;
-    for (int sp = 0; sp < splits; ++sp) s += pp[sp * split_stride];
+    for (int sp0 = 0; sp0 < splits; sp0 += 8) {
+      double v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = pp[(int64_t)min(sp0 + u, splits - 1) * split_stride];
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        if (sp0 + u < splits) s += v[u];
+    }
     s *= scale;
     if (out) out[(int64_t)i * ldo + j] = s;
     if (out32) out32[(int64_t)i * ld32 + j] = (float)s;

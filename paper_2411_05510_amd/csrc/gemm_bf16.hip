@@ -250,7 +250,9 @@ gemm_tbf16_mfma(const float *__restrict__ A, int64_t lda, const uint16_t *__rest
     }
 }
 
-// out[i][j] = sum_s part[s][i][j] (FP32 partials summed in FP64, fixed order)
+// out[i][j] = sum_s part[s][i][j] (FP32 partials summed in FP64, fixed order;
+// loaded eight splits at a time with the split index clamped, so that the loads
+// are in flight together)
 __global__ void __launch_bounds__(256)
 reduce_splits_f32(const float *__restrict__ part, int splits, int64_t split_stride, int64_t ldp,
                   int M, int N, double *__restrict__ out, int64_t ldo) {
@@ -258,8 +260,16 @@ reduce_splits_f32(const float *__restrict__ part, int splits, int64_t split_stri
   for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
        idx += (int64_t)gridDim.x * blockDim.x) {
     const int64_t i = idx / N, j = idx - i * N;
+    const float *pp = part + i * ldp + j;
     double s = 0.0;
-    for (int sp = 0; sp < splits; ++sp) s += (double)part[sp * split_stride + i * ldp + j];
+    for (int sp0 = 0; sp0 < splits; sp0 += 8) {
+      float v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = pp[(int64_t)min(sp0 + u, splits - 1) * split_stride];
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        if (sp0 + u < splits) s += (double)v[u];
+    }
     out[i * ldo + j] = s;
   }
 }
