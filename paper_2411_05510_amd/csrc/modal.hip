@@ -1409,7 +1409,10 @@ eig_persistent_kernel(const double *__restrict__ hbuf, const double *__restrict_
 }
 
 // ------------------------------------------------------------------ sort
-// Poles of order o sorted by (f, xi), index as the final tie-break.
+// Poles of order o sorted by (f, xi), index as the final tie-break.  The keys
+// pass through LDS 256 at a time, and every thread counts the keys below its
+// own (its rank); the mode shapes of 256 poles are then moved by the whole
+// block, consecutive threads on consecutive floats of a row.
 __global__ void __launch_bounds__(256)
 sort_kernel(int nmin, int step, int l, const int *__restrict__ npole,
             const int *__restrict__ flags_in, const double *__restrict__ tf,
@@ -1417,41 +1420,63 @@ sort_kernel(int nmin, int step, int l, const int *__restrict__ npole,
             const double *__restrict__ tphi, int32_t *__restrict__ count,
             int32_t *__restrict__ flags_out, double *__restrict__ f, double *__restrict__ xi,
             double *__restrict__ mu, float *__restrict__ phi) {
-  const int o = blockIdx.x;
+  __shared__ double sf[256], sx[256];
+  __shared__ int srank[256];
+  const int o = blockIdx.x, t = threadIdx.x;
   const OrderGeo geo = order_geo(o, nmin, step);
   const int cnt = npole[o];
   const int base = geo.pole;
-  if (threadIdx.x == 0) {
+  const int row = 2 * l;                     // floats of one mode shape
+  if (t == 0) {
     count[o] = cnt;
     flags_out[o] = flags_in[o];
   }
-  for (int i = threadIdx.x; i < cnt; i += blockDim.x) {
-    const double fi = tf[base + i], xi_i = txi[base + i];
+  for (int i0 = 0; i0 < cnt; i0 += 256) {
+    const int i = i0 + t;
+    const bool own = i < cnt;
+    const double fi = own ? tf[base + i] : 0.0, xi_i = own ? txi[base + i] : 0.0;
     int rank = 0;
-    for (int j = 0; j < cnt; ++j) {
-      const double fj = tf[base + j], xj = txi[base + j];
-      rank += (fj < fi) || (fj == fi && (xj < xi_i || (xj == xi_i && j < i)));
+    for (int j0 = 0; j0 < cnt; j0 += 256) {
+      __syncthreads();                       // the previous keys and ranks are read
+      if (j0 + t < cnt) {
+        sf[t] = tf[base + j0 + t];
+        sx[t] = txi[base + j0 + t];
+      }
+      __syncthreads();
+      const int jn = min(256, cnt - j0);
+      for (int jj = 0; jj < jn; ++jj) {
+        const int j = j0 + jj;
+        const double fj = sf[jj], xj = sx[jj];
+        rank += (fj < fi) || (fj == fi && (xj < xi_i || (xj == xi_i && j < i)));
+      }
     }
-    const int dst = base + rank;
-    f[dst] = fi;
-    xi[dst] = xi_i;
-    mu[2 * dst] = tmu[2 * (base + i)];
-    mu[2 * dst + 1] = tmu[2 * (base + i) + 1];
-    for (int a = 0; a < l; ++a) {
-      phi[((size_t)dst * l + a) * 2] = (float)tphi[((size_t)(base + i) * l + a) * 2];
-      phi[((size_t)dst * l + a) * 2 + 1] = (float)tphi[((size_t)(base + i) * l + a) * 2 + 1];
+    if (own) {
+      const int dst = base + rank;
+      srank[t] = rank;
+      f[dst] = fi;
+      xi[dst] = xi_i;
+      mu[2 * dst] = tmu[2 * (base + i)];
+      mu[2 * dst + 1] = tmu[2 * (base + i) + 1];
+    }
+    __syncthreads();
+    const int np = min(256, cnt - i0);
+    for (int idx = t; idx < np * row; idx += 256) {
+      const int q = idx / row, a = idx - q * row;
+      phi[(size_t)(base + srank[q]) * row + a] = (float)tphi[(size_t)(base + i0 + q) * row + a];
     }
   }
   // slots past the count are zero, so the outputs never depend on what the
-  // buffers held before
-  for (int i = cnt + threadIdx.x; i < geo.n / 2; i += blockDim.x) {
-    const int dst = base + i;
+  // buffers held before; they are one contiguous run of rows
+  const int nz = geo.n / 2 - cnt;
+  for (int q = t; q < nz; q += 256) {
+    const int dst = base + cnt + q;
     f[dst] = 0.0;
     xi[dst] = 0.0;
     mu[2 * dst] = 0.0;
     mu[2 * dst + 1] = 0.0;
-    for (int a = 0; a < 2 * l; ++a) phi[(size_t)dst * l * 2 + a] = 0.f;
   }
+  float *pz = phi + (size_t)(base + cnt) * row;
+  for (int idx = t; idx < nz * row; idx += 256) pz[idx] = 0.f;
 }
 
 // ------------------------------------------------------------------ launch
