@@ -1412,7 +1412,8 @@ eig_persistent_kernel(const double *__restrict__ hbuf, const double *__restrict_
 // Poles of order o sorted by (f, xi), index as the final tie-break.  The keys
 // pass through LDS 256 at a time, and every thread counts the keys below its
 // own (its rank); the mode shapes of 256 poles are then moved by the whole
-// block, consecutive threads on consecutive floats of a row.
+// block, consecutive threads on consecutive floats of a row.  With one
+// workgroup per order the copy is bound by load latency, not bandwidth.
 __global__ void __launch_bounds__(256)
 sort_kernel(int nmin, int step, int l, const int *__restrict__ npole,
             const int *__restrict__ flags_in, const double *__restrict__ tf,
@@ -1459,10 +1460,22 @@ sort_kernel(int nmin, int step, int l, const int *__restrict__ npole,
       mu[2 * dst + 1] = tmu[2 * (base + i) + 1];
     }
     __syncthreads();
-    const int np = min(256, cnt - i0);
-    for (int idx = t; idx < np * row; idx += 256) {
-      const int q = idx / row, a = idx - q * row;
-      phi[(size_t)(base + srank[q]) * row + a] = (float)tphi[(size_t)(base + i0 + q) * row + a];
+    // eight loads in flight per thread: indices clamped to the last entry,
+    // whose repeats are not stored
+    const int tot = min(256, cnt - i0) * row;
+    const double *src = tphi + (size_t)(base + i0) * row;
+    for (int idx0 = t; idx0 < tot; idx0 += 8 * 256) {
+      double v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = src[min(idx0 + u * 256, tot - 1)];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int idx = idx0 + u * 256;
+        if (idx < tot) {
+          const int q = idx / row, a = idx - q * row;
+          phi[(size_t)(base + srank[q]) * row + a] = (float)v[u];
+        }
+      }
     }
   }
   // slots past the count are zero, so the outputs never depend on what the
