@@ -336,6 +336,24 @@ ssi_status ssi_stability(ssi_ctx *ctx, const ssi_params *p, int32_t l,
                          const ssi_output *out, const ssi_stability_params *sp,
                          double *mpc, double *mpd, uint8_t *flags);
 
+/* For callers that cannot allocate device memory (work under HIP graph
+ * capture, serving loops or harnesses that forbid hipMalloc): ssi_stability
+ * with the same arguments and results, but its per-slot scratch (the
+ * hard-criteria verdict, one byte per pole slot) lives in a fixed static
+ * device array of ssi_stability_noalloc_max_slots() bytes (4 MiB) instead of
+ * the context workspace.  Calls no hipMalloc, hipFree or other allocating
+ * routine.  SSI_EINVAL, before any launch, when n_lags * pole_cap exceeds the
+ * array.  The array is one per GPU and shared by every call on that GPU from
+ * any context: calls that overlap on one GPU race (order them on one stream
+ * or synchronize between them).  The array keeps the last call's contents;
+ * every slot a call reads is written by that call first, so nothing needs
+ * clearing.  Its device address is looked up at ssi_create, once per device. */
+ssi_status ssi_stability_noalloc(ssi_ctx *ctx, const ssi_params *p, int32_t l,
+                                 const ssi_output *out, const ssi_stability_params *sp,
+                                 double *mpc, double *mpd, uint8_t *flags);
+/* Pole slots the static scratch of ssi_stability_noalloc holds.  Host-only. */
+int64_t ssi_stability_noalloc_max_slots(void);
+
 /* ------------------------------------------------------------- serving */
 
 /* Continuous batching of identifications on one GPU, for monitoring many

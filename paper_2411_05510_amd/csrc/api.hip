@@ -228,6 +228,15 @@ ssi_status ssi_create(int device, void *hip_stream, ssi_ctx **out) {
     delete c;
     return hip_fail(e, "status word");
   }
+  // device address of the static scratch of ssi_stability_noalloc (once per
+  // device, while the device is current)
+  uint8_t *scr = nullptr;
+  e = ssi::noalloc_scratch(device, &scr);
+  if (e != hipSuccess) {
+    (void)hipFree(c->status);
+    delete c;
+    return hip_fail(e, "hipGetSymbolAddress");
+  }
   *out = c;
   return SSI_OK;
 }
@@ -1094,24 +1103,33 @@ ssi_status ssi_modal(ssi_ctx *c, const double *u, const double *sigma, int64_t m
   return run_modal(c, b, u, m, k, l, p, lag_index, out);
 }
 
-ssi_status ssi_stability(ssi_ctx *c, const ssi_params *p, int32_t l, const ssi_output *out,
-                         const ssi_stability_params *sp, double *mpc, double *mpd,
-                         uint8_t *flags) {
+}  // extern "C"
+
+namespace {
+
+// Shared checks and launch of ssi_stability and ssi_stability_noalloc; `hc`
+// is the per-slot scratch (slots bytes), from the workspace or the static
+// array.  get_hc is called after validation with the slot count.
+template <typename GetHc>
+ssi_status stability_impl(ssi_ctx *c, const char *name, const ssi_params *p, int32_t l,
+                          const ssi_output *out, const ssi_stability_params *sp, double *mpc,
+                          double *mpd, uint8_t *flags, GetHc &&get_hc) {
   if (!c || !p || !out || !sp || !mpc || !mpd || !flags)
-    return fail(SSI_EINVAL, "ssi_stability: NULL argument");
+    return fail(SSI_EINVAL, "%s: NULL argument", name);
   if (!out->count || !out->f || !out->xi || !out->phi)
-    return fail(SSI_EINVAL, "ssi_stability: NULL output buffer");
+    return fail(SSI_EINVAL, "%s: NULL output buffer", name);
   if (l < 1 || p->n_lags < 1 || p->order_step < 1 || p->order_min < 1 ||
       p->order_max < p->order_min)
-    return fail(SSI_EINVAL, "ssi_stability: bad sizes");
+    return fail(SSI_EINVAL, "%s: bad sizes", name);
   if (!(sp->xi_max > 0.0) || !(sp->alpha_f >= 0.0) || !(sp->alpha_xi >= 0.0) ||
       !(sp->alpha_mac >= 0.0))
-    return fail(SSI_EINVAL, "ssi_stability: thresholds must be non-negative (xi_max > 0)");
+    return fail(SSI_EINVAL, "%s: thresholds must be non-negative (xi_max > 0)", name);
   DeviceGuard g(c->device);
   const int n_orders = n_orders_of(p);
   const int pole_cap = ssi_pole_offset(p, n_orders);
   const size_t slots = (size_t)p->n_lags * pole_cap;
-  ssi_status s = ws_reserve(c, aligned_bytes(slots, 1));
+  uint8_t *hc = nullptr;
+  ssi_status s = get_hc(slots, &hc);
   if (s != SSI_OK) return s;
   ssi::StabilityArgs a{};
   a.n_lags = p->n_lags;
@@ -1132,11 +1150,47 @@ ssi_status ssi_stability(ssi_ctx *c, const ssi_params *p, int32_t l, const ssi_o
   a.alpha_mac = sp->alpha_mac;
   a.mpc = mpc;
   a.mpd = mpd;
-  a.hc = ws_take<uint8_t>(c, slots);
+  a.hc = hc;
   a.flags = flags;
   SSI_HIP(ssi::launch_stability(a, c->stream));
   return SSI_OK;
 }
+
+}  // namespace
+
+extern "C" {
+
+ssi_status ssi_stability(ssi_ctx *c, const ssi_params *p, int32_t l, const ssi_output *out,
+                         const ssi_stability_params *sp, double *mpc, double *mpd,
+                         uint8_t *flags) {
+  return stability_impl(c, "ssi_stability", p, l, out, sp, mpc, mpd, flags,
+                        [c](size_t slots, uint8_t **hc) {
+                          ssi_status s = ws_reserve(c, aligned_bytes(slots, 1));
+                          if (s == SSI_OK) *hc = ws_take<uint8_t>(c, slots);
+                          return s;
+                        });
+}
+
+ssi_status ssi_stability_noalloc(ssi_ctx *c, const ssi_params *p, int32_t l,
+                                 const ssi_output *out, const ssi_stability_params *sp,
+                                 double *mpc, double *mpd, uint8_t *flags) {
+  return stability_impl(c, "ssi_stability_noalloc", p, l, out, sp, mpc, mpd, flags,
+                        [c](size_t slots, uint8_t **hc) {
+                          const size_t cap = ssi::noalloc_stability_slots();
+                          if (slots > cap)
+                            return fail(SSI_EINVAL,
+                                        "ssi_stability_noalloc: %zu pole slots exceed the "
+                                        "fixed scratch of %zu",
+                                        slots, cap);
+                          // every slot of the scratch that the kernels read is
+                          // written first by quality_kernel: nothing to clear
+                          const hipError_t e = ssi::noalloc_scratch(c->device, hc);
+                          if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress");
+                          return SSI_OK;
+                        });
+}
+
+int64_t ssi_stability_noalloc_max_slots(void) { return (int64_t)ssi::noalloc_stability_slots(); }
 
 ssi_status ssi_identify(ssi_ctx *c, const float *y, int32_t l, int64_t n, int64_t ldy,
                         const ssi_params *p, const ssi_output *out) {

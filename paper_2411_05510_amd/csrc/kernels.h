@@ -141,5 +141,10 @@ struct StabilityArgs {
   uint8_t *flags;
 };
 hipError_t launch_stability(const StabilityArgs &a, hipStream_t st);
+// Static device scratch of the allocation-free stability entry point:
+// capacity in pole slots, and its device address on `device` (which must be
+// current; looked up with hipGetSymbolAddress once per device).
+size_t noalloc_stability_slots();
+hipError_t noalloc_scratch(int device, uint8_t **ptr);
 
 }  // namespace ssi

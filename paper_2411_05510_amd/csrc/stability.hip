@@ -17,10 +17,24 @@
 //   alpha_mac; along the lag axis likewise with the same order of the
 //   previous lag.  Stable: hard criteria and (order axis or lag axis).
 // Everything is FP64 (mode shapes are widened from their FP32 storage).
+#include <mutex>
+
 #include "common.h"
 #include "kernels.h"
 
 namespace {
+
+// Fixed device array for ssi_stability_noalloc: the hard-criteria verdict of
+// every pole slot (one byte per slot), for callers that cannot allocate.
+// Each GPU the library runs on holds its own copy until the process ends.
+constexpr size_t kNoAllocSlots = size_t(4) << 20;
+__device__ __align__(256) uint8_t scratch[kNoAllocSlots];
+
+// Device address of `scratch` per device, from hipGetSymbolAddress.  In host
+// code the array's name is only a host-side stand-in, never a device address.
+constexpr int kMaxScratchDevices = 64;
+std::mutex g_scratch_mu;
+uint8_t *g_scratch_dev[kMaxScratchDevices] = {};
 
 constexpr double kHalfPi = 1.5707963267948966;
 
@@ -187,6 +201,23 @@ soft_kernel(int n_lags, int n_orders, int nmin, int step, int pole_cap, int l,
 }
 
 namespace ssi {
+
+size_t noalloc_stability_slots() { return kNoAllocSlots; }
+
+// The caller has made `device` current.  Looks the address up once per
+// device; later calls return the cached pointer.
+hipError_t noalloc_scratch(int device, uint8_t **ptr) {
+  if (device < 0 || device >= kMaxScratchDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[device]) {
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_dev[device] = static_cast<uint8_t *>(p);
+  }
+  *ptr = g_scratch_dev[device];
+  return hipSuccess;
+}
 
 hipError_t launch_stability(const StabilityArgs &a, hipStream_t st) {
   const int64_t total = (int64_t)a.n_lags * a.pole_cap;

@@ -34,6 +34,7 @@ EXPORTED = (
     "ssi_set_corr_mode", "ssi_tuned_splits", "ssi_footprint", "ssi_server_create", "ssi_server_destroy",
     "ssi_server_submit", "ssi_server_poll", "ssi_server_wait", "ssi_server_result",
     "ssi_server_release", "ssi_server_get_stats", "ssi_server_last_error", "ssi_stability",
+    "ssi_stability_noalloc", "ssi_stability_noalloc_max_slots",
 )
 
 POLE_HC, POLE_STABLE_ORDER, POLE_STABLE_LAG, POLE_STABLE = 1, 2, 4, 8
@@ -165,6 +166,10 @@ def lib() -> ctypes.CDLL:
             "ssi_server_last_error": ([], ctypes.c_char_p),
             "ssi_stability": ([vp, P, i32, ctypes.POINTER(_Output),
                                ctypes.POINTER(_StabilityParams), vp, vp, vp], ctypes.c_int),
+            "ssi_stability_noalloc": ([vp, P, i32, ctypes.POINTER(_Output),
+                                       ctypes.POINTER(_StabilityParams), vp, vp, vp],
+                                      ctypes.c_int),
+            "ssi_stability_noalloc_max_slots": ([], i64),
         }
         for name, (args, res) in sig.items():
             fn = getattr(L, name)
@@ -373,20 +378,26 @@ class Context:
 
     def stability(self, out: "Output", l: int, xi_max: float = 0.10, mpc_min: float = 0.60,
                   mpd_max: float = 0.50, alpha_f: float = 0.01, alpha_xi: float = 0.03,
-                  alpha_mac: float = 0.02):
-        """(mpc, mpd, flags) device tensors [n_lags, pole_cap] of the poles in out."""
+                  alpha_mac: float = 0.02, noalloc: bool = False, into=None):
+        """(mpc, mpd, flags) device tensors [n_lags, pole_cap] of the poles in out.
+        noalloc: call ssi_stability_noalloc (static scratch).  into: caller's
+        (mpc, mpd, flags) tensors to write instead of new ones."""
         import torch
         lay = out.layout
         shape = (lay["n_lags"], lay["pole_cap"])
         dev = out.f.device
-        mpc = torch.zeros(shape, dtype=torch.float64, device=dev)
-        mpd = torch.zeros(shape, dtype=torch.float64, device=dev)
-        flags = torch.zeros(shape, dtype=torch.uint8, device=dev)
+        if into is None:
+            mpc = torch.zeros(shape, dtype=torch.float64, device=dev)
+            mpd = torch.zeros(shape, dtype=torch.float64, device=dev)
+            flags = torch.zeros(shape, dtype=torch.uint8, device=dev)
+        else:
+            mpc, mpd, flags = into
         cp = out.params.c()
         co = out.c()
         sp = _StabilityParams(xi_max, mpc_min, mpd_max, alpha_f, alpha_xi, alpha_mac)
-        _check(lib().ssi_stability(self._h, ctypes.byref(cp), l, ctypes.byref(co),
-                                   ctypes.byref(sp), _ptr(mpc), _ptr(mpd), _ptr(flags)))
+        fn = lib().ssi_stability_noalloc if noalloc else lib().ssi_stability
+        _check(fn(self._h, ctypes.byref(cp), l, ctypes.byref(co), ctypes.byref(sp), _ptr(mpc),
+                  _ptr(mpd), _ptr(flags)))
         return mpc, mpd, flags
 
     # --------------------------------------------------- identification
