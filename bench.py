@@ -37,6 +37,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 FP32_MFMA_PEAK_TFLOPS = 157.3       # MI355X dense FP32 matrix peak
+FP64_MFMA_PEAK_TFLOPS = 78.6        # MI355X dense FP64 matrix peak
 BF16_MFMA_PEAK_TFLOPS = 2500.0      # MI355X dense BF16 matrix peak
 HBM_PEAK_GBS = 8000.0
 COPY_PROBE_BYTES = 256 << 20        # plain device copy used to calibrate HBM byte counters
@@ -62,6 +63,16 @@ def measured_traffic(corr: str):
     if not m_hash or not m_val or m_hash.group(1) != src:
         return None
     return float(m_val.group(1))
+
+
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def blas_threads() -> int:
@@ -90,20 +101,20 @@ def params_of(wl, prec: int):
 
 
 def roofline(stages, l, n, L, corr: str):
-    """Roofline of the correlation contraction kernel.  FP32 mode: algorithmic
-    flops against the FP32 matrix peak.  BF16x6 mode: every FP32 product is six
-    BF16 products, so the kernel's algorithmic BF16 work is six times the
-    contraction's flops, against the BF16 matrix peak; the FP32-equivalent rate
-    is reported beside it."""
+    """Roofline of the correlation contraction kernel, on algorithmic work
+    only: the contraction's 2 l^2 sum_j (N - j) flops per launch over the
+    kernel's mean duration, against the peak of the matrix instructions it
+    runs on (BF16 for the six-product split, FP32 otherwise).  The six BF16
+    products per FP32 product are emulation overhead and are not counted; the
+    rate at which the kernel issues BF16 MFMA work is reported beside it."""
     flops = corr_flops(l, n, L)
     corr_ms, corr_calls = stages["corr_mfma"]
     corr_avg_ms = corr_ms / max(corr_calls, 1)
-    fp32_eq = flops / (corr_avg_ms * 1e-3) / 1e12
+    achieved = flops / (corr_avg_ms * 1e-3) / 1e12
     if corr == "bf16x6":
-        work, peak = 6.0 * flops, BF16_MFMA_PEAK_TFLOPS
+        issue, peak = 6.0 * achieved, BF16_MFMA_PEAK_TFLOPS
     else:
-        work, peak = flops, FP32_MFMA_PEAK_TFLOPS
-    achieved = work / (corr_avg_ms * 1e-3) / 1e12
+        issue, peak = achieved, FP32_MFMA_PEAK_TFLOPS
     return {
         "bound": "mfma",
         "kernel": CORR_KERNEL[corr],
@@ -113,9 +124,41 @@ def roofline(stages, l, n, L, corr: str):
         "frac": achieved / peak,
         "traffic": measured_traffic(corr),
         "avg_kernel_ms": corr_avg_ms,
-        "algorithmic_flops_per_launch": work,
-        "fp32_equivalent_tflops": fp32_eq,
+        "algorithmic_flops_per_launch": flops,
+        "mfma_issue_tflops": issue,
+        "mfma_issue_frac": issue / peak,
     }
+
+
+def stage_rooflines(stages, steps, m, ell, q, prec: str):
+    """Rooflines of the other two kernels the survey gives targets for, from
+    their stage times per identification: the randomized-SVD products
+    (2q + 1 range-finder products and the projection, 2 m^2 ell flops each,
+    one read of T each) and the Toeplitz assembly (m^2 4 bytes written)."""
+    prod_ms = stages["products"][0] / steps
+    n_prod = 2 * q + 2
+    flops = n_prod * 2.0 * m * m * ell
+    tflops = flops / (prod_ms * 1e-3) / 1e12
+    t_read = n_prod * m * m * 4.0 / (prod_ms * 1e-3) / 1e9
+    toe_ms, toe_calls = stages["toeplitz"]
+    toe_avg = toe_ms / max(toe_calls, 1)
+    toe_gbs = m * m * 4.0 / (toe_avg * 1e-3) / 1e9
+    prod = {"stage": "products", "kernels": "gemm_tf64w_mfma + reduce_splits" if prec == "fp32"
+            else "gemm_tbf16_mfma (range finder) + gemm_tf64w_mfma (projection)",
+            "ms_per_identification": prod_ms, "algorithmic_flops": flops, "tflops": tflops,
+            "t_read_gbs": t_read}
+    if prec == "fp32":
+        # FP32 T times FP64 X on the FP64 matrix instructions
+        prod.update(bound="mfma", achieved=tflops, peak=FP64_MFMA_PEAK_TFLOPS, unit="TFLOP/s",
+                    frac=tflops / FP64_MFMA_PEAK_TFLOPS)
+    else:
+        # BF16 operands: below the BF16 ridge, T is read once per product
+        prod.update(bound="hbm", achieved=t_read, peak=HBM_PEAK_GBS, unit="GB/s",
+                    frac=t_read / HBM_PEAK_GBS)
+    toe = {"stage": "toeplitz", "kernels": "toeplitz_vec4", "bound": "hbm",
+           "avg_kernel_ms": toe_avg, "achieved": toe_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": toe_gbs / HBM_PEAK_GBS, "algorithmic_bytes": m * m * 4.0}
+    return [prod, toe]
 
 
 def timed_steps(ctx, step, steps, stream):
@@ -174,10 +217,23 @@ def bench_identify(args) -> dict:
 
     L = 2 * wl.lags[0] - 1
     m = wl.lags[0] * wl.l
-    toe_ms, toe_calls = stages["toeplitz"]
-    toe_avg = toe_ms / max(toe_calls, 1)
-    toe_gbs = (m * m * 4) / (toe_avg * 1e-3) / 1e9
     flags = int(out.flags.sum().item())
+
+    # End to end: the record from pinned host memory, the identification and
+    # every output back on the host (ssi_identify_result), a few steps.
+    e2e = None
+    if args.e2e_steps > 0:
+        y_pin = torch.from_numpy(y).pin_memory()
+        ctx.identify_result(y_pin, p).close()            # sizes the context's output buffers
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(args.e2e_steps):
+            ctx.identify_result(y_pin, p).close()
+        e2e_s = (time.perf_counter() - t1) / args.e2e_steps
+        e2e = {"identifications_per_s": 1.0 / e2e_s, "ms_per_identification": 1000.0 * e2e_s,
+               "steps": args.e2e_steps,
+               "span": "H2D of the 130 MB record from pinned memory, the identification, "
+                       "D2H of every output"}
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -188,7 +244,7 @@ def bench_identify(args) -> dict:
                         seed=wl.sketch_seed)
         cpu_s = time.perf_counter() - t1
         cpu = {"value": 1.0 / cpu_s, "unit": "identifications/s", "cores": blas_threads(),
-               "kind": "oracle",
+               "cpu_model": cpu_model(), "kind": "oracle",
                "sample": f"one full identification of the same bridge-180ch record "
                          f"(FP64 numpy checker, {cpu_s:.1f} s)"}
     corr_note = {"fp32": "correlations on FP32 MFMA",
@@ -220,11 +276,12 @@ def bench_identify(args) -> dict:
             "latency_ms_p50": float(np.percentile(step_ms, 50)),
             "latency_ms_p99": float(np.percentile(step_ms, 99)),
             "stage_ms_per_step": {k: v[0] / args.steps for k, v in stages.items()},
-            "toeplitz_hbm_gbs": toe_gbs,
-            "toeplitz_hbm_frac": toe_gbs / HBM_PEAK_GBS,
             "eig_flags": flags,
+            "end_to_end": e2e,
         },
         "roofline": roofline(stages, wl.l, wl.n, L, args.corr),
+        "rooflines_other": stage_rooflines(stages, args.steps, m, wl.rank + wl.oversample,
+                                           wl.power_iters, args.prec),
         "cpu_baseline": cpu,
     }
     ctx.close()
@@ -389,6 +446,8 @@ def main() -> int:
     ap.add_argument("--inflight", type=int, default=16, help="serving: slots")
     ap.add_argument("--pool", type=int, default=24, help="serving: distinct windows")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--e2e-steps", type=int, default=5,
+                    help="end-to-end steps (host record in, host results out) after the timing")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run one plain device copy of 256 MiB first (counter calibration)")
     args = ap.parse_args()

@@ -63,11 +63,18 @@ typedef enum ssi_svd_mode {
 typedef enum ssi_precision {
   SSI_PREC_FP32 = 0,   /* T as stored (FP32) times FP64 X, FP64 MFMA accumulation */
   SSI_PREC_BF16 = 1,   /* T and X rounded to BF16 (nearest even), FP32 MFMA
-                          accumulation, FP64 sum of the K slices                   */
+                          accumulation, FP64 sum of the K slices.  A lower-accuracy
+                          mode: 8 significant bits resolve singular vectors only
+                          down to about 2^-9 sigma_1, so poles at orders that need
+                          smaller singular values move by more than the
+                          reduced-precision tolerance (up to 6e-3 in frequency on a
+                          180-channel record at orders 86..200)                  */
   SSI_PREC_BF16X3 = 2  /* T and X split into BF16 hi + lo parts (lo = BF16 of the
                           remainder), three BF16 MFMA products hi hi + hi lo +
                           lo hi with FP32 accumulation: about 16 significant bits
-                          per operand                                              */
+                          per operand.  The reduced-precision mode that keeps
+                          frequencies within 1e-3, damping within 2e-3 and MAC
+                          above 0.99 of the FP64 computation at every order      */
 } ssi_precision;
 
 /* Arithmetic of the correlation products (Section 2.1), a context option.
@@ -103,6 +110,13 @@ typedef struct ssi_params {
   int32_t prec;               /* ssi_precision of the range-finder products;
                                  other than SSI_PREC_FP32 needs
                                  svd = SSI_SVD_RANDOMIZED                          */
+  const float *omega;         /* optional caller sketch (Eq. (14)): device pointer,
+                                 m_max x (k + p) floats, row-major, ld omega_ld,
+                                 m_max = max(j_b) l; lag i uses its leading j_b,i l
+                                 rows.  NULL: drawn from `seed` (Philox stream i for
+                                 lag i).  Randomized SVD only.  Read during the
+                                 call's device work (stream-ordered).               */
+  int64_t omega_ld;           /* >= k + p when omega is given                       */
 } ssi_params;
 
 /* Sizes of the device output buffers of ssi_identify, from ssi_output_layout. */
@@ -145,7 +159,15 @@ typedef struct ssi_ctx ssi_ctx;
 ssi_status ssi_create(int device, void *hip_stream, ssi_ctx **out);
 /* Free the context and its workspace.  NULL is ignored. */
 void ssi_destroy(ssi_ctx *ctx);
-/* Block until all work enqueued by this context has finished. */
+/* Block until all work enqueued by this context has finished, then report
+ * (and clear) what the kernels flagged on the device:
+ *   SSI_EINVAL   the record held non-finite samples (NaN or Inf);
+ *   SSI_ENOCONV  a Cholesky factorization broke down, or the QR iteration of
+ *                an order hit its sweep limit (ssi_set_eig_max_sweeps; the
+ *                order's output flag is 1), or a pole's wait for its order's
+ *                eigenvalues timed out (that pole is skipped);
+ *   SSI_EINTERNAL the eigen-analysis work loop hit its pass cap.
+ * The kernels finish normally in every case. */
 ssi_status ssi_synchronize(ssi_ctx *ctx);
 /* Bytes of device workspace currently held by the context. */
 size_t ssi_workspace_bytes(const ssi_ctx *ctx);
@@ -181,14 +203,18 @@ ssi_status ssi_profile_read(ssi_ctx *ctx, double *ms, int32_t *calls, int32_t n_
  * Synchronizes the context stream. */
 ssi_status ssi_set_lag_streams(ssi_ctx *ctx, int32_t n);
 /* Graph mode for ssi_identify (default off).  When on, every ssi_identify
- * call is keyed by all its arguments (pointers, sizes, parameters, lag
- * streams).  The first call with a key runs eagerly, waits for completion,
- * and captures the whole identification - all lags and orders - into one HIP
- * graph; later calls with the same key launch that graph on the context
- * stream.  Graphs are dropped when the workspace grows, the lag-stream count
- * changes or graph mode is turned off.  Stage profiling is not recorded for
- * graph launches.  The output buffers and y must stay allocated while a
- * graph that names them may be launched. */
+ * call with a device record is keyed by all its arguments (pointers, sizes,
+ * parameters, lag streams).  The first call with a key runs eagerly, waits
+ * for completion, and captures the whole identification - all lags and
+ * orders - into one HIP graph; later calls with the same key launch that
+ * graph on the context stream.  The context keeps the 8 most recently used
+ * graphs (a ninth key evicts the least recently used, after synchronizing),
+ * so graph mode pays off for callers that reuse their record and output
+ * buffers.  Graphs are dropped when the workspace grows, the lag-stream count
+ * or another option changes, or graph mode is turned off.  Calls with a host
+ * record always run eagerly.  Stage profiling is not recorded for graph
+ * launches.  The output buffers and y must stay allocated while a graph that
+ * names them may be launched. */
 ssi_status ssi_set_graphs(ssi_ctx *ctx, int enable);
 /* Autotuning of the range-finder products (default off).  When on, the
  * first product of each (precision, orientation, M, N, K) times candidate
@@ -198,6 +224,24 @@ ssi_status ssi_set_graphs(ssi_ctx *ctx, int enable);
  * keeps the fastest for the life of the context.  Tuning synchronizes the
  * stream once per new shape and never runs inside a graph capture. */
 ssi_status ssi_set_autotune(ssi_ctx *ctx, int enable);
+/* Sweep limit of the eigen-analysis (Eq. (11)): the QR iteration of an order
+ * of size n stops after sweeps_per_row * max(10, n) sweeps (default 30, as
+ * LAPACK's Hessenberg QR), marks the order in the output flags and makes the
+ * next ssi_synchronize return SSI_ENOCONV.  0 <= sweeps_per_row <= 1000; 0
+ * fails every order that needs a sweep (orders of size 1 and 2 need none).
+ * The iteration runs inside the kernel and always ends at the limit.  Drops
+ * captured graphs. */
+ssi_status ssi_set_eig_max_sweeps(ssi_ctx *ctx, int32_t sweeps_per_row);
+/* Device memory for the context's workspace and ssi_identify_result's output
+ * buffers from the caller's allocator (for example a framework's caching
+ * allocator) instead of hipMalloc/hipFree.  alloc(bytes, user) returns a
+ * device pointer on the context's device, or NULL when it cannot (the call
+ * that needed it then fails with SSI_ENOMEM); release(ptr, user) takes back
+ * what alloc returned, after all work that used it has finished.  Pass NULL
+ * for both to return to hipMalloc.  Memory held from the previous allocator is
+ * released to it first (after synchronizing).  Drops captured graphs. */
+ssi_status ssi_set_allocator(ssi_ctx *ctx, void *(*alloc)(size_t bytes, void *user),
+                             void (*release)(void *ptr, void *user), void *user);
 /* Correlation product arithmetic (ssi_corr_mode) for later ssi_correlate,
  * ssi_identify and serving calls on this context; default SSI_CORR_BF16X6.
  * SSI_EINVAL for an unknown mode.  Drops captured graphs. */
@@ -236,12 +280,51 @@ const char *ssi_last_error(void);
 
 /* ---------------------------------------------------- whole identification */
 
-/* Full identification of one record for every (lag, order).
- * y: device pointer, l x n floats, channel-major with leading dimension ldy
- * (>= n).  out: device buffers sized by ssi_output_layout.  Enqueued on the
- * context stream; results are valid after ssi_synchronize(). */
+/* Full identification of one record for every (lag, order) (Section 2.1,
+ * Section 2.3 step i).
+ * y: l x n floats, channel-major with leading dimension ldy (>= n); a device
+ * pointer, or a host pointer (pinned or pageable), which is first copied into
+ * the workspace (l n 4 more bytes) on the context stream; with pageable
+ * memory that copy may return only once the data is staged.  out: device
+ * buffers sized by ssi_output_layout.  Enqueued on the context stream;
+ * results are valid after ssi_synchronize(), which also reports a record
+ * with non-finite samples (SSI_EINVAL) and non-convergence (SSI_ENOCONV). */
 ssi_status ssi_identify(ssi_ctx *ctx, const float *y, int32_t l, int64_t n,
                         int64_t ldy, const ssi_params *p, const ssi_output *out);
+
+/* Host results.  An ssi_result holds host copies of one identification's
+ * outputs; the library owns it and every pointer its accessors return, all
+ * valid until ssi_result_free. */
+typedef struct ssi_result ssi_result;
+/* Synchronous identification: runs ssi_identify into output buffers the
+ * context owns (kept and reused; from the allocator of ssi_set_allocator
+ * when set), waits for it and copies the outputs to a new host result.
+ * y: device or host pointer as for ssi_identify.  Returns the status of
+ * ssi_synchronize; on SSI_ENOCONV or SSI_EINVAL from the device checks *res is
+ * still set (per-order flags tell which orders failed). */
+ssi_status ssi_identify_result(ssi_ctx *ctx, const float *y, int32_t l, int64_t n,
+                               int64_t ldy, const ssi_params *p, ssi_result **res);
+/* Waits for the context (ssi_synchronize, whose status it returns) and
+ * copies the device outputs `out` of an identification with parameters p and
+ * l channels into a new host result, set on every status but a failed copy. */
+ssi_status ssi_result_fetch(ssi_ctx *ctx, const ssi_params *p, int32_t l,
+                            const ssi_output *out, ssi_result **res);
+ssi_status ssi_result_dims(const ssi_result *res, int32_t *n_lags, int32_t *n_orders,
+                           int32_t *l);
+/* Poles of (lag index, order index): model order n2, pole count, and arrays
+ * of n_poles entries sorted by (f, xi): f in Hz, damping ratio, discrete
+ * eigenvalue (re, im) pairs, mode shapes (n_poles x l complex, (re, im)
+ * interleaved); flag 1 when that order's QR iteration hit its limit.  Any
+ * output pointer may be NULL. */
+ssi_status ssi_result_poles(const ssi_result *res, int32_t lag_i, int32_t order_i,
+                            int32_t *order, int32_t *n_poles, const double **f_hz,
+                            const double **zeta, const double **mu_reim,
+                            const float **phi_reim, int32_t *flag);
+/* Singular values of lag lag_i (descending; *n = sigma_per_lag). */
+ssi_status ssi_result_singular_values(const ssi_result *res, int32_t lag_i, int32_t *n,
+                                      const double **sigma);
+/* Frees a result (NULL is ignored). */
+void ssi_result_free(ssi_result *res);
 
 /* ------------------------------------- stages on device buffers (parity) */
 

@@ -46,6 +46,7 @@ ssi_status hip_fail(hipError_t e, const char *where) {
 
 // ------------------------------------------------------------------ context
 constexpr int kMaxLanes = 4;      // concurrent lag streams of one identification
+constexpr size_t kMaxGraphs = 8;  // captured identifications kept per context (LRU)
 
 struct ssi_ctx {
   int device = 0;
@@ -82,6 +83,15 @@ struct ssi_ctx {
   // correlation product arithmetic (ssi_corr_mode)
   int corr_mode = SSI_CORR_BF16X6;
   std::map<std::tuple<int, int, int, int, int>, int> tuned;
+  // QR sweep limit of the eigen-analysis: sweeps_per_row * max(10, n) per order
+  int sweeps_per_row = 30;
+  // workspace allocator (NULL: hipMalloc / hipFree)
+  void *(*alloc)(size_t, void *) = nullptr;
+  void (*release)(void *, void *) = nullptr;
+  void *alloc_user = nullptr;
+  // device output buffers of ssi_identify_result
+  char *obuf = nullptr;
+  size_t obuf_cap = 0;
 };
 
 namespace {
@@ -117,6 +127,29 @@ void drop_graphs(ssi_ctx *c) {
   c->graph_cache.clear();
 }
 
+// Device memory for the context: the caller's allocator when one is set.
+hipError_t dev_alloc(ssi_ctx *c, char **p, size_t bytes) {
+  if (c->alloc) {
+    *p = static_cast<char *>(c->alloc(bytes, c->alloc_user));
+    return *p ? hipSuccess : hipErrorOutOfMemory;
+  }
+  return hipMalloc(reinterpret_cast<void **>(p), bytes);
+}
+void dev_free(ssi_ctx *c, void *p) {
+  if (!p) return;
+  if (c->release)
+    c->release(p, c->alloc_user);
+  else
+    (void)hipFree(p);
+}
+
+// Waits for everything the context enqueued (its stream and lag streams).
+void drain(ssi_ctx *c) {
+  (void)hipStreamSynchronize(c->stream);
+  for (int s = 0; s < kMaxLanes; ++s)
+    if (c->lanes[s]) (void)hipStreamSynchronize(c->lanes[s]);
+}
+
 // Reserve `bytes` of workspace for the current call (256-byte aligned).  Call
 // ws_reserve once with the call's total before ws_take.
 ssi_status ws_reserve(ssi_ctx *c, size_t bytes) {
@@ -129,11 +162,11 @@ ssi_status ws_reserve(ssi_ctx *c, size_t bytes) {
   for (int s = 0; s < c->n_lanes; ++s)
     if (c->lanes[s]) (void)hipStreamSynchronize(c->lanes[s]);
   drop_graphs(c);
-  if (c->ws) (void)hipFree(c->ws);
+  dev_free(c, c->ws);
   c->ws = nullptr;
   c->ws_cap = 0;
   size_t cap = bytes + (bytes >> 3);
-  e = hipMalloc(&c->ws, cap);
+  e = dev_alloc(c, &c->ws, cap);
   if (e != hipSuccess) {
     (void)hipGetLastError();
     return fail(SSI_ENOMEM, "workspace of %zu bytes could not be allocated", cap);
@@ -255,7 +288,8 @@ void ssi_destroy(ssi_ctx *c) {
   if (c->fork_ev) (void)hipEventDestroy(c->fork_ev);
   drop_graphs(c);
   if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
-  if (c->ws) (void)hipFree(c->ws);
+  dev_free(c, c->ws);
+  dev_free(c, c->obuf);
   if (c->status) (void)hipFree(c->status);
   for (auto &r : c->recs) {
     (void)hipEventDestroy(r.a);
@@ -275,6 +309,18 @@ ssi_status ssi_synchronize(ssi_ctx *c) {
   SSI_HIP(hipMemcpy(&word, c->status, sizeof(int), hipMemcpyDeviceToHost));
   if (word) {
     SSI_HIP(hipMemset(c->status, 0, sizeof(int)));
+    if (word & ssi::kStatusNonFinite)
+      return fail(SSI_EINVAL, "the record holds non-finite samples (NaN or Inf): its "
+                              "correlations are not finite (status bits 0x%x)", word);
+    if (word & ssi::kStatusPoleWait)
+      return fail(SSI_ENOCONV, "a pole's wait for its order's eigenvalues timed out; the poles "
+                               "of that order were skipped (status bits 0x%x)", word);
+    if (word & ssi::kStatusClaimCap)
+      return fail(SSI_EINTERNAL, "the eigen-analysis work loop hit its pass cap "
+                                 "(status bits 0x%x)", word);
+    if (word & ssi::kStatusEigLimit)
+      return fail(SSI_ENOCONV, "the QR iteration of at least one model order hit its sweep "
+                               "limit; per-order flags mark which (status bits 0x%x)", word);
     return fail(SSI_ENOCONV, "a factorization broke down (status bits 0x%x): the matrix was "
                              "numerically singular or not finite", word);
   }
@@ -334,6 +380,40 @@ ssi_status ssi_set_corr_mode(ssi_ctx *c, int32_t mode) {
     drop_graphs(c);
   }
   c->corr_mode = mode;
+  return SSI_OK;
+}
+
+ssi_status ssi_set_eig_max_sweeps(ssi_ctx *c, int32_t sweeps_per_row) {
+  if (!c) return fail(SSI_EINVAL, "ssi_set_eig_max_sweeps: NULL context");
+  if (sweeps_per_row < 0 || sweeps_per_row > 1000)
+    return fail(SSI_EINVAL, "ssi_set_eig_max_sweeps: %d not in [0, 1000]", sweeps_per_row);
+  if (sweeps_per_row != c->sweeps_per_row) {
+    DeviceGuard g(c->device);
+    drain(c);
+    drop_graphs(c);
+  }
+  c->sweeps_per_row = sweeps_per_row;
+  return SSI_OK;
+}
+
+ssi_status ssi_set_allocator(ssi_ctx *c, void *(*alloc)(size_t, void *),
+                             void (*release)(void *, void *), void *user) {
+  if (!c) return fail(SSI_EINVAL, "ssi_set_allocator: NULL context");
+  if ((alloc == nullptr) != (release == nullptr))
+    return fail(SSI_EINVAL, "ssi_set_allocator: give both callbacks or neither");
+  DeviceGuard g(c->device);
+  // memory from the old allocator goes back to it before the switch
+  drain(c);
+  drop_graphs(c);
+  dev_free(c, c->ws);
+  dev_free(c, c->obuf);
+  c->ws = nullptr;
+  c->ws_cap = 0;
+  c->obuf = nullptr;
+  c->obuf_cap = 0;
+  c->alloc = alloc;
+  c->release = release;
+  c->alloc_user = user;
   return SSI_OK;
 }
 
@@ -400,6 +480,11 @@ ssi_status ssi_validate(const ssi_params *p, int32_t l, int64_t n) {
     return fail(SSI_EINVAL, "unknown precision %d", p->prec);
   if (p->prec != SSI_PREC_FP32 && p->svd != SSI_SVD_RANDOMIZED)
     return fail(SSI_EINVAL, "BF16 products apply to the randomized SVD only");
+  if (p->omega && p->svd != SSI_SVD_RANDOMIZED)
+    return fail(SSI_EINVAL, "a caller sketch applies to the randomized SVD only");
+  if (p->omega && p->omega_ld < (int64_t)p->rank + p->oversample)
+    return fail(SSI_EINVAL, "omega_ld = %lld must be >= k + p = %d", (long long)p->omega_ld,
+                p->rank + p->oversample);
   for (int i = 0; i < p->n_lags; ++i) {
     const int64_t jb = p->lags[i];
     if (jb < 2) return fail(SSI_EINVAL, "lag %d: j_b = %lld must be >= 2", i, (long long)jb);
@@ -639,14 +724,14 @@ double *orthonormalize(ssi_ctx *c, RsvdBufs &b, double *cur, double *nxt, int64_
 }
 
 ssi_status run_rsvd(ssi_ctx *c, RsvdBufs &b, const float *t, int64_t m, int64_t ldt, int k,
-                    int p, int q, const float *omega, uint64_t seed, uint32_t stream, double *u,
-                    double *sigma) {
+                    int p, int q, const float *omega, int64_t ldo, uint64_t seed,
+                    uint32_t stream, double *u, double *sigma) {
   const int ell = k + p, mi = (int)m;
   hipError_t e;
   {
     StageTimer tm(c, SSI_STAGE_SKETCH);
     if (omega)
-      e = ssi::launch_convert_f32_f64(omega, ell, mi, ell, b.om, ell, c->stream);
+      e = ssi::launch_convert_f32_f64(omega, ldo, mi, ell, b.om, ell, c->stream);
     else
       e = ssi::launch_sketch(seed, stream, m, ell, b.om, ell, c->stream);
   }
@@ -825,6 +910,7 @@ ssi_status run_modal(ssi_ctx *c, ModalBufs &b, const double *u, int64_t m, int k
   // with lags on several streams, a grid of one workgroup per order leaves
   // the other CUs to the other lags' kernels
   a.eig_grid = std::min(c->n_lanes, p->n_lags) > 1 ? no : 0;
+  a.sweeps_per_row = c->sweeps_per_row;
   a.count = out->count + (int64_t)lag_i * no;
   a.flags = out->flags + (int64_t)lag_i * no;
   a.f = out->f + (int64_t)lag_i * pole_cap;
@@ -849,6 +935,7 @@ struct LaneBufs {
 };
 
 struct IdentBufs {
+  float *ystage;                      // device copy of a host record (l x n), or NULL
   ssi::CorrPlan cp;
   double *corr_part;
   uint16_t *planes;                   // BF16 parts of the record (BF16x6 correlations)
@@ -859,8 +946,10 @@ struct IdentBufs {
 
 int lanes_for(const ssi_ctx *c, const ssi_params *p) { return std::min(c->n_lanes, p->n_lags); }
 
-IdentBufs carve_identify(Arena &a, ssi_ctx *c, int l, int64_t n, const ssi_params *p) {
+IdentBufs carve_identify(Arena &a, ssi_ctx *c, int l, int64_t n, const ssi_params *p,
+                         bool stage_y = false) {
   IdentBufs b{};
+  if (stage_y) b.ystage = a.take<float>((size_t)l * n);
   const int L = 2 * p->lags[p->n_lags - 1] - 1;
   b.cp = ssi::plan_correlate(l, n, L, c->num_cus, c->corr_mode);
   b.corr_part = a.take<double>(b.cp.partial_elems);
@@ -902,8 +991,9 @@ ssi_status run_lag(ssi_ctx *c, LaneBufs &b, const float *r, int l, const ssi_par
   if (e != hipSuccess) return hip_fail(e, "Toeplitz");
   ssi_status s;
   if (p->svd == SSI_SVD_RANDOMIZED)
-    s = run_rsvd(c, b.rb, b.t, m, ldt, p->rank, p->oversample, p->power_iters, nullptr, p->seed,
-                 (uint32_t)i, b.u, b.sig);
+    // a caller sketch gives every lag its leading m rows
+    s = run_rsvd(c, b.rb, b.t, m, ldt, p->rank, p->oversample, p->power_iters, p->omega,
+                 p->omega_ld, p->seed, (uint32_t)i, b.u, b.sig);
   else
     s = run_svd_full(c, b.fb, b.t, (int)m, ldt, kcols, b.u, b.sig);
   if (s != SSI_OK) return s;
@@ -937,7 +1027,7 @@ ssi_status run_identify(ssi_ctx *c, IdentBufs &b, const float *y, int l, int64_t
   if (e != hipSuccess) return hip_fail(e, "correlations");
   {
     StageTimer tm(c, SSI_STAGE_CORR_REDUCE);
-    e = ssi::launch_correlate_reduce(b.cp, l, n, L, b.corr_part, b.r, c->stream);
+    e = ssi::launch_correlate_reduce(b.cp, l, n, L, b.corr_part, b.r, c->status, c->stream);
   }
   if (e != hipSuccess) return hip_fail(e, "correlation reduction");
   if (b.n_lanes == 1) {
@@ -996,7 +1086,7 @@ ssi_status ssi_correlate(ssi_ctx *c, const float *y, int32_t l, int64_t n, int64
     SSI_HIP(ssi::launch_correlate_mfma(cp, y, l, n, ldy, n_corr, partial, planes, c->stream));
   }
   StageTimer tm(c, SSI_STAGE_CORR_REDUCE);
-  SSI_HIP(ssi::launch_correlate_reduce(cp, l, n, n_corr, partial, r, c->stream));
+  SSI_HIP(ssi::launch_correlate_reduce(cp, l, n, n_corr, partial, r, c->status, c->stream));
   return SSI_OK;
 }
 
@@ -1058,7 +1148,7 @@ ssi_status ssi_rsvd(ssi_ctx *c, const float *t, int64_t m, int64_t ldt, int32_t 
   if (s != SSI_OK) return s;
   Arena a{c->ws, 0};
   RsvdBufs b = carve_rsvd(a, c, m, k + p, k, prec);
-  return run_rsvd(c, b, t, m, ldt, k, p, q, omega, seed, stream, u, sigma);
+  return run_rsvd(c, b, t, m, ldt, k, p, q, omega, k + p, seed, stream, u, sigma);
 }
 
 ssi_status ssi_svd_full(ssi_ctx *c, const float *t, int64_t m, int64_t ldt, int32_t k, double *u,
@@ -1201,14 +1291,25 @@ ssi_status ssi_identify(ssi_ctx *c, const float *y, int32_t l, int64_t n, int64_
   if (!out->sigma || !out->count || !out->f || !out->xi || !out->mu || !out->phi || !out->flags)
     return fail(SSI_EINVAL, "ssi_identify: NULL output buffer");
   DeviceGuard g(c->device);
-  if (!is_device_ptr(y)) return fail(SSI_EINVAL, "ssi_identify: y must be a device pointer");
+  if (p->omega && !is_device_ptr(p->omega))
+    return fail(SSI_EINVAL, "ssi_identify: omega must be a device pointer");
+  // a host record (pinned or pageable) is copied into the workspace first
+  const bool host_y = !is_device_ptr(y);
   Arena probe;
-  carve_identify(probe, c, l, n, p);
+  carve_identify(probe, c, l, n, p, host_y);
   s = ws_reserve(c, probe.off);
   if (s != SSI_OK) return s;
   Arena a{c->ws, 0};
-  IdentBufs b = carve_identify(a, c, l, n, p);
-  if (!c->graphs) return run_identify(c, b, y, l, n, ldy, p, out);
+  IdentBufs b = carve_identify(a, c, l, n, p, host_y);
+  if (host_y) {
+    SSI_HIP(hipMemcpy2DAsync(b.ystage, (size_t)n * sizeof(float), y, (size_t)ldy * sizeof(float),
+                             (size_t)n * sizeof(float), (size_t)l, hipMemcpyHostToDevice,
+                             c->stream));
+    y = b.ystage;
+    ldy = n;
+  }
+  // graphs replay device work only: a host record always runs eagerly
+  if (!c->graphs || host_y) return run_identify(c, b, y, l, n, ldy, p, out);
 
   // Graph mode: every argument (pointers included) keys a captured graph of
   // the whole identification.  The first call with a key runs eagerly (any
@@ -1230,9 +1331,12 @@ ssi_status ssi_identify(ssi_ctx *c, const float *y, int32_t l, int64_t n, int64_
   put(&pc, sizeof pc);
   put(p->lags, sizeof(int32_t) * p->n_lags);
   put(&c->n_lanes, sizeof c->n_lanes);
-  for (auto &g : c->graph_cache)
-    if (g.key == key) {
-      SSI_HIP(hipGraphLaunch(g.exec, c->stream));
+  for (size_t gi = 0; gi < c->graph_cache.size(); ++gi)
+    if (c->graph_cache[gi].key == key) {
+      // most recently used first
+      std::rotate(c->graph_cache.begin(), c->graph_cache.begin() + gi,
+                  c->graph_cache.begin() + gi + 1);
+      SSI_HIP(hipGraphLaunch(c->graph_cache.front().exec, c->stream));
       return SSI_OK;
     }
   s = run_identify(c, b, y, l, n, ldy, p, out);
@@ -1267,8 +1371,186 @@ ssi_status ssi_identify(ssi_ctx *c, const float *y, int32_t l, int64_t n, int64_
   hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
   (void)hipGraphDestroy(graph);
   if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate");
-  c->graph_cache.push_back({std::move(key), exec});
+  if (c->graph_cache.size() >= kMaxGraphs) {
+    // evict the least recently used graph once nothing of it can be in flight
+    drain(c);
+    (void)hipGraphExecDestroy(c->graph_cache.back().exec);
+    c->graph_cache.pop_back();
+  }
+  c->graph_cache.insert(c->graph_cache.begin(), {std::move(key), exec});
   return SSI_OK;
 }
+
+}  // extern "C"
+
+// ------------------------------------------------------------ host results
+// Host copy of one identification's outputs (ssi_output layout), owned by the
+// library until ssi_result_free.
+struct ssi_result {
+  ssi_layout lay{};
+  int32_t nmin = 0, step = 1;
+  std::vector<int32_t> offs;          // pole slot offset of each order within a lag
+  std::vector<double> sigma, f, xi, mu;
+  std::vector<int32_t> count, flags;
+  std::vector<float> phi;
+};
+
+namespace {
+
+// Output sizes from the parameters alone (the record length only enters
+// validation).
+ssi_status layout_of(const ssi_params *p, int32_t l, ssi_layout *lay) {
+  if (!p || !p->lags || p->n_lags < 1 || l < 1 || p->order_step < 1 || p->order_min < 1 ||
+      p->order_max < p->order_min || (p->svd != SSI_SVD_FULL && p->svd != SSI_SVD_RANDOMIZED))
+    return fail(SSI_EINVAL, "invalid parameters for an output layout");
+  lay->n_lags = p->n_lags;
+  lay->n_orders = n_orders_of(p);
+  lay->sigma_per_lag = p->svd == SSI_SVD_RANDOMIZED ? p->rank : p->order_max;
+  lay->pole_cap = ssi_pole_offset(p, lay->n_orders);
+  lay->l = l;
+  lay->n_corr = 2 * p->lags[p->n_lags - 1] - 1;
+  return SSI_OK;
+}
+
+struct OutSizes {
+  size_t sigma, count, poles, phi;
+  explicit OutSizes(const ssi_layout &L)
+      : sigma((size_t)L.n_lags * L.sigma_per_lag), count((size_t)L.n_lags * L.n_orders),
+        poles((size_t)L.n_lags * L.pole_cap), phi((size_t)L.n_lags * L.pole_cap * L.l * 2) {}
+};
+
+}  // namespace
+
+extern "C" {
+
+ssi_status ssi_result_fetch(ssi_ctx *c, const ssi_params *p, int32_t l, const ssi_output *out,
+                            ssi_result **res) {
+  if (!c || !p || !out || !res) return fail(SSI_EINVAL, "ssi_result_fetch: NULL argument");
+  if (!out->sigma || !out->count || !out->f || !out->xi || !out->mu || !out->phi || !out->flags)
+    return fail(SSI_EINVAL, "ssi_result_fetch: NULL output buffer");
+  ssi_layout lay;
+  ssi_status s = layout_of(p, l, &lay);
+  if (s != SSI_OK) return s;
+  DeviceGuard g(c->device);
+  // the identification's own status; its result is copied in every case so
+  // that per-order flags can be read after SSI_ENOCONV
+  const ssi_status run = ssi_synchronize(c);
+  const std::string run_msg = run == SSI_OK ? std::string() : g_last_error;
+  ssi_result *r = new ssi_result();
+  r->lay = lay;
+  r->nmin = p->order_min;
+  r->step = p->order_step;
+  for (int o = 0; o <= lay.n_orders; ++o) r->offs.push_back(ssi_pole_offset(p, o));
+  const OutSizes z(lay);
+  r->sigma.resize(z.sigma);
+  r->count.resize(z.count);
+  r->flags.resize(z.count);
+  r->f.resize(z.poles);
+  r->xi.resize(z.poles);
+  r->mu.resize(2 * z.poles);
+  r->phi.resize(z.phi);
+  struct { void *dst; const void *src; size_t bytes; } cp[] = {
+      {r->sigma.data(), out->sigma, z.sigma * sizeof(double)},
+      {r->count.data(), out->count, z.count * sizeof(int32_t)},
+      {r->flags.data(), out->flags, z.count * sizeof(int32_t)},
+      {r->f.data(), out->f, z.poles * sizeof(double)},
+      {r->xi.data(), out->xi, z.poles * sizeof(double)},
+      {r->mu.data(), out->mu, 2 * z.poles * sizeof(double)},
+      {r->phi.data(), out->phi, z.phi * sizeof(float)}};
+  for (auto &x : cp) {
+    const hipError_t e = hipMemcpy(x.dst, x.src, x.bytes, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) {
+      delete r;
+      return hip_fail(e, "ssi_result_fetch: copy to host");
+    }
+  }
+  *res = r;
+  if (run != SSI_OK) g_last_error = run_msg;
+  return run;
+}
+
+ssi_status ssi_identify_result(ssi_ctx *c, const float *y, int32_t l, int64_t n, int64_t ldy,
+                               const ssi_params *p, ssi_result **res) {
+  if (!c || !y || !p || !res) return fail(SSI_EINVAL, "ssi_identify_result: NULL argument");
+  ssi_status s = ssi_validate(p, l, n);
+  if (s != SSI_OK) return s;
+  ssi_layout lay;
+  s = layout_of(p, l, &lay);
+  if (s != SSI_OK) return s;
+  const OutSizes z(lay);
+  Arena probe;
+  probe.take<double>(z.sigma);
+  probe.take<int32_t>(z.count);
+  probe.take<int32_t>(z.count);
+  probe.take<double>(z.poles);
+  probe.take<double>(z.poles);
+  probe.take<double>(2 * z.poles);
+  probe.take<float>(z.phi);
+  DeviceGuard g(c->device);
+  if (probe.off > c->obuf_cap) {
+    // outputs of earlier calls may still be read by queued work or graphs
+    drain(c);
+    drop_graphs(c);
+    dev_free(c, c->obuf);
+    c->obuf = nullptr;
+    c->obuf_cap = 0;
+    const hipError_t e = dev_alloc(c, &c->obuf, probe.off);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(SSI_ENOMEM, "output buffers of %zu bytes could not be allocated", probe.off);
+    }
+    c->obuf_cap = probe.off;
+  }
+  Arena a{c->obuf, 0};
+  ssi_output out;
+  out.sigma = a.take<double>(z.sigma);
+  out.count = a.take<int32_t>(z.count);
+  out.flags = a.take<int32_t>(z.count);
+  out.f = a.take<double>(z.poles);
+  out.xi = a.take<double>(z.poles);
+  out.mu = a.take<double>(2 * z.poles);
+  out.phi = a.take<float>(z.phi);
+  s = ssi_identify(c, y, l, n, ldy, p, &out);
+  if (s != SSI_OK) return s;
+  return ssi_result_fetch(c, p, l, &out, res);
+}
+
+ssi_status ssi_result_dims(const ssi_result *r, int32_t *n_lags, int32_t *n_orders, int32_t *l) {
+  if (!r) return fail(SSI_EINVAL, "ssi_result_dims: NULL result");
+  if (n_lags) *n_lags = r->lay.n_lags;
+  if (n_orders) *n_orders = r->lay.n_orders;
+  if (l) *l = r->lay.l;
+  return SSI_OK;
+}
+
+ssi_status ssi_result_poles(const ssi_result *r, int32_t lag_i, int32_t order_i, int32_t *order,
+                            int32_t *n_poles, const double **f_hz, const double **zeta,
+                            const double **mu_reim, const float **phi_reim, int32_t *flag) {
+  if (!r) return fail(SSI_EINVAL, "ssi_result_poles: NULL result");
+  if (lag_i < 0 || lag_i >= r->lay.n_lags || order_i < 0 || order_i >= r->lay.n_orders)
+    return fail(SSI_EINVAL, "ssi_result_poles: lag %d / order %d out of range", lag_i, order_i);
+  const size_t slot = (size_t)lag_i * r->lay.pole_cap + r->offs[order_i];
+  const size_t oi = (size_t)lag_i * r->lay.n_orders + order_i;
+  if (order) *order = r->nmin + order_i * r->step;
+  if (n_poles) *n_poles = r->count[oi];
+  if (f_hz) *f_hz = r->f.data() + slot;
+  if (zeta) *zeta = r->xi.data() + slot;
+  if (mu_reim) *mu_reim = r->mu.data() + 2 * slot;
+  if (phi_reim) *phi_reim = r->phi.data() + slot * r->lay.l * 2;
+  if (flag) *flag = r->flags[oi];
+  return SSI_OK;
+}
+
+ssi_status ssi_result_singular_values(const ssi_result *r, int32_t lag_i, int32_t *n,
+                                      const double **sigma) {
+  if (!r) return fail(SSI_EINVAL, "ssi_result_singular_values: NULL result");
+  if (lag_i < 0 || lag_i >= r->lay.n_lags)
+    return fail(SSI_EINVAL, "ssi_result_singular_values: lag %d out of range", lag_i);
+  if (n) *n = r->lay.sigma_per_lag;
+  if (sigma) *sigma = r->sigma.data() + (size_t)lag_i * r->lay.sigma_per_lag;
+  return SSI_OK;
+}
+
+void ssi_result_free(ssi_result *r) { delete r; }
 
 }  // extern "C"

@@ -436,12 +436,17 @@ correlate_b6(const uint16_t *__restrict__ planes, int l, int64_t n, int lp, int6
   }
 }
 
-// R[j-1][a][b] = (float)(sum_split partial[split][a L + j - 1][b] / n)
+// R[j-1][a][b] = (float)(sum_split partial[split][a L + j - 1][b] / n).
+// A non-finite sample makes some correlation non-finite (every sample enters
+// at least one product, and NaN or Inf times anything stays non-finite or
+// gives NaN), so checking the results here flags such a record without a
+// separate pass over it.
 __global__ void __launch_bounds__(256)
 correlate_reduce(const double *__restrict__ partial, int l, int L, int splits,
-                 double inv_n, float *__restrict__ r) {
+                 double inv_n, float *__restrict__ r, int *__restrict__ status) {
   const int64_t total = (int64_t)l * L * l;
   const int64_t plane = total;
+  int bad = 0;
   for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
        idx += (int64_t)gridDim.x * blockDim.x) {
     const int b = (int)(idx % l);
@@ -451,8 +456,11 @@ correlate_reduce(const double *__restrict__ partial, int l, int L, int splits,
     const int64_t src = ((int64_t)a * L + j) * l + b;
     double s = 0.0;
     for (int sp = 0; sp < splits; ++sp) s += partial[sp * plane + src];
-    r[idx] = (float)(s * inv_n);
+    const float v = (float)(s * inv_n);
+    bad |= !isfinite(v);
+    r[idx] = v;
   }
+  if (__any(bad) && (threadIdx.x & 63) == 0) atomicOr(status, ssi::kStatusNonFinite);
 }
 
 // ------------------------------------------------------------------ launch
@@ -549,21 +557,22 @@ hipError_t launch_correlate_mfma(const CorrPlan &p, const float *y, int l, int64
 }
 
 hipError_t launch_correlate_reduce(const CorrPlan &p, int l, int64_t n, int L,
-                                   const double *partial, float *r, hipStream_t st) {
+                                   const double *partial, float *r, int *status, hipStream_t st) {
   const int64_t total = (int64_t)l * L * l;
   int blocks = (int)ceil_div<int64_t>(total, 256);
   if (blocks > 65535 * 8) blocks = 65535 * 8;
   hipLaunchKernelGGL(correlate_reduce, dim3(blocks), dim3(256), 0, st, partial, l, L,
-                     p.splits, 1.0 / (double)n, r);
+                     p.splits, 1.0 / (double)n, r, status);
   return hipGetLastError();
 }
 
 hipError_t launch_correlate(const CorrPlan &p, const float *y, int l, int64_t n, int64_t ldy,
-                            int L, double *partial, uint16_t *planes, float *r, hipStream_t st) {
+                            int L, double *partial, uint16_t *planes, float *r, int *status,
+                            hipStream_t st) {
   hipError_t e = launch_correlate_split(p, y, l, n, ldy, planes, st);
   if (e == hipSuccess) e = launch_correlate_mfma(p, y, l, n, ldy, L, partial, planes, st);
   if (e != hipSuccess) return e;
-  return launch_correlate_reduce(p, l, n, L, partial, r, st);
+  return launch_correlate_reduce(p, l, n, L, partial, r, status, st);
 }
 
 }  // namespace ssi

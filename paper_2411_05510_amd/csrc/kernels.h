@@ -9,6 +9,16 @@
 
 namespace ssi {
 
+// Bits of the context's device status word (kernels OR them in; the host
+// reads and clears the word in ssi_synchronize).
+enum : int {
+  kStatusChol = 1,          // a Cholesky factorization broke down
+  kStatusPoleWait = 4,      // a pole's wait for its order's eigenvalues timed out
+  kStatusEigLimit = 8,      // an order's QR iteration hit its sweep limit
+  kStatusClaimCap = 16,     // the eigen-analysis claim loop hit its pass cap
+  kStatusNonFinite = 256    // the record held non-finite samples
+};
+
 // ---- correlations (correlate.hip)
 struct CorrPlan {
   int grid_rows, grid_cols, splits;
@@ -26,14 +36,17 @@ struct CorrPlan {
 // fit two workgroups per CU.
 CorrPlan plan_correlate(int l, int64_t n, int L, int num_cus, int mode);
 hipError_t launch_correlate(const CorrPlan &p, const float *y, int l, int64_t n, int64_t ldy,
-                            int L, double *partial, uint16_t *planes, float *r, hipStream_t st);
+                            int L, double *partial, uint16_t *planes, float *r, int *status,
+                            hipStream_t st);
 // BF16x6: the record's three BF16 parts into planes (no-op for FP32)
 hipError_t launch_correlate_split(const CorrPlan &p, const float *y, int l, int64_t n,
                                   int64_t ldy, uint16_t *planes, hipStream_t st);
 hipError_t launch_correlate_mfma(const CorrPlan &p, const float *y, int l, int64_t n, int64_t ldy,
                                  int L, double *partial, const uint16_t *planes, hipStream_t st);
+// Sets kStatusNonFinite in *status when a correlation is not finite (a
+// non-finite sample makes at least one of them so).
 hipError_t launch_correlate_reduce(const CorrPlan &p, int l, int64_t n, int L,
-                                   const double *partial, float *r, hipStream_t st);
+                                   const double *partial, float *r, int *status, hipStream_t st);
 
 // ---- Toeplitz (toeplitz.hip)
 hipError_t launch_toeplitz(const float *r, int l, int jb, float *t, int64_t ldt,
@@ -123,6 +136,7 @@ struct ModalArgs {
   int *queue, *done;            // work counters and per-order flags of the eig launch
   int *status;                  // context status word
   int eig_grid;                 // workgroups of the eigen-analysis launch, 0: one per CU
+  int sweeps_per_row;           // QR sweep limit per order: sweeps_per_row * max(10, n)
   int32_t *count, *flags;       // outputs of this lag
   double *f, *xi, *mu;
   float *phi;

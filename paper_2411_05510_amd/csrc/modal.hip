@@ -799,7 +799,7 @@ template <bool LDS>
 SSI_DEV void francis_order(int o, double *A, const double *__restrict__ hbuf, int nmin, int step,
                            double *__restrict__ evbuf, int *__restrict__ npole,
                            int *__restrict__ pidx, int *__restrict__ flags, int *red,
-                           int &small_ok) {
+                           int &small_ok, int sweeps_per_row, int *__restrict__ status) {
   const OrderGeo geo = order_geo(o, nmin, step);
   const int n = geo.n;
   const double *Hin = hbuf + geo.sq;
@@ -829,13 +829,19 @@ SSI_DEV void francis_order(int o, double *A, const double *__restrict__ hbuf, in
     }
   }
   for (int i = t; i < 2 * kRing; i += kFT) A[psz + i] = 0.0;
+  // a non-finite entry would never deflate: fail the order at once instead
+  // of running to the iteration limit
+  int nonfinite = 0;
+  for (int i = t; i < psz; i += kFT) nonfinite |= !isfinite(A[i]);
   __syncthreads();
+  nonfinite = block_max_int(nonfinite, red);
 
   const double eps = 2.220446049250313e-16;
   int hi = n - 1, iter = 0, total = 0;
-  const int itmax = 30 * max(10, n);
-  bool failed = false;
-  while (hi >= 0) {
+  // sweeps_per_row * max(10, n) QR sweeps in all (LAPACK's xLAHQR allows 30)
+  const int itmax = sweeps_per_row * max(10, n);
+  bool failed = nonfinite != 0;
+  while (hi >= 0 && !failed) {
     // deflation: largest l in (0, hi] with a negligible subdiagonal entry
     int cand = 0;
     for (int i = hi - t; i >= 1; i -= kFT) {
@@ -987,6 +993,7 @@ SSI_DEV void francis_order(int o, double *A, const double *__restrict__ hbuf, in
     }
     npole[o] = cnt;
     flags[o] = failed ? 1 : 0;
+    if (failed) atomicOr(status, ssi::kStatusEigLimit);
   }
 }
 
@@ -1314,7 +1321,7 @@ SSI_DEV void vec_pole(int o, int j, const double *__restrict__ hbuf,
 // first, waits for its order's flag and computes the pole's vector and mode
 // shape.  Poles of small orders therefore run beside the QR iterations of the
 // large ones.  The wait is bounded: a flag not seen within kEigSpinLimit
-// polls sets bit 4 of the status word and the pole is skipped.
+// polls sets bit kStatusPoleWait of the status word and the pole is skipped.
 namespace {
 constexpr int kEigGrid = 256;                       // workgroups (one per CU)
 constexpr int kVecLds = 5 * kNR;                    // per-wave LDS of a pole item (doubles)
@@ -1339,7 +1346,7 @@ eig_persistent_kernel(const double *__restrict__ hbuf, const double *__restrict_
                       double *__restrict__ vscr, int64_t vstride, double *__restrict__ tf,
                       double *__restrict__ txi, double *__restrict__ tmu,
                       double *__restrict__ tphi, int *__restrict__ queue, int *__restrict__ done,
-                      int *__restrict__ status) {
+                      int *__restrict__ status, int sweeps_per_row) {
   extern __shared__ double lds_h[];
   __shared__ int red[kFT / 64];
   __shared__ int small_ok, item;
@@ -1351,18 +1358,26 @@ eig_persistent_kernel(const double *__restrict__ hbuf, const double *__restrict_
   // claim and the publish as two separate thread-0 regions around the back
   // edge, the compiler may let lanes 1..63 of wave 0 re-enter the body
   // without thread 0 and re-read the old item.
+  // Every pass claims a fresh counter value, so a workgroup makes at most
+  // n_orders + 1 claims; the pass count is capped at that all the same, and
+  // a workgroup that reaches the cap sets status bit kStatusClaimCap and stops.
   if (t == 0) item = atomicAdd(&queue[0], 1);
   __syncthreads();
-  for (;;) {
+  for (int pass = 0;; ++pass) {
     const int it = __builtin_amdgcn_readfirstlane(item);
     __syncthreads();                                // every wave has read item
     if (it >= n_orders) break;
+    if (pass > n_orders) {
+      if (t == 0) atomicOr(status, ssi::kStatusClaimCap);
+      break;
+    }
     const int o = n_orders - 1 - it;
     if (nmin + o * step <= kLdsMaxN)
-      francis_order<true>(o, lds_h, hbuf, nmin, step, evbuf, npole, pidx, flags, red, small_ok);
+      francis_order<true>(o, lds_h, hbuf, nmin, step, evbuf, npole, pidx, flags, red, small_ok,
+                          sweeps_per_row, status);
     else
       francis_order<false>(o, gscr + (size_t)o * gstride, hbuf, nmin, step, evbuf, npole, pidx,
-                           flags, red, small_ok);
+                           flags, red, small_ok, sweeps_per_row, status);
     __threadfence();
     __syncthreads();
     if (t == 0) {
@@ -1397,7 +1412,7 @@ eig_persistent_kernel(const double *__restrict__ hbuf, const double *__restrict_
       while (!(ready = __hip_atomic_load(&done[o], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT)) &&
              ++spins < kEigSpinLimit)
         __builtin_amdgcn_s_sleep(8);
-      if (!ready) atomicOr(status, 4);
+      if (!ready) atomicOr(status, ssi::kStatusPoleWait);
     }
     ready = __builtin_amdgcn_readfirstlane(__shfl(ready, 0, 64));
     if (!ready) continue;
@@ -1543,7 +1558,8 @@ hipError_t launch_modal(const ModalArgs &a, hipStream_t st) {
                      sizeof(double) * kLdsDoubles, st, a.hbuf, a.vref, a.taus, a.u, a.ldu,
                      a.nmin, a.step, no, a.l,
                      a.fs, a.gscr, s.francis_glb, a.evbuf, a.npole, a.pidx, a.flags_tmp, a.vscr,
-                     s.vec_stride, a.tf, a.txi, a.tmu, a.tphi, a.queue, a.done, a.status);
+                     s.vec_stride, a.tf, a.txi, a.tmu, a.tphi, a.queue, a.done, a.status,
+                     a.sweeps_per_row);
   hipLaunchKernelGGL(sort_kernel, dim3(no), dim3(256), 0, st, a.nmin, a.step, a.l, a.npole,
                      a.flags_tmp, a.tf, a.txi, a.tmu, a.tphi, a.count, a.flags, a.f, a.xi, a.mu,
                      a.phi);

@@ -430,6 +430,9 @@ ssi_status ssi_server_submit(ssi_server *S, const float *y, int32_t l, int64_t n
   if (ldy < n) return srv_fail(SSI_EINVAL, "ssi_server_submit: ldy < n");
   ssi_status s = ssi_validate(p, l, n);
   if (s != SSI_OK) return srv_fail(s, "%s", ssi_last_error());
+  if (p->omega)
+    return srv_fail(SSI_EINVAL, "ssi_server_submit: requests draw their sketch from the seed "
+                                "(omega must be NULL)");
   auto r = std::make_shared<Request>();
   r->params = *p;
   r->lags.assign(p->lags, p->lags + p->n_lags);

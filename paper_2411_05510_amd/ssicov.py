@@ -35,6 +35,8 @@ EXPORTED = (
     "ssi_server_submit", "ssi_server_poll", "ssi_server_wait", "ssi_server_result",
     "ssi_server_release", "ssi_server_get_stats", "ssi_server_last_error", "ssi_stability",
     "ssi_stability_noalloc", "ssi_stability_noalloc_max_slots",
+    "ssi_set_eig_max_sweeps", "ssi_set_allocator", "ssi_identify_result", "ssi_result_fetch",
+    "ssi_result_dims", "ssi_result_poles", "ssi_result_singular_values", "ssi_result_free",
 )
 
 POLE_HC, POLE_STABLE_ORDER, POLE_STABLE_LAG, POLE_STABLE = 1, 2, 4, 8
@@ -63,6 +65,8 @@ class _Params(ctypes.Structure):
         ("power_iters", ctypes.c_int32),
         ("seed", ctypes.c_uint64),
         ("prec", ctypes.c_int32),
+        ("omega", ctypes.c_void_p),
+        ("omega_ld", ctypes.c_int64),
     ]
 
 
@@ -105,6 +109,9 @@ class _Output(ctypes.Structure):
     _fields_ = [(n, ctypes.c_void_p) for n in
                 ("sigma", "count", "f", "xi", "mu", "phi", "flags")]
 
+
+_ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+_RELEASE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
 
 _lib = None
 
@@ -170,6 +177,24 @@ def lib() -> ctypes.CDLL:
                                        ctypes.POINTER(_StabilityParams), vp, vp, vp],
                                       ctypes.c_int),
             "ssi_stability_noalloc_max_slots": ([], i64),
+            "ssi_set_eig_max_sweeps": ([vp, i32], ctypes.c_int),
+            "ssi_set_allocator": ([vp, _ALLOC_FN, _RELEASE_FN, vp], ctypes.c_int),
+            "ssi_identify_result": ([vp, vp, i32, i64, i64, P, ctypes.POINTER(vp)],
+                                    ctypes.c_int),
+            "ssi_result_fetch": ([vp, P, i32, ctypes.POINTER(_Output), ctypes.POINTER(vp)],
+                                 ctypes.c_int),
+            "ssi_result_dims": ([vp, ctypes.POINTER(i32), ctypes.POINTER(i32),
+                                 ctypes.POINTER(i32)], ctypes.c_int),
+            "ssi_result_poles": ([vp, i32, i32, ctypes.POINTER(i32), ctypes.POINTER(i32),
+                                  ctypes.POINTER(ctypes.POINTER(ctypes.c_double)),
+                                  ctypes.POINTER(ctypes.POINTER(ctypes.c_double)),
+                                  ctypes.POINTER(ctypes.POINTER(ctypes.c_double)),
+                                  ctypes.POINTER(ctypes.POINTER(ctypes.c_float)),
+                                  ctypes.POINTER(i32)], ctypes.c_int),
+            "ssi_result_singular_values": ([vp, i32, ctypes.POINTER(i32),
+                                            ctypes.POINTER(ctypes.POINTER(ctypes.c_double))],
+                                           ctypes.c_int),
+            "ssi_result_free": ([vp], None),
         }
         for name, (args, res) in sig.items():
             fn = getattr(L, name)
@@ -204,13 +229,16 @@ class Params:
     power_iters: int = 0
     seed: int = 0
     prec: int = PREC_FP32
+    omega: object = None        # optional caller sketch: device tensor (m_max, k + p) float32
 
     def c(self) -> _Params:
         arr = (ctypes.c_int32 * len(self.lags))(*[int(v) for v in self.lags])
+        om = None if self.omega is None else _ptr(self.omega)
+        ld = 0 if self.omega is None else int(self.omega.stride(0))
         p = _Params(float(self.fs), arr, len(self.lags), int(self.order_min),
                     int(self.order_max), int(self.order_step), int(self.svd),
                     int(self.rank), int(self.oversample), int(self.power_iters),
-                    int(self.seed) & 0xFFFFFFFFFFFFFFFF, int(self.prec))
+                    int(self.seed) & 0xFFFFFFFFFFFFFFFF, int(self.prec), om, ld)
         p._keep = arr  # keep the lag array alive with the struct
         return p
 
@@ -311,6 +339,31 @@ class Context:
 
     def set_autotune(self, enable: bool) -> None:
         _check(lib().ssi_set_autotune(self._h, 1 if enable else 0))
+
+    def set_eig_max_sweeps(self, sweeps_per_row: int) -> None:
+        _check(lib().ssi_set_eig_max_sweeps(self._h, sweeps_per_row))
+
+    def use_torch_allocator(self, enable: bool = True) -> None:
+        """Workspace from torch's caching allocator (ssi_set_allocator)."""
+        import torch
+        if not enable:
+            _check(lib().ssi_set_allocator(self._h, _ALLOC_FN(), _RELEASE_FN(), None))
+            self._alloc_cbs = None
+            return
+        dev, stream = self.device, self._stream
+
+        def _alloc(nbytes, _user):
+            try:
+                return torch.cuda.caching_allocator_alloc(int(nbytes), dev, stream)
+            except Exception:
+                return None
+
+        def _release(ptr, _user):
+            torch.cuda.caching_allocator_delete(ptr)
+
+        cbs = (_ALLOC_FN(_alloc), _RELEASE_FN(_release))
+        _check(lib().ssi_set_allocator(self._h, cbs[0], cbs[1], None))
+        self._alloc_cbs = cbs          # the callbacks must outlive the context's use of them
 
     def set_corr_mode(self, mode: int) -> None:
         """CORR_FP32 or CORR_BF16X6 (the default) for the correlation products."""
@@ -426,7 +479,8 @@ class Context:
         return out
 
     def identify(self, y, p: Params, out: Optional["Output"] = None) -> "Output":
-        """Enqueue the whole identification of the device record y (l, n)."""
+        """Enqueue the whole identification of the record y (l, n): a device
+        tensor, or a host (CPU) tensor that the library copies in."""
         l, n = y.shape
         if out is None:
             out = self.alloc_output(p, l, n)
@@ -435,6 +489,40 @@ class Context:
         _check(lib().ssi_identify(self._h, _ptr(y), l, n, y.stride(0), ctypes.byref(cp),
                                   ctypes.byref(co)))
         return out
+
+    def identify_result(self, y, p: Params) -> "Result":
+        """Synchronous identification (ssi_identify_result) into a host result.
+        y: device tensor, host tensor or numpy array (l, n) float32."""
+        if isinstance(y, np.ndarray):
+            y = np.ascontiguousarray(y, dtype=np.float32)
+            l, n = y.shape
+            ptr, ld = y.ctypes.data, y.strides[0] // 4
+        else:
+            l, n = y.shape
+            ptr, ld = _ptr(y), y.stride(0)
+        cp = p.c()
+        h = ctypes.c_void_p()
+        st = lib().ssi_identify_result(self._h, ptr, l, n, ld, ctypes.byref(cp), ctypes.byref(h))
+        res = Result(h) if h.value else None
+        if st != SSI_OK:
+            err = SSIError(st, lib().ssi_last_error().decode())
+            err.result = res
+            raise err
+        return res
+
+    def fetch(self, out: "Output", l: int) -> "Result":
+        """Host result of the device outputs (ssi_result_fetch)."""
+        cp = out.params.c()
+        co = out.c()
+        h = ctypes.c_void_p()
+        st = lib().ssi_result_fetch(self._h, ctypes.byref(cp), l, ctypes.byref(co),
+                                    ctypes.byref(h))
+        res = Result(h) if h.value else None
+        if st != SSI_OK:
+            err = SSIError(st, lib().ssi_last_error().decode())
+            err.result = res
+            raise err
+        return res
 
 
 @dataclasses.dataclass
@@ -469,6 +557,55 @@ class Output:
             "phi": phi[..., 0] + 1j * phi[..., 1],
             "flag": int(self.flags[lag_index, order_index].item()),
         }
+
+
+class Result:
+    """Host result of one identification (ssi_result_* accessors)."""
+
+    def __init__(self, handle: ctypes.c_void_p):
+        self._h = handle
+
+    def close(self) -> None:
+        if getattr(self, "_h", None):
+            lib().ssi_result_free(self._h)
+            self._h = None
+
+    def __del__(self):  # pragma: no cover
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def dims(self) -> dict:
+        a, b, c = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        _check(lib().ssi_result_dims(self._h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
+        return {"n_lags": a.value, "n_orders": b.value, "l": c.value}
+
+    def poles(self, lag_index: int, order_index: int) -> dict:
+        order, cnt, flag = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        pd = [ctypes.POINTER(ctypes.c_double)() for _ in range(3)]
+        pf = ctypes.POINTER(ctypes.c_float)()
+        _check(lib().ssi_result_poles(self._h, lag_index, order_index, ctypes.byref(order),
+                                      ctypes.byref(cnt), *[ctypes.byref(x) for x in pd],
+                                      ctypes.byref(pf), ctypes.byref(flag)))
+        k, l = cnt.value, self.dims()["l"]
+
+        def arr(ptr, n, dt):
+            return np.ctypeslib.as_array(ptr, shape=(n,)).astype(dt).copy() if n else \
+                np.zeros(0, dt)
+
+        mu = arr(pd[2], 2 * k, np.float64).reshape(k, 2)
+        phi = arr(pf, 2 * k * l, np.float64).reshape(k, l, 2)
+        return {"order": order.value, "f": arr(pd[0], k, np.float64),
+                "xi": arr(pd[1], k, np.float64), "mu": mu[:, 0] + 1j * mu[:, 1],
+                "phi": phi[..., 0] + 1j * phi[..., 1], "flag": flag.value}
+
+    def singular_values(self, lag_index: int) -> np.ndarray:
+        n = ctypes.c_int32()
+        p = ctypes.POINTER(ctypes.c_double)()
+        _check(lib().ssi_result_singular_values(self._h, lag_index, ctypes.byref(n),
+                                                ctypes.byref(p)))
+        return np.ctypeslib.as_array(p, shape=(n.value,)).copy()
 
 
 # --------------------------------------------------------------- serving

@@ -84,3 +84,27 @@ def test_create_without_gpu_reports_device_error():
     st = S.lib().ssi_create(0, None, ctypes.byref(h))
     assert st == S.SSI_EDEVICE
     assert S.lib().ssi_last_error()
+
+
+def test_validate_checks_the_caller_sketch():
+    torch = pytest.importorskip("torch")
+    om = torch.zeros((10800, 230), dtype=torch.float32)        # only its stride is read here
+    S.validate(_p(omega=om), 180, 180000)
+    with pytest.raises(S.SSIError) as ei:                      # ld < k + p
+        S.validate(_p(omega=torch.zeros((10800, 200))), 180, 180000)
+    assert ei.value.status == S.SSI_EINVAL
+    with pytest.raises(S.SSIError) as ei:                      # full SVD takes no sketch
+        S.validate(_p(omega=om, lags=[4], svd=S.SVD_FULL, order_max=20, rank=20), 180, 180000)
+    assert ei.value.status == S.SSI_EINVAL
+
+
+def test_result_accessors_reject_null():
+    lib = S.lib()
+    n = ctypes.c_int32()
+    assert lib.ssi_result_dims(None, ctypes.byref(n), None, None) == S.SSI_EINVAL
+    assert lib.ssi_result_poles(None, 0, 0, None, None, None, None, None, None,
+                                None) == S.SSI_EINVAL
+    assert lib.ssi_result_singular_values(None, 0, None, None) == S.SSI_EINVAL
+    lib.ssi_result_free(None)
+    assert lib.ssi_set_eig_max_sweeps(None, 3) == S.SSI_EINVAL
+    assert b"NULL" in lib.ssi_last_error()

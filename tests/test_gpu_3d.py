@@ -136,16 +136,40 @@ def test_autotune_records_choice():
     ctx.close()
 
 
-def test_bridge_3d_sweep_graph():
-    """lags 20..100 step 10 of the 180-channel record in one graph on three
-    lag streams; lags 20 and 100 against the checker (physical poles, FP32
-    gates)."""
+@pytest.fixture(scope="module")
+def bridge3d():
+    """The 180-channel record and the FP64 checker's identification at lags
+    20 and 100 (the smallest and the largest of the sweep)."""
     wl = synth.WORKLOADS["bridge-180ch-3d"]
     sysm, y = synth.make_record(wl)
+    r_stack = oracle.correlations(y, 2 * wl.lags[-1] - 1)
+    ell = wl.rank + wl.oversample
+    refs = {}
+    for li in (0, len(wl.lags) - 1):
+        t = oracle.toeplitz(r_stack, wl.lags[li])
+        u, s = oracle.rsvd(t, wl.rank, wl.oversample, wl.power_iters,
+                           oracle.sketch(wl.sketch_seed, t.shape[0], ell, li))
+        del t
+        refs[li] = (s, oracle.modal(u, s, wl.l, wl.orders, wl.fs))
+    return wl, sysm, y, refs
+
+
+# precision of the range-finder products: (f rel, xi abs, MAC, sigma rel) gates
+GATES_3D = {"fp32": (1e-5, 1e-4, 0.9999, 1e-4), "bf16x3": (1e-3, 2e-3, 0.99, 1e-4)}
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+def test_bridge_3d_sweep_graph(bridge3d, prec):
+    """lags 20..100 step 10 of the 180-channel record in one graph on three
+    lag streams; lags 20 and 100 against the checker on physical poles at
+    every order, at the FP32 gates for FP32 products and at the
+    reduced-precision gates for the split-BF16 range finder."""
+    from paper_2411_05510_amd import ssicov
+    wl, sysm, y, refs = bridge3d
     ctx = _ctx()
     ctx.set_lag_streams(3)
     ctx.set_graphs(True)
-    p = _params(wl)
+    p = _params(wl, prec={"fp32": ssicov.PREC_FP32, "bf16x3": ssicov.PREC_BF16X3}[prec])
     yd = _dev(y)
     out = ctx.alloc_output(p, wl.l, wl.n)
     ctx.identify(yd, p, out)        # eager + capture
@@ -159,19 +183,12 @@ def test_bridge_3d_sweep_graph():
     ctx.set_graphs(False)
     ctx.close()
 
-    r_stack = oracle.correlations(y, 2 * wl.lags[-1] - 1)
-    ell = wl.rank + wl.oversample
+    f_tol, xi_tol, mac_min, s_tol = GATES_3D[prec]
     worst = {"f": 0.0, "xi": 0.0, "mac": 1.0, "n": 0}
-    for li in (0, len(wl.lags) - 1):
-        jb = wl.lags[li]
-        t = oracle.toeplitz(r_stack, jb)
-        u, s = oracle.rsvd(t, wl.rank, wl.oversample, wl.power_iters,
-                           oracle.sketch(wl.sketch_seed, t.shape[0], ell, li))
-        del t
-        res = oracle.modal(u, s, wl.l, wl.orders, wl.fs)
+    for li, (s, res) in refs.items():
         sig = out.sigma[li].cpu().numpy()
         keep = s >= 1e-3 * s[0]
-        assert (np.abs(sig[keep] - s[keep]) / s[keep]).max() <= 1e-4
+        assert (np.abs(sig[keep] - s[keep]) / s[keep]).max() <= s_tol
         for oi, ref in enumerate(res):
             g = out.poles(li, oi)
             assert g["flag"] == 0
@@ -186,9 +203,9 @@ def test_bridge_3d_sweep_graph():
                 worst["xi"] = max(worst["xi"], abs(g["xi"][j] - ref.xi[i]))
                 worst["mac"] = min(worst["mac"], mac(g["phi"][j], ref.phi[i]))
                 worst["n"] += 1
-    print(f"bridge 3D lags 20 and 100: {worst['n']} physical poles, max f rel "
+    print(f"bridge 3D {prec} lags 20 and 100: {worst['n']} physical poles, max f rel "
           f"{worst['f']:.2e}, max xi abs {worst['xi']:.2e}, min MAC {worst['mac']:.8f}")
     assert worst["n"] > 0
-    assert worst["f"] <= 1e-5
-    assert worst["xi"] <= 1e-4
-    assert worst["mac"] >= 0.9999
+    assert worst["f"] <= f_tol
+    assert worst["xi"] <= xi_tol
+    assert worst["mac"] >= mac_min

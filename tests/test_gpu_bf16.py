@@ -12,9 +12,10 @@ everything after stay FP64.  Gates:
   rounding of 2^-9 per operand; the exact projection turns that into a
   perturbation of the basis only), and the leading subspace within the
   same error scaled by the inverse relative gap;
-* the whole identification of the 180-channel record: physical poles within
-  f rel 1e-3, damping abs 2e-3 and MAC 0.99 of the FP64 checker, at the
-  orders whose singular vectors the rounded operands resolve.
+* the whole identification of the 180-channel record with the split-BF16
+  range finder: physical poles within f rel 1e-3, damping abs 2e-3 and MAC
+  0.99 of the FP64 checker at every order; plain BF16 is held to the
+  accuracy it is documented to have (it is not offered at equal accuracy).
 """
 import numpy as np
 import pytest
@@ -102,19 +103,12 @@ def bridge():
     return wl, sysm, y, res
 
 
-@pytest.mark.parametrize("mode,resolution", [("bf16", 2.0 ** -9), ("bf16x3", 2.0 ** -17)])
-def test_identify_bridge_reduced_precision(ctx, bridge, mode, resolution):
-    """The 180-channel record with reduced-precision range-finder products:
-    physical poles of the FP64 checker (same record, same Philox sketch)
-    within f rel 1e-3, damping abs 2e-3 and MAC 0.99.  The gate covers the
-    orders n whose n-th singular value is above the relative resolution of
-    the operands (2^-9 sigma_1 for BF16, 2^-17 for the split hi + lo form):
-    below it the n-th singular vector is not determined by the rounded T, and
-    the poles that depend on it move (plain BF16 on this record: orders 86 and
-    up, by up to 6e-3)."""
+def _bridge_errors(ctx, bridge, prec):
+    """Per-order worst errors of the physical poles of the 180-channel record
+    identified with range-finder products `prec`, against the FP64 checker
+    (same record, same Philox sketch)."""
     from paper_2411_05510_amd import ssicov
     wl, sysm, y, res = bridge
-    prec = {"bf16": ssicov.PREC_BF16, "bf16x3": ssicov.PREC_BF16X3}[mode]
     p = ssicov.Params(fs=wl.fs, lags=list(wl.lags), order_min=wl.order_min,
                       order_max=wl.order_max, order_step=wl.order_step,
                       svd=ssicov.SVD_RANDOMIZED, rank=wl.rank, oversample=wl.oversample,
@@ -123,15 +117,11 @@ def test_identify_bridge_reduced_precision(ctx, bridge, mode, resolution):
     ctx.synchronize()
     sig = out.sigma[0].cpu().numpy()
     keep = res.sigma >= 1e-2 * res.sigma[0]
-    srel = np.abs(sig[keep] - res.sigma[keep]) / res.sigma[keep]
-    assert srel.max() <= 1e-6
-    ef, ex, em, gated_orders = [], [], [], 0
+    srel = float((np.abs(sig[keep] - res.sigma[keep]) / res.sigma[keep]).max())
+    per_order = {}
     for oi, n in enumerate(wl.orders):
         g = out.poles(0, oi)
         assert g["flag"] == 0
-        if res.sigma[n - 1] < resolution * res.sigma[0]:
-            continue
-        gated_orders += 1
         ref = res.poles[oi]
         for r, fr in enumerate(sysm.freqs):
             if len(ref) == 0:
@@ -140,13 +130,52 @@ def test_identify_bridge_reduced_precision(ctx, bridge, mode, resolution):
             if abs(ref.f[i] - fr) / fr >= 0.01 or mac(ref.phi[i], sysm.shapes[:, r]) < 0.9:
                 continue
             j = int(np.argmin(np.abs(g["f"] - ref.f[i])))
-            ef.append(abs(g["f"][j] - ref.f[i]) / ref.f[i])
-            ex.append(abs(g["xi"][j] - ref.xi[i]))
-            em.append(mac(g["phi"][j], ref.phi[i]))
-    assert ef, "no physical poles compared"
-    print(f"bridge {mode}: sigma rel max {srel.max():.2e}; {gated_orders} orders gated, "
-          f"{len(ef)} physical poles, max f rel {max(ef):.2e}, max xi abs {max(ex):.2e}, "
-          f"min MAC {min(em):.6f}")
-    assert max(ef) <= 1e-3
-    assert max(ex) <= 2e-3
-    assert min(em) >= 0.99
+            e = per_order.setdefault(n, [0.0, 0.0, 1.0, 0])
+            e[0] = max(e[0], abs(g["f"][j] - ref.f[i]) / ref.f[i])
+            e[1] = max(e[1], abs(g["xi"][j] - ref.xi[i]))
+            e[2] = min(e[2], mac(g["phi"][j], ref.phi[i]))
+            e[3] += 1
+    return srel, per_order
+
+
+def test_identify_bridge_split_bf16(ctx, bridge):
+    """The split-BF16 range finder (SSI_PREC_BF16X3), the reduced-precision
+    mode offered at equal accuracy: physical poles at every one of the 100
+    orders within f rel 1e-3, damping abs 2e-3 and MAC 0.99 of the FP64
+    checker."""
+    from paper_2411_05510_amd import ssicov
+    srel, per_order = _bridge_errors(ctx, bridge, ssicov.PREC_BF16X3)
+    wl = bridge[0]
+    f = max(e[0] for e in per_order.values())
+    x = max(e[1] for e in per_order.values())
+    m = min(e[2] for e in per_order.values())
+    n = sum(e[3] for e in per_order.values())
+    print(f"bridge bf16x3: sigma rel max {srel:.2e}; {len(per_order)} orders, {n} physical "
+          f"poles, max f rel {f:.2e}, max xi abs {x:.2e}, min MAC {m:.6f}")
+    assert len(per_order) == len(wl.orders)
+    assert srel <= 1e-6
+    assert f <= 1e-3 and x <= 2e-3 and m >= 0.99
+
+
+def test_identify_bridge_plain_bf16_accuracy(ctx, bridge):
+    """Plain BF16 operands (SSI_PREC_BF16) are a lower-accuracy mode, not an
+    equal-accuracy one: BF16 keeps 8 significant bits, and the randomized
+    SVD's singular vectors at orders near k depend on the products to far
+    better than that (the FP64 checker's own poles at orders 160 and up move
+    by up to 6e-3 when only the sketch seed changes).  What the mode does
+    meet, and what this test holds it to: singular values within 1e-6
+    relative above 1e-2 sigma_1, the reduced-precision gates at every order
+    up to 84 (sigma_n above 2^-9 sigma_1 on this record), and poles within
+    1e-2 relative in frequency at every order."""
+    from paper_2411_05510_amd import ssicov
+    srel, per_order = _bridge_errors(ctx, bridge, ssicov.PREC_BF16)
+    low = [e for n, e in per_order.items() if n <= 84]
+    f_all = max(e[0] for e in per_order.values())
+    print(f"bridge bf16: sigma rel max {srel:.2e}; orders <= 84: max f rel "
+          f"{max(e[0] for e in low):.2e}, max xi abs {max(e[1] for e in low):.2e}, min MAC "
+          f"{min(e[2] for e in low):.6f}; all orders: max f rel {f_all:.2e}")
+    assert srel <= 1e-6
+    assert max(e[0] for e in low) <= 1e-3
+    assert max(e[1] for e in low) <= 2e-3
+    assert min(e[2] for e in low) >= 0.99
+    assert f_all <= 1e-2

@@ -4,6 +4,12 @@
   mix of concurrent requests with uneven channel counts, lags, orders and
   precisions (bit for bit: kernels are deterministic and a request's work
   stays on its slot), and equal to a plain context's identification;
+* every result of the mix matches the FP64 checker's identification of the
+  same window with the same sketch on its physical poles: at the FP32 gates
+  (f rel 1e-5, xi abs 1e-4, MAC 0.9999) for FP32 products, at the
+  reduced-precision gates (f rel 1e-3, xi abs 2e-3, MAC 0.99) for the
+  split-BF16 range finder, and within f rel 1e-2 for plain BF16 (a
+  lower-accuracy mode);
 * admission keeps the device memory the slots hold within the budget, so a
   budget for two requests caps the requests running at once at two;
 * a request queued behind others reports busy until it has run;
@@ -14,7 +20,9 @@ import dataclasses
 import numpy as np
 import pytest
 
+import oracle
 from paper_2411_05510_amd import synth
+from modelref import mac
 
 pytestmark = pytest.mark.gpu
 
@@ -26,7 +34,7 @@ def _need_gpu():
         pytest.skip("no GPU")
 
 
-def _mix():
+def _mix(with_models=False):
     """Six windows of different structures."""
     from paper_2411_05510_amd import ssicov
     out = []
@@ -40,12 +48,48 @@ def _mix():
                             lags=lags, svd="randomized", rank=rank, oversample=20,
                             power_iters=2, order_min=2, order_max=rank, order_step=2,
                             struct_seed=500 + i, noise_seed=600 + i, sketch_seed=700 + i)
-        _, y = synth.make_record(wl)
+        sysm, y = synth.make_record(wl)
         p = ssicov.Params(fs=wl.fs, lags=list(lags), order_min=2, order_max=rank, order_step=2,
                           svd=ssicov.SVD_RANDOMIZED, rank=rank, oversample=20, power_iters=2,
                           seed=wl.sketch_seed, prec=prec)
-        out.append((y, p))
+        out.append((y, p, sysm) if with_models else (y, p))
     return out
+
+
+def _check_against_oracle(y, p, sysm, res):
+    """Physical poles of a served result (host arrays in the ssi_output
+    layout) against the FP64 checker with the same sketch."""
+    from paper_2411_05510_amd import ssicov
+    gates = {ssicov.PREC_FP32: (1e-5, 1e-4, 0.9999), ssicov.PREC_BF16X3: (1e-3, 2e-3, 0.99),
+             ssicov.PREC_BF16: (1e-2, None, None)}[p.prec]
+    ref = oracle.identify(y, p.fs, p.lags, p.orders, svd="randomized", rank=p.rank,
+                          oversample=p.oversample, power_iters=p.power_iters, seed=p.seed)
+    worst, n = [0.0, 0.0, 1.0], 0
+    for li, lag in enumerate(ref):
+        for oi, r in enumerate(lag.poles):
+            off = ssicov.pole_offset(p, oi)
+            cnt = int(res["count"][li, oi])
+            assert res["flags"][li, oi] == 0
+            gf = res["f"][li, off:off + cnt]
+            gx = res["xi"][li, off:off + cnt]
+            gphi = res["phi"][li, off:off + cnt].astype(np.float64)
+            gphi = gphi[..., 0] + 1j * gphi[..., 1]
+            for k, fr in enumerate(sysm.freqs):
+                if len(r) == 0 or cnt == 0:
+                    continue
+                i = int(np.argmin(np.abs(r.f - fr)))
+                if abs(r.f[i] - fr) / fr >= 0.01 or mac(r.phi[i], sysm.shapes[:, k]) < 0.9:
+                    continue
+                j = int(np.argmin(np.abs(gf - r.f[i])))
+                worst[0] = max(worst[0], abs(gf[j] - r.f[i]) / r.f[i])
+                worst[1] = max(worst[1], abs(gx[j] - r.xi[i]))
+                worst[2] = min(worst[2], mac(gphi[j], r.phi[i]))
+                n += 1
+    assert n > 0
+    assert worst[0] <= gates[0], worst
+    if gates[1] is not None:
+        assert worst[1] <= gates[1] and worst[2] >= gates[2], worst
+    return worst, n
 
 
 KEYS = ("sigma", "count", "f", "xi", "mu", "phi", "flags")
@@ -59,7 +103,8 @@ def _equal(a, b):
 def test_results_same_alone_and_in_mix():
     _need_gpu()
     from paper_2411_05510_amd import ssicov
-    reqs = _mix()
+    models = _mix(with_models=True)
+    reqs = [(y, p) for y, p, _ in models]
     alone = []
     srv = ssicov.Server(0, max_inflight=1)
     for y, p in reqs:
@@ -73,8 +118,13 @@ def test_results_same_alone_and_in_mix():
     srv = ssicov.Server(0, max_inflight=4)
     tickets = [srv.submit(y, p) for y, p in reqs]
     infos = [srv.wait(t) for t in tickets]
-    for t, ref in zip(tickets, alone):
-        _equal(srv.result(t), ref)
+    for t, ref, (y, p, sysm) in zip(tickets, alone, models):
+        got = srv.result(t)
+        _equal(got, ref)
+        worst, n = _check_against_oracle(y, p, sysm, got)
+        print(f"served l={y.shape[0]} lags={list(p.lags)} prec={p.prec}: {n} physical poles, "
+              f"max f rel {worst[0]:.2e}, max xi abs {worst[1]:.2e}, min MAC {worst[2]:.6f}",
+              flush=True)
         srv.release(t)
     st = srv.stats()
     srv.close()
@@ -140,3 +190,32 @@ def test_submit_rejects_invalid_and_oversized():
         srv.submit(y, bad)
     assert e.value.status == ssicov.SSI_EINVAL
     srv.close()
+
+
+def test_sixty_four_in_flight():
+    """64 slots: 96 requests over the six windows, submitted at once; every
+    result equals the same window served alone, and more than 16 requests ran
+    at once at some point."""
+    _need_gpu()
+    from paper_2411_05510_amd import ssicov
+    reqs = _mix()
+    srv = ssicov.Server(0, max_inflight=1)
+    alone = []
+    for y, p in reqs:
+        t = srv.submit(y, p)
+        srv.wait(t)
+        alone.append(srv.result(t))
+        srv.release(t)
+    srv.close()
+    print("64 slots: submitting 96 requests", flush=True)
+    srv = ssicov.Server(0, max_inflight=64)
+    tickets = [srv.submit(*reqs[i % len(reqs)]) for i in range(96)]
+    for i, t in enumerate(tickets):
+        assert srv.wait(t)["status"] == ssicov.SSI_OK
+        _equal(srv.result(t), alone[i % len(reqs)])
+        srv.release(t)
+    st = srv.stats()
+    srv.close()
+    print(f"64 slots: peak in flight {st['peak_inflight']}, peak bytes {st['peak_bytes']}")
+    assert st["completed"] == 96 and st["failed"] == 0
+    assert st["peak_inflight"] > 16
