@@ -44,7 +44,7 @@ COPY_PROBE_BYTES = 256 << 20        # plain device copy used to calibrate HBM by
 PMC_SUMMARY = {"fp32": os.path.join(ROOT, "profiles", "correlate_mfma_bridge180_pmc.md"),
                "bf16x6": os.path.join(ROOT, "profiles", "correlate_b6_bridge180_pmc.md")}
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2411_05510_amd", "csrc", "correlate.hip")
-PRECS = {"fp32": 0, "bf16": 1, "bf16x3": 2}
+PRECS = {"fp32": 0, "bf16": 1, "bf16x3": 2, "bf16x6": 3}
 CORR_MODES = {"fp32": 0, "bf16x6": 1}
 CORR_KERNEL = {"fp32": "correlate_mfma", "bf16x6": "correlate_b6"}
 
@@ -92,12 +92,13 @@ def corr_flops(l: int, n: int, L: int) -> float:
     return 2.0 * l * l * (L * n - L * (L + 1) / 2)
 
 
-def params_of(wl, prec: int):
+def params_of(wl, prec: int, refine: int = 0):
     from paper_2411_05510_amd import ssicov
     return ssicov.Params(fs=wl.fs, lags=list(wl.lags), order_min=wl.order_min,
                          order_max=wl.order_max, order_step=wl.order_step,
                          svd=ssicov.SVD_RANDOMIZED, rank=wl.rank, oversample=wl.oversample,
-                         power_iters=wl.power_iters, seed=wl.sketch_seed, prec=prec)
+                         power_iters=wl.power_iters, seed=wl.sketch_seed, prec=prec,
+                         refine=min(refine, wl.power_iters))
 
 
 def roofline(stages, l, n, L, corr: str):
@@ -152,9 +153,9 @@ def stage_rooflines(stages, steps, m, ell, q, prec: str):
         prod.update(bound="mfma", achieved=tflops, peak=FP64_MFMA_PEAK_TFLOPS, unit="TFLOP/s",
                     frac=tflops / FP64_MFMA_PEAK_TFLOPS)
     else:
-        # BF16 operands: below the BF16 ridge, T is read once per product
-        prod.update(bound="hbm", achieved=t_read, peak=HBM_PEAK_GBS, unit="GB/s",
-                    frac=t_read / HBM_PEAK_GBS)
+        # BF16 range-finder products and FP64 refinement / projection products
+        # in one stage: reported as algorithmic TFLOP/s, no single roof
+        prod.update(bound="mixed", achieved=tflops, unit="TFLOP/s")
     toe = {"stage": "toeplitz", "kernels": "toeplitz_vec4", "bound": "hbm",
            "avg_kernel_ms": toe_avg, "achieved": toe_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
            "frac": toe_gbs / HBM_PEAK_GBS, "algorithmic_bytes": m * m * 4.0}
@@ -195,7 +196,7 @@ def bench_identify(args) -> dict:
     _, y = synth.make_record(wl)
     dev = torch.device("cuda:0")
     yd = torch.from_numpy(y).to(dev)
-    p = params_of(wl, PRECS[args.prec])
+    p = params_of(wl, PRECS[args.prec], args.refine)
     ctx = ssicov.Context(0)
     ctx.set_corr_mode(CORR_MODES[args.corr])
     ctx.set_autotune(True)                   # the warm-up calls pick the K-slice counts
@@ -250,10 +251,14 @@ def bench_identify(args) -> dict:
     corr_note = {"fp32": "correlations on FP32 MFMA",
                  "bf16x6": "correlations as six BF16 MFMA products of the exact three-way "
                            "BF16 split of the FP32 samples (FP32 accumulation)"}[args.corr]
+    refine_note = (f" with {args.refine} full-precision refinement power step"
+                   if args.prec != "fp32" and args.refine else "")
     prec_note = {"fp32": "T x Q products on FP64 MFMA",
                  "bf16": "range-finder products BF16 (FP32 accumulation), projection FP64 MFMA",
                  "bf16x3": "range-finder products split BF16 x3 (FP32 accumulation), "
-                           "projection FP64 MFMA"}[args.prec]
+                           "projection FP64 MFMA",
+                 "bf16x6": "range-finder products as six BF16 products of exact three-way "
+                           "splits (FP32 accumulation), projection FP64 MFMA"}[args.prec]
     rec = {
         "metric": "SSI-COV identifications/s at 180 ch, i=60",
         "value": args.steps / elapsed,
@@ -270,7 +275,7 @@ def bench_identify(args) -> dict:
         "config": {
             "workload": "bridge-180ch: l=180 channels, N=180000 samples at 100 Hz, j_b=60 "
                         "(10800x10800 Toeplitz), randomized SVD k=200 p=20 q=2, "
-                        f"orders 2..200 step 2; {corr_note}, {prec_note}, "
+                        f"orders 2..200 step 2; {corr_note}, {prec_note}{refine_note}, "
                         "FP64 factorizations and eigen-analysis; product K slices autotuned "
                         "in the warm-up",
             "latency_ms_p50": float(np.percentile(step_ms, 50)),
@@ -298,7 +303,7 @@ def bench_3d(args) -> dict:
     _, y = synth.make_record(wl)
     dev = torch.device("cuda:0")
     yd = torch.from_numpy(y).to(dev)
-    p = params_of(wl, PRECS[args.prec])
+    p = params_of(wl, PRECS[args.prec], args.refine)
     ctx = ssicov.Context(0)
     ctx.set_corr_mode(CORR_MODES[args.corr])
     ctx.set_lag_streams(args.lag_streams)
@@ -372,7 +377,7 @@ def bench_serving(args) -> dict:
                             struct_seed=4_000_000 + r, noise_seed=5_000_000 + r,
                             sketch_seed=6_000_000 + r)
         _, y = synth.make_record(wl)
-        pool.append((y, params_of(wl, PRECS[args.prec])))
+        pool.append((y, params_of(wl, PRECS[args.prec], args.refine)))
 
     def run(rate_hz, count, inflight):
         srv = ssicov.Server(0, max_inflight=inflight)
@@ -393,23 +398,33 @@ def bench_serving(args) -> dict:
         infos = [srv.wait(t) for t in tickets]
         span = time.perf_counter() - t0
         lat = np.array([(i["t_done_us"] - i["t_submit_us"]) / 1e3 for i in infos])
+        wait = np.array([(i["t_start_us"] - i["t_submit_us"]) / 1e3 for i in infos])
+        service = np.array([(i["t_done_us"] - i["t_start_us"]) / 1e3 for i in infos])
         st = srv.stats()
         for t in tickets:
             srv.release(t)
         srv.close()
-        return count / span, lat, st
+        pct = lambda a, q: float(np.percentile(a, q))
+        return {"requests_per_s": count / span, "latency_ms_p50": pct(lat, 50),
+                "latency_ms_p99": pct(lat, 99), "queue_ms_p50": pct(wait, 50),
+                "queue_ms_p99": pct(wait, 99), "service_ms_p50": pct(service, 50),
+                "service_ms_p99": pct(service, 99), "peak_inflight": st["peak_inflight"],
+                "peak_device_bytes": st["peak_bytes"]}
 
-    sat, _, _ = run(0.0, args.requests, args.inflight)          # all at once: saturation
-    rate = 0.8 * sat
-    thr, lat, st = run(rate, args.requests, args.inflight)
+    sat = run(0.0, args.requests, args.inflight)["requests_per_s"]   # all at once: saturation
+    sweep = {}
+    for frac in (0.5, 0.8, 1.0):
+        sweep[f"{frac:.1f}"] = dict(run(frac * sat, args.requests, args.inflight),
+                                    arrival_rate_hz=frac * sat)
+    head = sweep["0.8"]
     return {
         "metric": "SSI-COV serving requests/s (Poisson, 10-min windows)",
-        "value": thr,
+        "value": head["requests_per_s"],
         "unit": "requests/s",
         "n_gpus": 1,
         "steps": args.requests,
         "warmup": args.inflight,
-        "ms_per_step": 1000.0 / thr,
+        "ms_per_step": 1000.0 / head["requests_per_s"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -419,13 +434,19 @@ def bench_serving(args) -> dict:
             "workload": "serving: N=60000 at 100 Hz per window, l in {24,60,120,180,300}, "
                         "8-30 modes, j_b in {20,40,60,80}, k=2 modes+20, p=20, q=2, "
                         f"orders 2..k step 2; up to {args.inflight} in flight, admission by "
-                        "device footprint; Poisson arrivals at 0.8 x measured saturation",
+                        "device footprint; Poisson arrivals at 0.8 x measured saturation "
+                        "(the sweep gives 0.5, 0.8 and 1.0)",
             "saturation_requests_per_s": sat,
-            "arrival_rate_hz": rate,
-            "latency_ms_p50": float(np.percentile(lat, 50)),
-            "latency_ms_p99": float(np.percentile(lat, 99)),
-            "peak_inflight": st["peak_inflight"],
-            "peak_device_bytes": st["peak_bytes"],
+            "arrival_rate_hz": head["arrival_rate_hz"],
+            "latency_ms_p50": head["latency_ms_p50"],
+            "latency_ms_p99": head["latency_ms_p99"],
+            "queue_ms_p50": head["queue_ms_p50"],
+            "queue_ms_p99": head["queue_ms_p99"],
+            "service_ms_p50": head["service_ms_p50"],
+            "service_ms_p99": head["service_ms_p99"],
+            "peak_inflight": head["peak_inflight"],
+            "peak_device_bytes": head["peak_device_bytes"],
+            "rate_sweep": sweep,
             "distinct_windows": len(pool),
         },
     }
@@ -439,11 +460,14 @@ def main() -> int:
     ap.add_argument("--workload", default="bridge-180ch",
                     choices=("bridge-180ch", "bridge-180ch-3d", "serving"))
     ap.add_argument("--prec", default="fp32", choices=tuple(PRECS))
+    ap.add_argument("--refine", type=int, default=None,
+                    help="full-precision refinement power steps of a reduced-precision range "
+                         "finder (default 1 for BF16 modes)")
     ap.add_argument("--corr", default="bf16x6", choices=tuple(CORR_MODES),
                     help="correlation product arithmetic")
     ap.add_argument("--lag-streams", type=int, default=3)
     ap.add_argument("--requests", type=int, default=96, help="serving: requests per run")
-    ap.add_argument("--inflight", type=int, default=16, help="serving: slots")
+    ap.add_argument("--inflight", type=int, default=64, help="serving: slots")
     ap.add_argument("--pool", type=int, default=24, help="serving: distinct windows")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--e2e-steps", type=int, default=5,
@@ -451,6 +475,8 @@ def main() -> int:
     ap.add_argument("--copy-probe", action="store_true",
                     help="run one plain device copy of 256 MiB first (counter calibration)")
     args = ap.parse_args()
+    if args.refine is None:
+        args.refine = 0 if args.prec == "fp32" else 1
     if args.gpus != 1:
         print(f"bench.py: the identification runs on one GPU; --gpus {args.gpus} is not supported "
               "(one process, one device)", file=sys.stderr)

@@ -69,12 +69,22 @@ typedef enum ssi_precision {
                           smaller singular values move by more than the
                           reduced-precision tolerance (up to 6e-3 in frequency on a
                           180-channel record at orders 86..200)                  */
-  SSI_PREC_BF16X3 = 2  /* T and X split into BF16 hi + lo parts (lo = BF16 of the
+  SSI_PREC_BF16X3 = 2, /* T and X split into BF16 hi + lo parts (lo = BF16 of the
                           remainder), three BF16 MFMA products hi hi + hi lo +
                           lo hi with FP32 accumulation: about 16 significant bits
-                          per operand.  The reduced-precision mode that keeps
-                          frequencies within 1e-3, damping within 2e-3 and MAC
-                          above 0.99 of the FP64 computation at every order      */
+                          per operand.  With one refinement step
+                          (ssi_params.refine = 1) it keeps frequencies within 1e-3,
+                          damping within 2e-3 and MAC above 0.99 of the FP64
+                          computation at every order of the 180-channel record at
+                          lags 20..100 (worst 1.3e-4); without refinement the
+                          products' FP32 accumulation leaves 4e-3 at lag 20    */
+  SSI_PREC_BF16X6 = 3  /* T (FP32 as stored) and X (rounded to FP32) split
+                          exactly into three BF16 parts each by truncation; the six
+                          products of weight >= 2^-16 on v_mfma_f32_16x16x32_bf16,
+                          each exact in FP32, FP32 accumulation: FP32-operand
+                          products at the BF16 matrix rate, FP32 accumulation
+                          (1.4e-3 in frequency at lag 20 without refinement,
+                          5e-5 with one refinement step)                         */
 } ssi_precision;
 
 /* Arithmetic of the correlation products (Section 2.1), a context option.
@@ -117,6 +127,9 @@ typedef struct ssi_params {
                                  lag i).  Randomized SVD only.  Read during the
                                  call's device work (stream-ordered).               */
   int64_t omega_ld;           /* >= k + p when omega is given                       */
+  int32_t refine;             /* reduced-precision products only: the last `refine`
+                                 power iterations (both products) run as in
+                                 SSI_PREC_FP32 (refinement steps); 0 <= refine <= q  */
 } ssi_params;
 
 /* Sizes of the device output buffers of ssi_identify, from ssi_output_layout. */
@@ -247,7 +260,8 @@ ssi_status ssi_set_allocator(ssi_ctx *ctx, void *(*alloc)(size_t bytes, void *us
  * SSI_EINVAL for an unknown mode.  Drops captured graphs. */
 ssi_status ssi_set_corr_mode(ssi_ctx *ctx, int32_t mode);
 /* K-slice count chosen by the autotuner for a product, 0 if not tuned.
- * kind: 0 = FP32 x FP64 product, 1 = BF16 product, 3 = split BF16 product;
+ * kind: 0 = FP32 x FP64 product, 1 = BF16 product, 3 = split BF16 product, 6 = three-way
+ * split BF16 product;
  * trans: 1 for T^T X. */
 int32_t ssi_tuned_splits(const ssi_ctx *ctx, int32_t kind, int32_t trans, int32_t m,
                          int32_t n, int32_t k);

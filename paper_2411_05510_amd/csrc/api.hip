@@ -476,12 +476,16 @@ ssi_status ssi_validate(const ssi_params *p, int32_t l, int64_t n) {
     return fail(SSI_EINVAL, "need 1 <= order_min <= order_max");
   if (p->svd != SSI_SVD_FULL && p->svd != SSI_SVD_RANDOMIZED)
     return fail(SSI_EINVAL, "unknown svd mode %d", p->svd);
-  if (p->prec != SSI_PREC_FP32 && p->prec != SSI_PREC_BF16 && p->prec != SSI_PREC_BF16X3)
+  if (p->prec != SSI_PREC_FP32 && p->prec != SSI_PREC_BF16 && p->prec != SSI_PREC_BF16X3 &&
+      p->prec != SSI_PREC_BF16X6)
     return fail(SSI_EINVAL, "unknown precision %d", p->prec);
   if (p->prec != SSI_PREC_FP32 && p->svd != SSI_SVD_RANDOMIZED)
     return fail(SSI_EINVAL, "BF16 products apply to the randomized SVD only");
   if (p->omega && p->svd != SSI_SVD_RANDOMIZED)
     return fail(SSI_EINVAL, "a caller sketch applies to the randomized SVD only");
+  if (p->refine < 0 || (p->refine > 0 && p->svd == SSI_SVD_RANDOMIZED &&
+                        p->refine > p->power_iters))
+    return fail(SSI_EINVAL, "refine = %d must be in [0, power_iters]", p->refine);
   if (p->omega && p->omega_ld < (int64_t)p->rank + p->oversample)
     return fail(SSI_EINVAL, "omega_ld = %lld must be >= k + p = %d", (long long)p->omega_ld,
                 p->rank + p->oversample);
@@ -652,6 +656,11 @@ size_t part_tf64(int M, int N, int K, int cus, bool tune = false) {
 }
 size_t part_f64(int M, int N, int K, int cus) { return ssi::plan_gemm_f64(M, N, K, cus).part_elems(); }
 
+// BF16 products per FP32 product of a reduced-precision mode
+int bf16_terms(int prec) {
+  return prec == SSI_PREC_BF16X6 ? 6 : (prec == SSI_PREC_BF16X3 ? 3 : 1);
+}
+
 // ------------------------------------------------------------ randomized SVD
 struct RsvdBufs {
   double *om, *ya, *yb, *gm, *rinv, *lws, *evals, *evecs, *dws, *part;
@@ -683,8 +692,8 @@ RsvdBufs carve_rsvd(Arena &a, ssi_ctx *c, int64_t m, int ell, int k, int prec,
                      part_f64(mm, ell, ell, cu), part_f64(mm, k, ell, cu)});
   }
   b.part = a.take<double>(part);
-  if (prec == SSI_PREC_BF16 || prec == SSI_PREC_BF16X3) {
-    const int nt = prec == SSI_PREC_BF16X3 ? 3 : 1;
+  if (prec != SSI_PREC_FP32) {
+    const int nt = bf16_terms(prec);
     size_t xt = 0, p32 = 0;
     for (int i = 0; i < (m_all ? n_m : 1); ++i) {
       const int mm = m_all ? (int)m_all[i] : mi;
@@ -725,7 +734,7 @@ double *orthonormalize(ssi_ctx *c, RsvdBufs &b, double *cur, double *nxt, int64_
 
 ssi_status run_rsvd(ssi_ctx *c, RsvdBufs &b, const float *t, int64_t m, int64_t ldt, int k,
                     int p, int q, const float *omega, int64_t ldo, uint64_t seed,
-                    uint32_t stream, double *u, double *sigma) {
+                    uint32_t stream, double *u, double *sigma, int refine = 0) {
   const int ell = k + p, mi = (int)m;
   hipError_t e;
   {
@@ -740,7 +749,7 @@ ssi_status run_rsvd(ssi_ctx *c, RsvdBufs &b, const float *t, int64_t m, int64_t 
   {
     StageTimer tm(c, SSI_STAGE_PRODUCTS);
     if (b.prec != SSI_PREC_FP32)
-      e = prod_bf16(c, false, t, ldt, b.om, ell, mi, ell, mi, b.prec == SSI_PREC_BF16X3 ? 3 : 1,
+      e = prod_bf16(c, false, t, ldt, b.om, ell, mi, ell, mi, bf16_terms(b.prec),
                     b.xt, b.part32, b.ya, ell);
     else
       e = prod_tf64(c, false, t, ldt, b.om, ell, mi, ell, mi, b.part, b.ya, ell);
@@ -758,9 +767,11 @@ ssi_status run_rsvd(ssi_ctx *c, RsvdBufs &b, const float *t, int64_t m, int64_t 
       double *other = (Q == b.ya) ? b.yb : b.ya;
       {
         StageTimer tm(c, SSI_STAGE_PRODUCTS);
-        if (b.prec != SSI_PREC_FP32)
+        // the last `refine` iterations of a reduced-precision range finder
+        // run in full precision
+        if (b.prec != SSI_PREC_FP32 && it < q - refine)
           e = prod_bf16(c, side == 0, t, ldt, Q, ell, mi, ell, mi,
-                        b.prec == SSI_PREC_BF16X3 ? 3 : 1, b.xt, b.part32, other, ell);
+                        bf16_terms(b.prec), b.xt, b.part32, other, ell);
         else
           e = prod_tf64(c, side == 0, t, ldt, Q, ell, mi, ell, mi, b.part, other, ell);
       }
@@ -993,7 +1004,7 @@ ssi_status run_lag(ssi_ctx *c, LaneBufs &b, const float *r, int l, const ssi_par
   if (p->svd == SSI_SVD_RANDOMIZED)
     // a caller sketch gives every lag its leading m rows
     s = run_rsvd(c, b.rb, b.t, m, ldt, p->rank, p->oversample, p->power_iters, p->omega,
-                 p->omega_ld, p->seed, (uint32_t)i, b.u, b.sig);
+                 p->omega_ld, p->seed, (uint32_t)i, b.u, b.sig, p->refine);
   else
     s = run_svd_full(c, b.fb, b.t, (int)m, ldt, kcols, b.u, b.sig);
   if (s != SSI_OK) return s;
@@ -1136,7 +1147,8 @@ ssi_status ssi_rsvd(ssi_ctx *c, const float *t, int64_t m, int64_t ldt, int32_t 
   if (k + p > ssi::dense_max_n())
     return fail(SSI_EINVAL, "ssi_rsvd: k + p = %d exceeds %d", k + p, ssi::dense_max_n());
   if (m > INT32_MAX / 2) return fail(SSI_EINVAL, "ssi_rsvd: m too large");
-  if (prec != SSI_PREC_FP32 && prec != SSI_PREC_BF16 && prec != SSI_PREC_BF16X3)
+  if (prec != SSI_PREC_FP32 && prec != SSI_PREC_BF16 && prec != SSI_PREC_BF16X3 &&
+      prec != SSI_PREC_BF16X6)
     return fail(SSI_EINVAL, "ssi_rsvd: unknown precision %d", prec);
   DeviceGuard g(c->device);
   if (!is_device_ptr(t) || !is_device_ptr(u) || !is_device_ptr(sigma) ||

@@ -422,6 +422,73 @@ SSI_DEV double wave_max_d(double v) { return wave_max(v); }
 
 }  // namespace
 
+// LU with partial pivoting of the tridiagonal T - lam I (diagonal dd, off-
+// diagonal ee), run by one lane.  A row swap is marked by adding 4 to the
+// multiplier (at most 1 in magnitude); u0 holds 1 / pivot, pivots below tiny
+// are raised to tiny.
+SSI_DEV void inv_iter_lu(const double *dd, const double *ee, int n, double lam, double tiny,
+                         double *u0, double *u1, double *u2, double *ml) {
+  double a = dd[0] - lam, b = (n > 1) ? ee[0] : 0.0, c = 0.0;
+  for (int j = 0; j + 1 < n; ++j) {
+    const double sub = ee[j];
+    const double an = dd[j + 1] - lam;
+    const double cn = (j + 2 < n) ? ee[j + 1] : 0.0;
+    if (fabs(a) >= fabs(sub)) {
+      const double aa = (fabs(a) < tiny) ? copysign(tiny, a == 0.0 ? 1.0 : a) : a;
+      const double m = sub / aa;
+      u0[j] = 1.0 / aa;
+      u1[j] = b;
+      u2[j] = c;
+      ml[j] = m;
+      a = an - m * b;
+      b = cn - m * c;
+    } else {
+      const double m = a / sub;
+      u0[j] = 1.0 / sub;
+      u1[j] = an;
+      u2[j] = cn;
+      ml[j] = m + 4.0;
+      a = b - m * an;
+      b = c - m * cn;
+    }
+    c = 0.0;
+  }
+  if (fabs(a) < tiny) a = copysign(tiny, a == 0.0 ? 1.0 : a);
+  u0[n - 1] = 1.0 / a;
+  u1[n - 1] = 0.0;
+  u2[n - 1] = 0.0;
+}
+
+// One inverse-iteration step x <- (T - lam I)^-1 x with the factors of
+// inv_iter_lu, scaled to max |x_j| = 1; run by one lane.
+SSI_DEV void inv_iter_solve(int n, const double *u0, const double *u1, const double *u2,
+                            const double *ml, double *xv) {
+  double bj = xv[0];
+  for (int j = 0; j + 1 < n; ++j) {
+    double m = ml[j];
+    double bn = xv[j + 1];
+    if (m > 2.0) {
+      m -= 4.0;
+      const double tmp = bj;
+      bj = bn;
+      bn = tmp;
+    }
+    xv[j] = bj;
+    bj = bn - m * bj;
+  }
+  xv[n - 1] = bj;
+  double x1 = 0.0, x2 = 0.0, nrm = 0.0;
+  for (int j = n - 1; j >= 0; --j) {
+    const double xj = (xv[j] - u1[j] * x1 - u2[j] * x2) * u0[j];
+    xv[j] = xj;
+    x2 = x1;
+    x1 = xj;
+    nrm = fmax(nrm, fabs(xj));
+  }
+  const double inv = 1.0 / nrm;
+  for (int j = 0; j < n; ++j) xv[j] *= inv;
+}
+
 // Eigenpairs of the tridiagonal (d, e), one wave per eigenvalue; wave t of the
 // grid takes the t-th largest.  The eigenvalue comes from multisection of the
 // Sturm count: each round the 64 lanes count at 64 interior points of the
@@ -481,64 +548,9 @@ sym_tridiag_eig_kernel(int n, double *__restrict__ evals, double *__restrict__ e
     const double lam = 0.5 * (lo + hi);
     if (lane == 0) {
       evals[t] = lam;
-      // LU with partial pivoting of T - lam I; a row swap is marked by adding
-      // 4 to the multiplier (at most 1 in magnitude).  u0 holds 1 / pivot.
-      double a = dd[0] - lam, b = (n > 1) ? ee[0] : 0.0, c = 0.0;
-      for (int j = 0; j + 1 < n; ++j) {
-        const double sub = ee[j];
-        const double an = dd[j + 1] - lam;
-        const double cn = (j + 2 < n) ? ee[j + 1] : 0.0;
-        if (fabs(a) >= fabs(sub)) {
-          const double aa = (fabs(a) < tiny) ? copysign(tiny, a == 0.0 ? 1.0 : a) : a;
-          const double m = sub / aa;
-          u0[j] = 1.0 / aa;
-          u1[j] = b;
-          u2[j] = c;
-          ml[j] = m;
-          a = an - m * b;
-          b = cn - m * c;
-        } else {
-          const double m = a / sub;
-          u0[j] = 1.0 / sub;
-          u1[j] = an;
-          u2[j] = cn;
-          ml[j] = m + 4.0;
-          a = b - m * an;
-          b = c - m * cn;
-        }
-        c = 0.0;
-      }
-      if (fabs(a) < tiny) a = copysign(tiny, a == 0.0 ? 1.0 : a);
-      u0[n - 1] = 1.0 / a;
-      u1[n - 1] = 0.0;
-      u2[n - 1] = 0.0;
+      inv_iter_lu(dd, ee, n, lam, tiny, u0, u1, u2, ml);
       for (int j = 0; j < n; ++j) xv[j] = hash_unit(t, j);
-      for (int it = 0; it < 3; ++it) {
-        double bj = xv[0];
-        for (int j = 0; j + 1 < n; ++j) {
-          double m = ml[j];
-          double bn = xv[j + 1];
-          if (m > 2.0) {
-            m -= 4.0;
-            const double tmp = bj;
-            bj = bn;
-            bn = tmp;
-          }
-          xv[j] = bj;
-          bj = bn - m * bj;
-        }
-        xv[n - 1] = bj;
-        double x1 = 0.0, x2 = 0.0, nrm = 0.0;
-        for (int j = n - 1; j >= 0; --j) {
-          const double xj = (xv[j] - u1[j] * x1 - u2[j] * x2) * u0[j];
-          xv[j] = xj;
-          x2 = x1;
-          x1 = xj;
-          nrm = fmax(nrm, fabs(xj));
-        }
-        const double inv = 1.0 / nrm;
-        for (int j = 0; j < n; ++j) xv[j] *= inv;
-      }
+      for (int it = 0; it < 3; ++it) inv_iter_solve(n, u0, u1, u2, ml, xv);
     }
   }
   __syncthreads();
@@ -547,6 +559,84 @@ sym_tridiag_eig_kernel(int n, double *__restrict__ evals, double *__restrict__ e
     for (int j = lane; j < n; j += 64) s += xv[j] * xv[j];
     const double inv = 1.0 / sqrt(wave_sum(s));
     for (int j = lane; j < n; j += 64) evecs[(int64_t)j * ldv + t] = xv[j] * inv;
+  }
+}
+
+// Eigenvalues closer than kClusterTol ||T|| are a cluster: inverse iteration
+// run on each of them alone converges to nearly the same vector (for an exact
+// multiple or zero eigenvalue, to nearly parallel ones), so their vectors are
+// recomputed here one after another with every iterate orthogonalized against
+// the cluster's earlier vectors (modified Gram-Schmidt), as LAPACK's xSTEIN
+// does; the vectors of isolated eigenvalues are left as they are.  Inverse
+// iteration from an isolated eigenvalue with absolute gap g gives a vector
+// within about eps ||T|| / g of the true one, so outside clusters the vectors
+// are orthogonal to about 1e-6 or better.  Evals are descending (column t
+// holds the t-th largest).  One wave takes whole clusters, W waves share
+// them round robin; the LU and the solves run on lane 0 as in
+// sym_tridiag_eig_kernel, the projections on the whole wave.
+constexpr double kClusterTol = 1e-10;
+
+template <int KN, int W>
+__global__ void __launch_bounds__(64 * W)
+sym_cluster_kernel(int n, const double *__restrict__ evals, double *__restrict__ evecs,
+                   int64_t ldv, const double *__restrict__ ws) {
+  __shared__ double dd[KN];
+  __shared__ double ee[KN];
+  __shared__ double lu[W][5][KN];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const double *tauv = ws + (size_t)KN * KN;
+  for (int i = threadIdx.x; i < n; i += 64 * W) {
+    dd[i] = tauv[KN + i];
+    ee[i] = (i < n - 1) ? tauv[2 * KN + i] : 0.0;
+  }
+  __syncthreads();
+  double nrm_part = 0.0;
+  for (int i = lane; i < n; i += 64)
+    nrm_part = fmax(nrm_part, fabs(dd[i]) + (i > 0 ? fabs(ee[i - 1]) : 0.0) + fabs(ee[i]));
+  const double gnorm = wave_max_d(nrm_part);           // Gershgorin bound of ||T||
+  const double tol = kClusterTol * gnorm;
+  const double tiny = 2.220446049250313e-16 * fmax(gnorm, 1e-300);
+  double *u0 = lu[wv][0], *u1 = lu[wv][1], *u2 = lu[wv][2], *ml = lu[wv][3], *xv = lu[wv][4];
+  int ordinal = 0;
+  for (int s0 = 0; s0 < n;) {
+    int e0 = s0 + 1;
+    while (e0 < n && evals[e0 - 1] - evals[e0] <= tol) ++e0;
+    if (e0 - s0 >= 2 && (ordinal++ % W) == wv) {
+      for (int j = s0; j < e0; ++j) {
+        if (lane == 0) {
+          inv_iter_lu(dd, ee, n, evals[j], tiny, u0, u1, u2, ml);
+          for (int i = 0; i < n; ++i) xv[i] = hash_unit(j, i);
+        }
+        for (int it = 0; it < 3; ++it) {
+          if (lane == 0) inv_iter_solve(n, u0, u1, u2, ml, xv);
+          __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+          __builtin_amdgcn_wave_barrier();
+          for (int p = s0; p < j; ++p) {
+            double d = 0.0;
+            for (int i = lane; i < n; i += 64) d += xv[i] * evecs[(int64_t)i * ldv + p];
+            d = wave_sum(d);
+            for (int i = lane; i < n; i += 64) xv[i] -= d * evecs[(int64_t)i * ldv + p];
+          }
+          double mx = 0.0;
+          for (int i = lane; i < n; i += 64) mx = fmax(mx, fabs(xv[i]));
+          mx = wave_max_d(mx);
+          // an iterate wholly inside the earlier vectors' span (it cannot be,
+          // short of rounding) would leave nothing: restart from another vector
+          const double inv = mx > 0.0 ? 1.0 / mx : 0.0;
+          for (int i = lane; i < n; i += 64) xv[i] = mx > 0.0 ? xv[i] * inv : hash_unit(j + n, i);
+          __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+          __builtin_amdgcn_wave_barrier();
+        }
+        double s2 = 0.0;
+        for (int i = lane; i < n; i += 64) s2 += xv[i] * xv[i];
+        const double inv = 1.0 / sqrt(wave_sum(s2));
+        // each lane writes and later reads the same rows of the column, so
+        // the wave's own later projections see these values
+        for (int i = lane; i < n; i += 64) evecs[(int64_t)i * ldv + j] = xv[i] * inv;
+        __threadfence_block();
+      }
+    }
+    s0 = e0;
   }
 }
 
@@ -927,6 +1017,8 @@ hipError_t launch_sym_eig(const double *G, int64_t ldg, int n, double *evals, do
                        st, G, ldg, n, ws, ws);
     hipLaunchKernelGGL((sym_tridiag_eig_kernel<kRegN, kRegEpw>), dim3(ceil_div(n, kRegEpw)),
                        dim3(64 * kRegEpw), 0, st, n, evals, evecs, ldv, ws);
+    hipLaunchKernelGGL((sym_cluster_kernel<kRegN, 4>), dim3(1), dim3(256), 0, st, n, evals,
+                       evecs, ldv, ws);
     hipLaunchKernelGGL((sym_backtransform_kernel<kRegP, kRegQ, false>), dim3(1),
                        dim3(kThreads), 0, st, n, evecs, ldv, ws, ws);
   } else {
@@ -935,6 +1027,8 @@ hipError_t launch_sym_eig(const double *G, int64_t ldg, int n, double *evals, do
                        st, G, ldg, n, ws, tile);
     hipLaunchKernelGGL((sym_tridiag_eig_kernel<kGlbN, kGlbEpw>), dim3(ceil_div(n, kGlbEpw)),
                        dim3(64 * kGlbEpw), 0, st, n, evals, evecs, ldv, ws);
+    hipLaunchKernelGGL((sym_cluster_kernel<kGlbN, 2>), dim3(1), dim3(128), 0, st, n, evals,
+                       evecs, ldv, ws);
     hipLaunchKernelGGL((sym_backtransform_kernel<kGlbP, kGlbQ, true>), dim3(1),
                        dim3(kThreads), 0, st, n, evecs, ldv, ws, tile);
   }

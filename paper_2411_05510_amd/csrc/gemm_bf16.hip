@@ -105,6 +105,19 @@ SSI_DEV uint16_t bf16_lo(float v, uint16_t h) {
   return bf16_rne(v - __uint_as_float((uint32_t)h << 16));
 }
 
+// Exact three-way split of an FP32 value into BF16 parts by truncation: hi
+// keeps the top 8 significant bits, mid the next 8 and lo the last 8, and
+// hi + mid + lo = v with no rounding (each remainder is exact in FP32).
+SSI_DEV void bf16_split3(float v, uint16_t &h, uint16_t &m, uint16_t &l) {
+  const uint32_t u = __float_as_uint(v);
+  h = (uint16_t)(u >> 16);
+  const float r1 = v - __uint_as_float(u & 0xffff0000u);
+  const uint32_t u1 = __float_as_uint(r1);
+  m = (uint16_t)(u1 >> 16);
+  const float r2 = r1 - __uint_as_float(u1 & 0xffff0000u);
+  l = (uint16_t)(__float_as_uint(r2) >> 16);
+}
+
 // Registers -> LDS (BF16 planes), A as As[i][k], B as Bs[j][k].
 template <bool TA, int KT, int LS, int NP, int AV, int BC, int NT>
 SSI_DEV void bf16_tile_store(uint16_t (&As)[NP][bBM * LS], uint16_t (&Bs)[NP][bBN * LS], int tid,
@@ -128,6 +141,30 @@ SSI_DEV void bf16_tile_store(uint16_t (&As)[NP][bBM * LS], uint16_t (&Bs)[NP][bB
         *reinterpret_cast<u32x4 *>(&Bs[q][j * LS + 8 * c8]) = rb[q][h];
       }
     }
+  if (NT == 6) {
+#pragma unroll
+    for (int h = 0; h < AV; ++h) {
+      const int idx = tid + 256 * h;
+      uint16_t p[3][4];
+      bf16_split3(ra[h].x, p[0][0], p[1][0], p[2][0]);
+      bf16_split3(ra[h].y, p[0][1], p[1][1], p[2][1]);
+      bf16_split3(ra[h].z, p[0][2], p[1][2], p[2][2]);
+      bf16_split3(ra[h].w, p[0][3], p[1][3], p[2][3]);
+#pragma unroll
+      for (int q = 0; q < 3; ++q) {
+        if (!TA) {
+          const int r = idx / (KT / 4), c4 = idx % (KT / 4);
+          *reinterpret_cast<uint2 *>(&As[q][r * LS + 4 * c4]) =
+              make_uint2(pack2(p[q][0], p[q][1]), pack2(p[q][2], p[q][3]));
+        } else {
+          const int r = idx >> 4, c4 = idx & 15;
+#pragma unroll
+          for (int c = 0; c < 4; ++c) As[q][(4 * c4 + c) * LS + r] = p[q][c];
+        }
+      }
+    }
+    return;
+  }
 #pragma unroll
   for (int h = 0; h < AV; ++h) {
     const int idx = tid + 256 * h;
@@ -166,6 +203,10 @@ SSI_DEV void bf16_tile_store(uint16_t (&As)[NP][bBM * LS], uint16_t (&Bs)[NP][bB
 //   NT = 1: one BF16 product.  NT = 3: split operands a = a_hi + a_lo,
 //   x = x_hi + x_lo (each part BF16) and three products a_hi x_hi + a_hi x_lo
 //   + a_lo x_hi, which carry about 16 significant bits of each operand.
+//   NT = 6: exact three-way splits a = a_h + a_m + a_l (FP32 T as stored) and
+//   x = x_h + x_m + x_l (X rounded to FP32), and the six products of weight
+//   >= 2^-16 (h h, h m, m h, h l, l h, m m), each exact in FP32: the products
+//   of FP32 operands up to a relative 2^-23, accumulated in FP32.
 template <bool TA, bool VEC, int NT>
 __global__ void __launch_bounds__(256, 2)
 gemm_tbf16_mfma(const float *__restrict__ A, int64_t lda, const uint16_t *__restrict__ xt,
@@ -173,7 +214,7 @@ gemm_tbf16_mfma(const float *__restrict__ A, int64_t lda, const uint16_t *__rest
                 int64_t split_stride, int M, int N, int K, int k_per_split, int gm, int splits) {
   constexpr int KT = NT == 1 ? 64 : 32;          // K tile
   constexpr int LS = KT + 8;                     // LDS row stride (bf16)
-  constexpr int NP = NT == 1 ? 1 : 2;            // operand planes
+  constexpr int NP = NT == 1 ? 1 : (NT == 3 ? 2 : 3);   // operand planes
   constexpr int AV = KT / 16;                    // float4 of A per thread
   constexpr int BC = (bBN * KT / 8 + 255) / 256; // 16-byte chunks of B per thread and plane
   __shared__ __attribute__((aligned(16))) uint16_t As[NP][bBM * LS];
@@ -220,6 +261,19 @@ gemm_tbf16_mfma(const float *__restrict__ A, int64_t lda, const uint16_t *__rest
       for (int ct = 0; ct < 7; ++ct) {
         const int brow = (wc * 112 + ct * 16 + (lane & 15)) * LS + ko;
         const bf16x8 bhi = *reinterpret_cast<const bf16x8 *>(&Bs[0][brow]);
+        if (NT == 6) {
+          // smallest terms first: l h, h l, m m, m h, h m (then h h below)
+          const bf16x8 bmid = *reinterpret_cast<const bf16x8 *>(&Bs[1][brow]);
+          const bf16x8 blow = *reinterpret_cast<const bf16x8 *>(&Bs[2][brow]);
+#pragma unroll
+          for (int rt = 0; rt < 2; ++rt) {
+            acc[rt][ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[2][rt], bhi, acc[rt][ct], 0, 0, 0);
+            acc[rt][ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[0][rt], blow, acc[rt][ct], 0, 0, 0);
+            acc[rt][ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[1][rt], bmid, acc[rt][ct], 0, 0, 0);
+            acc[rt][ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[1][rt], bhi, acc[rt][ct], 0, 0, 0);
+            acc[rt][ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[0][rt], bmid, acc[rt][ct], 0, 0, 0);
+          }
+        }
         if (NT == 3) {
           const bf16x8 blo = *reinterpret_cast<const bf16x8 *>(&Bs[NP - 1][brow]);
 #pragma unroll
@@ -275,28 +329,38 @@ reduce_splits_f32(const float *__restrict__ part, int splits, int64_t split_stri
 }
 
 // xt[j][k] = bf16(x[k][j]) for j < N, k < K; zero in the padding
-// (j < n_pad, k < k_pad).  With a second plane (lo != nullptr) the remainder
-// x - hi is rounded to BF16 there.  64 x 64 tiles through LDS.
+// (j < n_pad, k < k_pad), planes `planes` apart.  nt = 1: one plane, x
+// rounded to BF16.  nt = 3: a second plane with the remainder x - hi rounded
+// to BF16.  nt = 6: x rounded to FP32, then split exactly into three BF16
+// parts by truncation (bf16_split3), one per plane.  64 x 64 tiles through
+// LDS.
 __global__ void __launch_bounds__(256)
 pack_bf16_t(const double *__restrict__ x, int64_t ldx, int K, int N, uint16_t *__restrict__ xt,
-            uint16_t *__restrict__ lo, int64_t ldt, int n_pad, int k_pad) {
-  __shared__ uint16_t tile[2][64][66];
+            int64_t planes, int nt, int64_t ldt, int n_pad, int k_pad) {
+  __shared__ uint16_t tile[3][64][66];
   const int k0 = blockIdx.x * 64, j0 = blockIdx.y * 64;
   const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
   for (int r = ty; r < 64; r += 4) {          // read rows k of x, columns j
     const int k = k0 + r, j = j0 + tx;
     const double v = (k < K && j < N) ? x[(int64_t)k * ldx + j] : 0.0;
-    const uint16_t h = bf16_rne(v);
-    tile[0][r][tx] = h;
-    tile[1][r][tx] = bf16_rne(v - (double)__uint_as_float((uint32_t)h << 16));
+    if (nt == 6) {
+      uint16_t h, m, l;
+      bf16_split3((float)v, h, m, l);
+      tile[0][r][tx] = h;
+      tile[1][r][tx] = m;
+      tile[2][r][tx] = l;
+    } else {
+      const uint16_t h = bf16_rne(v);
+      tile[0][r][tx] = h;
+      tile[1][r][tx] = bf16_rne(v - (double)__uint_as_float((uint32_t)h << 16));
+    }
   }
   __syncthreads();
+  const int np = nt == 1 ? 1 : (nt == 3 ? 2 : 3);
   for (int r = ty; r < 64; r += 4) {          // write rows j of xt, columns k
     const int j = j0 + r, k = k0 + tx;
-    if (j < n_pad && k < k_pad) {
-      xt[(int64_t)j * ldt + k] = tile[0][tx][r];
-      if (lo) lo[(int64_t)j * ldt + k] = tile[1][tx][r];
-    }
+    if (j < n_pad && k < k_pad)
+      for (int q = 0; q < np; ++q) xt[q * planes + (int64_t)j * ldt + k] = tile[q][tx][r];
   }
 }
 
@@ -311,7 +375,7 @@ int grid_cap_b(int64_t work) {
 
 BfPlan plan_gemm_tbf16(int M, int N, int K, int num_cus, int force_splits, int nt) {
   BfPlan p{};
-  const int bKT = nt == 3 ? 32 : 64;
+  const int bKT = nt == 1 ? 64 : 32;
   p.nt = nt;
   p.gm = ceil_div(M, bBM);
   p.gn = ceil_div(N, bBN);
@@ -334,9 +398,8 @@ BfPlan plan_gemm_tbf16(int M, int N, int K, int num_cus, int force_splits, int n
 hipError_t launch_pack_bf16(const BfPlan &p, const double *x, int64_t ldx, int K, int N,
                             uint16_t *xt, hipStream_t st) {
   dim3 grid(ceil_div(p.k_pad, 64), ceil_div(p.n_pad, 64));
-  uint16_t *lo = p.nt == 3 ? xt + p.plane() : nullptr;
-  hipLaunchKernelGGL(pack_bf16_t, grid, dim3(256), 0, st, x, ldx, K, N, xt, lo, p.ldx, p.n_pad,
-                     p.k_pad);
+  hipLaunchKernelGGL(pack_bf16_t, grid, dim3(256), 0, st, x, ldx, K, N, xt, (int64_t)p.plane(),
+                     p.nt, p.ldx, p.n_pad, p.k_pad);
   return hipGetLastError();
 }
 
@@ -349,8 +412,12 @@ hipError_t launch_gemm_tbf16(const BfPlan &p, bool trans_a, const float *A, int6
   hipLaunchKernelGGL((gemm_tbf16_mfma<TA, V, NT>), grid, dim3(256), 0, st, A, lda, xt, p.ldx, \
                      (int64_t)p.plane(), part, p.ldc, p.split_stride, M, N, K, p.k_per_split,  \
                      p.gm, p.splits)
-#define SSI_BF_NT(TA, V) \
-  do { if (p.nt == 3) SSI_BF(TA, V, 3); else SSI_BF(TA, V, 1); } while (0)
+#define SSI_BF_NT(TA, V)                                                  \
+  do {                                                                    \
+    if (p.nt == 6) SSI_BF(TA, V, 6);                                      \
+    else if (p.nt == 3) SSI_BF(TA, V, 3);                                 \
+    else SSI_BF(TA, V, 1);                                                \
+  } while (0)
   if (trans_a) {
     if (vec) SSI_BF_NT(true, true); else SSI_BF_NT(true, false);
   } else {

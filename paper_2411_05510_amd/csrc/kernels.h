@@ -85,10 +85,11 @@ struct BfPlan {
   int64_t ldc, split_stride;     // FP32 partial sums: [splits][M][ldc]
   int n_pad, k_pad;              // BF16 operand X^T: n_pad x k_pad (ld ldx), zero-padded
   int64_t ldx;
-  int nt;                        // 1: one BF16 product; 3: split (hi + lo) operands
+  int nt;                        // 1: one BF16 product; 3: split (hi + lo) operands;
+                                 // 6: exact three-way splits, six products
   size_t part_elems() const { return (size_t)splits * (size_t)split_stride; }
   size_t plane() const { return (size_t)n_pad * (size_t)ldx; }
-  size_t xt_elems() const { return plane() * (nt == 3 ? 2 : 1); }
+  size_t xt_elems() const { return plane() * (nt == 1 ? 1 : (nt == 3 ? 2 : 3)); }
 };
 BfPlan plan_gemm_tbf16(int M, int N, int K, int num_cus, int splits = 0, int nt = 1);
 hipError_t launch_pack_bf16(const BfPlan &p, const double *x, int64_t ldx, int K, int N,

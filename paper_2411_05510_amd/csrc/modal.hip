@@ -829,11 +829,12 @@ SSI_DEV void francis_order(int o, double *A, const double *__restrict__ hbuf, in
     }
   }
   for (int i = t; i < 2 * kRing; i += kFT) A[psz + i] = 0.0;
+  __syncthreads();
   // a non-finite entry would never deflate: fail the order at once instead
-  // of running to the iteration limit
+  // of running to the iteration limit (read after the barrier: the copy
+  // above is spread over all threads)
   int nonfinite = 0;
   for (int i = t; i < psz; i += kFT) nonfinite |= !isfinite(A[i]);
-  __syncthreads();
   nonfinite = block_max_int(nonfinite, red);
 
   const double eps = 2.220446049250313e-16;

@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(HERE, "libssicov.so")
 
 SSI_OK, SSI_EINVAL, SSI_ENOMEM, SSI_EDEVICE, SSI_ENOCONV, SSI_EINTERNAL, SSI_EBUSY = range(7)
 SVD_FULL, SVD_RANDOMIZED = 0, 1
-PREC_FP32, PREC_BF16, PREC_BF16X3 = 0, 1, 2
+PREC_FP32, PREC_BF16, PREC_BF16X3, PREC_BF16X6 = 0, 1, 2, 3
 CORR_FP32, CORR_BF16X6 = 0, 1
 
 # Every symbol include/ssicov.h declares.
@@ -67,6 +67,7 @@ class _Params(ctypes.Structure):
         ("prec", ctypes.c_int32),
         ("omega", ctypes.c_void_p),
         ("omega_ld", ctypes.c_int64),
+        ("refine", ctypes.c_int32),
     ]
 
 
@@ -230,6 +231,7 @@ class Params:
     seed: int = 0
     prec: int = PREC_FP32
     omega: object = None        # optional caller sketch: device tensor (m_max, k + p) float32
+    refine: int = 0             # reduced precision: last `refine` power iterations in full precision
 
     def c(self) -> _Params:
         arr = (ctypes.c_int32 * len(self.lags))(*[int(v) for v in self.lags])
@@ -238,7 +240,8 @@ class Params:
         p = _Params(float(self.fs), arr, len(self.lags), int(self.order_min),
                     int(self.order_max), int(self.order_step), int(self.svd),
                     int(self.rank), int(self.oversample), int(self.power_iters),
-                    int(self.seed) & 0xFFFFFFFFFFFFFFFF, int(self.prec), om, ld)
+                    int(self.seed) & 0xFFFFFFFFFFFFFFFF, int(self.prec), om, ld,
+                    int(self.refine))
         p._keep = arr  # keep the lag array alive with the struct
         return p
 

@@ -125,3 +125,42 @@ def test_svd_full(ctx, m, k):
     ur, sr = oracle.full_svd(t32.astype(np.float64), k)
     _check_sigma(s.cpu().numpy(), sr)
     _check_subspace(u.cpu().numpy(), ur, sr, min(k, 10), 1e-7)
+
+
+@pytest.mark.parametrize("svd", ["randomized", "full"])
+def test_exactly_low_rank_toeplitz(ctx, svd):
+    """Exact correlations of a 4-mode model: T (120 x 120) has rank 8, and with
+    k = 40 the 32 trailing singular values are a cluster at the rounding level
+    of the FP32 matrix.  U must still be orthonormal (the eigensolver
+    orthogonalizes the vectors of clustered eigenvalues), the modal stage must
+    run at orders past the rank without a breakdown, and the order-8 poles are
+    the generated modes."""
+    from modelref import mac, modal_correlations
+    from paper_2411_05510_amd import ssicov
+    wl = synth.WORKLOADS["small-full-svd"]
+    sysm = synth.draw_system(wl.l, wl.n_modes, wl.f_range, wl.zeta_range, wl.fs,
+                             wl.struct_seed)
+    jb, k = 10, 40
+    t32 = oracle.toeplitz(modal_correlations(sysm, 2 * jb - 1), jb).astype(np.float32)
+    if svd == "randomized":
+        u, s = _run_rsvd(ctx, t32, k, 8, 1, seed=5)
+    else:
+        ud, sd = ctx.svd_full(_dev(t32), k)
+        ctx.synchronize()
+        u, s = ud.cpu().numpy(), sd.cpu().numpy()
+    orth = np.abs(u.T @ u - np.eye(k)).max()
+    print(f"{svd}: sigma_9 / sigma_1 = {s[8] / s[0]:.2e}, max |U^T U - I| = {orth:.2e}")
+    assert s[8] < 1e-6 * s[0]
+    assert orth <= 1e-8
+    p = ssicov.Params(fs=wl.fs, lags=[jb], order_min=2, order_max=k, order_step=2,
+                      svd=ssicov.SVD_RANDOMIZED, rank=k)
+    out = ctx.alloc_output(p, wl.l, 1000)
+    ctx.modal(_dev(u), _dev(s), wl.l, p, 0, out)
+    ctx.synchronize()
+    g = out.poles(0, 3)                       # order 8 = 2 x modes
+    assert g["flag"] == 0
+    np.testing.assert_allclose(np.sort(g["f"]), np.sort(sysm.freqs), rtol=1e-5)
+    for r in range(wl.n_modes):
+        j = int(np.argmin(np.abs(g["f"] - sysm.freqs[r])))
+        assert mac(g["phi"][j], sysm.shapes[:, r]) > 1 - 1e-6
+    assert int(out.flags.sum().item()) == 0
