@@ -376,6 +376,8 @@ SSI_DEV bool small_eig(double *a, int m, double *er, double *ei, int lane, doubl
     ++iter;
     double sh, tt;
     if (iter % 11 == 10) {
+      // exceptional shift after ten sweeps without deflation, with the
+      // constants 3/4 and -0.4375 of LAPACK's DLAHQR
       const double e = fabs(a[hi * kSM + hi - 1]) + fabs(a[(hi - 1) * kSM + hi - 2]);
       const double h11 = 0.75 * e + a[hi * kSM + hi], h12 = -0.4375 * e;
       sh = 2.0 * h11;
@@ -961,6 +963,7 @@ SSI_DEV void francis_order(int o, double *A, const double *__restrict__ hbuf, in
     if (nb == 1 && t == 0) {
       double sh, tt;
       if (iter % 11 == 10) {
+        // exceptional shift (constants 3/4 and -0.4375 of LAPACK's DLAHQR)
         const double e = fabs(A[ix(hi, hi - 1)]) + fabs(A[ix(hi - 1, hi - 2)]);
         const double h11 = 0.75 * e + A[ix(hi, hi)], h12 = -0.4375 * e;
         sh = 2.0 * h11;
