@@ -293,6 +293,78 @@ def bench_identify(args) -> dict:
     return rec
 
 
+# ------------------------------------------------------------ small record
+def bench_small(args) -> dict:
+    """The 12-channel record with the exact SVD (240 x 240 Toeplitz): a
+    latency line (identifications/s and p50/p99 per identification), with
+    the FP64 checker timed on all host threads and on one."""
+    import numpy as np
+    import torch
+    from paper_2411_05510_amd import ssicov, synth
+
+    wl = synth.WORKLOADS["small-full-svd"]
+    _, y = synth.make_record(wl)
+    dev = torch.device("cuda:0")
+    yd = torch.from_numpy(y).to(dev)
+    p = ssicov.Params(fs=wl.fs, lags=list(wl.lags), order_min=wl.order_min,
+                      order_max=wl.order_max, order_step=wl.order_step, svd=ssicov.SVD_FULL)
+    ctx = ssicov.Context(0)
+    out = ctx.alloc_output(p, wl.l, wl.n)
+    stream = torch.cuda.current_stream(dev)
+    for _ in range(args.warmup):
+        ctx.identify(yd, p, out)
+    ctx.synchronize()
+    elapsed, step_ms, stages = timed_steps(ctx, lambda: ctx.identify(yd, p, out), args.steps,
+                                           stream)
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+
+        def run_oracle():
+            t1 = time.perf_counter()
+            oracle.identify(y, wl.fs, wl.lags, wl.orders, svd="full")
+            return time.perf_counter() - t1
+
+        all_s = run_oracle()
+        one_s = None
+        try:
+            from threadpoolctl import threadpool_limits
+            with threadpool_limits(limits=1):
+                one_s = run_oracle()
+        except ImportError:
+            pass
+        cpu = {"value": 1.0 / all_s, "unit": "identifications/s", "cores": blas_threads(),
+               "cpu_model": cpu_model(), "kind": "oracle",
+               "one_thread_value": None if one_s is None else 1.0 / one_s,
+               "sample": f"one full identification of the same record (FP64 numpy checker with "
+                         f"its one-sided Jacobi SVD): {all_s:.2f} s on all threads"
+                         + ("" if one_s is None else f", {one_s:.2f} s on one thread")}
+    rec = {
+        "metric": "SSI-COV identifications/s, 12 ch, i=20, exact SVD",
+        "value": args.steps / elapsed,
+        "unit": "identifications/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1000.0 * elapsed / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": "small-full-svd: l=12, N=20000 at 50 Hz, j_b=20 (240x240 Toeplitz), "
+                        "exact SVD (FP64 eigen-decomposition of T T^T), orders 2..40 step 2",
+            "latency_ms_p50": float(np.percentile(step_ms, 50)),
+            "latency_ms_p99": float(np.percentile(step_ms, 99)),
+            "stage_ms_per_step": {k: v[0] / args.steps for k, v in stages.items()},
+        },
+        "cpu_baseline": cpu,
+    }
+    ctx.close()
+    return rec
+
+
 # ------------------------------------------------------------ 3D diagram
 def bench_3d(args) -> dict:
     import numpy as np
@@ -458,7 +530,7 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="bridge-180ch",
-                    choices=("bridge-180ch", "bridge-180ch-3d", "serving"))
+                    choices=("bridge-180ch", "bridge-180ch-3d", "serving", "small-full-svd"))
     ap.add_argument("--prec", default="fp32", choices=tuple(PRECS))
     ap.add_argument("--refine", type=int, default=None,
                     help="full-precision refinement power steps of a reduced-precision range "
@@ -482,7 +554,7 @@ def main() -> int:
               "(one process, one device)", file=sys.stderr)
         return 2
     fn = {"bridge-180ch": bench_identify, "bridge-180ch-3d": bench_3d,
-          "serving": bench_serving}[args.workload]
+          "serving": bench_serving, "small-full-svd": bench_small}[args.workload]
     print(json.dumps(fn(args)), flush=True)
     return 0
 
