@@ -198,8 +198,10 @@ enum {
   SSI_STAGE_PRODUCTS,        /* T X and T^T X products (incl. reduce)   */
   SSI_STAGE_ORTH,            /* CholeskyQR orthonormalisations          */
   SSI_STAGE_SMALL_SVD,       /* P P^T, eigen-decomposition, U = Q U~    */
-  SSI_STAGE_SHIFT_LS,        /* Gram matrices, Cholesky, W              */
-  SSI_STAGE_EIG,             /* per-order Hessenberg, QR, poles         */
+  SSI_STAGE_SHIFT_LS,        /* Gram matrices, Cholesky, W, X_n and their
+                                Hessenberg forms (per lag)              */
+  SSI_STAGE_EIG,             /* QR iterations, poles and sorting of every
+                                (lag, order), one launch                */
   SSI_STAGE_CORR_SPLIT,      /* BF16 parts of the record (BF16x6 mode)  */
   SSI_STAGE_COUNT
 };
@@ -207,12 +209,14 @@ ssi_status ssi_set_profiling(ssi_ctx *ctx, int enable);
 ssi_status ssi_profile_read(ssi_ctx *ctx, double *ms, int32_t *calls, int32_t n_stages);
 
 /* Lag sweep of the 3D stabilization diagram (Section 2.3, step i) over n
- * streams (1 <= n <= 4, default 1).  With n > 1, ssi_identify computes the
- * correlations once on the context stream, then runs lag i (Toeplitz, SVD and
- * modal stage) on internal stream i % n, each with its own buffers, and makes
- * the context stream wait for all of them before later work: results are
- * identical to n = 1; lags of different streams overlap on the device.  The
- * internal streams are created here (default priority, non-blocking).
+ * streams (1 <= n <= 4, default 1).  ssi_identify computes the correlations
+ * once on the context stream and prepares every lag (Toeplitz, SVD, shift
+ * least squares, Hessenberg forms); with n > 1 lag i is prepared on internal
+ * stream i % n, each with its own buffers, and the context stream waits for
+ * all of them.  The eigen-analysis, poles and sorting of every (lag, order)
+ * then run in one persistent launch on the context stream.  Results are
+ * identical for every n; lags of different streams overlap on the device.
+ * The internal streams are created here (default priority, non-blocking).
  * Synchronizes the context stream. */
 ssi_status ssi_set_lag_streams(ssi_ctx *ctx, int32_t n);
 /* Graph mode for ssi_identify (default off).  When on, every ssi_identify

@@ -841,21 +841,28 @@ ssi_status run_svd_full(ssi_ctx *c, FullBufs &b, const float *t, int m, int64_t 
 }
 
 // ------------------------------------------------------------ modal stage
-struct ModalBufs {
+// Per-lane buffers of the shift least squares and the order matrices X_n
+// (reused by the lags of a lane one after another).
+struct ModalLane {
+  double *gt, *hm, *rinv, *lws, *w, *dws, *part, *xbuf;
+};
+
+// Buffers of the eigen-analysis, one slot per lag of the launch (lag g at g
+// times each buffer's per-lag size), plus the per-wave scratch of the launch.
+struct ModalShared {
   ssi::ModalSizes sz;
-  double *gt, *hm, *rinv, *lws, *w, *dws, *part;
-  double *xbuf, *hbuf, *vref, *taus, *evbuf, *gscr, *vscr;
-  double *tf, *txi, *tmu, *tphi;
+  int n_lags, ldu;
+  double *hbuf, *vref, *taus, *evbuf, *gscr, *vscr;
+  double *tf, *txi, *tmu, *tphi, *uhead;
   int *npole, *pidx, *flags_tmp;
   int *queue, *done;
 };
 
-ModalBufs carve_modal(Arena &a, ssi_ctx *c, int64_t m, int l, const ssi_params *p) {
-  ModalBufs b{};
-  const int nmax = p->order_max;
-  b.sz = ssi::modal_sizes(p->order_min, nmax, p->order_step, l);
+ModalLane carve_modal_lane(Arena &a, ssi_ctx *c, int64_t m, int l, const ssi_params *p) {
+  ModalLane b{};
+  const int kk = p->order_max;               // leading columns used by the orders
   const int cu = c->num_cus;
-  const int kk = nmax;                       // leading columns used by the orders
+  const ssi::ModalSizes sz = ssi::modal_sizes(p->order_min, kk, p->order_step, l);
   b.gt = a.take<double>((size_t)kk * kk);
   b.hm = a.take<double>((size_t)kk * kk);
   b.rinv = a.take<double>((size_t)kk * kk);
@@ -863,73 +870,103 @@ ModalBufs carve_modal(Arena &a, ssi_ctx *c, int64_t m, int l, const ssi_params *
   b.w = a.take<double>((size_t)kk * kk);
   b.dws = a.take<double>(ssi::dense_ws_doubles(kk));
   b.part = a.take<double>(std::max(part_f64(kk, kk, (int)(m - l), cu), part_f64(kk, kk, kk, cu)));
-  b.xbuf = a.take<double>(b.sz.sq);
-  b.hbuf = a.take<double>(b.sz.sq);
-  b.vref = a.take<double>(b.sz.vref);
-  b.taus = a.take<double>(b.sz.taus);
-  b.evbuf = a.take<double>(2 * b.sz.vec);
-  b.gscr = a.take<double>((size_t)b.sz.n_orders * b.sz.francis_glb);
-  b.vscr = a.take<double>((size_t)b.sz.vec_waves * b.sz.vec_stride);
-  b.tf = a.take<double>(b.sz.poles);
-  b.txi = a.take<double>(b.sz.poles);
-  b.tmu = a.take<double>(2 * b.sz.poles);
-  b.tphi = a.take<double>(2 * b.sz.poles * l);
-  b.npole = a.take<int>(b.sz.n_orders);
-  b.pidx = a.take<int>(b.sz.vec);
-  b.flags_tmp = a.take<int>(b.sz.n_orders);
-  b.queue = a.take<int>(2);
-  b.done = a.take<int>(b.sz.n_orders);
+  b.xbuf = a.take<double>(sz.sq);
   return b;
 }
 
-// U: m x k (ld k).  Writes lag slot lag_i of out.
-ssi_status run_modal(ssi_ctx *c, ModalBufs &b, const double *u, int64_t m, int k, int l,
-                     const ssi_params *p, int lag_i, const ssi_output *out) {
-  const int kk = p->order_max, mt = (int)(m - l);
-  hipError_t e;
-  {
-    StageTimer tm_ls(c, SSI_STAGE_SHIFT_LS);
-    // Gram matrices of the shifted observability blocks (leading kk columns)
-    e = prod_f64(c, true, u, k, u, k, kk, kk, mt, b.part, b.gt, kk);
-    if (e != hipSuccess) return hip_fail(e, "U_top^T U_top");
-    e = prod_f64(c, true, u, k, u + (int64_t)l * k, k, kk, kk, mt, b.part, b.hm, kk);
-    if (e != hipSuccess) return hip_fail(e, "U_top^T U_bot");
-    e = ssi::launch_chol_inv(b.gt, kk, kk, 0.0, b.rinv, kk, b.lws, b.dws, c->status, c->stream);
-    if (e != hipSuccess) return hip_fail(e, "Cholesky of U_top^T U_top");
-    e = prod_f64(c, true, b.rinv, kk, b.hm, kk, kk, kk, kk, b.part, b.w, kk);
-    if (e != hipSuccess) return hip_fail(e, "W = R^-T H");
-  }
-  const int no = b.sz.n_orders;
-  int32_t pole_cap = 0;
-  for (int o = 0; o < no; ++o) pole_cap += (p->order_min + o * p->order_step) / 2;
+// ldu: columns of U (k); the first l rows of each lag's U are copied into
+// uhead, so the mode shapes of every lag are read from one place.
+ModalShared carve_modal_shared(Arena &a, int l, const ssi_params *p, int ldu, int n_lags) {
+  ModalShared b{};
+  b.sz = ssi::modal_sizes(p->order_min, p->order_max, p->order_step, l);
+  b.n_lags = n_lags;
+  b.ldu = ldu;
+  const size_t g = (size_t)n_lags;
+  b.hbuf = a.take<double>(g * b.sz.sq);
+  b.vref = a.take<double>(g * b.sz.vref);
+  b.taus = a.take<double>(g * b.sz.taus);
+  b.evbuf = a.take<double>(g * 2 * b.sz.vec);
+  b.gscr = a.take<double>(g * b.sz.n_orders * b.sz.francis_glb);
+  b.vscr = a.take<double>((size_t)b.sz.vec_waves * b.sz.vec_stride);
+  b.tf = a.take<double>(g * b.sz.poles);
+  b.txi = a.take<double>(g * b.sz.poles);
+  b.tmu = a.take<double>(g * 2 * b.sz.poles);
+  b.tphi = a.take<double>(g * 2 * b.sz.poles * l);
+  b.uhead = a.take<double>(g * l * ldu);
+  b.npole = a.take<int>(g * b.sz.n_orders);
+  b.pidx = a.take<int>(g * b.sz.vec);
+  b.flags_tmp = a.take<int>(g * b.sz.n_orders);
+  b.queue = a.take<int>(2);
+  b.done = a.take<int>(g * b.sz.n_orders);
+  return b;
+}
+
+ssi::ModalArgs modal_args(ssi_ctx *c, const ModalShared &sh, int l, const ssi_params *p) {
   ssi::ModalArgs a{};
-  a.sizes = b.sz;
+  a.sizes = sh.sz;
   a.nmin = p->order_min;
   a.step = p->order_step;
-  a.ldw = kk;
-  a.ldu = k;
+  a.n_lags = sh.n_lags;
+  a.ldw = p->order_max;
+  a.ldu = sh.ldu;
   a.l = l;
   a.fs = p->fs;
-  a.u = u;                    // mode shapes use U[0:l, :n]
+  a.u = sh.uhead;
+  a.hbuf = sh.hbuf; a.vref = sh.vref; a.taus = sh.taus;
+  a.evbuf = sh.evbuf; a.gscr = sh.gscr; a.vscr = sh.vscr;
+  a.tf = sh.tf; a.txi = sh.txi; a.tmu = sh.tmu; a.tphi = sh.tphi;
+  a.npole = sh.npole; a.pidx = sh.pidx; a.flags_tmp = sh.flags_tmp;
+  a.queue = sh.queue; a.done = sh.done; a.status = c->status;
+  a.sweeps_per_row = c->sweeps_per_row;
+  return a;
+}
+
+// Shift least squares and Hessenberg forms of every order of one lag into
+// lag slot `slot` of sh.  U: m x k (ld k).
+ssi_status run_modal_prep(ssi_ctx *c, ModalLane &b, ModalShared &sh, const double *u, int64_t m,
+                          int k, int l, const ssi_params *p, int slot) {
+  const int kk = p->order_max, mt = (int)(m - l);
+  hipError_t e;
+  StageTimer tm_ls(c, SSI_STAGE_SHIFT_LS);
+  // Gram matrices of the shifted observability blocks (leading kk columns)
+  e = prod_f64(c, true, u, k, u, k, kk, kk, mt, b.part, b.gt, kk);
+  if (e != hipSuccess) return hip_fail(e, "U_top^T U_top");
+  e = prod_f64(c, true, u, k, u + (int64_t)l * k, k, kk, kk, mt, b.part, b.hm, kk);
+  if (e != hipSuccess) return hip_fail(e, "U_top^T U_bot");
+  e = ssi::launch_chol_inv(b.gt, kk, kk, 0.0, b.rinv, kk, b.lws, b.dws, c->status, c->stream);
+  if (e != hipSuccess) return hip_fail(e, "Cholesky of U_top^T U_top");
+  e = prod_f64(c, true, b.rinv, kk, b.hm, kk, kk, kk, kk, b.part, b.w, kk);
+  if (e != hipSuccess) return hip_fail(e, "W = R^-T H");
+  ssi::ModalArgs a = modal_args(c, sh, l, p);
   a.rinv = b.rinv;
   a.w = b.w;
-  a.xbuf = b.xbuf; a.hbuf = b.hbuf; a.vref = b.vref; a.taus = b.taus;
-  a.evbuf = b.evbuf; a.gscr = b.gscr; a.vscr = b.vscr;
-  a.tf = b.tf; a.txi = b.txi; a.tmu = b.tmu; a.tphi = b.tphi;
-  a.npole = b.npole; a.pidx = b.pidx; a.flags_tmp = b.flags_tmp;
-  a.queue = b.queue; a.done = b.done; a.status = c->status;
-  // with lags on several streams, a grid of one workgroup per order leaves
-  // the other CUs to the other lags' kernels
-  a.eig_grid = std::min(c->n_lanes, p->n_lags) > 1 ? no : 0;
-  a.sweeps_per_row = c->sweeps_per_row;
-  a.count = out->count + (int64_t)lag_i * no;
-  a.flags = out->flags + (int64_t)lag_i * no;
-  a.f = out->f + (int64_t)lag_i * pole_cap;
-  a.xi = out->xi + (int64_t)lag_i * pole_cap;
-  a.mu = out->mu + 2 * (int64_t)lag_i * pole_cap;
-  a.phi = out->phi + 2 * (int64_t)lag_i * pole_cap * l;
+  a.xbuf = b.xbuf;
+  e = ssi::launch_modal_prep(a, slot, c->stream);
+  if (e != hipSuccess) return hip_fail(e, "Hessenberg reduction");
+  // mode shapes use U[0:l, :n]
+  e = hipMemcpy2DAsync(sh.uhead + (int64_t)slot * l * sh.ldu, sizeof(double) * sh.ldu, u,
+                       sizeof(double) * k, sizeof(double) * sh.ldu, (size_t)l,
+                       hipMemcpyDeviceToDevice, c->stream);
+  if (e != hipSuccess) return hip_fail(e, "mode-shape rows");
+  return SSI_OK;
+}
+
+// Eigen-analysis, poles and sorting of the sh.n_lags prepared lags in one
+// launch; slot g goes to lag slot lag0 + g of out.
+ssi_status run_modal_eig(ssi_ctx *c, ModalShared &sh, int l, const ssi_params *p, int lag0,
+                         const ssi_output *out, int eig_grid) {
+  const int no = sh.sz.n_orders;
+  const int64_t pole_cap = sh.sz.poles;
+  ssi::ModalArgs a = modal_args(c, sh, l, p);
+  a.eig_grid = eig_grid;
+  a.count = out->count + (int64_t)lag0 * no;
+  a.flags = out->flags + (int64_t)lag0 * no;
+  a.f = out->f + (int64_t)lag0 * pole_cap;
+  a.xi = out->xi + (int64_t)lag0 * pole_cap;
+  a.mu = out->mu + 2 * (int64_t)lag0 * pole_cap;
+  a.phi = out->phi + 2 * (int64_t)lag0 * pole_cap * l;
   StageTimer tm_eig(c, SSI_STAGE_EIG);
-  e = ssi::launch_modal(a, c->stream);
+  const hipError_t e = ssi::launch_modal_eig(a, c->stream);
   if (e != hipSuccess) return hip_fail(e, "modal kernels");
   return SSI_OK;
 }
@@ -942,7 +979,7 @@ struct LaneBufs {
   double *u, *sig;
   RsvdBufs rb;
   FullBufs fb;
-  ModalBufs mb;
+  ModalLane mb;
 };
 
 struct IdentBufs {
@@ -953,6 +990,7 @@ struct IdentBufs {
   float *r;
   int n_lanes;
   LaneBufs lane[kMaxLanes];
+  ModalShared ms;                     // every lag's eigen-analysis, one launch
 };
 
 int lanes_for(const ssi_ctx *c, const ssi_params *p) { return std::min(c->n_lanes, p->n_lags); }
@@ -982,14 +1020,17 @@ IdentBufs carve_identify(Arena &a, ssi_ctx *c, int l, int64_t n, const ssi_param
                          (int)ms.size());
     else
       lb.fb = carve_full(a, c, (int)mmax);
-    lb.mb = carve_modal(a, c, mmax, l, p);
+    lb.mb = carve_modal_lane(a, c, mmax, l, p);
   }
+  b.ms = carve_modal_shared(a, l, p, kcols, p->n_lags);
   return b;
 }
 
-// Enqueues one lag (Toeplitz, SVD, modal stage) on c->stream.
-ssi_status run_lag(ssi_ctx *c, LaneBufs &b, const float *r, int l, const ssi_params *p, int i,
-                   const ssi_output *out) {
+// Enqueues one lag (Toeplitz, SVD, shift least squares and Hessenberg forms
+// into lag slot i of ms) on c->stream; the eigen-analysis of all lags follows
+// in one launch.
+ssi_status run_lag(ssi_ctx *c, LaneBufs &b, ModalShared &ms, const float *r, int l,
+                   const ssi_params *p, int i, const ssi_output *out) {
   const int jb = p->lags[i];
   const int64_t m = (int64_t)jb * l;
   const int64_t ldt = (m + 3) & ~int64_t(3);
@@ -1011,7 +1052,7 @@ ssi_status run_lag(ssi_ctx *c, LaneBufs &b, const float *r, int l, const ssi_par
   e = hipMemcpyAsync(out->sigma + (int64_t)i * kcols, b.sig, sizeof(double) * kcols,
                      hipMemcpyDeviceToDevice, c->stream);
   if (e != hipSuccess) return hip_fail(e, "sigma copy");
-  return run_modal(c, b.mb, b.u, m, kcols, l, p, i, out);
+  return run_modal_prep(c, b.mb, ms, b.u, m, kcols, l, p, i);
 }
 
 // Points c->stream at another stream for the lifetime of the guard.
@@ -1043,29 +1084,31 @@ ssi_status run_identify(ssi_ctx *c, IdentBufs &b, const float *y, int l, int64_t
   if (e != hipSuccess) return hip_fail(e, "correlation reduction");
   if (b.n_lanes == 1) {
     for (int i = 0; i < p->n_lags; ++i) {
-      ssi_status s = run_lag(c, b.lane[0], b.r, l, p, i, out);
+      ssi_status s = run_lag(c, b.lane[0], b.ms, b.r, l, p, i, out);
       if (s != SSI_OK) return s;
     }
-    return SSI_OK;
+  } else {
+    // Several lanes: fork after the correlations and join before the
+    // eigen-analysis.  Lags of different lanes overlap on the device (the
+    // latency-bound factorizations of one lag run beside the products of
+    // the next).
+    hipStream_t main = c->stream;
+    SSI_HIP(hipEventRecord(c->fork_ev, main));
+    for (int s = 0; s < b.n_lanes; ++s) SSI_HIP(hipStreamWaitEvent(c->lanes[s], c->fork_ev, 0));
+    ssi_status st = SSI_OK;
+    for (int i = 0; i < p->n_lags && st == SSI_OK; ++i) {
+      const int s = i % b.n_lanes;
+      StreamSwap sw(c, c->lanes[s]);
+      st = run_lag(c, b.lane[s], b.ms, b.r, l, p, i, out);
+    }
+    for (int s = 0; s < b.n_lanes; ++s) {
+      SSI_HIP(hipEventRecord(c->join_ev[s], c->lanes[s]));
+      SSI_HIP(hipStreamWaitEvent(main, c->join_ev[s], 0));
+    }
+    if (st != SSI_OK) return st;
   }
-  // Several lanes: fork after the correlations, join before returning, so the
-  // caller's stream sees one ordered identification.  Lags of different
-  // lanes overlap on the device (the latency-bound modal stage of one lag
-  // runs beside the products of the next).
-  hipStream_t main = c->stream;
-  SSI_HIP(hipEventRecord(c->fork_ev, main));
-  for (int s = 0; s < b.n_lanes; ++s) SSI_HIP(hipStreamWaitEvent(c->lanes[s], c->fork_ev, 0));
-  ssi_status st = SSI_OK;
-  for (int i = 0; i < p->n_lags && st == SSI_OK; ++i) {
-    const int s = i % b.n_lanes;
-    StreamSwap sw(c, c->lanes[s]);
-    st = run_lag(c, b.lane[s], b.r, l, p, i, out);
-  }
-  for (int s = 0; s < b.n_lanes; ++s) {
-    SSI_HIP(hipEventRecord(c->join_ev[s], c->lanes[s]));
-    SSI_HIP(hipStreamWaitEvent(main, c->join_ev[s], 0));
-  }
-  return st;
+  // every (lag, order) of the diagram in one persistent launch
+  return run_modal_eig(c, b.ms, l, p, 0, out, 0);
 }
 
 }  // namespace
@@ -1197,12 +1240,16 @@ ssi_status ssi_modal(ssi_ctx *c, const double *u, const double *sigma, int64_t m
   if (lag_index < 0 || lag_index >= p->n_lags) return fail(SSI_EINVAL, "ssi_modal: bad lag index");
   DeviceGuard g(c->device);
   Arena probe;
-  carve_modal(probe, c, m, l, p);
+  carve_modal_lane(probe, c, m, l, p);
+  carve_modal_shared(probe, l, p, k, 1);
   ssi_status s = ws_reserve(c, probe.off);
   if (s != SSI_OK) return s;
   Arena a{c->ws, 0};
-  ModalBufs b = carve_modal(a, c, m, l, p);
-  return run_modal(c, b, u, m, k, l, p, lag_index, out);
+  ModalLane b = carve_modal_lane(a, c, m, l, p);
+  ModalShared sh = carve_modal_shared(a, l, p, k, 1);
+  s = run_modal_prep(c, b, sh, u, m, k, l, p, 0);
+  if (s != SSI_OK) return s;
+  return run_modal_eig(c, sh, l, p, lag_index, out, 0);
 }
 
 }  // extern "C"

@@ -124,11 +124,18 @@ struct ModalSizes {
   int64_t vec_waves, vec_stride, francis_glb;
 };
 ModalSizes modal_sizes(int nmin, int nmax, int step, int l);
+// Per-lag element strides of the modal buffers of a multi-lag launch: lag g's
+// Hessenberg matrices at hbuf + g sq, reflectors at vref + g vref, ..., the
+// first l rows of its U at u + g u.
+struct ModalStrides {
+  int64_t sq, vec, poles, vref, taus, u;
+};
 struct ModalArgs {
   ModalSizes sizes;
   int nmin, step, l;
+  int n_lags;                   // lags of the eigen-analysis launch
   int ldw;                      // leading dimension of rinv and w
-  int ldu;                      // leading dimension of u
+  int ldu;                      // leading dimension of u (the lags' first l rows of U)
   double fs;
   const double *u, *rinv, *w;
   double *xbuf, *hbuf, *vref, *taus, *evbuf, *gscr, *vscr;
@@ -138,11 +145,17 @@ struct ModalArgs {
   int *status;                  // context status word
   int eig_grid;                 // workgroups of the eigen-analysis launch, 0: one per CU
   int sweeps_per_row;           // QR sweep limit per order: sweeps_per_row * max(10, n)
-  int32_t *count, *flags;       // outputs of this lag
+  int32_t *count, *flags;       // outputs of the first lag of the launch
   double *f, *xi, *mu;
   float *phi;
 };
-hipError_t launch_modal(const ModalArgs &a, hipStream_t st);
+ModalStrides modal_strides(const ModalSizes &s, int l, int ldu);
+// X_n for every order (form_x) and their Hessenberg forms into lag slot `lag`
+// (uses rinv, w, xbuf, hbuf, vref, taus).
+hipError_t launch_modal_prep(const ModalArgs &a, int lag, hipStream_t st);
+// QR iterations, poles and sorting of all n_lags lags in one launch; outputs
+// of lag g at the output pointers plus g times the per-lag layout sizes.
+hipError_t launch_modal_eig(const ModalArgs &a, hipStream_t st);
 
 // ---- stability analysis (stability.hip)
 struct StabilityArgs {

@@ -1335,6 +1335,7 @@ static_assert(kFT / 64 * kVecLds <= kLdsDoubles, "pole items fit the workgroup's
 
 __global__ void __launch_bounds__(kFT)
 eig_init_kernel(int *__restrict__ queue, int *__restrict__ done, int n_orders) {
+  // n_orders here counts the (lag, order) items of the launch
   for (int i = threadIdx.x; i < n_orders + 2; i += blockDim.x) {
     if (i < 2) queue[i] = 0;
     else done[i - 2] = 0;
@@ -1350,42 +1351,49 @@ eig_persistent_kernel(const double *__restrict__ hbuf, const double *__restrict_
                       double *__restrict__ vscr, int64_t vstride, double *__restrict__ tf,
                       double *__restrict__ txi, double *__restrict__ tmu,
                       double *__restrict__ tphi, int *__restrict__ queue, int *__restrict__ done,
-                      int *__restrict__ status, int sweeps_per_row) {
+                      int *__restrict__ status, int sweeps_per_row, int n_lags,
+                      ssi::ModalStrides ls) {
   extern __shared__ double lds_h[];
   __shared__ int red[kFT / 64];
   __shared__ int small_ok, item;
   const int t = threadIdx.x, lane = t & 63;
   const int wave = __builtin_amdgcn_readfirstlane(t >> 6);
-  // ---- phase 1: orders, largest first.  The loop exit is a wave-uniform
+  // Work items are (lag, order) pairs of every lag of the launch; lag g's
+  // buffers sit at g times the per-lag stride of each buffer (ls).
+  const int n_items = n_lags * n_orders;
+  // ---- phase 1: orders, largest first across lags.  The loop exit is a wave-uniform
   // (scalar) branch, and thread 0's publish-and-claim is a single region
   // between two barriers: with the item read as a per-lane value, or the
   // claim and the publish as two separate thread-0 regions around the back
   // edge, the compiler may let lanes 1..63 of wave 0 re-enter the body
   // without thread 0 and re-read the old item.
   // Every pass claims a fresh counter value, so a workgroup makes at most
-  // n_orders + 1 claims; the pass count is capped at that all the same, and
+  // n_items + 1 claims; the pass count is capped at that all the same, and
   // a workgroup that reaches the cap sets status bit kStatusClaimCap and stops.
   if (t == 0) item = atomicAdd(&queue[0], 1);
   __syncthreads();
   for (int pass = 0;; ++pass) {
     const int it = __builtin_amdgcn_readfirstlane(item);
     __syncthreads();                                // every wave has read item
-    if (it >= n_orders) break;
-    if (pass > n_orders) {
+    if (it >= n_items) break;
+    if (pass > n_items) {
       if (t == 0) atomicOr(status, ssi::kStatusClaimCap);
       break;
     }
-    const int o = n_orders - 1 - it;
+    const int o = n_orders - 1 - it / n_lags, g = it - (it / n_lags) * n_lags;
+    const double *hb = hbuf + g * ls.sq;
+    double *ev = evbuf + g * 2 * ls.vec;
+    int *np = npole + g * n_orders, *pi = pidx + g * ls.vec, *fl = flags + g * n_orders;
     if (nmin + o * step <= kLdsMaxN)
-      francis_order<true>(o, lds_h, hbuf, nmin, step, evbuf, npole, pidx, flags, red, small_ok,
+      francis_order<true>(o, lds_h, hb, nmin, step, ev, np, pi, fl, red, small_ok,
                           sweeps_per_row, status);
     else
-      francis_order<false>(o, gscr + (size_t)o * gstride, hbuf, nmin, step, evbuf, npole, pidx,
-                           flags, red, small_ok, sweeps_per_row, status);
+      francis_order<false>(o, gscr + ((size_t)g * n_orders + o) * gstride, hb, nmin, step, ev,
+                           np, pi, fl, red, small_ok, sweeps_per_row, status);
     __threadfence();
     __syncthreads();
     if (t == 0) {
-      __hip_atomic_store(&done[o], 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(&done[g * n_orders + o], 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
       item = atomicAdd(&queue[0], 1);
     }
     __syncthreads();
@@ -1398,32 +1406,38 @@ eig_persistent_kernel(const double *__restrict__ hbuf, const double *__restrict_
   const int gw = blockIdx.x * (kFT / 64) + wave;
   double *ure = vscr + (size_t)gw * vstride;
   double *uim = ure + vstride / 2;
+  // pole slots, smallest orders first; within an order, lag by lag
   int total = 0;
-  for (int o = 0; o < n_orders; ++o) total += (nmin + o * step) / 2;
+  for (int o = 0; o < n_orders; ++o) total += n_lags * ((nmin + o * step) / 2);
   for (;;) {
     int it = 0;
     if (lane == 0) it = atomicAdd(&queue[1], 1);
     it = __builtin_amdgcn_readfirstlane(__shfl(it, 0, 64));
     if (it >= total) break;
     int o = 0, rem = it;
-    while (rem >= (nmin + o * step) / 2) {
-      rem -= (nmin + o * step) / 2;
+    while (rem >= n_lags * ((nmin + o * step) / 2)) {
+      rem -= n_lags * ((nmin + o * step) / 2);
       ++o;
     }
+    const int half = (nmin + o * step) / 2;
+    const int g = rem / half, j = rem - g * half;
+    int *dn = done + g * n_orders + o;
     int ready = 0;
     if (lane == 0) {
       long spins = 0;
-      while (!(ready = __hip_atomic_load(&done[o], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT)) &&
+      while (!(ready = __hip_atomic_load(dn, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT)) &&
              ++spins < kEigSpinLimit)
         __builtin_amdgcn_s_sleep(8);
       if (!ready) atomicOr(status, ssi::kStatusPoleWait);
     }
     ready = __builtin_amdgcn_readfirstlane(__shfl(ready, 0, 64));
     if (!ready) continue;
-    (void)__hip_atomic_load(&done[o], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);  // every lane
-    if (rem >= npole[o]) continue;
-    vec_pole(o, rem, hbuf, vref, taus, u, ldu, evbuf, pidx, nmin, step, l, fs, ure, uim, x_re,
-             x_im, mult_re, mult_im, swp, tf, txi, tmu, tphi);
+    (void)__hip_atomic_load(dn, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);  // every lane
+    if (j >= npole[g * n_orders + o]) continue;
+    vec_pole(o, j, hbuf + g * ls.sq, vref + g * ls.vref, taus + g * ls.taus, u + g * ls.u, ldu,
+             evbuf + g * 2 * ls.vec, pidx + g * ls.vec, nmin, step, l, fs, ure, uim, x_re, x_im,
+             mult_re, mult_im, swp, tf + g * ls.poles, txi + g * ls.poles, tmu + g * 2 * ls.poles,
+             tphi + g * 2 * ls.poles * l);
   }
 }
 
@@ -1439,10 +1453,27 @@ sort_kernel(int nmin, int step, int l, const int *__restrict__ npole,
             const double *__restrict__ txi, const double *__restrict__ tmu,
             const double *__restrict__ tphi, int32_t *__restrict__ count,
             int32_t *__restrict__ flags_out, double *__restrict__ f, double *__restrict__ xi,
-            double *__restrict__ mu, float *__restrict__ phi) {
+            double *__restrict__ mu, float *__restrict__ phi, int n_orders, int64_t poles) {
   __shared__ double sf[256], sx[256];
   __shared__ int srank[256];
   const int o = blockIdx.x, t = threadIdx.x;
+  // lag blockIdx.y: its inputs and its output slots at lag times the
+  // per-lag sizes (n_orders counts, poles pole slots)
+  {
+    const int g = blockIdx.y;
+    npole += g * n_orders;
+    flags_in += g * n_orders;
+    count += g * n_orders;
+    flags_out += g * n_orders;
+    tf += g * poles;
+    txi += g * poles;
+    f += g * poles;
+    xi += g * poles;
+    tmu += 2 * g * poles;
+    mu += 2 * g * poles;
+    tphi += 2 * g * poles * l;
+    phi += 2 * g * poles * l;
+  }
   const OrderGeo geo = order_geo(o, nmin, step);
   const int cnt = npole[o];
   const int base = geo.pole;
@@ -1534,39 +1565,59 @@ ModalSizes modal_sizes(int nmin, int nmax, int step, int l) {
   return s;
 }
 
-hipError_t launch_modal(const ModalArgs &a, hipStream_t st) {
+ModalStrides modal_strides(const ModalSizes &s, int l, int ldu) {
+  ModalStrides m{};
+  m.sq = s.sq;
+  m.vec = s.vec;
+  m.poles = s.poles;
+  m.vref = s.vref;
+  m.taus = s.taus;
+  m.u = (int64_t)l * ldu;
+  return m;
+}
+
+hipError_t launch_modal_prep(const ModalArgs &a, int lag, hipStream_t st) {
   const ModalSizes &s = a.sizes;
   const int no = s.n_orders;
-  {
-    const int nmax = a.nmin + (no - 1) * a.step;
-    hipLaunchKernelGGL(form_x_kernel, dim3(ceil_div(nmax * nmax, 256)), dim3(256), 0, st, a.rinv,
-                       a.w, a.ldw, a.nmin, a.step, no, a.xbuf);
-  }
-  if (a.nmin + (no - 1) * a.step <= 16 * 13)
-    hipLaunchKernelGGL(hess_kernel<13>, dim3(no), dim3(kT), 0, st, a.xbuf, a.nmin, a.step,
-                       a.hbuf, a.vref, a.taus);
+  const int nmax = a.nmin + (no - 1) * a.step;
+  const ModalStrides ls = modal_strides(s, a.l, a.ldu);
+  hipLaunchKernelGGL(form_x_kernel, dim3(ceil_div(nmax * nmax, 256)), dim3(256), 0, st, a.rinv,
+                     a.w, a.ldw, a.nmin, a.step, no, a.xbuf);
+  double *hb = a.hbuf + lag * ls.sq, *vr = a.vref + lag * ls.vref, *ta = a.taus + lag * ls.taus;
+  if (nmax <= 16 * 13)
+    hipLaunchKernelGGL(hess_kernel<13>, dim3(no), dim3(kT), 0, st, a.xbuf, a.nmin, a.step, hb,
+                       vr, ta);
   else
-    hipLaunchKernelGGL(hess_kernel<kTP>, dim3(no), dim3(kT), 0, st, a.xbuf, a.nmin, a.step,
-                       a.hbuf, a.vref, a.taus);
-  // QR iterations and pole vectors of all orders in one persistent launch
-  hipLaunchKernelGGL(eig_init_kernel, dim3(1), dim3(kFT), 0, st, a.queue, a.done, no);
+    hipLaunchKernelGGL(hess_kernel<kTP>, dim3(no), dim3(kT), 0, st, a.xbuf, a.nmin, a.step, hb,
+                       vr, ta);
+  return hipGetLastError();
+}
+
+hipError_t launch_modal_eig(const ModalArgs &a, hipStream_t st) {
+  const ModalSizes &s = a.sizes;
+  const int no = s.n_orders;
+  const int items = a.n_lags * no;
+  const ModalStrides ls = modal_strides(s, a.l, a.ldu);
+  // QR iterations and pole vectors of every (lag, order) in one persistent launch
+  hipLaunchKernelGGL(eig_init_kernel, dim3(1), dim3(kFT), 0, st, a.queue, a.done, items);
   hipError_t e = hipFuncSetAttribute((const void *)eig_persistent_kernel,
                                      hipFuncAttributeMaxDynamicSharedMemorySize,
                                      (int)(sizeof(double) * kLdsDoubles));
   if (e != hipSuccess) return e;
   // one workgroup per CU by default; a smaller grid (at least one workgroup
-  // per order) leaves CUs to work on other streams
-  const int grid = a.eig_grid > 0 ? std::min(std::max(a.eig_grid, std::min(no, kEigGrid)), kEigGrid)
-                                  : kEigGrid;
+  // per item) leaves CUs to work on other streams
+  const int grid = a.eig_grid > 0
+                       ? std::min(std::max(a.eig_grid, std::min(items, kEigGrid)), kEigGrid)
+                       : kEigGrid;
   hipLaunchKernelGGL(eig_persistent_kernel, dim3(grid), dim3(kFT),
                      sizeof(double) * kLdsDoubles, st, a.hbuf, a.vref, a.taus, a.u, a.ldu,
                      a.nmin, a.step, no, a.l,
                      a.fs, a.gscr, s.francis_glb, a.evbuf, a.npole, a.pidx, a.flags_tmp, a.vscr,
                      s.vec_stride, a.tf, a.txi, a.tmu, a.tphi, a.queue, a.done, a.status,
-                     a.sweeps_per_row);
-  hipLaunchKernelGGL(sort_kernel, dim3(no), dim3(256), 0, st, a.nmin, a.step, a.l, a.npole,
-                     a.flags_tmp, a.tf, a.txi, a.tmu, a.tphi, a.count, a.flags, a.f, a.xi, a.mu,
-                     a.phi);
+                     a.sweeps_per_row, a.n_lags, ls);
+  hipLaunchKernelGGL(sort_kernel, dim3(no, a.n_lags), dim3(256), 0, st, a.nmin, a.step, a.l,
+                     a.npole, a.flags_tmp, a.tf, a.txi, a.tmu, a.tphi, a.count, a.flags, a.f,
+                     a.xi, a.mu, a.phi, no, (int64_t)s.poles);
   return hipGetLastError();
 }
 
