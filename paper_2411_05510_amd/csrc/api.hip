@@ -312,9 +312,6 @@ ssi_status ssi_synchronize(ssi_ctx *c) {
     if (word & ssi::kStatusNonFinite)
       return fail(SSI_EINVAL, "the record holds non-finite samples (NaN or Inf): its "
                               "correlations are not finite (status bits 0x%x)", word);
-    if (word & ssi::kStatusPoleWait)
-      return fail(SSI_ENOCONV, "a pole's wait for its order's eigenvalues timed out; the poles "
-                               "of that order were skipped (status bits 0x%x)", word);
     if (word & ssi::kStatusClaimCap)
       return fail(SSI_EINTERNAL, "the eigen-analysis work loop hit its pass cap "
                                  "(status bits 0x%x)", word);
@@ -852,7 +849,7 @@ struct ModalLane {
 struct ModalShared {
   ssi::ModalSizes sz;
   int n_lags, ldu;
-  double *hbuf, *vref, *taus, *evbuf, *gscr, *vscr;
+  double *hbuf, *vref, *taus, *evbuf, *gscr;
   double *tf, *txi, *tmu, *tphi, *uhead;
   int *npole, *pidx, *flags_tmp;
   int *queue, *done;
@@ -874,8 +871,9 @@ ModalLane carve_modal_lane(Arena &a, ssi_ctx *c, int64_t m, int l, const ssi_par
   return b;
 }
 
-// ldu: columns of U (k); the first l rows of each lag's U are copied into
-// uhead, so the mode shapes of every lag are read from one place.
+// ldu: columns of U (k); the first l rows of each lag's U are copied,
+// transposed, into uhead, so the mode shapes of every lag are read from one
+// place.
 ModalShared carve_modal_shared(Arena &a, int l, const ssi_params *p, int ldu, int n_lags) {
   ModalShared b{};
   b.sz = ssi::modal_sizes(p->order_min, p->order_max, p->order_step, l);
@@ -887,7 +885,6 @@ ModalShared carve_modal_shared(Arena &a, int l, const ssi_params *p, int ldu, in
   b.taus = a.take<double>(g * b.sz.taus);
   b.evbuf = a.take<double>(g * 2 * b.sz.vec);
   b.gscr = a.take<double>(g * b.sz.n_orders * b.sz.francis_glb);
-  b.vscr = a.take<double>((size_t)b.sz.vec_waves * b.sz.vec_stride);
   b.tf = a.take<double>(g * b.sz.poles);
   b.txi = a.take<double>(g * b.sz.poles);
   b.tmu = a.take<double>(g * 2 * b.sz.poles);
@@ -896,7 +893,7 @@ ModalShared carve_modal_shared(Arena &a, int l, const ssi_params *p, int ldu, in
   b.npole = a.take<int>(g * b.sz.n_orders);
   b.pidx = a.take<int>(g * b.sz.vec);
   b.flags_tmp = a.take<int>(g * b.sz.n_orders);
-  b.queue = a.take<int>(2);
+  b.queue = a.take<int>(b.sz.queue_ints);
   b.done = a.take<int>(g * b.sz.n_orders);
   return b;
 }
@@ -913,7 +910,7 @@ ssi::ModalArgs modal_args(ssi_ctx *c, const ModalShared &sh, int l, const ssi_pa
   a.fs = p->fs;
   a.u = sh.uhead;
   a.hbuf = sh.hbuf; a.vref = sh.vref; a.taus = sh.taus;
-  a.evbuf = sh.evbuf; a.gscr = sh.gscr; a.vscr = sh.vscr;
+  a.evbuf = sh.evbuf; a.gscr = sh.gscr;
   a.tf = sh.tf; a.txi = sh.txi; a.tmu = sh.tmu; a.tphi = sh.tphi;
   a.npole = sh.npole; a.pidx = sh.pidx; a.flags_tmp = sh.flags_tmp;
   a.queue = sh.queue; a.done = sh.done; a.status = c->status;
@@ -943,10 +940,8 @@ ssi_status run_modal_prep(ssi_ctx *c, ModalLane &b, ModalShared &sh, const doubl
   a.xbuf = b.xbuf;
   e = ssi::launch_modal_prep(a, slot, c->stream);
   if (e != hipSuccess) return hip_fail(e, "Hessenberg reduction");
-  // mode shapes use U[0:l, :n]
-  e = hipMemcpy2DAsync(sh.uhead + (int64_t)slot * l * sh.ldu, sizeof(double) * sh.ldu, u,
-                       sizeof(double) * k, sizeof(double) * sh.ldu, (size_t)l,
-                       hipMemcpyDeviceToDevice, c->stream);
+  // mode shapes use U[0:l, :n], read transposed
+  e = ssi::launch_mode_head(u, k, l, sh.uhead + (int64_t)slot * l * sh.ldu, c->stream);
   if (e != hipSuccess) return hip_fail(e, "mode-shape rows");
   return SSI_OK;
 }

@@ -13,7 +13,6 @@ namespace ssi {
 // reads and clears the word in ssi_synchronize).
 enum : int {
   kStatusChol = 1,          // a Cholesky factorization broke down
-  kStatusPoleWait = 4,      // a pole's wait for its order's eigenvalues timed out
   kStatusEigLimit = 8,      // an order's QR iteration hit its sweep limit
   kStatusClaimCap = 16,     // the eigen-analysis claim loop hit its pass cap
   kStatusNonFinite = 256    // the record held non-finite samples
@@ -121,12 +120,13 @@ struct ModalSizes {
   int n_orders;
   int64_t sq, vec, poles;       // sums over orders of n^2, n, n/2
   int64_t vref, taus;           // doubles
-  int64_t vec_waves, vec_stride, francis_glb;
+  int64_t francis_glb;
+  int64_t queue_ints;           // work counters and deferred list of the eig launch
 };
 ModalSizes modal_sizes(int nmin, int nmax, int step, int l);
 // Per-lag element strides of the modal buffers of a multi-lag launch: lag g's
 // Hessenberg matrices at hbuf + g sq, reflectors at vref + g vref, ..., the
-// first l rows of its U at u + g u.
+// transposed first l rows of its U at u + g u.
 struct ModalStrides {
   int64_t sq, vec, poles, vref, taus, u;
 };
@@ -135,10 +135,11 @@ struct ModalArgs {
   int nmin, step, l;
   int n_lags;                   // lags of the eigen-analysis launch
   int ldw;                      // leading dimension of rinv and w
-  int ldu;                      // leading dimension of u (the lags' first l rows of U)
+  int ldu;                      // columns of U: u holds, per lag, U[0:l, :ldu] transposed
+                                // (ldu rows of l entries)
   double fs;
   const double *u, *rinv, *w;
-  double *xbuf, *hbuf, *vref, *taus, *evbuf, *gscr, *vscr;
+  double *xbuf, *hbuf, *vref, *taus, *evbuf, *gscr;
   double *tf, *txi, *tmu, *tphi;
   int *npole, *pidx, *flags_tmp;
   int *queue, *done;            // work counters and per-order flags of the eig launch
@@ -153,6 +154,9 @@ ModalStrides modal_strides(const ModalSizes &s, int l, int ldu);
 // X_n for every order (form_x) and their Hessenberg forms into lag slot `lag`
 // (uses rinv, w, xbuf, hbuf, vref, taus).
 hipError_t launch_modal_prep(const ModalArgs &a, int lag, hipStream_t st);
+// U[0:l, :k] (U: row-major, ld k) transposed into dst (k rows of l entries),
+// the layout the mode-shape products of the eigen-analysis read.
+hipError_t launch_mode_head(const double *u, int k, int l, double *dst, hipStream_t st);
 // QR iterations, poles and sorting of all n_lags lags in one launch; outputs
 // of lag g at the output pointers plus g times the per-lag layout sizes.
 hipError_t launch_modal_eig(const ModalArgs &a, hipStream_t st);

@@ -86,7 +86,7 @@ form_x_kernel(const double *__restrict__ rinv, const double *__restrict__ w, int
 
 // ------------------------------------------------------------------ hess
 // Householder reduction of X_n (n <= 224) to upper Hessenberg form.  Writes H
-// (n x n, ld n) to hbuf, reflector vectors (rows of kNR) to vref and their
+// (n x n, by columns: H(i, j) at j n + i) to hbuf, reflector vectors (rows of kNR) to vref and their
 // scalars to taus.  TP row blocks of 16 cover n <= 16 TP (13 for n <= 208
 // keeps the register tile clear of scratch spills; 14 for n <= 224).
 template <int TP>
@@ -222,7 +222,7 @@ hess_kernel(const double *__restrict__ xbuf, int nmin, int step, double *__restr
 #pragma unroll
     for (int q = 0; q < kTQ; ++q) {
       const int i = row_of(tr, p), j = col_of(tc, q);
-      if (i < n && j < n) H[(int64_t)i * n + j] = (j >= i - 1) ? g[p][q] : 0.0;
+      if (i < n && j < n) H[(int64_t)j * n + i] = (j >= i - 1) ? g[p][q] : 0.0;
     }
 }
 
@@ -822,7 +822,7 @@ SSI_DEV void francis_order(int o, double *A, const double *__restrict__ hbuf, in
   for (int i0 = 0; i0 < n; i0 += 16) {
     double v[16];
 #pragma unroll
-    for (int r = 0; r < 16; ++r) v[r] = Hin[(int64_t)min(i0 + r, n - 1) * n + tc];
+    for (int r = 0; r < 16; ++r) v[r] = Hin[(int64_t)tc * n + min(i0 + r, n - 1)];
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
       const int i = i0 + r;
@@ -1018,337 +1018,463 @@ SSI_DEV cplx cdiv(cplx a, cplx b) {
   const double r = b.re / b.im, den = b.im + r * b.re;
   return {(a.re * r + a.im) / den, (a.im * r - a.re) / den};
 }
+// Component-wise choice: a conditional on the structs themselves selects
+// between their addresses, which keeps both in scratch memory.
+SSI_DEV cplx csel(bool c, cplx a, cplx b) { return {c ? a.re : b.re, c ? a.im : b.im}; }
 SSI_DEV double wsum(double v) { return wave_sum(v); }
 SSI_DEV double wmax(double v) { return wave_max(v); }
 
 }  // namespace
 
+// Element e (wave-uniform) of a column spread over the wave as v[e / 64] in
+// lane e % 64: the register is chosen by a uniform select, then read once.
+// The empty asm hides the elements' origin: a select chain over the elements
+// of a register array would otherwise be turned into a dynamically indexed
+// array, which lives in scratch memory.
+template <int N>
+SSI_DEV double lane_pick(const double (&v)[N], int e) {
+  const int u = e >> 6;
+  double s = v[0];
+#pragma unroll
+  for (int q = 1; q < N; ++q) {
+    double t = v[q];
+    __asm__("" : "+v"(t));
+    s = (q == u) ? t : s;
+  }
+  return readlane_d(s, e & 63);
+}
+
+constexpr int kU = (kNR + 63) / 64;      // rows of a column per lane in a pole item
+constexpr int kRingV = 4;                // columns of H in flight in the shifted solve
+
+// x = (H - mu I)^{-1} b for an upper Hessenberg H (column-major, column c at
+// Hc + c n) by one wave, b given in registers (row i = lane + 64 u in br/bi[u]).
+// Gaussian elimination by columns from the right: step j (from n - 2 down to
+// 0) clears entry (j + 1, j) with column j + 1, swapping the two columns first
+// when |h(j + 1, j)| exceeds the pivot (adjacent pivoting), which makes
+// (H - mu I) E_{n-2} ... E_0 = R upper triangular.  Column j + 1 of R is final
+// after step j, so the column-oriented back substitution R y = b runs in the
+// same loop and R is never stored; then x = E_{n-2} ... E_0 y, applying E_0
+// first (the multipliers and swaps wait in LDS).  A pivot below tiny is
+// replaced by tiny, as in LAPACK's Hessenberg inverse iteration.  Columns of H
+// arrive through a register ring kRingV steps ahead.  Writes x to x_re/x_im.
+SSI_DEV void shifted_solve(const double *__restrict__ Hc, int n, cplx mu, double tiny,
+                           double (&br)[kU], double (&bi)[kU], double *x_re, double *x_im,
+                           double *mult_re, double *mult_im, int *swp) {
+  const int lane = threadIdx.x & 63;
+  auto col = [&](int c, int u) {            // clamped load of H(lane + 64 u, c)
+    const int i = lane + 64 * u;
+    return Hc[(int64_t)max(min(c, n - 1), 0) * n + min(i, n - 1)];
+  };
+  double hq[kRingV][kU];
+#pragma unroll
+  for (int d = 0; d < kRingV; ++d)
+#pragma unroll
+    for (int u = 0; u < kU; ++u) hq[d][u] = col(n - 2 - d, u);
+  // working column: column n - 1 of H - mu I
+  double wr_[kU], wi_[kU];
+#pragma unroll
+  for (int u = 0; u < kU; ++u) {
+    const int i = lane + 64 * u;
+    const double h = col(n - 1, u);
+    wr_[u] = i < n ? h - (i == n - 1 ? mu.re : 0.0) : 0.0;
+    wi_[u] = i == n - 1 ? -mu.im : 0.0;
+  }
+  for (int j0 = n - 2; j0 >= 0; j0 -= kRingV) {
+#pragma unroll
+    for (int d = 0; d < kRingV; ++d) {
+      const int j = j0 - d;                  // slot d holds column j
+      if (j < 0) break;
+      // column j of H - mu I: rows 0..j+1
+      double ar[kU], ai[kU];
+#pragma unroll
+      for (int u = 0; u < kU; ++u) {
+        const int i = lane + 64 * u;
+        ar[u] = i <= j + 1 ? hq[d][u] - (i == j ? mu.re : 0.0) : 0.0;
+        ai[u] = i == j ? -mu.im : 0.0;
+        hq[d][u] = col(j - kRingV, u);       // refill with column j - kRingV
+      }
+      const cplx wp{lane_pick(wr_, j + 1), lane_pick(wi_, j + 1)};
+      const double ap = lane_pick(ar, j + 1);      // h(j + 1, j), real
+      const bool swap = fabs(ap) > cabs1(wp);
+      // after the swap: pivot column pv (finalized as column j + 1 of R) and
+      // the column ov being cleared at row j + 1
+      cplx piv = csel(swap, cplx{ap, 0.0}, wp);
+      const cplx oth = csel(swap, wp, cplx{ap, 0.0});
+      piv = csel(cabs1(piv) < tiny, cplx{tiny, 0.0}, piv);
+      const cplx m = cdiv(oth, piv);
+      const cplx cj = {lane_pick(br, j + 1), lane_pick(bi, j + 1)};
+      const cplx y = cdiv(cj, piv);
+#pragma unroll
+      for (int u = 0; u < kU; ++u) {
+        const int i = lane + 64 * u;
+        const cplx pv = csel(swap, cplx{ar[u], ai[u]}, cplx{wr_[u], wi_[u]});
+        const cplx ov = csel(swap, cplx{wr_[u], wi_[u]}, cplx{ar[u], ai[u]});
+        const bool above = i <= j;
+        const cplx na = csub(ov, cmul(m, pv));
+        const cplx nb = csub(cplx{br[u], bi[u]}, cmul(y, pv));
+        wr_[u] = above ? na.re : 0.0;        // the next working column (column j)
+        wi_[u] = above ? na.im : 0.0;
+        br[u] = above ? nb.re : br[u];
+        bi[u] = above ? nb.im : bi[u];
+      }
+      if (lane == 0) {
+        mult_re[j] = m.re;
+        mult_im[j] = m.im;
+        swp[j] = swap;
+        x_re[j + 1] = y.re;
+        x_im[j + 1] = y.im;
+      }
+    }
+  }
+  {
+    cplx piv{lane_pick(wr_, 0), lane_pick(wi_, 0)};
+    piv = csel(cabs1(piv) < tiny, cplx{tiny, 0.0}, piv);
+    const cplx y = cdiv(cplx{lane_pick(br, 0), lane_pick(bi, 0)}, piv);
+    wave_sync();                           // x[1..n-1], mult and swp are in LDS
+    // x = E_{n-2} ... E_0 y.  E_j y: y_{j+1} -= m_j y_j, then y_j and y_{j+1}
+    // swap if the columns did.  cur is the current y_j (y_{j+1} is still
+    // untouched in x).  Every lane runs the recurrence (the same values: LDS
+    // broadcasts); lane 0 stores.
+    cplx cur = y;
+    for (int j = 0; j + 1 < n; ++j) {
+      const cplx m{mult_re[j], mult_im[j]};
+      const cplx nb = csub(cplx{x_re[j + 1], x_im[j + 1]}, cmul(m, cur));
+      const bool sw = swp[j] != 0;
+      const cplx fin = csel(sw, nb, cur);  // swapped: cur carries on as y_{j+1}
+      cur = csel(sw, cur, nb);
+      if (lane == 0) {
+        x_re[j] = fin.re;
+        x_im[j] = fin.im;
+      }
+    }
+    if (lane == 0) {
+      x_re[n - 1] = cur.re;
+      x_im[n - 1] = cur.im;
+    }
+  }
+  wave_sync();
+}
+
 // Vector, mode shape and continuous pole of pole j of order o, by one wave.
 // x_re, x_im, mult_re, mult_im (kNR doubles each) and swp (kNR ints) are this
-// wave's LDS; ure / uim its global scratch for the U rows of the LU.  Writes
-// the unsorted pole f, xi, mu, phi (l complex) at slot pole(o) + j of the
-// temporary arrays.
+// wave's LDS.  H is stored by columns; ut is U[0:l, :k] transposed (row c
+// holds column c of U, l entries).  Writes the unsorted pole f, xi, mu, phi
+// (l complex) at slot pole(o) + j of the temporary arrays.
+//
+// Every global load in the loops below is issued by all lanes: out-of-range
+// loads read a clamped address (a finite entry of the same matrix), the ring
+// registers hold the raw loaded values, and the masking select happens when a
+// value is used, kRingV (or kRingQ) steps later.  A load under a branch, or a
+// select right after it, makes the compiler wait for the load at once, which
+// defeats the rings that keep columns and reflectors several steps ahead.
 SSI_DEV void vec_pole(int o, int j, const double *__restrict__ hbuf,
                       const double *__restrict__ vref, const double *__restrict__ taus,
-                      const double *__restrict__ u, int ldu, const double *__restrict__ evbuf,
+                      const double *__restrict__ ut, const double *__restrict__ evbuf,
                       const int *__restrict__ pidx, int nmin, int step, int l, double fs,
-                      double *__restrict__ ure, double *__restrict__ uim, double *x_re,
-                      double *x_im, double *mult_re, double *mult_im, int *swp,
+                      double *x_re, double *x_im, double *mult_re, double *mult_im, int *swp,
                       double *__restrict__ tf, double *__restrict__ txi,
                       double *__restrict__ tmu, double *__restrict__ tphi) {
   const int lane = threadIdx.x & 63;
-  {
-    const OrderGeo geo = order_geo(o, nmin, step);
-    const int n = geo.n;
-    const double *Hn = hbuf + geo.sq;
-    const double *wr = evbuf + 2 * geo.vec, *wi = wr + n;
-    const int e = pidx[geo.vec + j];
-    const cplx mu{wr[e], wi[e]};
-    // U row r occupies [off(r), off(r) + n - r) with off(r) = r n - r (r - 1) / 2
-    auto uoff = [&](int r) { return (int64_t)r * n - (int64_t)r * (r - 1) / 2; };
-    double hnorm = 0.0;
-    for (int c = lane; c < n; c += 64) hnorm = fmax(hnorm, fabs(Hn[c]) + fabs(Hn[(int64_t)(n - 1) * n + c]));
-    hnorm = fmax(wmax(hnorm), cabs1(mu));
-    const double tiny = 2.220446049250313e-16 * fmax(hnorm, 1e-300);
-    // ---- LU of H - mu I with adjacent-row partial pivoting.  Lane c % 64
-    // holds column c of the active row in registers (u = c / 64).  Rows of H
-    // wait in a ring of kRing registers sets: the slot step r consumes is
-    // refilled at once with row r + 1 + kRingV, so every load has kRingV
-    // steps to arrive.  Finished U rows go to this wave's global scratch
-    // without waiting.
-    constexpr int kU = (kNR + 63) / 64;
-    constexpr int kRingV = 4;
-    double ar[kU], ai[kU];
-    double hq[kRingV][kU];
+  const OrderGeo geo = order_geo(o, nmin, step);
+  const int n = geo.n;
+  const double *Hc = hbuf + geo.sq;
+  const double *wr = evbuf + 2 * geo.vec, *wi = wr + n;
+  const int e = pidx[geo.vec + j];
+  const cplx mu{wr[e], wi[e]};
+  // scale of H: max over columns c of |h(0, c)| + |h(n - 1, c)|, and |mu|
+  double hnorm = 0.0;
+  for (int c = lane; c < n; c += 64)
+    hnorm = fmax(hnorm, fabs(Hc[(int64_t)c * n]) + fabs(Hc[(int64_t)c * n + n - 1]));
+  hnorm = fmax(wmax(hnorm), cabs1(mu));
+  const double tiny = 2.220446049250313e-16 * fmax(hnorm, 1e-300);
+  // ---- inverse iteration: x = (H - mu I)^{-1} 1, accepted when x has grown
+  // enough, max|x| tiny >= 0.1 / sqrt(n) (the acceptance test of LAPACK's
+  // Hessenberg inverse iteration); otherwise a second solve with the
+  // normalized x as right-hand side.
+  double br[kU], bi[kU];
+#pragma unroll
+  for (int u = 0; u < kU; ++u) {
+    br[u] = (lane + 64 * u) < n ? 1.0 : 0.0;
+    bi[u] = 0.0;
+  }
+  for (int pass = 0; pass < 2; ++pass) {
+    shifted_solve(Hc, n, mu, tiny, br, bi, x_re, x_im, mult_re, mult_im, swp);
+    double mx = 0.0;
+    for (int c = lane; c < n; c += 64) mx = fmax(mx, cabs1(cplx{x_re[c], x_im[c]}));
+    mx = wmax(mx);
+    const double inv = mx > 0.0 ? 1.0 / mx : 1.0;
 #pragma unroll
     for (int u = 0; u < kU; ++u) {
       const int c = lane + 64 * u;
-      const double h0 = c < n ? Hn[c] : 0.0;
-      ar[u] = h0 - (c == 0 ? mu.re : 0.0);
-      ai[u] = c == 0 ? -mu.im : 0.0;
+      const int cc = min(c, n - 1);
+      br[u] = c < n ? x_re[cc] * inv : 0.0;
+      bi[u] = c < n ? x_im[cc] * inv : 0.0;
     }
+    wave_sync();                            // every lane has read x
 #pragma unroll
-    for (int d = 0; d < kRingV; ++d)
-#pragma unroll
-      for (int u = 0; u < kU; ++u) {
-        const int c = lane + 64 * u, row = 1 + d;
-        hq[d][u] = (c < n && row < n) ? Hn[(int64_t)row * n + c] : 0.0;
-      }
-    for (int r0 = 0; r0 + 1 < n; r0 += kRingV) {
-#pragma unroll
-      for (int d = 0; d < kRingV; ++d) {
-        const int r = r0 + d;                       // step r uses row r + 1 (slot d)
-        if (r + 1 >= n) break;
-        const cplx piv_a{lane_value(ar, r), lane_value(ai, r)};
-        const double sub = lane_value(hq[d], r);
-        const bool swap = fabs(sub) > cabs1(piv_a);
-        cplx m;
-        if (swap) m = cdiv(piv_a, cplx{sub, 0.0});
-        else {
-          cplx pa = piv_a;
-          if (cabs1(pa) < tiny) pa = cplx{tiny, 0.0};
-          m = cdiv(cplx{sub, 0.0}, pa);
-        }
-        const int64_t off = uoff(r);
-#pragma unroll
-        for (int u = 0; u < kU; ++u) {
-          const int c = lane + 64 * u;
-          if (c >= r && c < n) {
-            const cplx arow{ar[u], ai[u]};
-            const cplx nrow{hq[d][u] - (c == r + 1 ? mu.re : 0.0), (c == r + 1 ? -mu.im : 0.0)};
-            const cplx urow = swap ? nrow : arow;
-            const cplx other = swap ? arow : nrow;
-            cplx uw = urow;
-            if (c == r && !swap && cabs1(piv_a) < tiny) uw = cplx{tiny, 0.0};
-            ure[off + (c - r)] = uw.re;
-            uim[off + (c - r)] = uw.im;
-            if (c > r) {
-              const cplx na = csub(other, cmul(m, urow));
-              ar[u] = na.re;
-              ai[u] = na.im;
-            }
-          }
-          const int row = r + 1 + kRingV;             // refill the slot
-          hq[d][u] = (c < n && row < n) ? Hn[(int64_t)row * n + c] : 0.0;
-        }
-        if (lane == 0) {
-          mult_re[r] = m.re;
-          mult_im[r] = m.im;
-          swp[r] = swap;
-        }
-      }
+    for (int u = 0; u < kU; ++u) {
+      const int c = lane + 64 * u;
+      if (c < n) { x_re[c] = br[u]; x_im[c] = bi[u]; }
     }
-    {
-      const int64_t off = uoff(n - 1);
-      cplx last{lane_value(ar, n - 1), lane_value(ai, n - 1)};
-      if (cabs1(last) < tiny) last = cplx{tiny, 0.0};
-      if (lane == 0) {
-        ure[off] = last.re;
-        uim[off] = last.im;
-      }
-    }
-    // the U rows written above are read back by other lanes below
-    __threadfence_block();
     wave_sync();
-    // ---- inverse iteration: U x = 1 (the right-hand side whose L-solve is
-    // all ones), accepted when x has grown enough, max|x| eps3 >= 0.1 /
-    // sqrt(n) with eps3 = tiny (the acceptance test of LAPACK's Hessenberg
-    // inverse iteration); otherwise a second step (L U) x = x.  Rows of U wait
-    // in a ring as above, kRingV rows ahead of the row being reduced.
-    for (int c = lane; c < n; c += 64) { x_re[c] = 1.0; x_im[c] = 0.0; }
-    wave_sync();
-    for (int pass = 0; pass < 2; ++pass) {
-      if (pass == 1 && lane == 0) {
-        cplx carry{x_re[0], x_im[0]};
-        for (int r = 0; r + 1 < n; ++r) {
-          cplx bj = carry, bn{x_re[r + 1], x_im[r + 1]};
-          if (swp[r]) { const cplx tmp = bj; bj = bn; bn = tmp; }
-          const cplx nb = csub(bn, cmul(cplx{mult_re[r], mult_im[r]}, bj));
-          x_re[r] = bj.re; x_im[r] = bj.im;
-          carry = nb;
-        }
-        x_re[n - 1] = carry.re;
-        x_im[n - 1] = carry.im;
-      }
-      wave_sync();
-      // slot d holds row r0 - d: its off-diagonal part (uq) and diagonal (dq)
-      double uqr[kRingV][kU], uqi[kRingV][kU], dqr[kRingV], dqi[kRingV];
+    if (mx * tiny >= 0.1 / sqrt((double)n)) break;    // grown enough: accepted
+  }
+  // ---- psi_X = Q psi_H, Q = H_0 H_1 ... H_{n-3} the reflectors of the
+  // Hessenberg reduction (H_k = I - tau_k v_k v_k^T, v_k zero at and above
+  // row k): applied from H_{n-3} down to H_0, psi in registers (lane c % 64,
+  // slot c / 64), the reflector rows arriving through a register ring.
+  {
+    const double *vr = vref + (size_t)o * kNR * kNR;
+    const double *tv = taus + (size_t)o * kNR;
+    constexpr int kRingQ = 8;
+    double pr_[kU], pi_[kU], vq[kRingQ][kU];
 #pragma unroll
-      for (int d = 0; d < kRingV; ++d) {
-        const int rr = n - 1 - d;
-        const int64_t o2 = rr >= 0 ? uoff(rr) : 0;
-#pragma unroll
-        for (int u = 0; u < kU; ++u) {
-          const int c = lane + 64 * u;
-          const bool in = rr >= 0 && c > rr && c < n;
-          uqr[d][u] = in ? ure[o2 + (c - rr)] : 0.0;
-          uqi[d][u] = in ? uim[o2 + (c - rr)] : 0.0;
-        }
-        dqr[d] = rr >= 0 ? ure[o2] : 1.0;
-        dqi[d] = rr >= 0 ? uim[o2] : 0.0;
-      }
-      for (int r0 = n - 1; r0 >= 0; r0 -= kRingV) {
-#pragma unroll
-        for (int d = 0; d < kRingV; ++d) {
-          const int r = r0 - d;
-          if (r < 0) break;
-          double sre = 0.0, sim = 0.0;
-#pragma unroll
-          for (int u = 0; u < kU; ++u) {
-            const int c = lane + 64 * u;
-            if (c > r && c < n) {
-              const cplx xv = cmul(cplx{uqr[d][u], uqi[d][u]}, cplx{x_re[c], x_im[c]});
-              sre += xv.re;
-              sim += xv.im;
-            }
-          }
-          const double dre = dqr[d], dim = dqi[d];
-          // refill the slot with row r - kRingV
-          const int rr = r - kRingV;
-          const int64_t o2 = rr >= 0 ? uoff(rr) : 0;
-#pragma unroll
-          for (int u = 0; u < kU; ++u) {
-            const int c = lane + 64 * u;
-            const bool in = rr >= 0 && c > rr && c < n;
-            uqr[d][u] = in ? ure[o2 + (c - rr)] : 0.0;
-            uqi[d][u] = in ? uim[o2 + (c - rr)] : 0.0;
-          }
-          dqr[d] = rr >= 0 ? ure[o2] : 1.0;
-          dqi[d] = rr >= 0 ? uim[o2] : 0.0;
-          sre = wsum(sre);
-          sim = wsum(sim);
-          const cplx num = csub(cplx{x_re[r], x_im[r]}, cplx{sre, sim});
-          const cplx xr = cdiv(num, cplx{dre, dim});
-          wave_sync();                    // every lane has read x[r]
-          if (lane == 0) {
-            x_re[r] = xr.re;
-            x_im[r] = xr.im;
-          }
-          wave_sync();
-        }
-      }
-      double mx = 0.0;
-      for (int c = lane; c < n; c += 64) mx = fmax(mx, cabs1(cplx{x_re[c], x_im[c]}));
-      mx = wmax(mx);
-      const double inv = mx > 0.0 ? 1.0 / mx : 1.0;
-      for (int c = lane; c < n; c += 64) { x_re[c] *= inv; x_im[c] *= inv; }
-      wave_sync();
-      if (mx * tiny >= 0.1 / sqrt((double)n)) break;    // grown enough: accepted
+    for (int u2 = 0; u2 < kU; ++u2) {
+      pr_[u2] = br[u2];
+      pi_[u2] = bi[u2];
     }
-    // ---- psi_X = Q psi_H, Q = H_0 H_1 ... H_{n-3} the reflectors of the
-    // Hessenberg reduction (H_k = I - tau_k v_k v_k^T, v_k zero at and above
-    // row k): applied from H_{n-3} down to H_0, psi in registers (lane c % 64,
-    // slot c / 64), the reflector rows arriving through a register ring.
-    {
-      const double *vr = vref + (size_t)o * kNR * kNR;
-      const double *tv = taus + (size_t)o * kNR;
-      constexpr int kRingQ = 8;
-      double pr_[kU], pi_[kU], vq[kRingQ][kU];
+#pragma unroll
+    for (int d = 0; d < kRingQ; ++d)
 #pragma unroll
       for (int u2 = 0; u2 < kU; ++u2) {
-        const int c = lane + 64 * u2;
-        pr_[u2] = c < n ? x_re[c] : 0.0;
-        pi_[u2] = c < n ? x_im[c] : 0.0;
+        const int c = lane + 64 * u2, k = n - 3 - d;
+        vq[d][u2] = vr[(size_t)max(k, 0) * kNR + min(c, n - 1)];
       }
+    for (int k0 = n - 3; k0 >= 0; k0 -= kRingQ) {
 #pragma unroll
-      for (int d = 0; d < kRingQ; ++d)
+      for (int d = 0; d < kRingQ; ++d) {
+        const int k = k0 - d;
+        if (k < 0) break;
+        const double tau = tv[k];
+        double vk[kU];                      // row k of the reflectors, rows < n
+        double sre = 0.0, sim = 0.0;
 #pragma unroll
         for (int u2 = 0; u2 < kU; ++u2) {
-          const int c = lane + 64 * u2, k = n - 3 - d;
-          vq[d][u2] = (k >= 0 && c < n) ? vr[(size_t)k * kNR + c] : 0.0;
+          vk[u2] = (lane + 64 * u2 < n) ? vq[d][u2] : 0.0;
+          sre += vk[u2] * pr_[u2];
+          sim += vk[u2] * pi_[u2];
         }
-      for (int k0 = n - 3; k0 >= 0; k0 -= kRingQ) {
+        sre = tau * wsum(sre);
+        sim = tau * wsum(sim);
 #pragma unroll
-        for (int d = 0; d < kRingQ; ++d) {
-          const int k = k0 - d;
-          if (k < 0) break;
-          const double tau = tv[k];
-          double sre = 0.0, sim = 0.0;
-#pragma unroll
-          for (int u2 = 0; u2 < kU; ++u2) {
-            sre += vq[d][u2] * pr_[u2];
-            sim += vq[d][u2] * pi_[u2];
-          }
-          sre = tau * wsum(sre);
-          sim = tau * wsum(sim);
-#pragma unroll
-          for (int u2 = 0; u2 < kU; ++u2) {
-            pr_[u2] -= sre * vq[d][u2];
-            pi_[u2] -= sim * vq[d][u2];
-            const int c = lane + 64 * u2, kn = k - kRingQ;   // refill with reflector k - kRingQ
-            vq[d][u2] = (kn >= 0 && c < n) ? vr[(size_t)kn * kNR + c] : 0.0;
-          }
+        for (int u2 = 0; u2 < kU; ++u2) {
+          pr_[u2] -= sre * vk[u2];
+          pi_[u2] -= sim * vk[u2];
+          // refill with reflector k - kRingQ (raw: masked when it is used)
+          const int c = lane + 64 * u2, kn = k - kRingQ;
+          vq[d][u2] = vr[(size_t)max(kn, 0) * kNR + min(c, n - 1)];
         }
       }
-      wave_sync();                        // every lane has read x before it is overwritten
+    }
 #pragma unroll
-      for (int u2 = 0; u2 < kU; ++u2) {
-        const int c = lane + 64 * u2;
-        if (c < n) { x_re[c] = pr_[u2]; x_im[c] = pi_[u2]; }
-      }
-      wave_sync();
-    }
-    // ---- phi = U[0:l, :n] psi_X (Eq. (12) via C = first l rows of the
-    // observability matrix), unit 2-norm, largest-modulus entry real positive
-    const int slot = geo.pole + j;
-    double *ph = tphi + (size_t)slot * l * 2;
-    double nrm2 = 0.0, best = -1.0, bre = 1.0, bim = 0.0;
-    for (int a = lane; a < l; a += 64) {
-      double sre = 0.0, sim = 0.0;
-      for (int c = 0; c < n; ++c) {
-        const double cv = u[(int64_t)a * ldu + c];
-        sre += cv * x_re[c];
-        sim += cv * x_im[c];
-      }
-      ph[2 * a] = sre;
-      ph[2 * a + 1] = sim;
-      const double m2 = sre * sre + sim * sim;
-      nrm2 += m2;
-      if (m2 > best) { best = m2; bre = sre; bim = sim; }
-    }
-    nrm2 = wsum(nrm2);
-    // lane holding the largest-modulus entry (ties: lowest lane)
-    double bmax = wmax(best);
-    const unsigned long long ball = __ballot(best == bmax);
-    const int src = __ffsll((long long)ball) - 1;
-    bre = __shfl(bre, src, 64);
-    bim = __shfl(bim, src, 64);
-    const double bm = sqrt(bre * bre + bim * bim);
-    const double inv = (nrm2 > 0.0 && bm > 0.0) ? 1.0 / (sqrt(nrm2) * bm) : 1.0;
-    // multiply by conj(b) / (|b| |phi|)
-    const double cre = bre * inv, cim = -bim * inv;
-    for (int a = lane; a < l; a += 64) {
-      const double pr = ph[2 * a], pi = ph[2 * a + 1];
-      ph[2 * a] = pr * cre - pi * cim;
-      ph[2 * a + 1] = pr * cim + pi * cre;
-    }
-    if (lane == 0) {
-      const double lr = 0.5 * log(mu.re * mu.re + mu.im * mu.im) * fs;
-      const double li = atan2(mu.im, mu.re) * fs;
-      const double al = sqrt(lr * lr + li * li);
-      tf[slot] = al / (2.0 * M_PI);
-      txi[slot] = -lr / al;
-      tmu[2 * slot] = mu.re;
-      tmu[2 * slot + 1] = mu.im;
+    for (int u2 = 0; u2 < kU; ++u2) {
+      const int c = lane + 64 * u2;
+      if (c < n) { x_re[c] = pr_[u2]; x_im[c] = pi_[u2]; }
     }
     wave_sync();
   }
+  // ---- phi = U[0:l, :n] psi_X (Eq. (12) via C = first l rows of the
+  // observability matrix), unit 2-norm, largest-modulus entry real positive.
+  // Lane a holds rows a + 64 r of phi (r < kSR, a pass of 64 kSR rows): row
+  // c of ut is read by consecutive lanes (coalesced), psi_X[c] is an LDS
+  // broadcast, and the loads of kSC columns of every row block are in flight
+  // together.  Columns past n read column n - 1 and are weighted by zero.
+  constexpr int kSR = 4, kSC = 8;
+  const int slot = geo.pole + j;
+  double *ph = tphi + (size_t)slot * l * 2;
+  double nrm2 = 0.0, best = -1.0, bre = 1.0, bim = 0.0;
+  for (int a0 = 0; a0 < l; a0 += 64 * kSR) {
+    int ac[kSR];
+#pragma unroll
+    for (int r = 0; r < kSR; ++r) ac[r] = min(a0 + 64 * r + lane, l - 1);
+    double sre[kSR], sim[kSR];
+#pragma unroll
+    for (int r = 0; r < kSR; ++r) { sre[r] = 0.0; sim[r] = 0.0; }
+    for (int c0 = 0; c0 < n; c0 += kSC) {
+      double cv[kSC][kSR];
+#pragma unroll
+      for (int q = 0; q < kSC; ++q)
+#pragma unroll
+        for (int r = 0; r < kSR; ++r) cv[q][r] = ut[(int64_t)min(c0 + q, n - 1) * l + ac[r]];
+#pragma unroll
+      for (int q = 0; q < kSC; ++q) {
+        const int cq = min(c0 + q, n - 1);
+        const double w = (c0 + q < n) ? 1.0 : 0.0;
+        const double xr = x_re[cq] * w, xi = x_im[cq] * w;
+#pragma unroll
+        for (int r = 0; r < kSR; ++r) {
+          sre[r] += cv[q][r] * xr;
+          sim[r] += cv[q][r] * xi;
+        }
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < kSR; ++r) {
+      const int a = a0 + 64 * r + lane;
+      if (a < l) {
+        ph[2 * a] = sre[r];
+        ph[2 * a + 1] = sim[r];
+        const double m2 = sre[r] * sre[r] + sim[r] * sim[r];
+        nrm2 += m2;
+        if (m2 > best) { best = m2; bre = sre[r]; bim = sim[r]; }
+      }
+    }
+  }
+  nrm2 = wsum(nrm2);
+  // lane holding the largest-modulus entry (ties: lowest lane)
+  const double bmax = wmax(best);
+  const unsigned long long ball = __ballot(best == bmax);
+  const int src = __ffsll((long long)ball) - 1;
+  bre = __shfl(bre, src, 64);
+  bim = __shfl(bim, src, 64);
+  const double bm = sqrt(bre * bre + bim * bim);
+  const double inv = (nrm2 > 0.0 && bm > 0.0) ? 1.0 / (sqrt(nrm2) * bm) : 1.0;
+  // multiply by conj(b) / (|b| |phi|)
+  const double cre = bre * inv, cim = -bim * inv;
+  for (int a = lane; a < l; a += 64) {
+    const double pr = ph[2 * a], pi = ph[2 * a + 1];
+    ph[2 * a] = pr * cre - pi * cim;
+    ph[2 * a + 1] = pr * cim + pi * cre;
+  }
+  if (lane == 0) {
+    const double lr = 0.5 * log(mu.re * mu.re + mu.im * mu.im) * fs;
+    const double li = atan2(mu.im, mu.re) * fs;
+    const double al = sqrt(lr * lr + li * li);
+    tf[slot] = al / (2.0 * M_PI);
+    txi[slot] = -lr / al;
+    tmu[2 * slot] = mu.re;
+    tmu[2 * slot + 1] = mu.im;
+  }
+  wave_sync();
 }
 
 // ------------------------------------------------------------------ eig
 // Eigenvalues and pole vectors of every order in one persistent launch of
-// one workgroup per CU.  Phase 1: each workgroup takes whole orders from a
-// counter, largest first, and runs the QR iteration on them; finishing an
-// order publishes its eigenvalues with a release store of done[o].  Phase 2:
-// once the order counter is exhausted (every order is then held by a running
-// workgroup), each wave takes poles from a second counter, smallest orders
-// first, waits for its order's flag and computes the pole's vector and mode
-// shape.  Poles of small orders therefore run beside the QR iterations of the
-// large ones.  The wait is bounded: a flag not seen within kEigSpinLimit
-// polls sets bit kStatusPoleWait of the status word and the pole is skipped.
+// one workgroup per CU, followed by a short launch for the poles left over.
+// Phase 1: each workgroup takes whole orders from a counter, largest first,
+// and runs the QR iteration on them; finishing an order publishes its
+// eigenvalues with a release store of done[o] and then lowers the count of
+// orders still running.  Phase 2: while some order is still running, each
+// wave takes poles from a second counter, smallest orders first; a pole whose
+// order has not finished is not waited for: the wave appends it to a deferred
+// list and leaves.  Poles of small orders thus run beside the QR iterations
+// of the large ones, workgroups with nothing ready leave the chip at once
+// (work on other streams can use the CUs while the largest orders finish),
+// and the deferred poles and those never claimed are left to the tail launch
+// (pole_tail_kernel), whose waves all find their orders finished.  Every
+// claim is one fetch-and-add: a compare-and-swap claim that first checks the
+// order serializes thousands of waves on one counter.
 namespace {
 constexpr int kEigGrid = 256;                       // workgroups (one per CU)
 constexpr int kVecLds = 5 * kNR;                    // per-wave LDS of a pole item (doubles)
-constexpr long kEigSpinLimit = 1L << 24;
+// queue: [0] next order item, [1] next pole item, [2] order items still
+// running, [3] deferred poles, [4] next tail item, [5..] the deferred poles
+// (at most one per wave of the persistent launch)
+constexpr int kQDeferred = 5;
+constexpr int kMaxDeferred = kEigGrid * (kFT / 64);
 static_assert(kFT / 64 * kVecLds <= kLdsDoubles, "pole items fit the workgroup's LDS");
+
+// Pole items, smallest orders first; within an order, lag by lag and pole by pole.
+SSI_DEV int pole_items_total(int n_orders, int n_lags, int nmin, int step) {
+  int total = 0;
+  for (int o = 0; o < n_orders; ++o) total += n_lags * ((nmin + o * step) / 2);
+  return total;
+}
+struct PoleItem { int o, g, j; };
+SSI_DEV PoleItem pole_item(int it, int n_lags, int nmin, int step) {
+  int o = 0, rem = it;
+  while (rem >= n_lags * ((nmin + o * step) / 2)) {
+    rem -= n_lags * ((nmin + o * step) / 2);
+    ++o;
+  }
+  const int half = (nmin + o * step) / 2;
+  const int g = rem / half;
+  return {o, g, rem - g * half};
+}
+
+// Claims the next pole item for lane 0's wave, or returns -1 (the wave
+// leaves).  Persistent launch: none once every order has finished (the rest
+// is the tail's); a claimed pole of an unfinished order is deferred.  Tail
+// launch: the deferred poles, then the poles never claimed.
+SSI_DEV int claim_pole(int *queue, const int *done, int total, int n_orders, int n_lags,
+                       int nmin, int step, bool tail, int *status) {
+  if (!tail) {
+    if (__hip_atomic_load(&queue[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) <= 0) return -1;
+    const int c = atomicAdd(&queue[1], 1);
+    if (c >= total) return -1;
+    const PoleItem pi = pole_item(c, n_lags, nmin, step);
+    if (__hip_atomic_load(&done[pi.g * n_orders + pi.o], __ATOMIC_ACQUIRE,
+                          __HIP_MEMORY_SCOPE_AGENT))
+      return c;
+    const int d = atomicAdd(&queue[3], 1);
+    if (d < kMaxDeferred) queue[kQDeferred + d] = c;
+    else atomicOr(status, ssi::kStatusClaimCap);    // cannot happen: one per wave
+    return -1;
+  }
+  const int ndef = min(__hip_atomic_load(&queue[3], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT),
+                       kMaxDeferred);
+  const int first = min(__hip_atomic_load(&queue[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT),
+                        total);
+  const int t = atomicAdd(&queue[4], 1);
+  if (t < ndef) return queue[kQDeferred + t];
+  const int it = first + (t - ndef);
+  return it < total ? it : -1;
+}
+
+// Pole items for one wave until claim_pole gives none.  x: this wave's LDS
+// (kVecLds doubles).
+SSI_DEV void pole_phase(bool tail, double *x, const double *__restrict__ hbuf,
+                        const double *__restrict__ vref, const double *__restrict__ taus,
+                        const double *__restrict__ u, int nmin, int step, int n_orders,
+                        int l, double fs, const double *__restrict__ evbuf,
+                        const int *__restrict__ npole, const int *__restrict__ pidx,
+                        double *__restrict__ tf,
+                        double *__restrict__ txi, double *__restrict__ tmu,
+                        double *__restrict__ tphi, int *__restrict__ queue,
+                        const int *__restrict__ done, int *__restrict__ status, int n_lags,
+                        const ssi::ModalStrides &ls) {
+  const int lane = threadIdx.x & 63;
+  double *x_re = x, *x_im = x_re + kNR, *mult_re = x_im + kNR, *mult_im = mult_re + kNR;
+  int *swp = reinterpret_cast<int *>(mult_im + kNR);
+  const int total = pole_items_total(n_orders, n_lags, nmin, step);
+  for (;;) {
+    int it = -1;
+    if (lane == 0)
+      it = claim_pole(queue, done, total, n_orders, n_lags, nmin, step, tail, status);
+    it = __builtin_amdgcn_readfirstlane(__shfl(it, 0, 64));
+    if (it < 0) break;
+    const PoleItem pi = pole_item(it, n_lags, nmin, step);
+    const int *dn = done + pi.g * n_orders + pi.o;
+    // every lane acquires the order's eigenvalues; an order that never ran
+    // (the phase-1 pass cap, reported through the status word) has no poles
+    if (!__hip_atomic_load(dn, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT)) continue;
+    if (pi.j >= npole[pi.g * n_orders + pi.o]) continue;
+    const int g = pi.g;
+    vec_pole(pi.o, pi.j, hbuf + g * ls.sq, vref + g * ls.vref, taus + g * ls.taus, u + g * ls.u,
+             evbuf + g * 2 * ls.vec, pidx + g * ls.vec, nmin, step, l, fs, x_re, x_im,
+             mult_re, mult_im, swp, tf + g * ls.poles, txi + g * ls.poles,
+             tmu + g * 2 * ls.poles, tphi + g * 2 * ls.poles * l);
+  }
+}
 }  // namespace
 
 __global__ void __launch_bounds__(kFT)
-eig_init_kernel(int *__restrict__ queue, int *__restrict__ done, int n_orders) {
-  // n_orders here counts the (lag, order) items of the launch
-  for (int i = threadIdx.x; i < n_orders + 2; i += blockDim.x) {
-    if (i < 2) queue[i] = 0;
-    else done[i - 2] = 0;
+eig_init_kernel(int *__restrict__ queue, int *__restrict__ done, int n_items) {
+  // the counters of queue (the deferred list needs no clearing)
+  for (int i = threadIdx.x; i < n_items + kQDeferred; i += blockDim.x) {
+    if (i < kQDeferred) queue[i] = i == 2 ? n_items : 0;
+    else done[i - kQDeferred] = 0;
   }
 }
 
 __global__ void __launch_bounds__(kFT)
 eig_persistent_kernel(const double *__restrict__ hbuf, const double *__restrict__ vref,
-                      const double *__restrict__ taus, const double *__restrict__ u, int ldu,
+                      const double *__restrict__ taus, const double *__restrict__ u,
                       int nmin, int step, int n_orders, int l, double fs,
                       double *__restrict__ gscr, int64_t gstride, double *__restrict__ evbuf,
                       int *__restrict__ npole, int *__restrict__ pidx, int *__restrict__ flags,
-                      double *__restrict__ vscr, int64_t vstride, double *__restrict__ tf,
+                      double *__restrict__ tf,
                       double *__restrict__ txi, double *__restrict__ tmu,
                       double *__restrict__ tphi, int *__restrict__ queue, int *__restrict__ done,
                       int *__restrict__ status, int sweeps_per_row, int n_lags,
@@ -1356,7 +1482,7 @@ eig_persistent_kernel(const double *__restrict__ hbuf, const double *__restrict_
   extern __shared__ double lds_h[];
   __shared__ int red[kFT / 64];
   __shared__ int small_ok, item;
-  const int t = threadIdx.x, lane = t & 63;
+  const int t = threadIdx.x;
   const int wave = __builtin_amdgcn_readfirstlane(t >> 6);
   // Work items are (lag, order) pairs of every lag of the launch; lag g's
   // buffers sit at g times the per-lag stride of each buffer (ls).
@@ -1394,51 +1520,45 @@ eig_persistent_kernel(const double *__restrict__ hbuf, const double *__restrict_
     __syncthreads();
     if (t == 0) {
       __hip_atomic_store(&done[g * n_orders + o], 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_fetch_add(&queue[2], -1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
       item = atomicAdd(&queue[0], 1);
     }
     __syncthreads();
   }
-  // ---- phase 2: poles, smallest orders first
+  // ---- phase 2: poles of finished orders, smallest orders first
   __syncthreads();                                  // LDS of the QR iteration is free
-  double *x_re = lds_h + wave * kVecLds;
-  double *x_im = x_re + kNR, *mult_re = x_im + kNR, *mult_im = mult_re + kNR;
-  int *swp = reinterpret_cast<int *>(mult_im + kNR);
-  const int gw = blockIdx.x * (kFT / 64) + wave;
-  double *ure = vscr + (size_t)gw * vstride;
-  double *uim = ure + vstride / 2;
-  // pole slots, smallest orders first; within an order, lag by lag
-  int total = 0;
-  for (int o = 0; o < n_orders; ++o) total += n_lags * ((nmin + o * step) / 2);
-  for (;;) {
-    int it = 0;
-    if (lane == 0) it = atomicAdd(&queue[1], 1);
-    it = __builtin_amdgcn_readfirstlane(__shfl(it, 0, 64));
-    if (it >= total) break;
-    int o = 0, rem = it;
-    while (rem >= n_lags * ((nmin + o * step) / 2)) {
-      rem -= n_lags * ((nmin + o * step) / 2);
-      ++o;
-    }
-    const int half = (nmin + o * step) / 2;
-    const int g = rem / half, j = rem - g * half;
-    int *dn = done + g * n_orders + o;
-    int ready = 0;
-    if (lane == 0) {
-      long spins = 0;
-      while (!(ready = __hip_atomic_load(dn, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT)) &&
-             ++spins < kEigSpinLimit)
-        __builtin_amdgcn_s_sleep(8);
-      if (!ready) atomicOr(status, ssi::kStatusPoleWait);
-    }
-    ready = __builtin_amdgcn_readfirstlane(__shfl(ready, 0, 64));
-    if (!ready) continue;
-    (void)__hip_atomic_load(dn, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);  // every lane
-    if (j >= npole[g * n_orders + o]) continue;
-    vec_pole(o, j, hbuf + g * ls.sq, vref + g * ls.vref, taus + g * ls.taus, u + g * ls.u, ldu,
-             evbuf + g * 2 * ls.vec, pidx + g * ls.vec, nmin, step, l, fs, ure, uim, x_re, x_im,
-             mult_re, mult_im, swp, tf + g * ls.poles, txi + g * ls.poles, tmu + g * 2 * ls.poles,
-             tphi + g * 2 * ls.poles * l);
-  }
+  pole_phase(false, lds_h + wave * kVecLds, hbuf, vref, taus, u,
+             nmin, step, n_orders, l, fs, evbuf, npole, pidx, tf, txi, tmu,
+             tphi, queue, done, status, n_lags, ls);
+}
+
+// The poles phase 2 left: every order has finished when this launch starts.
+// kTailWaves waves per workgroup, one per SIMD.
+constexpr int kTailWaves = 4;
+__global__ void __launch_bounds__(64 * kTailWaves)
+pole_tail_kernel(const double *__restrict__ hbuf, const double *__restrict__ vref,
+                 const double *__restrict__ taus, const double *__restrict__ u,
+                 int nmin, int step, int n_orders, int l, double fs,
+                 const double *__restrict__ evbuf, const int *__restrict__ npole,
+                 const int *__restrict__ pidx,
+                 double *__restrict__ tf, double *__restrict__ txi, double *__restrict__ tmu,
+                 double *__restrict__ tphi, int *__restrict__ queue,
+                 const int *__restrict__ done, int *__restrict__ status, int n_lags,
+                 ssi::ModalStrides ls) {
+  extern __shared__ double lds_v[];
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  pole_phase(true, lds_v + wave * kVecLds, hbuf, vref, taus, u,
+             nmin, step, n_orders, l, fs, evbuf, npole, pidx, tf, txi, tmu,
+             tphi, queue, done, status, n_lags, ls);
+}
+
+// dst[c l + a] = U[a, c] for a < l, c < k: thread i takes entry i of dst.
+__global__ void __launch_bounds__(256)
+mode_head_kernel(const double *__restrict__ u, int k, int l, double *__restrict__ dst) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= (int64_t)k * l) return;
+  const int64_t c = i / l, a = i - c * l;
+  dst[i] = u[a * k + c];
 }
 
 // ------------------------------------------------------------------ sort
@@ -1559,9 +1679,8 @@ ModalSizes modal_sizes(int nmin, int nmax, int step, int l) {
   }
   s.vref = (int64_t)s.n_orders * kNR * kNR;
   s.taus = (int64_t)s.n_orders * kNR;
-  s.vec_waves = (int64_t)kEigGrid * (kFT / 64);
-  s.vec_stride = 2 * ((int64_t)kNR * (kNR + 1) / 2 + 64);
   s.francis_glb = (int64_t)HIdx::packed_size(kNR) + kExtra;
+  s.queue_ints = kQDeferred + kMaxDeferred;
   return s;
 }
 
@@ -1593,6 +1712,14 @@ hipError_t launch_modal_prep(const ModalArgs &a, int lag, hipStream_t st) {
   return hipGetLastError();
 }
 
+hipError_t launch_mode_head(const double *u, int k, int l, double *dst, hipStream_t st) {
+  const int64_t total = (int64_t)k * l;
+  if (total == 0) return hipSuccess;
+  hipLaunchKernelGGL(mode_head_kernel, dim3((unsigned)ceil_div<int64_t>(total, 256)), dim3(256), 0, st,
+                     u, k, l, dst);
+  return hipGetLastError();
+}
+
 hipError_t launch_modal_eig(const ModalArgs &a, hipStream_t st) {
   const ModalSizes &s = a.sizes;
   const int no = s.n_orders;
@@ -1610,11 +1737,15 @@ hipError_t launch_modal_eig(const ModalArgs &a, hipStream_t st) {
                        ? std::min(std::max(a.eig_grid, std::min(items, kEigGrid)), kEigGrid)
                        : kEigGrid;
   hipLaunchKernelGGL(eig_persistent_kernel, dim3(grid), dim3(kFT),
-                     sizeof(double) * kLdsDoubles, st, a.hbuf, a.vref, a.taus, a.u, a.ldu,
+                     sizeof(double) * kLdsDoubles, st, a.hbuf, a.vref, a.taus, a.u,
                      a.nmin, a.step, no, a.l,
-                     a.fs, a.gscr, s.francis_glb, a.evbuf, a.npole, a.pidx, a.flags_tmp, a.vscr,
-                     s.vec_stride, a.tf, a.txi, a.tmu, a.tphi, a.queue, a.done, a.status,
+                     a.fs, a.gscr, s.francis_glb, a.evbuf, a.npole, a.pidx, a.flags_tmp,
+                     a.tf, a.txi, a.tmu, a.tphi, a.queue, a.done, a.status,
                      a.sweeps_per_row, a.n_lags, ls);
+  hipLaunchKernelGGL(pole_tail_kernel, dim3(2 * kEigGrid), dim3(64 * kTailWaves),
+                     sizeof(double) * kVecLds * kTailWaves, st, a.hbuf, a.vref, a.taus, a.u,
+                     a.nmin, a.step, no, a.l, a.fs, a.evbuf, a.npole, a.pidx,
+                     a.tf, a.txi, a.tmu, a.tphi, a.queue, a.done, a.status, a.n_lags, ls);
   hipLaunchKernelGGL(sort_kernel, dim3(no, a.n_lags), dim3(256), 0, st, a.nmin, a.step, a.l,
                      a.npole, a.flags_tmp, a.tf, a.txi, a.tmu, a.tphi, a.count, a.flags, a.f,
                      a.xi, a.mu, a.phi, no, (int64_t)s.poles);
