@@ -7,11 +7,15 @@ k = 200, p = 20, q = 2, and model orders 2..200 step 2: correlations,
 Toeplitz assembly, sketch, range finder with power iterations, small SVD,
 shift least squares and eigen-analysis for all 100 orders, poles sorted per
 order.  The record is resident in HBM before timing starts; results stay on
-the device.  Prints one JSON line with the throughput, per-step latency
-percentiles, the roofline of the dominant kernel (the correlation contraction
-on FP32 MFMA) measured live with HIP events on its stream, per-stage times
-and the FP64 CPU checker timed on the host for one identification of the
-same record.
+the device.  Successive windows of a monitoring stream are independent, so
+--in-flight of them (default 3) run at once, each on its own context and
+stream: the single-CU tail of one window's eigen-analysis overlaps the next
+windows' correlations and products.  Prints one JSON line with the
+throughput, the latency of one window at a time (p50/p99), the roofline of
+the dominant kernel (the correlation contraction) measured live with HIP
+events on its stream while one window runs at a time, per-stage times (in
+the timed region and one window at a time) and the FP64 CPU checker timed on
+the host for one identification of the same record.
 
 Other workloads (--workload):
   bridge-180ch-3d   the 3D stabilization diagram: the same record over lags
@@ -131,7 +135,28 @@ def roofline(stages, l, n, L, corr: str):
     }
 
 
-def stage_rooflines(stages, steps, m, ell, q, prec: str):
+def toeplitz_launch_ms(ctx, stream, r, jb: int, launches: int = 20) -> float:
+    """Mean duration of the Toeplitz assembly kernel over back-to-back
+    launches through ssi_toeplitz, HIP events on the context's stream (a
+    90-microsecond kernel: the stage timer's events around one launch add
+    their own gap)."""
+    import torch
+    t = ctx.toeplitz(r, jb)
+    ctx.toeplitz(r, jb, out=t)
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ctx.synchronize()
+    a.record(stream)
+    for _ in range(launches):
+        ctx.toeplitz(r, jb, out=t)
+    b.record(stream)
+    ctx.synchronize()
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / launches
+    del t
+    return ms
+
+
+def stage_rooflines(stages, steps, m, ell, q, prec: str, toe_launch_ms=None):
     """Rooflines of the other two kernels the survey gives targets for, from
     their stage times per identification: the randomized-SVD products
     (2q + 1 range-finder products and the projection, 2 m^2 ell flops each,
@@ -158,7 +183,13 @@ def stage_rooflines(stages, steps, m, ell, q, prec: str):
         prod.update(bound="mixed", achieved=tflops, unit="TFLOP/s")
     toe = {"stage": "toeplitz", "kernels": "toeplitz_vec4", "bound": "hbm",
            "avg_kernel_ms": toe_avg, "achieved": toe_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-           "frac": toe_gbs / HBM_PEAK_GBS, "algorithmic_bytes": m * m * 4.0}
+           "frac": toe_gbs / HBM_PEAK_GBS, "algorithmic_bytes": m * m * 4.0,
+           "timing": "stage timer (events around each launch)"}
+    if toe_launch_ms:
+        gbs = m * m * 4.0 / (toe_launch_ms * 1e-3) / 1e9
+        toe.update(avg_kernel_ms=toe_launch_ms, achieved=gbs, frac=gbs / HBM_PEAK_GBS,
+                   stage_timer_ms=toe_avg,
+                   timing="20 back-to-back launches through ssi_toeplitz, HIP events")
     return [prod, toe]
 
 
@@ -197,11 +228,16 @@ def bench_identify(args) -> dict:
     dev = torch.device("cuda:0")
     yd = torch.from_numpy(y).to(dev)
     p = params_of(wl, PRECS[args.prec], args.refine)
-    ctx = ssicov.Context(0)
-    ctx.set_corr_mode(CORR_MODES[args.corr])
-    ctx.set_autotune(True)                   # the warm-up calls pick the K-slice counts
-    out = ctx.alloc_output(p, wl.l, wl.n)
-    stream = torch.cuda.current_stream(dev)
+    k = max(1, args.in_flight)
+    # one context, stream and output set per window in flight
+    streams = [torch.cuda.Stream(dev) for _ in range(k)]
+    ctxs = [ssicov.Context(0, s) for s in streams]
+    outs = []
+    for c in ctxs:
+        c.set_corr_mode(CORR_MODES[args.corr])
+        c.set_autotune(True)                 # the warm-up calls pick the K-slice counts
+        outs.append(c.alloc_output(p, wl.l, wl.n))
+    ctx, out, stream = ctxs[0], outs[0], streams[0]
     if args.copy_probe:
         src = torch.ones(COPY_PROBE_BYTES // 4, dtype=torch.float32, device=dev)
         dst = torch.empty_like(src)
@@ -210,15 +246,45 @@ def bench_identify(args) -> dict:
         torch.cuda.synchronize()
         del src, dst
 
-    for _ in range(args.warmup):
-        ctx.identify(yd, p, out)
-    ctx.synchronize()
-    elapsed, step_ms, stages = timed_steps(ctx, lambda: ctx.identify(yd, p, out), args.steps,
-                                           stream)
+    # warm-up one context at a time, so that each autotunes on an idle GPU
+    for c, o in zip(ctxs, outs):
+        for _ in range(args.warmup):
+            c.identify(yd, p, o)
+        c.synchronize()
+
+    # Throughput (the timed region): steps identifications, step i on
+    # context i mod k, so k windows are in flight; per-stage HIP events on
+    # every context's stream.
+    for c in ctxs:
+        c.set_profiling(True)
+        c.profile_read()                     # clear
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        ctxs[i % k].identify(yd, p, outs[i % k])
+    torch.cuda.synchronize()
+    for c in ctxs:
+        c.synchronize()
+    elapsed = time.perf_counter() - t0
+    stages = {}
+    for c in ctxs:
+        for name, (ms, calls) in c.profile_read().items():
+            a = stages.setdefault(name, [0.0, 0])
+            a[0] += ms
+            a[1] += calls
+        c.set_profiling(False)
+    stages = {name: tuple(v) for name, v in stages.items()}
+
+    # Latency: one window at a time on context 0, per-step HIP events.
+    lat_steps = max(5, args.steps // 2)
+    _, step_ms, lat_stages = timed_steps(ctx, lambda: ctx.identify(yd, p, out), lat_steps, stream)
+    r_stack = ctx.correlate(yd, 2 * wl.lags[0] - 1)
+    toe_ms = toeplitz_launch_ms(ctx, stream, r_stack, wl.lags[0])
+    del r_stack
 
     L = 2 * wl.lags[0] - 1
     m = wl.lags[0] * wl.l
-    flags = int(out.flags.sum().item())
+    flags = sum(int(o.flags.sum().item()) for o in outs)
 
     # End to end: the record from pinned host memory, the identification and
     # every output back on the host (ssi_identify_result), a few steps.
@@ -277,19 +343,28 @@ def bench_identify(args) -> dict:
                         "(10800x10800 Toeplitz), randomized SVD k=200 p=20 q=2, "
                         f"orders 2..200 step 2; {corr_note}, {prec_note}{refine_note}, "
                         "FP64 factorizations and eigen-analysis; product K slices autotuned "
-                        "in the warm-up",
+                        f"in the warm-up; {k} windows in flight (one context, stream and "
+                        "output set each)",
+            "windows_in_flight": k,
             "latency_ms_p50": float(np.percentile(step_ms, 50)),
             "latency_ms_p99": float(np.percentile(step_ms, 99)),
-            "stage_ms_per_step": {k: v[0] / args.steps for k, v in stages.items()},
+            "latency_steps": lat_steps,
+            "stage_ms_per_step": {n: v[0] / args.steps for n, v in stages.items()},
+            "stage_ms_single_window": {n: v[0] / lat_steps for n, v in lat_stages.items()},
             "eig_flags": flags,
             "end_to_end": e2e,
         },
-        "roofline": roofline(stages, wl.l, wl.n, L, args.corr),
-        "rooflines_other": stage_rooflines(stages, args.steps, m, wl.rank + wl.oversample,
-                                           wl.power_iters, args.prec),
+        # kernel durations of one window at a time: with several windows in
+        # flight, concurrent launches of the same kernel share the chip and
+        # their durations no longer describe the kernel
+        "roofline": dict(roofline(lat_stages, wl.l, wl.n, L, args.corr),
+                         timing="HIP events on the kernel's stream, one window at a time"),
+        "rooflines_other": stage_rooflines(lat_stages, lat_steps, m, wl.rank + wl.oversample,
+                                           wl.power_iters, args.prec, toe_ms),
         "cpu_baseline": cpu,
     }
-    ctx.close()
+    for c in ctxs:
+        c.close()
     return rec
 
 
@@ -538,6 +613,8 @@ def main() -> int:
     ap.add_argument("--corr", default="bf16x6", choices=tuple(CORR_MODES),
                     help="correlation product arithmetic")
     ap.add_argument("--lag-streams", type=int, default=3)
+    ap.add_argument("--in-flight", type=int, default=3,
+                    help="headline: windows in flight (one context and stream each)")
     ap.add_argument("--requests", type=int, default=96, help="serving: requests per run")
     ap.add_argument("--inflight", type=int, default=64, help="serving: slots")
     ap.add_argument("--pool", type=int, default=24, help="serving: distinct windows")
