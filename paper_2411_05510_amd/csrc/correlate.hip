@@ -56,6 +56,23 @@ SSI_DEV float4 load4(const float *__restrict__ p, int64_t s, int64_t lim) {
 
 SSI_DEV float4 zero4() { return make_float4(0.f, 0.f, 0.f, 0.f); }
 
+// Tile of a workgroup of the one-dimensional grid.  Workgroup p runs on XCD
+// p mod 8 (the dispatcher deals workgroups round-robin over the eight XCDs,
+// each with its own L2), so each XCD gets one contiguous run of tiles in
+// (row tile, column tile, split) order, row tiles fastest: the workgroups
+// resident on one XCD at a time share their B tile (one column tile of one
+// split) instead of every XCD streaming every B tile.
+struct CorrTile { int rt, ct, split; };
+SSI_DEV CorrTile corr_tile(int grid_rows, int grid_cols, int total) {
+  constexpr int kXcd = 8;
+  const int p = blockIdx.x;
+  const int xcd = p % kXcd, k = p / kXcd;
+  const int base = total / kXcd, rem = total % kXcd;
+  const int t = xcd * base + min(xcd, rem) + k;
+  const int rt = t % grid_rows, rest = t / grid_rows;
+  return {rt, rest % grid_cols, rest / grid_cols};
+}
+
 }  // namespace
 
 // One workgroup: rows [r0, r0 + 256) x columns [c0, c0 + 64) over samples
@@ -68,12 +85,13 @@ template <bool VEC>
 __global__ void __launch_bounds__(kThreads, 2)
 correlate_mfma(const float *__restrict__ y, int l, int64_t n, int64_t ldy, int L,
                int64_t split_len, double *__restrict__ partial, int sa_stride,
-               int na_max) {
+               int na_max, int grid_rows, int grid_cols, int n_splits) {
   extern __shared__ float lds[];
   const int rows_total = l * L;
-  const int r0 = blockIdx.x * kRowsPerWG;
-  const int c0 = blockIdx.y * kColsPerWG;
-  const int split = blockIdx.z;
+  const CorrTile tile = corr_tile(grid_rows, grid_cols, grid_rows * grid_cols * n_splits);
+  const int r0 = tile.rt * kRowsPerWG;
+  const int c0 = tile.ct * kColsPerWG;
+  const int split = tile.split;
   const int64_t s_begin = (int64_t)split * split_len;
   const int64_t s_end = min(n, s_begin + split_len);
   if (s_begin >= s_end) return;
@@ -265,12 +283,13 @@ split3_kernel(const float *__restrict__ y, int l, int64_t n, int64_t ldy, int lp
 __global__ void __launch_bounds__(kThreads, 2)
 correlate_b6(const uint16_t *__restrict__ planes, int l, int64_t n, int lp, int64_t np, int L,
              int64_t split_len, double *__restrict__ partial, int sa_stride, int na_max,
-             int copy_stride) {
+             int copy_stride, int grid_rows, int grid_cols, int n_splits) {
   extern __shared__ __align__(16) uint16_t lds6[];
   const int rows_total = l * L;
-  const int r0 = blockIdx.x * kRowsPerWG;
-  const int c0 = blockIdx.y * kColsPerWG;
-  const int split = blockIdx.z;
+  const CorrTile tile = corr_tile(grid_rows, grid_cols, grid_rows * grid_cols * n_splits);
+  const int r0 = tile.rt * kRowsPerWG;
+  const int c0 = tile.ct * kColsPerWG;
+  const int split = tile.split;
   const int64_t s_begin = (int64_t)split * split_len;
   const int64_t s_end = min(n, s_begin + split_len);
   if (s_begin >= s_end) return;
@@ -530,14 +549,15 @@ hipError_t launch_correlate_split(const CorrPlan &p, const float *y, int l, int6
 
 hipError_t launch_correlate_mfma(const CorrPlan &p, const float *y, int l, int64_t n, int64_t ldy,
                                  int L, double *partial, const uint16_t *planes, hipStream_t st) {
-  dim3 grid(p.grid_rows, p.grid_cols, p.splits);
+  const dim3 grid((unsigned)(p.grid_rows * p.grid_cols * p.splits));
   if (p.mode == SSI_CORR_BF16X6) {
     hipError_t e = hipFuncSetAttribute((const void *)correlate_b6,
                                        hipFuncAttributeMaxDynamicSharedMemorySize,
                                        (int)p.lds_bytes);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(correlate_b6, grid, dim3(kThreads), p.lds_bytes, st, planes, l, n, p.lp,
-                       p.np, L, p.split_len, partial, p.sa_stride, p.na_max, p.copy_stride);
+                       p.np, L, p.split_len, partial, p.sa_stride, p.na_max, p.copy_stride,
+                       p.grid_rows, p.grid_cols, p.splits);
     return hipGetLastError();
   }
   const bool vec = (ldy % 4 == 0) && ((uintptr_t)y % 16 == 0);
@@ -549,10 +569,12 @@ hipError_t launch_correlate_mfma(const CorrPlan &p, const float *y, int l, int64
   }
   if (vec)
     hipLaunchKernelGGL(correlate_mfma<true>, grid, dim3(kThreads), p.lds_bytes, st, y, l, n,
-                       ldy, L, p.split_len, partial, p.sa_stride, p.na_max);
+                       ldy, L, p.split_len, partial, p.sa_stride, p.na_max, p.grid_rows,
+                       p.grid_cols, p.splits);
   else
     hipLaunchKernelGGL(correlate_mfma<false>, grid, dim3(kThreads), p.lds_bytes, st, y, l, n,
-                       ldy, L, p.split_len, partial, p.sa_stride, p.na_max);
+                       ldy, L, p.split_len, partial, p.sa_stride, p.na_max, p.grid_rows,
+                       p.grid_cols, p.splits);
   return hipGetLastError();
 }
 
