@@ -193,6 +193,25 @@ def stage_rooflines(stages, steps, m, ell, q, prec: str, toe_launch_ms=None):
     return [prod, toe]
 
 
+def tuned_configs(ctx, wl, prec: str) -> dict:
+    """Launch configurations the autotuner kept for the range-finder products
+    of each lag: {m: {"T X": ..., "T^T X": ...}} with K slices and tile rows."""
+    kind = {"fp32": 0, "bf16": 1, "bf16x3": 3, "bf16x6": 6}[prec]
+    ell = wl.rank + wl.oversample
+    out = {}
+    for jb in wl.lags:
+        m = jb * wl.l
+        cfg = {}
+        for name, trans in (("T X", False), ("T^T X", True)):
+            v = ctx.tuned_splits(kind, trans, m, ell, m)
+            if v:
+                cfg[name] = {"k_slices": v % 100,
+                             "tile_rows": 64 if (kind == 0 and v >= 100) else
+                             (128 if kind == 0 else None)}
+        out[str(m)] = cfg
+    return out
+
+
 def timed_steps(ctx, step, steps, stream):
     """Run `steps` calls of step() bracketed by device synchronization, with
     per-step HIP events on the library stream.  Returns (elapsed s, step ms,
@@ -352,6 +371,7 @@ def bench_identify(args) -> dict:
             "stage_ms_per_step": {n: v[0] / args.steps for n, v in stages.items()},
             "stage_ms_single_window": {n: v[0] / lat_steps for n, v in lat_stages.items()},
             "eig_flags": flags,
+            "autotuned_products": tuned_configs(ctx, wl, args.prec),
             "end_to_end": e2e,
         },
         # kernel durations of one window at a time: with several windows in
@@ -498,6 +518,7 @@ def bench_3d(args) -> dict:
             "poles": n_poles,
             "stable_poles": n_stable,
             "correlation_flops": corr_flops(wl.l, wl.n, L),
+            "autotuned_products": tuned_configs(ctx, wl, args.prec),
         },
     }
     ctx.close()

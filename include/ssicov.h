@@ -235,12 +235,18 @@ ssi_status ssi_set_lag_streams(ssi_ctx *ctx, int32_t n);
 ssi_status ssi_set_graphs(ssi_ctx *ctx, int enable);
 /* Autotuning of the range-finder products (default off).  When on, the
  * first product of each (precision, orientation, M, N, K) times candidate
- * K-slice counts (the planner's own choice, then 2, 4, 6, 8, 12, 16) with
- * HIP events on the context stream
- * (each candidate computes the full product, so results are unaffected) and
+ * launch configurations with HIP events on the context stream: K-slice
+ * counts (the planner's own choice, then 2, 4, 6, 8, 12, 16) and, for the
+ * FP32 x FP64 products, each of them on 128-row and on 64-row output tiles
+ * (each candidate computes the full product, so results are unaffected), and
  * keeps the fastest for the life of the context.  Tuning synchronizes the
  * stream once per new shape and never runs inside a graph capture. */
 ssi_status ssi_set_autotune(ssi_ctx *ctx, int enable);
+/* Output-tile height of the FP32 x FP64 range-finder products for products
+ * the autotuner has not tuned: 0 (default) or 128 for 128-row tiles, 64 for
+ * 64-row tiles (pins the configuration, e.g. for timing or testing one tile
+ * shape).  SSI_EINVAL for other values.  Drops captured graphs. */
+ssi_status ssi_set_product_tile_rows(ssi_ctx *ctx, int32_t rows);
 /* Sweep limit of the eigen-analysis (Eq. (11)): the QR iteration of an order
  * of size n stops after sweeps_per_row * max(10, n) sweeps (default 30, as
  * LAPACK's Hessenberg QR), marks the order in the output flags and makes the
@@ -263,7 +269,9 @@ ssi_status ssi_set_allocator(ssi_ctx *ctx, void *(*alloc)(size_t bytes, void *us
  * ssi_identify and serving calls on this context; default SSI_CORR_BF16X6.
  * SSI_EINVAL for an unknown mode.  Drops captured graphs. */
 ssi_status ssi_set_corr_mode(ssi_ctx *ctx, int32_t mode);
-/* K-slice count chosen by the autotuner for a product, 0 if not tuned.
+/* Launch configuration chosen by the autotuner for a product, 0 if not
+ * tuned: the K-slice count, plus 100 when the FP32 x FP64 product runs on
+ * 64-row output tiles instead of 128-row ones.
  * kind: 0 = FP32 x FP64 product, 1 = BF16 product, 3 = split BF16 product, 6 = three-way
  * split BF16 product;
  * trans: 1 for T^T X. */

@@ -80,6 +80,7 @@ struct ssi_ctx {
   std::vector<Graph> graph_cache;
   // product autotuning: (kind, trans, M, N, K) -> K slices
   bool autotune = false;
+  int tile_rows = 128;            // FP32 x FP64 product tiles when not tuned
   // correlation product arithmetic (ssi_corr_mode)
   int corr_mode = SSI_CORR_BF16X6;
   std::map<std::tuple<int, int, int, int, int>, int> tuned;
@@ -367,6 +368,20 @@ ssi_status ssi_set_autotune(ssi_ctx *c, int enable) {
   return SSI_OK;
 }
 
+ssi_status ssi_set_product_tile_rows(ssi_ctx *c, int32_t rows) {
+  if (!c) return fail(SSI_EINVAL, "ssi_set_product_tile_rows: NULL context");
+  if (rows != 0 && rows != 64 && rows != 128)
+    return fail(SSI_EINVAL, "ssi_set_product_tile_rows: rows = %d must be 0, 64 or 128", rows);
+  const int r = rows == 64 ? 64 : 128;
+  if (r != c->tile_rows) {
+    DeviceGuard g(c->device);
+    drain(c);
+    drop_graphs(c);
+  }
+  c->tile_rows = r;
+  return SSI_OK;
+}
+
 ssi_status ssi_set_corr_mode(ssi_ctx *c, int32_t mode) {
   if (!c) return fail(SSI_EINVAL, "ssi_set_corr_mode: NULL context");
   if (mode != SSI_CORR_FP32 && mode != SSI_CORR_BF16X6)
@@ -556,16 +571,19 @@ bool is_device_ptr(const void *p) {
 
 // ------------------------------------------------------------ products
 // out = op(T) X with T FP32 and X FP64 (FP64 MFMA, split-K partial sums).
-// Number of K slices of a range-finder product.  With autotuning on, the
-// first product of each shape times every candidate slice count on the
-// stream (each run computes the full, correct product) and keeps the fastest
-// for later calls, which are then also safe to capture in a graph.
+// Launch configuration of a range-finder product: its number of K slices
+// and, for the FP32 x FP64 kernel, its output-tile height.  With autotuning
+// on, the first product of each shape times every candidate configuration on
+// the stream (each run computes the full, correct product) and keeps the
+// fastest for later calls, which are then also safe to capture in a graph.
+// A configuration is encoded as slices + kTuneTile64 for 64-row tiles.
 constexpr int kTuneSplits[] = {2, 4, 6, 8, 12, 16};
 constexpr int kTuneMaxSplits = 16;
+constexpr int kTuneTile64 = 100;
 
 template <typename Launch>
 int tuned_splits(ssi_ctx *c, int kind, bool ta, int M, int N, int K, int planned, Launch &&run,
-                 hipError_t &err) {
+                 hipError_t &err, bool tiles = false) {
   const auto key = std::make_tuple(kind, ta ? 1 : 0, M, N, K);
   auto it = c->tuned.find(key);
   if (it != c->tuned.end()) return it->second;
@@ -574,11 +592,15 @@ int tuned_splits(ssi_ctx *c, int kind, bool ta, int M, int N, int K, int planned
   if (!a || !b) return 0;
   int best = 0;
   float best_ms = 0.f;
-  int cands[1 + sizeof(kTuneSplits) / sizeof(int)];
+  int cands[2 * (1 + sizeof(kTuneSplits) / sizeof(int))];
   int nc = 0;
   cands[nc++] = planned;                        // the planner's own choice first
   for (int v : kTuneSplits)
     if (v != planned) cands[nc++] = v;
+  if (tiles) {
+    const int n1 = nc;
+    for (int i = 0; i < n1; ++i) cands[nc++] = cands[i] + kTuneTile64;
+  }
   for (int ci = 0; ci < nc; ++ci) {
     const int cand = cands[ci];
     err = run(cand);                            // warm-up
@@ -602,17 +624,19 @@ int tuned_splits(ssi_ctx *c, int kind, bool ta, int M, int N, int K, int planned
 
 hipError_t prod_tf64(ssi_ctx *c, bool ta, const float *T, int64_t ldt, const double *X,
                      int64_t ldx, int M, int N, int K, double *part, double *out, int64_t ldo) {
-  auto run = [&](int splits) {
-    const ssi::GemmPlan gp = ssi::plan_gemm_tf64(M, N, K, c->num_cus, splits);
+  auto run = [&](int cfg) {
+    const int bm = cfg >= kTuneTile64 ? 64 : 128;
+    const ssi::GemmPlan gp = ssi::plan_gemm_tf64(M, N, K, c->num_cus, cfg % kTuneTile64, bm);
     hipError_t e = ssi::launch_gemm_tf64(gp, ta, T, ldt, X, ldx, M, N, K, part, c->stream);
     if (e != hipSuccess) return e;
     return ssi::launch_reduce(gp, part, M, N, 1.0, out, ldo, nullptr, 0, c->stream);
   };
   hipError_t err = hipSuccess;
   const int planned = ssi::plan_gemm_tf64(M, N, K, c->num_cus).splits;
-  const int splits = tuned_splits(c, 0, ta, M, N, K, planned, run, err);
+  int cfg = tuned_splits(c, 0, ta, M, N, K, planned, run, err, true);
+  if (cfg == 0 && c->tile_rows == 64) cfg = kTuneTile64;   // untuned: planned slices
   if (err != hipSuccess) return err;
-  return run(splits);
+  return run(cfg);
 }
 
 hipError_t prod_f64(ssi_ctx *c, bool ta, const double *A, int64_t lda, const double *B,

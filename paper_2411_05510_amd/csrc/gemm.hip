@@ -26,16 +26,19 @@ constexpr int dBM = 64, dBN = 64, dKT = 16, dLS = dKT + 2;    // fp64 tiles
 //   TA = false: A is M x K (lda);  TA = true: A is K x M (lda), op(A) = A^T.
 //   A FP32, B FP64 K x N (ldb).  VEC: lda % 4 == 0 and A 16-byte aligned;
 //   BVEC: ldb even and B 16-byte aligned.
-// 128 x 224 output tile, 32-deep K tiles and 8 waves
-// (4 x 2, each 32 x 112): the LDS tiles are double-buffered and the next K
-// tile is loaded into registers while the MFMAs of the current one run, so a
+// BM x 224 output tile (BM = 128 or 64), 32-deep K tiles and 8 waves (4 x 2,
+// each BM/4 x 112): the LDS tiles are double-buffered and the next K tile is
+// loaded into registers while the MFMAs of the current one run, so a
 // workgroup streams T with one barrier per K tile.  One workgroup per CU
-// (150 KB of LDS); the FP64 operand is read from L2 once per 128 rows.
+// (150 / 135 KB of LDS); the FP64 operand is read from L2 once per BM rows.
+// The autotuner picks BM with the K-slice count: 128 halves the re-reads of
+// the FP64 operand, 64 gives twice the row tiles on short sides.
 namespace {
-constexpr int wBM = 128, wBN = 224, wKT = 32;
+constexpr int wBN = 224, wKT = 32;
 constexpr int wLA = wKT + 4;          // FP32 A row stride (floats), A stored [i][k]
 constexpr int wLB = wBN + 4;          // FP64 B row stride (doubles), B stored [k][j]
-constexpr int wAS = wBM * wLA, wBS = wKT * wLB;   // one buffer, elements
+constexpr int wBS = wKT * wLB;        // one B buffer, elements
+template <int BM> constexpr int wAS = BM * wLA;   // one A buffer, elements
 typedef double f64x2v __attribute__((ext_vector_type(2)));
 typedef float f32x4v __attribute__((ext_vector_type(4)));
 
@@ -45,13 +48,14 @@ typedef float f32x4v __attribute__((ext_vector_type(4)));
 // The loads then stay in flight across the MFMAs of the current tile: with a
 // bounds branch around each load the compiler waits for every load before
 // issuing the next.
-template <bool TA, bool VEC, bool BVEC>
+template <int BM, bool TA, bool VEC, bool BVEC>
 SSI_DEV void tf64w_load(const float *__restrict__ A, int64_t lda, const double *__restrict__ B,
                         int64_t ldb, int M, int N, int m0, int n0, int k0, int ke, int tid,
-                        f32x4v (&ra)[2], f64x2v (&rb)[7], unsigned &msk) {
+                        f32x4v (&ra)[BM / 64], f64x2v (&rb)[7], unsigned &msk) {
+  constexpr int kI4 = BM / 4;                              // 4-row groups of i (TA)
   unsigned m = 0u;
 #pragma unroll
-  for (int h = 0; h < 2; ++h) {
+  for (int h = 0; h < BM / 64; ++h) {
     const int idx = tid + 512 * h;
     f32x4v v;
     if (!TA) {
@@ -69,7 +73,7 @@ SSI_DEV void tf64w_load(const float *__restrict__ A, int64_t lda, const double *
 #pragma unroll
       for (int c = 0; c < 4; ++c) m |= (gi < M && gk + c < ke ? 1u : 0u) << (4 * h + c);
     } else {
-      const int kr = idx >> 5, c4 = idx & 31;             // k row, 4-column group of i
+      const int kr = idx / kI4, c4 = idx % kI4;           // k row, 4-column group of i
       const int gk = k0 + kr, gi = m0 + 4 * c4;
       const float *p = A + (int64_t)min(gk, ke - 1) * lda;
       if (VEC) {
@@ -105,11 +109,12 @@ SSI_DEV void tf64w_load(const float *__restrict__ A, int64_t lda, const double *
   msk = m;
 }
 
-template <bool TA>
+template <int BM, bool TA>
 SSI_DEV void tf64w_store(float *__restrict__ As, double *__restrict__ Bs, int tid,
-                         const f32x4v (&ra)[2], const f64x2v (&rb)[7], unsigned msk) {
+                         const f32x4v (&ra)[BM / 64], const f64x2v (&rb)[7], unsigned msk) {
+  constexpr int kI4 = BM / 4;
 #pragma unroll
-  for (int h = 0; h < 2; ++h) {
+  for (int h = 0; h < BM / 64; ++h) {
     const int idx = tid + 512 * h;
     f32x4v v = ra[h];
     v.x = (msk >> (4 * h)) & 1u ? v.x : 0.f;
@@ -120,7 +125,7 @@ SSI_DEV void tf64w_store(float *__restrict__ As, double *__restrict__ Bs, int ti
       const int r = idx >> 3, c4 = idx & 7;
       *reinterpret_cast<f32x4v *>(&As[r * wLA + 4 * c4]) = v;
     } else {
-      const int kr = idx >> 5, c4 = idx & 31;
+      const int kr = idx / kI4, c4 = idx % kI4;
       As[(4 * c4 + 0) * wLA + kr] = v.x;
       As[(4 * c4 + 1) * wLA + kr] = v.y;
       As[(4 * c4 + 2) * wLA + kr] = v.z;
@@ -139,56 +144,58 @@ SSI_DEV void tf64w_store(float *__restrict__ As, double *__restrict__ Bs, int ti
 }
 }  // namespace
 
-template <bool TA, bool VEC, bool BVEC>
+template <int BM, bool TA, bool VEC, bool BVEC>
 __global__ void __launch_bounds__(512, 1)
 gemm_tf64w_mfma(const float *__restrict__ A, int64_t lda, const double *__restrict__ B,
                 int64_t ldb, double *__restrict__ C, int64_t ldc, int64_t split_stride, int M,
                 int N, int K, int k_per_split, int gm, int splits) {
+  constexpr int RT = BM / 64;                                    // row tiles of 16 per wave
+  constexpr int AS = wAS<BM>;
   extern __shared__ __attribute__((aligned(16))) double smem[];
-  float *Asb = reinterpret_cast<float *>(smem);                  // [2][wAS] floats
-  double *Bsb = smem + wAS;                                       // [2][wBS] doubles (wAS even)
+  float *Asb = reinterpret_cast<float *>(smem);                  // [2][AS] floats
+  double *Bsb = smem + AS;                                        // [2][wBS] doubles (AS even)
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);   // uniform: the column
                                                                // checks stay scalar
   const int wr = wave & 3, wc = wave >> 2;
   const int split = blockIdx.x % splits;
   const int rest = blockIdx.x / splits;
-  const int m0 = (rest % gm) * wBM, n0 = (rest / gm) * wBN;
+  const int m0 = (rest % gm) * BM, n0 = (rest / gm) * wBN;
   const int kb = split * k_per_split;
   const int ke = min(K, kb + k_per_split);
 
-  f64x4 acc[2][7];
+  f64x4 acc[RT][7];
 #pragma unroll
-  for (int rt = 0; rt < 2; ++rt)
+  for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
     for (int ct = 0; ct < 7; ++ct) acc[rt][ct] = f64x4{0.0, 0.0, 0.0, 0.0};
   bool colok[7];
 #pragma unroll
   for (int ct = 0; ct < 7; ++ct) colok[ct] = n0 + wc * 112 + ct * 16 < N;
 
-  f32x4v ra[2];
+  f32x4v ra[RT];
   f64x2v rb[7];
   unsigned msk = 0u;
   int buf = 0;
   if (kb < ke) {
-    tf64w_load<TA, VEC, BVEC>(A, lda, B, ldb, M, N, m0, n0, kb, ke, tid, ra, rb, msk);
-    tf64w_store<TA>(Asb, Bsb, tid, ra, rb, msk);
+    tf64w_load<BM, TA, VEC, BVEC>(A, lda, B, ldb, M, N, m0, n0, kb, ke, tid, ra, rb, msk);
+    tf64w_store<BM, TA>(Asb, Bsb, tid, ra, rb, msk);
   }
   __syncthreads();
   for (int k0 = kb; k0 < ke; k0 += wKT) {
     const bool more = k0 + wKT < ke;
     if (more)
-      tf64w_load<TA, VEC, BVEC>(A, lda, B, ldb, M, N, m0, n0, k0 + wKT, ke, tid, ra, rb, msk);
-    const float *As = Asb + buf * wAS;
+      tf64w_load<BM, TA, VEC, BVEC>(A, lda, B, ldb, M, N, m0, n0, k0 + wKT, ke, tid, ra, rb, msk);
+    const float *As = Asb + buf * AS;
     const double *Bs = Bsb + buf * wBS;
 #pragma unroll
     for (int hk = 0; hk < wKT / 16; ++hk) {
       const int ko = 16 * hk + 4 * (lane >> 4);
-      f32x4v a4[2];
+      f32x4v a4[RT];
 #pragma unroll
-      for (int rt = 0; rt < 2; ++rt)
+      for (int rt = 0; rt < RT; ++rt)
         a4[rt] = *reinterpret_cast<const f32x4v *>(
-            &As[(wr * 32 + rt * 16 + (lane & 15)) * wLA + ko]);
+            &As[(wr * 16 * RT + rt * 16 + (lane & 15)) * wLA + ko]);
 #pragma unroll
       for (int s = 0; s < 4; ++s) {
         double bv[7];
@@ -198,7 +205,7 @@ gemm_tf64w_mfma(const float *__restrict__ A, int64_t lda, const double *__restri
         for (int ct = 0; ct < 7; ++ct) {
           if (!colok[ct]) continue;
 #pragma unroll
-          for (int rt = 0; rt < 2; ++rt)
+          for (int rt = 0; rt < RT; ++rt)
             acc[rt][ct] = __builtin_amdgcn_mfma_f64_16x16x4f64((double)a4[rt][s], bv[ct],
                                                                acc[rt][ct], 0, 0, 0);
         }
@@ -206,7 +213,7 @@ gemm_tf64w_mfma(const float *__restrict__ A, int64_t lda, const double *__restri
     }
     if (more) {
       // the other buffer was last read before the previous barrier
-      tf64w_store<TA>(Asb + (buf ^ 1) * wAS, Bsb + (buf ^ 1) * wBS, tid, ra, rb, msk);
+      tf64w_store<BM, TA>(Asb + (buf ^ 1) * AS, Bsb + (buf ^ 1) * wBS, tid, ra, rb, msk);
     }
     __syncthreads();
     buf ^= 1;
@@ -215,13 +222,13 @@ gemm_tf64w_mfma(const float *__restrict__ A, int64_t lda, const double *__restri
   // D layout of 16x16x4f64: lane holds rows (lane/16) + 4 q, column lane%16.
   double *dst = C + (int64_t)split * split_stride;
 #pragma unroll
-  for (int rt = 0; rt < 2; ++rt)
+  for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
     for (int ct = 0; ct < 7; ++ct) {
       const int col = n0 + wc * 112 + ct * 16 + (lane & 15);
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        const int row = m0 + wr * 32 + rt * 16 + (lane >> 4) + 4 * q;
+        const int row = m0 + wr * 16 * RT + rt * 16 + (lane >> 4) + 4 * q;
         if (row < M && col < N) dst[(int64_t)row * ldc + col] = acc[rt][ct][q];
       }
     }
@@ -406,9 +413,10 @@ int grid_cap(int64_t work) {
 }
 }  // namespace
 
-GemmPlan plan_gemm_tf64(int M, int N, int K, int num_cus, int force_splits) {
+GemmPlan plan_gemm_tf64(int M, int N, int K, int num_cus, int force_splits, int bm) {
   GemmPlan p{};
-  p.gm = ceil_div(M, wBM);
+  p.bm = bm == 64 ? 64 : 128;
+  p.gm = ceil_div(M, p.bm);
   p.gn = ceil_div(N, wBN);
   // One workgroup per CU: pick the K-slice count whose workgroup count fills
   // whole rounds of the CUs best (fewest idle CU slots), at most 16 slices
@@ -454,20 +462,21 @@ GemmPlan plan_gemm_f64(int M, int N, int K, int num_cus) {
   return p;
 }
 
-template <bool TA>
+template <int BM, bool TA>
 static hipError_t launch_tf64_variant(const GemmPlan &p, bool vec, bool bvec, const float *A,
                                       int64_t lda, const double *B, int64_t ldb, int M, int N,
                                       int K, double *part, hipStream_t st) {
   const dim3 grid((unsigned)((int64_t)p.gm * p.gn * p.splits));
-  // two FP32 A buffers (wAS floats each = wAS doubles in all) and two FP64 B buffers
-  const size_t lds = sizeof(double) * (size_t)(wAS + 2 * wBS);
+  // two FP32 A buffers (AS floats each = AS doubles in all) and two FP64 B buffers
+  const size_t lds = sizeof(double) * (size_t)(wAS<BM> + 2 * wBS);
 #define SSI_TF64(V, BV)                                                                        \
   do {                                                                                         \
-    hipError_t e = hipFuncSetAttribute((const void *)gemm_tf64w_mfma<TA, V, BV>,               \
+    hipError_t e = hipFuncSetAttribute((const void *)gemm_tf64w_mfma<BM, TA, V, BV>,           \
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);  \
     if (e != hipSuccess) return e;                                                             \
-    hipLaunchKernelGGL((gemm_tf64w_mfma<TA, V, BV>), grid, dim3(512), lds, st, A, lda, B, ldb, \
-                       part, p.ldc, p.split_stride, M, N, K, p.k_per_split, p.gm, p.splits);   \
+    hipLaunchKernelGGL((gemm_tf64w_mfma<BM, TA, V, BV>), grid, dim3(512), lds, st, A, lda, B,  \
+                       ldb, part, p.ldc, p.split_stride, M, N, K, p.k_per_split, p.gm,         \
+                       p.splits);                                                              \
   } while (0)
   if (vec && bvec) SSI_TF64(true, true);
   else if (vec) SSI_TF64(true, false);
@@ -482,9 +491,14 @@ hipError_t launch_gemm_tf64(const GemmPlan &p, bool trans_a, const float *A, int
                             hipStream_t st) {
   const bool vec = (lda % 4 == 0) && ((uintptr_t)A % 16 == 0);
   const bool bvec = (ldb % 2 == 0) && ((uintptr_t)B % 16 == 0);
-  hipError_t e = trans_a
-                     ? launch_tf64_variant<true>(p, vec, bvec, A, lda, B, ldb, M, N, K, part, st)
-                     : launch_tf64_variant<false>(p, vec, bvec, A, lda, B, ldb, M, N, K, part, st);
+  hipError_t e;
+  if (p.bm == 64)
+    e = trans_a ? launch_tf64_variant<64, true>(p, vec, bvec, A, lda, B, ldb, M, N, K, part, st)
+                : launch_tf64_variant<64, false>(p, vec, bvec, A, lda, B, ldb, M, N, K, part, st);
+  else
+    e = trans_a ? launch_tf64_variant<128, true>(p, vec, bvec, A, lda, B, ldb, M, N, K, part, st)
+                : launch_tf64_variant<128, false>(p, vec, bvec, A, lda, B, ldb, M, N, K, part,
+                                                  st);
   if (e != hipSuccess) return e;
   return hipGetLastError();
 }

@@ -60,12 +60,13 @@ hipError_t launch_sketch(uint64_t seed, uint32_t stream, int64_t m, int ell, dou
 // ---- dense products (gemm.hip)
 struct GemmPlan {
   int gm, gn, splits, k_per_split;
+  int bm;                        // rows of an output tile (FP32 x FP64 products: 128 or 64)
   int64_t ldc, split_stride;     // partial-sum layout: [splits][M][ldc]
   size_t part_elems() const { return (size_t)splits * (size_t)split_stride; }
 };
 // splits > 0 forces the number of K slices (autotuning); 0 picks it from the
-// shape and the CU count.
-GemmPlan plan_gemm_tf64(int M, int N, int K, int num_cus, int splits = 0);
+// shape and the CU count.  bm: output-tile rows, 128 (default) or 64.
+GemmPlan plan_gemm_tf64(int M, int N, int K, int num_cus, int splits = 0, int bm = 128);
 GemmPlan plan_gemm_f64(int M, int N, int K, int num_cus);
 hipError_t launch_gemm_tf64(const GemmPlan &p, bool trans_a, const float *A, int64_t lda,
                             const double *B, int64_t ldb, int M, int N, int K, double *part,

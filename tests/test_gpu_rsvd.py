@@ -76,6 +76,30 @@ def test_rsvd_low_rank_plus_noise(ctx, m, k, p, q, pad, decay):
     _check_subspace(u, ur, sr, k // 2, 2e-6)
 
 
+@pytest.mark.parametrize("m,k,p,q,pad", [(701, 30, 7, 2, 3), (300, 20, 13, 1, 2), (130, 40, 9, 3, 1),
+                                         (1000, 30, 12, 1, 0)])
+def test_rsvd_64_row_product_tiles(m, k, p, q, pad):
+    """The FP32 x FP64 products on 64-row output tiles (the autotuner's other
+    tile shape), pinned with ssi_set_product_tile_rows: same gates as the
+    128-row default, including a leading dimension that is not a multiple of
+    four (the scalar load path) and a ragged last row tile."""
+    from paper_2411_05510_amd import ssicov
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    c = ssicov.Context(0)
+    try:
+        c.set_product_tile_rows(64)
+        t32 = synth.random_lowrank(m, m, k, seed=m + 3 * k, decay=0.8, noise=1e-5)
+        u, s = _run_rsvd(c, t32, k, p, q, seed=13, pad=pad)
+        om = oracle.sketch(13, m, k + p, 0)
+        ur, sr = oracle.rsvd(t32.astype(np.float64), k, p, q, om)
+        _check_sigma(s, sr)
+        assert np.abs(u.T @ u - np.eye(k)).max() < 1e-8
+        _check_subspace(u, ur, sr, k // 2, 2e-6)
+    finally:
+        c.close()
+
+
 def test_rsvd_full_width_is_exact(ctx):
     m = 48
     t32 = synth.random_matrix(m, m, seed=4)
