@@ -7,3 +7,4 @@ with the GPU path.
 from .ssicov_ref import *  # noqa: F401,F403
 from . import philox  # noqa: F401
 from . import stability  # noqa: F401
+from . import fp8  # noqa: F401
