@@ -48,7 +48,7 @@ COPY_PROBE_BYTES = 256 << 20        # plain device copy used to calibrate HBM by
 PMC_SUMMARY = {"fp32": os.path.join(ROOT, "profiles", "correlate_mfma_bridge180_pmc.md"),
                "bf16x6": os.path.join(ROOT, "profiles", "correlate_b6_bridge180_pmc.md")}
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2411_05510_amd", "csrc", "correlate.hip")
-PRECS = {"fp32": 0, "bf16": 1, "bf16x3": 2, "bf16x6": 3}
+PRECS = {"fp32": 0, "bf16": 1, "bf16x3": 2, "bf16x6": 3, "fp8": 4}
 CORR_MODES = {"fp32": 0, "bf16x6": 1}
 CORR_KERNEL = {"fp32": "correlate_mfma", "bf16x6": "correlate_b6"}
 
@@ -170,7 +170,9 @@ def stage_rooflines(stages, steps, m, ell, q, prec: str, toe_launch_ms=None):
     toe_avg = toe_ms / max(toe_calls, 1)
     toe_gbs = m * m * 4.0 / (toe_avg * 1e-3) / 1e9
     prod = {"stage": "products", "kernels": "gemm_tf64w_mfma + reduce_splits" if prec == "fp32"
-            else "gemm_tbf16_mfma (range finder) + gemm_tf64w_mfma (projection)",
+            else ("quant_rows_f32 / quant_cols + gemm_fp8_mfma (range finder) + gemm_tf64w_mfma "
+                  "(refinement, projection)" if prec == "fp8" else
+                  "gemm_tbf16_mfma (range finder) + gemm_tf64w_mfma (refinement, projection)"),
             "ms_per_identification": prod_ms, "algorithmic_flops": flops, "tflops": tflops,
             "t_read_gbs": t_read}
     if prec == "fp32":
@@ -196,7 +198,7 @@ def stage_rooflines(stages, steps, m, ell, q, prec: str, toe_launch_ms=None):
 def tuned_configs(ctx, wl, prec: str) -> dict:
     """Launch configurations the autotuner kept for the range-finder products
     of each lag: {m: {"T X": ..., "T^T X": ...}} with K slices and tile rows."""
-    kind = {"fp32": 0, "bf16": 1, "bf16x3": 3, "bf16x6": 6}[prec]
+    kind = {"fp32": 0, "bf16": 1, "bf16x3": 3, "bf16x6": 6, "fp8": 0}[prec]
     ell = wl.rank + wl.oversample
     out = {}
     for jb in wl.lags:
@@ -343,7 +345,9 @@ def bench_identify(args) -> dict:
                  "bf16x3": "range-finder products split BF16 x3 (FP32 accumulation), "
                            "projection FP64 MFMA",
                  "bf16x6": "range-finder products as six BF16 products of exact three-way "
-                           "splits (FP32 accumulation), projection FP64 MFMA"}[args.prec]
+                           "splits (FP32 accumulation), projection FP64 MFMA",
+                 "fp8": "range-finder products block-scaled FP8 E4M3 (32-element E8M0 "
+                        "scales, FP32 accumulation), projection FP64 MFMA"}[args.prec]
     rec = {
         "metric": "SSI-COV identifications/s at 180 ch, i=60",
         "value": args.steps / elapsed,

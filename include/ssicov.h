@@ -78,13 +78,24 @@ typedef enum ssi_precision {
                           computation at every order of the 180-channel record at
                           lags 20..100 (worst 1.3e-4); without refinement the
                           products' FP32 accumulation leaves 4e-3 at lag 20    */
-  SSI_PREC_BF16X6 = 3  /* T (FP32 as stored) and X (rounded to FP32) split
+  SSI_PREC_BF16X6 = 3, /* T (FP32 as stored) and X (rounded to FP32) split
                           exactly into three BF16 parts each by truncation; the six
                           products of weight >= 2^-16 on v_mfma_f32_16x16x32_bf16,
                           each exact in FP32, FP32 accumulation: FP32-operand
                           products at the BF16 matrix rate, FP32 accumulation
                           (1.4e-3 in frequency at lag 20 without refinement,
                           5e-5 with one refinement step)                         */
+  SSI_PREC_FP8 = 4     /* T and X block-scaled FP8 E4M3 along the contraction
+                          index (32 elements per power-of-two E8M0 scale; the
+                          block maximum scaled into [128, 256), nearest even),
+                          v_mfma_scale_f32_16x16x128_f8f6f4 with FP32
+                          accumulation, FP64 sum of the K slices.  T is quantized
+                          twice per randomized SVD (along rows for T X, along
+                          columns for T^T X), X before each product.  A
+                          lower-accuracy mode: 3 mantissa bits per operand leave
+                          frequencies within about 1e-2 of the FP64 computation
+                          on a 180-channel record with one refinement step
+                          (ssi_params.refine), the form it is meant to run in   */
 } ssi_precision;
 
 /* Arithmetic of the correlation products (Section 2.1), a context option.

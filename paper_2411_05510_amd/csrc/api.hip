@@ -489,10 +489,10 @@ ssi_status ssi_validate(const ssi_params *p, int32_t l, int64_t n) {
   if (p->svd != SSI_SVD_FULL && p->svd != SSI_SVD_RANDOMIZED)
     return fail(SSI_EINVAL, "unknown svd mode %d", p->svd);
   if (p->prec != SSI_PREC_FP32 && p->prec != SSI_PREC_BF16 && p->prec != SSI_PREC_BF16X3 &&
-      p->prec != SSI_PREC_BF16X6)
+      p->prec != SSI_PREC_BF16X6 && p->prec != SSI_PREC_FP8)
     return fail(SSI_EINVAL, "unknown precision %d", p->prec);
   if (p->prec != SSI_PREC_FP32 && p->svd != SSI_SVD_RANDOMIZED)
-    return fail(SSI_EINVAL, "BF16 products apply to the randomized SVD only");
+    return fail(SSI_EINVAL, "reduced-precision products apply to the randomized SVD only");
   if (p->omega && p->svd != SSI_SVD_RANDOMIZED)
     return fail(SSI_EINVAL, "a caller sketch applies to the randomized SVD only");
   if (p->refine < 0 || (p->refine > 0 && p->svd == SSI_SVD_RANDOMIZED &&
@@ -687,6 +687,9 @@ struct RsvdBufs {
   double *om, *ya, *yb, *gm, *rinv, *lws, *evals, *evecs, *dws, *part;
   uint16_t *xt;        // BF16 X^T of the reduced-precision products
   float *part32;       // their FP32 split partials
+  // FP8 products: T quantized along rows (q8, s8) and along columns (q8t,
+  // s8t), X along columns (x8, xs8)
+  uint8_t *q8, *s8, *q8t, *s8t, *x8, *xs8;
   int ell;
   int prec;
 };
@@ -713,7 +716,25 @@ RsvdBufs carve_rsvd(Arena &a, ssi_ctx *c, int64_t m, int ell, int k, int prec,
                      part_f64(mm, ell, ell, cu), part_f64(mm, k, ell, cu)});
   }
   b.part = a.take<double>(part);
-  if (prec != SSI_PREC_FP32) {
+  if (prec == SSI_PREC_FP8) {
+    size_t q = 0, sc = 0, xq = 0, xs = 0, p32 = 0;
+    for (int i = 0; i < (m_all ? n_m : 1); ++i) {
+      const int mm = m_all ? (int)m_all[i] : mi;
+      const ssi::Fp8Plan fp = ssi::plan_gemm_fp8(mm, ell, mm, cu);
+      q = std::max(q, (size_t)mm * fp.kp);
+      sc = std::max(sc, fp.scale_bytes(mm));
+      xq = std::max(xq, (size_t)fp.n_pad * fp.kp);
+      xs = std::max(xs, fp.scale_bytes(fp.n_pad));
+      p32 = std::max(p32, fp.part_elems());
+    }
+    b.q8 = a.take<uint8_t>(q);
+    b.q8t = a.take<uint8_t>(q);
+    b.s8 = a.take<uint8_t>(sc);
+    b.s8t = a.take<uint8_t>(sc);
+    b.x8 = a.take<uint8_t>(xq);
+    b.xs8 = a.take<uint8_t>(xs);
+    b.part32 = a.take<float>(p32);
+  } else if (prec != SSI_PREC_FP32) {
     const int nt = bf16_terms(prec);
     size_t xt = 0, p32 = 0;
     for (int i = 0; i < (m_all ? n_m : 1); ++i) {
@@ -729,6 +750,31 @@ RsvdBufs carve_rsvd(Arena &a, ssi_ctx *c, int64_t m, int ell, int k, int prec,
     b.part32 = a.take<float>(p32);
   }
   return b;
+}
+
+// out = op(T) X on the FP8 operands (T quantized by quant_t8 for this SVD).
+hipError_t prod_fp8(ssi_ctx *c, RsvdBufs &b, bool ta, const double *X, int64_t ldx, int M,
+                    int N, int K, double *out, int64_t ldo) {
+  const ssi::Fp8Plan fp = ssi::plan_gemm_fp8(M, N, K, c->num_cus);
+  hipError_t e = ssi::launch_quant_cols_f64(X, ldx, K, N, fp.kp, fp.n_pad, b.x8, b.xs8,
+                                            c->stream);
+  if (e != hipSuccess) return e;
+  e = ssi::launch_gemm_fp8(fp, ta ? b.q8t : b.q8, ta ? b.s8t : b.s8, b.x8, b.xs8, M, N, b.part32,
+                           c->stream);
+  if (e != hipSuccess) return e;
+  ssi::BfPlan rp{};
+  rp.splits = fp.splits;
+  rp.split_stride = fp.split_stride;
+  rp.ldc = fp.ldc;
+  return ssi::launch_reduce_f32(rp, b.part32, M, N, out, ldo, c->stream);
+}
+
+// T (m x m) quantized to FP8 along its rows and along its columns.
+hipError_t quant_t8(ssi_ctx *c, RsvdBufs &b, const float *t, int64_t ldt, int m) {
+  const ssi::Fp8Plan fp = ssi::plan_gemm_fp8(m, b.ell, m, c->num_cus);
+  hipError_t e = ssi::launch_quant_rows_f32(t, ldt, m, m, fp.kp, b.q8, b.s8, c->stream);
+  if (e != hipSuccess) return e;
+  return ssi::launch_quant_cols_f32(t, ldt, m, m, fp.kp, m, b.q8t, b.s8t, c->stream);
 }
 
 // Basis of the columns of cur (m x ell, FP64) by shifted CholeskyQR: pass 1
@@ -769,7 +815,10 @@ ssi_status run_rsvd(ssi_ctx *c, RsvdBufs &b, const float *t, int64_t m, int64_t 
   // Y = T Omega, Q = orth(Y)
   {
     StageTimer tm(c, SSI_STAGE_PRODUCTS);
-    if (b.prec != SSI_PREC_FP32)
+    if (b.prec == SSI_PREC_FP8) {
+      e = quant_t8(c, b, t, ldt, mi);
+      if (e == hipSuccess) e = prod_fp8(c, b, false, b.om, ell, mi, ell, mi, b.ya, ell);
+    } else if (b.prec != SSI_PREC_FP32)
       e = prod_bf16(c, false, t, ldt, b.om, ell, mi, ell, mi, bf16_terms(b.prec),
                     b.xt, b.part32, b.ya, ell);
     else
@@ -790,7 +839,9 @@ ssi_status run_rsvd(ssi_ctx *c, RsvdBufs &b, const float *t, int64_t m, int64_t 
         StageTimer tm(c, SSI_STAGE_PRODUCTS);
         // the last `refine` iterations of a reduced-precision range finder
         // run in full precision
-        if (b.prec != SSI_PREC_FP32 && it < q - refine)
+        if (b.prec == SSI_PREC_FP8 && it < q - refine)
+          e = prod_fp8(c, b, side == 0, Q, ell, mi, ell, mi, other, ell);
+        else if (b.prec != SSI_PREC_FP32 && it < q - refine)
           e = prod_bf16(c, side == 0, t, ldt, Q, ell, mi, ell, mi,
                         bf16_terms(b.prec), b.xt, b.part32, other, ell);
         else
@@ -1210,7 +1261,7 @@ ssi_status ssi_rsvd(ssi_ctx *c, const float *t, int64_t m, int64_t ldt, int32_t 
     return fail(SSI_EINVAL, "ssi_rsvd: k + p = %d exceeds %d", k + p, ssi::dense_max_n());
   if (m > INT32_MAX / 2) return fail(SSI_EINVAL, "ssi_rsvd: m too large");
   if (prec != SSI_PREC_FP32 && prec != SSI_PREC_BF16 && prec != SSI_PREC_BF16X3 &&
-      prec != SSI_PREC_BF16X6)
+      prec != SSI_PREC_BF16X6 && prec != SSI_PREC_FP8)
     return fail(SSI_EINVAL, "ssi_rsvd: unknown precision %d", prec);
   DeviceGuard g(c->device);
   if (!is_device_ptr(t) || !is_device_ptr(u) || !is_device_ptr(sigma) ||

@@ -100,6 +100,30 @@ hipError_t launch_gemm_tbf16(const BfPlan &p, bool trans_a, const float *A, int6
 hipError_t launch_reduce_f32(const BfPlan &p, const float *part, int M, int N, double *out,
                              int64_t ldo, hipStream_t st);
 
+// ---- FP8 range-finder products (gemm_fp8.hip): C = A B^T, A (M x K) and B
+// (N x K) block-scaled FP8 E4M3 along K (32 elements per power-of-two scale)
+struct Fp8Plan {
+  int gm, gn, splits, k_per_split;
+  int kp;                        // K rounded up to the 128-deep step (bytes per row)
+  int n_pad;                     // rows of the quantized B (a multiple of the 224-row tile)
+  int64_t ldc, split_stride;     // FP32 partial sums: [splits][M][ldc]
+  size_t part_elems() const { return (size_t)splits * (size_t)split_stride; }
+  size_t scale_bytes(int rows) const { return (size_t)rows * (size_t)(kp / 32); }
+};
+Fp8Plan plan_gemm_fp8(int M, int N, int K, int num_cus, int splits = 0);
+// q[r][0:kp] (E4M3) and s[r][0:kp/32] (E8M0) of a[r][0:cols] (zero past cols)
+hipError_t launch_quant_rows_f32(const float *a, int64_t lda, int rows, int cols, int kp,
+                                 uint8_t *q, uint8_t *s, hipStream_t st);
+// q[j][k] of a[k][j] (the transpose) for j < out_rows, k < kp (zero past the
+// rows x cols input)
+hipError_t launch_quant_cols_f32(const float *a, int64_t lda, int rows, int cols, int kp,
+                                 int out_rows, uint8_t *q, uint8_t *s, hipStream_t st);
+hipError_t launch_quant_cols_f64(const double *a, int64_t lda, int rows, int cols, int kp,
+                                 int out_rows, uint8_t *q, uint8_t *s, hipStream_t st);
+hipError_t launch_gemm_fp8(const Fp8Plan &p, const uint8_t *qa, const uint8_t *sa,
+                           const uint8_t *qb, const uint8_t *sb, int M, int N, float *part,
+                           hipStream_t st);
+
 hipError_t launch_convert_f32_f64(const float *in, int64_t ldi, int M, int N, double *out,
                                   int64_t ldo, hipStream_t st);
 hipError_t launch_sqrt_clamp(const double *ev, int k, double *sigma, hipStream_t st);

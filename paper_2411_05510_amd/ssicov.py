@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(HERE, "libssicov.so")
 
 SSI_OK, SSI_EINVAL, SSI_ENOMEM, SSI_EDEVICE, SSI_ENOCONV, SSI_EINTERNAL, SSI_EBUSY = range(7)
 SVD_FULL, SVD_RANDOMIZED = 0, 1
-PREC_FP32, PREC_BF16, PREC_BF16X3, PREC_BF16X6 = 0, 1, 2, 3
+PREC_FP32, PREC_BF16, PREC_BF16X3, PREC_BF16X6, PREC_FP8 = 0, 1, 2, 3, 4
 CORR_FP32, CORR_BF16X6 = 0, 1
 
 # Every symbol include/ssicov.h declares.
