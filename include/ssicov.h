@@ -389,14 +389,16 @@ ssi_status ssi_sketch(ssi_ctx *ctx, uint64_t seed, uint32_t stream, int64_t m,
 /* Randomized SVD of the m x m matrix T (Algorithm 1, Eq. (13)-(18)):
  * Y = T Omega; Q = orth(Y); q times: Q = orth(T^T Q), Q = orth(T Q);
  * P = Q^T T; P = U~ S V^T; U = Q U~.  The range-finder products follow
- * `prec` (ssi_precision); the projection multiplies FP32 T by FP64 Q with
- * FP64 MFMA accumulation; orthonormal bases (shifted CholeskyQR), the small
- * SVD and U are FP64.
+ * `prec` (ssi_precision), except the last `refine` power iterations, which
+ * run as SSI_PREC_FP32 (0 <= refine <= q; refinement steps of a
+ * reduced-precision range finder); the projection multiplies FP32 T by FP64
+ * Q with FP64 MFMA accumulation; orthonormal bases (shifted CholeskyQR), the
+ * small SVD and U are FP64.
  * t: device m x ldt floats.  omega: device m x (k+p) floats (ld k+p), or NULL
  * to draw it with ssi_sketch(seed, stream).  u: device m x k doubles
  * (row-major, ld k).  sigma: device k doubles, descending. */
 ssi_status ssi_rsvd(ssi_ctx *ctx, const float *t, int64_t m, int64_t ldt,
-                    int32_t k, int32_t p, int32_t q, int32_t prec,
+                    int32_t k, int32_t p, int32_t q, int32_t prec, int32_t refine,
                     const float *omega, uint64_t seed, uint32_t stream, double *u,
                     double *sigma);
 

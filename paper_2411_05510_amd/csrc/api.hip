@@ -1251,12 +1251,14 @@ ssi_status ssi_workspace_estimate(const ssi_params *p, int32_t l, int64_t n, siz
 }
 
 ssi_status ssi_rsvd(ssi_ctx *c, const float *t, int64_t m, int64_t ldt, int32_t k, int32_t p,
-                    int32_t q, int32_t prec, const float *omega, uint64_t seed, uint32_t stream,
-                    double *u, double *sigma) {
+                    int32_t q, int32_t prec, int32_t refine, const float *omega, uint64_t seed,
+                    uint32_t stream, double *u, double *sigma) {
   if (!c) return fail(SSI_EINVAL, "ssi_rsvd: NULL context");
   if (!t || !u || !sigma) return fail(SSI_EINVAL, "ssi_rsvd: NULL buffer");
   if (m < 1 || ldt < m || k < 1 || p < 0 || q < 0 || (int64_t)k + p > m)
     return fail(SSI_EINVAL, "ssi_rsvd: need 1 <= k, 0 <= p, 0 <= q, k + p <= m <= ldt");
+  if (refine < 0 || refine > q)
+    return fail(SSI_EINVAL, "ssi_rsvd: refine = %d must be in [0, q]", refine);
   if (k + p > ssi::dense_max_n())
     return fail(SSI_EINVAL, "ssi_rsvd: k + p = %d exceeds %d", k + p, ssi::dense_max_n());
   if (m > INT32_MAX / 2) return fail(SSI_EINVAL, "ssi_rsvd: m too large");
@@ -1273,7 +1275,7 @@ ssi_status ssi_rsvd(ssi_ctx *c, const float *t, int64_t m, int64_t ldt, int32_t 
   if (s != SSI_OK) return s;
   Arena a{c->ws, 0};
   RsvdBufs b = carve_rsvd(a, c, m, k + p, k, prec);
-  return run_rsvd(c, b, t, m, ldt, k, p, q, omega, k + p, seed, stream, u, sigma);
+  return run_rsvd(c, b, t, m, ldt, k, p, q, omega, k + p, seed, stream, u, sigma, refine);
 }
 
 ssi_status ssi_svd_full(ssi_ctx *c, const float *t, int64_t m, int64_t ldt, int32_t k, double *u,

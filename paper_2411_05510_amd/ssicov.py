@@ -149,7 +149,8 @@ def lib() -> ctypes.CDLL:
             "ssi_correlate": ([vp, vp, i32, i64, i64, i32, vp], ctypes.c_int),
             "ssi_toeplitz": ([vp, vp, i32, i32, vp, i64], ctypes.c_int),
             "ssi_sketch": ([vp, u64, u32, i64, i32, vp, i64], ctypes.c_int),
-            "ssi_rsvd": ([vp, vp, i64, i64, i32, i32, i32, i32, vp, u64, u32, vp, vp], ctypes.c_int),
+            "ssi_rsvd": ([vp, vp, i64, i64, i32, i32, i32, i32, i32, vp, u64, u32, vp, vp],
+                         ctypes.c_int),
             "ssi_svd_full": ([vp, vp, i64, i64, i32, vp, vp], ctypes.c_int),
             "ssi_modal": ([vp, vp, vp, i64, i32, i32, P, i32, ctypes.POINTER(_Output)],
                           ctypes.c_int),
@@ -418,14 +419,14 @@ class Context:
         return out
 
     def rsvd(self, t, k: int, p: int, q: int, omega=None, seed: int = 0, stream: int = 0,
-             prec: int = PREC_FP32):
+             prec: int = PREC_FP32, refine: int = 0):
         """(U (m, k) float64, sigma (k,) float64) of the device matrix t (m, ldt) float32."""
         import torch
         m = t.shape[0]
         u = torch.empty((m, k), dtype=torch.float64, device=t.device)
         s = torch.empty((k,), dtype=torch.float64, device=t.device)
         om = _ptr(omega) if omega is not None else None
-        _check(lib().ssi_rsvd(self._h, _ptr(t), m, t.stride(0), k, p, q, prec, om,
+        _check(lib().ssi_rsvd(self._h, _ptr(t), m, t.stride(0), k, p, q, prec, refine, om,
                               seed & 0xFFFFFFFFFFFFFFFF, stream, _ptr(u), _ptr(s)))
         return u, s
 

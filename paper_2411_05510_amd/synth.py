@@ -131,6 +131,7 @@ class Workload:
     struct_seed: int = 0
     noise_seed: int = 0
     sketch_seed: int = 0
+    min_rel_spacing: float = 0.01   # adjacent generated frequencies differ by at least this
 
     @property
     def orders(self) -> List[int]:
@@ -172,7 +173,7 @@ WORKLOADS: Dict[str, Workload] = {
                        zeta_range=(0.005, 0.03), noise=0.03, lags=(100,),
                        svd="randomized", rank=400, oversample=40,
                        power_iters=3, order_min=2, order_max=400,
-                       order_step=4),
+                       order_step=4, min_rel_spacing=0.002),
 }
 
 
@@ -181,7 +182,7 @@ def make_record(wl: Workload, n: Optional[int] = None):
 
     Returns (system, y) with y float32 of shape (l, n)."""
     sysm = draw_system(wl.l, wl.n_modes, wl.f_range, wl.zeta_range, wl.fs,
-                       wl.struct_seed)
+                       wl.struct_seed, wl.min_rel_spacing)
     y = simulate(sysm, wl.n if n is None else n, wl.noise, wl.noise_seed)
     return sysm, y
 
