@@ -28,7 +28,7 @@
 
 namespace {
 
-constexpr int fBM = 64, fBN = 224, fKS = 128;    // workgroup tile, K step
+constexpr int fBM = 128, fBN = 224, fKS = 128;   // workgroup tile, K step
 constexpr int kBlk = 32;                         // elements per scale
 
 typedef int i32x8 __attribute__((ext_vector_type(8)));
@@ -124,19 +124,33 @@ quant_cols(const T *__restrict__ a, int64_t lda, int rows, int cols, int kp, int
 }
 
 // C_part[split][i][j] = sum_{k in split} A[i][k] B[j][k] (dequantized), FP32.
-// 4 waves (2 x 2), each 32 x 112 (2 x 7 tiles of 16 x 16); operands are read
-// straight from global memory (A streams once per column half, B stays in
-// L2), two K steps of fragments in registers so the next step's loads are in
-// flight during the current step's products.  Every load is issued, at an
-// index clamped into the split, so no load sits under a branch.
-__global__ void __launch_bounds__(256)
+// 8 waves (4 x 2), each 32 x 112 (2 x 7 tiles of 16 x 16), on a 128 x 224
+// tile.  Each 128-deep K step of A (128 rows) and B (224 rows), codes and
+// scales, is staged in LDS by the whole workgroup (rows padded to 144 bytes,
+// so the 16 rows a fragment read touches start in different banks), double
+// buffered: the next step's global loads are in registers while the current
+// step's products run, with one barrier per step.  Every global load is
+// issued at an index clamped into its array, so none sits under a branch.
+namespace {
+constexpr int fLS = fKS + 16;                    // LDS row stride (bytes)
+constexpr int fAT = fBM * fLS, fBT = fBN * fLS;  // one buffer of A / B codes
+constexpr int kFThreads = 512;
+// codes, one scale word per thread (rows of A, then of B, then unused), and a
+// 16-byte dummy slot per thread for the B chunks past the tile
+constexpr int fBuf = fAT + fBT + 4 * kFThreads + 16 * kFThreads;
+static_assert(fBM * fKS / 16 == 2 * kFThreads, "two A chunks per thread");
+static_assert(fBN * fKS / 16 <= 4 * kFThreads, "at most four B chunks per thread");
+}  // namespace
+
+__global__ void __launch_bounds__(kFThreads)
 gemm_fp8_mfma(const uint8_t *__restrict__ qa, const uint8_t *__restrict__ sa,
               const uint8_t *__restrict__ qb, const uint8_t *__restrict__ sb, int kp, int M,
-              int N, float *__restrict__ C, int64_t ldc, int64_t split_stride, int k_per_split,
-              int gm, int splits) {
+              int N, int n_pad, float *__restrict__ C, int64_t ldc, int64_t split_stride,
+              int k_per_split, int gm, int splits) {
+  extern __shared__ __align__(16) uint8_t lds8[];
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int wr = wave & 1, wc = wave >> 1;
+  const int wr = wave & 3, wc = wave >> 2;
   const int split = blockIdx.x % splits, rest = blockIdx.x / splits;
   const int m0 = (rest % gm) * fBM, n0 = (rest / gm) * fBN;
   const int kb = split * k_per_split, ke = min(kp, kb + k_per_split);
@@ -144,64 +158,106 @@ gemm_fp8_mfma(const uint8_t *__restrict__ qa, const uint8_t *__restrict__ sa,
   const int r = lane & 15, g = lane >> 4;
   const int nb = kp / kBlk;
 
-  const uint8_t *pa[2], *psa[2], *pb[7], *psb[7];
+  // global chunks of this thread: A rows ar[h] (h < 2), B rows br[h] (h < 4)
+  const uint8_t *ga[2], *gb[4];
+  int la[2], lb[4];
 #pragma unroll
-  for (int rt = 0; rt < 2; ++rt) {
-    const int row = min(m0 + wr * 32 + rt * 16 + r, M - 1);
-    pa[rt] = qa + (int64_t)row * kp + 16 * g;
-    psa[rt] = sa + (int64_t)row * nb + g;
+  for (int h = 0; h < 2; ++h) {
+    const int idx = tid + kFThreads * h, row = idx >> 3, ch = idx & 7;
+    ga[h] = qa + (int64_t)min(m0 + row, M - 1) * kp + 16 * ch;
+    la[h] = row * fLS + 16 * ch;
   }
 #pragma unroll
-  for (int ct = 0; ct < 7; ++ct) {
-    const int col = n0 + wc * 112 + ct * 16 + r;       // < the padded B rows
-    pb[ct] = qb + (int64_t)col * kp + 16 * g;
-    psb[ct] = sb + (int64_t)col * nb + g;
+  for (int h = 0; h < 4; ++h) {
+    const int idx = tid + kFThreads * h;
+    const bool ok = idx < fBN * fKS / 16;
+    const int row = ok ? idx >> 3 : 0, ch = idx & 7;
+    gb[h] = qb + (int64_t)min(n0 + row, n_pad - 1) * kp + 16 * ch;
+    // chunks past the tile land in this thread's dummy slot: no store branch
+    lb[h] = ok ? fAT + row * fLS + 16 * ch : fAT + fBT + 4 * kFThreads + 16 * tid;
   }
+  // scale words (the 4 blocks of a step): A rows for tid < 128, B rows for
+  // 128 <= tid < 352; the other threads load a valid word and store it unused
+  const int srow = tid < fBM ? tid : tid - fBM;
+  const uint8_t *gs = tid < fBM ? sa + (int64_t)min(m0 + srow, M - 1) * nb
+                                : sb + (int64_t)min(n0 + min(srow, fBN - 1), n_pad - 1) * nb;
+
+  // the next step's chunks (plain registers: arrays captured by a lambda
+  // end up in scratch memory)
+  uint4 ra0, ra1, rb0, rb1, rb2, rb3;
+  uint32_t rs = 0;
+#define SSI_FP8_GLOAD(k0)                                                       \
+  do {                                                                          \
+    ra0 = *reinterpret_cast<const uint4 *>(ga[0] + (k0));                       \
+    ra1 = *reinterpret_cast<const uint4 *>(ga[1] + (k0));                       \
+    rb0 = *reinterpret_cast<const uint4 *>(gb[0] + (k0));                       \
+    rb1 = *reinterpret_cast<const uint4 *>(gb[1] + (k0));                       \
+    rb2 = *reinterpret_cast<const uint4 *>(gb[2] + (k0));                       \
+    rb3 = *reinterpret_cast<const uint4 *>(gb[3] + (k0));                       \
+    rs = *reinterpret_cast<const uint32_t *>(gs + (k0) / kBlk);                 \
+  } while (0)
+#define SSI_FP8_LSTORE(buf)                                                     \
+  do {                                                                          \
+    *reinterpret_cast<uint4 *>((buf) + la[0]) = ra0;                            \
+    *reinterpret_cast<uint4 *>((buf) + la[1]) = ra1;                            \
+    *reinterpret_cast<uint4 *>((buf) + lb[0]) = rb0;                            \
+    *reinterpret_cast<uint4 *>((buf) + lb[1]) = rb1;                            \
+    *reinterpret_cast<uint4 *>((buf) + lb[2]) = rb2;                            \
+    *reinterpret_cast<uint4 *>((buf) + lb[3]) = rb3;                            \
+    reinterpret_cast<uint32_t *>((buf) + fAT + fBT)[tid] = rs;                  \
+  } while (0)
+
   f32x4v acc[2][7];
 #pragma unroll
   for (int rt = 0; rt < 2; ++rt)
 #pragma unroll
     for (int ct = 0; ct < 7; ++ct) acc[rt][ct] = f32x4v{0.f, 0.f, 0.f, 0.f};
 
-  auto frag = [](const uint8_t *p, int k0) {
-    const uint4 lo = *reinterpret_cast<const uint4 *>(p + k0);
-    const uint4 hi = *reinterpret_cast<const uint4 *>(p + k0 + 64);
+  auto frag = [](const uint8_t *p) {
+    const uint4 lo = *reinterpret_cast<const uint4 *>(p);
+    const uint4 hi = *reinterpret_cast<const uint4 *>(p + 64);
     i32x8 f;
     f[0] = (int)lo.x; f[1] = (int)lo.y; f[2] = (int)lo.z; f[3] = (int)lo.w;
     f[4] = (int)hi.x; f[5] = (int)hi.y; f[6] = (int)hi.z; f[7] = (int)hi.w;
     return f;
   };
-  i32x8 xa[2], xb[7], ya[2], yb[7];
-  int xsa[2], xsb[7], ysa[2], ysb[7];
-  auto load = [&](int k0, i32x8 (&fa)[2], i32x8 (&fb)[7], int (&s_a)[2], int (&s_b)[7]) {
+  const int klast = ke - fKS;                    // a valid step start
+  if (steps > 0) {
+    SSI_FP8_GLOAD(kb);
+    SSI_FP8_LSTORE(lds8);
+  }
+  __syncthreads();
+  for (int s = 0; s < steps; ++s) {
+    const uint8_t *buf = lds8 + (s & 1) * fBuf;
+    SSI_FP8_GLOAD(min(kb + (s + 1) * fKS, klast));   // the next step, in flight
+    const uint8_t *As = buf, *Bs = buf + fAT;
+    const uint32_t *Ss = reinterpret_cast<const uint32_t *>(buf + fAT + fBT);
+    i32x8 fa[2], fb[7];
+    int sa_[2], sb_[7];
 #pragma unroll
     for (int rt = 0; rt < 2; ++rt) {
-      fa[rt] = frag(pa[rt], k0);
-      s_a[rt] = psa[rt][k0 / kBlk];
+      const int row = wr * 32 + rt * 16 + r;
+      fa[rt] = frag(As + row * fLS + 16 * g);
+      sa_[rt] = (int)((Ss[row] >> (8 * g)) & 0xFFu);
     }
 #pragma unroll
     for (int ct = 0; ct < 7; ++ct) {
-      fb[ct] = frag(pb[ct], k0);
-      s_b[ct] = psb[ct][k0 / kBlk];
+      const int row = wc * 112 + ct * 16 + r;
+      fb[ct] = frag(Bs + row * fLS + 16 * g);
+      sb_[ct] = (int)((Ss[fBM + row] >> (8 * g)) & 0xFFu);
     }
-  };
-  auto mma = [&](const i32x8 (&fa)[2], const i32x8 (&fb)[7], const int (&s_a)[2],
-                 const int (&s_b)[7]) {
 #pragma unroll
     for (int ct = 0; ct < 7; ++ct)
 #pragma unroll
       for (int rt = 0; rt < 2; ++rt)
         acc[rt][ct] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(
-            fa[rt], fb[ct], acc[rt][ct], 0, 0, 0, s_a[rt], 0, s_b[ct]);
-  };
-  const int klast = ke - fKS;                            // a valid step start
-  if (steps > 0) load(kb, xa, xb, xsa, xsb);
-  for (int s = 0; s < steps; s += 2) {
-    load(min(kb + (s + 1) * fKS, klast), ya, yb, ysa, ysb);
-    mma(xa, xb, xsa, xsb);
-    load(min(kb + (s + 2) * fKS, klast), xa, xb, xsa, xsb);
-    if (s + 1 < steps) mma(ya, yb, ysa, ysb);
+            fa[rt], fb[ct], acc[rt][ct], 0, 0, 0, sa_[rt], 0, sb_[ct]);
+    // the other buffer was last read before the previous barrier
+    SSI_FP8_LSTORE(lds8 + ((s + 1) & 1) * fBuf);
+    __syncthreads();
   }
+#undef SSI_FP8_GLOAD
+#undef SSI_FP8_LSTORE
 
   // D layout of 16x16 MFMA: lane holds rows 4 (lane / 16) + q, column lane % 16.
   float *dst = C + (int64_t)split * split_stride;
@@ -226,10 +282,10 @@ Fp8Plan plan_gemm_fp8(int M, int N, int K, int num_cus, int force_splits) {
   p.gm = ceil_div(M, fBM);
   p.gn = ceil_div(N, fBN);
   p.n_pad = p.gn * fBN;
-  // two workgroups per CU; fill about two rounds, at least 4 K steps a slice
+  // one workgroup per CU; fill about two rounds, at least 4 K steps a slice
   const int64_t tiles = (int64_t)p.gm * p.gn;
   const int64_t steps = p.kp / fKS;
-  int64_t splits = ceil_div<int64_t>((int64_t)num_cus * 4, tiles);
+  int64_t splits = ceil_div<int64_t>((int64_t)num_cus * 2, tiles);
   splits = std::max<int64_t>(1, std::min<int64_t>({splits, 16, ceil_div<int64_t>(steps, 4)}));
   if (force_splits > 0) splits = std::min<int64_t>(force_splits, steps);
   const int64_t sps = ceil_div<int64_t>(steps, splits);          // steps per slice
@@ -268,8 +324,12 @@ hipError_t launch_gemm_fp8(const Fp8Plan &p, const uint8_t *qa, const uint8_t *s
                            const uint8_t *qb, const uint8_t *sb, int M, int N, float *part,
                            hipStream_t st) {
   const dim3 grid((unsigned)((int64_t)p.gm * p.gn * p.splits));
-  hipLaunchKernelGGL(gemm_fp8_mfma, grid, dim3(256), 0, st, qa, sa, qb, sb, p.kp, M, N, part,
-                     p.ldc, p.split_stride, p.k_per_split, p.gm, p.splits);
+  const size_t lds = 2 * (size_t)fBuf;
+  hipError_t e = hipFuncSetAttribute((const void *)gemm_fp8_mfma,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(gemm_fp8_mfma, grid, dim3(kFThreads), lds, st, qa, sa, qb, sb, p.kp, M, N,
+                     p.n_pad, part, p.ldc, p.split_stride, p.k_per_split, p.gm, p.splits);
   return hipGetLastError();
 }
 
