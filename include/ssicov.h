@@ -292,7 +292,7 @@ int32_t ssi_tuned_splits(const ssi_ctx *ctx, int32_t kind, int32_t trans, int32_
 /* ----------------------------------------------- host-only helpers (no GPU) */
 
 /* Check parameters against l channels and n samples: 2 <= j_b, 2 j_b - 1 < n,
- * 1 <= order_min <= order_max <= min(l (j_b - 1), 224) for every lag; for the
+ * 1 <= order_min <= order_max <= min(l (j_b - 1), 448) for every lag; for the
  * randomized mode order_max <= k and k + p <= min(j_b l, 1024); for the full
  * SVD j_b l <= 1024.  Host-only. */
 ssi_status ssi_validate(const ssi_params *p, int32_t l, int64_t n);
@@ -413,7 +413,7 @@ ssi_status ssi_svd_full(ssi_ctx *ctx, const float *t, int64_t m, int64_t ldt,
  * through the similar matrix pinv(U_top,n) U_bot,n, which has the same
  * eigenvalues, with phi = U[0:l, :n] psi (so sigma only scales and is not
  * read).  u: device m x k doubles (ld k), sigma: device k doubles, m = jb l,
- * order_max <= min(k, m - l, 224).  Writes lag slot `lag_index` of `out`
+ * order_max <= min(k, m - l, 448).  Writes lag slot `lag_index` of `out`
  * (out->sigma is not written). */
 ssi_status ssi_modal(ssi_ctx *ctx, const double *u, const double *sigma,
                      int64_t m, int32_t k, int32_t l, const ssi_params *p,

@@ -10,7 +10,8 @@
 // Per order n (one workgroup each):
 //   form_x      X_n = Rinv[:n,:n] W[:n,:n]
 //   hess        Householder reduction X_n = Q H Q^T (H upper Hessenberg),
-//               matrix held in registers over a 16 x 32 thread grid
+//               matrix held in registers over a 16 x 32 thread grid (n <= 224)
+//               or reduced in place in global memory (n <= 448)
 //   francis     eigenvalues of H by the Francis double-shift QR iteration with
 //               deflation, H packed in LDS (n <= 200) or in global scratch
 //   vec         per pole (Im mu > 0): inverse iteration on H - mu I in complex
@@ -28,7 +29,8 @@ namespace {
 
 constexpr int kT = 512;                 // threads of the register-tile kernels
 constexpr int kTP = 14, kTQ = 7;        // 16 x 32 grid, n <= 224
-constexpr int kNR = 224;
+constexpr int kNR = 224;                // largest order of the register-tile reduction
+constexpr int kNMax = 448;              // largest order of the modal stage
 
 SSI_DEV int row_of(int tr, int p) { return tr + 16 * p; }
 SSI_DEV int col_of(int tc, int q) { return tc + 32 * q; }
@@ -86,9 +88,11 @@ form_x_kernel(const double *__restrict__ rinv, const double *__restrict__ w, int
 
 // ------------------------------------------------------------------ hess
 // Householder reduction of X_n (n <= 224) to upper Hessenberg form.  Writes H
-// (n x n, by columns: H(i, j) at j n + i) to hbuf, reflector vectors (rows of kNR) to vref and their
-// scalars to taus.  TP row blocks of 16 cover n <= 16 TP (13 for n <= 208
-// keeps the register tile clear of scratch spills; 14 for n <= 224).
+// (n x n, by columns: H(i, j) at j n + i) to hbuf, the reflector vectors to
+// vref (v_k in row k of an n x n block at the order's offset sq) and their
+// scalars to taus (at the order's offset vec).  TP row blocks of 16 cover
+// n <= 16 TP (13 for n <= 208 keeps the register tile clear of scratch
+// spills; 14 for n <= 224).
 template <int TP>
 __global__ void __launch_bounds__(kT)
 hess_kernel(const double *__restrict__ xbuf, int nmin, int step, double *__restrict__ hbuf,
@@ -101,8 +105,8 @@ hess_kernel(const double *__restrict__ xbuf, int nmin, int step, double *__restr
   const int n = geo.n;
   const double *X = xbuf + geo.sq;
   double *H = hbuf + geo.sq;
-  double *vr = vref + (size_t)blockIdx.x * kNR * kNR;
-  double *tv = taus + (size_t)blockIdx.x * kNR;
+  double *vr = vref + geo.sq;
+  double *tv = taus + geo.vec;
   const int t = threadIdx.x, tr = t & 15, tc = t >> 4, lane = t & 63, wave = t >> 6;
   double g[TP][kTQ];
 #pragma unroll
@@ -143,7 +147,7 @@ hess_kernel(const double *__restrict__ xbuf, int nmin, int step, double *__restr
           if (i < n) {
             const double v = (i == k + 1) ? v1 : sel(i > k + 1, g[p][kq]);
             vbuf[i] = v;
-            vr[(size_t)k * kNR + i] = v;
+            vr[(size_t)k * n + i] = v;
           }
         }
         if (tr == 0) {
@@ -226,6 +230,225 @@ hess_kernel(const double *__restrict__ xbuf, int nmin, int step, double *__restr
     }
 }
 
+// ------------------------------------------------------------------ hess (global)
+// Householder reduction of X_n for kNR < n <= kNMax, in place in global
+// memory: X_n is copied into H by columns and reduced there; the reflectors
+// and their scalars are written as by hess_kernel.  One workgroup of kHG
+// threads per order; in a pass over columns, wave w takes the columns
+// j = w (mod kHW) and lane a holds rows a + 64 u (u < kHU) of each.
+//
+// With v, tau the reflector of step k, z = X^T v and p = X v (X as step
+// k - 1 left it), the two-sided update P X P (P = I - tau v v^T) is
+//   X - tau v z^T - w v^T,   w = tau (p - tau (z . v) v),
+// since (P X) v = p - tau (z . v) v.  The next step's z and p need column
+// k + 1 as this step leaves it, so each step first updates column k + 1
+// alone and forms the next reflector from it; the pass that then updates
+// columns k + 2 .. n - 1 accumulates the next z (per column) and p (per row)
+// from the values it writes.  Each active column is read and written once
+// per step.
+constexpr int kHG = 512, kHW = kHG / 64, kHU = kNMax / 64;
+static_assert(kNMax <= kHG, "one row per thread in the column steps");
+
+namespace {
+
+// Sums of a and b over the workgroup (kHG threads); red holds 2 kHW doubles.
+SSI_DEV void hg_sum2(double &a, double &b, double *red) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  a = wave_sum(a);
+  b = wave_sum(b);
+  __syncthreads();                       // red is free
+  if (lane == 0) {
+    red[wave] = a;
+    red[kHW + wave] = b;
+  }
+  __syncthreads();
+  a = 0.0;
+  b = 0.0;
+#pragma unroll
+  for (int w = 0; w < kHW; ++w) {
+    a += red[w];
+    b += red[kHW + w];
+  }
+}
+
+// Reflector of step c from column c; thread t < n holds entry (t, c) in x.
+// Writes v to sv and to row c of vr, tau to *stau and tv[c]; returns the
+// thread's entry of the reduced column (alpha at row c + 1, zero below).
+SSI_DEV double hg_reflector(double x, int c, int n, double *sv, double *stau, double *vr,
+                            double *tv, double *red) {
+  const int t = threadIdx.x;
+  double s2 = (t > c + 1 && t < n) ? x * x : 0.0;
+  double x1 = (t == c + 1) ? x : 0.0;
+  hg_sum2(s2, x1, red);
+  double tau = 0.0, v1 = 0.0, alpha = 0.0;
+  if (s2 > 0.0) {
+    alpha = -copysign(sqrt(x1 * x1 + s2), x1);
+    v1 = x1 - alpha;
+    tau = 2.0 / (s2 + v1 * v1);
+  }
+  if (t < n) {
+    const double v = (t == c + 1) ? v1 : (t > c + 1 ? x : 0.0);
+    sv[t] = v;
+    vr[(size_t)c * n + t] = v;
+  }
+  if (t == 0) {
+    *stau = tau;
+    tv[c] = tau;
+  }
+  return (tau != 0.0 && t > c) ? (t == c + 1 ? alpha : 0.0) : x;
+}
+
+// One pass over columns jbeg..n-1: with UPD, x -= tau v_i z_j + w_i v_j and
+// store; with ACC, zn[j] = sum_i vn_i x(i, j) and pacc_i += x(i, j) vn_j.
+// Two columns per wave are in flight together.
+template <bool UPD, bool ACC>
+SSI_DEV void hg_pass(double *H, int n, int jbeg, double tau, const double *v, const double *z,
+                     const double *w, const double *vn, double *zn, double (&pacc)[kHU]) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  double vi[kHU], wi[kHU], vni[kHU];
+#pragma unroll
+  for (int u = 0; u < kHU; ++u) {
+    const int i = lane + 64 * u, ic = min(i, n - 1);
+    vi[u] = (UPD && i < n) ? v[ic] : 0.0;
+    wi[u] = (UPD && i < n) ? w[ic] : 0.0;
+    vni[u] = (ACC && i < n) ? vn[ic] : 0.0;
+    pacc[u] = 0.0;
+  }
+  for (int j0 = jbeg + wave; j0 < n; j0 += 2 * kHW) {
+    const int j1 = j0 + kHW;
+    const bool has1 = j1 < n;
+    double *c0 = H + (int64_t)j0 * n, *c1 = H + (int64_t)min(j1, n - 1) * n;
+    double x0[kHU], x1[kHU];
+#pragma unroll
+    for (int u = 0; u < kHU; ++u) {
+      const int ic = min(lane + 64 * u, n - 1);
+      x0[u] = c0[ic];
+      x1[u] = c1[ic];
+    }
+    if (UPD) {
+      const double tz0 = tau * z[j0], vj0 = v[j0];
+      const double tz1 = has1 ? tau * z[j1] : 0.0, vj1 = has1 ? v[j1] : 0.0;
+#pragma unroll
+      for (int u = 0; u < kHU; ++u) {
+        x0[u] -= vi[u] * tz0 + wi[u] * vj0;
+        x1[u] -= vi[u] * tz1 + wi[u] * vj1;
+      }
+#pragma unroll
+      for (int u = 0; u < kHU; ++u) {
+        const int i = lane + 64 * u;
+        if (i < n) {
+          c0[i] = x0[u];
+          if (has1) c1[i] = x1[u];
+        }
+      }
+    }
+    if (ACC) {
+      const double vn0 = vn[j0], vn1 = has1 ? vn[j1] : 0.0;
+      double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+      for (int u = 0; u < kHU; ++u) {
+        s0 += vni[u] * x0[u];
+        s1 += vni[u] * x1[u];
+        pacc[u] += x0[u] * vn0 + x1[u] * vn1;
+      }
+      s0 = wave_sum(s0);
+      s1 = wave_sum(s1);
+      if (lane == 0) {
+        zn[j0] = s0;
+        if (has1) zn[j1] = s1;
+      }
+    }
+  }
+}
+
+// p of the next step from the per-wave partials, then its w:
+// w_i = tau (p_i - tau (z . v) v_i), z . v over the columns from jbeg.
+SSI_DEV void hg_finish(int n, int jbeg, const double (&pacc)[kHU], double (*pp)[kNMax],
+                       double tau, const double *v, const double *z, double *w, double *red) {
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+#pragma unroll
+  for (int u = 0; u < kHU; ++u) {
+    const int i = lane + 64 * u;
+    if (i < n) pp[wave][i] = pacc[u];
+  }
+  __syncthreads();
+  double p = 0.0;
+  if (t < n) {
+#pragma unroll
+    for (int q = 0; q < kHW; ++q) p += pp[q][t];
+  }
+  double zv = (t >= jbeg && t < n) ? z[t] * v[t] : 0.0, unused = 0.0;
+  hg_sum2(zv, unused, red);
+  if (t < n) w[t] = tau * (p - tau * zv * v[t]);
+  __syncthreads();
+}
+
+}  // namespace
+
+__global__ void __launch_bounds__(kHG)
+hess_glb_kernel(const double *__restrict__ xbuf, int nmin, int step, int o0,
+                double *__restrict__ hbuf, double *__restrict__ vref, double *__restrict__ taus) {
+  __shared__ double sv[2][kNMax];        // reflector of this step, of the next
+  __shared__ double sz[2][kNMax];        // z of this step, of the next (by column)
+  __shared__ double sw[kNMax];           // w of this step (by row)
+  __shared__ double pp[kHW][kNMax];      // per-wave partial sums of the next p
+  __shared__ double red[2 * kHW];
+  __shared__ double stau[2];
+  const OrderGeo geo = order_geo(o0 + blockIdx.x, nmin, step);
+  const int n = geo.n;
+  const double *X = xbuf + geo.sq;
+  double *H = hbuf + geo.sq;
+  double *vr = vref + geo.sq;
+  double *tv = taus + geo.vec;
+  const int t = threadIdx.x;
+  // H(i, j) = X(i, j) by columns
+  for (int idx = t; idx < n * n; idx += kHG) {
+    const int j = idx / n, i = idx - j * n;
+    H[idx] = X[(int64_t)i * n + j];
+  }
+  __syncthreads();
+  if (n < 3) return;
+  // step 0: its reflector from column 0, then its z and p by a read pass
+  {
+    double x = t < n ? H[t] : 0.0;
+    x = hg_reflector(x, 0, n, sv[0], &stau[0], vr, tv, red);
+    if (t < n) H[t] = x;
+    __syncthreads();
+    double pacc[kHU];
+    hg_pass<false, true>(H, n, 1, 0.0, sv[0], sz[0], sw, sv[0], sz[0], pacc);
+    hg_finish(n, 1, pacc, pp, stau[0], sv[0], sz[0], sw, red);
+  }
+  int cur = 0;
+  for (int k = 0; k <= n - 3; ++k) {
+    const int nx = cur ^ 1;
+    const double tau = stau[cur];
+    const bool more = k + 1 <= n - 3;
+    // column k + 1 under step k, then the reflector of step k + 1 from it
+    const int64_t ck = (int64_t)(k + 1) * n;
+    double x = 0.0;
+    if (t < n) {
+      x = H[ck + t];
+      x -= tau * sv[cur][t] * sz[cur][k + 1] + sw[t] * sv[cur][k + 1];
+    }
+    if (more) x = hg_reflector(x, k + 1, n, sv[nx], &stau[nx], vr, tv, red);
+    if (t < n) H[ck + t] = x;
+    __syncthreads();
+    // columns k + 2 .. n - 1 under step k, accumulating step k + 1's z and p
+    double pacc[kHU];
+    if (more) {
+      if (tau != 0.0)
+        hg_pass<true, true>(H, n, k + 2, tau, sv[cur], sz[cur], sw, sv[nx], sz[nx], pacc);
+      else
+        hg_pass<false, true>(H, n, k + 2, tau, sv[cur], sz[cur], sw, sv[nx], sz[nx], pacc);
+      hg_finish(n, k + 2, pacc, pp, stau[nx], sv[nx], sz[nx], sw, red);
+    } else if (tau != 0.0) {
+      hg_pass<true, false>(H, n, k + 2, tau, sv[cur], sz[cur], sw, sv[nx], sz[nx], pacc);
+      __syncthreads();
+    }
+    cur = nx;
+  }
+}
+
 // ------------------------------------------------------------------ francis
 namespace {
 
@@ -243,7 +466,6 @@ constexpr double kShiftTol = 1e-10;
 // hold a window's reflectors during a multishift sweep.
 constexpr int kExtra = 2 * kRing + 2 * kSM + 2 * kNB + kSM * kSM;
 constexpr int kLdsMaxN = 200;
-constexpr int kRowIt = (kNR + 63) / 64;  // panel elements per lane in a bulge step
 constexpr int kLdsDoubles = 20299 + kExtra;   // 20299 = packed size at n = 200
 
 // Upper Hessenberg H in packed rows (row 0: columns 0..n-1; row i >= 1:
@@ -462,7 +684,9 @@ SSI_DEV double lane_value(const double (&v)[N], int e) {
 }
 
 // One double-shift sweep over the active window [l, hi] by one wave (the
-// shift pair (s, t) in shp[0..1]); wave-level ordering only.
+// shift pair (s, t) in shp[0..1]); wave-level ordering only.  RI: row or
+// column elements per lane (64 RI >= n).
+template <int RI>
 SSI_DEV void chase1(double *A, const HIdx &ix, int l, int hi, const double *shp, int lane) {
   constexpr int nb = 1, wave = 0;
   const int psz = ix.b2;
@@ -505,10 +729,10 @@ SSI_DEV void chase1(double *A, const HIdx &ix, int l, int hi, const double *shp,
       const int r2 = three ? ix.base(k + 2) : r1;
       const int s2 = psz + ((k + 2) & (kRing - 1));
       const int len = hi - k + 1;
-      int i0[kRowIt], i1[kRowIt], i2[kRowIt];
-      double a0[kRowIt], a1[kRowIt], a2[kRowIt];
+      int i0[RI], i1[RI], i2[RI];
+      double a0[RI], a1[RI], a2[RI];
 #pragma unroll
-      for (int u = 0; u < kRowIt; ++u) {
+      for (int u = 0; u < RI; ++u) {
         if (64 * u >= len) break;
         const int j = k + min(lane + 64 * u, len - 1);
         i0[u] = r0 + j;
@@ -519,7 +743,7 @@ SSI_DEV void chase1(double *A, const HIdx &ix, int l, int hi, const double *shp,
         a2[u] = three ? A[i2[u]] : 0.0;
       }
 #pragma unroll
-      for (int u = 0; u < kRowIt; ++u) {
+      for (int u = 0; u < RI; ++u) {
         if (64 * u >= len) break;
         if (lane + 64 * u >= len) continue;
         const double d = beta * (a0[u] + v1 * a1[u] + v2 * a2[u]);
@@ -540,10 +764,10 @@ SSI_DEV void chase1(double *A, const HIdx &ix, int l, int hi, const double *shp,
       const int len = min(k + 3, hi) - l + 1;
       const int sk2 = psz + ((k + 2) & (kRing - 1));
       const int sk3 = psz + ((k + 3) & (kRing - 1));
-      int i0[kRowIt], i1[kRowIt], i2[kRowIt];
-      double a0[kRowIt], a1[kRowIt], a2[kRowIt], nv[kRowIt];
+      int i0[RI], i1[RI], i2[RI];
+      double a0[RI], a1[RI], a2[RI], nv[RI];
 #pragma unroll
-      for (int u = 0; u < kRowIt; ++u) {
+      for (int u = 0; u < RI; ++u) {
         nv[u] = 0.0;
         if (64 * u >= len) break;
         const int i = l + min(lane + 64 * u, len - 1);
@@ -556,7 +780,7 @@ SSI_DEV void chase1(double *A, const HIdx &ix, int l, int hi, const double *shp,
         a2[u] = three ? A[i2[u]] : 0.0;
       }
 #pragma unroll
-      for (int u = 0; u < kRowIt; ++u) {
+      for (int u = 0; u < RI; ++u) {
         if (64 * u >= len) break;
         if (lane + 64 * u >= len) continue;
         const double d = beta * (a0[u] + v1 * a1[u] + v2 * a2[u]);
@@ -740,7 +964,7 @@ SSI_DEV void chase_win(double *A, const HIdx &ix, int l, int hi, const double *s
     const int n_right = max(0, hi - w1 + 1);
     const int n_top = r_beg - l;
     const int r_lo = r_beg - w0, r_hi = c_end - w0;   // local entries inside [l, hi]
-    if (t < n_right + n_top) {
+    for (int sg = t; sg < n_right + n_top; sg += kFT) {
       // Entry r of this thread's segment sits at s0 + r d - (right ? r (r - 1) / 2 : 0):
       // a column of rows w0 + r (packed row starts base(w0 + r) = base(w0) + r (n - w0)
       // - r (r - 1) / 2) or a row over columns w0 + r.  Every entry is loaded, at an
@@ -748,8 +972,8 @@ SSI_DEV void chase_win(double *A, const HIdx &ix, int l, int hi, const double *s
       // back.  Entries outside [r_lo, r_hi) are never stored: the reflectors that touch
       // them have beta = 0 (bulges not yet in, or past, the active window) or v2 = 0
       // (the last, two-row step), so they only multiply finite values by zero.
-      const bool right = t < n_right;
-      const int s0 = right ? ix.base(w0) + w1 + t : ix.base(l + t - n_right) + w0;
+      const bool right = sg < n_right;
+      const int s0 = right ? ix.base(w0) + w1 + sg : ix.base(l + sg - n_right) + w0;
       const int d = right ? ix.n - w0 : 1;
       const int rmask = right ? -1 : 0;
       const unsigned valid = ((1u << r_hi) - 1u) & ~((1u << r_lo) - 1u);
@@ -814,20 +1038,20 @@ SSI_DEV void francis_order(int o, double *A, const double *__restrict__ hbuf, in
   double *sev = shp + 2 * kNB;               // [2][kSM]
   double *sblk = sev + 2 * kSM;              // [kSM][kSM]
   double *refl = sev;                        // during a sweep: [kAdv][kNB][3] reflectors
-  // Thread t copies column t (n <= kNR < kFT) of 16 rows per round: the 16
+  // Thread t copies columns t, t + kFT, ... 16 rows per round: the 16
   // loads are unconditional (clamped) and in flight together; row by row,
   // each load would wait for the previous row's store.
-  static_assert(kNR <= kFT, "one column per thread");
-  const int tc = min(t, n - 1);
-  for (int i0 = 0; i0 < n; i0 += 16) {
-    double v[16];
+  for (int c = t; c < n; c += kFT) {
+    for (int i0 = 0; i0 < n; i0 += 16) {
+      double v[16];
 #pragma unroll
-    for (int r = 0; r < 16; ++r) v[r] = Hin[(int64_t)tc * n + min(i0 + r, n - 1)];
+      for (int r = 0; r < 16; ++r) v[r] = Hin[(int64_t)c * n + min(i0 + r, n - 1)];
 #pragma unroll
-    for (int r = 0; r < 16; ++r) {
-      const int i = i0 + r;
-      const int j0 = i == 0 ? 0 : i - 1;
-      if (i < n && t < n && t >= j0) A[ix.row_start(i) + t - j0] = v[r];
+      for (int r = 0; r < 16; ++r) {
+        const int i = i0 + r;
+        const int j0 = i == 0 ? 0 : i - 1;
+        if (i < n && c >= j0) A[ix.row_start(i) + c - j0] = v[r];
+      }
     }
   }
   for (int i = t; i < 2 * kRing; i += kFT) A[psz + i] = 0.0;
@@ -984,7 +1208,7 @@ SSI_DEV void francis_order(int o, double *A, const double *__restrict__ hbuf, in
     if (nb > 1) {
       chase_win(A, ix, l, hi, shp, refl, wave, lane);
     } else {
-      if (wave == 0) chase1(A, ix, l, hi, shp, lane);
+      if (wave == 0) chase1<LDS ? 4 : kNMax / 64>(A, ix, l, hi, shp, lane);
       __syncthreads();
     }
   }
@@ -1044,8 +1268,11 @@ SSI_DEV double lane_pick(const double (&v)[N], int e) {
   return readlane_d(s, e & 63);
 }
 
-constexpr int kU = (kNR + 63) / 64;      // rows of a column per lane in a pole item
-constexpr int kRingV = 4;                // columns of H in flight in the shifted solve
+// A pole item of order n <= 64 KU keeps rows lane + 64 u (u < KU) of a
+// column in registers: KU = 4 up to order 256, 7 up to kNMax.
+// columns of H in flight in the shifted solve (fewer for the wider columns,
+// whose registers the persistent launch cannot spare)
+template <int KU> constexpr int ring_v() { return KU <= 4 ? 4 : 2; }
 
 // x = (H - mu I)^{-1} b for an upper Hessenberg H (column-major, column c at
 // Hc + c n) by one wave, b given in registers (row i = lane + 64 u in br/bi[u]).
@@ -1057,24 +1284,26 @@ constexpr int kRingV = 4;                // columns of H in flight in the shifte
 // same loop and R is never stored; then x = E_{n-2} ... E_0 y, applying E_0
 // first (the multipliers and swaps wait in LDS).  A pivot below tiny is
 // replaced by tiny, as in LAPACK's Hessenberg inverse iteration.  Columns of H
-// arrive through a register ring kRingV steps ahead.  Writes x to x_re/x_im.
+// arrive through a register ring ring_v<KU>() steps ahead.  Writes x to x_re/x_im.
+template <int KU>
 SSI_DEV void shifted_solve(const double *__restrict__ Hc, int n, cplx mu, double tiny,
-                           double (&br)[kU], double (&bi)[kU], double *x_re, double *x_im,
+                           double (&br)[KU], double (&bi)[KU], double *x_re, double *x_im,
                            double *mult_re, double *mult_im, int *swp) {
   const int lane = threadIdx.x & 63;
   auto col = [&](int c, int u) {            // clamped load of H(lane + 64 u, c)
     const int i = lane + 64 * u;
     return Hc[(int64_t)max(min(c, n - 1), 0) * n + min(i, n - 1)];
   };
-  double hq[kRingV][kU];
+  constexpr int kRingV = ring_v<KU>();
+  double hq[kRingV][KU];
 #pragma unroll
   for (int d = 0; d < kRingV; ++d)
 #pragma unroll
-    for (int u = 0; u < kU; ++u) hq[d][u] = col(n - 2 - d, u);
+    for (int u = 0; u < KU; ++u) hq[d][u] = col(n - 2 - d, u);
   // working column: column n - 1 of H - mu I
-  double wr_[kU], wi_[kU];
+  double wr_[KU], wi_[KU];
 #pragma unroll
-  for (int u = 0; u < kU; ++u) {
+  for (int u = 0; u < KU; ++u) {
     const int i = lane + 64 * u;
     const double h = col(n - 1, u);
     wr_[u] = i < n ? h - (i == n - 1 ? mu.re : 0.0) : 0.0;
@@ -1086,9 +1315,9 @@ SSI_DEV void shifted_solve(const double *__restrict__ Hc, int n, cplx mu, double
       const int j = j0 - d;                  // slot d holds column j
       if (j < 0) break;
       // column j of H - mu I: rows 0..j+1
-      double ar[kU], ai[kU];
+      double ar[KU], ai[KU];
 #pragma unroll
-      for (int u = 0; u < kU; ++u) {
+      for (int u = 0; u < KU; ++u) {
         const int i = lane + 64 * u;
         ar[u] = i <= j + 1 ? hq[d][u] - (i == j ? mu.re : 0.0) : 0.0;
         ai[u] = i == j ? -mu.im : 0.0;
@@ -1106,7 +1335,7 @@ SSI_DEV void shifted_solve(const double *__restrict__ Hc, int n, cplx mu, double
       const cplx cj = {lane_pick(br, j + 1), lane_pick(bi, j + 1)};
       const cplx y = cdiv(cj, piv);
 #pragma unroll
-      for (int u = 0; u < kU; ++u) {
+      for (int u = 0; u < KU; ++u) {
         const int i = lane + 64 * u;
         const cplx pv = csel(swap, cplx{ar[u], ai[u]}, cplx{wr_[u], wi_[u]});
         const cplx ov = csel(swap, cplx{wr_[u], wi_[u]}, cplx{ar[u], ai[u]});
@@ -1157,7 +1386,7 @@ SSI_DEV void shifted_solve(const double *__restrict__ Hc, int n, cplx mu, double
 }
 
 // Vector, mode shape and continuous pole of pole j of order o, by one wave.
-// x_re, x_im, mult_re, mult_im (kNR doubles each) and swp (kNR ints) are this
+// x_re, x_im, mult_re, mult_im (64 KU doubles each) and swp (64 KU ints) are this
 // wave's LDS.  H is stored by columns; ut is U[0:l, :k] transposed (row c
 // holds column c of U, l entries).  Writes the unsorted pole f, xi, mu, phi
 // (l complex) at slot pole(o) + j of the temporary arrays.
@@ -1165,9 +1394,10 @@ SSI_DEV void shifted_solve(const double *__restrict__ Hc, int n, cplx mu, double
 // Every global load in the loops below is issued by all lanes: out-of-range
 // loads read a clamped address (a finite entry of the same matrix), the ring
 // registers hold the raw loaded values, and the masking select happens when a
-// value is used, kRingV (or kRingQ) steps later.  A load under a branch, or a
+// value is used, ring_v<KU>() (or kRingQ) steps later.  A load under a branch, or a
 // select right after it, makes the compiler wait for the load at once, which
 // defeats the rings that keep columns and reflectors several steps ahead.
+template <int KU>
 SSI_DEV void vec_pole(int o, int j, const double *__restrict__ hbuf,
                       const double *__restrict__ vref, const double *__restrict__ taus,
                       const double *__restrict__ ut, const double *__restrict__ evbuf,
@@ -1192,20 +1422,20 @@ SSI_DEV void vec_pole(int o, int j, const double *__restrict__ hbuf,
   // enough, max|x| tiny >= 0.1 / sqrt(n) (the acceptance test of LAPACK's
   // Hessenberg inverse iteration); otherwise a second solve with the
   // normalized x as right-hand side.
-  double br[kU], bi[kU];
+  double br[KU], bi[KU];
 #pragma unroll
-  for (int u = 0; u < kU; ++u) {
+  for (int u = 0; u < KU; ++u) {
     br[u] = (lane + 64 * u) < n ? 1.0 : 0.0;
     bi[u] = 0.0;
   }
   for (int pass = 0; pass < 2; ++pass) {
-    shifted_solve(Hc, n, mu, tiny, br, bi, x_re, x_im, mult_re, mult_im, swp);
+    shifted_solve<KU>(Hc, n, mu, tiny, br, bi, x_re, x_im, mult_re, mult_im, swp);
     double mx = 0.0;
     for (int c = lane; c < n; c += 64) mx = fmax(mx, cabs1(cplx{x_re[c], x_im[c]}));
     mx = wmax(mx);
     const double inv = mx > 0.0 ? 1.0 / mx : 1.0;
 #pragma unroll
-    for (int u = 0; u < kU; ++u) {
+    for (int u = 0; u < KU; ++u) {
       const int c = lane + 64 * u;
       const int cc = min(c, n - 1);
       br[u] = c < n ? x_re[cc] * inv : 0.0;
@@ -1213,7 +1443,7 @@ SSI_DEV void vec_pole(int o, int j, const double *__restrict__ hbuf,
     }
     wave_sync();                            // every lane has read x
 #pragma unroll
-    for (int u = 0; u < kU; ++u) {
+    for (int u = 0; u < KU; ++u) {
       const int c = lane + 64 * u;
       if (c < n) { x_re[c] = br[u]; x_im[c] = bi[u]; }
     }
@@ -1225,21 +1455,21 @@ SSI_DEV void vec_pole(int o, int j, const double *__restrict__ hbuf,
   // row k): applied from H_{n-3} down to H_0, psi in registers (lane c % 64,
   // slot c / 64), the reflector rows arriving through a register ring.
   {
-    const double *vr = vref + (size_t)o * kNR * kNR;
-    const double *tv = taus + (size_t)o * kNR;
-    constexpr int kRingQ = 8;
-    double pr_[kU], pi_[kU], vq[kRingQ][kU];
+    const double *vr = vref + geo.sq;
+    const double *tv = taus + geo.vec;
+    constexpr int kRingQ = KU <= 4 ? 8 : 4;
+    double pr_[KU], pi_[KU], vq[kRingQ][KU];
 #pragma unroll
-    for (int u2 = 0; u2 < kU; ++u2) {
+    for (int u2 = 0; u2 < KU; ++u2) {
       pr_[u2] = br[u2];
       pi_[u2] = bi[u2];
     }
 #pragma unroll
     for (int d = 0; d < kRingQ; ++d)
 #pragma unroll
-      for (int u2 = 0; u2 < kU; ++u2) {
+      for (int u2 = 0; u2 < KU; ++u2) {
         const int c = lane + 64 * u2, k = n - 3 - d;
-        vq[d][u2] = vr[(size_t)max(k, 0) * kNR + min(c, n - 1)];
+        vq[d][u2] = vr[(size_t)max(k, 0) * n + min(c, n - 1)];
       }
     for (int k0 = n - 3; k0 >= 0; k0 -= kRingQ) {
 #pragma unroll
@@ -1247,10 +1477,10 @@ SSI_DEV void vec_pole(int o, int j, const double *__restrict__ hbuf,
         const int k = k0 - d;
         if (k < 0) break;
         const double tau = tv[k];
-        double vk[kU];                      // row k of the reflectors, rows < n
+        double vk[KU];                      // row k of the reflectors, rows < n
         double sre = 0.0, sim = 0.0;
 #pragma unroll
-        for (int u2 = 0; u2 < kU; ++u2) {
+        for (int u2 = 0; u2 < KU; ++u2) {
           vk[u2] = (lane + 64 * u2 < n) ? vq[d][u2] : 0.0;
           sre += vk[u2] * pr_[u2];
           sim += vk[u2] * pi_[u2];
@@ -1258,17 +1488,17 @@ SSI_DEV void vec_pole(int o, int j, const double *__restrict__ hbuf,
         sre = tau * wsum(sre);
         sim = tau * wsum(sim);
 #pragma unroll
-        for (int u2 = 0; u2 < kU; ++u2) {
+        for (int u2 = 0; u2 < KU; ++u2) {
           pr_[u2] -= sre * vk[u2];
           pi_[u2] -= sim * vk[u2];
           // refill with reflector k - kRingQ (raw: masked when it is used)
           const int c = lane + 64 * u2, kn = k - kRingQ;
-          vq[d][u2] = vr[(size_t)max(kn, 0) * kNR + min(c, n - 1)];
+          vq[d][u2] = vr[(size_t)max(kn, 0) * n + min(c, n - 1)];
         }
       }
     }
 #pragma unroll
-    for (int u2 = 0; u2 < kU; ++u2) {
+    for (int u2 = 0; u2 < KU; ++u2) {
       const int c = lane + 64 * u2;
       if (c < n) { x_re[c] = pr_[u2]; x_im[c] = pi_[u2]; }
     }
@@ -1367,13 +1597,14 @@ SSI_DEV void vec_pole(int o, int j, const double *__restrict__ hbuf,
 // order serializes thousands of waves on one counter.
 namespace {
 constexpr int kEigGrid = 256;                       // workgroups (one per CU)
-constexpr int kVecLds = 5 * kNR;                    // per-wave LDS of a pole item (doubles)
+// per-wave LDS of a pole item (doubles): x_re, x_im, mult_re, mult_im, swp
+template <int KU> constexpr int vec_lds() { return 5 * 64 * KU; }
 // queue: [0] next order item, [1] next pole item, [2] order items still
 // running, [3] deferred poles, [4] next tail item, [5..] the deferred poles
 // (at most one per wave of the persistent launch)
 constexpr int kQDeferred = 5;
 constexpr int kMaxDeferred = kEigGrid * (kFT / 64);
-static_assert(kFT / 64 * kVecLds <= kLdsDoubles, "pole items fit the workgroup's LDS");
+static_assert(kFT / 64 * vec_lds<kNMax / 64>() <= kLdsDoubles, "pole items fit the workgroup's LDS");
 
 // Pole items, smallest orders first; within an order, lag by lag and pole by pole.
 SSI_DEV int pole_items_total(int n_orders, int n_lags, int nmin, int step) {
@@ -1423,7 +1654,8 @@ SSI_DEV int claim_pole(int *queue, const int *done, int total, int n_orders, int
 }
 
 // Pole items for one wave until claim_pole gives none.  x: this wave's LDS
-// (kVecLds doubles).
+// (vec_lds<KU>() doubles).
+template <int KU>
 SSI_DEV void pole_phase(bool tail, double *x, const double *__restrict__ hbuf,
                         const double *__restrict__ vref, const double *__restrict__ taus,
                         const double *__restrict__ u, int nmin, int step, int n_orders,
@@ -1435,8 +1667,9 @@ SSI_DEV void pole_phase(bool tail, double *x, const double *__restrict__ hbuf,
                         const int *__restrict__ done, int *__restrict__ status, int n_lags,
                         const ssi::ModalStrides &ls) {
   const int lane = threadIdx.x & 63;
-  double *x_re = x, *x_im = x_re + kNR, *mult_re = x_im + kNR, *mult_im = mult_re + kNR;
-  int *swp = reinterpret_cast<int *>(mult_im + kNR);
+  double *x_re = x, *x_im = x_re + 64 * KU, *mult_re = x_im + 64 * KU,
+         *mult_im = mult_re + 64 * KU;
+  int *swp = reinterpret_cast<int *>(mult_im + 64 * KU);
   const int total = pole_items_total(n_orders, n_lags, nmin, step);
   for (;;) {
     int it = -1;
@@ -1451,7 +1684,7 @@ SSI_DEV void pole_phase(bool tail, double *x, const double *__restrict__ hbuf,
     if (!__hip_atomic_load(dn, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT)) continue;
     if (pi.j >= npole[pi.g * n_orders + pi.o]) continue;
     const int g = pi.g;
-    vec_pole(pi.o, pi.j, hbuf + g * ls.sq, vref + g * ls.vref, taus + g * ls.taus, u + g * ls.u,
+    vec_pole<KU>(pi.o, pi.j, hbuf + g * ls.sq, vref + g * ls.vref, taus + g * ls.taus, u + g * ls.u,
              evbuf + g * 2 * ls.vec, pidx + g * ls.vec, nmin, step, l, fs, x_re, x_im,
              mult_re, mult_im, swp, tf + g * ls.poles, txi + g * ls.poles,
              tmu + g * 2 * ls.poles, tphi + g * 2 * ls.poles * l);
@@ -1468,6 +1701,7 @@ eig_init_kernel(int *__restrict__ queue, int *__restrict__ done, int n_items) {
   }
 }
 
+template <int KU>
 __global__ void __launch_bounds__(kFT)
 eig_persistent_kernel(const double *__restrict__ hbuf, const double *__restrict__ vref,
                       const double *__restrict__ taus, const double *__restrict__ u,
@@ -1527,7 +1761,7 @@ eig_persistent_kernel(const double *__restrict__ hbuf, const double *__restrict_
   }
   // ---- phase 2: poles of finished orders, smallest orders first
   __syncthreads();                                  // LDS of the QR iteration is free
-  pole_phase(false, lds_h + wave * kVecLds, hbuf, vref, taus, u,
+  pole_phase<KU>(false, lds_h + wave * vec_lds<KU>(), hbuf, vref, taus, u,
              nmin, step, n_orders, l, fs, evbuf, npole, pidx, tf, txi, tmu,
              tphi, queue, done, status, n_lags, ls);
 }
@@ -1535,6 +1769,7 @@ eig_persistent_kernel(const double *__restrict__ hbuf, const double *__restrict_
 // The poles phase 2 left: every order has finished when this launch starts.
 // kTailWaves waves per workgroup, one per SIMD.
 constexpr int kTailWaves = 4;
+template <int KU>
 __global__ void __launch_bounds__(64 * kTailWaves)
 pole_tail_kernel(const double *__restrict__ hbuf, const double *__restrict__ vref,
                  const double *__restrict__ taus, const double *__restrict__ u,
@@ -1547,7 +1782,7 @@ pole_tail_kernel(const double *__restrict__ hbuf, const double *__restrict__ vre
                  ssi::ModalStrides ls) {
   extern __shared__ double lds_v[];
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  pole_phase(true, lds_v + wave * kVecLds, hbuf, vref, taus, u,
+  pole_phase<KU>(true, lds_v + wave * vec_lds<KU>(), hbuf, vref, taus, u,
              nmin, step, n_orders, l, fs, evbuf, npole, pidx, tf, txi, tmu,
              tphi, queue, done, status, n_lags, ls);
 }
@@ -1665,7 +1900,7 @@ sort_kernel(int nmin, int step, int l, const int *__restrict__ npole,
 // ------------------------------------------------------------------ launch
 namespace ssi {
 
-int modal_max_order() { return kNR; }
+int modal_max_order() { return kNMax; }
 
 
 ModalSizes modal_sizes(int nmin, int nmax, int step, int l) {
@@ -1677,9 +1912,10 @@ ModalSizes modal_sizes(int nmin, int nmax, int step, int l) {
     s.vec += n;
     s.poles += n / 2;
   }
-  s.vref = (int64_t)s.n_orders * kNR * kNR;
-  s.taus = (int64_t)s.n_orders * kNR;
-  s.francis_glb = (int64_t)HIdx::packed_size(kNR) + kExtra;
+  s.vref = s.sq;                 // reflector v_k of order n: row k of an n x n block
+  s.taus = s.vec;
+  // packed matrix of each order above the LDS limit in global scratch
+  s.francis_glb = nmax > kLdsMaxN ? (int64_t)HIdx::packed_size(nmax) + kExtra : 0;
   s.queue_ints = kQDeferred + kMaxDeferred;
   return s;
 }
@@ -1703,12 +1939,18 @@ hipError_t launch_modal_prep(const ModalArgs &a, int lag, hipStream_t st) {
   hipLaunchKernelGGL(form_x_kernel, dim3(ceil_div(nmax * nmax, 256)), dim3(256), 0, st, a.rinv,
                      a.w, a.ldw, a.nmin, a.step, no, a.xbuf);
   double *hb = a.hbuf + lag * ls.sq, *vr = a.vref + lag * ls.vref, *ta = a.taus + lag * ls.taus;
-  if (nmax <= 16 * 13)
-    hipLaunchKernelGGL(hess_kernel<13>, dim3(no), dim3(kT), 0, st, a.xbuf, a.nmin, a.step, hb,
-                       vr, ta);
-  else
-    hipLaunchKernelGGL(hess_kernel<kTP>, dim3(no), dim3(kT), 0, st, a.xbuf, a.nmin, a.step, hb,
-                       vr, ta);
+  // orders up to kNR in the register tile, the rest (orders ascend) in global memory
+  const int no_reg = a.nmin > kNR ? 0 : std::min(no, (kNR - a.nmin) / a.step + 1);
+  const int nmax_reg = a.nmin + (no_reg - 1) * a.step;
+  if (no_reg > 0 && nmax_reg <= 16 * 13)
+    hipLaunchKernelGGL(hess_kernel<13>, dim3(no_reg), dim3(kT), 0, st, a.xbuf, a.nmin, a.step,
+                       hb, vr, ta);
+  else if (no_reg > 0)
+    hipLaunchKernelGGL(hess_kernel<kTP>, dim3(no_reg), dim3(kT), 0, st, a.xbuf, a.nmin, a.step,
+                       hb, vr, ta);
+  if (no > no_reg)
+    hipLaunchKernelGGL(hess_glb_kernel, dim3(no - no_reg), dim3(kHG), 0, st, a.xbuf, a.nmin,
+                       a.step, no_reg, hb, vr, ta);
   return hipGetLastError();
 }
 
@@ -1720,32 +1962,46 @@ hipError_t launch_mode_head(const double *u, int k, int l, double *dst, hipStrea
   return hipGetLastError();
 }
 
-hipError_t launch_modal_eig(const ModalArgs &a, hipStream_t st) {
+namespace {
+// Launches of the eigen-analysis for orders up to 64 KU.
+template <int KU>
+hipError_t launch_eig_ku(const ModalArgs &a, const ModalStrides &ls, int grid, hipStream_t st) {
   const ModalSizes &s = a.sizes;
   const int no = s.n_orders;
-  const int items = a.n_lags * no;
-  const ModalStrides ls = modal_strides(s, a.l, a.ldu);
-  // QR iterations and pole vectors of every (lag, order) in one persistent launch
-  hipLaunchKernelGGL(eig_init_kernel, dim3(1), dim3(kFT), 0, st, a.queue, a.done, items);
-  hipError_t e = hipFuncSetAttribute((const void *)eig_persistent_kernel,
+  hipError_t e = hipFuncSetAttribute((const void *)eig_persistent_kernel<KU>,
                                      hipFuncAttributeMaxDynamicSharedMemorySize,
                                      (int)(sizeof(double) * kLdsDoubles));
   if (e != hipSuccess) return e;
-  // one workgroup per CU by default; a smaller grid (at least one workgroup
-  // per item) leaves CUs to work on other streams
-  const int grid = a.eig_grid > 0
-                       ? std::min(std::max(a.eig_grid, std::min(items, kEigGrid)), kEigGrid)
-                       : kEigGrid;
-  hipLaunchKernelGGL(eig_persistent_kernel, dim3(grid), dim3(kFT),
+  hipLaunchKernelGGL(eig_persistent_kernel<KU>, dim3(grid), dim3(kFT),
                      sizeof(double) * kLdsDoubles, st, a.hbuf, a.vref, a.taus, a.u,
                      a.nmin, a.step, no, a.l,
                      a.fs, a.gscr, s.francis_glb, a.evbuf, a.npole, a.pidx, a.flags_tmp,
                      a.tf, a.txi, a.tmu, a.tphi, a.queue, a.done, a.status,
                      a.sweeps_per_row, a.n_lags, ls);
-  hipLaunchKernelGGL(pole_tail_kernel, dim3(2 * kEigGrid), dim3(64 * kTailWaves),
-                     sizeof(double) * kVecLds * kTailWaves, st, a.hbuf, a.vref, a.taus, a.u,
-                     a.nmin, a.step, no, a.l, a.fs, a.evbuf, a.npole, a.pidx,
+  hipLaunchKernelGGL(pole_tail_kernel<KU>, dim3(2 * kEigGrid), dim3(64 * kTailWaves),
+                     sizeof(double) * vec_lds<KU>() * kTailWaves, st, a.hbuf, a.vref, a.taus,
+                     a.u, a.nmin, a.step, no, a.l, a.fs, a.evbuf, a.npole, a.pidx,
                      a.tf, a.txi, a.tmu, a.tphi, a.queue, a.done, a.status, a.n_lags, ls);
+  return hipGetLastError();
+}
+}  // namespace
+
+hipError_t launch_modal_eig(const ModalArgs &a, hipStream_t st) {
+  const ModalSizes &s = a.sizes;
+  const int no = s.n_orders;
+  const int items = a.n_lags * no;
+  const int nmax = a.nmin + (no - 1) * a.step;
+  const ModalStrides ls = modal_strides(s, a.l, a.ldu);
+  // QR iterations and pole vectors of every (lag, order) in one persistent launch
+  hipLaunchKernelGGL(eig_init_kernel, dim3(1), dim3(kFT), 0, st, a.queue, a.done, items);
+  // one workgroup per CU by default; a smaller grid (at least one workgroup
+  // per item) leaves CUs to work on other streams
+  const int grid = a.eig_grid > 0
+                       ? std::min(std::max(a.eig_grid, std::min(items, kEigGrid)), kEigGrid)
+                       : kEigGrid;
+  const hipError_t e = nmax <= 256 ? launch_eig_ku<4>(a, ls, grid, st)
+                                   : launch_eig_ku<kNMax / 64>(a, ls, grid, st);
+  if (e != hipSuccess) return e;
   hipLaunchKernelGGL(sort_kernel, dim3(no, a.n_lags), dim3(256), 0, st, a.nmin, a.step, a.l,
                      a.npole, a.flags_tmp, a.tf, a.txi, a.tmu, a.tphi, a.count, a.flags, a.f,
                      a.xi, a.mu, a.phi, no, (int64_t)s.poles);

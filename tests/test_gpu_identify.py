@@ -238,6 +238,60 @@ def test_modal_orders_above_200_same_inputs(ctx):
     assert np.array(stats["mac"]).min() >= 1 - 1e-6
 
 
+def test_modal_orders_to_400_same_inputs(ctx):
+    """Orders 196..400 step 12, fed the checker's U and sigma of a 60-channel
+    record's 480 x 480 Toeplitz matrix (k = 416): the QR iteration in LDS
+    (196) and in global memory, the Hessenberg reduction in registers (up to
+    224) and in global memory (above), and pole vectors with seven rows per
+    lane.  Physical poles: f rel <= 1e-10, xi abs <= 1e-9, MAC >= 1 - 1e-6.
+    Every checker eigenvalue has a GPU eigenvalue within what a backward
+    stable eigen-solver may move it: 1e3 eps ||X_n||_F kappa_i, kappa_i the
+    eigenvalue's condition number (1 / |y_i^H x_i| for unit left and right
+    eigenvectors) of X_n = S^1/2 A_n S^-1/2, the matrix the GPU reduces."""
+    import scipy.linalg
+    wl = synth.Workload(name="wide400", l=60, n=20000, fs=100.0, n_modes=8,
+                        f_range=(1.0, 20.0), zeta_range=(0.01, 0.03), noise=0.05,
+                        lags=(8,), svd="randomized", rank=416, oversample=16,
+                        power_iters=1, order_min=196, order_max=400, order_step=12,
+                        struct_seed=15, noise_seed=16, sketch_seed=17)
+    sysm, y = synth.make_record(wl)
+    jb = wl.lags[0]
+    t = oracle.toeplitz(oracle.correlations(y, 2 * jb - 1), jb)
+    u, s = oracle.rsvd(t, wl.rank, wl.oversample, wl.power_iters,
+                       oracle.sketch(wl.sketch_seed, t.shape[0], wl.rank + wl.oversample, 0))
+    p = _params(wl)
+    out = ctx.alloc_output(p, wl.l, wl.n)
+    ctx.modal(_dev(u), _dev(s), wl.l, p, 0, out)
+    ctx.synchronize()
+    ref = oracle.modal(u, s, wl.l, wl.orders, wl.fs)
+    stats = {"f": [], "xi": [], "mac": []}
+    eps = np.finfo(np.float64).eps
+    worst = 0.0
+    for oi, n in enumerate(wl.orders):
+        gpu = out.poles(0, oi)
+        assert gpu["flag"] == 0, f"order {n}"
+        _compare_order(gpu, ref[oi], _physical(ref[oi], sysm), stats)
+        assert abs(len(gpu["f"]) - len(ref[oi])) <= 1, f"order {n}"
+        a, _ = oracle.shift_ls(u, s, wl.l, n)
+        sq = np.sqrt(s[:n])
+        x = sq[:, None] * a / sq[None, :]
+        ev, vl, vr = scipy.linalg.eig(x, left=True, right=True)
+        kappa = 1.0 / np.maximum(np.abs(np.sum(vl.conj() * vr, axis=0)), 1e-300)
+        bound = 1e3 * eps * np.linalg.norm(x) * kappa
+        mu_gpu = gpu["mu"]
+        for m in ref[oi].mu:
+            i = int(np.argmin(np.abs(ev - m)))
+            d = np.min(np.abs(mu_gpu - m))
+            worst = max(worst, d / bound[i])
+            assert d <= bound[i], (f"order {n}: |d mu| {d:.2e} > bound {bound[i]:.2e} "
+                                   f"(kappa {kappa[i]:.1e})")
+    print(f"orders 196..400: {len(stats['f'])} physical poles, max f rel "
+          f"{max(stats['f']):.2e}, max |d mu| / bound {worst:.2e}")
+    assert np.array(stats["f"]).max() <= 1e-10
+    assert np.array(stats["xi"]).max() <= 1e-9
+    assert np.array(stats["mac"]).min() >= 1 - 1e-6
+
+
 def test_identify_deterministic(ctx):
     wl = synth.WORKLOADS["small-full-svd"]
     _, y = synth.make_record(wl, n=8000)
