@@ -869,7 +869,8 @@ ssi_status run_rsvd(ssi_ctx *c, RsvdBufs &b, const float *t, int64_t m, int64_t 
   StageTimer tm_small(c, SSI_STAGE_SMALL_SVD);
   e = prod_f64(c, true, pt, ell, pt, ell, ell, ell, mi, b.part, b.gm, ell);
   if (e != hipSuccess) return hip_fail(e, "P P^T");
-  e = ssi::launch_sym_eig(b.gm, ell, ell, b.evals, b.evecs, ell, b.dws, c->status, c->stream);
+  e = ssi::launch_sym_eig(b.gm, ell, ell, k, b.evals, b.evecs, ell, b.dws, c->status,
+                          c->stream);
   if (e != hipSuccess) return hip_fail(e, "small eigen-decomposition");
   e = ssi::launch_sqrt_clamp(b.evals, k, sigma, c->stream);
   if (e != hipSuccess) return hip_fail(e, "sigma");
@@ -902,7 +903,7 @@ ssi_status run_svd_full(ssi_ctx *c, FullBufs &b, const float *t, int m, int64_t 
   if (e != hipSuccess) return hip_fail(e, "transpose");
   e = prod_f64(c, true, b.tt, m, b.tt, m, m, m, m, b.part, b.gm, m);
   if (e != hipSuccess) return hip_fail(e, "T T^T");
-  e = ssi::launch_sym_eig(b.gm, m, m, b.evals, b.evecs, m, b.dws, c->status, c->stream);
+  e = ssi::launch_sym_eig(b.gm, m, m, k, b.evals, b.evecs, m, b.dws, c->status, c->stream);
   if (e != hipSuccess) return hip_fail(e, "eigen-decomposition");
   e = ssi::launch_sqrt_clamp(b.evals, k, sigma, c->stream);
   if (e != hipSuccess) return hip_fail(e, "sigma");

@@ -8,6 +8,8 @@
 // only broadcasts one row or column per step.  Two storage policies share the
 // code:
 //   registers   (n <= 224): 14 x 7 entries per thread, the fast path;
+//   mid         (n <= 448): the matrix in global memory (L2-resident), coalesced
+//               column passes and MFMA block updates (kernels below);
 //   global      (n <= 1024): 64 x 32 entries per thread in thread-private,
 //               lane-interleaved (coalesced) scratch, for the full SVD of
 //               larger Toeplitz matrices.
@@ -499,7 +501,7 @@ SSI_DEV void inv_iter_solve(int n, const double *u0, const double *u1, const dou
 }
 
 // Eigenpairs of the tridiagonal (d, e), one wave per eigenvalue; wave t of the
-// grid takes the t-th largest.  The eigenvalue comes from multisection of the
+// grid takes the t-th largest, and its eigenvector when t < nvec.  The eigenvalue comes from multisection of the
 // Sturm count: each round the 64 lanes count at 64 interior points of the
 // bracket [lo, hi] (invariant: count(lo) <= target < count(hi)) and the
 // bracket shrinks to the pair of neighbouring points that straddles the
@@ -508,7 +510,7 @@ SSI_DEV void inv_iter_solve(int n, const double *u0, const double *u1, const dou
 // pivoting, held in the wave's slice of LDS and run by lane 0.
 template <int KN, int EPW>
 __global__ void __launch_bounds__(64 * EPW)
-sym_tridiag_eig_kernel(int n, double *__restrict__ evals, double *__restrict__ evecs,
+sym_tridiag_eig_kernel(int n, int nvec, double *__restrict__ evals, double *__restrict__ evecs,
                        int64_t ldv, const double *__restrict__ ws) {
   __shared__ double dd[KN];
   __shared__ double ee[KN];
@@ -555,15 +557,15 @@ sym_tridiag_eig_kernel(int n, double *__restrict__ evals, double *__restrict__ e
       lo = fmax(lo, nlo);
     }
     const double lam = 0.5 * (lo + hi);
-    if (lane == 0) {
-      evals[t] = lam;
+    if (lane == 0) evals[t] = lam;
+    if (lane == 0 && t < nvec) {
       inv_iter_lu(dd, ee, n, lam, tiny, u0, u1, u2, ml);
       for (int j = 0; j < n; ++j) xv[j] = hash_unit(t, j);
       for (int it = 0; it < 3; ++it) inv_iter_solve(n, u0, u1, u2, ml, xv);
     }
   }
   __syncthreads();
-  if (t < n) {
+  if (t < nvec) {
     double s = 0.0;
     for (int j = lane; j < n; j += 64) s += xv[j] * xv[j];
     const double inv = 1.0 / sqrt(wave_sum(s));
@@ -587,12 +589,14 @@ sym_tridiag_eig_kernel(int n, double *__restrict__ evals, double *__restrict__ e
 // descending (column t holds the t-th largest).  One wave takes whole
 // clusters, W waves share them round robin; the LU and the solves run on
 // lane 0 as in sym_tridiag_eig_kernel, the projections on the whole wave.
+// Only the vectors t < nvec are wanted: a cluster's members are recomputed up
+// to nvec - 1 (each is orthogonalized against the earlier ones only).
 constexpr double kClusterTol = 1e-12;
 
 template <int KN, int W>
 __global__ void __launch_bounds__(64 * W)
-sym_cluster_kernel(int n, const double *__restrict__ evals, double *__restrict__ evecs,
-                   int64_t ldv, const double *__restrict__ ws) {
+sym_cluster_kernel(int n, int nvec, const double *__restrict__ evals,
+                   double *__restrict__ evecs, int64_t ldv, const double *__restrict__ ws) {
   __shared__ double dd[KN];
   __shared__ double ee[KN];
   __shared__ double lu[W][5][KN];
@@ -611,11 +615,11 @@ sym_cluster_kernel(int n, const double *__restrict__ evals, double *__restrict__
   const double tiny = 2.220446049250313e-16 * fmax(gnorm, 1e-300);
   double *u0 = lu[wv][0], *u1 = lu[wv][1], *u2 = lu[wv][2], *ml = lu[wv][3], *xv = lu[wv][4];
   int ordinal = 0;
-  for (int s0 = 0; s0 < n;) {
+  for (int s0 = 0; s0 < nvec;) {
     int e0 = s0 + 1;
     while (e0 < n && evals[e0 - 1] - evals[e0] <= tol) ++e0;
     if (e0 - s0 >= 2 && (ordinal++ % W) == wv) {
-      for (int j = s0; j < e0; ++j) {
+      for (int j = s0; j < min(e0, nvec); ++j) {
         if (lane == 0) {
           inv_iter_lu(dd, ee, n, evals[j], tiny, u0, u1, u2, ml);
           for (int i = 0; i < n; ++i) xv[i] = hash_unit(j, i);
@@ -879,7 +883,7 @@ chol_blk_kernel(const double *__restrict__ G, int64_t ldg, int n, double shift_r
   if (t == 0 && bad) atomicOr(status, 1);
 }
 
-// X = L^{-1} for the lower-triangular L in Lws (ld n), n <= 16 kIbMax, by 16 x
+// X = L^{-1} for the lower-triangular L in Lws (ld n), n <= 16 IB, by 16 x
 // 16 blocks: workgroup b takes block column b.  The inverses D_i of the
 // diagonal blocks i >= b come first (one 16-lane group per block, lane c a
 // forward substitution for column c, blocks staged in LDS); then block row by
@@ -888,16 +892,18 @@ chol_blk_kernel(const double *__restrict__ G, int64_t ldg, int n, double shift_r
 // and the partial products added through LDS.  The chain is nb - b block
 // steps instead of n - 16 b row steps.  Rows and columns past n are those of
 // the identity.  Writes Rinv = X^T (upper, zero below the diagonal) for rows
-// 16 b .. 16 b + 15.  LDS (dynamic): D [kIbMax][256], X [kIbMax][256] (the
-// diagonal blocks of L before D exists), partials [4][256].
+// 16 b .. 16 b + 15.  LDS (dynamic): D [IB][256], X [IB][256] (the
+// diagonal blocks of L before D exists), partials [4][256].  IB = 14 (n <= 224)
+// or 28 (n <= 448, 120 KiB of LDS).
 constexpr int kIbMax = 14;
+template <int IB>
 __global__ void __launch_bounds__(256)
 tri_inv_blk_kernel(int n, const double *__restrict__ Lws, double *__restrict__ Rinv,
                    int64_t ldr) {
   extern __shared__ double tib[];
-  double *dinv = tib;                                  // [kIbMax][16][16]
-  double *xc = tib + kIbMax * 256;                     // [kIbMax][16][16]
-  double *sp = tib + 2 * kIbMax * 256;                 // [4][16][16]
+  double *dinv = tib;                                  // [IB][16][16]
+  double *xc = tib + IB * 256;                     // [IB][16][16]
+  double *sp = tib + 2 * IB * 256;                 // [4][16][16]
   const int nb = (n + 15) >> 4, b = blockIdx.x;
   const int t = threadIdx.x, lane = t & 63;
   const int wave = __builtin_amdgcn_readfirstlane(t >> 6);
@@ -908,20 +914,20 @@ tri_inv_blk_kernel(int n, const double *__restrict__ Lws, double *__restrict__ R
   };
   // stage the diagonal blocks i = b.. of L (entry t of each block)
   {
-    double v[kIbMax];
+    double v[IB];
 #pragma unroll
-    for (int g = 0; g < kIbMax; ++g) {
+    for (int g = 0; g < IB; ++g) {
       const int i = b + g;
       v[g] = lg(16 * i + (t >> 4), 16 * i + (t & 15));
     }
 #pragma unroll
-    for (int g = 0; g < kIbMax; ++g)
+    for (int g = 0; g < IB; ++g)
       if (b + g < nb) xc[g * 256 + t] = v[g];
   }
   __syncthreads();
   {
-    const int g = t >> 4, c = t & 15;                  // block b + g, column c
-    if (b + g < nb) {
+    const int c = t & 15;                              // block b + g, column c
+    for (int g = t >> 4; g < IB && b + g < nb; g += 16) {
       const double *l = xc + g * 256;
       double x[16];
 #pragma unroll
@@ -948,15 +954,15 @@ tri_inv_blk_kernel(int n, const double *__restrict__ Lws, double *__restrict__ R
   __syncthreads();
   for (int i = b + 1; i < nb; ++i) {
     const int ks = 4 * (i - b);                        // MFMA steps of 4 terms
-    double av[kIbMax];
+    double av[IB];
 #pragma unroll
-    for (int u = 0; u < kIbMax; ++u) {
+    for (int u = 0; u < IB; ++u) {
       const int kk = 4 * (wave + 4 * u) + (lane >> 4);
       av[u] = lg(16 * i + (lane & 15), 16 * b + kk);
     }
     f64x4 acc = f64x4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-    for (int u = 0; u < kIbMax; ++u) {
+    for (int u = 0; u < IB; ++u) {
       const int st = wave + 4 * u;
       if (st < ks) {
         const int kk = 4 * st + (lane >> 4);
@@ -982,6 +988,420 @@ tri_inv_blk_kernel(int n, const double *__restrict__ Lws, double *__restrict__ R
   }
 }
 
+// ---------------------------------------------------------------- mid sizes
+namespace {
+// Orders the LDS accesses of one wave (its lanes run in lockstep; the fence
+// keeps the compiler from moving accesses across).
+SSI_DEV void mid_wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+}
+}  // namespace
+
+// 224 < n <= kMidN: the matrix stays in global memory (n^2 doubles, at most
+// 1.6 MiB, so it lives in L2) and the kernels are organized so that every
+// access is coalesced and many are in flight, instead of one thread walking
+// its slots of the global tile.
+constexpr int kMidN = 448;
+constexpr int kMidU = kMidN / 64;        // rows of a column per lane
+constexpr int kMidKN = 1024;             // row stride of the reflectors (the global layout)
+
+// Lower Cholesky factor L (into Lws, ld n, lower triangle) of G + shift_rel
+// tr(G) I for n <= kMidN, by 16 x 16 blocks, right-looking, the trailing
+// matrix kept in Lws itself.  For block column k: wave 0 factors the diagonal
+// block (adding the shift to its diagonal: the shift commutes with the
+// trailing updates), each thread solves one panel row against it (the panel
+// is kept in LDS), then the kMidCT / 64 waves subtract P_i P_j^T from the
+// trailing blocks (i, j), k < j <= i, four blocks per wave at a time (their
+// loads in flight together) on v_mfma_f64_16x16x4f64.  Rows and columns past n: loads
+// are clamped, such entries are never stored, and their panel rows are zero.
+// status bit 0 is set on a non-positive pivot.
+constexpr int kMidCT = 512;              // threads (one panel row each: n - 16 < kMidCT)
+__global__ void __launch_bounds__(kMidCT)
+chol_mid_kernel(const double *__restrict__ G, int64_t ldg, int n, double shift_rel,
+                double *__restrict__ Lws, int *__restrict__ status) {
+  __shared__ double panel[kMidN][17];
+  __shared__ double lkk[16][17];
+  __shared__ double rdiag[16];
+  __shared__ double red[kMidCT / 64];
+  __shared__ int bad;
+  const int t = threadIdx.x, lane = t & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(t >> 6);
+  const int nb = (n + 15) >> 4;
+  // the lower triangle of G into Lws, and the trace
+  double tr_part = 0.0;
+  for (int idx = t; idx < n * n; idx += kMidCT) {
+    const int i = idx / n, j = idx - i * n;
+    if (j <= i) {
+      const double v = G[(int64_t)i * ldg + j];
+      Lws[idx] = v;
+      tr_part += (i == j) ? v : 0.0;
+    }
+  }
+  if (t == 0) bad = 0;
+  tr_part = wave_sum(tr_part);
+  if (lane == 0) red[wave] = tr_part;
+  __syncthreads();
+  double trace = 0.0;
+#pragma unroll
+  for (int w = 0; w < kMidCT / 64; ++w) trace += red[w];
+  const double shift = shift_rel * trace;
+  for (int k = 0; k < nb; ++k) {
+    const int r0 = 16 * k;
+    if (wave == 0) {
+      // diagonal block, factored in LDS by wave 0 (zero above the diagonal,
+      // the identity past n)
+      for (int e = lane; e < 256; e += 64) {
+        const int r = e >> 4, c = e & 15;
+        const int gi = r0 + r, gj = r0 + c;
+        const double v = Lws[(int64_t)min(gi, n - 1) * n + min(gj, n - 1)];
+        const bool in = gi < n && gj < n && c <= r;
+        lkk[r][c] = in ? v + (r == c ? shift : 0.0) : (r == c ? 1.0 : 0.0);
+      }
+      mid_wave_sync();
+      for (int c = 0; c < 16; ++c) {
+        double piv = lkk[c][c];
+        if (!(piv > 0.0)) {
+          if (lane == 0) bad = 1;
+          piv = 1e-300;
+        }
+        const double d = sqrt(piv), rd = 1.0 / d;
+        mid_wave_sync();                      // every lane has read the pivot
+        if (lane == c) lkk[c][c] = d;
+        if (lane > c && lane < 16) lkk[lane][c] *= rd;
+        if (lane == 0) rdiag[c] = rd;
+        mid_wave_sync();
+        for (int e = lane; e < 256; e += 64) {
+          const int r = e >> 4, j = e & 15;
+          if (j > c && r >= j) lkk[r][j] -= lkk[r][c] * lkk[j][c];
+        }
+        mid_wave_sync();
+      }
+      for (int e = lane; e < 256; e += 64) {
+        const int r = e >> 4, c = e & 15;
+        if (r0 + r < n && r0 + c < n)
+          Lws[(int64_t)(r0 + r) * n + r0 + c] = (c <= r) ? lkk[r][c] : 0.0;
+      }
+    }
+    __syncthreads();
+    // panel rows below the diagonal block: x L_kk^T = w
+    const int prow = r0 + 16 + t;
+    if (prow < 16 * nb) {
+      double x[16];
+#pragma unroll
+      for (int c = 0; c < 16; ++c)
+        x[c] = Lws[(int64_t)min(prow, n - 1) * n + min(r0 + c, n - 1)];
+#pragma unroll
+      for (int c = 0; c < 16; ++c) {
+        double v = (prow < n && r0 + c < n) ? x[c] : 0.0;
+#pragma unroll
+        for (int m = 0; m < c; ++m) v -= x[m] * lkk[c][m];
+        x[c] = v * rdiag[c];
+        // one row of L_kk at a time in registers: the compiler would
+        // otherwise load all 136 entries up front
+        __asm__ volatile("" ::: "memory");
+      }
+#pragma unroll
+      for (int c = 0; c < 16; ++c) panel[t][c] = x[c];
+      if (prow < n)
+#pragma unroll
+        for (int c = 0; c < 16; ++c)
+          if (r0 + c < n) Lws[(int64_t)prow * n + r0 + c] = x[c];
+    }
+    __syncthreads();
+    // trailing blocks (i, j) = (k + 1 + ii, k + 1 + jj), jj <= ii < m, as
+    // T = m (m + 1) / 2 ids, four per wave per round
+    const int m = nb - 1 - k, T = m * (m + 1) / 2;
+    for (int id0 = 4 * wave; id0 < T; id0 += 4 * (kMidCT / 64)) {
+      f64x4 acc[4];
+      int bi[4], bj[4];
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        const int id = min(id0 + b, T - 1);
+        // row of id in the triangle: the float root is off by at most one
+        int ii = (int)((sqrtf(8.0f * id + 1.0f) - 1.0f) * 0.5f);
+        ii -= (ii * (ii + 1) / 2 > id) ? 1 : 0;
+        ii += ((ii + 1) * (ii + 2) / 2 <= id) ? 1 : 0;
+        bi[b] = ii;
+        bj[b] = id - ii * (ii + 1) / 2;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int gr = r0 + 16 + 16 * bi[b] + (lane >> 4) + 4 * q;
+          const int gc = r0 + 16 + 16 * bj[b] + (lane & 15);
+          acc[b][q] = Lws[(int64_t)min(gr, n - 1) * n + min(gc, n - 1)];
+        }
+      }
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+#pragma unroll
+        for (int st = 0; st < 4; ++st) {
+          const int kk = 4 * st + (lane >> 4);
+          acc[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(-panel[16 * bi[b] + (lane & 15)][kk],
+                                                        panel[16 * bj[b] + (lane & 15)][kk],
+                                                        acc[b], 0, 0, 0);
+        }
+      }
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        if (id0 + b >= T) continue;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int gr = r0 + 16 + 16 * bi[b] + (lane >> 4) + 4 * q;
+          const int gc = r0 + 16 + 16 * bj[b] + (lane & 15);
+          if (gr < n && gc < n && gc <= gr) Lws[(int64_t)gr * n + gc] = acc[b][q];
+        }
+      }
+    }
+    __syncthreads();
+  }
+  if (t == 0 && bad) atomicOr(status, 1);
+}
+
+namespace {
+constexpr int kMidT = 512, kMidW = kMidT / 64;
+
+// Sum over the workgroup (kMidT threads); red holds kMidW doubles.
+SSI_DEV double mid_sum(double a, double *red) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  a = wave_sum(a);
+  __syncthreads();                        // red is free
+  if (lane == 0) red[wave] = a;
+  __syncthreads();
+  double s = 0.0;
+#pragma unroll
+  for (int w = 0; w < kMidW; ++w) s += red[w];
+  return s;
+}
+}  // namespace
+
+// Householder tridiagonalization of the symmetric G for n <= kMidN, in place
+// in global memory: G is copied by columns into A (n x n) and reduced there;
+// the reflectors, tau, d and e go to ws in the layout of the global path (row
+// stride kMidKN).  With v, tau the reflector of step k and p = tau B v (B the
+// trailing block as step k - 1 left it), the update is B - v w^T - w v^T,
+// w = p - (tau / 2) (v . p) v.  The next step needs column k + 1 as this step
+// leaves it, so each step first updates that column alone (its diagonal entry
+// is then d[k + 1]) and forms the next reflector from it; the pass that then
+// updates the trailing columns k + 2 .. n - 1 (rows from k + 2) accumulates
+// the next p, column by column (B is symmetric).  One read and one write of
+// the trailing block per step.
+__global__ void __launch_bounds__(kMidT)
+sym_tridiag_mid_kernel(const double *__restrict__ G, int64_t ldg, int n,
+                       double *__restrict__ ws, double *__restrict__ A) {
+  __shared__ double sv[2][kMidN];        // reflector of this step, of the next
+  __shared__ double sp[2][kMidN];        // p (by column), then w, of this step / the next
+  __shared__ double red[kMidW];
+  __shared__ double stau[2];
+  double *vref = ws;
+  double *tauv = ws + (size_t)kMidKN * kMidKN;
+  double *dd = tauv + kMidKN;
+  double *ee = dd + kMidKN;
+  const int t = threadIdx.x, lane = t & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(t >> 6);
+  // A(i, j) = G(j, i): column j of A is row j of G (coalesced; G is symmetric)
+  for (int idx = t; idx < n * n; idx += kMidT) {
+    const int j = idx / n, i = idx - j * n;
+    A[idx] = G[(int64_t)j * ldg + i];
+  }
+  __syncthreads();
+  if (n < 3) {
+    if (t < n) dd[t] = A[(int64_t)t * n + t];
+    if (t == 0 && n == 2) ee[0] = A[1];
+    return;
+  }
+  // Reflector of step c from column c (x: entry (t, c), rows t > c used):
+  // writes v to sv[slot] and row c of vref, tau, d[c] (= dc) and e[c].
+  auto reflector = [&](double x, int c, int slot, double dc) {
+    double s2 = (t > c + 1 && t < n) ? x * x : 0.0;
+    s2 = mid_sum(s2, red);
+    double x1 = (t == c + 1) ? x : 0.0;
+    x1 = mid_sum(x1, red);
+    double tau = 0.0, alpha = x1, v1 = 0.0;
+    if (s2 > 0.0) {
+      alpha = -copysign(sqrt(x1 * x1 + s2), x1);
+      v1 = x1 - alpha;
+      tau = 2.0 / (s2 + v1 * v1);
+    }
+    if (t < n) {
+      const double v = (t == c + 1) ? v1 : (t > c + 1 ? x : 0.0);
+      sv[slot][t] = v;
+      vref[(size_t)c * kMidKN + t] = v;
+    }
+    if (t == 0) {
+      stau[slot] = tau;
+      tauv[c] = tau;
+      dd[c] = dc;
+      ee[c] = alpha;
+    }
+  };
+  // One pass over columns jbeg..n-1, rows from jbeg: with UPD, x -= v_i w_j +
+  // w_i v_j and store; then pn[j] = sum_i vn_i x(i, j) (the next p before tau).
+  auto pass = [&](int jbeg, bool upd, const double *v, const double *w, const double *vn,
+                  double *pn) {
+    double vi[kMidU], wi[kMidU], vni[kMidU];
+#pragma unroll
+    for (int u = 0; u < kMidU; ++u) {
+      const int i = lane + 64 * u, ic = min(i, n - 1);
+      const bool act = i >= jbeg && i < n;
+      vi[u] = act ? v[ic] : 0.0;
+      wi[u] = act ? w[ic] : 0.0;
+      vni[u] = act ? vn[ic] : 0.0;
+    }
+    for (int j0 = jbeg + wave; j0 < n; j0 += 2 * kMidW) {
+      const int j1 = j0 + kMidW;
+      const bool has1 = j1 < n;
+      double *c0 = A + (int64_t)j0 * n, *c1 = A + (int64_t)min(j1, n - 1) * n;
+      double x0[kMidU], x1[kMidU];
+#pragma unroll
+      for (int u = 0; u < kMidU; ++u) {
+        const int ic = min(lane + 64 * u, n - 1);
+        x0[u] = c0[ic];
+        x1[u] = c1[ic];
+      }
+      if (upd) {
+        const double vj0 = v[j0], wj0 = w[j0];
+        const double vj1 = has1 ? v[j1] : 0.0, wj1 = has1 ? w[j1] : 0.0;
+#pragma unroll
+        for (int u = 0; u < kMidU; ++u) {
+          x0[u] -= vi[u] * wj0 + wi[u] * vj0;
+          x1[u] -= vi[u] * wj1 + wi[u] * vj1;
+        }
+#pragma unroll
+        for (int u = 0; u < kMidU; ++u) {
+          const int i = lane + 64 * u;
+          if (i >= jbeg && i < n) {
+            c0[i] = x0[u];
+            if (has1) c1[i] = x1[u];
+          }
+        }
+      }
+      double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+      for (int u = 0; u < kMidU; ++u) {
+        s0 += vni[u] * x0[u];
+        s1 += vni[u] * x1[u];
+      }
+      s0 = wave_sum(s0);
+      s1 = wave_sum(s1);
+      if (lane == 0) {
+        pn[j0] = s0;
+        if (has1) pn[j1] = s1;
+      }
+    }
+  };
+  // p <- tau p, then w = p - (tau / 2) (v . p) v over rows from jbeg
+  auto finish = [&](int jbeg, int slot) {
+    __syncthreads();
+    const double tau = stau[slot];
+    const bool act = t >= jbeg && t < n;
+    const double p = act ? tau * sp[slot][t] : 0.0;
+    const double vt = act ? sv[slot][t] : 0.0;
+    const double K = mid_sum(vt * p, red);
+    if (act) sp[slot][t] = p - 0.5 * tau * K * vt;
+    __syncthreads();
+  };
+  {
+    const double x = t < n ? A[t] : 0.0;
+    const double d0 = A[0];
+    reflector(x, 0, 0, d0);
+    __syncthreads();
+    pass(1, false, sv[0], sp[0], sv[0], sp[0]);
+    finish(1, 0);
+  }
+  int cur = 0;
+  for (int k = 0; k <= n - 3; ++k) {
+    const int nx = cur ^ 1;
+    // column k + 1 (rows from k + 1) under step k
+    const int64_t ck = (int64_t)(k + 1) * n;
+    double x = 0.0;
+    const bool act = t >= k + 1 && t < n;
+    if (act) {
+      x = A[ck + t];
+      x -= sv[cur][t] * sp[cur][k + 1] + sp[cur][t] * sv[cur][k + 1];
+    }
+    const double dk1 = (t == k + 1) ? x : 0.0;
+    if (k + 1 <= n - 3) {
+      const double d1 = mid_sum(dk1, red);
+      reflector(x, k + 1, nx, d1);
+      __syncthreads();
+      if (stau[cur] != 0.0)
+        pass(k + 2, true, sv[cur], sp[cur], sv[nx], sp[nx]);
+      else
+        pass(k + 2, false, sv[cur], sp[cur], sv[nx], sp[nx]);
+      finish(k + 2, nx);
+    } else {
+      // k + 1 = n - 2: the last column pair; d[n-2], e[n-2] from column n - 2
+      // as updated, d[n-1] from the last column's update
+      if (t == n - 2) dd[n - 2] = x;
+      if (t == n - 1) {
+        ee[n - 2] = x;
+        const double y = A[(int64_t)(n - 1) * n + n - 1];
+        const double vl = sv[cur][n - 1], wl = sp[cur][n - 1];
+        dd[n - 1] = y - 2.0 * vl * wl;
+      }
+    }
+    cur = nx;
+  }
+}
+
+// V <- H_0 H_1 ... H_{n-3} V for n <= kMidN (reflectors in the layout of
+// sym_tridiag_mid_kernel): one wave per column of V, which it keeps in
+// registers (row lane + 64 u in slot u); the reflector rows arrive through a
+// register ring kMidRing steps ahead (raw values, masked when used).  Only
+// the columns j < nvec are transformed.
+constexpr int kMidRing = 4;
+__global__ void __launch_bounds__(256)
+sym_backtransform_mid_kernel(int n, int nvec, double *__restrict__ evecs, int64_t ldv,
+                             const double *__restrict__ ws) {
+  const int lane = threadIdx.x & 63;
+  const int j = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (j >= nvec) return;
+  const double *vref = ws;
+  const double *tauv = ws + (size_t)kMidKN * kMidKN;
+  double x[kMidU];
+#pragma unroll
+  for (int u = 0; u < kMidU; ++u) {
+    const int i = lane + 64 * u;
+    const double v = evecs[(int64_t)min(i, n - 1) * ldv + j];
+    x[u] = i < n ? v : 0.0;
+  }
+  double vq[kMidRing][kMidU], tq[kMidRing];
+#pragma unroll
+  for (int d = 0; d < kMidRing; ++d) {
+    const int k = max(n - 3 - d, 0);
+#pragma unroll
+    for (int u = 0; u < kMidU; ++u) vq[d][u] = vref[(size_t)k * kMidKN + min(lane + 64 * u, n - 1)];
+    tq[d] = tauv[k];
+  }
+  for (int k0 = n - 3; k0 >= 0; k0 -= kMidRing) {
+#pragma unroll
+    for (int d = 0; d < kMidRing; ++d) {
+      const int k = k0 - d;
+      if (k < 0) break;
+      const double tau = tq[d];
+      double vk[kMidU], s = 0.0;
+#pragma unroll
+      for (int u = 0; u < kMidU; ++u) {
+        vk[u] = (lane + 64 * u < n) ? vq[d][u] : 0.0;
+        s += vk[u] * x[u];
+      }
+      s = tau * wave_sum(s);
+#pragma unroll
+      for (int u = 0; u < kMidU; ++u) x[u] -= s * vk[u];
+      const int kn = max(k - kMidRing, 0);
+#pragma unroll
+      for (int u = 0; u < kMidU; ++u)
+        vq[d][u] = vref[(size_t)kn * kMidKN + min(lane + 64 * u, n - 1)];
+      tq[d] = tauv[kn];
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < kMidU; ++u) {
+    const int i = lane + 64 * u;
+    if (i < n) evecs[(int64_t)i * ldv + j] = x[u];
+  }
+}
+
 namespace ssi {
 
 namespace {
@@ -992,6 +1412,8 @@ constexpr int kRegN = Geo<kRegP, kRegQ>::kN;
 constexpr int kGlbN = Geo<kGlbP, kGlbQ>::kN;
 
 constexpr int kRegEpw = 4, kGlbEpw = 1;   // eigenvalues (waves) per workgroup
+
+static_assert(kMidKN == kGlbN, "mid-size kernels write the global path's layout");
 
 double *glb_tile(double *ws) { return ws + (size_t)kGlbN * kGlbN + 3 * kGlbN; }
 }  // namespace
@@ -1010,11 +1432,21 @@ hipError_t launch_chol_inv(const double *G, int64_t ldg, int n, double shift_rel
     hipLaunchKernelGGL(chol_blk_kernel, dim3(1), dim3(64 * kCbWaves), 0, st, G, ldg, n,
                        shift_rel, Lws, status);
     const size_t lds = sizeof(double) * (size_t)(2 * kIbMax + 4) * 256;
-    hipError_t e = hipFuncSetAttribute((const void *)tri_inv_blk_kernel,
+    hipError_t e = hipFuncSetAttribute((const void *)tri_inv_blk_kernel<kIbMax>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(tri_inv_blk_kernel, dim3(ceil_div(n, 16)), dim3(256), lds, st, n, Lws,
-                       Rinv, ldr);
+    hipLaunchKernelGGL(tri_inv_blk_kernel<kIbMax>, dim3(ceil_div(n, 16)), dim3(256), lds, st, n,
+                       Lws, Rinv, ldr);
+  } else if (n <= kMidN) {
+    hipLaunchKernelGGL(chol_mid_kernel, dim3(1), dim3(kMidCT), 0, st, G, ldg, n, shift_rel, Lws,
+                       status);
+    constexpr int kIb = kMidN / 16;
+    const size_t lds = sizeof(double) * (size_t)(2 * kIb + 4) * 256;
+    hipError_t e = hipFuncSetAttribute((const void *)tri_inv_blk_kernel<kIb>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(tri_inv_blk_kernel<kIb>, dim3(ceil_div(n, 16)), dim3(256), lds, st, n,
+                       Lws, Rinv, ldr);
   } else {
     double *tile = glb_tile(ws);
     hipLaunchKernelGGL((chol_kernel<kGlbP, kGlbQ, true>), dim3(1), dim3(kThreads), 0, st, G,
@@ -1025,25 +1457,34 @@ hipError_t launch_chol_inv(const double *G, int64_t ldg, int n, double shift_rel
   return hipGetLastError();
 }
 
-hipError_t launch_sym_eig(const double *G, int64_t ldg, int n, double *evals, double *evecs,
-                          int64_t ldv, double *ws, int *status, hipStream_t st) {
+hipError_t launch_sym_eig(const double *G, int64_t ldg, int n, int nvec, double *evals,
+                          double *evecs, int64_t ldv, double *ws, int *status, hipStream_t st) {
   (void)status;
   if (n <= kRegN) {
     hipLaunchKernelGGL((sym_tridiag_kernel<kRegP, kRegQ, false>), dim3(1), dim3(kThreads), 0,
                        st, G, ldg, n, ws, ws);
     hipLaunchKernelGGL((sym_tridiag_eig_kernel<kRegN, kRegEpw>), dim3(ceil_div(n, kRegEpw)),
-                       dim3(64 * kRegEpw), 0, st, n, evals, evecs, ldv, ws);
-    hipLaunchKernelGGL((sym_cluster_kernel<kRegN, 4>), dim3(1), dim3(256), 0, st, n, evals,
+                       dim3(64 * kRegEpw), 0, st, n, nvec, evals, evecs, ldv, ws);
+    hipLaunchKernelGGL((sym_cluster_kernel<kRegN, 4>), dim3(1), dim3(256), 0, st, n, nvec, evals,
                        evecs, ldv, ws);
     hipLaunchKernelGGL((sym_backtransform_kernel<kRegP, kRegQ, false>), dim3(1),
                        dim3(kThreads), 0, st, n, evecs, ldv, ws, ws);
+  } else if (n <= kMidN) {
+    hipLaunchKernelGGL(sym_tridiag_mid_kernel, dim3(1), dim3(kMidT), 0, st, G, ldg, n, ws,
+                       glb_tile(ws));
+    hipLaunchKernelGGL((sym_tridiag_eig_kernel<kGlbN, kGlbEpw>), dim3(ceil_div(n, kGlbEpw)),
+                       dim3(64 * kGlbEpw), 0, st, n, nvec, evals, evecs, ldv, ws);
+    hipLaunchKernelGGL((sym_cluster_kernel<kGlbN, 2>), dim3(1), dim3(128), 0, st, n, nvec, evals,
+                       evecs, ldv, ws);
+    hipLaunchKernelGGL(sym_backtransform_mid_kernel, dim3(ceil_div(nvec, 4)), dim3(256), 0, st,
+                       n, nvec, evecs, ldv, ws);
   } else {
     double *tile = glb_tile(ws);
     hipLaunchKernelGGL((sym_tridiag_kernel<kGlbP, kGlbQ, true>), dim3(1), dim3(kThreads), 0,
                        st, G, ldg, n, ws, tile);
     hipLaunchKernelGGL((sym_tridiag_eig_kernel<kGlbN, kGlbEpw>), dim3(ceil_div(n, kGlbEpw)),
-                       dim3(64 * kGlbEpw), 0, st, n, evals, evecs, ldv, ws);
-    hipLaunchKernelGGL((sym_cluster_kernel<kGlbN, 2>), dim3(1), dim3(128), 0, st, n, evals,
+                       dim3(64 * kGlbEpw), 0, st, n, nvec, evals, evecs, ldv, ws);
+    hipLaunchKernelGGL((sym_cluster_kernel<kGlbN, 2>), dim3(1), dim3(128), 0, st, n, nvec, evals,
                        evecs, ldv, ws);
     hipLaunchKernelGGL((sym_backtransform_kernel<kGlbP, kGlbQ, true>), dim3(1),
                        dim3(kThreads), 0, st, n, evecs, ldv, ws, tile);

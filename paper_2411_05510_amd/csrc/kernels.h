@@ -136,8 +136,10 @@ int dense_max_n();
 size_t dense_ws_doubles(int n);
 hipError_t launch_chol_inv(const double *G, int64_t ldg, int n, double shift_rel, double *Rinv,
                            int64_t ldr, double *Lws, double *ws, int *status, hipStream_t st);
-hipError_t launch_sym_eig(const double *G, int64_t ldg, int n, double *evals, double *evecs,
-                          int64_t ldv, double *ws, int *status, hipStream_t st);
+// all n eigenvalues (descending) and the eigenvectors of the leading nvec
+// (columns 0..nvec-1 of evecs; the others are left unspecified)
+hipError_t launch_sym_eig(const double *G, int64_t ldg, int n, int nvec, double *evals,
+                          double *evecs, int64_t ldv, double *ws, int *status, hipStream_t st);
 
 // ---- modal stage (modal.hip)
 int modal_max_order();
