@@ -16,7 +16,9 @@ import numpy as np
 from typing import List, Optional, Sequence
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libssicov.so")
+# SSI_LIBRARY selects another build of the same library (the host-sanitized
+# one of build.build_sanitized, for the sanitizer test)
+LIB_PATH = os.environ.get("SSI_LIBRARY") or os.path.join(HERE, "libssicov.so")
 
 SSI_OK, SSI_EINVAL, SSI_ENOMEM, SSI_EDEVICE, SSI_ENOCONV, SSI_EINTERNAL, SSI_EBUSY = range(7)
 SVD_FULL, SVD_RANDOMIZED = 0, 1
