@@ -169,9 +169,11 @@ gemm_tf64w_mfma(const float *__restrict__ A, int64_t lda, const double *__restri
   for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
     for (int ct = 0; ct < 7; ++ct) acc[rt][ct] = f64x4{0.0, 0.0, 0.0, 0.0};
-  bool colok[7];
-#pragma unroll
-  for (int ct = 0; ct < 7; ++ct) colok[ct] = n0 + wc * 112 + ct * 16 < N;
+  // A wave whose 112 columns all lie past N skips its products; otherwise
+  // all seven column tiles run (columns past N hold zeros in the B tile and
+  // are not stored): a branch per tile would split the MFMA sequence into
+  // blocks, with a wait for every LDS read at each block boundary.
+  const bool wave_cols = n0 + wc * 112 < N;
 
   f32x4v ra[RT];
   f64x2v rb[7];
@@ -190,6 +192,7 @@ gemm_tf64w_mfma(const float *__restrict__ A, int64_t lda, const double *__restri
     const double *Bs = Bsb + buf * wBS;
 #pragma unroll
     for (int hk = 0; hk < wKT / 16; ++hk) {
+      if (!wave_cols) break;
       const int ko = 16 * hk + 4 * (lane >> 4);
       f32x4v a4[RT];
 #pragma unroll
@@ -203,7 +206,6 @@ gemm_tf64w_mfma(const float *__restrict__ A, int64_t lda, const double *__restri
         for (int ct = 0; ct < 7; ++ct) bv[ct] = Bs[(ko + s) * wLB + wc * 112 + ct * 16 + (lane & 15)];
 #pragma unroll
         for (int ct = 0; ct < 7; ++ct) {
-          if (!colok[ct]) continue;
 #pragma unroll
           for (int rt = 0; rt < RT; ++rt)
             acc[rt][ct] = __builtin_amdgcn_mfma_f64_16x16x4f64((double)a4[rt][s], bv[ct],
