@@ -559,6 +559,7 @@ def bench_large_rsvd(args) -> dict:
     jb = wl.lags[0]
     k, p, q = wl.rank, wl.oversample, wl.power_iters
     ctx = ssicov.Context(0)
+    ctx.set_autotune(True)              # the warm-up call picks the product shapes
     stream = torch.cuda.current_stream(dev)
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
     torch.cuda.synchronize()
@@ -643,6 +644,7 @@ def bench_array600(args) -> dict:
     del y
     stream = torch.cuda.Stream(dev)
     ctx = ssicov.Context(0, stream)
+    ctx.set_autotune(True)              # the warm-up identification picks the product shapes
     runs = {}
     for name, prec, refine, steps in (("fp8", ssicov.PREC_FP8, 1, max(1, args.steps)),
                                       ("fp32", ssicov.PREC_FP32, 0, 1)):
@@ -724,6 +726,7 @@ def bench_array600(args) -> dict:
                             "orders_202_398": dist(hi_order) if len(em) else None,
                             "physical_fp32_poles_without_fp8_pole_within_1pct": unmatched},
             "eig_flags": flags,
+            "autotuned_products": tuned_configs(ctx, wl, "fp32"),
             "parity": "the modal stage at orders up to 400 is checked against the FP64 "
                       "checker on identical inputs at a smaller record; here FP8 against the "
                       "FP32 path",
