@@ -238,12 +238,12 @@ def test_modal_orders_above_200_same_inputs(ctx):
     assert np.array(stats["mac"]).min() >= 1 - 1e-6
 
 
-def test_modal_orders_to_400_same_inputs(ctx):
-    """Orders 196..400 step 12, fed the checker's U and sigma of a 60-channel
-    record's 480 x 480 Toeplitz matrix (k = 416): the QR iteration in LDS
-    (196) and in global memory, the Hessenberg reduction in registers (up to
-    224) and in global memory (above), and pole vectors with seven rows per
-    lane.  Physical poles: f rel <= 1e-10, xi abs <= 1e-9, MAC >= 1 - 1e-6.
+def test_modal_orders_to_448_same_inputs(ctx):
+    """Orders 196..448 step 12 (448 is the largest the modal kernels take),
+    fed the checker's U and sigma of a 60-channel record's 540 x 540 Toeplitz
+    matrix (k = 456): the QR iteration in LDS (196) and in global memory, the
+    Hessenberg reduction in registers (up to 224) and in global memory
+    (above), and pole vectors with seven rows per lane.  Physical poles: f rel <= 1e-10, xi abs <= 1e-9, MAC >= 1 - 1e-6.
     Every checker eigenvalue has a GPU eigenvalue within what a backward
     stable eigen-solver may move it: 1e3 eps ||X_n||_F kappa_i, kappa_i the
     eigenvalue's condition number (1 / |y_i^H x_i| for unit left and right
@@ -251,8 +251,8 @@ def test_modal_orders_to_400_same_inputs(ctx):
     import scipy.linalg
     wl = synth.Workload(name="wide400", l=60, n=20000, fs=100.0, n_modes=8,
                         f_range=(1.0, 20.0), zeta_range=(0.01, 0.03), noise=0.05,
-                        lags=(8,), svd="randomized", rank=416, oversample=16,
-                        power_iters=1, order_min=196, order_max=400, order_step=12,
+                        lags=(9,), svd="randomized", rank=456, oversample=16,
+                        power_iters=1, order_min=196, order_max=448, order_step=12,
                         struct_seed=15, noise_seed=16, sketch_seed=17)
     sysm, y = synth.make_record(wl)
     jb = wl.lags[0]
@@ -285,7 +285,7 @@ def test_modal_orders_to_400_same_inputs(ctx):
             worst = max(worst, d / bound[i])
             assert d <= bound[i], (f"order {n}: |d mu| {d:.2e} > bound {bound[i]:.2e} "
                                    f"(kappa {kappa[i]:.1e})")
-    print(f"orders 196..400: {len(stats['f'])} physical poles, max f rel "
+    print(f"orders 196..448: {len(stats['f'])} physical poles, max f rel "
           f"{max(stats['f']):.2e}, max |d mu| / bound {worst:.2e}")
     assert np.array(stats["f"]).max() <= 1e-10
     assert np.array(stats["xi"]).max() <= 1e-9

@@ -61,14 +61,16 @@ def _run_rsvd(ctx, t32, k, p, q, seed=7, stream=0, pad=0):
                                                (300, 20, 13, 1, 2, 0.8), (420, 190, 19, 1, 0, 0.98),
                                                (420, 200, 24, 1, 0, 0.98),
                                                (600, 230, 10, 1, 0, 0.99),
-                                               (1000, 400, 40, 1, 0, 0.99)])
+                                               (1000, 400, 40, 1, 0, 0.99),
+                                               (900, 400, 48, 1, 1, 0.99)])
 def test_rsvd_low_rank_plus_noise(ctx, m, k, p, q, pad, decay):
     """ell = k + p of 33 and 209 end in a partial 16 x 16 block of the blocked
     Cholesky and triangular inverse, 224 fills the largest register-path block
     count, 240 and 440 take the mid-size kernels (the matrix in global memory:
     blocked Cholesky with MFMA trailing updates, the 28-block triangular
     inverse, tridiagonalization and back-transformation by column passes;
-    224 < ell <= 448), 440 with a ragged last block."""
+    224 < ell <= 448), 440 with a ragged last block, 448 the largest they
+    take (28 full blocks)."""
     t32 = synth.random_lowrank(m, m, k, seed=m + k, decay=decay, noise=1e-5)
     u, s = _run_rsvd(ctx, t32, k, p, q, seed=11, pad=pad)
     om = oracle.sketch(11, m, k + p, 0)
@@ -144,7 +146,8 @@ def test_rsvd_bridge_toeplitz(ctx):
     _check_subspace(u.cpu().numpy(), ur, sr, 2 * wl.n_modes, 1e-6)
 
 
-@pytest.mark.parametrize("m,k", [(120, 40), (240, 40), (37, 37), (300, 40), (480, 40)])
+@pytest.mark.parametrize("m,k", [(120, 40), (240, 40), (37, 37), (300, 40), (448, 40), (449, 40),
+                                 (480, 40)])
 def test_svd_full(ctx, m, k):
     t32 = synth.random_lowrank(m, m, min(m, 60), seed=m, decay=0.9, noise=1e-4)
     u, s = ctx.svd_full(_dev(t32), k)
