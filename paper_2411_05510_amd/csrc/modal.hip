@@ -15,12 +15,13 @@
 //   francis     eigenvalues of H by the Francis double-shift QR iteration with
 //               deflation, H packed in LDS (n <= 200) or in global scratch
 //   vec         per pole (Im mu > 0): inverse iteration on H - mu I in complex
-//               arithmetic (Hessenberg LU with partial pivoting), psi_H, then
+//               arithmetic (column elimination with adjacent pivoting, one
+//               wave per pole, 4 or 7 rows of a column per lane), psi_H, then
 //               psi_X = Q psi_H by the Hessenberg reflectors and phi =
 //               U[0:l, :n] psi_X, normalised; lambda = ln(mu) f_s, f, xi
 //   francis and vec run in one persistent launch (eig_persistent_kernel):
-//   whole orders first, largest first, then poles, smallest orders first,
-//   each waiting for its order's eigenvalues
+//   whole orders first, largest first, then poles, smallest orders first;
+//   a pole whose order has not finished is deferred to pole_tail_kernel
 //   sort        poles of the order sorted by (f, xi) into the output slots
 #include "common.h"
 #include "kernels.h"
