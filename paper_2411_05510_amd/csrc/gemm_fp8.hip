@@ -81,37 +81,66 @@ SSI_DEV void quant_block(const float (&v)[kBlk], uint8_t *__restrict__ q, uint8_
 
 }  // namespace
 
-// Row quantization: q[r][k] from a[r][k] (k < cols, zero up to kp), one
-// thread per block; consecutive threads take consecutive blocks of a row.
+// Row quantization: q[r][k] from a[r][k] (k < cols, zero up to kp).  Eight
+// lanes share a 32-element block, four elements each (one 16-byte load when
+// rows are 16-byte aligned, VEC), so a wave reads 1 KiB of a row at once and
+// writes 256 contiguous code bytes; the block maximum is a maximum over the
+// eight lanes.  Lanes past the last block work on block 0 and store nothing.
+template <bool VEC>
 __global__ void __launch_bounds__(256)
 quant_rows_f32(const float *__restrict__ a, int64_t lda, int rows, int cols, int kp,
                uint8_t *__restrict__ q, uint8_t *__restrict__ s) {
   const int nb = kp / kBlk;
-  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (t >= (int64_t)rows * nb) return;
-  const int r = (int)(t / nb), b = (int)(t - (int64_t)r * nb);
+  const int64_t blk = ((int64_t)blockIdx.x * 256 + threadIdx.x) >> 3;
+  const int sub = threadIdx.x & 7;
+  const bool live = blk < (int64_t)rows * nb;
+  const int64_t bc = live ? blk : 0;
+  const int r = (int)(bc / nb), b = (int)(bc - (int64_t)r * nb);
   const float *src = a + (int64_t)r * lda;
-  float v[kBlk];
+  const int k0 = b * kBlk + 4 * sub;
+  float v[4];
+  if (VEC && k0 + 3 < cols) {
+    const f32x4v x = *reinterpret_cast<const f32x4v *>(src + k0);
+    v[0] = x.x; v[1] = x.y; v[2] = x.z; v[3] = x.w;
+  } else {
 #pragma unroll
-  for (int i = 0; i < kBlk; ++i) {
-    const int k = b * kBlk + i;
-    const float x = src[min(k, cols - 1)];
-    v[i] = k < cols ? x : 0.0f;
+    for (int i = 0; i < 4; ++i) {
+      const int k = k0 + i;
+      const float x = src[min(k, cols - 1)];
+      v[i] = k < cols ? x : 0.0f;
+    }
   }
-  quant_block(v, q + (int64_t)r * kp + b * kBlk, s + (int64_t)r * nb + b);
+  float amax = fmaxf(fmaxf(fabsf(v[0]), fabsf(v[1])), fmaxf(fabsf(v[2]), fabsf(v[3])));
+  amax = fmaxf(amax, __shfl_xor(amax, 1, 64));
+  amax = fmaxf(amax, __shfl_xor(amax, 2, 64));
+  amax = fmaxf(amax, __shfl_xor(amax, 4, 64));
+  const int e = block_exp(amax);
+  uint32_t c = 0;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) c |= e4m3_code(ldexpf(v[j], -e)) << (8 * j);
+  if (live) {
+    *reinterpret_cast<uint32_t *>(q + (int64_t)r * kp + k0) = c;
+    if (sub == 0) s[(int64_t)r * nb + b] = (uint8_t)(e + 127);
+  }
 }
 
 // Column quantization (the transpose): q[j][k] from a[k][j] for j < cols and
-// k < rows (zero past them, up to out_rows x kp); consecutive threads take
-// consecutive j of one block row, so every load of the 32 is coalesced.
+// k < rows (zero past them, up to out_rows x kp).  A workgroup takes 64
+// columns and 8 consecutive blocks of k, wave w block w: the lanes of a wave
+// take consecutive j, so every one of the 32 loads is coalesced, and the
+// eight waves write adjacent 32-byte pieces of each column's codes, 256
+// contiguous bytes per column.
+constexpr int kQcCols = 64, kQcBlocks = 8;
 template <typename T>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(64 * kQcBlocks)
 quant_cols(const T *__restrict__ a, int64_t lda, int rows, int cols, int kp, int out_rows,
            uint8_t *__restrict__ q, uint8_t *__restrict__ s) {
   const int nb = kp / kBlk;
-  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (t >= (int64_t)out_rows * nb) return;
-  const int b = (int)(t / out_rows), j = (int)(t - (int64_t)b * out_rows);
+  const int njt = (out_rows + kQcCols - 1) / kQcCols;
+  const int jt = blockIdx.x % njt, bg = blockIdx.x / njt;
+  const int j = jt * kQcCols + (threadIdx.x & (kQcCols - 1));
+  const int b = bg * kQcBlocks + (threadIdx.x >> 6);
+  if (j >= out_rows || b >= nb) return;
   const int jc = min(j, cols - 1);
   float v[kBlk];
 #pragma unroll
@@ -298,24 +327,33 @@ Fp8Plan plan_gemm_fp8(int M, int N, int K, int num_cus, int force_splits) {
 
 hipError_t launch_quant_rows_f32(const float *a, int64_t lda, int rows, int cols, int kp,
                                  uint8_t *q, uint8_t *s, hipStream_t st) {
-  const int64_t n = (int64_t)rows * (kp / kBlk);
-  hipLaunchKernelGGL(quant_rows_f32, dim3((unsigned)ceil_div<int64_t>(n, 256)), dim3(256), 0, st,
-                     a, lda, rows, cols, kp, q, s);
+  const int64_t lanes = (int64_t)rows * (kp / kBlk) * 8;
+  const dim3 grid((unsigned)ceil_div<int64_t>(lanes, 256));
+  if (lda % 4 == 0 && (uintptr_t)a % 16 == 0)
+    hipLaunchKernelGGL(quant_rows_f32<true>, grid, dim3(256), 0, st, a, lda, rows, cols, kp, q, s);
+  else
+    hipLaunchKernelGGL(quant_rows_f32<false>, grid, dim3(256), 0, st, a, lda, rows, cols, kp, q,
+                       s);
   return hipGetLastError();
 }
 
+namespace {
+dim3 quant_cols_grid(int out_rows, int kp) {
+  const int64_t njt = ceil_div(out_rows, kQcCols), nbg = ceil_div(kp / kBlk, kQcBlocks);
+  return dim3((unsigned)(njt * nbg));
+}
+}  // namespace
+
 hipError_t launch_quant_cols_f32(const float *a, int64_t lda, int rows, int cols, int kp,
                                  int out_rows, uint8_t *q, uint8_t *s, hipStream_t st) {
-  const int64_t n = (int64_t)out_rows * (kp / kBlk);
-  hipLaunchKernelGGL(quant_cols<float>, dim3((unsigned)ceil_div<int64_t>(n, 256)), dim3(256), 0,
+  hipLaunchKernelGGL(quant_cols<float>, quant_cols_grid(out_rows, kp), dim3(64 * kQcBlocks), 0,
                      st, a, lda, rows, cols, kp, out_rows, q, s);
   return hipGetLastError();
 }
 
 hipError_t launch_quant_cols_f64(const double *a, int64_t lda, int rows, int cols, int kp,
                                  int out_rows, uint8_t *q, uint8_t *s, hipStream_t st) {
-  const int64_t n = (int64_t)out_rows * (kp / kBlk);
-  hipLaunchKernelGGL(quant_cols<double>, dim3((unsigned)ceil_div<int64_t>(n, 256)), dim3(256), 0,
+  hipLaunchKernelGGL(quant_cols<double>, quant_cols_grid(out_rows, kp), dim3(64 * kQcBlocks), 0,
                      st, a, lda, rows, cols, kp, out_rows, q, s);
   return hipGetLastError();
 }
