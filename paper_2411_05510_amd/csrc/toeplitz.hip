@@ -3,13 +3,14 @@
 // with R_j stored at r_stack[(j - 1) l l + a l + b].
 //
 // A pure HBM write stream (m^2 floats) whose source, the 2 jb - 1 blocks of R,
-// stays in L2 / Infinity Cache.  A workgroup covers 4096 floats of one row;
-// in each of its four 16-byte store instructions the lanes of a wave write
+// stays in L2 / Infinity Cache.  A workgroup covers 2048 floats of one row;
+// in each of its two 16-byte store instructions the lanes of a wave write
 // consecutive float4s, so every store instruction of a wave is one contiguous
-// 1 KiB run of full cache lines.  The stores carry the nontemporal hint: T is
-// written once and read back only by the next kernel, after far more data than
-// the caches hold has passed, and with the hint the store stream runs at the
-// rate of a plain fill kernel (4.1 -> 5.6 TB/s at m = 10800).  The vector path needs l, ldt and both
+// 1 KiB run of full cache lines.  Measured at m = 10800 with 256 threads: two
+// stores per thread 6.0-6.4 TB/s, four 5.5-5.6, one 4.9-5.1.  The stores carry
+// the nontemporal hint: T is written once and read back only by the next
+// kernel, after far more data than the caches hold has passed (4.1 TB/s
+// without it).  The vector path needs l, ldt and both
 // pointers 16-byte aligned (a float4 then never straddles two blocks);
 // otherwise a scalar path is used.
 #include "common.h"
@@ -17,7 +18,7 @@
 
 namespace {
 
-constexpr int kVecPerThread = 4;                 // float4 stores per thread
+constexpr int kVecPerThread = 2;                 // float4 stores per thread
 constexpr int kThreads = 256;
 constexpr int kFloatsPerBlock = kThreads * kVecPerThread * 4;
 
