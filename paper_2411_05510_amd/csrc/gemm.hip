@@ -333,20 +333,24 @@ gemm_f64_mfma(const double *__restrict__ A, int64_t lda, const double *__restric
     }
 }
 
-// out[i][j] = scale * sum_s part[s][i][j]; optional FP32 copy.  Block
-// (x, y) takes row y (and the rows gridDim.y apart) and 256 columns from
-// 256 x: no index division, coalesced rows; splits summed in order.  The
-// partials are loaded eight at a time, unconditionally (split index clamped to
-// the last one, whose repeats are not added), so the eight loads are in flight
-// together; a load per split inside the summing loop waited for the previous.
+// out[i][j] = scale * sum_s part[s][i][j]; optional FP32 copy.  One thread
+// per output element over the flattened M x N range (grid-stride), so every
+// lane of every workgroup works also when N is not a multiple of the
+// workgroup width (N = 220 with a workgroup per row used 86 % of its lanes and
+// ran at 1.6 TB/s); splits summed in order.  The partials are loaded eight at
+// a time, unconditionally (split index clamped to the last one, whose repeats
+// are not added), so the eight loads are in flight together; a load per split
+// inside the summing loop waited for the previous.
 __global__ void __launch_bounds__(256)
 reduce_splits(const double *__restrict__ part, int splits, int64_t split_stride, int64_t ldp,
               int M, int N, double scale, double *__restrict__ out, int64_t ldo,
               float *__restrict__ out32, int64_t ld32) {
-  const int j = blockIdx.x * 256 + threadIdx.x;
-  if (j >= N) return;
-  for (int i = blockIdx.y; i < M; i += gridDim.y) {
-    const double *pp = part + (int64_t)i * ldp + j;
+  const int64_t total = (int64_t)M * N;
+  for (int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x; idx < total;
+       idx += (int64_t)gridDim.x * 256) {
+    const int64_t i = idx / N;
+    const int j = (int)(idx - i * N);
+    const double *pp = part + i * ldp + j;
     double s = 0.0;
     for (int sp0 = 0; sp0 < splits; sp0 += 8) {
       double v[8];
@@ -357,8 +361,8 @@ reduce_splits(const double *__restrict__ part, int splits, int64_t split_stride,
         if (sp0 + u < splits) s += v[u];
     }
     s *= scale;
-    if (out) out[(int64_t)i * ldo + j] = s;
-    if (out32) out32[(int64_t)i * ld32 + j] = (float)s;
+    if (out) out[i * ldo + j] = s;
+    if (out32) out32[i * ld32 + j] = (float)s;
   }
 }
 
@@ -521,9 +525,8 @@ hipError_t launch_gemm_f64(const GemmPlan &p, bool trans_a, const double *A, int
 hipError_t launch_reduce(const GemmPlan &p, const double *part, int M, int N, double scale,
                          double *out, int64_t ldo, float *out32, int64_t ld32, hipStream_t st) {
   if (M <= 0 || N <= 0) return hipSuccess;
-  const dim3 grid(ceil_div(N, 256), std::min(M, 65535));
-  hipLaunchKernelGGL(reduce_splits, grid, dim3(256), 0, st, part, p.splits, p.split_stride,
-                     p.ldc, M, N, scale, out, ldo, out32, ld32);
+  hipLaunchKernelGGL(reduce_splits, dim3(grid_cap((int64_t)M * N)), dim3(256), 0, st, part,
+                     p.splits, p.split_stride, p.ldc, M, N, scale, out, ldo, out32, ld32);
   return hipGetLastError();
 }
 
