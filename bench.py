@@ -258,7 +258,8 @@ def bench_identify(args) -> dict:
     yd = torch.from_numpy(y).to(dev)
     p = params_of(wl, PRECS[args.prec], args.refine)
     k = max(1, args.in_flight)
-    # one context, stream and output set per window in flight
+    # one context, stream, copy of the record and output set per window in flight
+    yds = [yd] + [yd.clone() for _ in range(k - 1)]
     streams = [torch.cuda.Stream(dev) for _ in range(k)]
     ctxs = [ssicov.Context(0, s) for s in streams]
     outs = []
@@ -276,9 +277,9 @@ def bench_identify(args) -> dict:
         del src, dst
 
     # warm-up one context at a time, so that each autotunes on an idle GPU
-    for c, o in zip(ctxs, outs):
+    for c, o, yc in zip(ctxs, outs, yds):
         for _ in range(args.warmup):
-            c.identify(yd, p, o)
+            c.identify(yc, p, o)
         c.synchronize()
 
     # Throughput (the timed region): steps identifications, step i on
@@ -290,7 +291,7 @@ def bench_identify(args) -> dict:
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(args.steps):
-        ctxs[i % k].identify(yd, p, outs[i % k])
+        ctxs[i % k].identify(yds[i % k], p, outs[i % k])
     torch.cuda.synchronize()
     for c in ctxs:
         c.synchronize()
@@ -374,8 +375,8 @@ def bench_identify(args) -> dict:
                         "(10800x10800 Toeplitz), randomized SVD k=200 p=20 q=2, "
                         f"orders 2..200 step 2; {corr_note}, {prec_note}{refine_note}, "
                         "FP64 factorizations and eigen-analysis; product K slices autotuned "
-                        f"in the warm-up; {k} windows in flight (one context, stream and "
-                        "output set each)",
+                        f"in the warm-up; {k} windows in flight (one context, stream, copy of "
+                        "the record and output set each)",
             "windows_in_flight": k,
             "hip_hw_queues": int(os.environ.get("GPU_MAX_HW_QUEUES", "4")),
             "latency_ms_p50": float(np.percentile(step_ms, 50)),
