@@ -46,11 +46,13 @@ BF16_MFMA_PEAK_TFLOPS = 2500.0      # MI355X dense BF16 matrix peak
 HBM_PEAK_GBS = 8000.0
 COPY_PROBE_BYTES = 256 << 20        # plain device copy used to calibrate HBM byte counters
 PMC_SUMMARY = {"fp32": os.path.join(ROOT, "profiles", "correlate_mfma_bridge180_pmc.md"),
-               "bf16x6": os.path.join(ROOT, "profiles", "correlate_b6_bridge180_pmc.md")}
+               "bf16x6": os.path.join(ROOT, "profiles", "correlate_b6_bridge180_pmc.md"),
+               "f16x3": os.path.join(ROOT, "profiles", "correlate_h3_bridge180_pmc.md")}
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2411_05510_amd", "csrc", "correlate.hip")
 PRECS = {"fp32": 0, "bf16": 1, "bf16x3": 2, "bf16x6": 3, "fp8": 4}
-CORR_MODES = {"fp32": 0, "bf16x6": 1}
-CORR_KERNEL = {"fp32": "correlate_mfma", "bf16x6": "correlate_b6"}
+CORR_MODES = {"fp32": 0, "bf16x6": 1, "f16x3": 2}
+CORR_KERNEL = {"fp32": "correlate_mfma", "bf16x6": "correlate_b6", "f16x3": "correlate_h3"}
+FP16_MFMA_PEAK_TFLOPS = 2500.0      # MI355X dense FP16 matrix peak
 
 
 def measured_traffic(corr: str):
@@ -117,15 +119,18 @@ def roofline(stages, l, n, L, corr: str):
     """Roofline of the correlation contraction kernel, on algorithmic work
     only: the contraction's 2 l^2 sum_j (N - j) flops per launch over the
     kernel's mean duration, against the peak of the matrix instructions it
-    runs on (BF16 for the six-product split, FP32 otherwise).  The six BF16
-    products per FP32 product are emulation overhead and are not counted; the
-    rate at which the kernel issues BF16 MFMA work is reported beside it."""
+    runs on (BF16 for the six-product split, FP16 for the three-product
+    split, FP32 otherwise).  The several split products per FP32 product are
+    emulation overhead and are not counted; the rate at which the kernel
+    issues matrix work is reported beside it."""
     flops = corr_flops(l, n, L)
     corr_ms, corr_calls = stages["corr_mfma"]
     corr_avg_ms = corr_ms / max(corr_calls, 1)
     achieved = flops / (corr_avg_ms * 1e-3) / 1e12
     if corr == "bf16x6":
         issue, peak = 6.0 * achieved, BF16_MFMA_PEAK_TFLOPS
+    elif corr == "f16x3":
+        issue, peak = 3.0 * achieved, FP16_MFMA_PEAK_TFLOPS
     else:
         issue, peak = achieved, FP32_MFMA_PEAK_TFLOPS
     return {
@@ -346,7 +351,10 @@ def bench_identify(args) -> dict:
                          f"(FP64 numpy checker, {cpu_s:.1f} s)"}
     corr_note = {"fp32": "correlations on FP32 MFMA",
                  "bf16x6": "correlations as six BF16 MFMA products of the exact three-way "
-                           "BF16 split of the FP32 samples (FP32 accumulation)"}[args.corr]
+                           "BF16 split of the FP32 samples (FP32 accumulation)",
+                 "f16x3": "correlations as three FP16 MFMA products of the two-way FP16 "
+                          "split of the power-of-two-scaled FP32 samples (22 significant "
+                          "bits, FP32 accumulation)"}[args.corr]
     refine_note = (f" with {args.refine} full-precision refinement power step"
                    if args.prec != "fp32" and args.refine else "")
     prec_note = {"fp32": "T x Q products on FP64 MFMA",
@@ -846,7 +854,7 @@ def main() -> int:
     ap.add_argument("--refine", type=int, default=None,
                     help="full-precision refinement power steps of a reduced-precision range "
                          "finder (default 1 for BF16 modes)")
-    ap.add_argument("--corr", default="bf16x6", choices=tuple(CORR_MODES),
+    ap.add_argument("--corr", default="f16x3", choices=tuple(CORR_MODES),
                     help="correlation product arithmetic")
     ap.add_argument("--lag-streams", type=int, default=3)
     ap.add_argument("--in-flight", type=int, default=4,

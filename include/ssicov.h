@@ -99,18 +99,31 @@ typedef enum ssi_precision {
 } ssi_precision;
 
 /* Arithmetic of the correlation products (Section 2.1), a context option.
- * Both accumulate FP32 products in FP32 over 32-sample steps, fold into FP64
+ * All accumulate FP32 products in FP32 over 32-sample steps, fold into FP64
  * every 256 samples and sum the time splits in FP64. */
 typedef enum ssi_corr_mode {
   SSI_CORR_FP32 = 0,   /* FP32 samples on v_mfma_f32_16x16x4f32                   */
-  SSI_CORR_BF16X6 = 1  /* each FP32 sample split exactly into three BF16 parts
+  SSI_CORR_BF16X6 = 1, /* each FP32 sample split exactly into three BF16 parts
                           (hi + mid + lo, by truncation); the six cross products of
                           weight >= 2^-16 on v_mfma_f32_16x16x32_bf16, each exact in
                           FP32; the three dropped terms are below 2^-23 |y_a y_b|.
                           Needs 6 l' N' bytes of workspace for the parts (l', N':
                           channels and samples rounded up); falls back to
                           SSI_CORR_FP32 when a tile would not fit (tiny lag counts
-                          with many channels).  The default.                      */
+                          with many channels).                                    */
+  SSI_CORR_F16X3 = 2   /* each channel scaled by a power of two 2^e_a that puts its
+                          largest |sample| in [2^13, 2^14); each scaled sample x
+                          split into two FP16 parts, hi = FP16(x) and
+                          lo = FP16(x - hi) (nearest even), so hi + lo equals x to
+                          2^-22 |x|; the three cross products hi hi, hi lo, lo hi
+                          on v_mfma_f32_16x16x32_f16, each exact in FP32, the
+                          dropped lo lo below 2^-22 |x_a x_b|; the sums scaled back
+                          by 2^-(e_a + e_b) exactly.  Per product the error is at
+                          most about 2^-21 |y_a y_b|, below the worst-case rounding
+                          of the 256-sample FP32 accumulation that every mode
+                          shares.  Needs 4 l' N' + 36 l' bytes of workspace; falls
+                          back to SSI_CORR_FP32 like SSI_CORR_BF16X6.  The
+                          default.                                                */
 } ssi_corr_mode;
 
 /* Identification parameters (Section 2.1 and 2.3 control parameters). */
@@ -213,7 +226,7 @@ enum {
                                 Hessenberg forms (per lag)              */
   SSI_STAGE_EIG,             /* QR iterations, poles and sorting of every
                                 (lag, order), one launch                */
-  SSI_STAGE_CORR_SPLIT,      /* BF16 parts of the record (BF16x6 mode)  */
+  SSI_STAGE_CORR_SPLIT,      /* split parts of the record (BF16x6, FP16x3) */
   SSI_STAGE_COUNT
 };
 ssi_status ssi_set_profiling(ssi_ctx *ctx, int enable);
@@ -277,7 +290,7 @@ ssi_status ssi_set_eig_max_sweeps(ssi_ctx *ctx, int32_t sweeps_per_row);
 ssi_status ssi_set_allocator(ssi_ctx *ctx, void *(*alloc)(size_t bytes, void *user),
                              void (*release)(void *ptr, void *user), void *user);
 /* Correlation product arithmetic (ssi_corr_mode) for later ssi_correlate,
- * ssi_identify and serving calls on this context; default SSI_CORR_BF16X6.
+ * ssi_identify and serving calls on this context; default SSI_CORR_F16X3.
  * SSI_EINVAL for an unknown mode.  Drops captured graphs. */
 ssi_status ssi_set_corr_mode(ssi_ctx *ctx, int32_t mode);
 /* Launch configuration chosen by the autotuner for a product, 0 if not

@@ -82,7 +82,7 @@ struct ssi_ctx {
   bool autotune = false;
   int tile_rows = 128;            // FP32 x FP64 product tiles when not tuned
   // correlation product arithmetic (ssi_corr_mode)
-  int corr_mode = SSI_CORR_BF16X6;
+  int corr_mode = SSI_CORR_F16X3;
   std::map<std::tuple<int, int, int, int, int>, int> tuned;
   // QR sweep limit of the eigen-analysis: sweeps_per_row * max(10, n) per order
   int sweeps_per_row = 30;
@@ -384,7 +384,7 @@ ssi_status ssi_set_product_tile_rows(ssi_ctx *c, int32_t rows) {
 
 ssi_status ssi_set_corr_mode(ssi_ctx *c, int32_t mode) {
   if (!c) return fail(SSI_EINVAL, "ssi_set_corr_mode: NULL context");
-  if (mode != SSI_CORR_FP32 && mode != SSI_CORR_BF16X6)
+  if (mode != SSI_CORR_FP32 && mode != SSI_CORR_BF16X6 && mode != SSI_CORR_F16X3)
     return fail(SSI_EINVAL, "ssi_set_corr_mode: unknown mode %d", mode);
   if (mode != c->corr_mode) {
     DeviceGuard g(c->device);
@@ -1138,7 +1138,7 @@ ssi_status run_identify(ssi_ctx *c, IdentBufs &b, const float *y, int l, int64_t
                         int64_t ldy, const ssi_params *p, const ssi_output *out) {
   const int L = 2 * p->lags[p->n_lags - 1] - 1;
   hipError_t e;
-  if (b.cp.mode == SSI_CORR_BF16X6) {
+  if (b.cp.mode != SSI_CORR_FP32) {
     StageTimer tm(c, SSI_STAGE_CORR_SPLIT);
     e = ssi::launch_correlate_split(b.cp, y, l, n, ldy, b.planes, c->stream);
     if (e != hipSuccess) return hip_fail(e, "correlation split");
@@ -1150,7 +1150,8 @@ ssi_status run_identify(ssi_ctx *c, IdentBufs &b, const float *y, int l, int64_t
   if (e != hipSuccess) return hip_fail(e, "correlations");
   {
     StageTimer tm(c, SSI_STAGE_CORR_REDUCE);
-    e = ssi::launch_correlate_reduce(b.cp, l, n, L, b.corr_part, b.r, c->status, c->stream);
+    e = ssi::launch_correlate_reduce(b.cp, l, n, L, b.corr_part, b.planes, b.r, c->status,
+                                     c->stream);
   }
   if (e != hipSuccess) return hip_fail(e, "correlation reduction");
   if (b.n_lanes == 1) {
@@ -1202,7 +1203,7 @@ ssi_status ssi_correlate(ssi_ctx *c, const float *y, int32_t l, int64_t n, int64
   if (s != SSI_OK) return s;
   double *partial = ws_take<double>(c, cp.partial_elems);
   uint16_t *planes = ws_take<uint16_t>(c, cp.planes_elems);
-  if (cp.mode == SSI_CORR_BF16X6) {
+  if (cp.mode != SSI_CORR_FP32) {
     StageTimer tm(c, SSI_STAGE_CORR_SPLIT);
     SSI_HIP(ssi::launch_correlate_split(cp, y, l, n, ldy, planes, c->stream));
   }
@@ -1211,7 +1212,8 @@ ssi_status ssi_correlate(ssi_ctx *c, const float *y, int32_t l, int64_t n, int64
     SSI_HIP(ssi::launch_correlate_mfma(cp, y, l, n, ldy, n_corr, partial, planes, c->stream));
   }
   StageTimer tm(c, SSI_STAGE_CORR_REDUCE);
-  SSI_HIP(ssi::launch_correlate_reduce(cp, l, n, n_corr, partial, r, c->status, c->stream));
+  SSI_HIP(ssi::launch_correlate_reduce(cp, l, n, n_corr, partial, planes, r, c->status,
+                                       c->stream));
   return SSI_OK;
 }
 

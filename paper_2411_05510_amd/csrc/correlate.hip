@@ -217,6 +217,7 @@ correlate_mfma(const float *__restrict__ y, int l, int64_t n, int64_t ldy, int L
 
 // ------------------------------------------------------------ BF16x6 path
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
 namespace {
@@ -270,6 +271,85 @@ split3_kernel(const float *__restrict__ y, int l, int64_t n, int64_t ldy, int lp
   }
 }
 
+// FP16x3 path, step 1: partial maxima of |sample| per channel row, kScaleParts
+// workgroups per channel, each over one contiguous part of the record (zero
+// for the padding channels c >= l).  fmaxf drops NaN; a NaN or Inf sample
+// still reaches the products and makes a correlation non-finite.
+constexpr int kScaleParts = 8;
+
+__global__ void __launch_bounds__(256)
+chan_max_kernel(const float *__restrict__ y, int l, int64_t n, int64_t ldy,
+                float *__restrict__ pmax) {
+  __shared__ float part[4];
+  const int c = blockIdx.x, g = blockIdx.y;
+  const int64_t len = (n + kScaleParts - 1) / kScaleParts;
+  const int64_t s_end = min(n, (g + 1) * len);
+  float mx = 0.0f;
+  if (c < l) {
+    const float *row = y + (int64_t)c * ldy;
+    int64_t s = g * len + threadIdx.x;
+    for (; s + 3 * 256 < s_end; s += 4 * 256) {
+      const float a = row[s], b = row[s + 256], d = row[s + 512], e = row[s + 768];
+      mx = fmaxf(mx, fmaxf(fmaxf(fabsf(a), fabsf(b)), fmaxf(fabsf(d), fabsf(e))));
+    }
+    for (; s < s_end; s += 256) mx = fmaxf(mx, fabsf(row[s]));
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) mx = fmaxf(mx, __shfl_xor(mx, off));
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = mx;
+  __syncthreads();
+  if (threadIdx.x == 0)
+    pmax[c * kScaleParts + g] = fmaxf(fmaxf(part[0], part[1]), fmaxf(part[2], part[3]));
+}
+
+// The channel's scale exponent e: 2^e brings its largest |sample| into
+// [2^13, 2^14), well inside the FP16 range; e = 0 for an all-zero or
+// non-finite channel and for the padding channels.
+SSI_DEV int chan_exponent(const float *__restrict__ pmax, int c) {
+  float mx = 0.0f;
+#pragma unroll
+  for (int g = 0; g < kScaleParts; ++g) mx = fmaxf(mx, pmax[c * kScaleParts + g]);
+  if (!(mx > 0.0f) || !isfinite(mx)) return 0;
+  int ex;
+  (void)frexpf(mx, &ex);                         // mx = m 2^ex, m in [1/2, 1)
+  return 14 - ex;
+}
+
+// FP16x3 path, step 2: planes[q][c][s] (q = hi, lo) of x = y 2^e_c, and
+// the exponents e_c:
+// hi = FP16(x), lo = FP16(x - hi) (round to nearest even; x - hi is exact in
+// FP32), so |x - hi - lo| <= 2^-22 |x| for normal FP16 parts, and below
+// 2^-25 absolutely (2^-38 of the channel maximum) for the smallest samples.
+// Zero past the record and for channels c >= l.
+__global__ void __launch_bounds__(256)
+split2h_kernel(const float *__restrict__ y, int l, int64_t n, int64_t ldy, int lp, int64_t np,
+               const float *__restrict__ pmax, int *__restrict__ exps,
+               uint16_t *__restrict__ planes) {
+  const int64_t per_row = np / 4;
+  const int64_t total = (int64_t)lp * per_row;
+  const int64_t plane = (int64_t)lp * np;
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const int c = (int)(idx / per_row);
+    const int64_t s = (idx - (int64_t)c * per_row) * 4;
+    const int e = chan_exponent(pmax, c);
+    if (s == 0) exps[c] = e;                     // for the reduction's scale-back
+    uint32_t hb[4], lb[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const float x = (c < l && s + i < n) ? ldexpf(y[(int64_t)c * ldy + s + i], e) : 0.0f;
+      const _Float16 h = (_Float16)x;
+      const _Float16 w = (_Float16)(x - (float)h);
+      hb[i] = __builtin_bit_cast(uint16_t, h);
+      lb[i] = __builtin_bit_cast(uint16_t, w);
+    }
+    const int64_t o = (int64_t)c * np + s;
+    *reinterpret_cast<uint2 *>(planes + o) = make_uint2(hb[0] | (hb[1] << 16), hb[2] | (hb[3] << 16));
+    *reinterpret_cast<uint2 *>(planes + plane + o) =
+        make_uint2(lb[0] | (lb[1] << 16), lb[2] | (lb[3] << 16));
+  }
+}
+
 // Same tiling and outputs as correlate_mfma, on the three BF16 planes.  One
 // K step covers 32 samples.  An A fragment of rows (a, j) is, in lane (row, g),
 // the 8 samples s + 8 g + j .. + 7 of channel a's window: they start at any
@@ -280,10 +360,11 @@ split3_kernel(const float *__restrict__ y, int l, int64_t n, int64_t ldy, int lp
 // record and past the channels, so no load needs a guard; split_len is a
 // multiple of the tile, so a tile never reaches past its split except at the
 // end of the record.
-__global__ void __launch_bounds__(kThreads, 2)
-correlate_b6(const uint16_t *__restrict__ planes, int l, int64_t n, int lp, int64_t np, int L,
-             int64_t split_len, double *__restrict__ partial, int sa_stride, int na_max,
-             int copy_stride, int grid_rows, int grid_cols, int n_splits) {
+template <int NP>
+SSI_DEV __forceinline__ void
+correlate_split_body(const uint16_t *__restrict__ planes, int l, int64_t n, int lp, int64_t np,
+                     int L, int64_t split_len, double *__restrict__ partial, int sa_stride,
+                     int na_max, int copy_stride, int grid_rows, int grid_cols, int n_splits) {
   extern __shared__ __align__(16) uint16_t lds6[];
   const int rows_total = l * L;
   const CorrTile tile = corr_tile(grid_rows, grid_cols, grid_rows * grid_cols * n_splits);
@@ -295,10 +376,10 @@ correlate_b6(const uint16_t *__restrict__ planes, int l, int64_t n, int lp, int6
   if (s_begin >= s_end) return;
   const int64_t plane = (int64_t)lp * np;
 
-  // [3][64][kSB6] B tile, then 8 copies (stride copy_stride) of the
-  // [3][na_max][sa_stride] A window, copy c holding window sample t + c at t
+  // [NP][64][kSB6] B tile, then 8 copies (stride copy_stride) of the
+  // [NP][na_max][sa_stride] A window, copy c holding window sample t + c at t
   uint16_t *yb = lds6;
-  uint16_t *ya = lds6 + 3 * kColsPerWG * kSB6;
+  uint16_t *ya = lds6 + NP * kColsPerWG * kSB6;
   const int pa = na_max * sa_stride;                    // elements per plane of a copy
 
   const int tid = threadIdx.x;
@@ -332,11 +413,12 @@ correlate_b6(const uint16_t *__restrict__ planes, int l, int64_t n, int lp, int6
       for (int q = 0; q < 4; ++q) accd[t][u][q] = 0.0;
     }
 
-  // B tile: 3 planes x 64 rows x 16 chunks of 8 samples = 3072 chunks, 6 per
-  // thread.  A window: 3 planes x na rows x wa8 chunks; a thread takes chunk
-  // c8 and the one after it and writes the eight shifted copies of chunk c8.
-  const int nA = 3 * na * wa8;
-  u32x4 rb[6], ra0 = u32x4{0u, 0u, 0u, 0u}, ra1 = ra0;
+  // B tile: NP planes x 64 rows x 16 chunks of 8 samples = NP x 1024 chunks,
+  // 2 NP per thread.  A window: NP planes x na rows x wa8 chunks; a thread
+  // takes chunk c8 and the one after it and writes the eight shifted copies of
+  // chunk c8.
+  const int nA = NP * na * wa8;
+  u32x4 rb[2 * NP], ra0 = u32x4{0u, 0u, 0u, 0u}, ra1 = ra0;
   int qa = 0, ia = 0, ca = 0;
   if (tid < nA) {
     qa = tid / (na * wa8);
@@ -346,7 +428,7 @@ correlate_b6(const uint16_t *__restrict__ planes, int l, int64_t n, int lp, int6
   }
   auto load_tile = [&](int64_t s0) {
 #pragma unroll
-    for (int h = 0; h < 6; ++h) {
+    for (int h = 0; h < 2 * NP; ++h) {
       const int idx = tid + kThreads * h;
       const int q = idx >> 10, rem = idx & 1023, row = rem >> 4, ch = rem & 15;
       rb[h] = *reinterpret_cast<const u32x4 *>(planes + q * plane + (int64_t)(c0 + row) * np +
@@ -376,7 +458,7 @@ correlate_b6(const uint16_t *__restrict__ planes, int l, int64_t n, int lp, int6
   };
   auto store_tile = [&](int64_t s0) {
 #pragma unroll
-    for (int h = 0; h < 6; ++h) {
+    for (int h = 0; h < 2 * NP; ++h) {
       const int idx = tid + kThreads * h;
       const int q = idx >> 10, rem = idx & 1023, row = rem >> 4, ch = rem & 15;
       *reinterpret_cast<u32x4 *>(&yb[(q * kColsPerWG + row) * kSB6 + 8 * ch]) = rb[h];
@@ -400,28 +482,52 @@ correlate_b6(const uint16_t *__restrict__ planes, int l, int64_t n, int lp, int6
 
 #pragma unroll 2
     for (int kk = 0; kk < kST; kk += 32) {
-      bf16x8 bf[2][3];
+      if constexpr (NP == 3) {
+        bf16x8 bf[2][3];
 #pragma unroll
-      for (int u = 0; u < 2; ++u)
+        for (int u = 0; u < 2; ++u)
 #pragma unroll
-        for (int q = 0; q < 3; ++q)
-          bf[u][q] = *reinterpret_cast<const bf16x8 *>(&yb[q * kColsPerWG * kSB6 + offB[u] + kk]);
+          for (int q = 0; q < 3; ++q)
+            bf[u][q] = *reinterpret_cast<const bf16x8 *>(&yb[q * kColsPerWG * kSB6 + offB[u] + kk]);
 #pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        bf16x8 af[3];
+        for (int t = 0; t < 4; ++t) {
+          bf16x8 af[3];
 #pragma unroll
-        for (int q = 0; q < 3; ++q)
-          af[q] = *reinterpret_cast<const bf16x8 *>(&ya[offA[t] + q * pa + kk]);
+          for (int q = 0; q < 3; ++q)
+            af[q] = *reinterpret_cast<const bf16x8 *>(&ya[offA[t] + q * pa + kk]);
 #pragma unroll
-        for (int u = 0; u < 2; ++u) {
-          f32x4 c = acc[t][u];
-          c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[2], bf[u][0], c, 0, 0, 0);   // lo hi
-          c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[0], bf[u][2], c, 0, 0, 0);   // hi lo
-          c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[1], bf[u][1], c, 0, 0, 0);   // mid mid
-          c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[1], bf[u][0], c, 0, 0, 0);   // mid hi
-          c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[0], bf[u][1], c, 0, 0, 0);   // hi mid
-          c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[0], bf[u][0], c, 0, 0, 0);   // hi hi
-          acc[t][u] = c;
+          for (int u = 0; u < 2; ++u) {
+            f32x4 c = acc[t][u];
+            c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[2], bf[u][0], c, 0, 0, 0);   // lo hi
+            c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[0], bf[u][2], c, 0, 0, 0);   // hi lo
+            c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[1], bf[u][1], c, 0, 0, 0);   // mid mid
+            c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[1], bf[u][0], c, 0, 0, 0);   // mid hi
+            c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[0], bf[u][1], c, 0, 0, 0);   // hi mid
+            c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[0], bf[u][0], c, 0, 0, 0);   // hi hi
+            acc[t][u] = c;
+          }
+        }
+      } else {
+        f16x8 bf[2][2];
+#pragma unroll
+        for (int u = 0; u < 2; ++u)
+#pragma unroll
+          for (int q = 0; q < 2; ++q)
+            bf[u][q] = *reinterpret_cast<const f16x8 *>(&yb[q * kColsPerWG * kSB6 + offB[u] + kk]);
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          f16x8 af[2];
+#pragma unroll
+          for (int q = 0; q < 2; ++q)
+            af[q] = *reinterpret_cast<const f16x8 *>(&ya[offA[t] + q * pa + kk]);
+#pragma unroll
+          for (int u = 0; u < 2; ++u) {
+            f32x4 c = acc[t][u];
+            c = __builtin_amdgcn_mfma_f32_16x16x32_f16(af[1], bf[u][0], c, 0, 0, 0);    // lo hi
+            c = __builtin_amdgcn_mfma_f32_16x16x32_f16(af[0], bf[u][1], c, 0, 0, 0);    // hi lo
+            c = __builtin_amdgcn_mfma_f32_16x16x32_f16(af[0], bf[u][0], c, 0, 0, 0);    // hi hi
+            acc[t][u] = c;
+          }
         }
       }
     }
@@ -439,7 +545,7 @@ correlate_b6(const uint16_t *__restrict__ planes, int l, int64_t n, int lp, int6
     }
   }
 
-  // D layout of 16x16x32 bf16: lane holds rows 4*(lane/16)+q, column lane%16.
+  // D layout of 16x16x32 bf16 and f16: lane holds rows 4*(lane/16)+q, column lane%16.
   double *dst = partial + (int64_t)split * rows_total * l;
 #pragma unroll
   for (int t = 0; t < 4; ++t) {
@@ -455,14 +561,33 @@ correlate_b6(const uint16_t *__restrict__ planes, int l, int64_t n, int lp, int6
   }
 }
 
-// R[j-1][a][b] = (float)(sum_split partial[split][a L + j - 1][b] / n).
+__global__ void __launch_bounds__(kThreads, 2)
+correlate_b6(const uint16_t *__restrict__ planes, int l, int64_t n, int lp, int64_t np, int L,
+             int64_t split_len, double *__restrict__ partial, int sa_stride, int na_max,
+             int copy_stride, int grid_rows, int grid_cols, int n_splits) {
+  correlate_split_body<3>(planes, l, n, lp, np, L, split_len, partial, sa_stride, na_max,
+                          copy_stride, grid_rows, grid_cols, n_splits);
+}
+
+// FP16x3: the same tiling on the two FP16 planes of the scaled record.
+__global__ void __launch_bounds__(kThreads, 2)
+correlate_h3(const uint16_t *__restrict__ planes, int l, int64_t n, int lp, int64_t np, int L,
+             int64_t split_len, double *__restrict__ partial, int sa_stride, int na_max,
+             int copy_stride, int grid_rows, int grid_cols, int n_splits) {
+  correlate_split_body<2>(planes, l, n, lp, np, L, split_len, partial, sa_stride, na_max,
+                          copy_stride, grid_rows, grid_cols, n_splits);
+}
+
+// R[j-1][a][b] = (float)(sum_split partial[split][a L + j - 1][b] / n), times
+// 2^-(e_a + e_b) when the FP16x3 path scaled the channels (exps not null).
 // A non-finite sample makes some correlation non-finite (every sample enters
 // at least one product, and NaN or Inf times anything stays non-finite or
 // gives NaN), so checking the results here flags such a record without a
 // separate pass over it.
 __global__ void __launch_bounds__(256)
 correlate_reduce(const double *__restrict__ partial, int l, int L, int splits,
-                 double inv_n, float *__restrict__ r, int *__restrict__ status) {
+                 double inv_n, const int *__restrict__ exps, float *__restrict__ r,
+                 int *__restrict__ status) {
   const int64_t total = (int64_t)l * L * l;
   const int64_t plane = total;
   int bad = 0;
@@ -475,7 +600,9 @@ correlate_reduce(const double *__restrict__ partial, int l, int L, int splits,
     const int64_t src = ((int64_t)a * L + j) * l + b;
     double s = 0.0;
     for (int sp = 0; sp < splits; ++sp) s += partial[sp * plane + src];
-    const float v = (float)(s * inv_n);
+    s *= inv_n;
+    if (exps) s = ldexp(s, -(exps[a] + exps[b]));   // undo the FP16x3 channel scales (exact)
+    const float v = (float)s;
     bad |= !isfinite(v);
     r[idx] = v;
   }
@@ -484,6 +611,13 @@ correlate_reduce(const double *__restrict__ partial, int l, int L, int splits,
 
 // ------------------------------------------------------------------ launch
 namespace ssi {
+
+namespace {
+// FP16x3: the channel exponents stored after the two planes
+int *corr_exps(const CorrPlan &p, const uint16_t *planes) {
+  return reinterpret_cast<int *>(const_cast<uint16_t *>(planes) + (size_t)2 * p.lp * p.np);
+}
+}  // namespace
 
 CorrPlan plan_correlate(int l, int64_t n, int L, int num_cus, int mode) {
   CorrPlan p{};
@@ -507,7 +641,8 @@ CorrPlan plan_correlate(int l, int64_t n, int L, int num_cus, int mode) {
   if (p.na_max > l) p.na_max = l;
   p.partial_elems = (size_t)p.splits * rows_total * l;
   p.mode = SSI_CORR_FP32;
-  if (mode == SSI_CORR_BF16X6) {
+  if (mode == SSI_CORR_BF16X6 || mode == SSI_CORR_F16X3) {
+    const int nplanes = mode == SSI_CORR_BF16X6 ? 3 : 2;
     // window row: samples up to 127 + L past the tile start, whole 16-byte chunks
     const int sa = (kST + L + 7) / 8 * 8;
     // copy stride: whole chunks, 5 chunks (20 dwords) past a multiple of 64
@@ -515,17 +650,21 @@ CorrPlan plan_correlate(int l, int64_t n, int L, int num_cus, int mode) {
     // 0..7 at two or three chunk positions, and an odd chunk offset between
     // copies spreads them over the banks (measured: 6.3 ms against 6.75 ms
     // for an offset of 2 chunks and 9.5 ms for none on the 180-channel record)
-    int cs = 3 * p.na_max * sa;
+    int cs = nplanes * p.na_max * sa;
     cs = (cs + 127) / 128 * 128 + 40;
-    const size_t lds = sizeof(uint16_t) * ((size_t)3 * kColsPerWG * kSB6 + (size_t)8 * cs);
+    const size_t lds =
+        sizeof(uint16_t) * ((size_t)nplanes * kColsPerWG * kSB6 + (size_t)8 * cs);
     if (lds <= 160 * 1024) {
-      p.mode = SSI_CORR_BF16X6;
+      p.mode = mode;
       p.sa_stride = sa;
       p.copy_stride = cs;
       p.lds_bytes = lds;
       p.lp = p.grid_cols * kColsPerWG;
       p.np = (n + 2 * kST + L + 64 + 7) / 8 * 8;   // every window and tile read stays inside
-      p.planes_elems = (size_t)3 * p.lp * p.np;
+      // FP16x3: the lp channel exponents (int32) and the kScaleParts partial
+      // maxima per channel (FP32) follow the two planes
+      p.planes_elems = (size_t)nplanes * p.lp * p.np +
+                       (mode == SSI_CORR_F16X3 ? (size_t)2 * p.lp * (1 + kScaleParts) : 0);
     }
   }
   if (p.mode == SSI_CORR_FP32) {
@@ -539,25 +678,35 @@ CorrPlan plan_correlate(int l, int64_t n, int L, int num_cus, int mode) {
 
 hipError_t launch_correlate_split(const CorrPlan &p, const float *y, int l, int64_t n,
                                   int64_t ldy, uint16_t *planes, hipStream_t st) {
-  if (p.mode != SSI_CORR_BF16X6) return hipSuccess;
+  if (p.mode == SSI_CORR_FP32) return hipSuccess;
   const int64_t chunks = (int64_t)p.lp * (p.np / 4);
   const int blocks = (int)std::min<int64_t>(ceil_div<int64_t>(chunks, 256), 65535 * 4);
-  hipLaunchKernelGGL(split3_kernel, dim3(blocks), dim3(256), 0, st, y, l, n, ldy, p.lp, p.np,
-                     planes);
+  if (p.mode == SSI_CORR_BF16X6) {
+    hipLaunchKernelGGL(split3_kernel, dim3(blocks), dim3(256), 0, st, y, l, n, ldy, p.lp, p.np,
+                       planes);
+    return hipGetLastError();
+  }
+  int *exps = corr_exps(p, planes);
+  float *pmax = reinterpret_cast<float *>(exps + p.lp);
+  hipLaunchKernelGGL(chan_max_kernel, dim3(p.lp, kScaleParts), dim3(256), 0, st, y, l, n, ldy,
+                     pmax);
+  hipLaunchKernelGGL(split2h_kernel, dim3(blocks), dim3(256), 0, st, y, l, n, ldy, p.lp, p.np,
+                     pmax, exps, planes);
   return hipGetLastError();
 }
 
 hipError_t launch_correlate_mfma(const CorrPlan &p, const float *y, int l, int64_t n, int64_t ldy,
                                  int L, double *partial, const uint16_t *planes, hipStream_t st) {
   const dim3 grid((unsigned)(p.grid_rows * p.grid_cols * p.splits));
-  if (p.mode == SSI_CORR_BF16X6) {
-    hipError_t e = hipFuncSetAttribute((const void *)correlate_b6,
+  if (p.mode == SSI_CORR_BF16X6 || p.mode == SSI_CORR_F16X3) {
+    const auto fn = p.mode == SSI_CORR_BF16X6 ? correlate_b6 : correlate_h3;
+    hipError_t e = hipFuncSetAttribute((const void *)fn,
                                        hipFuncAttributeMaxDynamicSharedMemorySize,
                                        (int)p.lds_bytes);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(correlate_b6, grid, dim3(kThreads), p.lds_bytes, st, planes, l, n, p.lp,
-                       p.np, L, p.split_len, partial, p.sa_stride, p.na_max, p.copy_stride,
-                       p.grid_rows, p.grid_cols, p.splits);
+    hipLaunchKernelGGL(fn, grid, dim3(kThreads), p.lds_bytes, st, planes, l, n, p.lp, p.np, L,
+                       p.split_len, partial, p.sa_stride, p.na_max, p.copy_stride, p.grid_rows,
+                       p.grid_cols, p.splits);
     return hipGetLastError();
   }
   const bool vec = (ldy % 4 == 0) && ((uintptr_t)y % 16 == 0);
@@ -579,12 +728,15 @@ hipError_t launch_correlate_mfma(const CorrPlan &p, const float *y, int l, int64
 }
 
 hipError_t launch_correlate_reduce(const CorrPlan &p, int l, int64_t n, int L,
-                                   const double *partial, float *r, int *status, hipStream_t st) {
+                                   const double *partial, const uint16_t *planes, float *r,
+                                   int *status, hipStream_t st) {
   const int64_t total = (int64_t)l * L * l;
   int blocks = (int)ceil_div<int64_t>(total, 256);
   if (blocks > 65535 * 8) blocks = 65535 * 8;
   hipLaunchKernelGGL(correlate_reduce, dim3(blocks), dim3(256), 0, st, partial, l, L,
-                     p.splits, 1.0 / (double)n, r, status);
+                     p.splits, 1.0 / (double)n,
+                     p.mode == SSI_CORR_F16X3 ? corr_exps(p, planes) : (const int *)nullptr, r,
+                     status);
   return hipGetLastError();
 }
 
@@ -594,7 +746,7 @@ hipError_t launch_correlate(const CorrPlan &p, const float *y, int l, int64_t n,
   hipError_t e = launch_correlate_split(p, y, l, n, ldy, planes, st);
   if (e == hipSuccess) e = launch_correlate_mfma(p, y, l, n, ldy, L, partial, planes, st);
   if (e != hipSuccess) return e;
-  return launch_correlate_reduce(p, l, n, L, partial, r, status, st);
+  return launch_correlate_reduce(p, l, n, L, partial, planes, r, status, st);
 }
 
 }  // namespace ssi

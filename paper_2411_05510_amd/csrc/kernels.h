@@ -25,19 +25,23 @@ struct CorrPlan {
   int sa_stride, na_max;
   size_t lds_bytes;
   size_t partial_elems;
-  int mode;                     // SSI_CORR_FP32 or SSI_CORR_BF16X6 (the path taken)
-  int lp;                       // BF16x6: channel rows of each plane (multiple of 64)
-  int64_t np;                   // BF16x6: samples per plane row
-  int copy_stride;              // BF16x6: elements between the shifted A-window copies
-  size_t planes_elems;          // BF16x6: 3 lp np bf16 elements of split planes, else 0
+  int mode;                     // ssi_corr_mode of the path taken
+  int lp;                       // split paths: channel rows of each plane (multiple of 64)
+  int64_t np;                   // split paths: samples per plane row
+  int copy_stride;              // split paths: elements between the shifted A-window copies
+  size_t planes_elems;          // BF16x6: 3 lp np bf16 elements of split planes;
+                                // FP16x3: 2 lp np fp16 elements, then lp int32 exponents
+                                // and 8 lp FP32 partial maxima;
+                                // FP32: 0
 };
-// mode: the requested path; BF16x6 falls back to FP32 where its tiles do not
-// fit two workgroups per CU.
+// mode: the requested path; the split paths fall back to FP32 where their
+// tiles do not fit two workgroups per CU.
 CorrPlan plan_correlate(int l, int64_t n, int L, int num_cus, int mode);
 hipError_t launch_correlate(const CorrPlan &p, const float *y, int l, int64_t n, int64_t ldy,
                             int L, double *partial, uint16_t *planes, float *r, int *status,
                             hipStream_t st);
-// BF16x6: the record's three BF16 parts into planes (no-op for FP32)
+// BF16x6: the record's three BF16 parts into planes; FP16x3: the channel
+// scales and the two FP16 parts; no-op for FP32
 hipError_t launch_correlate_split(const CorrPlan &p, const float *y, int l, int64_t n,
                                   int64_t ldy, uint16_t *planes, hipStream_t st);
 hipError_t launch_correlate_mfma(const CorrPlan &p, const float *y, int l, int64_t n, int64_t ldy,
@@ -45,7 +49,8 @@ hipError_t launch_correlate_mfma(const CorrPlan &p, const float *y, int l, int64
 // Sets kStatusNonFinite in *status when a correlation is not finite (a
 // non-finite sample makes at least one of them so).
 hipError_t launch_correlate_reduce(const CorrPlan &p, int l, int64_t n, int L,
-                                   const double *partial, float *r, int *status, hipStream_t st);
+                                   const double *partial, const uint16_t *planes, float *r,
+                                   int *status, hipStream_t st);
 
 // ---- Toeplitz (toeplitz.hip)
 hipError_t launch_toeplitz(const float *r, int l, int jb, float *t, int64_t ldt,

@@ -23,7 +23,7 @@ LIB_PATH = os.environ.get("SSI_LIBRARY") or os.path.join(HERE, "libssicov.so")
 SSI_OK, SSI_EINVAL, SSI_ENOMEM, SSI_EDEVICE, SSI_ENOCONV, SSI_EINTERNAL, SSI_EBUSY = range(7)
 SVD_FULL, SVD_RANDOMIZED = 0, 1
 PREC_FP32, PREC_BF16, PREC_BF16X3, PREC_BF16X6, PREC_FP8 = 0, 1, 2, 3, 4
-CORR_FP32, CORR_BF16X6 = 0, 1
+CORR_FP32, CORR_BF16X6, CORR_F16X3 = 0, 1, 2
 
 # Every symbol include/ssicov.h declares.
 EXPORTED = (
@@ -377,7 +377,7 @@ class Context:
         self._alloc_cbs = cbs          # the callbacks must outlive the context's use of them
 
     def set_corr_mode(self, mode: int) -> None:
-        """CORR_FP32 or CORR_BF16X6 (the default) for the correlation products."""
+        """CORR_FP32, CORR_BF16X6 or CORR_F16X3 (the default) for the correlation products."""
         _check(lib().ssi_set_corr_mode(self._h, mode))
 
     def tuned_splits(self, kind: int, trans: bool, m: int, n: int, k: int) -> int:

@@ -116,22 +116,27 @@ def test_caller_sketch_matches_checker(ctx, record):
     assert not np.array_equal(other.sigma.cpu().numpy(), out.sigma.cpu().numpy())
 
 
+@pytest.mark.parametrize("corr", [0, 1, 2], ids=["fp32", "bf16x6", "f16x3"])
 @pytest.mark.parametrize("bad", [np.nan, np.inf, -np.inf])
-def test_non_finite_record_is_rejected(ctx, record, bad):
+def test_non_finite_record_is_rejected(ctx, record, bad, corr):
     from paper_2411_05510_amd import ssicov
     _, y = record
     yb = y.copy()
     yb[3, 777] = bad
-    print(f"non-finite record: sample (3, 777) = {bad}", flush=True)
-    ctx.identify(torch.from_numpy(yb).cuda(), _params())
-    with pytest.raises(ssicov.SSIError) as ei:
+    print(f"non-finite record: sample (3, 777) = {bad}, correlation mode {corr}", flush=True)
+    ctx.set_corr_mode(corr)
+    try:
+        ctx.identify(torch.from_numpy(yb).cuda(), _params())
+        with pytest.raises(ssicov.SSIError) as ei:
+            ctx.synchronize()
+        assert ei.value.status == ssicov.SSI_EINVAL
+        assert "non-finite" in str(ei.value)
+        # the context stays usable and the status word was cleared
+        out = ctx.identify(torch.from_numpy(y).cuda(), _params())
         ctx.synchronize()
-    assert ei.value.status == ssicov.SSI_EINVAL
-    assert "non-finite" in str(ei.value)
-    # the context stays usable and the status word was cleared
-    out = ctx.identify(torch.from_numpy(y).cuda(), _params())
-    ctx.synchronize()
-    assert int(out.flags.sum().item()) == 0
+        assert int(out.flags.sum().item()) == 0
+    finally:
+        ctx.set_corr_mode(2)
 
 
 def test_sweep_limit_gives_enoconv(ctx, record):

@@ -46,7 +46,7 @@ def _corr_check(ctx, y, n_corr, tol=1e-5, fwd_tol=1e-6):
 
 
 # ------------------------------------------------------------ correlations
-MODES = pytest.mark.parametrize("mode", [0, 1], ids=["fp32", "bf16x6"])
+MODES = pytest.mark.parametrize("mode", [0, 1, 2], ids=["fp32", "bf16x6", "f16x3"])
 
 
 @MODES
@@ -102,18 +102,22 @@ def test_correlate_deterministic(ctx, mode):
 
 def test_correlate_modes_agree_exact_inputs(ctx):
     """Samples with at most 8 significant bits (small integers times a power of
-    two): the BF16 split is hi alone, every product is exact in either path,
-    and sums below 2^24 are exact in FP32, so both paths return identical
-    stacks."""
+    two): the BF16 split is hi alone, the FP16 split of the scaled sample is hi
+    alone, every product is exact in each path, and sums below 2^24 (after the
+    power-of-two channel scale) are exact in FP32, so all paths return
+    identical stacks."""
     rng = np.random.default_rng(5)
     y = (rng.integers(-15, 16, size=(19, 3000)) * 0.25).astype(np.float32)
+    y[7] *= 2.0 ** -40            # channels of very different scale
+    y[11] *= 2.0 ** 30
     out = []
-    for mode in (0, 1):
+    for mode in (0, 1, 2):
         ctx.set_corr_mode(mode)
         out.append(ctx.correlate(_dev(y), 25).cpu().numpy())
-    ctx.set_corr_mode(1)
+    ctx.set_corr_mode(2)
     ref = oracle.correlations(y, 25)
     assert np.array_equal(out[0], out[1])
+    assert np.array_equal(out[0], out[2])
     # the exact sums are scaled by 1/N and rounded to FP32 once
     np.testing.assert_allclose(out[1].astype(np.float64), ref, rtol=2.0 ** -23, atol=0)
 
