@@ -8,7 +8,7 @@ Toeplitz assembly, sketch, range finder with power iterations, small SVD,
 shift least squares and eigen-analysis for all 100 orders, poles sorted per
 order.  The record is resident in HBM before timing starts; results stay on
 the device.  Successive windows of a monitoring stream are independent, so
---in-flight of them (default 4) run at once, each on its own context and
+--in-flight of them (default 12) run at once, each on its own context and
 stream: the single-CU tail of one window's eigen-analysis overlaps the next
 windows' correlations and products.  Prints one JSON line with the
 throughput, the latency of one window at a time (p50/p99), the roofline of
@@ -857,14 +857,14 @@ def main() -> int:
     ap.add_argument("--corr", default="f16x3", choices=tuple(CORR_MODES),
                     help="correlation product arithmetic")
     ap.add_argument("--lag-streams", type=int, default=3)
-    ap.add_argument("--in-flight", type=int, default=4,
+    ap.add_argument("--in-flight", type=int, default=12,
                     help="headline: windows in flight (one context and stream each)")
     ap.add_argument("--requests", type=int, default=96, help="serving: requests per run")
     ap.add_argument("--inflight", type=int, default=64, help="serving: slots")
     ap.add_argument("--pool", type=int, default=24, help="serving: distinct windows")
     ap.add_argument("--hw-queues", type=int, default=None,
                     help="HIP hardware queues of the process (GPU_MAX_HW_QUEUES, 1..32); default "
-                         "8 for the headline with windows in flight, the runtime's own otherwise")
+                         "16 for the headline with windows in flight, the runtime's own otherwise")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--e2e-steps", type=int, default=5,
                     help="end-to-end steps (host record in, host results out) after the timing")
@@ -874,16 +874,19 @@ def main() -> int:
     if args.refine is None:
         args.refine = 0 if args.prec == "fp32" else 1
     # HIP gives a process four hardware queues by default; streams beyond that
-    # share a queue and run one after the other.  Four windows in flight plus
-    # torch's own stream need five, so the headline raises the count to eight
-    # (a larger value from the environment is kept).  The serving loop keeps
+    # share a queue and run one after the other.  The headline's twelve
+    # windows in flight plus torch's own stream share sixteen (measured with
+    # the FP16x3 correlations: 61-64 identifications/s with four windows on
+    # eight queues, 66-67 with ten on sixteen, 70-71 with twelve on sixteen,
+    # 69-72 with sixteen or twenty on 32); a larger value from the
+    # environment is kept.  The serving loop keeps
     # the default: with eight queues its 64 slots' kernels interleave more,
     # which lowered latency but also the saturation rate.  Set before the HIP
     # runtime starts (nothing above has touched the GPU).
     if args.hw_queues is not None:
         os.environ["GPU_MAX_HW_QUEUES"] = str(max(1, min(32, args.hw_queues)))
-    elif args.workload == "bridge-180ch" and int(os.environ.get("GPU_MAX_HW_QUEUES", "4") or "4") < 8:
-        os.environ["GPU_MAX_HW_QUEUES"] = "8"
+    elif args.workload == "bridge-180ch" and int(os.environ.get("GPU_MAX_HW_QUEUES", "4") or "4") < 16:
+        os.environ["GPU_MAX_HW_QUEUES"] = "16"
     if args.gpus != 1:
         print(f"bench.py: the identification runs on one GPU; --gpus {args.gpus} is not supported "
               "(one process, one device)", file=sys.stderr)
