@@ -270,6 +270,7 @@ def bench_identify(args) -> dict:
     outs = []
     for c in ctxs:
         c.set_corr_mode(CORR_MODES[args.corr])
+        c.set_eig_workgroups(args.eig_workgroups)
         c.set_autotune(True)                 # the warm-up calls pick the K-slice counts
         outs.append(c.alloc_output(p, wl.l, wl.n))
     ctx, out, stream = ctxs[0], outs[0], streams[0]
@@ -386,6 +387,7 @@ def bench_identify(args) -> dict:
                         f"in the warm-up; {k} windows in flight (one context, stream, copy of "
                         "the record and output set each)",
             "windows_in_flight": k,
+            "eig_workgroups": args.eig_workgroups or "one per CU",
             "hip_hw_queues": int(os.environ.get("GPU_MAX_HW_QUEUES", "4")),
             "latency_ms_p50": float(np.percentile(step_ms, 50)),
             "latency_ms_p99": float(np.percentile(step_ms, 99)),
@@ -857,6 +859,8 @@ def main() -> int:
     ap.add_argument("--corr", default="f16x3", choices=tuple(CORR_MODES),
                     help="correlation product arithmetic")
     ap.add_argument("--lag-streams", type=int, default=3)
+    ap.add_argument("--eig-workgroups", type=int, default=0,
+                    help="headline: workgroups of each eigen-analysis launch (0: one per CU)")
     ap.add_argument("--in-flight", type=int, default=12,
                     help="headline: windows in flight (one context and stream each)")
     ap.add_argument("--requests", type=int, default=96, help="serving: requests per run")

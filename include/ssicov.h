@@ -271,6 +271,13 @@ ssi_status ssi_set_autotune(ssi_ctx *ctx, int enable);
  * 64-row tiles (pins the configuration, e.g. for timing or testing one tile
  * shape).  SSI_EINVAL for other values.  Drops captured graphs. */
 ssi_status ssi_set_product_tile_rows(ssi_ctx *ctx, int32_t rows);
+/* Workgroups of the identification's eigen-analysis launch (Eq. (11) for
+ * every order in one persistent launch): 0 (default) for one per CU; n > 0
+ * for n workgroups, raised to the number of (lag, order) items when smaller
+ * and capped at one per CU.  Fewer workgroups leave CUs to the kernels of
+ * other windows running on other streams at the same time; results are
+ * unaffected.  SSI_EINVAL for n < 0.  Drops captured graphs. */
+ssi_status ssi_set_eig_workgroups(ssi_ctx *ctx, int32_t n);
 /* Sweep limit of the eigen-analysis (Eq. (11)): the QR iteration of an order
  * of size n stops after sweeps_per_row * max(10, n) sweeps (default 30, as
  * LAPACK's Hessenberg QR), marks the order in the output flags and makes the

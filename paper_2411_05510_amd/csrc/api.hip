@@ -83,6 +83,8 @@ struct ssi_ctx {
   int tile_rows = 128;            // FP32 x FP64 product tiles when not tuned
   // correlation product arithmetic (ssi_corr_mode)
   int corr_mode = SSI_CORR_F16X3;
+  // workgroups of the identification's eigen-analysis launch (0: one per CU)
+  int eig_workgroups = 0;
   std::map<std::tuple<int, int, int, int, int>, int> tuned;
   // QR sweep limit of the eigen-analysis: sweeps_per_row * max(10, n) per order
   int sweeps_per_row = 30;
@@ -379,6 +381,18 @@ ssi_status ssi_set_product_tile_rows(ssi_ctx *c, int32_t rows) {
     drop_graphs(c);
   }
   c->tile_rows = r;
+  return SSI_OK;
+}
+
+ssi_status ssi_set_eig_workgroups(ssi_ctx *c, int32_t n) {
+  if (!c) return fail(SSI_EINVAL, "ssi_set_eig_workgroups: NULL context");
+  if (n < 0) return fail(SSI_EINVAL, "ssi_set_eig_workgroups: n = %d must be >= 0", n);
+  if (n != c->eig_workgroups) {
+    DeviceGuard g(c->device);
+    drain(c);
+    drop_graphs(c);
+  }
+  c->eig_workgroups = n;
   return SSI_OK;
 }
 
@@ -1180,7 +1194,7 @@ ssi_status run_identify(ssi_ctx *c, IdentBufs &b, const float *y, int l, int64_t
     if (st != SSI_OK) return st;
   }
   // every (lag, order) of the diagram in one persistent launch
-  return run_modal_eig(c, b.ms, l, p, 0, out, 0);
+  return run_modal_eig(c, b.ms, l, p, 0, out, c->eig_workgroups);
 }
 
 }  // namespace

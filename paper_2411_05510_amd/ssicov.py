@@ -37,7 +37,7 @@ EXPORTED = (
     "ssi_server_submit", "ssi_server_poll", "ssi_server_wait", "ssi_server_result",
     "ssi_server_release", "ssi_server_get_stats", "ssi_server_last_error", "ssi_stability",
     "ssi_stability_noalloc", "ssi_stability_noalloc_max_slots",
-    "ssi_set_eig_max_sweeps", "ssi_set_product_tile_rows", "ssi_set_allocator",
+    "ssi_set_eig_max_sweeps", "ssi_set_product_tile_rows", "ssi_set_eig_workgroups", "ssi_set_allocator",
     "ssi_identify_result", "ssi_result_fetch",
     "ssi_result_dims", "ssi_result_poles", "ssi_result_singular_values", "ssi_result_free",
 )
@@ -184,6 +184,7 @@ def lib() -> ctypes.CDLL:
             "ssi_stability_noalloc_max_slots": ([], i64),
             "ssi_set_eig_max_sweeps": ([vp, i32], ctypes.c_int),
             "ssi_set_product_tile_rows": ([vp, i32], ctypes.c_int),
+            "ssi_set_eig_workgroups": ([vp, i32], ctypes.c_int),
             "ssi_set_allocator": ([vp, _ALLOC_FN, _RELEASE_FN, vp], ctypes.c_int),
             "ssi_identify_result": ([vp, vp, i32, i64, i64, P, ctypes.POINTER(vp)],
                                     ctypes.c_int),
@@ -350,6 +351,10 @@ class Context:
 
     def set_product_tile_rows(self, rows: int) -> None:
         _check(lib().ssi_set_product_tile_rows(self._h, rows))
+
+    def set_eig_workgroups(self, n: int) -> None:
+        """Workgroups of the eigen-analysis launch (0: one per CU)."""
+        _check(lib().ssi_set_eig_workgroups(self._h, n))
 
     def set_eig_max_sweeps(self, sweeps_per_row: int) -> None:
         _check(lib().ssi_set_eig_max_sweeps(self._h, sweeps_per_row))

@@ -107,5 +107,6 @@ def test_result_accessors_reject_null():
     assert lib.ssi_result_singular_values(None, 0, None, None) == S.SSI_EINVAL
     lib.ssi_result_free(None)
     assert lib.ssi_set_eig_max_sweeps(None, 3) == S.SSI_EINVAL
+    assert lib.ssi_set_eig_workgroups(None, 0) == S.SSI_EINVAL
     assert lib.ssi_set_product_tile_rows(None, 64) == S.SSI_EINVAL
     assert b"NULL" in lib.ssi_last_error()

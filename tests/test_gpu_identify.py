@@ -305,6 +305,28 @@ def test_identify_deterministic(ctx):
     assert torch.equal(fa, b.f) and torch.equal(pa, b.phi)
 
 
+def test_identify_eig_workgroups_same_results(ctx):
+    """A smaller eigen-analysis grid (raised to one workgroup per order)
+    changes which workgroup computes each order and pole, not the arithmetic:
+    the poles equal those of the default grid."""
+    wl = synth.WORKLOADS["small-full-svd"]
+    _, y = synth.make_record(wl, n=8000)
+    p = _params(wl)
+    yd = _dev(y)
+    a = ctx.identify(yd, p)
+    ctx.synchronize()
+    fa, pa, ca = a.f.clone(), a.phi.clone(), a.count.clone()
+    ctx.set_eig_workgroups(3)
+    try:
+        b = ctx.identify(yd, p)
+        ctx.synchronize()
+    finally:
+        ctx.set_eig_workgroups(0)
+    assert torch.equal(ca, b.count)
+    assert torch.allclose(fa, b.f, rtol=1e-12, atol=0)
+    assert torch.allclose(pa, b.phi, rtol=1e-10, atol=1e-12)
+
+
 _BRIDGE_REF = {}
 
 
