@@ -122,6 +122,37 @@ def test_correlate_modes_agree_exact_inputs(ctx):
     np.testing.assert_allclose(out[1].astype(np.float64), ref, rtol=2.0 ** -23, atol=0)
 
 
+@MODES
+def test_correlate_channel_scales(ctx, mode):
+    """Channels far outside the FP16 range (1e15 and 1e-15 times a unit
+    record), an all-zero channel and a ragged size: every mode matches the
+    checker to 1e-6 rms_a rms_b per entry, and the zero channel's
+    correlations are exactly zero.  Without the per-channel power-of-two
+    scale the FP16 parts of the large channel would overflow and those of the
+    small one underflow."""
+    y = synth.random_matrix(9, 4001, seed=17).astype(np.float64)
+    y[2] *= 1e15
+    y[5] *= 1e-15
+    y[7] = 0.0
+    y = y.astype(np.float32)
+    L = 13
+    ctx.set_corr_mode(mode)
+    try:
+        got = ctx.correlate(_dev(y), L).cpu().numpy().astype(np.float64)
+        ctx.synchronize()
+    finally:
+        ctx.set_corr_mode(2)
+    ref = oracle.correlations(y, L)
+    rms = np.sqrt(np.mean(y.astype(np.float64) ** 2, axis=1))
+    scale = np.outer(rms, rms)[None]
+    nz = scale > 0
+    err = np.abs(got - ref)
+    assert np.all(np.isfinite(got))
+    assert (err[np.broadcast_to(nz, err.shape)] / np.broadcast_to(scale, err.shape)[
+        np.broadcast_to(nz, err.shape)]).max() <= 1e-6
+    assert np.all(got[:, 7, :] == 0.0) and np.all(got[:, :, 7] == 0.0)
+
+
 # ---------------------------------------------------------------- Toeplitz
 @pytest.mark.parametrize("l,jb,pad", [(12, 20, 0), (7, 9, 3), (180, 60, 16), (4, 2, 0),
                                       (1, 5, 1)])
