@@ -625,9 +625,12 @@ CorrPlan plan_correlate(int l, int64_t n, int L, int num_cus, int mode) {
   p.grid_rows = ceil_div(rows_total, kRowsPerWG);
   p.grid_cols = ceil_div(l, kColsPerWG);
   const int tiles = p.grid_rows * p.grid_cols;
-  // Aim for about four resident rounds of two workgroups per CU, with at
-  // least 1024 samples per split.
-  const int64_t target = (int64_t)num_cus * 2 * 4;
+  // Aim for about four resident rounds of workgroups, with at least 1024
+  // samples per split: two workgroups per CU for the FP32 path, one for the
+  // split paths (their registers allow one eight-wave workgroup per CU), so
+  // that the split paths write half as many FP64 partials.
+  const bool split_mode = mode == SSI_CORR_BF16X6 || mode == SSI_CORR_F16X3;
+  const int64_t target = (int64_t)num_cus * (split_mode ? 1 : 2) * 4;
   int64_t splits = ceil_div<int64_t>(target, tiles);
   const int64_t max_splits = ceil_div<int64_t>(n, 1024);
   if (splits > max_splits) splits = max_splits;
